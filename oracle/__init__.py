@@ -1,0 +1,377 @@
+"""CPU oracle for the geometric matrix ordering method (arXiv 1105.4490).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package; the product path (the
+HIP library and its binding) never does.  It shares no code with the product.
+
+The hypergraph models of the paper's Table 1 are written here in numpy; the
+rest (components, cut, quantized 2-means, recursive ordering, coarsening,
+tree, gradient, multilevel layout) is plain sequential C in
+``vmo_oracle.c``, compiled with ``-O2 -ffp-contract=off`` and called through
+ctypes.  Each function cites the passage of the paper it follows.
+
+Parity pins: every function here is checked by ``tests/test_oracle_*.py``
+against values the paper prints, closed forms, brute force or independent
+library routines; see the test files for the pin of each function.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vmo_oracle.c")
+_LIB = os.path.join(_HERE, "_vmo_oracle.so")
+
+ROW_NET, COLUMN_NET, SYMMETRIC = 0, 1, 2
+NET_MODE, GRAPH_MODE = 0, 1
+SBD, BBD = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (gcc, -O2, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+@dataclass
+class Hypergraph:
+    """Weighted hypergraph (Definition of a hypergraph, Sec. 1.1): nets as CSR
+    (ptr int64 [l+1], pins int32 ascending within a net), w [k] and c [l]
+    float32 or None (all ones)."""
+    k: int
+    l: int
+    ptr: np.ndarray
+    pins: np.ndarray
+    w: np.ndarray | None = None
+    c: np.ndarray | None = None
+
+    def nets(self):
+        for e in range(self.l):
+            yield self.pins[self.ptr[e]:self.ptr[e + 1]]
+
+
+def hypergraph(k, nets, w=None, c=None) -> Hypergraph:
+    """Hypergraph from a Python list of nets (each an iterable of vertex ids)."""
+    nets = [sorted(int(v) for v in e) for e in nets]
+    ptr = np.zeros(len(nets) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(e) for e in nets])
+    pins = np.array([v for e in nets for v in e], dtype=np.int32)
+    return Hypergraph(int(k), len(nets), ptr, pins,
+                      None if w is None else np.asarray(w, dtype=np.float32),
+                      None if c is None else np.asarray(c, dtype=np.float32))
+
+
+# ---------------------------------------------------------------- Table 1 ----
+
+def rownet(m, n, rowptr, col) -> Hypergraph:
+    """Row-net model (Table 1): vertices = columns, net i = columns of row i."""
+    return Hypergraph(int(n), int(m), np.asarray(rowptr, np.int64).copy(), np.asarray(col, np.int32).copy())
+
+
+def transpose(m, n, rowptr, col):
+    """CSR of A^T (columns ascending within each row of A^T), by stable sort."""
+    rowptr = np.asarray(rowptr, np.int64)
+    col = np.asarray(col, np.int64)
+    rows = np.repeat(np.arange(m, dtype=np.int64), np.diff(rowptr))
+    order = np.lexsort((rows, col))
+    tptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(col, minlength=n), out=tptr[1:])
+    return tptr, rows[order].astype(np.int32)
+
+
+def colnet(m, n, rowptr, col) -> Hypergraph:
+    """Column-net model (Table 1): vertices = rows, net j = rows with a_ij != 0."""
+    tptr, tcol = transpose(m, n, rowptr, col)
+    return Hypergraph(int(m), int(n), tptr, tcol)
+
+
+def symmetric(m, n, rowptr, col) -> Hypergraph:
+    """Symmetric model (Table 1) of a square pattern: nets are the distinct
+    pairs {i, j}, i < j, with a_ij != 0 or a_ji != 0, ordered by (i, j);
+    diagonal entries are dropped (they would be one-vertex nets)."""
+    assert m == n
+    rowptr = np.asarray(rowptr, np.int64)
+    rows = np.repeat(np.arange(m, dtype=np.int64), np.diff(rowptr))
+    cols = np.asarray(col, np.int64)
+    a = np.minimum(rows, cols)
+    b = np.maximum(rows, cols)
+    keep = a != b
+    key = np.unique(a[keep] * n + b[keep])
+    l = key.shape[0]
+    pins = np.empty(2 * l, dtype=np.int32)
+    pins[0::2] = key // n
+    pins[1::2] = key % n
+    return Hypergraph(int(n), int(l), np.arange(0, 2 * l + 1, 2, dtype=np.int64), pins)
+
+
+def model(kind, m, n, rowptr, col) -> Hypergraph:
+    return (rownet, colnet, symmetric)[kind](m, n, rowptr, col)
+
+
+# ---------------------------------------------------------------- C parts ----
+
+def dual(h: Hypergraph) -> Hypergraph:
+    """Dual hypergraph (Definition of the dual, Sec. 1.1); weights and costs swap."""
+    dptr = np.zeros(h.k + 1, dtype=np.int64)
+    dp = np.zeros(max(int(h.ptr[-1]), 1), dtype=np.int32)
+    rc = lib().o_dual(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(dptr), _p(dp))
+    assert rc == 0
+    return Hypergraph(h.l, h.k, dptr, dp[:int(h.ptr[-1])], h.c, h.w)
+
+
+def components(h: Hypergraph) -> np.ndarray:
+    """label(v) = smallest vertex id in v's connected component (Algorithm 1)."""
+    lab = np.zeros(h.k, dtype=np.int32)
+    rc = lib().o_components(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(lab))
+    assert rc == 0
+    return lab
+
+
+def cut(h: Hypergraph, part, nparts: int):
+    """(lambda-1) metric, cut-net metric, number of cut nets, part weights."""
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    out = np.zeros(3, dtype=np.float64)
+    pw = np.zeros(max(nparts, 1), dtype=np.float64)
+    rc = lib().o_cut(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(h.c), _p(part), _p(h.w),
+                     C.c_int32(nparts), _p(out), _p(pw))
+    assert rc == 0
+    return {"lambda_minus_one": out[0], "cut_net": out[1], "nets_cut": int(out[2]), "part_weight": pw[:nparts]}
+
+
+def quantize(x):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    k = x.shape[1]
+    q = np.zeros((4, k), dtype=np.uint32)
+    lo = np.zeros(4, dtype=np.float32)
+    s = C.c_double(0)
+    rc = lib().o_quantize(C.c_int32(k), _p(x), _p(q), _p(lo), C.byref(s))
+    assert rc == 0
+    return q, lo, s.value
+
+
+def splitmix64(seed, n):
+    """n-th output of the SplitMix64 stream seeded with `seed`."""
+    f = lib().o_splitmix64
+    f.restype = C.c_uint64
+    return int(f(C.c_uint64(seed), C.c_uint64(n)))
+
+
+def rng(seed, a, b, c):
+    f = lib().o_rng
+    f.restype = C.c_uint64
+    return int(f(C.c_uint64(seed), C.c_uint64(a), C.c_uint64(b), C.c_uint64(c)))
+
+
+@dataclass
+class BisectResult:
+    split: bool
+    side: np.ndarray
+    centres: np.ndarray
+    iters: int
+    plane: np.ndarray
+
+
+def bisect(x, seed: int, t_max: int = 32) -> BisectResult:
+    """One 2-means split (Algorithm 4, m = 2; plane of Algorithm 7)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    k = x.shape[1]
+    side = np.zeros(k, dtype=np.uint8)
+    cen = np.zeros(8, dtype=np.float32)
+    it = C.c_int32(0)
+    plane = np.zeros(5, dtype=np.float64)
+    rc = lib().o_bisect(C.c_int32(k), _p(x), C.c_uint64(seed), C.c_int32(t_max), _p(side), _p(cen),
+                        C.byref(it), _p(plane))
+    assert rc >= 0
+    return BisectResult(rc == 0, side, cen.reshape(2, 4), it.value, plane)
+
+
+@dataclass
+class OrderResult:
+    vperm: np.ndarray
+    nperm: np.ndarray | None
+    part: np.ndarray
+    node_heap: np.ndarray
+    node_vptr: np.ndarray
+    node_nptr: np.ndarray | None
+    split_cut: np.ndarray
+    n_nodes: int
+
+
+def order(h: Hypergraph, x, P: int, seed: int, mode: int = NET_MODE, ord: int = SBD, t_max: int = 32,
+          job: int = 0) -> OrderResult:
+    """Recursive SBD/BBD ordering (Algorithm 7 applied recursively, Sec. 4.2)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    k, l = h.k, h.l
+    vperm = np.zeros(k, dtype=np.int32)
+    part = np.zeros(k, dtype=np.int32)
+    nperm = np.zeros(max(l, 1), dtype=np.int32) if mode == NET_MODE else None
+    heap = np.zeros(4 * P, dtype=np.int32)
+    vptr = np.zeros(4 * P + 1, dtype=np.int32)
+    nptr = np.zeros(4 * P + 2, dtype=np.int32) if mode == NET_MODE else None
+    sc = np.zeros(4 * P, dtype=np.float64)
+    nn = C.c_int32(0)
+    rc = lib().o_order(C.c_int32(k), C.c_int32(l), _p(h.ptr), _p(h.pins), _p(h.c), C.c_int(mode), C.c_int(ord),
+                       _p(x), C.c_int32(P), C.c_uint64(seed), C.c_uint64(job), C.c_int32(t_max), _p(vperm),
+                       _p(nperm), _p(part), _p(heap), _p(vptr), _p(nptr), _p(sc), C.byref(nn))
+    if rc != 0:
+        raise ValueError("oracle order rejected its input")
+    return OrderResult(vperm, None if nperm is None else nperm[:l], part, heap, vptr, nptr, sc, nn.value)
+
+
+# ---------------------------------------------------------------- layout ----
+
+class LayoutParams(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("coarsest_iters", C.c_int32), ("level_iters", C.c_int32),
+                ("min_coarse", C.c_int32), ("max_levels", C.c_int32), ("leaf_cap", C.c_int32),
+                ("match_max_net", C.c_int32), ("theta", C.c_float), ("step0_frac", C.c_float),
+                ("decay", C.c_float), ("jitter", C.c_float), ("stall", C.c_float), ("pack_gap", C.c_float)]
+
+
+def layout_params(seed=1, coarsest_iters=100, level_iters=30, min_coarse=64, max_levels=40, leaf_cap=8,
+                  match_max_net=64, theta=0.5, step0_frac=0.1, decay=0.9, jitter=1e-3, stall=0.95,
+                  pack_gap=0.1) -> LayoutParams:
+    return LayoutParams(seed, coarsest_iters, level_iters, min_coarse, max_levels, leaf_cap, match_max_net,
+                        theta, step0_frac, decay, jitter, stall, pack_gap)
+
+
+def _wc(h: Hypergraph):
+    w = h.w if h.w is not None else np.ones(h.k, dtype=np.float32)
+    c = h.c if h.c is not None else np.ones(max(h.l, 1), dtype=np.float32)
+    return np.ascontiguousarray(w, np.float32), np.ascontiguousarray(c, np.float32)
+
+
+def coarsen(h: Hypergraph, seed: int, comp: int = 0, level: int = 0, match_max: int = 64):
+    """One coarsening step (Sec. 2.3).  Returns (pi, coarse hypergraph)."""
+    w, c = _wc(h)
+    pi = np.zeros(h.k, dtype=np.int32)
+    cptr = np.zeros(h.l + 1, dtype=np.int64)
+    cpins = np.zeros(max(int(h.ptr[-1]), 1), dtype=np.int32)
+    cw = np.zeros(h.k, dtype=np.float32)
+    cc = np.zeros(max(h.l, 1), dtype=np.float32)
+    kc, lc = C.c_int32(0), C.c_int32(0)
+    rc = lib().o_coarsen(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(w), _p(c), C.c_uint64(seed),
+                         C.c_uint64(comp), C.c_int32(level), C.c_int32(match_max), _p(pi), C.byref(kc), C.byref(lc),
+                         _p(cptr), _p(cpins), _p(cw), _p(cc))
+    assert rc == 0
+    kc, lc = kc.value, lc.value
+    return pi, Hypergraph(kc, lc, cptr[:lc + 1].copy(), cpins[:int(cptr[lc])].copy(), cw[:kc].copy(), cc[:lc].copy())
+
+
+@dataclass
+class Tree:
+    n: int
+    first: np.ndarray
+    count: np.ndarray
+    depth: np.ndarray
+    leaf: np.ndarray
+    next: np.ndarray
+    cell2: np.ndarray
+    W: np.ndarray
+    X: np.ndarray
+    order: np.ndarray
+
+
+def tree(x, w=None, leaf_cap: int = 8) -> Tree:
+    """2^d-tree with cluster charges (Sec. 2.1, Algorithm 3)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    k = x.shape[1]
+    w = np.ones(k, np.float32) if w is None else np.ascontiguousarray(w, np.float32)
+    cap = 17 * k + 64
+    ints = np.zeros((cap, 8), dtype=np.int32)
+    cell2 = np.zeros((cap, 4), dtype=np.int32)
+    flt = np.zeros((cap, 5), dtype=np.float32)
+    order_ = np.zeros(k, dtype=np.int32)
+    n = lib().o_tree(C.c_int32(k), _p(x), _p(w), C.c_int32(leaf_cap), _p(ints), _p(cell2), _p(flt), _p(order_),
+                     C.c_int32(cap))
+    assert n > 0
+    return Tree(n, ints[:n, 0].copy(), ints[:n, 1].copy(), ints[:n, 2].copy(), ints[:n, 3].copy(),
+                ints[:n, 4].copy(), cell2[:n].copy(), flt[:n, 0].copy(), flt[:n, 1:].copy(), order_)
+
+
+def gradient(h: Hypergraph, x, theta=0.5, leaf_cap=8):
+    """Gradient of eq. (6) as eq. (7): attraction + tree-walk repulsion. Returns (y, z)."""
+    w, c = _wc(h)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.zeros((4, h.k), dtype=np.float32)
+    z = np.zeros((4, max(h.l, 1)), dtype=np.float32)
+    rc = lib().o_gradient(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(w), _p(c), _p(x),
+                          C.c_float(theta), C.c_int32(leaf_cap), _p(y), _p(z))
+    assert rc == 0
+    return y, z[:, :h.l]
+
+
+def gradient_sample(h: Hypergraph, x, ids, theta=0.5, leaf_cap=8):
+    """Gradient at sampled vertices, and each one's interaction count."""
+    w, c = _wc(h)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    y = np.zeros((4, ids.shape[0]), dtype=np.float32)
+    nint = np.zeros(ids.shape[0], dtype=np.int64)
+    rc = lib().o_gradient_sample(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(w), _p(c), _p(x),
+                                 C.c_float(theta), C.c_int32(leaf_cap), C.c_int32(ids.shape[0]), _p(ids), _p(y),
+                                 _p(nint))
+    assert rc == 0
+    return y, nint
+
+
+def layout_iter(h: Hypergraph, x, params: LayoutParams, it: int, alpha: float = 0.0):
+    """One steepest-descent step (Algorithm 3).  Returns (x_new, y, alpha)."""
+    w, c = _wc(h)
+    x = np.ascontiguousarray(x, dtype=np.float32).copy()
+    y = np.zeros((4, h.k), dtype=np.float32)
+    a = C.c_double(alpha)
+    rc = lib().o_layout_iter(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(w), _p(c), _p(x),
+                             C.byref(params), C.c_int32(it), C.byref(a), _p(y))
+    assert rc == 0
+    return x, y, a.value
+
+
+def layout_init(k: int, seed: int, comp: int = 0, level: int = 0):
+    x = np.zeros((4, k), dtype=np.float32)
+    lib().o_layout_init(C.c_int32(k), C.c_uint64(seed), C.c_uint64(comp), C.c_int32(level), _p(x))
+    return x
+
+
+def layout_prolong(pi, xc, seed: int, comp: int, flevel: int, jitter: float = 1e-3):
+    pi = np.ascontiguousarray(pi, np.int32)
+    xc = np.ascontiguousarray(xc, np.float32)
+    kf, kc = pi.shape[0], xc.shape[1]
+    xf = np.zeros((4, kf), dtype=np.float32)
+    lib().o_layout_prolong(C.c_int32(kf), C.c_int32(kc), _p(pi), _p(xc), C.c_uint64(seed), C.c_uint64(comp),
+                           C.c_int32(flevel), C.c_float(jitter), _p(xf))
+    return xf
+
+
+def layout(h: Hypergraph, params: LayoutParams | None = None):
+    """Multilevel layout of every component, packed (Algorithm 2)."""
+    params = params or layout_params()
+    w, c = _wc(h)
+    x = np.zeros((4, h.k), dtype=np.float32)
+    rc = lib().o_layout(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(w), _p(c), C.byref(params), _p(x))
+    assert rc == 0
+    return x

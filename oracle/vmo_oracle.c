@@ -1,0 +1,1210 @@
+/*
+ * CPU ORACLE for the geometric matrix ordering method of Fagginger Auer and
+ * Bisseling, "A Geometric Approach to Matrix Ordering" (arXiv 1105.4490).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product (the HIP
+ * library behind include/vmo.h) shares no code, header, table or helper with
+ * it.  Everything here is written sequentially, in the order the paper
+ * states its steps, with the free choices the paper leaves open fixed as
+ * listed below.  Compile with -O2 -ffp-contract=off (no fused multiply-add,
+ * so every float and double operation is a single IEEE rounding).
+ *
+ * Contents (paper passage in brackets):
+ *   o_rng             counter-based SplitMix64 (Steele, Lea, Flood 2014).
+ *   o_dual            dual hypergraph [Definition of the dual, Sec. 1.1].
+ *   o_components      connected components, label = minimum vertex id
+ *                     [Algorithm 1, Sec. 2.3; Theorem on disconnected graphs].
+ *   o_cut             (lambda-1), cut-net metric, part weights
+ *                     [Sec. 4.1 cut rows/columns; footnote on the cut-net
+ *                      metric; Table 4 max cut per split].
+ *   o_quantize        20-bit grid for exact 2-means sums (not in the paper;
+ *                     an exactness device, see the reading of Alg. 4 below).
+ *   o_bisect          one 2-means split [Algorithm 4 with m = 2, Algorithm 7
+ *                     first part: sides and splitting plane].
+ *   o_order           recursive SBD/BBD ordering, net mode and graph mode
+ *                     [Algorithm 7; Sec. 4.1 recursive BBD; Sec. 4.2
+ *                      permutations; Sec. 5 SBD form].
+ *   o_coarsen         one coarsening step [Sec. 2.3, coarsening by greedy
+ *                     heavy-net matching, single-neighbour rule, net merge].
+ *   o_tree            2^d-tree with cluster charges [Sec. 2.1 tree
+ *                     approximation; Algorithm 3 tree and sibling links].
+ *   o_layout_iter     one steepest-descent step [Algorithm 3; eq. (7)].
+ *   o_layout          multilevel layout of every component, packed
+ *                     [Algorithm 2; Theorem on connectedness].
+ *
+ * Readings of points the paper leaves open (the GPU path implements the same
+ * readings from its own code):
+ *   - Ids are 0-based.  Nets form a multiset: duplicates and empty nets are
+ *     kept, so the dual of the dual is the hypergraph itself.
+ *   - d = 4, alpha = beta = 1, gamma = 2, delta = d - 2 = 2 (Sec. 2.1, Sec. 5).
+ *   - Coordinates are FP32 (the paper packs one point in a 4-float register).
+ *   - 2-means runs on coordinates quantized once per job to a 2^20 grid; sums
+ *     are exact int64, the plane test is FP64 evaluated left to right, and a
+ *     point with s(v) <= 0 goes to part 1 (Algorithm 7 uses <=).
+ *   - k-means++ seeding draws from SplitMix64 keyed by (seed, job, node); the
+ *     D^2 draw is exact 128/192-bit integer arithmetic.
+ *   - Lloyd iterations stop when no assignment changes, or after t_max
+ *     centre updates ("a fixed number of iterations" in Algorithm 4).
+ *   - A node with K parts gives ceil(K/2) to side 1 and floor(K/2) to side 2;
+ *     it is a leaf if K = 1, it has < 2 vertices, all its points coincide, or
+ *     a side comes out empty ("until it can no longer continue", Sec. 5).
+ *   - Net mode: a net belongs to the deepest node whose vertex set holds all
+ *     its pins.  SBD lists nodes in-order, BBD post-order; ascending id within
+ *     a block; empty nets last.  Graph mode: the separator loop of Algorithm 7
+ *     visits edges in net order, and the separator S_h sits at node h.
+ *   - Layout: far-field test on integer cell geometry, theta = 1/2; tree
+ *     moments summed bottom-up in FP64; every vertex steps a length set by
+ *     the bounding-box volume along its own gradient direction, the length
+ *     shrinking by 0.9 per step; coarsening and random choices keyed by
+ *     SplitMix64.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+/* ------------------------------------------------------------------------- */
+/* SplitMix64: state advances by the golden gamma, output is the mix function */
+static uint64_t o_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+#define O_GAMMA 0x9E3779B97F4A7C15ULL
+
+/* Counter-based draw: chained SplitMix64 outputs keyed by three words. */
+uint64_t o_rng(uint64_t seed, uint64_t a, uint64_t b, uint64_t c) {
+  uint64_t h = o_mix64(seed + O_GAMMA * (a + 1));
+  h = o_mix64(h + O_GAMMA * (b + 1));
+  return o_mix64(h + O_GAMMA * (c + 1));
+}
+
+/* n-th output (n >= 1) of the plain SplitMix64 stream started at `seed`. */
+uint64_t o_splitmix64(uint64_t seed, uint64_t n) { return o_mix64(seed + O_GAMMA * n); }
+
+#define TAG_INIT 1u
+#define TAG_PROLONG 2u
+#define TAG_MATCH 3u
+#define TAG_KMEANS 16u
+
+/* ------------------------------------------------------------------------- */
+/* Dual hypergraph: net v of G* lists, in ascending order, the nets holding v */
+int o_dual(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, int64_t* dptr, int32_t* dpins) {
+  memset(dptr, 0, sizeof(int64_t) * (size_t)(k + 1));
+  for (int64_t p = 0; p < ptr[l]; ++p) {
+    if (pins[p] < 0 || pins[p] >= k) return -1;
+    dptr[pins[p] + 1]++;
+  }
+  for (int32_t v = 0; v < k; ++v) dptr[v + 1] += dptr[v];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
+  for (int32_t v = 0; v < k; ++v) fill[v] = dptr[v];
+  for (int32_t e = 0; e < l; ++e)
+    for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) dpins[fill[pins[p]]++] = e;
+  free(fill);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Connected components by breadth-first search from each vertex in ascending
+   order: the first vertex that reaches a component is its minimum id. */
+int o_components(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, int32_t* label) {
+  int64_t* dptr = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k + 1));
+  int32_t* dp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ptr[l] > 0 ? ptr[l] : 1));
+  if (o_dual(k, l, ptr, pins, dptr, dp)) { free(dptr); free(dp); return -1; }
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
+  char* net_seen = (char*)calloc((size_t)(l > 0 ? l : 1), 1);
+  for (int32_t v = 0; v < k; ++v) label[v] = -1;
+  for (int32_t s = 0; s < k; ++s) {
+    if (label[s] >= 0) continue;
+    int32_t qh = 0, qt = 0;
+    queue[qt++] = s;
+    label[s] = s;
+    while (qh < qt) {
+      int32_t v = queue[qh++];
+      for (int64_t a = dptr[v]; a < dptr[v + 1]; ++a) {
+        int32_t e = dp[a];
+        if (net_seen[e]) continue;
+        net_seen[e] = 1;
+        for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) {
+          int32_t u = pins[p];
+          if (label[u] < 0) { label[u] = s; queue[qt++] = u; }
+        }
+      }
+    }
+  }
+  free(dptr); free(dp); free(queue); free(net_seen);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Cut metrics of a partition.  lambda(e) = number of distinct part ids among
+   the pins of e.  out[0] = sum c(e) max(lambda-1, 0); out[1] = sum of c(e)
+   over nets with lambda > 1; out[2] = number of such nets.  part_weight[p] =
+   sum of w(v) over part(v) = p for p < nparts (ids >= nparts are not
+   weighed).  Sums in FP64 in ascending net / vertex order. */
+int o_cut(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* c,
+          const int32_t* part, const float* w, int32_t nparts, double* out, double* part_weight) {
+  int64_t maxlen = 0;
+  for (int32_t e = 0; e < l; ++e) if (ptr[e + 1] - ptr[e] > maxlen) maxlen = ptr[e + 1] - ptr[e];
+  int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxlen > 0 ? maxlen : 1));
+  double lm1 = 0.0, cn = 0.0, ncut = 0.0;
+  for (int32_t e = 0; e < l; ++e) {
+    int64_t len = ptr[e + 1] - ptr[e];
+    if (len == 0) continue;
+    for (int64_t p = 0; p < len; ++p) {
+      int32_t v = pins[ptr[e] + p];
+      if (v < 0 || v >= k) { free(buf); return -1; }
+      buf[p] = part[v];
+    }
+    qsort(buf, (size_t)len, sizeof(int32_t), cmp_i32);
+    int64_t lam = 1;
+    for (int64_t p = 1; p < len; ++p) if (buf[p] != buf[p - 1]) lam++;
+    double ce = c ? (double)c[e] : 1.0;
+    lm1 += ce * (double)(lam - 1);
+    if (lam > 1) { cn += ce; ncut += 1.0; }
+  }
+  out[0] = lm1; out[1] = cn; out[2] = ncut;
+  if (part_weight) {
+    for (int32_t p = 0; p < nparts; ++p) part_weight[p] = 0.0;
+    for (int32_t v = 0; v < k; ++v)
+      if (part[v] >= 0 && part[v] < nparts) part_weight[part[v]] += w ? (double)w[v] : 1.0;
+  }
+  free(buf);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Quantization: once per job, map the bounding box of the FP32 points to a
+   2^20 grid.  lo = exact FP32 minimum per dimension; ext = largest side in
+   FP64; scale = (2^20 - 1) / ext; q = floor((x - lo) * scale). */
+#define QMAX 1048575u
+int o_quantize(int32_t k, const float* x, uint32_t* q, float* lo_out, double* scale_out) {
+  float lo[4], hi[4];
+  for (int d = 0; d < 4; ++d) {
+    lo[d] = x[(size_t)d * k];
+    hi[d] = x[(size_t)d * k];
+    for (int32_t i = 0; i < k; ++i) {
+      float v = x[(size_t)d * k + i];
+      if (!isfinite(v)) return -1;
+      if (v < lo[d]) lo[d] = v;
+      if (v > hi[d]) hi[d] = v;
+    }
+  }
+  double ext = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    double e = (double)hi[d] - (double)lo[d];
+    if (e > ext) ext = e;
+  }
+  double s = ext > 0.0 ? (double)QMAX / ext : 0.0;
+  for (int d = 0; d < 4; ++d) {
+    for (int32_t i = 0; i < k; ++i) {
+      uint32_t v = 0;
+      if (s > 0.0) {
+        double t = ((double)x[(size_t)d * k + i] - (double)lo[d]) * s;
+        double f = floor(t);
+        v = f >= (double)QMAX ? QMAX : (uint32_t)f;
+      }
+      q[(size_t)d * k + i] = v;
+    }
+    lo_out[d] = lo[d];
+  }
+  *scale_out = s;
+  return 0;
+}
+
+/* Splitting plane of Algorithm 7: r = z2 - z1, delta = (z1 + z2)/2 . r.
+   Every product and sum is rounded separately, left to right. */
+static void plane_from(const double* c1, const double* c2, double* r, double* delta) {
+  double m[4];
+  for (int d = 0; d < 4; ++d) {
+    r[d] = c2[d] - c1[d];
+    double s = c1[d] + c2[d];
+    m[d] = s * 0.5;
+  }
+  double a0 = m[0] * r[0];
+  double a1 = m[1] * r[1];
+  double a2 = m[2] * r[2];
+  double a3 = m[3] * r[3];
+  double t = a0 + a1;
+  t = t + a2;
+  t = t + a3;
+  *delta = t;
+}
+
+/* s(v) = x(v).r - delta, same rounding discipline.  s <= 0 means part 1. */
+static double splane(const uint32_t* q, size_t stride, int32_t v, const double* r, double delta) {
+  double a0 = (double)q[v] * r[0];
+  double a1 = (double)q[stride + v] * r[1];
+  double a2 = (double)q[2 * stride + v] * r[2];
+  double a3 = (double)q[3 * stride + v] * r[3];
+  double t = a0 + a1;
+  t = t + a2;
+  t = t + a3;
+  return t - delta;
+}
+
+/* One 2-means split of the vertices ids[0..n) (ascending ids) of node h of
+   job `job`: k-means++ seeding with m = 2, then Lloyd iterations, Algorithm 4;
+   sides by the plane of Algorithm 7.  Returns 0 when split (side[i] in {1,2}),
+   1 when the node cannot split (all points coincide, or a side came out
+   empty).  cen = centres used in the final assignment (grid units),
+   plane = (r0..r3, delta), iters = centre updates done. */
+static int o_split(const uint32_t* q, size_t stride, const int32_t* ids, int32_t n, uint64_t seed,
+                   uint64_t job, int32_t h, int32_t t_max, uint8_t* side, double cen[2][4],
+                   double plane[5], int32_t* iters) {
+  uint64_t key = TAG_KMEANS | (job << 8);
+  *iters = 0;
+  /* z1: uniform member of the node */
+  uint64_t r0 = o_rng(seed, key, (uint64_t)h, 0);
+  int32_t i1 = (int32_t)(((u128)r0 * (u128)(uint64_t)n) >> 64);
+  /* D^2 weights, exact */
+  int64_t* dd = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  u128 T = 0;
+  int32_t v1 = ids[i1];
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t v = ids[i];
+    int64_t s = 0;
+    for (int d = 0; d < 4; ++d) {
+      int64_t df = (int64_t)q[d * stride + v] - (int64_t)q[d * stride + v1];
+      s += df * df;
+    }
+    dd[i] = s;
+    T += (u128)(uint64_t)s;
+  }
+  if (T == 0) { free(dd); return 1; }
+  /* t = floor(r1 * T / 2^64) with T < 2^75: 192-bit product, high part */
+  uint64_t r1 = o_rng(seed, key, (uint64_t)h, 1);
+  uint64_t Tlo = (uint64_t)T, Thi = (uint64_t)(T >> 64);
+  u128 plo = (u128)r1 * (u128)Tlo;
+  u128 t = (plo >> 64) + (u128)r1 * (u128)Thi;
+  u128 acc = 0;
+  int32_t i2 = -1;
+  for (int32_t i = 0; i < n; ++i) {
+    acc += (u128)(uint64_t)dd[i];
+    if (acc > t) { i2 = i; break; }
+  }
+  free(dd);
+  int32_t v2 = ids[i2];
+  double c1[4], c2[4], r[4], delta;
+  for (int d = 0; d < 4; ++d) { c1[d] = (double)q[d * stride + v1]; c2[d] = (double)q[d * stride + v2]; }
+  plane_from(c1, c2, r, &delta);
+  int64_t cnt[2] = {0, 0};
+  for (int32_t i = 0; i < n; ++i) {
+    double s = splane(q, stride, ids[i], r, delta);
+    side[i] = s <= 0.0 ? 1 : 2;
+    cnt[side[i] - 1]++;
+  }
+  if (cnt[0] == 0 || cnt[1] == 0) return 1;
+  for (int32_t it = 1; it <= t_max; ++it) {
+    int64_t S[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    int64_t N[2] = {0, 0};
+    for (int32_t i = 0; i < n; ++i) {
+      int a = side[i] - 1;
+      N[a]++;
+      for (int d = 0; d < 4; ++d) S[a][d] += (int64_t)q[d * stride + ids[i]];
+    }
+    double m1[4], m2[4], rr[4], dl;
+    for (int d = 0; d < 4; ++d) {
+      m1[d] = (double)S[0][d] / (double)N[0];
+      m2[d] = (double)S[1][d] / (double)N[1];
+    }
+    plane_from(m1, m2, rr, &dl);
+    int64_t nc[2] = {0, 0};
+    int changed = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      double s = splane(q, stride, ids[i], rr, dl);
+      uint8_t sd = s <= 0.0 ? 1 : 2;
+      if (sd != side[i]) changed = 1;
+      side[i] = sd;
+      nc[sd - 1]++;
+    }
+    memcpy(c1, m1, sizeof c1);
+    memcpy(c2, m2, sizeof c2);
+    memcpy(r, rr, sizeof r);
+    delta = dl;
+    *iters = it;
+    if (nc[0] == 0 || nc[1] == 0) return 1;
+    if (!changed) break;
+  }
+  for (int d = 0; d < 4; ++d) { cen[0][d] = c1[d]; cen[1][d] = c2[d]; plane[d] = r[d]; }
+  plane[4] = delta;
+  return 0;
+}
+
+/* One split of a whole point set (vmo_bisect): quantize, then o_split on all
+   k points with job 0, node 1.  side[v] = 0 for part 1, 1 for part 2.
+   centres [2][4] reported in coordinates: lo + c / scale, rounded to FP32.
+   Returns 0 split, 1 unsplittable (side all 0), <0 error. */
+int o_bisect(int32_t k, const float* x, uint64_t seed, int32_t t_max, uint8_t* side_out,
+             float* centres, int32_t* iters, double* plane_out) {
+  if (k < 1) return -1;
+  uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * 4 * (size_t)k);
+  float lo[4];
+  double s;
+  if (o_quantize(k, x, q, lo, &s)) { free(q); return -1; }
+  int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  for (int32_t i = 0; i < k; ++i) ids[i] = i;
+  uint8_t* sd = (uint8_t*)malloc((size_t)k);
+  double cen[2][4], plane[5];
+  int rc = 1;
+  *iters = 0;
+  if (k >= 2) rc = o_split(q, (size_t)k, ids, k, seed, 0, 1, t_max, sd, cen, plane, iters);
+  if (rc == 0) {
+    for (int32_t i = 0; i < k; ++i) side_out[i] = (uint8_t)(sd[i] - 1);
+    for (int a = 0; a < 2; ++a)
+      for (int d = 0; d < 4; ++d) centres[a * 4 + d] = (float)((double)lo[d] + cen[a][d] / s);
+    if (plane_out) for (int d = 0; d < 5; ++d) plane_out[d] = plane[d];
+  } else {
+    for (int32_t i = 0; i < k; ++i) side_out[i] = 0;
+    for (int a = 0; a < 2; ++a) for (int d = 0; d < 4; ++d) centres[a * 4 + d] = 0.0f;
+  }
+  free(q); free(ids); free(sd);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Recursive ordering. */
+typedef struct {
+  int exists, leaf, K, p0;
+  int32_t* verts; int32_t nv;   /* leaf: its vertices; internal: unused      */
+  int32_t* sep; int32_t ns;     /* graph mode separator S_h (ascending)       */
+  int32_t* nets; int32_t nn;    /* net mode: nets alive at this node          */
+} ONode;
+
+static void emit_walk(ONode* nd, int32_t nmax, int32_t h, int post, int32_t* order, int32_t* cnt) {
+  if (h >= nmax || !nd[h].exists) return;
+  if (nd[h].leaf) { order[(*cnt)++] = h; return; }
+  emit_walk(nd, nmax, 2 * h, post, order, cnt);
+  if (!post) order[(*cnt)++] = h;
+  emit_walk(nd, nmax, 2 * h + 1, post, order, cnt);
+  if (post) order[(*cnt)++] = h;
+}
+
+/* mode 0 = net mode (cut nets placed at the node that splits them),
+   mode 1 = graph mode (Algorithm 7 vertex separator; nets must be edges
+   {v, w} with v < w).  ord 0 = SBD (in-order), 1 = BBD (post-order).
+   Outputs (caller allocated): vperm[k], nperm[l] (net mode; may be NULL),
+   part[k], node_heap[4P], node_vptr[4P+1], node_nptr[4P+2] (net mode; may be
+   NULL), split_cut[4P] (by emission rank), n_nodes[1].  Returns 0 or <0. */
+int o_order(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* c,
+            int mode, int ord, const float* x, int32_t P, uint64_t seed, uint64_t job, int32_t t_max,
+            int32_t* vperm, int32_t* nperm, int32_t* part, int32_t* node_heap, int32_t* node_vptr,
+            int32_t* node_nptr, double* split_cut, int32_t* n_nodes_out) {
+  if (k < 1 || P < 1 || l < 0) return -1;
+  if (mode == 1)
+    for (int32_t e = 0; e < l; ++e)
+      if (ptr[e + 1] - ptr[e] != 2 || pins[ptr[e]] >= pins[ptr[e] + 1]) return -1;
+  int32_t nmax = 4 * P;
+  uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * 4 * (size_t)k);
+  float lo[4];
+  double sc;
+  if (o_quantize(k, x, q, lo, &sc)) { free(q); return -1; }
+  ONode* nd = (ONode*)calloc((size_t)nmax, sizeof(ONode));
+  int32_t* netnode = (int32_t*)malloc(sizeof(int32_t) * (size_t)(l > 0 ? l : 1));
+  int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  uint8_t* sd_of = (uint8_t*)malloc((size_t)k);
+  double* s_of = (double*)malloc(sizeof(double) * (size_t)k);
+  char* in_sep = (char*)calloc((size_t)k, 1);
+  for (int32_t v = 0; v < k; ++v) mark[v] = 0;
+  for (int32_t e = 0; e < l; ++e) netnode[e] = -1; /* -1 = empty net */
+  nd[1].exists = 1; nd[1].K = P; nd[1].p0 = 0;
+  nd[1].verts = (int32_t*)malloc(sizeof(int32_t) * (size_t)k); nd[1].nv = k;
+  for (int32_t v = 0; v < k; ++v) nd[1].verts[v] = v;
+  if (mode == 0) {
+    nd[1].nets = (int32_t*)malloc(sizeof(int32_t) * (size_t)(l > 0 ? l : 1));
+    for (int32_t e = 0; e < l; ++e) if (ptr[e + 1] > ptr[e]) nd[1].nets[nd[1].nn++] = e;
+  }
+  for (int32_t h = 1; h < nmax; ++h) {
+    ONode* N = &nd[h];
+    if (!N->exists) continue;
+    int32_t n = N->nv;
+    uint8_t* side = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+    double cen[2][4], plane[5];
+    int32_t its;
+    int rc = 1;
+    if (N->K > 1 && n >= 2) rc = o_split(q, (size_t)k, N->verts, n, seed, job, h, t_max, side, cen, plane, &its);
+    if (rc != 0) {
+      N->leaf = 1;
+      for (int32_t i = 0; i < N->nn; ++i) netnode[N->nets[i]] = h;
+      free(side);
+      continue;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+      int32_t v = N->verts[i];
+      mark[v] = h; sd_of[v] = side[i];
+      s_of[v] = splane(q, (size_t)k, v, plane, plane[4]);
+    }
+    if (mode == 1) {
+      /* Algorithm 7 separator: edges in order; a cut edge whose ends are both
+         still in parts 1/2 sends the end nearer the plane into S (ties: v). */
+      N->sep = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+      for (int32_t e = 0; e < l; ++e) {
+        int32_t a = pins[ptr[e]], b = pins[ptr[e] + 1];
+        if (mark[a] != h || mark[b] != h) continue;
+        if (in_sep[a] || in_sep[b]) continue;
+        if (sd_of[a] == sd_of[b]) continue;
+        if (fabs(s_of[a]) <= fabs(s_of[b])) in_sep[a] = 1; else in_sep[b] = 1;
+      }
+      for (int32_t i = 0; i < n; ++i) if (in_sep[N->verts[i]]) N->sep[N->ns++] = N->verts[i];
+    }
+    int32_t Kl = (N->K + 1) / 2, Kr = N->K / 2;
+    ONode* L = &nd[2 * h];
+    ONode* R = &nd[2 * h + 1];
+    L->exists = R->exists = 1;
+    L->K = Kl; L->p0 = N->p0; R->K = Kr; R->p0 = N->p0 + Kl;
+    L->verts = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    R->verts = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+      int32_t v = N->verts[i];
+      if (in_sep[v]) continue;
+      if (side[i] == 1) L->verts[L->nv++] = v; else R->verts[R->nv++] = v;
+    }
+    if (mode == 0) {
+      L->nets = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N->nn > 0 ? N->nn : 1));
+      R->nets = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N->nn > 0 ? N->nn : 1));
+      for (int32_t i = 0; i < N->nn; ++i) {
+        int32_t e = N->nets[i];
+        int has1 = 0, has2 = 0;
+        for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) {
+          if (sd_of[pins[p]] == 1) has1 = 1; else has2 = 1;
+        }
+        if (has1 && has2) netnode[e] = h;
+        else if (has1) L->nets[L->nn++] = e;
+        else R->nets[R->nn++] = e;
+      }
+    }
+    free(side);
+  }
+  /* emission */
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)nmax);
+  int32_t nnodes = 0;
+  emit_walk(nd, nmax, 1, ord == 1, order, &nnodes);
+  int32_t vp = 0;
+  for (int32_t r = 0; r < nnodes; ++r) {
+    int32_t h = order[r];
+    node_heap[r] = h;
+    node_vptr[r] = vp;
+    if (nd[h].leaf) {
+      for (int32_t i = 0; i < nd[h].nv; ++i) { vperm[vp++] = nd[h].verts[i]; part[nd[h].verts[i]] = nd[h].p0; }
+    } else {
+      for (int32_t i = 0; i < nd[h].ns; ++i) { vperm[vp++] = nd[h].sep[i]; part[nd[h].sep[i]] = P + h; }
+    }
+    split_cut[r] = 0.0;
+    if (mode == 1 && !nd[h].leaf) split_cut[r] = (double)nd[h].ns;
+  }
+  for (int32_t r = nnodes; r < nmax; ++r) { node_heap[r] = -1; node_vptr[r] = k; split_cut[r] = 0.0; }
+  node_vptr[nmax] = k;
+  if (mode == 0) {
+    int32_t np = 0;
+    for (int32_t r = 0; r < nnodes; ++r) {
+      int32_t h = order[r];
+      if (node_nptr) node_nptr[r] = np;
+      for (int32_t e = 0; e < l; ++e)
+        if (netnode[e] == h) {
+          if (nperm) nperm[np] = e;
+          np++;
+          if (!nd[h].leaf) split_cut[r] += c ? (double)c[e] : 1.0;
+        }
+    }
+    if (node_nptr) node_nptr[nnodes] = np;
+    for (int32_t e = 0; e < l; ++e) if (netnode[e] < 0) { if (nperm) nperm[np] = e; np++; }
+    if (node_nptr) for (int32_t r = nnodes + 1; r <= nmax + 1; ++r) node_nptr[r] = l;
+  }
+  *n_nodes_out = nnodes;
+  for (int32_t h = 0; h < nmax; ++h) { free(nd[h].verts); free(nd[h].sep); free(nd[h].nets); }
+  free(nd); free(order); free(q); free(netnode); free(mark); free(sd_of); free(s_of); free(in_sep);
+  return 0;
+}
+
+/* ========================================================================= */
+/* Layout (Section 2).                                                        */
+
+typedef struct {
+  uint64_t seed;
+  int32_t coarsest_iters, level_iters, min_coarse, max_levels, leaf_cap, match_max_net;
+  float theta, step0_frac, decay, jitter, stall, pack_gap;
+} o_layout_params;
+
+/* ---- coarsening ---------------------------------------------------------- */
+typedef struct { int32_t u, v; double om; uint64_t hs; } OPair;
+
+static int cmp_pair_uv(const void* a, const void* b) {
+  const OPair* x = (const OPair*)a; const OPair* y = (const OPair*)b;
+  if (x->u != y->u) return x->u < y->u ? -1 : 1;
+  if (x->v != y->v) return x->v < y->v ? -1 : 1;
+  if (x->om != y->om) return x->om > y->om ? -1 : 1;
+  return 0;
+}
+/* priority: larger omega first, then larger hash, then smaller (u, v) */
+static int cmp_pair_prio(const void* a, const void* b) {
+  const OPair* x = (const OPair*)a; const OPair* y = (const OPair*)b;
+  if (x->om != y->om) return x->om > y->om ? -1 : 1;
+  if (x->hs != y->hs) return x->hs > y->hs ? -1 : 1;
+  if (x->u != y->u) return x->u < y->u ? -1 : 1;
+  if (x->v != y->v) return x->v < y->v ? -1 : 1;
+  return 0;
+}
+
+typedef struct { int32_t e, len; const int32_t* p; } ONetImg;
+static int cmp_img(const void* a, const void* b) {
+  const ONetImg* x = (const ONetImg*)a; const ONetImg* y = (const ONetImg*)b;
+  int32_t m = x->len < y->len ? x->len : y->len;
+  for (int32_t i = 0; i < m; ++i) if (x->p[i] != y->p[i]) return x->p[i] < y->p[i] ? -1 : 1;
+  if (x->len != y->len) return x->len < y->len ? -1 : 1;
+  return (x->e > y->e) - (x->e < y->e);
+}
+typedef struct { int32_t rep, len; const int32_t* p; float c; } OCNet;
+static int cmp_cnet(const void* a, const void* b) {
+  const OCNet* x = (const OCNet*)a; const OCNet* y = (const OCNet*)b;
+  return (x->rep > y->rep) - (x->rep < y->rep);
+}
+
+/* One coarsening step (Sec. 2.3).  Candidate pairs share a net e with
+   2 <= |e| <= match_max; omega(pair) = max over shared candidate nets of
+   c(e)/(|e|-1).  Greedy maximal matching in decreasing priority (omega, hash,
+   then smaller ids); then each unmatched vertex with exactly one candidate
+   neighbour joins that neighbour's group.  Groups are numbered by their
+   smallest member.  Coarse weight = sum of member weights (ascending member
+   id); a net's image is the set of its members' groups; images of size < 2
+   are dropped, equal images merge with summed cost (ascending net id) and
+   are ordered by their smallest net id.
+   Outputs: pi[k]; *kc, *lc; cptr[l+1], cpins[ptr[l]], cw[k], cc[l] (upper
+   bounds on size; caller allocates). */
+int o_coarsen(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+              const float* c, uint64_t seed, uint64_t comp, int32_t level, int32_t match_max,
+              int32_t* pi, int32_t* kc_out, int32_t* lc_out, int64_t* cptr, int32_t* cpins,
+              float* cw, float* cc) {
+  /* candidate pairs */
+  int64_t np = 0;
+  for (int32_t e = 0; e < l; ++e) {
+    int64_t s = ptr[e + 1] - ptr[e];
+    if (s >= 2 && s <= match_max) np += s * (s - 1) / 2;
+  }
+  OPair* pr = (OPair*)malloc(sizeof(OPair) * (size_t)(np > 0 ? np : 1));
+  int64_t t = 0;
+  for (int32_t e = 0; e < l; ++e) {
+    int64_t s = ptr[e + 1] - ptr[e];
+    if (s < 2 || s > match_max) continue;
+    double om = (double)(c ? c[e] : 1.0f) / (double)(s - 1);
+    for (int64_t i = 0; i < s; ++i)
+      for (int64_t j = i + 1; j < s; ++j) {
+        pr[t].u = pins[ptr[e] + i]; pr[t].v = pins[ptr[e] + j]; pr[t].om = om; ++t;
+      }
+  }
+  qsort(pr, (size_t)np, sizeof(OPair), cmp_pair_uv);
+  int64_t nu = 0;
+  for (int64_t i = 0; i < np; ++i)
+    if (nu == 0 || pr[i].u != pr[nu - 1].u || pr[i].v != pr[nu - 1].v) pr[nu++] = pr[i];
+  uint64_t mkey = TAG_MATCH | ((uint64_t)level << 8) | (comp << 32);
+  int32_t* nbr_cnt = (int32_t*)calloc((size_t)k, sizeof(int32_t));
+  int32_t* nbr_one = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  for (int64_t i = 0; i < nu; ++i) {
+    pr[i].hs = o_rng(seed, mkey, (uint64_t)pr[i].u, (uint64_t)pr[i].v);
+    nbr_cnt[pr[i].u]++; nbr_one[pr[i].u] = pr[i].v;
+    nbr_cnt[pr[i].v]++; nbr_one[pr[i].v] = pr[i].u;
+  }
+  qsort(pr, (size_t)nu, sizeof(OPair), cmp_pair_prio);
+  int32_t* mate = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  for (int32_t v = 0; v < k; ++v) mate[v] = -1;
+  for (int64_t i = 0; i < nu; ++i)
+    if (mate[pr[i].u] < 0 && mate[pr[i].v] < 0) { mate[pr[i].u] = pr[i].v; mate[pr[i].v] = pr[i].u; }
+  /* group roots */
+  int32_t* root = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  for (int32_t v = 0; v < k; ++v) root[v] = mate[v] >= 0 ? (v < mate[v] ? v : mate[v]) : v;
+  for (int32_t v = 0; v < k; ++v)
+    if (mate[v] < 0 && nbr_cnt[v] == 1) {
+      int32_t u = nbr_one[v];
+      root[v] = mate[u] >= 0 ? (u < mate[u] ? u : mate[u]) : u;
+    }
+  int32_t* gmin = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  for (int32_t v = 0; v < k; ++v) gmin[v] = k;
+  for (int32_t v = 0; v < k; ++v) if (v < gmin[root[v]]) gmin[root[v]] = v;
+  int32_t* cid = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  int32_t kc = 0;
+  for (int32_t v = 0; v < k; ++v) cid[v] = -1;
+  for (int32_t v = 0; v < k; ++v) if (gmin[root[v]] == v) cid[v] = kc++;
+  for (int32_t v = 0; v < k; ++v) pi[v] = cid[gmin[root[v]]];
+  for (int32_t g = 0; g < kc; ++g) cw[g] = 0.0f;
+  for (int32_t v = 0; v < k; ++v) cw[pi[v]] = cw[pi[v]] + (w ? w[v] : 1.0f);
+  /* net images */
+  int32_t* img = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ptr[l] > 0 ? ptr[l] : 1));
+  ONetImg* im = (ONetImg*)malloc(sizeof(ONetImg) * (size_t)(l > 0 ? l : 1));
+  int32_t nim = 0;
+  for (int32_t e = 0; e < l; ++e) {
+    int64_t s = ptr[e + 1] - ptr[e];
+    int32_t* b = img + ptr[e];
+    for (int64_t i = 0; i < s; ++i) b[i] = pi[pins[ptr[e] + i]];
+    qsort(b, (size_t)s, sizeof(int32_t), cmp_i32);
+    int32_t u = 0;
+    for (int64_t i = 0; i < s; ++i) if (u == 0 || b[i] != b[u - 1]) b[u++] = b[i];
+    if (u >= 2) { im[nim].e = e; im[nim].len = u; im[nim].p = b; ++nim; }
+  }
+  qsort(im, (size_t)nim, sizeof(ONetImg), cmp_img);
+  OCNet* cn = (OCNet*)malloc(sizeof(OCNet) * (size_t)(nim > 0 ? nim : 1));
+  int32_t ncn = 0;
+  for (int32_t i = 0; i < nim; ++i) {
+    int same = ncn > 0 && cn[ncn - 1].len == im[i].len &&
+               memcmp(cn[ncn - 1].p, im[i].p, sizeof(int32_t) * (size_t)im[i].len) == 0;
+    float ce = c ? c[im[i].e] : 1.0f;
+    if (same) { cn[ncn - 1].c = cn[ncn - 1].c + ce; }
+    else { cn[ncn].rep = im[i].e; cn[ncn].len = im[i].len; cn[ncn].p = im[i].p; cn[ncn].c = ce; ++ncn; }
+  }
+  qsort(cn, (size_t)ncn, sizeof(OCNet), cmp_cnet);
+  cptr[0] = 0;
+  for (int32_t j = 0; j < ncn; ++j) {
+    memcpy(cpins + cptr[j], cn[j].p, sizeof(int32_t) * (size_t)cn[j].len);
+    cptr[j + 1] = cptr[j] + cn[j].len;
+    cc[j] = cn[j].c;
+  }
+  *kc_out = kc; *lc_out = ncn;
+  free(pr); free(nbr_cnt); free(nbr_one); free(mate); free(root); free(gmin); free(cid);
+  free(img); free(im); free(cn);
+  return 0;
+}
+
+/* ---- 2^d-tree ------------------------------------------------------------ */
+/* Node layout in pre-order.  A node at depth L covers one cell of side
+   2^(16-L) key units of a 2^16 grid over the bounding cube of the points
+   (side = largest bbox side).  It is a leaf if it holds <= leaf_cap points or
+   L = 16; otherwise its children are its non-empty sub-cells in Morton digit
+   order.  next = index just after the node's subtree (n_nodes = end).
+   Charges: W = sum of weights, X = weighted mean, both summed bottom-up in
+   FP64 (leaf: its points in sorted order; internal: its children in order). */
+typedef struct {
+  int32_t first, count, depth, leaf, next;
+  int32_t cell2[4];   /* cell centre x 2, key units */
+  float W, X[4];
+  double Wd, Sd[4];
+} OTNode;
+
+typedef struct {
+  int32_t k, n, cap, nalloc;
+  uint32_t* kq;        /* [4][k] 16-bit key coordinates, by vertex        */
+  uint64_t* key;       /* [k] Morton key, by vertex                       */
+  int32_t* order;      /* [k] vertices sorted by (key, id)                */
+  OTNode* nd;
+} OTree;
+
+static const uint64_t* g_sort_keys;
+static int cmp_by_key(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  uint64_t kx = g_sort_keys[x], ky = g_sort_keys[y];
+  if (kx != ky) return kx < ky ? -1 : 1;
+  return (x > y) - (x < y);
+}
+
+static int digit_of(uint64_t key, int depth) { return (int)((key >> (4 * (16 - depth))) & 15u); }
+
+static int32_t tree_build_rec(OTree* T, int32_t first, int32_t count, int depth, const float* x,
+                              const float* w) {
+  if (T->n == T->nalloc) {
+    T->nalloc = 2 * T->nalloc + 64;
+    T->nd = (OTNode*)realloc(T->nd, sizeof(OTNode) * (size_t)T->nalloc);
+  }
+  int32_t me = T->n++;
+  OTNode* N = &T->nd[me];
+  N->first = first; N->count = count; N->depth = depth;
+  int32_t side = 1 << (16 - depth);
+  int32_t v0 = T->order[first];
+  for (int d = 0; d < 4; ++d) {
+    int32_t lo = (int32_t)((T->kq[(size_t)d * T->k + v0] >> (16 - depth)) << (16 - depth));
+    if (depth == 0) lo = 0;
+    N->cell2[d] = 2 * lo + side;
+  }
+  double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+  if (count <= T->cap || depth == 16) {
+    N->leaf = 1;
+    for (int32_t i = first; i < first + count; ++i) {
+      int32_t v = T->order[i];
+      double wv = (double)w[v];
+      Wd += wv;
+      for (int d = 0; d < 4; ++d) Sd[d] += wv * (double)x[(size_t)d * T->k + v];
+    }
+  } else {
+    N->leaf = 0;
+    int32_t i = first;
+    while (i < first + count) {
+      int dg = digit_of(T->key[T->order[i]], depth + 1);
+      int32_t j = i;
+      while (j < first + count && digit_of(T->key[T->order[j]], depth + 1) == dg) ++j;
+      int32_t ch = tree_build_rec(T, i, j - i, depth + 1, x, w);
+      Wd += T->nd[ch].Wd;
+      for (int d = 0; d < 4; ++d) Sd[d] += T->nd[ch].Sd[d];
+      i = j;
+    }
+    N = &T->nd[me];
+  }
+  N->Wd = Wd;
+  for (int d = 0; d < 4; ++d) N->Sd[d] = Sd[d];
+  N->W = (float)Wd;
+  for (int d = 0; d < 4; ++d) N->X[d] = (float)(Sd[d] / Wd);
+  N->next = T->n;
+  return me;
+}
+
+static int otree_build(OTree* T, int32_t k, const float* x, const float* w, int32_t cap) {
+  T->k = k; T->cap = cap; T->n = 0;
+  T->kq = (uint32_t*)malloc(sizeof(uint32_t) * 4 * (size_t)k);
+  T->key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)k);
+  T->order = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  T->nalloc = 2 * k + 64;
+  T->nd = (OTNode*)malloc(sizeof(OTNode) * (size_t)T->nalloc);
+  float lo[4], hi[4];
+  for (int d = 0; d < 4; ++d) {
+    lo[d] = hi[d] = x[(size_t)d * k];
+    for (int32_t i = 0; i < k; ++i) {
+      float v = x[(size_t)d * k + i];
+      if (!isfinite(v)) return -1;
+      if (v < lo[d]) lo[d] = v;
+      if (v > hi[d]) hi[d] = v;
+    }
+  }
+  double ext = 0.0;
+  for (int d = 0; d < 4; ++d) { double e = (double)hi[d] - (double)lo[d]; if (e > ext) ext = e; }
+  double s = ext > 0.0 ? 65536.0 / ext : 0.0;
+  for (int32_t i = 0; i < k; ++i) {
+    uint64_t key = 0;
+    uint32_t kq[4];
+    for (int d = 0; d < 4; ++d) {
+      uint32_t v = 0;
+      if (s > 0.0) {
+        double f = floor(((double)x[(size_t)d * k + i] - (double)lo[d]) * s);
+        v = f >= 65535.0 ? 65535u : (uint32_t)f;
+      }
+      kq[d] = v;
+      T->kq[(size_t)d * k + i] = v;
+    }
+    for (int b = 15; b >= 0; --b)
+      for (int d = 0; d < 4; ++d) key = (key << 1) | ((kq[d] >> b) & 1u);
+    T->key[i] = key;
+    T->order[i] = i;
+  }
+  g_sort_keys = T->key;
+  qsort(T->order, (size_t)k, sizeof(int32_t), cmp_by_key);
+  tree_build_rec(T, 0, k, 0, x, w);
+  return 0;
+}
+static void otree_free(OTree* T) { free(T->kq); free(T->key); free(T->order); free(T->nd); }
+
+/* Exported for tree parity: node fields in pre-order.  ints[n][8] = first,
+   count, depth, leaf, next, and three zeros; cell2[n][4]; flt[n][5] = W, X0..X3.
+   order_out[k] = vertices in sorted order.  Returns the node count, <0 error. */
+int o_tree(int32_t k, const float* x, const float* w, int32_t cap, int32_t* ints, int32_t* cell2,
+           float* flt, int32_t* order_out, int32_t max_nodes) {
+  OTree T;
+  if (otree_build(&T, k, x, w, cap)) { otree_free(&T); return -1; }
+  if (T.n > max_nodes) { otree_free(&T); return -2; }
+  for (int32_t t = 0; t < T.n; ++t) {
+    OTNode* N = &T.nd[t];
+    int32_t* r = ints + 8 * (size_t)t;
+    r[0] = N->first; r[1] = N->count; r[2] = N->depth; r[3] = N->leaf; r[4] = N->next;
+    r[5] = r[6] = r[7] = 0;
+    for (int d = 0; d < 4; ++d) cell2[4 * (size_t)t + d] = N->cell2[d];
+    flt[5 * (size_t)t] = N->W;
+    for (int d = 0; d < 4; ++d) flt[5 * (size_t)t + 1 + d] = N->X[d];
+  }
+  for (int32_t i = 0; i < k; ++i) order_out[i] = T.order[i];
+  int32_t n = T.n;
+  otree_free(&T);
+  return n;
+}
+
+/* Interaction of point n with charge W at X: (d-2) W w_n |X-x|^-4 (X-x). */
+static void interact(float* y, const float* xn, float wn, const float* X, float W) {
+  float dx[4];
+  for (int d = 0; d < 4; ++d) dx[d] = X[d] - xn[d];
+  float r2 = dx[0] * dx[0];
+  r2 = r2 + dx[1] * dx[1];
+  r2 = r2 + dx[2] * dx[2];
+  r2 = r2 + dx[3] * dx[3];
+  if (!(r2 > 0.0f)) return;
+  float num = 2.0f * W;
+  num = num * wn;
+  float den = r2 * r2;
+  float f = num / den;
+  for (int d = 0; d < 4; ++d) y[d] = y[d] + f * dx[d];
+}
+
+static int node_far(const OTNode* N, const int32_t* p2, double th2) {
+  if (!(th2 > 0.0)) return 0;
+  int64_t D2 = 0;
+  for (int d = 0; d < 4; ++d) { int64_t t = (int64_t)p2[d] - (int64_t)N->cell2[d]; D2 += t * t; }
+  int64_t s2 = (int64_t)2 << (16 - N->depth);
+  return (double)(s2 * s2) < th2 * (double)D2;
+}
+
+/* Depth-first walk: far node -> one cluster charge; near internal node ->
+   its children in order; near leaf -> every other point of the leaf. */
+static void walk_rec(const OTree* T, int32_t t, int32_t n, const float* xn, float wn,
+                     const int32_t* p2, double th2, const float* x, const float* w, float* y) {
+  const OTNode* N = &T->nd[t];
+  if (node_far(N, p2, th2)) { interact(y, xn, wn, N->X, N->W); return; }
+  if (!N->leaf) {
+    int32_t ch = t + 1;
+    while (ch != N->next) { walk_rec(T, ch, n, xn, wn, p2, th2, x, w, y); ch = T->nd[ch].next; }
+    return;
+  }
+  for (int32_t i = N->first; i < N->first + N->count; ++i) {
+    int32_t v = T->order[i];
+    if (v == n) continue;
+    float xv[4];
+    for (int d = 0; d < 4; ++d) xv[d] = x[(size_t)d * T->k + v];
+    interact(y, xn, wn, xv, w[v]);
+  }
+}
+
+/* Net centres z_j = (sum of pins) / |e_j|, pins summed in CSR order. */
+static void centres(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* x, float* z) {
+  for (int32_t e = 0; e < l; ++e) {
+    int64_t s = ptr[e + 1] - ptr[e];
+    for (int d = 0; d < 4; ++d) {
+      float a = 0.0f;
+      for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) a = a + x[(size_t)d * k + pins[p]];
+      z[(size_t)d * l + e] = s > 0 ? a / (float)s : 0.0f;
+    }
+  }
+}
+
+/* Gradient (eq. 7): attraction over the vertex's nets in ascending net
+   order, then the tree walk.  y is [4][k]. */
+static int gradient(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+                    const float* c, const float* x, float theta, int32_t cap, float* y) {
+  float* z = (float*)malloc(sizeof(float) * 4 * (size_t)(l > 0 ? l : 1));
+  centres(k, l, ptr, pins, x, z);
+  int64_t* dptr = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k + 1));
+  int32_t* dp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ptr[l] > 0 ? ptr[l] : 1));
+  o_dual(k, l, ptr, pins, dptr, dp);
+  for (int32_t n = 0; n < k; ++n) {
+    for (int d = 0; d < 4; ++d) {
+      float a = 0.0f;
+      for (int64_t t = dptr[n]; t < dptr[n + 1]; ++t) {
+        int32_t e = dp[t];
+        float ce = c ? c[e] : 1.0f;
+        float df = x[(size_t)d * k + n] - z[(size_t)d * l + e];
+        a = a + ce * df;
+      }
+      y[(size_t)d * k + n] = a;
+    }
+  }
+  free(z); free(dptr); free(dp);
+  OTree T;
+  if (otree_build(&T, k, x, w, cap)) { otree_free(&T); return -1; }
+  double th2 = (double)theta * (double)theta;
+  for (int32_t n = 0; n < k; ++n) {
+    float xn[4], yn[4];
+    int32_t p2[4];
+    for (int d = 0; d < 4; ++d) {
+      xn[d] = x[(size_t)d * k + n];
+      yn[d] = y[(size_t)d * k + n];
+      p2[d] = 2 * (int32_t)T.kq[(size_t)d * k + n] + 1;
+    }
+    walk_rec(&T, 0, n, xn, w[n], p2, th2, x, w, yn);
+    for (int d = 0; d < 4; ++d) y[(size_t)d * k + n] = yn[d];
+  }
+  otree_free(&T);
+  return 0;
+}
+
+/* Exported gradient for parity of the attraction/repulsion kernels. */
+int o_gradient(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+               const float* c, const float* x, float theta, int32_t cap, float* y, float* z) {
+  if (z) centres(k, l, ptr, pins, x, z);
+  return gradient(k, l, ptr, pins, w, c, x, theta, cap, y);
+}
+
+/* One steepest-descent step (Algorithm 3).  it = step index at this level;
+   *alpha carries the step length between calls.  At it == 0 it is set from
+   the bounding box, alpha = step0 * V^(1/4) (V = box volume; if V = 0 the
+   largest side replaces V^(1/4)); afterwards alpha <- decay * alpha.  Each
+   vertex is then moved a distance alpha against its own gradient:
+   x_n <- x_n - (alpha / |y_n|) y_n  (vertices with y_n = 0 stay).  This is
+   the reading of "comparing the bounding box volume to the individual
+   gradients of the vertices" with the step rule of the cited force-directed
+   method (Hu 2005). */
+int o_layout_iter(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+                  const float* c, float* x, const o_layout_params* P, int32_t it, double* alpha,
+                  float* y_out) {
+  float* y = (float*)malloc(sizeof(float) * 4 * (size_t)k);
+  if (gradient(k, l, ptr, pins, w, c, x, P->theta, P->leaf_cap, y)) { free(y); return -1; }
+  if (it == 0) {
+    float lo[4], hi[4];
+    for (int d = 0; d < 4; ++d) {
+      lo[d] = hi[d] = x[(size_t)d * k];
+      for (int32_t i = 0; i < k; ++i) {
+        float v = x[(size_t)d * k + i];
+        if (v < lo[d]) lo[d] = v;
+        if (v > hi[d]) hi[d] = v;
+      }
+    }
+    double V = 1.0, ext = 0.0;
+    for (int d = 0; d < 4; ++d) {
+      double e = (double)hi[d] - (double)lo[d];
+      V = V * e;
+      if (e > ext) ext = e;
+    }
+    double side = V > 0.0 ? sqrt(sqrt(V)) : ext;
+    *alpha = (double)P->step0_frac * side;
+  } else {
+    *alpha = *alpha * (double)P->decay;
+  }
+  for (int32_t i = 0; i < k; ++i) {
+    float yv[4];
+    for (int d = 0; d < 4; ++d) yv[d] = y[(size_t)d * k + i];
+    float n2 = yv[0] * yv[0];
+    n2 = n2 + yv[1] * yv[1];
+    n2 = n2 + yv[2] * yv[2];
+    n2 = n2 + yv[3] * yv[3];
+    if (!(n2 > 0.0f)) continue;
+    float f = (float)(*alpha / sqrt((double)n2));
+    for (int d = 0; d < 4; ++d) {
+      float t = f * yv[d];
+      x[(size_t)d * k + i] = x[(size_t)d * k + i] - t;
+    }
+  }
+  if (y_out) memcpy(y_out, y, sizeof(float) * 4 * (size_t)k);
+  free(y);
+  return 0;
+}
+
+/* Random start of the coarsest level: x = (u - 1/2) k^(1/4), u a 24-bit
+   uniform in [0,1). */
+void o_layout_init(int32_t k, uint64_t seed, uint64_t comp, int32_t level, float* x) {
+  float a = (float)sqrt(sqrt((double)k));
+  uint64_t key = TAG_INIT | ((uint64_t)level << 8) | (comp << 32);
+  for (int32_t v = 0; v < k; ++v)
+    for (int d = 0; d < 4; ++d) {
+      uint64_t r = o_rng(seed, key, (uint64_t)v, (uint64_t)d);
+      float u = (float)(uint32_t)(r >> 40) * 0x1p-24f;
+      x[(size_t)d * k + v] = (u - 0.5f) * a;
+    }
+}
+
+/* Prolongation (Algorithm 2): x_f(v) = sigma x_c(pi(v)) + eps u, sigma =
+   (k_f/k_c)^(1/4), eps = jitter * (largest side of x_c) / k_c^(1/4),
+   u uniform in [-1, 1) (24-bit grid), keyed by the fine level index. */
+void o_layout_prolong(int32_t kf, int32_t kc, const int32_t* pi, const float* xc, uint64_t seed,
+                      uint64_t comp, int32_t flevel, float jitter, float* xf) {
+  float lo[4], hi[4];
+  for (int d = 0; d < 4; ++d) {
+    lo[d] = hi[d] = xc[(size_t)d * kc];
+    for (int32_t i = 0; i < kc; ++i) {
+      float v = xc[(size_t)d * kc + i];
+      if (v < lo[d]) lo[d] = v;
+      if (v > hi[d]) hi[d] = v;
+    }
+  }
+  double ext = 0.0;
+  for (int d = 0; d < 4; ++d) { double e = (double)hi[d] - (double)lo[d]; if (e > ext) ext = e; }
+  float sigma = (float)sqrt(sqrt((double)kf / (double)kc));
+  double epsd = (double)jitter * ext;
+  float eps = (float)(epsd / sqrt(sqrt((double)kc)));
+  uint64_t key = TAG_PROLONG | ((uint64_t)flevel << 8) | (comp << 32);
+  for (int32_t v = 0; v < kf; ++v)
+    for (int d = 0; d < 4; ++d) {
+      uint64_t r = o_rng(seed, key, (uint64_t)v, (uint64_t)d);
+      float u = (float)(uint32_t)(r >> 40) * 0x1p-23f;
+      u = u - 1.0f;
+      float a = sigma * xc[(size_t)d * kc + pi[v]];
+      float b = eps * u;
+      xf[(size_t)d * kf + v] = a + b;
+    }
+}
+
+typedef struct { int32_t k, l; int64_t* ptr; int32_t* pins; float* w; float* c; int32_t* pi; } OLvl;
+
+/* Multilevel layout of one connected hypergraph (Algorithm 2). */
+static int layout_component(OLvl* G0, const o_layout_params* P, uint64_t comp, float* xout) {
+  int32_t cap_levels = P->max_levels + 1;
+  OLvl* L = (OLvl*)calloc((size_t)cap_levels, sizeof(OLvl));
+  L[0] = *G0;
+  int32_t J = 0;
+  while (L[J].k > P->min_coarse && J < P->max_levels) {
+    OLvl* F = &L[J];
+    OLvl C;
+    C.pi = (int32_t*)malloc(sizeof(int32_t) * (size_t)F->k);
+    C.ptr = (int64_t*)malloc(sizeof(int64_t) * (size_t)(F->l + 1));
+    C.pins = (int32_t*)malloc(sizeof(int32_t) * (size_t)(F->ptr[F->l] > 0 ? F->ptr[F->l] : 1));
+    C.w = (float*)malloc(sizeof(float) * (size_t)F->k);
+    C.c = (float*)malloc(sizeof(float) * (size_t)(F->l > 0 ? F->l : 1));
+    o_coarsen(F->k, F->l, F->ptr, F->pins, F->w, F->c, P->seed, comp, J, P->match_max_net, C.pi,
+              &C.k, &C.l, C.ptr, C.pins, C.w, C.c);
+    if ((double)C.k > (double)P->stall * (double)F->k) {
+      free(C.pi); free(C.ptr); free(C.pins); free(C.w); free(C.c);
+      break;
+    }
+    F->pi = C.pi;
+    C.pi = NULL;
+    L[J + 1] = C;
+    ++J;
+  }
+  float* x = (float*)malloc(sizeof(float) * 4 * (size_t)L[J].k);
+  o_layout_init(L[J].k, P->seed, comp, J, x);
+  for (int32_t j = J; j >= 0; --j) {
+    int32_t iters = j == J ? P->coarsest_iters : P->level_iters;
+    double alpha = 0.0;
+    for (int32_t it = 0; it < iters; ++it)
+      if (o_layout_iter(L[j].k, L[j].l, L[j].ptr, L[j].pins, L[j].w, L[j].c, x, P, it, &alpha, NULL))
+        return -1;
+    if (j > 0) {
+      float* xf = (float*)malloc(sizeof(float) * 4 * (size_t)L[j - 1].k);
+      o_layout_prolong(L[j - 1].k, L[j].k, L[j - 1].pi, x, P->seed, comp, j - 1, P->jitter, xf);
+      free(x);
+      x = xf;
+    }
+  }
+  memcpy(xout, x, sizeof(float) * 4 * (size_t)G0->k);
+  free(x);
+  for (int32_t j = 1; j <= J; ++j) { free(L[j].ptr); free(L[j].pins); free(L[j].w); free(L[j].c); free(L[j].pi); }
+  free(L[0].pi);
+  free(L);
+  return 0;
+}
+
+/* Full layout: components (minimum-id labels, ascending), each laid out
+   alone, then packed side by side along the first axis with gap
+   pack_gap * (largest component side).  x is [4][k]. */
+int o_layout(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+             const float* c, const o_layout_params* P, float* x) {
+  int32_t* label = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  if (o_components(k, l, ptr, pins, label)) { free(label); return -1; }
+  int32_t* local = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  int32_t* csize = (int32_t*)calloc((size_t)k, sizeof(int32_t));
+  for (int32_t v = 0; v < k; ++v) local[v] = csize[label[v]]++;
+  float* xl = (float*)malloc(sizeof(float) * 4 * (size_t)k);
+  /* per component layout into xl (component-local SoA blocks at offset) */
+  int32_t* coff = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  int32_t off = 0;
+  for (int32_t v = 0; v < k; ++v) if (label[v] == v) { coff[v] = off; off += csize[v]; }
+  int rc = 0;
+  for (int32_t r = 0; r < k && rc == 0; ++r) {
+    if (label[r] != r) continue;
+    int32_t kc = csize[r];
+    float* xc = xl + 4 * (size_t)coff[r];
+    if (kc == 1) { for (int d = 0; d < 4; ++d) xc[d] = 0.0f; continue; }
+    OLvl G;
+    memset(&G, 0, sizeof G);
+    G.k = kc;
+    int32_t nl = 0;
+    int64_t npins = 0;
+    for (int32_t e = 0; e < l; ++e)
+      if (ptr[e + 1] > ptr[e] && label[pins[ptr[e]]] == r) { nl++; npins += ptr[e + 1] - ptr[e]; }
+    G.l = nl;
+    G.ptr = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nl + 1));
+    G.pins = (int32_t*)malloc(sizeof(int32_t) * (size_t)(npins > 0 ? npins : 1));
+    G.w = (float*)malloc(sizeof(float) * (size_t)kc);
+    G.c = (float*)malloc(sizeof(float) * (size_t)(nl > 0 ? nl : 1));
+    G.ptr[0] = 0;
+    int32_t j = 0;
+    for (int32_t e = 0; e < l; ++e) {
+      if (!(ptr[e + 1] > ptr[e] && label[pins[ptr[e]]] == r)) continue;
+      for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) G.pins[G.ptr[j] + (p - ptr[e])] = local[pins[p]];
+      G.ptr[j + 1] = G.ptr[j] + (ptr[e + 1] - ptr[e]);
+      G.c[j] = c ? c[e] : 1.0f;
+      ++j;
+    }
+    for (int32_t v = 0; v < k; ++v) if (label[v] == r) G.w[local[v]] = w ? w[v] : 1.0f;
+    rc = layout_component(&G, P, (uint64_t)r, xc);
+    free(G.ptr); free(G.pins); free(G.w); free(G.c);
+  }
+  if (rc == 0) {
+    /* packing */
+    double maxext = 0.0;
+    for (int32_t r = 0; r < k; ++r) {
+      if (label[r] != r) continue;
+      int32_t kc = csize[r];
+      float* xc = xl + 4 * (size_t)coff[r];
+      for (int d = 0; d < 4; ++d) {
+        float lo = xc[(size_t)d * kc], hi = lo;
+        for (int32_t i = 0; i < kc; ++i) { float v = xc[(size_t)d * kc + i]; if (v < lo) lo = v; if (v > hi) hi = v; }
+        double e = (double)hi - (double)lo;
+        if (e > maxext) maxext = e;
+      }
+    }
+    double gap = (double)P->pack_gap * maxext;
+    double offx = 0.0;
+    for (int32_t r = 0; r < k; ++r) {
+      if (label[r] != r) continue;
+      int32_t kc = csize[r];
+      float* xc = xl + 4 * (size_t)coff[r];
+      float lo[4];
+      double ext = 0.0;
+      for (int d = 0; d < 4; ++d) {
+        float a = xc[(size_t)d * kc], b = a;
+        for (int32_t i = 0; i < kc; ++i) { float v = xc[(size_t)d * kc + i]; if (v < a) a = v; if (v > b) b = v; }
+        lo[d] = a;
+        double e = (double)b - (double)a;
+        if (e > ext) ext = e;
+      }
+      for (int32_t v = 0; v < k; ++v) {
+        if (label[v] != r) continue;
+        int32_t i = local[v];
+        double t0 = (double)xc[i] - (double)lo[0];
+        x[v] = (float)(t0 + offx);
+        for (int d = 1; d < 4; ++d) x[(size_t)d * k + v] = (float)((double)xc[(size_t)d * kc + i] - (double)lo[d]);
+      }
+      offx = offx + ext;
+      offx = offx + gap;
+    }
+  }
+  free(label); free(local); free(csize); free(xl); free(coff);
+  return rc;
+}
+
+/* Gradient at a sample of vertices (for checks at full size): y[4][ns] for
+   the vertices ids[0..ns), plus the number of charge interactions each one's
+   walk performed (far nodes + leaf pairs, zero-distance pairs included). */
+static int64_t g_walk_count;
+static void walk_count_rec(const OTree* T, int32_t t, int32_t n, const int32_t* p2, double th2) {
+  const OTNode* N = &T->nd[t];
+  if (node_far(N, p2, th2)) { g_walk_count++; return; }
+  if (!N->leaf) {
+    int32_t ch = t + 1;
+    while (ch != N->next) { walk_count_rec(T, ch, n, p2, th2); ch = T->nd[ch].next; }
+    return;
+  }
+  for (int32_t i = N->first; i < N->first + N->count; ++i)
+    if (T->order[i] != n) g_walk_count++;
+}
+
+int o_gradient_sample(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+                      const float* c, const float* x, float theta, int32_t cap, int32_t ns,
+                      const int32_t* ids, float* y, int64_t* nint) {
+  float* z = (float*)malloc(sizeof(float) * 4 * (size_t)(l > 0 ? l : 1));
+  centres(k, l, ptr, pins, x, z);
+  int64_t* dptr = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k + 1));
+  int32_t* dp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ptr[l] > 0 ? ptr[l] : 1));
+  o_dual(k, l, ptr, pins, dptr, dp);
+  OTree T;
+  if (otree_build(&T, k, x, w, cap)) { otree_free(&T); free(z); free(dptr); free(dp); return -1; }
+  double th2 = (double)theta * (double)theta;
+  for (int32_t s = 0; s < ns; ++s) {
+    int32_t n = ids[s];
+    float xn[4], yn[4];
+    int32_t p2[4];
+    for (int d = 0; d < 4; ++d) {
+      float a = 0.0f;
+      for (int64_t t = dptr[n]; t < dptr[n + 1]; ++t) {
+        int32_t e = dp[t];
+        float ce = c ? c[e] : 1.0f;
+        float df = x[(size_t)d * k + n] - z[(size_t)d * l + e];
+        a = a + ce * df;
+      }
+      yn[d] = a;
+      xn[d] = x[(size_t)d * k + n];
+      p2[d] = 2 * (int32_t)T.kq[(size_t)d * k + n] + 1;
+    }
+    walk_rec(&T, 0, n, xn, w[n], p2, th2, x, w, yn);
+    for (int d = 0; d < 4; ++d) y[(size_t)d * ns + s] = yn[d];
+    if (nint) { g_walk_count = 0; walk_count_rec(&T, 0, n, p2, th2); nint[s] = g_walk_count; }
+  }
+  otree_free(&T); free(z); free(dptr); free(dp);
+  return 0;
+}
