@@ -1,0 +1,254 @@
+/*
+ * vmo.h -- C ABI of the MI355X (gfx950) implementation of the geometric
+ * ("visual") matrix ordering of Fagginger Auer and Bisseling, "A Geometric
+ * Approach to Matrix Ordering" (arXiv 1105.4490).
+ *
+ * Pointer conventions.  Every array argument is a DEVICE pointer unless its
+ * comment says (host).  The caller owns every input and output buffer and
+ * keeps it alive until the call returns.  The library owns only its
+ * workspace, a per-context caching pool of device memory.  Every call runs its
+ * kernels on `stream` (a hipStream_t; NULL = the null stream) and returns after
+ * that stream has finished the call's work, so outputs are ready on return.
+ * Calls on one context must not overlap (one context per host thread).
+ *
+ * Errors.  No call throws.  A call returns VMO_OK (0) or a negative status;
+ * vmo_last_error() then holds a message.  Inputs are validated on the host
+ * for scalars and on the device for array contents (pins in range and
+ * ascending within a net, weights and coordinates finite); invalid content is
+ * reported as VMO_E_INVALID without writing partial results the caller could
+ * mistake for output.
+ *
+ * Ids are 0-based (the paper counts from 1).  Permutations are in gather form:
+ * perm[new] = old.
+ */
+#ifndef VMO_H
+#define VMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vmo_status;
+enum {
+  VMO_OK = 0,
+  VMO_E_INVALID = -1,     /* bad argument or array content                  */
+  VMO_E_NOMEM = -2,       /* device allocation failed                       */
+  VMO_E_DEVICE = -3,      /* a HIP runtime call failed                      */
+  VMO_E_UNSUPPORTED = -4, /* a size beyond what this build handles          */
+  VMO_E_BUSY = -5         /* serving queue full                             */
+};
+
+typedef struct vmo_ctx_s* vmo_ctx;
+typedef void* vmo_stream; /* hipStream_t */
+
+/* Context on HIP device `device`.  Allocates nothing until first use. */
+vmo_status vmo_create(vmo_ctx* out /* (host) */, int device);
+/* Frees the context and its workspace pool. */
+vmo_status vmo_destroy(vmo_ctx ctx);
+/* Message of the last failed call on this context (host string, owned by the
+   context, valid until the next call). */
+const char* vmo_last_error(vmo_ctx ctx);
+/* Bytes currently held by the context's workspace pool. */
+size_t vmo_pool_bytes(vmo_ctx ctx);
+
+/* ---------------------------------------------------------------------------
+ * Hypergraph (Definition of a hypergraph, Sec. 1.1).  V = {0..k-1}; the nets
+ * E form a collection (duplicates and empty nets allowed) stored as CSR:
+ * net e holds pins[net_ptr[e] .. net_ptr[e+1]), strictly ascending, each in
+ * [0, k).  w: vertex weights [k] (NULL = all 1); c: net costs [l] (NULL = all
+ * 1).  Weights and costs are >= 0; the layout needs them > 0.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t k, l;
+  const int64_t* net_ptr; /* [l+1], net_ptr[0] = 0 */
+  const int32_t* pins;    /* [net_ptr[l]]          */
+  const float* w;         /* [k] or NULL           */
+  const float* c;         /* [l] or NULL           */
+} vmo_hypergraph;
+
+/* Matrix-to-hypergraph models (Table 1).  Input: the pattern of an m x n
+   sparse matrix as CSR (rowptr int64 [m+1], col int32, columns strictly
+   ascending within a row; values are not used).
+     VMO_ROW_NET:    vertices = the n columns, net i = columns of row i.
+     VMO_COLUMN_NET: vertices = the m rows, net j = rows with a_ij != 0.
+     VMO_SYMMETRIC:  (m == n) vertices = 0..n-1, nets = the distinct pairs
+                     {i, j}, i < j, with a_ij != 0 or a_ji != 0, in
+                     lexicographic order; diagonal entries are dropped.
+   Outputs: net_ptr [cap_nets+1], pins [cap_pins]; capacities must be at
+   least: row-net l = m, pins = nnz; column-net l = n, pins = nnz; symmetric
+   l <= nnz, pins <= 2 nnz.  *k, *l, *npins (host) receive the sizes. */
+enum { VMO_ROW_NET = 0, VMO_COLUMN_NET = 1, VMO_SYMMETRIC = 2 };
+vmo_status vmo_model(vmo_ctx ctx, int model, int32_t m, int32_t n, const int64_t* rowptr,
+                     const int32_t* col, int64_t* net_ptr, int32_t* pins, int32_t cap_nets,
+                     int64_t cap_pins, int32_t* k, int32_t* l, int64_t* npins, vmo_stream stream);
+
+/* Dual hypergraph (Definition of the dual, Sec. 1.1): net v of the dual
+   lists, ascending, the nets of h that contain v.  Outputs dptr [k+1],
+   dpins [net_ptr[l]].  (Weights and costs swap roles; they are not copied.) */
+vmo_status vmo_dual(vmo_ctx ctx, const vmo_hypergraph* h, int64_t* dptr, int32_t* dpins,
+                    vmo_stream stream);
+
+/* Connected components (Algorithm 1, Sec. 2.3): label[v] = the smallest
+   vertex id in v's component, where nets connect their pins. */
+vmo_status vmo_components(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, vmo_stream stream);
+
+/* Cut metrics of a partition (Sec. 4.1: a row/column is cut when it meets
+   more than one diagonal block; the cut-net metric of the footnote there;
+   Table 4 takes the maximum over splits).  lambda(e) = number of distinct
+   values of part[] over the pins of net e.  Part ids are >= 0 and below
+   2^30.  part_weight[p] (optional, [nparts]) = sum of w over part p < nparts.
+   Integral costs give exact sums; other costs are summed in FP64. */
+typedef struct {
+  double lambda_minus_one; /* sum_e c(e) max(lambda(e) - 1, 0) */
+  double cut_net;          /* sum of c(e) over nets with lambda(e) > 1 */
+  int64_t nets_cut;        /* number of nets with lambda(e) > 1 */
+} vmo_cut_result;
+vmo_status vmo_cut(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, int32_t nparts,
+                   double* part_weight, vmo_cut_result* out /* (host) */, vmo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * One 2-means split (Algorithm 4 with m = 2; sides by the plane of
+ * Algorithm 7).  x: k points in R^4 as FP32 SoA [4][k] (x[d*k + i]).  The
+ * points are mapped once to a 2^20 grid over their bounding box; k-means++
+ * seeding (exact D^2 draw from SplitMix64 keyed by seed) and at most t_max
+ * Lloyd updates follow, with exact integer sums and an FP64 plane test
+ * (s <= 0 -> part 1).  Outputs: side[k] (0 = part 1, 1 = part 2),
+ * centres [2][4] FP32 (the centres of the final assignment), *iters (host)
+ * = Lloyd updates performed, *split (host) = 1 if split, 0 if the points
+ * cannot be split (all coincide, or a side came out empty; side = 0). */
+vmo_status vmo_bisect(vmo_ctx ctx, const float* x, int32_t k, uint64_t seed, int32_t t_max,
+                      uint8_t* side, float* centres, int32_t* iters, int32_t* split,
+                      vmo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Layout (Sec. 2): coordinates x: V -> R^4 minimising eq. (6) by the
+ * multilevel steepest descent of Algorithms 2 and 3, each connected component
+ * alone, components then packed side by side.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  uint64_t seed;          /* keys every random draw                       */
+  int32_t coarsest_iters; /* descent steps at the coarsest level (100)    */
+  int32_t level_iters;    /* descent steps at every other level (30)      */
+  int32_t min_coarse;     /* stop coarsening at <= this many vertices (64)*/
+  int32_t max_levels;     /* at most this many coarsenings (40)           */
+  int32_t leaf_cap;       /* tree leaves hold <= this many points (8)     */
+  int32_t match_max_net;  /* nets larger than this do not propose (64)   */
+  float theta;            /* opening angle of the tree walk (0.5; 0 = exact) */
+  float step0_frac;       /* first step = this x box volume^(1/4) (0.1)   */
+  float decay;            /* step length factor per step (0.9)            */
+  float jitter;           /* prolongation displacement scale (1e-3)       */
+  float stall;            /* stop coarsening if k shrinks by less (0.95)  */
+  float pack_gap;         /* gap between packed components (0.1)          */
+} vmo_layout_params;
+/* Fills p with the defaults above and the given seed. */
+void vmo_layout_defaults(vmo_layout_params* p /* (host) */, uint64_t seed);
+
+/* Full layout.  x [4][k] FP32 SoA output. */
+vmo_status vmo_layout(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p /* (host) */,
+                      float* x, vmo_stream stream);
+
+/* One coarsening step (Sec. 2.3: greedy heavy-net matching, single-neighbour
+   vertices join their neighbour, identical nets merge with summed cost).
+   level and comp key the random tie-break.  Outputs: pi[k] (coarse id of each
+   vertex), coarse hypergraph into cptr [l+1], cpins [net_ptr[l]], cw [k],
+   cc [l] (capacities of the fine sizes suffice); *kc, *lc (host). */
+vmo_status vmo_coarsen(vmo_ctx ctx, const vmo_hypergraph* h, uint64_t seed, uint64_t comp,
+                       int32_t level, int32_t match_max_net, int32_t* pi, int64_t* cptr,
+                       int32_t* cpins, float* cw, float* cc, int32_t* kc, int32_t* lc,
+                       vmo_stream stream);
+
+/* The 2^d-tree of Algorithm 3 over points x [4][k] with weights w [k]
+   (NULL = 1): pre-order nodes; a node at depth L covers a cell of side
+   2^(16-L) of a 2^16 grid on the bounding cube; leaves hold <= leaf_cap
+   points (or share one grid cell).  Outputs (capacity max_nodes, at most
+   17 k + 1 nodes exist): ints [n][8] = first, count, depth, leaf, next, 0,0,0;
+   cell2 [n][4] = cell centre x 2 in grid units; flt [n][5] = W, X0..X3
+   (charge and its weighted centre); order [k] = point ids in tree order.
+   *n_nodes (host). */
+vmo_status vmo_tree(vmo_ctx ctx, const float* x, const float* w, int32_t k, int32_t leaf_cap,
+                    int32_t* ints, int32_t* cell2, float* flt, int32_t* order, int32_t max_nodes,
+                    int32_t* n_nodes, vmo_stream stream);
+
+/* Gradient eq. (7) of the energy at x: attraction through the net centres,
+   repulsion by the tree walk of Algorithm 3.  y [4][k], z [4][l] (net
+   centres, may be NULL); *interactions (host, may be NULL) = charge
+   interactions evaluated by the walk. */
+vmo_status vmo_gradient(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, float theta,
+                        int32_t leaf_cap, float* y, float* z, int64_t* interactions,
+                        vmo_stream stream);
+
+/* `iters` descent steps of Algorithm 3 on x in place, steps it0 .. it0+iters-1
+   of a level.  *alpha (host) carries the step length: set from the bounding
+   box at step 0, multiplied by p->decay after every step. */
+vmo_status vmo_layout_steps(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p,
+                            float* x, int32_t it0, int32_t iters, double* alpha, vmo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Recursive ordering (Algorithm 7 applied recursively, Sec. 4.2; recursive
+ * BBD of Sec. 4.1; recursive SBD of Sec. 5).  A node of the split tree with K
+ * parts splits its vertices by 2-means into side 1 (ceil(K/2) parts, heap id
+ * 2h) and side 2 (floor(K/2) parts, heap id 2h+1); it is a leaf if K = 1,
+ * it has < 2 vertices, or its points cannot split.
+ *   VMO_NET mode: any hypergraph; a net belongs to the deepest node holding
+ *     all its pins (it is cut at that node when the node is internal).
+ *   VMO_GRAPH mode: every net is an edge {v, w}, v < w; after each split the
+ *     separator loop of Algorithm 7 (edges in net order; the end nearer the
+ *     plane joins S, ties to v) builds S_h, which leaves both children.
+ * SBD emits nodes in-order (left, node, right); BBD post-order.  Vertices in a
+ * block ascend by id; nets within a node's block ascend; empty nets last.
+ * ------------------------------------------------------------------------- */
+enum { VMO_NET = 0, VMO_GRAPH = 1 };
+enum { VMO_SBD = 0, VMO_BBD = 1 };
+typedef struct {
+  int32_t* vperm;     /* [k] new -> old                                       */
+  int32_t* nperm;     /* [l] new -> old (VMO_NET; NULL to skip)               */
+  int32_t* part;      /* [k] leaf part in [0,P); separator vertices P + heap id */
+  int32_t* node_heap; /* [4P] heap id of the node at each emission rank, -1 pad */
+  int32_t* node_vptr; /* [4P+1] vertex block boundaries by rank, k pad        */
+  int32_t* node_nptr; /* [4P+2] net block boundaries by rank, then the empty-net
+                          bucket, l pad (VMO_NET; NULL to skip)                */
+  double* split_cut;  /* [4P] by rank: nets cut at the node (sum of costs) in
+                          VMO_NET, |S_h| in VMO_GRAPH; 0 for leaves           */
+  int32_t* n_nodes;   /* [1] number of tree nodes                             */
+} vmo_order_out;
+
+/* x: coordinates [4][k]; NULL = compute them first with vmo_layout(lp).
+   P >= 1 parts; t_max Lloyd updates per split (32 is the usual value). */
+vmo_status vmo_order(vmo_ctx ctx, const vmo_hypergraph* h, int mode, int order, const float* x,
+                     const vmo_layout_params* lp /* (host) */, int32_t P, uint64_t seed,
+                     int32_t t_max, const vmo_order_out* out /* (host) */, vmo_stream stream);
+vmo_status vmo_order_sbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const float* x,
+                         const vmo_layout_params* lp, int32_t P, uint64_t seed, int32_t t_max,
+                         const vmo_order_out* out, vmo_stream stream);
+vmo_status vmo_order_bbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const float* x,
+                         const vmo_layout_params* lp, int32_t P, uint64_t seed, int32_t t_max,
+                         const vmo_order_out* out, vmo_stream stream);
+
+/* Many orderings in one pass: every level of every job is processed by the
+   same launches over one segment list (jobs[i].job_index keys its random
+   draws as the job number).  Results equal those of vmo_order per job with
+   the same job_index. */
+typedef struct {
+  vmo_hypergraph h;
+  int32_t mode, order;
+  const float* x;       /* [4][k]; must not be NULL here                    */
+  int32_t P;
+  uint64_t seed;
+  uint64_t job_index;
+  vmo_order_out out;
+} vmo_job;
+vmo_status vmo_order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs /* (host) */,
+                           int32_t t_max, vmo_stream stream);
+
+/* Same ordering with one launch sequence per segment per level (the plain
+   per-subproblem form, for comparison with vmo_order_batch). */
+vmo_status vmo_order_batch_plain(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, int32_t t_max,
+                                 vmo_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VMO_H */

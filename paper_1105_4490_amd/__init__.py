@@ -1,0 +1,297 @@
+"""Python binding of libvmo (include/vmo.h): geometric matrix ordering on MI355X.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libvmo.so``.  PyTorch supplies device memory (tensors) and the current
+HIP stream.  If the library is not built this module raises at first use;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvmo.so")
+
+VMO_OK, VMO_E_INVALID, VMO_E_NOMEM, VMO_E_DEVICE, VMO_E_UNSUPPORTED, VMO_E_BUSY = 0, -1, -2, -3, -4, -5
+ROW_NET, COLUMN_NET, SYMMETRIC = 0, 1, 2
+NET, GRAPH = 0, 1
+SBD, BBD = 0, 1
+
+
+class VmoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"vmo status {status}: {msg}")
+        self.status = status
+
+
+class Hypergraph(C.Structure):
+    _fields_ = [("k", C.c_int32), ("l", C.c_int32), ("net_ptr", C.c_void_p), ("pins", C.c_void_p),
+                ("w", C.c_void_p), ("c", C.c_void_p)]
+
+
+class LayoutParams(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("coarsest_iters", C.c_int32), ("level_iters", C.c_int32),
+                ("min_coarse", C.c_int32), ("max_levels", C.c_int32), ("leaf_cap", C.c_int32),
+                ("match_max_net", C.c_int32), ("theta", C.c_float), ("step0_frac", C.c_float),
+                ("decay", C.c_float), ("jitter", C.c_float), ("stall", C.c_float), ("pack_gap", C.c_float)]
+
+
+class OrderOut(C.Structure):
+    _fields_ = [("vperm", C.c_void_p), ("nperm", C.c_void_p), ("part", C.c_void_p), ("node_heap", C.c_void_p),
+                ("node_vptr", C.c_void_p), ("node_nptr", C.c_void_p), ("split_cut", C.c_void_p),
+                ("n_nodes", C.c_void_p)]
+
+
+class Job(C.Structure):
+    _fields_ = [("h", Hypergraph), ("mode", C.c_int32), ("order", C.c_int32), ("x", C.c_void_p), ("P", C.c_int32),
+                ("seed", C.c_uint64), ("job_index", C.c_uint64), ("out", OrderOut)]
+
+
+class CutResult(C.Structure):
+    _fields_ = [("lambda_minus_one", C.c_double), ("cut_net", C.c_double), ("nets_cut", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1105_4490_amd.build` "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        L.vmo_last_error.restype = C.c_char_p
+        L.vmo_pool_bytes.restype = C.c_size_t
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def layout_params(seed=1, **kw) -> LayoutParams:
+    p = LayoutParams()
+    lib().vmo_layout_defaults(C.byref(p), C.c_uint64(seed))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@dataclass
+class DeviceHypergraph:
+    """A hypergraph whose arrays live on the GPU (Definition of a hypergraph, Sec. 1.1)."""
+    k: int
+    l: int
+    net_ptr: torch.Tensor   # int64 [l+1]
+    pins: torch.Tensor      # int32
+    w: torch.Tensor | None = None
+    c: torch.Tensor | None = None
+
+    def cstruct(self) -> Hypergraph:
+        return Hypergraph(self.k, self.l, _ptr(self.net_ptr), _ptr(self.pins) if self.pins.numel() else None,
+                          _ptr(self.w), _ptr(self.c))
+
+    @staticmethod
+    def from_host(h, device="cuda"):
+        """From any object with k, l, ptr/net_ptr, pins, w, c (numpy arrays)."""
+        ptr = getattr(h, "ptr", None)
+        if ptr is None:
+            ptr = h.net_ptr
+        t = lambda a, dt: None if a is None else torch.as_tensor(a, dtype=dt).to(device).contiguous()
+        pins = t(h.pins, torch.int32)
+        if pins.numel() == 0:
+            pins = torch.zeros(1, dtype=torch.int32, device=device)
+        return DeviceHypergraph(int(h.k), int(h.l), t(ptr, torch.int64), pins, t(getattr(h, "w", None), torch.float32),
+                                t(getattr(h, "c", None), torch.float32))
+
+
+class Context:
+    """One vmo context on one GPU (calls on it must not overlap)."""
+
+    def __init__(self, device: int | None = None):
+        self.device = torch.cuda.current_device() if device is None else device
+        h = C.c_void_p()
+        self._check(lib().vmo_create(C.byref(h), C.c_int(self.device)), ctx=None)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vmo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, ctx="self"):
+        if st != VMO_OK:
+            msg = lib().vmo_last_error(self.h).decode() if ctx is not None else "vmo_create failed"
+            raise VmoError(st, msg)
+
+    def pool_bytes(self) -> int:
+        return int(lib().vmo_pool_bytes(self.h))
+
+    # --------------------------------------------------------------- models --
+    def model(self, kind: int, m: int, n: int, rowptr: torch.Tensor, col: torch.Tensor) -> DeviceHypergraph:
+        nnz = int(col.numel())
+        cap_nets = {ROW_NET: m, COLUMN_NET: n, SYMMETRIC: max(nnz, 1)}[kind]
+        cap_pins = {ROW_NET: nnz, COLUMN_NET: nnz, SYMMETRIC: 2 * nnz}[kind]
+        dev = rowptr.device
+        net_ptr = torch.empty(cap_nets + 1, dtype=torch.int64, device=dev)
+        pins = torch.empty(max(cap_pins, 1), dtype=torch.int32, device=dev)
+        k, l, npins = C.c_int32(), C.c_int32(), C.c_int64()
+        self._check(lib().vmo_model(self.h, C.c_int(kind), C.c_int32(m), C.c_int32(n), _ptr(rowptr),
+                                    _ptr(col) if nnz else None, _ptr(net_ptr), _ptr(pins), C.c_int32(cap_nets),
+                                    C.c_int64(cap_pins), C.byref(k), C.byref(l), C.byref(npins), _stream()))
+        return DeviceHypergraph(k.value, l.value, net_ptr[:l.value + 1], pins[:max(npins.value, 1)])
+
+    def dual(self, h: DeviceHypergraph) -> DeviceHypergraph:
+        npins = int(h.net_ptr[-1].item())
+        dptr = torch.empty(h.k + 1, dtype=torch.int64, device=h.net_ptr.device)
+        dp = torch.empty(max(npins, 1), dtype=torch.int32, device=h.net_ptr.device)
+        hs = h.cstruct()
+        self._check(lib().vmo_dual(self.h, C.byref(hs), _ptr(dptr), _ptr(dp), _stream()))
+        return DeviceHypergraph(h.l, h.k, dptr, dp, h.c, h.w)
+
+    def components(self, h: DeviceHypergraph) -> torch.Tensor:
+        lab = torch.empty(h.k, dtype=torch.int32, device=h.net_ptr.device)
+        hs = h.cstruct()
+        self._check(lib().vmo_components(self.h, C.byref(hs), _ptr(lab), _stream()))
+        return lab
+
+    def cut(self, h: DeviceHypergraph, part: torch.Tensor, nparts: int):
+        pw = torch.empty(max(nparts, 1), dtype=torch.float64, device=part.device)
+        r = CutResult()
+        hs = h.cstruct()
+        self._check(lib().vmo_cut(self.h, C.byref(hs), _ptr(part), C.c_int32(nparts), _ptr(pw), C.byref(r),
+                                  _stream()))
+        return {"lambda_minus_one": r.lambda_minus_one, "cut_net": r.cut_net, "nets_cut": r.nets_cut,
+                "part_weight": pw[:nparts]}
+
+    # ------------------------------------------------------------- bisection --
+    def bisect(self, x: torch.Tensor, seed: int, t_max: int = 32):
+        k = x.shape[1]
+        side = torch.empty(k, dtype=torch.uint8, device=x.device)
+        cen = torch.empty(8, dtype=torch.float32, device=x.device)
+        it, sp = C.c_int32(), C.c_int32()
+        self._check(lib().vmo_bisect(self.h, _ptr(x), C.c_int32(k), C.c_uint64(seed), C.c_int32(t_max), _ptr(side),
+                                     _ptr(cen), C.byref(it), C.byref(sp), _stream()))
+        return {"split": bool(sp.value), "side": side, "centres": cen.view(2, 4), "iters": it.value}
+
+    # -------------------------------------------------------------- ordering --
+    @staticmethod
+    def _out(h: DeviceHypergraph, P: int, mode: int, dev):
+        o = {"vperm": torch.empty(h.k, dtype=torch.int32, device=dev),
+             "nperm": torch.empty(max(h.l, 1), dtype=torch.int32, device=dev) if mode == NET else None,
+             "part": torch.empty(h.k, dtype=torch.int32, device=dev),
+             "node_heap": torch.empty(4 * P, dtype=torch.int32, device=dev),
+             "node_vptr": torch.empty(4 * P + 1, dtype=torch.int32, device=dev),
+             "node_nptr": torch.empty(4 * P + 2, dtype=torch.int32, device=dev) if mode == NET else None,
+             "split_cut": torch.empty(4 * P, dtype=torch.float64, device=dev),
+             "n_nodes": torch.empty(1, dtype=torch.int32, device=dev)}
+        s = OrderOut(*[_ptr(o[f]) for f in ("vperm", "nperm", "part", "node_heap", "node_vptr", "node_nptr",
+                                            "split_cut", "n_nodes")])
+        return o, s
+
+    def order(self, h: DeviceHypergraph, x: torch.Tensor | None, P: int, seed: int, mode: int = NET,
+              order: int = SBD, t_max: int = 32, lp: LayoutParams | None = None):
+        dev = h.net_ptr.device
+        o, s = self._out(h, P, mode, dev)
+        hs = h.cstruct()
+        self._check(lib().vmo_order(self.h, C.byref(hs), C.c_int(mode), C.c_int(order), _ptr(x),
+                                    C.byref(lp) if lp is not None else None, C.c_int32(P), C.c_uint64(seed),
+                                    C.c_int32(t_max), C.byref(s), _stream()))
+        if o["nperm"] is not None:
+            o["nperm"] = o["nperm"][:h.l]
+        return o
+
+    def order_batch(self, jobs, t_max: int = 32, plain: bool = False):
+        """jobs: list of dicts with h, x, P, seed, mode, order, job_index."""
+        outs = []
+        arr = (Job * len(jobs))()
+        keep = []
+        for i, jb in enumerate(jobs):
+            h = jb["h"]
+            o, s = self._out(h, jb["P"], jb.get("mode", NET), h.net_ptr.device)
+            hs = h.cstruct()
+            keep.append((o, s, hs))
+            arr[i] = Job(hs, jb.get("mode", NET), jb.get("order", SBD), _ptr(jb["x"]).value, jb["P"], jb["seed"],
+                         jb.get("job_index", i), s)
+            outs.append(o)
+        fn = lib().vmo_order_batch_plain if plain else lib().vmo_order_batch
+        self._check(fn(self.h, C.c_int32(len(jobs)), arr, C.c_int32(t_max), _stream()))
+        for jb, o in zip(jobs, outs):
+            if o["nperm"] is not None:
+                o["nperm"] = o["nperm"][:jb["h"].l]
+        return outs
+
+    # ---------------------------------------------------------------- layout --
+    def layout(self, h: DeviceHypergraph, params: LayoutParams | None = None) -> torch.Tensor:
+        params = params or layout_params()
+        x = torch.empty((4, h.k), dtype=torch.float32, device=h.net_ptr.device)
+        hs = h.cstruct()
+        self._check(lib().vmo_layout(self.h, C.byref(hs), C.byref(params), _ptr(x), _stream()))
+        return x
+
+    def coarsen(self, h: DeviceHypergraph, seed: int, comp: int = 0, level: int = 0, match_max: int = 64):
+        dev = h.net_ptr.device
+        npins = int(h.net_ptr[-1].item())
+        pi = torch.empty(h.k, dtype=torch.int32, device=dev)
+        cptr = torch.empty(h.l + 1, dtype=torch.int64, device=dev)
+        cpins = torch.empty(max(npins, 1), dtype=torch.int32, device=dev)
+        cw = torch.empty(h.k, dtype=torch.float32, device=dev)
+        cc = torch.empty(max(h.l, 1), dtype=torch.float32, device=dev)
+        kc, lc = C.c_int32(), C.c_int32()
+        hs = h.cstruct()
+        self._check(lib().vmo_coarsen(self.h, C.byref(hs), C.c_uint64(seed), C.c_uint64(comp), C.c_int32(level),
+                                      C.c_int32(match_max), _ptr(pi), _ptr(cptr), _ptr(cpins), _ptr(cw), _ptr(cc),
+                                      C.byref(kc), C.byref(lc), _stream()))
+        kc, lc = kc.value, lc.value
+        return pi, DeviceHypergraph(kc, lc, cptr[:lc + 1], cpins[:max(int(cptr[lc].item()), 1)], cw[:kc], cc[:lc])
+
+    def tree(self, x: torch.Tensor, w: torch.Tensor | None = None, leaf_cap: int = 8):
+        k = x.shape[1]
+        dev = x.device
+        cap = 17 * k + 64
+        ints = torch.empty((cap, 8), dtype=torch.int32, device=dev)
+        cell2 = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+        flt = torch.empty((cap, 5), dtype=torch.float32, device=dev)
+        order = torch.empty(k, dtype=torch.int32, device=dev)
+        n = C.c_int32()
+        self._check(lib().vmo_tree(self.h, _ptr(x), _ptr(w), C.c_int32(k), C.c_int32(leaf_cap), _ptr(ints),
+                                   _ptr(cell2), _ptr(flt), _ptr(order), C.c_int32(cap), C.byref(n), _stream()))
+        n = n.value
+        return {"n": n, "ints": ints[:n], "cell2": cell2[:n], "flt": flt[:n], "order": order}
+
+    def gradient(self, h: DeviceHypergraph, x: torch.Tensor, theta: float = 0.5, leaf_cap: int = 8):
+        dev = x.device
+        y = torch.empty((4, h.k), dtype=torch.float32, device=dev)
+        z = torch.empty((4, max(h.l, 1)), dtype=torch.float32, device=dev)
+        nint = C.c_int64()
+        hs = h.cstruct()
+        self._check(lib().vmo_gradient(self.h, C.byref(hs), _ptr(x), C.c_float(theta), C.c_int32(leaf_cap), _ptr(y),
+                                       _ptr(z), C.byref(nint), _stream()))
+        return y, z[:, :h.l], nint.value
+
+    def layout_steps(self, h: DeviceHypergraph, x: torch.Tensor, params: LayoutParams, it0: int, iters: int,
+                     alpha: float = 0.0):
+        a = C.c_double(alpha)
+        hs = h.cstruct()
+        self._check(lib().vmo_layout_steps(self.h, C.byref(hs), C.byref(params), _ptr(x), C.c_int32(it0),
+                                           C.c_int32(iters), C.byref(a), _stream()))
+        return a.value

@@ -1,0 +1,290 @@
+// C ABI of include/vmo.h: argument checks, context handling, and dispatch to
+// the device code.  No exception crosses this boundary.
+#include "order_engine.h"
+
+struct vmo_ctx_s : vmo::Ctx {};
+
+namespace vmo {
+void model(Ctx& c, int model, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, int64_t* net_ptr,
+           int32_t* pins, int32_t cap_nets, int64_t cap_pins, int32_t* k_out, int32_t* l_out, int64_t* np_out,
+           hipStream_t s);
+void dual(Ctx& c, const vmo_hypergraph* h, int64_t* dptr, int32_t* dpins, hipStream_t s);
+void cut(Ctx& c, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, double* part_weight,
+         vmo_cut_result* out, hipStream_t s);
+void layout(Ctx& c, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, hipStream_t s);
+void coarsen(Ctx& c, const vmo_hypergraph* h, uint64_t seed, uint64_t comp, int32_t level, int32_t match_max,
+             int32_t* pi, int64_t* cptr, int32_t* cpins, float* cw, float* cc, int32_t* kc, int32_t* lc,
+             hipStream_t s);
+void tree(Ctx& c, const float* x, const float* w, int32_t k, int32_t cap, int32_t* ints, int32_t* cell2, float* flt,
+          int32_t* order, int32_t max_nodes, int32_t* n_nodes, hipStream_t s);
+void gradient(Ctx& c, const vmo_hypergraph* h, const float* x, float theta, int32_t cap, float* y, float* z,
+              int64_t* nint, hipStream_t s);
+void layout_steps(Ctx& c, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, int32_t it0, int32_t iters,
+                  double* alpha, hipStream_t s);
+}  // namespace vmo
+
+#define API_BEGIN(ctx, stream)                                    \
+  if (!(ctx)) return VMO_E_INVALID;                               \
+  vmo::Ctx& C = *static_cast<vmo::Ctx*>(ctx);                     \
+  hipStream_t S = static_cast<hipStream_t>(stream);               \
+  C.err.clear();                                                  \
+  try {                                                           \
+    VMO_HIP(hipSetDevice(C.device));
+
+#define API_END                                                   \
+  }                                                               \
+  catch (vmo::Error & e) {                                        \
+    C.err = e.what();                                             \
+    (void)hipStreamSynchronize(S);                                \
+    (void)hipGetLastError();                                      \
+    return e.status;                                              \
+  }                                                               \
+  catch (std::exception & e) {                                    \
+    C.err = e.what();                                             \
+    (void)hipStreamSynchronize(S);                                \
+    (void)hipGetLastError();                                      \
+    return VMO_E_DEVICE;                                          \
+  }                                                               \
+  return VMO_OK;
+
+extern "C" {
+
+vmo_status vmo_create(vmo_ctx* out, int device) {
+  if (!out) return VMO_E_INVALID;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return VMO_E_DEVICE;
+  }
+  vmo_ctx_s* c = new (std::nothrow) vmo_ctx_s();
+  if (!c) return VMO_E_NOMEM;
+  c->device = device;
+  *out = c;
+  return VMO_OK;
+}
+
+vmo_status vmo_destroy(vmo_ctx ctx) {
+  if (!ctx) return VMO_E_INVALID;
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+  return VMO_OK;
+}
+
+const char* vmo_last_error(vmo_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+size_t vmo_pool_bytes(vmo_ctx ctx) { return ctx ? ctx->pool.held() : 0; }
+
+vmo_status vmo_model(vmo_ctx ctx, int model, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col,
+                     int64_t* net_ptr, int32_t* pins, int32_t cap_nets, int64_t cap_pins, int32_t* k, int32_t* l,
+                     int64_t* npins, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::model(C, model, m, n, rowptr, col, net_ptr, pins, cap_nets, cap_pins, k, l, npins, S);
+  API_END
+}
+
+vmo_status vmo_dual(vmo_ctx ctx, const vmo_hypergraph* h, int64_t* dptr, int32_t* dpins, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::dual(C, h, dptr, dpins, S);
+  API_END
+}
+
+vmo_status vmo_components(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::validate_hypergraph(C, h, false, S);
+  VMO_REQUIRE(label != nullptr, "label is NULL");
+  vmo::components(C, h->k, h->l, h->net_ptr, h->pins, label, S);
+  VMO_HIP(hipStreamSynchronize(S));
+  API_END
+}
+
+vmo_status vmo_cut(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, double* part_weight,
+                   vmo_cut_result* out, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::cut(C, h, part, nparts, part_weight, out, S);
+  API_END
+}
+
+vmo_status vmo_bisect(vmo_ctx ctx, const float* x, int32_t k, uint64_t seed, int32_t t_max, uint8_t* side,
+                      float* centres, int32_t* iters, int32_t* split, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  VMO_REQUIRE(k >= 1, "k must be >= 1");
+  VMO_REQUIRE(t_max >= 0, "t_max must be >= 0");
+  VMO_REQUIRE(side && centres && iters && split, "NULL output");
+  vmo::validate_finite(C, x, 4 * (int64_t)k, "x", S);
+  std::vector<vmo::JobHost> jobs(1);
+  memset(&jobs[0], 0, sizeof(vmo::JobHost));
+  jobs[0].h.k = k;
+  jobs[0].mode = VMO_NET;
+  jobs[0].order = VMO_SBD;
+  jobs[0].x = x;
+  jobs[0].P = 2;
+  jobs[0].seed = seed;
+  jobs[0].job_index = 0;
+  vmo::Engine e(C, S);
+  e.setup(jobs);
+  int sp = 0, it = 0;
+  if (e.S > 0) {
+    e.two_means(0, e.S, 0, e.Np, t_max);
+    int32_t st = vmo::read1(e.cur.state.p, S);
+    sp = st == vmo::kStDone ? 1 : 0;
+    it = vmo::read1(e.cur.iters.p, S);
+  }
+  vmo::bisect_outputs(e, side, centres, sp);
+  VMO_HIP(hipStreamSynchronize(S));
+  *iters = sp ? it : 0;
+  *split = sp;
+  API_END
+}
+
+static void check_order_args(vmo::Ctx& C, const vmo_hypergraph* h, int mode, int order, int32_t P, int32_t t_max,
+                             const vmo_order_out* out, hipStream_t S) {
+  VMO_REQUIRE(mode == VMO_NET || mode == VMO_GRAPH, "mode must be VMO_NET or VMO_GRAPH");
+  VMO_REQUIRE(order == VMO_SBD || order == VMO_BBD, "order must be VMO_SBD or VMO_BBD");
+  VMO_REQUIRE(P >= 1 && P <= (1 << 24), "P must be in [1, 2^24]");
+  VMO_REQUIRE(t_max >= 0, "t_max must be >= 0");
+  VMO_REQUIRE(out && out->vperm && out->part && out->node_heap && out->node_vptr && out->split_cut && out->n_nodes,
+              "NULL output array");
+  vmo::validate_hypergraph(C, h, false, S);
+  if (mode == VMO_GRAPH) {
+    int64_t np = vmo::read1(h->net_ptr + h->l, S);
+    VMO_REQUIRE(np == 2 * (int64_t)h->l, "graph mode needs every net to be an edge {v, w}");
+    // each net of exactly two pins: net_ptr[e] = 2e is checked by the ascending
+    // pin check plus the total; a net of 1 and one of 3 pins would pass the
+    // total, so check the pointer array itself
+    std::vector<int64_t> hp((size_t)h->l + 1);
+    VMO_HIP(hipMemcpyAsync(hp.data(), h->net_ptr, 8 * hp.size(), hipMemcpyDeviceToHost, S));
+    VMO_HIP(hipStreamSynchronize(S));
+    for (int64_t e = 0; e <= h->l; ++e) VMO_REQUIRE(hp[e] == 2 * e, "graph mode needs every net to be an edge {v, w}");
+  }
+}
+
+static void run_order(vmo::Ctx& C, std::vector<vmo::JobHost>& jobs, int32_t t_max, bool plain, hipStream_t S) {
+  vmo::Engine e(C, S);
+  e.setup(jobs);
+  e.set_edges(jobs);
+  e.run_levels(t_max, plain);
+  e.finish(jobs);
+}
+
+vmo_status vmo_order(vmo_ctx ctx, const vmo_hypergraph* h, int mode, int order, const float* x,
+                     const vmo_layout_params* lp, int32_t P, uint64_t seed, int32_t t_max, const vmo_order_out* out,
+                     vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  check_order_args(C, h, mode, order, P, t_max, out, S);
+  vmo::Buf<float> xl;
+  if (!x) {
+    VMO_REQUIRE(lp != nullptr, "x is NULL and no layout parameters were given");
+    xl = vmo::Buf<float>(C.pool, 4 * (size_t)h->k);
+    vmo::layout(C, h, lp, xl.p, S);
+    x = xl.p;
+  } else {
+    vmo::validate_finite(C, x, 4 * (int64_t)h->k, "x", S);
+  }
+  std::vector<vmo::JobHost> jobs(1);
+  memset(&jobs[0], 0, sizeof(vmo::JobHost));
+  jobs[0].h = *h;
+  jobs[0].mode = mode;
+  jobs[0].order = order;
+  jobs[0].x = x;
+  jobs[0].P = P;
+  jobs[0].seed = seed;
+  jobs[0].job_index = 0;
+  jobs[0].out = *out;
+  run_order(C, jobs, t_max, false, S);
+  API_END
+}
+
+vmo_status vmo_order_sbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const float* x, const vmo_layout_params* lp,
+                         int32_t P, uint64_t seed, int32_t t_max, const vmo_order_out* out, vmo_stream stream) {
+  return vmo_order(ctx, h, mode, VMO_SBD, x, lp, P, seed, t_max, out, stream);
+}
+vmo_status vmo_order_bbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const float* x, const vmo_layout_params* lp,
+                         int32_t P, uint64_t seed, int32_t t_max, const vmo_order_out* out, vmo_stream stream) {
+  return vmo_order(ctx, h, mode, VMO_BBD, x, lp, P, seed, t_max, out, stream);
+}
+
+static vmo_status order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, int32_t t_max, bool plain,
+                              vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  VMO_REQUIRE(njobs >= 1 && jobs != nullptr, "need at least one job");
+  std::vector<vmo::JobHost> J(njobs);
+  for (int32_t i = 0; i < njobs; ++i) {
+    const vmo_job& a = jobs[i];
+    check_order_args(C, &a.h, a.mode, a.order, a.P, t_max, &a.out, S);
+    VMO_REQUIRE(a.x != nullptr, "batch jobs need coordinates");
+    vmo::validate_finite(C, a.x, 4 * (int64_t)a.h.k, "x", S);
+    memset(&J[i], 0, sizeof(vmo::JobHost));
+    J[i].h = a.h;
+    J[i].mode = a.mode;
+    J[i].order = a.order;
+    J[i].x = a.x;
+    J[i].P = a.P;
+    J[i].seed = a.seed;
+    J[i].job_index = a.job_index;
+    J[i].out = a.out;
+  }
+  run_order(C, J, t_max, plain, S);
+  API_END
+}
+
+vmo_status vmo_order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, int32_t t_max, vmo_stream stream) {
+  return order_batch(ctx, njobs, jobs, t_max, false, stream);
+}
+vmo_status vmo_order_batch_plain(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, int32_t t_max, vmo_stream stream) {
+  return order_batch(ctx, njobs, jobs, t_max, true, stream);
+}
+
+void vmo_layout_defaults(vmo_layout_params* p, uint64_t seed) {
+  if (!p) return;
+  p->seed = seed;
+  p->coarsest_iters = 100;
+  p->level_iters = 30;
+  p->min_coarse = 64;
+  p->max_levels = 40;
+  p->leaf_cap = 8;
+  p->match_max_net = 64;
+  p->theta = 0.5f;
+  p->step0_frac = 0.1f;
+  p->decay = 0.9f;
+  p->jitter = 1e-3f;
+  p->stall = 0.95f;
+  p->pack_gap = 0.1f;
+}
+
+vmo_status vmo_layout(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::layout(C, h, p, x, S);
+  API_END
+}
+
+vmo_status vmo_coarsen(vmo_ctx ctx, const vmo_hypergraph* h, uint64_t seed, uint64_t comp, int32_t level,
+                       int32_t match_max_net, int32_t* pi, int64_t* cptr, int32_t* cpins, float* cw, float* cc,
+                       int32_t* kc, int32_t* lc, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::coarsen(C, h, seed, comp, level, match_max_net, pi, cptr, cpins, cw, cc, kc, lc, S);
+  API_END
+}
+
+vmo_status vmo_tree(vmo_ctx ctx, const float* x, const float* w, int32_t k, int32_t leaf_cap, int32_t* ints,
+                    int32_t* cell2, float* flt, int32_t* order, int32_t max_nodes, int32_t* n_nodes,
+                    vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::tree(C, x, w, k, leaf_cap, ints, cell2, flt, order, max_nodes, n_nodes, S);
+  API_END
+}
+
+vmo_status vmo_gradient(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, float theta, int32_t leaf_cap, float* y,
+                        float* z, int64_t* interactions, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::gradient(C, h, x, theta, leaf_cap, y, z, interactions, S);
+  API_END
+}
+
+vmo_status vmo_layout_steps(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, int32_t it0,
+                            int32_t iters, double* alpha, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::layout_steps(C, h, p, x, it0, iters, alpha, S);
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,999 @@
+// Recursive SBD/BBD ordering on the GPU: quantization, segmented k-means++
+// seeding and Lloyd iterations (Algorithm 4 with m = 2), the plane and
+// separator of Algorithm 7, the stable three-way partition of every split,
+// and the emission of permutations (Sec. 4.1, 4.2, 5).
+//
+// Every level of the recursion, for every job of a batch, is one segment list;
+// each kernel below covers all segments of a level in one launch (the plain
+// per-subproblem form reuses the same kernels with one segment per launch).
+#include "order_engine.h"
+
+namespace vmo {
+
+constexpr uint32_t kQMax = 1048575u;  // 2^20 - 1 grid
+constexpr int kT = 256;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// -------------------------------------------------------- device helpers ----
+// s(v) = x(v).r - delta, products and sums rounded one by one, left to right.
+__device__ __forceinline__ double plane_eval(uint32_t q0, uint32_t q1, uint32_t q2, uint32_t q3,
+                                             const double* pl) {
+  double a0 = (double)q0 * pl[0];
+  double a1 = (double)q1 * pl[1];
+  double a2 = (double)q2 * pl[2];
+  double a3 = (double)q3 * pl[3];
+  double t = a0 + a1;
+  t = t + a2;
+  t = t + a3;
+  return t - pl[4];
+}
+// r = c2 - c1, delta = ((c1 + c2) / 2) . r with the same rounding discipline.
+__device__ __forceinline__ void plane_from(const double* c1, const double* c2, double* pl) {
+  double m[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    pl[d] = c2[d] - c1[d];
+    double s = c1[d] + c2[d];
+    m[d] = s * 0.5;
+  }
+  double a0 = m[0] * pl[0];
+  double a1 = m[1] * pl[1];
+  double a2 = m[2] * pl[2];
+  double a3 = m[3] * pl[3];
+  double t = a0 + a1;
+  t = t + a2;
+  t = t + a3;
+  pl[4] = t;
+}
+
+__device__ __forceinline__ int32_t find_job(const JobDev* jobs, int32_t nj, int64_t pos) {
+  int32_t lo = 0, hi = nj;
+  while (hi - lo > 1) {
+    int32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].voff <= pos) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Segmented sum across a wavefront.  Lanes hold (key, v[F]); equal keys form
+// contiguous lane runs.  Afterwards the first lane of each run holds the run's
+// total and returns true.  key < 0 = no segment.
+template <int F>
+__device__ __forceinline__ bool wave_seg_sum(int key, int64_t (&v)[F]) {
+  int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int ok = __shfl_down(key, off, 64);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      int64_t o = __shfl_down(v[f], off, 64);
+      if (lane + off < 64 && ok == key) v[f] += o;
+    }
+  }
+  int prev = __shfl_up(key, 1, 64);
+  return key >= 0 && (lane == 0 || prev != key);
+}
+
+// --------------------------------------------------------- setup kernels ----
+__global__ void k_gather_x(const JobDev* jobs, int32_t nj, const float* const* xptr, int64_t N,
+                           int64_t Np, float* xs, int32_t* id, int32_t* pos) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Np; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i >= N) {
+      for (int d = 0; d < 4; ++d) xs[d * Np + i] = 0.0f;
+      id[i] = -1;
+      continue;
+    }
+    int32_t j = find_job(jobs, nj, i);
+    int64_t loc = i - jobs[j].voff;
+    const float* x = xptr[j];
+    for (int d = 0; d < 4; ++d) xs[d * Np + i] = x[(int64_t)d * jobs[j].k + loc];
+    id[i] = (int32_t)i;
+    pos[i] = (int32_t)i;
+  }
+}
+
+// Per-job bounding box (exact FP32 min / max through ordered integer keys).
+__global__ void k_bbox(const JobDev* jobs, int32_t nj, const float* xs, int64_t N, int64_t Np, uint32_t* box) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = -1;
+  uint32_t mn[4], mx[4];
+  for (int d = 0; d < 4; ++d) { mn[d] = 0xffffffffu; mx[d] = 0u; }
+  if (i < N) {
+    key = find_job(jobs, nj, i);
+    for (int d = 0; d < 4; ++d) mn[d] = mx[d] = fkey(xs[d * Np + i]);
+  }
+  int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int ok = __shfl_down(key, off, 64);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      uint32_t a = __shfl_down(mn[d], off, 64), b = __shfl_down(mx[d], off, 64);
+      if (lane + off < 64 && ok == key) {
+        mn[d] = a < mn[d] ? a : mn[d];
+        mx[d] = b > mx[d] ? b : mx[d];
+      }
+    }
+  }
+  int prev = __shfl_up(key, 1, 64);
+  if (key >= 0 && (lane == 0 || prev != key))
+    for (int d = 0; d < 4; ++d) {
+      atomicMin(&box[key * 8 + d], mn[d]);
+      atomicMax(&box[key * 8 + 4 + d], mx[d]);
+    }
+}
+
+// Per job: lo = exact FP32 minimum, scale = (2^20 - 1) / largest side (FP64).
+__global__ void k_job_scale(JobDev* jobs, int32_t nj, const uint32_t* box) {
+  int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nj) return;
+  double ext = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    float lo = fkey_inv(box[j * 8 + d]), hi = fkey_inv(box[j * 8 + 4 + d]);
+    jobs[j].lo[d] = lo;
+    double e = (double)hi - (double)lo;
+    if (e > ext) ext = e;
+  }
+  jobs[j].scale = ext > 0.0 ? (double)kQMax / ext : 0.0;
+}
+
+__global__ void k_quantize(const JobDev* jobs, int32_t nj, const float* xs, int64_t N, int64_t Np, uint32_t* q) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Np; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i >= N) {
+      for (int d = 0; d < 4; ++d) q[d * Np + i] = 0;
+      continue;
+    }
+    int32_t j = find_job(jobs, nj, i);
+    double s = jobs[j].scale;
+    for (int d = 0; d < 4; ++d) {
+      uint32_t v = 0;
+      if (s > 0.0) {
+        double t = ((double)xs[d * Np + i] - (double)jobs[j].lo[d]) * s;
+        double f = floor(t);
+        v = f >= (double)kQMax ? kQMax : (uint32_t)f;
+      }
+      q[d * Np + i] = v;
+    }
+  }
+}
+
+// --------------------------------------------------------- level kernels ----
+// Segment of every position in [p0, p1) for segments [s0, s0 + S).
+__global__ void k_segpos(const int64_t* sbeg, const int64_t* send, int64_t s0, int64_t S, int64_t p0,
+                         int64_t p1, int32_t* segpos) {
+  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = s0, hi = s0 + S;
+    if (S == 0 || sbeg[lo] > i) { segpos[i] = -1; continue; }
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (sbeg[mid] <= i) lo = mid; else hi = mid;
+    }
+    segpos[i] = i < send[lo] ? (int32_t)lo : -1;
+  }
+}
+
+// z1: uniform member of the segment; clears the accumulators.
+__global__ void k_seed1(const JobDev* jobs, SegArrays sg, int64_t s0, int64_t S) {
+  int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= s0 + S) return;
+  const JobDev& J = jobs[sg.job[s]];
+  uint64_t n = (uint64_t)(sg.end[s] - sg.beg[s]);
+  uint64_t r0 = rng3(J.seed, kTagKmeans | (J.job_index << 8), (uint64_t)sg.h[s], 0);
+  sg.i1[s] = sg.beg[s] + (int64_t)__umul64hi(r0, n);
+  for (int f = 0; f < kAccF; ++f) sg.acc[s * kAccF + f] = 0;
+  sg.state[s] = kStIter;
+  sg.iters[s] = 0;
+}
+
+// D^2 = |q - q(z1)|^2 (exact int64) per position, and the segment sums of q.
+__global__ __launch_bounds__(kT) void k_d2(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
+                                           int64_t p0, int64_t p1, U128* dd) {
+  int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = -1;
+  int64_t v[4] = {0, 0, 0, 0};
+  if (i < p1) {
+    int32_t s = segpos[i];
+    U128 out{0, 0};
+    if (s >= 0) {
+      key = s;
+      int64_t j = sg.i1[s];
+      uint64_t d2 = 0;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        int64_t a = (int64_t)q[d * Np + i];
+        int64_t df = a - (int64_t)q[d * Np + j];
+        d2 += (uint64_t)(df * df);
+        v[d] = a;
+      }
+      out.lo = d2;
+    }
+    dd[i] = out;
+  }
+  if (wave_seg_sum<4>(key, v))
+    for (int d = 0; d < 4; ++d) atomicAdd((unsigned long long*)&sg.acc[key * kAccF + kAccTot + d], (unsigned long long)v[d]);
+}
+
+// z2 by the D^2 draw: t = floor(r1 T / 2^64) (exact), z2 = first position whose
+// inclusive prefix exceeds t.  T = 0 -> the node cannot split.
+__global__ void k_seed2(const JobDev* jobs, SegArrays sg, int64_t s0, int64_t S, const U128* pre,
+                        const uint32_t* q, int64_t Np) {
+  int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= s0 + S) return;
+  const JobDev& J = jobs[sg.job[s]];
+  int64_t b = sg.beg[s], e = sg.end[s];
+  U128 base = pre[b];
+  U128 T = u128_sub(pre[e], base);
+  if (u128_zero(T)) { sg.state[s] = kStLeaf; return; }
+  uint64_t r1 = rng3(J.seed, kTagKmeans | (J.job_index << 8), (uint64_t)sg.h[s], 1);
+  // t = (r1 * T.lo >> 64) + r1 * T.hi
+  U128 t;
+  t.lo = r1 * T.hi;
+  t.hi = __umul64hi(r1, T.hi);
+  t = u128_add(t, U128{__umul64hi(r1, T.lo), 0});
+  U128 target = u128_add(base, t);
+  int64_t lo = b + 1, hi = e;  // smallest j in [b+1, e] with pre[j] > target
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (u128_gt(pre[mid], target)) hi = mid; else lo = mid + 1;
+  }
+  int64_t i2 = lo - 1, i1 = sg.i1[s];
+  double c1[4], c2[4];
+  for (int d = 0; d < 4; ++d) {
+    c1[d] = (double)q[d * Np + i1];
+    c2[d] = (double)q[d * Np + i2];
+    sg.cen[s * 8 + d] = c1[d];
+    sg.cen[s * 8 + 4 + d] = c2[d];
+  }
+  plane_from(c1, c2, &sg.plane[s * 5]);
+}
+
+// One Lloyd assignment: side by the plane, sums of side 1, count of side 1,
+// and the number of changed assignments.
+__global__ __launch_bounds__(kT) void k_assign(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
+                                               int64_t p0, int64_t p1, int it, uint8_t* side) {
+  int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = -1;
+  int64_t v[6] = {0, 0, 0, 0, 0, 0};
+  if (i < p1) {
+    int32_t s = segpos[i];
+    if (s >= 0 && sg.state[s] == kStIter) {
+      key = s;
+      uint32_t a0 = q[i], a1 = q[Np + i], a2 = q[2 * Np + i], a3 = q[3 * Np + i];
+      double sv = plane_eval(a0, a1, a2, a3, &sg.plane[s * 5]);
+      uint8_t sd = sv <= 0.0 ? 1 : 2;
+      if (it > 0 && sd != side[i]) v[5] = 1;
+      side[i] = sd;
+      if (sd == 1) { v[0] = a0; v[1] = a1; v[2] = a2; v[3] = a3; v[4] = 1; }
+    }
+  }
+  if (wave_seg_sum<6>(key, v))
+    for (int f = 0; f < 6; ++f)
+      if (v[f]) atomicAdd((unsigned long long*)&sg.acc[key * kAccF + kAccS1 + f], (unsigned long long)v[f]);
+}
+
+// After assignment `it`: empty side -> leaf; unchanged or t_max -> done;
+// else new centres (FP64 means of the exact sums) for the next assignment.
+__global__ void k_lloyd_fin(SegArrays sg, int64_t s0, int64_t S, int it, int t_max, int32_t* active) {
+  int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= s0 + S || sg.state[s] != kStIter) return;
+  int64_t* a = &sg.acc[s * kAccF];
+  int64_t n = sg.end[s] - sg.beg[s];
+  int64_t n1 = a[kAccS1 + 4], n2 = n - n1, ch = a[kAccS1 + 5];
+  if (n1 == 0 || n2 == 0) { sg.state[s] = kStLeaf; return; }
+  if ((it > 0 && ch == 0) || it >= t_max) { sg.state[s] = kStDone; return; }
+  double m1[4], m2[4];
+  for (int d = 0; d < 4; ++d) {
+    int64_t S1 = a[kAccS1 + d];
+    int64_t S2 = a[kAccTot + d] - S1;
+    m1[d] = (double)S1 / (double)n1;
+    m2[d] = (double)S2 / (double)n2;
+    sg.cen[s * 8 + d] = m1[d];
+    sg.cen[s * 8 + 4 + d] = m2[d];
+  }
+  plane_from(m1, m2, &sg.plane[s * 5]);
+  sg.iters[s] = it + 1;
+  for (int f = 0; f < 6; ++f) a[kAccS1 + f] = 0;
+  atomicAdd(active, 1);
+}
+
+// ------------------------------------------------------------- separator ----
+// Cut edges of splitting segments: both ends in the segment, sides differ.
+// Only segments [s0, s0 + S) count: positions outside them may hold segment
+// ids of other launches, which are never dereferenced.
+__global__ void k_cutedges(const int32_t* edges, int64_t e0, int64_t e1, const int32_t* pos, const int32_t* segpos,
+                           int64_t s0, int64_t S, const int32_t* state, const uint8_t* side, int32_t* flag) {
+  for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t pa = pos[edges[2 * e]], pb = pos[edges[2 * e + 1]];
+    int32_t sa = segpos[pa], sb = segpos[pb];
+    int ok = sa >= s0 && sa < s0 + S && sa == sb;
+    ok = ok && state[sa] == kStDone && side[pa] != side[pb];
+    flag[e] = ok;
+  }
+}
+__global__ void k_compact_edges(const int32_t* flag, const int32_t* scan, const int32_t* edges, int64_t e0,
+                                int64_t e1, const int32_t* pos, const int32_t* segpos, int32_t* cand,
+                                uint32_t* candseg) {
+  for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += (int64_t)gridDim.x * blockDim.x) {
+    if (!flag[e]) continue;
+    int32_t o = scan[e];
+    cand[o] = (int32_t)e;
+    candseg[o] = (uint32_t)segpos[pos[edges[2 * e]]];
+  }
+}
+__global__ void k_cbounds(const uint32_t* candseg, int64_t nc, int64_t* cbeg, int64_t* cend) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t s = candseg[i];
+    if (i == 0 || candseg[i - 1] != s) cbeg[s] = i;
+    if (i == nc - 1 || candseg[i + 1] != s) cend[s] = i + 1;
+  }
+}
+
+// Algorithm 7 separator loop, one wavefront per segment.  Its cut edges come in
+// edge order, 64 at a time; edges already touching S are dropped; inside a
+// chunk, edges are resolved in order with ballots: once an edge puts its end
+// nearer the plane (smaller |s|; ties to the first end) into S, every later
+// edge of the chunk touching that vertex is dropped.
+__global__ __launch_bounds__(kT) void k_separator(SegArrays sg, int64_t s0, int64_t S, const int64_t* cbeg,
+                                                  const int64_t* cend, const int32_t* cand, const int32_t* edges,
+                                                  const int32_t* pos, const uint32_t* q, int64_t Np, int32_t* sep) {
+  int64_t s = s0 + (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+  if (s >= s0 + S) return;
+  int lane = lane_id();
+  int64_t b = cbeg[s], e = cend[s];
+  if (b >= e) return;
+  const double* pl = &sg.plane[s * 5];
+  for (int64_t base = b; base < e; base += 64) {
+    int64_t idx = base + lane;
+    bool valid = idx < e;
+    int32_t pa = -1, pb = -1, ch = -1;
+    bool alive = false;
+    if (valid) {
+      int32_t ed = cand[idx];
+      pa = pos[edges[2 * ed]];
+      pb = pos[edges[2 * ed + 1]];
+      double sa = fabs(plane_eval(q[pa], q[Np + pa], q[2 * Np + pa], q[3 * Np + pa], pl));
+      double sb = fabs(plane_eval(q[pb], q[Np + pb], q[2 * Np + pb], q[3 * Np + pb], pl));
+      ch = sa <= sb ? pa : pb;
+      int ia = __hip_atomic_load(&sep[pa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int ib = __hip_atomic_load(&sep[pb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      alive = !ia && !ib;
+    }
+    uint64_t mask = __ballot(valid && alive);
+    uint64_t rem = mask;
+    while (rem) {
+      int j = __builtin_ctzll(rem);
+      rem &= rem - 1;
+      int32_t cj = __shfl(ch, j, 64);
+      uint64_t kill = __ballot(valid && lane > j && (pa == cj || pb == cj));
+      mask &= ~kill;
+      rem &= ~kill;
+    }
+    if (valid && ((mask >> lane) & 1ull)) __hip_atomic_store(&sep[ch], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+  }
+}
+
+__global__ void k_mark_sep(const int32_t* sep, int64_t p0, int64_t p1, uint8_t* side) {
+  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1; i += (int64_t)gridDim.x * blockDim.x)
+    if (sep[i]) side[i] = 3;
+}
+
+// ------------------------------------------------------------- partition ----
+__global__ void k_classes(const int32_t* segpos, const int32_t* state, const uint8_t* side, int64_t p0, int64_t p1,
+                          uint64_t* cls) {
+  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t s = segpos[i];
+    uint64_t v = 0;
+    if (s >= 0 && state[s] == kStDone) v = side[i] == 1 ? 1ull : (side[i] == 2 ? (1ull << 32) : 0ull);
+    cls[i] = v;
+  }
+}
+
+struct Counts3 {
+  int64_t n1, n2, n3;
+};
+__device__ __forceinline__ Counts3 seg_counts(const uint64_t* pre, int64_t b, int64_t e) {
+  uint64_t d = pre[e] - pre[b];
+  Counts3 c;
+  c.n1 = (int64_t)(d & 0xffffffffull);
+  c.n2 = (int64_t)(d >> 32);
+  c.n3 = (e - b) - c.n1 - c.n2;
+  return c;
+}
+
+// Stable three-way partition of every split segment: part 1, then part 2 and
+// the separator (BBD: 1 | 2 | S; SBD: 1 | S | 2), ascending within each.
+__global__ __launch_bounds__(kT) void k_partition(const JobDev* jobs, SegArrays sg, const int32_t* segpos,
+                                                  const uint8_t* side, const uint64_t* pre, const uint32_t* q,
+                                                  const int32_t* id, int64_t Np, int64_t p0, int64_t p1,
+                                                  uint32_t* q2, int32_t* id2, int32_t* pos) {
+  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t s = segpos[i];
+    int64_t dest = i;
+    if (s >= 0 && sg.state[s] == kStDone) {
+      int64_t b = sg.beg[s], e = sg.end[s];
+      Counts3 c = seg_counts(pre, b, e);
+      uint64_t d = pre[i] - pre[b];
+      int64_t r1 = (int64_t)(d & 0xffffffffull), r2 = (int64_t)(d >> 32), r3 = (i - b) - r1 - r2;
+      bool bbd = jobs[sg.job[s]].ord == VMO_BBD;
+      uint8_t sd = side[i];
+      if (sd == 1) dest = b + r1;
+      else if (sd == 2) dest = bbd ? b + c.n1 + r2 : b + c.n1 + c.n3 + r2;
+      else dest = bbd ? b + c.n1 + c.n2 + r3 : b + c.n1 + r3;
+      pos[id[i]] = (int32_t)dest;
+    }
+    for (int d = 0; d < 4; ++d) q2[d * Np + dest] = q[d * Np + i];
+    id2[dest] = id[i];
+  }
+}
+
+// Per processed segment: node-table entries for the node and its children;
+// the number of children that go on splitting.
+__global__ void k_children(const JobDev* jobs, SegArrays sg, int64_t s0, int64_t S, const uint64_t* pre, NodeArrays nd,
+                           int32_t* nnext) {
+  int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= s0 + S) return;
+  const JobDev& J = jobs[sg.job[s]];
+  int64_t nb = J.node_base;
+  int32_t h = sg.h[s];
+  int64_t b = sg.beg[s], e = sg.end[s];
+  int32_t cnt = 0;
+  if (sg.state[s] != kStDone) {
+    nd.state[nb + h] = kNodeLeaf;
+    nd.beg[nb + h] = b;
+    nd.end[nb + h] = e;
+  } else {
+    Counts3 c = seg_counts(pre, b, e);
+    bool bbd = J.ord == VMO_BBD;
+    nd.state[nb + h] = kNodeInternal;
+    nd.beg[nb + h] = bbd ? b + c.n1 + c.n2 : b + c.n1;
+    nd.end[nb + h] = nd.beg[nb + h] + c.n3;
+    int32_t K = sg.K[s], K1 = (K + 1) / 2, K2 = K / 2;
+    int64_t cb[2] = {b, bbd ? b + c.n1 : b + c.n1 + c.n3};
+    int64_t cn[2] = {c.n1, c.n2};
+    int32_t ck[2] = {K1, K2}, cp[2] = {sg.p0[s], sg.p0[s] + K1};
+    for (int t = 0; t < 2; ++t) {
+      int32_t hc = 2 * h + t;
+      nd.K[nb + hc] = ck[t];
+      nd.p0[nb + hc] = cp[t];
+      nd.beg[nb + hc] = cb[t];
+      nd.end[nb + hc] = cb[t] + cn[t];
+      if (ck[t] == 1 || cn[t] < 2) nd.state[nb + hc] = kNodeLeaf;
+      else { nd.state[nb + hc] = kNodePending; ++cnt; }
+    }
+  }
+  nnext[s - s0] = cnt;
+}
+
+__global__ void k_children_write(SegArrays sg, int64_t s0, int64_t S, const int32_t* nscan, const JobDev* jobs,
+                                 NodeArrays nd, SegArrays nx, int64_t t0) {
+  int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= s0 + S || sg.state[s] != kStDone) return;
+  int64_t o = t0 + nscan[s - s0];
+  int64_t nb = jobs[sg.job[s]].node_base;
+  for (int t = 0; t < 2; ++t) {
+    int32_t hc = 2 * sg.h[s] + t;
+    if (nd.state[nb + hc] != kNodePending) continue;
+    nx.beg[o] = nd.beg[nb + hc];
+    nx.end[o] = nd.end[nb + hc];
+    nx.job[o] = sg.job[s];
+    nx.h[o] = hc;
+    nx.K[o] = nd.K[nb + hc];
+    nx.p0[o] = nd.p0[nb + hc];
+    ++o;
+  }
+}
+
+// ------------------------------------------------------------- emission ----
+// Leaf vertices get the leaf's first part; separator vertices P + heap id.
+__global__ void k_node_fill(const JobDev* jobs, int32_t nj, NodeArrays nd, int64_t NT, const int32_t* id,
+                            int32_t* const* part_out, int32_t* leafh) {
+  for (int64_t g = blockIdx.x; g < NT; g += gridDim.x) {
+    int32_t st = nd.state[g];
+    if (st != kNodeLeaf && st != kNodeInternal) continue;
+    int32_t lo = 0, hi = nj;
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (jobs[mid].node_base <= g) lo = mid; else hi = mid;
+    }
+    const JobDev& J = jobs[lo];
+    int32_t h = (int32_t)(g - J.node_base);
+    int32_t pv = st == kNodeLeaf ? nd.p0[g] : J.P + h;
+    int32_t* part = part_out[lo];
+    for (int64_t i = nd.beg[g] + threadIdx.x; i < nd.end[g]; i += blockDim.x) {
+      int32_t v = id[i];
+      if (part) part[v - J.voff] = pv;
+      leafh[v] = h;
+    }
+  }
+}
+
+__global__ void k_vperm(const JobDev* jobs, int32_t nj, const int32_t* id, int64_t N, int32_t* const* vperm) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t j = find_job(jobs, nj, i);
+    vperm[j][i - jobs[j].voff] = (int32_t)(id[i] - jobs[j].voff);
+  }
+}
+
+// One thread per job: in-order (SBD) or post-order (BBD) walk of the heap tree.
+__global__ void k_emit(const JobDev* jobs, int32_t nj, NodeArrays nd, const OutPtrs* outs, int32_t* rank_of) {
+  int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nj) return;
+  const JobDev& J = jobs[j];
+  const OutPtrs& O = outs[j];
+  int64_t nb = J.node_base;
+  int32_t nmax = 4 * J.P;
+  int32_t stk[80];
+  int8_t stage[80];
+  int sp = 0;
+  int32_t r = 0;
+  stk[0] = 1; stage[0] = 0; sp = 1;
+  bool post = J.ord == VMO_BBD;
+  while (sp > 0) {
+    int32_t h = stk[sp - 1];
+    int32_t st = nd.state[nb + h];
+    bool leaf = st == kNodeLeaf;
+    bool emit = false;
+    if (leaf) { emit = true; --sp; }
+    else if (stage[sp - 1] == 0) { stage[sp - 1] = 1; stk[sp] = 2 * h; stage[sp] = 0; ++sp; }
+    else if (stage[sp - 1] == 1) {
+      stage[sp - 1] = 2;
+      if (!post) emit = true;
+      stk[sp] = 2 * h + 1; stage[sp] = 0; ++sp;
+    } else {
+      if (post) emit = true;
+      --sp;
+    }
+    if (emit) {
+      O.node_heap[r] = h;
+      O.node_vptr[r] = (int32_t)(nd.beg[nb + h] - J.voff);
+      O.split_cut[r] = (!leaf && J.mode == VMO_GRAPH) ? (double)(nd.end[nb + h] - nd.beg[nb + h]) : 0.0;
+      rank_of[nb + h] = r;
+      ++r;
+    }
+  }
+  for (int32_t t = r; t < nmax; ++t) {
+    O.node_heap[t] = -1;
+    O.node_vptr[t] = J.k;
+    O.split_cut[t] = 0.0;
+  }
+  O.node_vptr[nmax] = J.k;
+  O.n_nodes[0] = r;
+  if (O.node_nptr) {
+    // filled after the net sort; pad here
+    for (int32_t t = 0; t <= nmax + 1; ++t) O.node_nptr[t] = J.nnets;
+  }
+}
+
+__device__ __forceinline__ int32_t heap_lca(int32_t a, int32_t b) {
+  // bring to equal depth, then climb together
+  int da = 31 - __clz(a), db = 31 - __clz(b);
+  if (da > db) a >>= (da - db); else b >>= (db - da);
+  while (a != b) { a >>= 1; b >>= 1; }
+  return a;
+}
+
+// Net mode: a net belongs to the lowest common ancestor of its pins' leaves.
+__global__ void k_net_node(const JobDev* jobs, int32_t nj, const int64_t* nptr, const int32_t* npins, int64_t L,
+                           const int64_t* jnoff, const int32_t* leafh, const int32_t* rank_of, const OutPtrs* outs,
+                           const int64_t* keybase, uint32_t* key, int32_t* val, int32_t* node_of_net) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < L; g += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nj;
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (jnoff[mid] <= g) lo = mid; else hi = mid;
+    }
+    const JobDev& J = jobs[lo];
+    int64_t b = nptr[g], e = nptr[g + 1];
+    int32_t rk;
+    int32_t node = 0;
+    if (b == e) rk = outs[lo].n_nodes[0];
+    else {
+      node = leafh[npins[b]];
+      for (int64_t p = b + 1; p < e; ++p) node = heap_lca(node, leafh[npins[p]]);
+      rk = rank_of[J.node_base + node];
+    }
+    node_of_net[g] = node;
+    key[g] = (uint32_t)(keybase[lo] + rk);
+    val[g] = (int32_t)(g - jnoff[lo]);
+  }
+}
+
+__global__ void k_net_cut(const JobDev* jobs, int32_t nj, const int64_t* jnoff, int64_t L, const int32_t* node_of_net,
+                          NodeArrays nd, const int32_t* rank_of, float* const* costs, const OutPtrs* outs,
+                          const uint32_t* key, const int64_t* keybase, int64_t* keycount) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < L; g += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nj;
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (jnoff[mid] <= g) lo = mid; else hi = mid;
+    }
+    atomicAdd((unsigned long long*)&keycount[key[g]], 1ull);
+    int32_t node = node_of_net[g];
+    if (node == 0) continue;
+    const JobDev& J = jobs[lo];
+    if (nd.state[J.node_base + node] != kNodeInternal) continue;
+    const float* c = costs[lo];
+    double cv = c ? (double)c[g - jnoff[lo]] : 1.0;
+    atomicAdd(&outs[lo].split_cut[rank_of[J.node_base + node]], cv);
+  }
+}
+
+__global__ void k_net_out(const JobDev* jobs, int32_t nj, const int64_t* jnoff, int64_t L, const int32_t* val,
+                          const OutPtrs* outs) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < L; g += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nj;
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (jnoff[mid] <= g) lo = mid; else hi = mid;
+    }
+    if (outs[lo].nperm) outs[lo].nperm[g - jnoff[lo]] = val[g];
+  }
+}
+
+__global__ void k_net_ptr(const JobDev* jobs, int32_t nj, const int64_t* keyscan, const int64_t* keybase,
+                          const int64_t* jnoff, const OutPtrs* outs) {
+  int32_t j = blockIdx.x;
+  if (j >= nj) return;
+  const OutPtrs& O = outs[j];
+  if (!O.node_nptr) return;
+  int32_t n = O.n_nodes[0];
+  for (int32_t r = threadIdx.x; r <= n; r += blockDim.x)
+    O.node_nptr[r] = (int32_t)(keyscan[keybase[j] + r] - jnoff[j]);
+}
+
+__global__ void k_bisect_out(const JobDev* jobs, SegArrays sg, const uint8_t* side, int64_t k, uint8_t* out,
+                             int split) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = split ? (uint8_t)(side[i] - 1) : (uint8_t)0;
+}
+
+__global__ void k_bisect_centres(const JobDev* jobs, SegArrays sg, float* cen, int split) {
+  int t = threadIdx.x;
+  if (t >= 8) return;
+  int d = t & 3;
+  cen[t] = split ? (float)((double)jobs[0].lo[d] + sg.cen[t] / jobs[0].scale) : 0.0f;
+}
+
+__global__ void k_init_roots(const JobDev* jobs, int32_t nj, NodeArrays nd) {
+  int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nj) return;
+  int64_t g = jobs[j].node_base + 1;
+  nd.state[g] = (jobs[j].k < 2 || jobs[j].P == 1) ? kNodeLeaf : kNodePending;
+  nd.beg[g] = jobs[j].voff;
+  nd.end[g] = jobs[j].voff + jobs[j].k;
+  nd.K[g] = jobs[j].P;
+  nd.p0[g] = 0;
+}
+
+// ---------------------------------------------------------------- engine ----
+static unsigned gsz(int64_t n) {
+  int64_t b = (n + kT - 1) / kT;
+  return (unsigned)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+void Engine::alloc_segments(SegBufs& b, int64_t cap) {
+  b.beg = Buf<int64_t>(c.pool, cap);
+  b.end = Buf<int64_t>(c.pool, cap);
+  b.job = Buf<int32_t>(c.pool, cap);
+  b.h = Buf<int32_t>(c.pool, cap);
+  b.K = Buf<int32_t>(c.pool, cap);
+  b.p0 = Buf<int32_t>(c.pool, cap);
+  b.state = Buf<int32_t>(c.pool, cap);
+  b.iters = Buf<int32_t>(c.pool, cap);
+  b.i1 = Buf<int64_t>(c.pool, cap);
+  b.acc = Buf<int64_t>(c.pool, cap * kAccF);
+  b.plane = Buf<double>(c.pool, cap * 5);
+  b.cen = Buf<double>(c.pool, cap * 8);
+  b.cap = cap;
+}
+
+SegArrays Engine::view(SegBufs& b) {
+  SegArrays v;
+  v.beg = b.beg.p; v.end = b.end.p; v.job = b.job.p; v.h = b.h.p; v.K = b.K.p; v.p0 = b.p0.p;
+  v.state = b.state.p; v.iters = b.iters.p; v.i1 = b.i1.p; v.acc = b.acc.p; v.plane = b.plane.p; v.cen = b.cen.p;
+  return v;
+}
+
+void Engine::setup(const std::vector<JobHost>& jobs) {
+  nj = (int32_t)jobs.size();
+  hj.resize(nj);
+  int64_t voff = 0, nbase = 0, eoff = 0, noff = 0;
+  std::vector<const float*> xp(nj);
+  for (int32_t j = 0; j < nj; ++j) {
+    const JobHost& H = jobs[j];
+    JobDev& D = hj[j];
+    memset(&D, 0, sizeof D);
+    D.voff = voff; D.k = H.h.k; D.P = H.P; D.mode = H.mode; D.ord = H.order;
+    D.seed = H.seed; D.job_index = H.job_index; D.node_base = nbase; D.nnets = H.h.l;
+    D.eoff = eoff; D.noff = noff;
+    voff += H.h.k;
+    nbase += 4 * (int64_t)H.P;
+    if (H.mode == VMO_GRAPH) eoff += H.h.l; else noff += H.h.l;
+    xp[j] = H.x;
+  }
+  N = voff;
+  Np = (N + 3) & ~int64_t(3);
+  NT = nbase;
+  E = eoff;
+  L = noff;
+  VMO_REQUIRE(N < (int64_t(1) << 31) - 8, "too many vertices in one call");
+  dj = Buf<JobDev>(c.pool, nj);
+  VMO_HIP(hipMemcpyAsync(dj.p, hj.data(), sizeof(JobDev) * nj, hipMemcpyHostToDevice, s));
+  Buf<const float*> dxp(c.pool, nj);
+  VMO_HIP(hipMemcpyAsync(dxp.p, xp.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
+  // coordinates -> concatenated SoA, ids, positions
+  Buf<float> xs(c.pool, 4 * Np);
+  q = Buf<uint32_t>(c.pool, 4 * Np);
+  q2 = Buf<uint32_t>(c.pool, 4 * Np);
+  id = Buf<int32_t>(c.pool, Np);
+  id2 = Buf<int32_t>(c.pool, Np);
+  pos = Buf<int32_t>(c.pool, Np);
+  side = Buf<uint8_t>(c.pool, Np);
+  segpos = Buf<int32_t>(c.pool, Np);
+  VMO_LAUNCH(k_gather_x, gsz(Np), kT, 0, s, dj.p, nj, dxp.p, N, Np, xs.p, id.p, pos.p);
+  Buf<uint32_t> box(c.pool, 8 * (size_t)nj);
+  std::vector<uint32_t> hbox(8 * (size_t)nj);
+  for (int32_t j = 0; j < nj; ++j)
+    for (int d = 0; d < 4; ++d) { hbox[8 * j + d] = 0xffffffffu; hbox[8 * j + 4 + d] = 0u; }
+  VMO_HIP(hipMemcpyAsync(box.p, hbox.data(), sizeof(uint32_t) * hbox.size(), hipMemcpyHostToDevice, s));
+  VMO_LAUNCH(k_bbox, nblocks(N, kT), kT, 0, s, dj.p, nj, xs.p, N, Np, box.p);
+  VMO_LAUNCH(k_job_scale, nblocks(nj, 64), 64, 0, s, dj.p, nj, box.p);
+  VMO_LAUNCH(k_quantize, gsz(Np), kT, 0, s, dj.p, nj, xs.p, N, Np, q.p);
+  VMO_HIP(hipMemcpyAsync(hj.data(), dj.p, sizeof(JobDev) * nj, hipMemcpyDeviceToHost, s));
+  // node tables
+  nd_state = Buf<int32_t>(c.pool, NT);
+  nd_K = Buf<int32_t>(c.pool, NT);
+  nd_p0 = Buf<int32_t>(c.pool, NT);
+  nd_beg = Buf<int64_t>(c.pool, NT);
+  nd_end = Buf<int64_t>(c.pool, NT);
+  fill_i32(nd_state.p, kNodeNone, NT, s);
+  // level-0 segments: one per job root that can split
+  std::vector<int64_t> b0, e0;
+  std::vector<int32_t> j0, h0, K0, p00;
+  for (int32_t j = 0; j < nj; ++j) {
+    bool leaf = hj[j].k < 2 || hj[j].P == 1;
+    if (!leaf) {
+      b0.push_back(hj[j].voff); e0.push_back(hj[j].voff + hj[j].k);
+      j0.push_back(j); h0.push_back(1); K0.push_back(hj[j].P); p00.push_back(0);
+    }
+  }
+  VMO_LAUNCH(k_init_roots, nblocks(nj, 64), 64, 0, s, dj.p, nj, nodes());
+  S = (int64_t)b0.size();
+  alloc_segments(cur, S > 0 ? S : 1);
+  if (S > 0) {
+    VMO_HIP(hipMemcpyAsync(cur.beg.p, b0.data(), 8 * S, hipMemcpyHostToDevice, s));
+    VMO_HIP(hipMemcpyAsync(cur.end.p, e0.data(), 8 * S, hipMemcpyHostToDevice, s));
+    VMO_HIP(hipMemcpyAsync(cur.job.p, j0.data(), 4 * S, hipMemcpyHostToDevice, s));
+    VMO_HIP(hipMemcpyAsync(cur.h.p, h0.data(), 4 * S, hipMemcpyHostToDevice, s));
+    VMO_HIP(hipMemcpyAsync(cur.K.p, K0.data(), 4 * S, hipMemcpyHostToDevice, s));
+    VMO_HIP(hipMemcpyAsync(cur.p0.p, p00.data(), 4 * S, hipMemcpyHostToDevice, s));
+  }
+  VMO_HIP(hipStreamSynchronize(s));
+}
+
+void Engine::set_edges(const std::vector<JobHost>& jobs) {
+  // graph-mode edges, global vertex ids; net-mode nets, global pins
+  edges = Buf<int32_t>(c.pool, 2 * (E > 0 ? E : 1));
+  nptr = Buf<int64_t>(c.pool, L + 1);
+  int64_t npins = 0;
+  for (int32_t j = 0; j < nj; ++j)
+    if (jobs[j].mode == VMO_NET) npins += read1(jobs[j].h.net_ptr + jobs[j].h.l, s);
+  npins_ = npins;
+  npins_buf = Buf<int32_t>(c.pool, npins > 0 ? npins : 1);
+  jnoff = Buf<int64_t>(c.pool, nj);
+  std::vector<int64_t> hnoff(nj);
+  int64_t pinoff = 0;
+  for (int32_t j = 0; j < nj; ++j) {
+    const JobHost& H = jobs[j];
+    hnoff[j] = hj[j].noff;
+    if (H.mode == VMO_GRAPH) {
+      if (H.h.l > 0)
+        launch_offset_copy_i32(H.h.pins, edges.p + 2 * hj[j].eoff, 2 * (int64_t)H.h.l, (int32_t)hj[j].voff);
+    } else {
+      launch_offset_copy_ptr(H.h.net_ptr, nptr.p + hj[j].noff, (int64_t)H.h.l + 1, pinoff);
+      int64_t np = read1(H.h.net_ptr + H.h.l, s);
+      if (np > 0) launch_offset_copy_i32(H.h.pins, npins_buf.p + pinoff, np, (int32_t)hj[j].voff);
+      pinoff += np;
+    }
+  }
+  VMO_HIP(hipMemcpyAsync(jnoff.p, hnoff.data(), 8 * nj, hipMemcpyHostToDevice, s));
+}
+
+__global__ void k_offset_copy_i32(const int32_t* in, int32_t* out, int64_t n, int32_t add) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = in[i] + add;
+}
+__global__ void k_offset_copy_ptr(const int64_t* in, int64_t* out, int64_t n, int64_t add) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = in[i] + add;
+}
+void Engine::launch_offset_copy_i32(const int32_t* in, int32_t* out, int64_t n, int32_t add) {
+  VMO_LAUNCH(k_offset_copy_i32, gsz(n), kT, 0, s, in, out, n, add);
+}
+void Engine::launch_offset_copy_ptr(const int64_t* in, int64_t* out, int64_t n, int64_t add) {
+  VMO_LAUNCH(k_offset_copy_ptr, gsz(n), kT, 0, s, in, out, n, add);
+}
+
+// Seeding and Lloyd iterations for segments [s0, s0+Sn) over positions [p0, p1).
+void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max) {
+  SegArrays sg = view(cur);
+  int64_t np = p1 - p0;
+  VMO_LAUNCH(k_segpos, gsz(np), kT, 0, s, cur.beg.p, cur.end.p, s0, Sn, p0, p1, segpos.p);
+  VMO_LAUNCH(k_seed1, nblocks(Sn, kT), kT, 0, s, dj.p, sg, s0, Sn);
+  Buf<U128> dd(c.pool, Np + 1);
+  VMO_LAUNCH(k_d2, nblocks(np, kT), kT, 0, s, sg, segpos.p, q.p, Np, p0, p1, dd.p);
+  scan_exclusive<U128>(c, dd.p + p0, dd.p + p0, np, dd.p + p1, s);
+  VMO_LAUNCH(k_seed2, nblocks(Sn, kT), kT, 0, s, dj.p, sg, s0, Sn, dd.p, q.p, Np);
+  Buf<int32_t> active(c.pool, 1);
+  for (int it = 0; it <= t_max; ++it) {
+    VMO_LAUNCH(k_assign, nblocks(np, kT), kT, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p);
+    VMO_HIP(hipMemsetAsync(active.p, 0, 4, s));
+    VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p);
+    if (read1(active.p, s) == 0) break;
+  }
+}
+
+// Separator (graph mode) for segments [s0, s0+Sn) using edges [e0, e1).
+void Engine::separator(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int64_t e0, int64_t e1) {
+  if (e1 <= e0) return;
+  SegArrays sg = view(cur);
+  int64_t ne = e1 - e0;
+  Buf<int32_t> flag(c.pool, E + 1), scn(c.pool, E + 1);
+  VMO_LAUNCH(k_cutedges, gsz(ne), kT, 0, s, edges.p, e0, e1, pos.p, segpos.p, s0, Sn, cur.state.p, side.p, flag.p);
+  scan_exclusive<int32_t>(c, flag.p + e0, scn.p + e0, ne, scn.p + E, s);
+  int32_t nc = read1(scn.p + E, s);
+  // positions' separator flags
+  Buf<int32_t> sep(c.pool, Np);
+  fill_i32(sep.p + p0, 0, p1 - p0, s);
+  if (nc > 0) {
+    Buf<int32_t> cand(c.pool, nc);
+    Buf<uint32_t> cseg(c.pool, nc);
+    VMO_LAUNCH(k_compact_edges, gsz(ne), kT, 0, s, flag.p, scn.p, edges.p, e0, e1, pos.p, segpos.p, cand.p, cseg.p);
+    radix_sort<uint32_t>(c, cseg.p, cand.p, nc, bits_for((uint64_t)(s0 + Sn)), s);
+    Buf<int64_t> cb(c.pool, s0 + Sn), ce(c.pool, s0 + Sn);
+    fill_i64(cb.p + s0, 0, Sn, s);
+    fill_i64(ce.p + s0, 0, Sn, s);
+    VMO_LAUNCH(k_cbounds, gsz(nc), kT, 0, s, cseg.p, (int64_t)nc, cb.p, ce.p);
+    VMO_LAUNCH(k_separator, nblocks(Sn, kT / 64), kT, 0, s, sg, s0, Sn, cb.p, ce.p, cand.p, edges.p, pos.p, q.p, Np,
+               sep.p);
+  }
+  VMO_LAUNCH(k_mark_sep, gsz(p1 - p0), kT, 0, s, sep.p, p0, p1, side.p);
+}
+
+// Partition of segments [s0, s0+Sn), node table, next-level segments.
+int64_t Engine::partition(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, SegBufs& nx, int64_t t0) {
+  SegArrays sg = view(cur);
+  int64_t np = p1 - p0;
+  Buf<uint64_t> cls(c.pool, Np + 1);
+  VMO_LAUNCH(k_classes, gsz(np), kT, 0, s, segpos.p, cur.state.p, side.p, p0, p1, cls.p);
+  scan_exclusive<uint64_t>(c, cls.p + p0, cls.p + p0, np, cls.p + p1, s);
+  VMO_LAUNCH(k_partition, gsz(np), kT, 0, s, dj.p, sg, segpos.p, side.p, cls.p, q.p, id.p, Np, p0, p1, q2.p, id2.p,
+             pos.p);
+  // copy back the moved range (positions outside [p0,p1) are untouched in q2/id2)
+  for (int d = 0; d < 4; ++d)
+    VMO_HIP(hipMemcpyAsync(q.p + d * Np + p0, q2.p + d * Np + p0, 4 * np, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipMemcpyAsync(id.p + p0, id2.p + p0, 4 * np, hipMemcpyDeviceToDevice, s));
+  NodeArrays nd = nodes();
+  Buf<int32_t> cnt(c.pool, Sn + 1);
+  VMO_LAUNCH(k_children, nblocks(Sn, kT), kT, 0, s, dj.p, sg, s0, Sn, cls.p, nd, cnt.p);
+  scan_exclusive<int32_t>(c, cnt.p, cnt.p, Sn, cnt.p + Sn, s);
+  int32_t nn = read1(cnt.p + Sn, s);
+  if (nn > 0) {
+    if (t0 + nn > nx.cap) {
+      SegBufs bigger;
+      alloc_segments(bigger, 2 * (t0 + nn));
+      if (t0 > 0) copy_segments(nx, bigger, t0);
+      nx = std::move(bigger);
+    }
+    VMO_LAUNCH(k_children_write, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, cnt.p, dj.p, nd, view(nx), t0);
+  }
+  return nn;
+}
+
+void Engine::copy_segments(SegBufs& a, SegBufs& b, int64_t n) {
+  VMO_HIP(hipMemcpyAsync(b.beg.p, a.beg.p, 8 * n, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipMemcpyAsync(b.end.p, a.end.p, 8 * n, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipMemcpyAsync(b.job.p, a.job.p, 4 * n, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipMemcpyAsync(b.h.p, a.h.p, 4 * n, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipMemcpyAsync(b.K.p, a.K.p, 4 * n, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipMemcpyAsync(b.p0.p, a.p0.p, 4 * n, hipMemcpyDeviceToDevice, s));
+}
+
+NodeArrays Engine::nodes() {
+  NodeArrays nd;
+  nd.state = nd_state.p; nd.K = nd_K.p; nd.p0 = nd_p0.p; nd.beg = nd_beg.p; nd.end = nd_end.p;
+  return nd;
+}
+
+void Engine::run_levels(int t_max, bool plain) {
+  while (S > 0) {
+    SegBufs nx;
+    alloc_segments(nx, 2 * S);
+    int64_t nn = 0;
+    if (!plain) {
+      two_means(0, S, 0, Np, t_max);
+      separator(0, S, 0, Np, 0, E);
+      nn = partition(0, S, 0, Np, nx, 0);
+    } else {
+      // one launch sequence per segment
+      std::vector<int64_t> hb(S), he(S);
+      std::vector<int32_t> hjob(S);
+      VMO_HIP(hipMemcpyAsync(hb.data(), cur.beg.p, 8 * S, hipMemcpyDeviceToHost, s));
+      VMO_HIP(hipMemcpyAsync(he.data(), cur.end.p, 8 * S, hipMemcpyDeviceToHost, s));
+      VMO_HIP(hipMemcpyAsync(hjob.data(), cur.job.p, 4 * S, hipMemcpyDeviceToHost, s));
+      VMO_HIP(hipStreamSynchronize(s));
+      for (int64_t t = 0; t < S; ++t) {
+        const JobDev& J = hj[hjob[t]];
+        two_means(t, 1, hb[t], he[t], t_max);
+        if (J.mode == VMO_GRAPH) separator(t, 1, hb[t], he[t], J.eoff, J.eoff + J.nnets);
+        nn += partition(t, 1, hb[t], he[t], nx, nn);
+      }
+    }
+    cur = std::move(nx);
+    S = nn;
+  }
+}
+
+void Engine::finish(const std::vector<JobHost>& jobs) {
+  std::vector<OutPtrs> ho(nj);
+  std::vector<int32_t*> hpart(nj), hvperm(nj);
+  std::vector<float*> hcost(nj);
+  for (int32_t j = 0; j < nj; ++j) {
+    const vmo_order_out& o = jobs[j].out;
+    ho[j].vperm = o.vperm; ho[j].nperm = o.nperm; ho[j].part = o.part; ho[j].node_heap = o.node_heap;
+    ho[j].node_vptr = o.node_vptr; ho[j].node_nptr = jobs[j].mode == VMO_NET ? o.node_nptr : nullptr;
+    ho[j].split_cut = o.split_cut; ho[j].n_nodes = o.n_nodes;
+    hpart[j] = o.part; hvperm[j] = o.vperm;
+    hcost[j] = const_cast<float*>(jobs[j].h.c);
+  }
+  Buf<OutPtrs> douts(c.pool, nj);
+  Buf<int32_t*> dpart(c.pool, nj), dvperm(c.pool, nj);
+  Buf<float*> dcost(c.pool, nj);
+  VMO_HIP(hipMemcpyAsync(douts.p, ho.data(), sizeof(OutPtrs) * nj, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(dpart.p, hpart.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(dvperm.p, hvperm.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(dcost.p, hcost.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
+  NodeArrays nd = nodes();
+  Buf<int32_t> leafh(c.pool, Np);
+  VMO_LAUNCH(k_node_fill, (unsigned)(NT < 65536 ? (NT > 0 ? NT : 1) : 65536), kT, 0, s, dj.p, nj, nd, NT, id.p,
+             dpart.p, leafh.p);
+  VMO_LAUNCH(k_vperm, gsz(N), kT, 0, s, dj.p, nj, id.p, N, dvperm.p);
+  Buf<int32_t> rank_of(c.pool, NT);
+  VMO_LAUNCH(k_emit, nblocks(nj, 64), 64, 0, s, dj.p, nj, nd, douts.p, rank_of.p);
+  if (L > 0) {
+    // key space per job: 4P + 1 (ranks, then the empty-net bucket)
+    std::vector<int64_t> kb(nj);
+    int64_t kt = 0;
+    for (int32_t j = 0; j < nj; ++j) { kb[j] = kt; kt += hj[j].mode == VMO_NET ? 4 * (int64_t)hj[j].P + 1 : 0; }
+    VMO_REQUIRE(kt < (int64_t(1) << 32), "too many tree nodes in one call");
+    Buf<int64_t> keybase(c.pool, nj);
+    VMO_HIP(hipMemcpyAsync(keybase.p, kb.data(), 8 * nj, hipMemcpyHostToDevice, s));
+    // only net-mode jobs own nets; jnoff of graph jobs equals the next job's, so
+    // the binary search below always lands on the net-mode job owning net g
+    Buf<uint32_t> key(c.pool, L);
+    Buf<int32_t> val(c.pool, L), nnode(c.pool, L);
+    VMO_LAUNCH(k_net_node, gsz(L), kT, 0, s, dj.p, nj, nptr.p, npins_buf.p, L, jnoff.p, leafh.p, rank_of.p, douts.p,
+               keybase.p, key.p, val.p, nnode.p);
+    Buf<int64_t> kc(c.pool, kt + 1);
+    fill_i64(kc.p, 0, kt + 1, s);
+    VMO_LAUNCH(k_net_cut, gsz(L), kT, 0, s, dj.p, nj, jnoff.p, L, nnode.p, nd, rank_of.p, dcost.p, douts.p, key.p,
+               keybase.p, kc.p);
+    scan_exclusive<int64_t>(c, kc.p, kc.p, kt, kc.p + kt, s);
+    radix_sort<uint32_t>(c, key.p, val.p, L, bits_for((uint64_t)kt), s);
+    VMO_LAUNCH(k_net_out, gsz(L), kT, 0, s, dj.p, nj, jnoff.p, L, val.p, douts.p);
+    VMO_LAUNCH(k_net_ptr, nj, kT, 0, s, dj.p, nj, kc.p, keybase.p, jnoff.p, douts.p);
+  }
+  VMO_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace vmo
+
+namespace vmo {
+void bisect_outputs(Engine& e, uint8_t* side, float* centres, int split) {
+  SegArrays sg = e.view(e.cur);
+  VMO_LAUNCH(k_bisect_out, gsz(e.N), kT, 0, e.s, e.dj.p, sg, e.side.p, e.N, side, split);
+  VMO_LAUNCH(k_bisect_centres, 1, 64, 0, e.s, e.dj.p, sg, centres, split);
+}
+}  // namespace vmo

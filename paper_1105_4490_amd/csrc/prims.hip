@@ -1,0 +1,400 @@
+// Device primitives: caching pool, scans, LSD radix sort, fills, input
+// validation, CSR transpose and connected components.
+#include "vmo_internal.h"
+
+namespace vmo {
+
+// ------------------------------------------------------------------ pool ----
+size_t Pool::size_class(size_t b) {
+  if (b <= 4096) return (b + 255) & ~size_t(255);
+  int lg = 63 - __builtin_clzll(b);
+  size_t g = size_t(1) << (lg - 2);
+  return (b + g - 1) & ~(g - 1);
+}
+
+void* Pool::get(size_t bytes) {
+  size_t cls = size_class(bytes);
+  auto it = free_.lower_bound(cls);
+  if (it != free_.end() && it->first <= 2 * cls) {
+    void* p = it->second;
+    free_.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, cls);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    trim();
+    e = hipMalloc(&p, cls);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(VMO_E_NOMEM, "device allocation of " + std::to_string(cls) + " bytes failed");
+    }
+  }
+  size_[p] = cls;
+  held_ += cls;
+  return p;
+}
+
+void Pool::put(void* p) {
+  auto it = size_.find(p);
+  if (it == size_.end()) return;
+  free_.emplace(it->second, p);
+}
+
+void Pool::trim() {
+  for (auto& kv : free_) {
+    (void)hipFree(kv.second);
+    held_ -= size_[kv.second];
+    size_.erase(kv.second);
+  }
+  free_.clear();
+}
+
+Pool::~Pool() {
+  for (auto& kv : size_) (void)hipFree(kv.first);
+}
+
+// ------------------------------------------------------------------ scan ----
+constexpr int kScanT = 256, kScanI = 8, kScanTile = kScanT * kScanI;
+
+template <class T> __device__ __forceinline__ T tzero() { return T(0); }
+template <> __device__ __forceinline__ U128 tzero<U128>() { return U128{0, 0}; }
+template <class T> __device__ __forceinline__ T tadd(T a, T b) { return a + b; }
+template <> __device__ __forceinline__ U128 tadd<U128>(U128 a, U128 b) { return u128_add(a, b); }
+
+// Block-wide exclusive scan of one value per thread; *tot = block sum.
+template <class T>
+__device__ T block_excl(T v, T* sh, T* tot) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanT; off <<= 1) {
+    T a = t >= off ? sh[t - off] : tzero<T>();
+    __syncthreads();
+    if (t >= off) sh[t] = tadd(sh[t], a);
+    __syncthreads();
+  }
+  T ex = t > 0 ? sh[t - 1] : tzero<T>();
+  *tot = sh[kScanT - 1];
+  __syncthreads();
+  return ex;
+}
+
+template <class T>
+__global__ __launch_bounds__(kScanT) void k_scan_reduce(const T* __restrict__ in, int64_t n, T* part) {
+  __shared__ T sh[kScanT];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
+  T s = tzero<T>();
+#pragma unroll
+  for (int i = 0; i < kScanI; ++i)
+    if (base + i < n) s = tadd(s, in[base + i]);
+  T tot;
+  (void)block_excl(s, sh, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <class T>
+__global__ __launch_bounds__(kScanT) void k_scan_down(const T* in, T* out, int64_t n, const T* part,
+                                                      T* total, int last_block) {
+  __shared__ T sh[kScanT];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
+  T v[kScanI];
+  T s = tzero<T>();
+#pragma unroll
+  for (int i = 0; i < kScanI; ++i) {
+    v[i] = base + i < n ? in[base + i] : tzero<T>();
+    s = tadd(s, v[i]);
+  }
+  T tot;
+  T ex = block_excl(s, sh, &tot);
+  T run = part ? tadd(part[blockIdx.x], ex) : ex;
+#pragma unroll
+  for (int i = 0; i < kScanI; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run = tadd(run, v[i]);
+  }
+  if (total && (int)blockIdx.x == last_block && threadIdx.x == kScanT - 1) *total = run;
+}
+
+template <class T>
+void scan_exclusive(Ctx& c, const T* in, T* out, int64_t n, T* total, hipStream_t s) {
+  if (n <= 0) {
+    if (total) VMO_HIP(hipMemsetAsync(total, 0, sizeof(T), s));
+    return;
+  }
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 1) {
+    VMO_LAUNCH((k_scan_down<T>), 1, kScanT, 0, s, in, out, n, (const T*)nullptr, total, 0);
+    return;
+  }
+  Buf<T> part(c.pool, nb);
+  VMO_LAUNCH((k_scan_reduce<T>), (unsigned)nb, kScanT, 0, s, in, n, part.p);
+  scan_exclusive<T>(c, part.p, part.p, nb, total, s);
+  VMO_LAUNCH((k_scan_down<T>), (unsigned)nb, kScanT, 0, s, in, out, n, (const T*)part.p, (T*)nullptr, 0);
+}
+
+template void scan_exclusive<int32_t>(Ctx&, const int32_t*, int32_t*, int64_t, int32_t*, hipStream_t);
+template void scan_exclusive<int64_t>(Ctx&, const int64_t*, int64_t*, int64_t, int64_t*, hipStream_t);
+template void scan_exclusive<uint64_t>(Ctx&, const uint64_t*, uint64_t*, int64_t, uint64_t*, hipStream_t);
+template void scan_exclusive<U128>(Ctx&, const U128*, U128*, int64_t, U128*, hipStream_t);
+
+// ------------------------------------------------------------ radix sort ----
+constexpr int kRsT = 256, kRsI = 16, kRsTile = kRsT * kRsI;
+
+template <class K>
+__global__ __launch_bounds__(kRsT) void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift,
+                                                  int32_t* hist, int ntiles) {
+  __shared__ int cnt[256];
+  int t = threadIdx.x;
+  cnt[t] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int i = 0; i < kRsI; ++i) {
+    int64_t idx = base + i * kRsT + t;
+    if (idx < n) atomicAdd(&cnt[(int)((keys[idx] >> shift) & 255u)], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)t * ntiles + blockIdx.x] = cnt[t];
+}
+
+// Stable scatter: keys of one tile are ranked in their original order; within
+// a round of 256 keys, lanes of a wave with equal digits are found with eight
+// ballots, waves are ordered through LDS.
+template <class K>
+__global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                     K* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
+                                                     int shift, const int32_t* __restrict__ offs, int ntiles) {
+  __shared__ int run[256];
+  __shared__ int wc[4][256];
+  int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  run[t] = offs[(int64_t)t * ntiles + blockIdx.x];
+  int64_t base = (int64_t)blockIdx.x * kRsTile;
+  const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+  for (int r = 0; r < kRsI; ++r) {
+    wc[0][t] = 0; wc[1][t] = 0; wc[2][t] = 0; wc[3][t] = 0;
+    __syncthreads();
+    int64_t idx = base + r * kRsT + t;
+    bool valid = idx < n;
+    K key = valid ? kin[idx] : K(0);
+    int dig = (int)((key >> shift) & 255u);
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (dig >> b) & 1;
+      uint64_t bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    int rank = __popcll(m & below);
+    if (valid && rank == 0) wc[w][dig] = __popcll(m);
+    __syncthreads();
+    if (valid) {
+      int off = run[dig];
+      for (int ww = 0; ww < w; ++ww) off += wc[ww][dig];
+      int dest = off + rank;
+      kout[dest] = key;
+      if (vin) vout[dest] = vin[idx];
+    }
+    __syncthreads();
+    run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+    __syncthreads();
+  }
+}
+
+template <class K>
+void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t s) {
+  if (n <= 1 || bits <= 0) return;
+  int passes = (bits + 7) / 8;
+  int ntiles = (int)((n + kRsTile - 1) / kRsTile);
+  Buf<K> k2(c.pool, n);
+  Buf<int32_t> v2(c.pool, vals ? n : 1);
+  Buf<int32_t> hist(c.pool, (size_t)256 * ntiles);
+  K* ka = keys; K* kb = k2.p;
+  int32_t* va = vals; int32_t* vb = vals ? v2.p : nullptr;
+  for (int ps = 0; ps < passes; ++ps) {
+    int shift = 8 * ps;
+    VMO_LAUNCH((k_rs_hist<K>), ntiles, kRsT, 0, s, ka, n, shift, hist.p, ntiles);
+    scan_exclusive<int32_t>(c, hist.p, hist.p, (int64_t)256 * ntiles, nullptr, s);
+    VMO_LAUNCH((k_rs_scatter<K>), ntiles, kRsT, 0, s, ka, va, kb, vb, n, shift, hist.p, ntiles);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != keys) {
+    VMO_HIP(hipMemcpyAsync(keys, ka, sizeof(K) * n, hipMemcpyDeviceToDevice, s));
+    if (vals) VMO_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+  }
+}
+template void radix_sort<uint32_t>(Ctx&, uint32_t*, int32_t*, int64_t, int, hipStream_t);
+template void radix_sort<uint64_t>(Ctx&, uint64_t*, int32_t*, int64_t, int, hipStream_t);
+
+// ----------------------------------------------------------------- fills ----
+template <class T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_iota(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
+}
+static unsigned gs_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n > 0) VMO_LAUNCH(k_fill<int32_t>, gs_blocks(n), 256, 0, s, p, v, n);
+}
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s) {
+  if (n > 0) VMO_LAUNCH(k_fill<int64_t>, gs_blocks(n), 256, 0, s, p, v, n);
+}
+void iota_i32(int32_t* p, int64_t n, hipStream_t s) {
+  if (n > 0) VMO_LAUNCH(k_iota, gs_blocks(n), 256, 0, s, p, n);
+}
+
+// ------------------------------------------------------------ validation ----
+__global__ void k_check_ptr(const int64_t* ptr, int32_t l, int* bad) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < l; e += (int64_t)gridDim.x * blockDim.x) {
+    if (ptr[e + 1] < ptr[e]) atomicOr(bad, 1);
+    if (e == 0 && ptr[0] != 0) atomicOr(bad, 1);
+  }
+}
+// pins of net e: in range and strictly ascending (checked per pin with its
+// predecessor inside the same net, net found by binary search)
+__global__ void k_check_pins(const int64_t* ptr, const int32_t* pins, int32_t l, int32_t k, int64_t np, int* bad) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    int32_t v = pins[p];
+    if (v < 0 || v >= k) { atomicOr(bad, 2); continue; }
+    int32_t lo = 0, hi = l;  // last e with ptr[e] <= p
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (ptr[mid] <= p) lo = mid; else hi = mid;
+    }
+    if (p > ptr[lo] && pins[p - 1] >= v) atomicOr(bad, 4);
+  }
+}
+__global__ void k_check_vals(const float* v, int64_t n, int positive, int* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float a = v[i];
+    if (!(a >= 0.0f) || !(a < __builtin_inff()) || (positive && !(a > 0.0f))) atomicOr(bad, 8);
+  }
+}
+__global__ void k_check_finite(const float* v, int64_t n, int* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float a = v[i];
+    if (!(a == a) || a == __builtin_inff() || a == -__builtin_inff()) atomicOr(bad, 16);
+  }
+}
+
+void validate_hypergraph(Ctx& c, const vmo_hypergraph* h, bool positive_wc, hipStream_t s) {
+  VMO_REQUIRE(h != nullptr, "hypergraph is NULL");
+  VMO_REQUIRE(h->k >= 1, "hypergraph needs k >= 1");
+  VMO_REQUIRE(h->l >= 0, "hypergraph needs l >= 0");
+  VMO_REQUIRE(h->net_ptr != nullptr, "net_ptr is NULL");
+  Buf<int> bad(c.pool, 1);
+  VMO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+  if (h->l > 0) VMO_LAUNCH(k_check_ptr, gs_blocks(h->l), 256, 0, s, h->net_ptr, h->l, bad.p);
+  int b0 = read1(bad.p, s);
+  VMO_REQUIRE(b0 == 0, "net_ptr must start at 0 and be non-decreasing");
+  int64_t np = read1(h->net_ptr + h->l, s);
+  VMO_REQUIRE(np >= 0 && np < (int64_t(1) << 31) * 2, "too many pins");
+  if (np > 0) {
+    VMO_REQUIRE(h->pins != nullptr, "pins is NULL");
+    VMO_LAUNCH(k_check_pins, gs_blocks(np), 256, 0, s, h->net_ptr, h->pins, h->l, h->k, np, bad.p);
+  }
+  if (h->w) VMO_LAUNCH(k_check_vals, gs_blocks(h->k), 256, 0, s, h->w, (int64_t)h->k, positive_wc ? 1 : 0, bad.p);
+  if (h->c && h->l > 0) VMO_LAUNCH(k_check_vals, gs_blocks(h->l), 256, 0, s, h->c, (int64_t)h->l, positive_wc ? 1 : 0, bad.p);
+  int b = read1(bad.p, s);
+  VMO_REQUIRE(!(b & 2), "a pin is out of range [0, k)");
+  VMO_REQUIRE(!(b & 4), "pins of a net must be strictly ascending");
+  VMO_REQUIRE(!(b & 8), positive_wc ? "weights and costs must be finite and > 0" : "weights and costs must be finite and >= 0");
+}
+
+void validate_finite(Ctx& c, const float* x, int64_t n, const char* what, hipStream_t s) {
+  VMO_REQUIRE(x != nullptr, std::string(what) + " is NULL");
+  Buf<int> bad(c.pool, 1);
+  VMO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+  if (n > 0) VMO_LAUNCH(k_check_finite, gs_blocks(n), 256, 0, s, x, n, bad.p);
+  VMO_REQUIRE(read1(bad.p, s) == 0, std::string(what) + " must be finite");
+}
+
+// -------------------------------------------------------------- transpose ----
+__global__ void k_row_of(const int64_t* ptr, int32_t nrows, int64_t np, int32_t* row) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nrows;
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (ptr[mid] <= p) lo = mid; else hi = mid;
+    }
+    row[p] = lo;
+  }
+}
+__global__ void k_count_cols(const int32_t* idx, int64_t np, int64_t* cnt) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd((unsigned long long*)&cnt[idx[p]], 1ull);
+}
+__global__ void k_widen(const int32_t* in, uint32_t* out, int64_t n) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+    out[p] = (uint32_t)in[p];
+}
+
+void csr_transpose(Ctx& c, int32_t nrows, int32_t ncols, const int64_t* ptr, const int32_t* idx,
+                   int64_t* optr, int32_t* oidx, hipStream_t s) {
+  int64_t np = read1(ptr + nrows, s);
+  Buf<int64_t> cnt(c.pool, (size_t)ncols + 1);
+  fill_i64(cnt.p, 0, (int64_t)ncols + 1, s);
+  if (np > 0) {
+    VMO_LAUNCH(k_count_cols, gs_blocks(np), 256, 0, s, idx, np, cnt.p);
+    Buf<uint32_t> key(c.pool, np);
+    VMO_LAUNCH(k_widen, gs_blocks(np), 256, 0, s, idx, key.p, np);
+    VMO_LAUNCH(k_row_of, gs_blocks(np), 256, 0, s, ptr, nrows, np, oidx);
+    radix_sort<uint32_t>(c, key.p, oidx, np, bits_for((uint64_t)(ncols > 0 ? ncols - 1 : 0)), s);
+  }
+  scan_exclusive<int64_t>(c, cnt.p, optr, ncols, optr + ncols, s);
+}
+
+// ------------------------------------------------------------- components ----
+__device__ __forceinline__ int32_t uf_parent(int32_t* par, int32_t x) {
+  return __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t uf_find(int32_t* par, int32_t x) {
+  int32_t p = uf_parent(par, x);
+  while (p != x) {
+    x = p;
+    p = uf_parent(par, x);
+  }
+  return x;
+}
+// Link the pins of each net (consecutive pairs) into one tree; a root is
+// always hooked under a smaller root, so every final root is its tree's
+// smallest vertex -- the union step of Algorithm 1.
+__global__ void k_cc_union(const int64_t* ptr, const int32_t* pins, int32_t l, int32_t* par) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < l; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t b = ptr[e], en = ptr[e + 1];
+    for (int64_t p = b + 1; p < en; ++p) {
+      int32_t a = pins[p - 1], bb = pins[p];
+      while (true) {
+        a = uf_find(par, a);
+        bb = uf_find(par, bb);
+        if (a == bb) break;
+        if (a > bb) { int32_t t = a; a = bb; bb = t; }
+        int32_t old = atomicCAS(&par[bb], bb, a);
+        if (old == bb) break;
+        bb = old;
+      }
+    }
+  }
+}
+__global__ void k_cc_final(int32_t* par, int32_t k, int32_t* label) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x)
+    label[v] = uf_find(par, (int32_t)v);
+}
+
+void components(Ctx& c, int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, int32_t* label,
+                hipStream_t s) {
+  Buf<int32_t> par(c.pool, k);
+  iota_i32(par.p, k, s);
+  if (l > 0) VMO_LAUNCH(k_cc_union, gs_blocks(l), 256, 0, s, ptr, pins, l, par.p);
+  VMO_LAUNCH(k_cc_final, gs_blocks(k), 256, 0, s, par.p, k, label);
+}
+
+}  // namespace vmo

@@ -1,0 +1,198 @@
+// Internal declarations of the HIP implementation behind include/vmo.h.
+// gfx950 only: 64-wide wavefronts, 256-thread blocks unless stated.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "../../include/vmo.h"
+
+namespace vmo {
+
+// ---------------------------------------------------------------- errors ----
+struct Error : std::runtime_error {
+  vmo_status status;
+  Error(vmo_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define VMO_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::vmo::Error(e_ == hipErrorOutOfMemory ? VMO_E_NOMEM : VMO_E_DEVICE,        \
+                         std::string(#call ": ") + hipGetErrorString(e_));              \
+  } while (0)
+
+#define VMO_REQUIRE(cond, msg)                                                          \
+  do {                                                                                  \
+    if (!(cond)) throw ::vmo::Error(VMO_E_INVALID, msg);                                \
+  } while (0)
+
+// ------------------------------------------------------------------ pool ----
+// Caching device allocator: blocks are kept after release and handed out
+// again for requests of at most the same size class.  Calls synchronise their
+// stream before returning, so a released block is idle when reused.
+class Pool {
+ public:
+  ~Pool();
+  void* get(size_t bytes);
+  void put(void* p);
+  size_t held() const { return held_; }
+  void trim();
+
+ private:
+  static size_t size_class(size_t bytes);
+  std::multimap<size_t, void*> free_;
+  std::unordered_map<void*, size_t> size_;
+  size_t held_ = 0;
+};
+
+template <class T>
+struct Buf {
+  Pool* pool = nullptr;
+  T* p = nullptr;
+  size_t n = 0;
+  Buf() = default;
+  Buf(Pool& pl, size_t count) : pool(&pl), n(count) {
+    p = static_cast<T*>(pl.get((count > 0 ? count : 1) * sizeof(T)));
+  }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept : pool(o.pool), p(o.p), n(o.n) { o.p = nullptr; }
+  Buf& operator=(Buf&& o) noexcept {
+    release();
+    pool = o.pool; p = o.p; n = o.n; o.p = nullptr;
+    return *this;
+  }
+  ~Buf() { release(); }
+  void release() {
+    if (p && pool) pool->put(p);
+    p = nullptr;
+  }
+  T* operator()() const { return p; }
+};
+
+struct Ctx {
+  int device = 0;
+  std::string err;
+  Pool pool;
+};
+
+// Device scalar readback (synchronises `s`).
+template <class T>
+T read1(const T* dptr, hipStream_t s) {
+  T v;
+  VMO_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+inline unsigned nblocks(int64_t n, int per) {
+  int64_t b = (n + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > 0x7fffffff) b = 0x7fffffff;
+  return (unsigned)b;
+}
+
+#define VMO_LAUNCH(kernel, grid, block, shmem, stream, ...)                                   \
+  do {                                                                                        \
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__);          \
+    VMO_HIP(hipGetLastError());                                                               \
+  } while (0)
+
+// ------------------------------------------------------------ randomness ----
+// SplitMix64 (Steele, Lea, Flood 2014): state advances by the golden gamma,
+// each output is the mix function of the state.  rng3 chains three streams:
+// the (c+1)-th output of the stream seeded by the (b+1)-th output of the
+// stream seeded by the (a+1)-th output of the stream seeded by `seed`.
+__host__ __device__ inline uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ULL;
+__host__ __device__ inline uint64_t rng3(uint64_t seed, uint64_t a, uint64_t b, uint64_t c) {
+  uint64_t h = sm_mix(seed + kGamma * (a + 1));
+  h = sm_mix(h + kGamma * (b + 1));
+  return sm_mix(h + kGamma * (c + 1));
+}
+enum : uint64_t { kTagInit = 1, kTagProlong = 2, kTagMatch = 3, kTagKmeans = 16 };
+
+// Ordered-integer image of a float: a < b  <=>  fkey(a) < fkey(b).
+__host__ __device__ inline uint32_t fkey(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float fkey_inv(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __builtin_bit_cast(float, u);
+}
+
+// 128-bit unsigned as two words (exact D^2 sums of the k-means++ draw).
+struct U128 {
+  uint64_t lo, hi;
+};
+__host__ __device__ inline U128 u128_add(U128 a, U128 b) {
+  U128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1u : 0u);
+  return r;
+}
+__host__ __device__ inline U128 u128_sub(U128 a, U128 b) {
+  U128 r;
+  r.lo = a.lo - b.lo;
+  r.hi = a.hi - b.hi - (a.lo < b.lo ? 1u : 0u);
+  return r;
+}
+__host__ __device__ inline bool u128_gt(U128 a, U128 b) {
+  return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo);
+}
+__host__ __device__ inline bool u128_zero(U128 a) { return a.lo == 0 && a.hi == 0; }
+
+// ---------------------------------------------------------------- prims ----
+// Exclusive scan of n values (out may alias in); *total (device, optional)
+// receives the sum.  T: int32_t, int64_t, uint64_t, U128.
+template <class T>
+void scan_exclusive(Ctx& c, const T* in, T* out, int64_t n, T* total, hipStream_t s);
+
+// Stable LSD radix sort of keys (uint32_t or uint64_t) on bits [0, bits), with
+// optional int32 values carried along.  Sorted output overwrites keys/vals.
+template <class K>
+void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t s);
+
+// Fill helpers.
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+void iota_i32(int32_t* p, int64_t n, hipStream_t s);
+
+// Device-side validation of a hypergraph's pins (range, strictly ascending)
+// and of optional weights/costs (finite, >= 0 or > 0).  Throws VMO_E_INVALID.
+void validate_hypergraph(Ctx& c, const vmo_hypergraph* h, bool positive_wc, hipStream_t s);
+void validate_finite(Ctx& c, const float* x, int64_t n, const char* what, hipStream_t s);
+
+// Transpose of a CSR incidence (rows -> columns): out row j lists, ascending,
+// the input rows containing j.  nrows, ncols, ptr [nrows+1], idx -> optr
+// [ncols+1], oidx [ptr[nrows]].
+void csr_transpose(Ctx& c, int32_t nrows, int32_t ncols, const int64_t* ptr, const int32_t* idx,
+                   int64_t* optr, int32_t* oidx, hipStream_t s);
+
+// Components: label[v] = minimum vertex id of v's component.
+void components(Ctx& c, int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins,
+                int32_t* label, hipStream_t s);
+
+inline int bits_for(uint64_t maxval) {
+  int b = 0;
+  while (b < 64 && (maxval >> b) != 0) ++b;
+  return b;
+}
+
+}  // namespace vmo

@@ -1,0 +1,40 @@
+"""The C-ABI library builds, loads without a GPU, and exports every function
+that include/vmo.h declares (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "vmo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vmo_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for want in ["vmo_create", "vmo_destroy", "vmo_layout", "vmo_bisect", "vmo_order_sbd", "vmo_order_bbd",
+                 "vmo_cut", "vmo_order_batch", "vmo_dual", "vmo_model", "vmo_components"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1105_4490_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_1105_4490_amd import build
+        build.build()
+    L = ctypes.CDLL(P.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_refuses_without_library(tmp_path, monkeypatch):
+    import paper_1105_4490_amd as P
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "none.so"))
+    monkeypatch.setattr(P, "_lib", None)
+    with pytest.raises(ImportError):
+        P.lib()
