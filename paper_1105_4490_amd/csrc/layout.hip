@@ -1,23 +1,1175 @@
-// Multilevel layout (Sec. 2, Algorithms 1-3).
+// Multilevel layout on the GPU (Sec. 2): components (Algorithm 1),
+// coarsening by greedy heavy-net matching (Sec. 2.3), the 2^d-tree with
+// cluster charges and its sibling-link walk (Algorithm 3, Sec. 2.1), steepest
+// descent steps (Algorithm 3), prolongation (Algorithm 2) and packing of the
+// components side by side.
+//
+// Every floating-point step follows a fixed operation order (no contraction):
+// net centres and attraction sum in CSR order, the walk visits nodes in
+// pre-order, tree charges sum bottom-up in FP64, so one descent step gives the
+// same bits as a sequential evaluation of the same definition.
 #include "vmo_internal.h"
 
 namespace vmo {
-void layout(Ctx&, const vmo_hypergraph*, const vmo_layout_params*, float*, hipStream_t) {
-  throw Error(VMO_E_UNSUPPORTED, "layout not built yet");
+
+constexpr int kLT = 256;
+static unsigned gsz(int64_t n) {
+  int64_t b = (n + kLT - 1) / kLT;
+  return (unsigned)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
 }
-void coarsen(Ctx&, const vmo_hypergraph*, uint64_t, uint64_t, int32_t, int32_t, int32_t*, int64_t*, int32_t*, float*,
-             float*, int32_t*, int32_t*, hipStream_t) {
-  throw Error(VMO_E_UNSUPPORTED, "layout not built yet");
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// ================================================================= level ====
+struct Level {
+  int32_t k = 0, l = 0;
+  int64_t np = 0;
+  Buf<int64_t> ptr, dptr;
+  Buf<int32_t> pins, dpins;
+  Buf<float> w, c;
+  Buf<int32_t> pi;  // map to the next coarser level
+};
+
+static void make_dual(Ctx& C, Level& L, hipStream_t s) {
+  L.dptr = Buf<int64_t>(C.pool, (size_t)L.k + 1);
+  L.dpins = Buf<int32_t>(C.pool, L.np > 0 ? L.np : 1);
+  csr_transpose(C, L.l, L.k, L.ptr.p, L.pins.p, L.dptr.p, L.dpins.p, s);
 }
-void tree(Ctx&, const float*, const float*, int32_t, int32_t, int32_t*, int32_t*, float*, int32_t*, int32_t, int32_t*,
-          hipStream_t) {
-  throw Error(VMO_E_UNSUPPORTED, "layout not built yet");
+
+// ============================================================ bounding box ==
+__global__ void k_box(const float* x, int32_t k, uint32_t* box) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t mn[4], mx[4];
+  for (int d = 0; d < 4; ++d) {
+    uint32_t f = v < k ? fkey(x[(int64_t)d * k + v]) : 0xffffffffu;
+    mn[d] = f;
+    mx[d] = v < k ? f : 0u;
+  }
+  for (int off = 32; off > 0; off >>= 1)
+    for (int d = 0; d < 4; ++d) {
+      uint32_t a = __shfl_xor(mn[d], off, 64), b = __shfl_xor(mx[d], off, 64);
+      mn[d] = a < mn[d] ? a : mn[d];
+      mx[d] = b > mx[d] ? b : mx[d];
+    }
+  if ((threadIdx.x & 63) == 0)
+    for (int d = 0; d < 4; ++d) {
+      atomicMin(&box[d], mn[d]);
+      atomicMax(&box[4 + d], mx[d]);
+    }
 }
-void gradient(Ctx&, const vmo_hypergraph*, const float*, float, int32_t, float*, float*, int64_t*, hipStream_t) {
-  throw Error(VMO_E_UNSUPPORTED, "layout not built yet");
+__global__ void k_box_init(uint32_t* box) {
+  int t = threadIdx.x;
+  if (t < 4) box[t] = 0xffffffffu;
+  else if (t < 8) box[t] = 0u;
 }
-void layout_steps(Ctx&, const vmo_hypergraph*, const vmo_layout_params*, float*, int32_t, int32_t, double*,
-                  hipStream_t) {
-  throw Error(VMO_E_UNSUPPORTED, "layout not built yet");
+
+struct HostBox {
+  float lo[4], hi[4];
+  double ext() const {
+    double e = 0.0;
+    for (int d = 0; d < 4; ++d) {
+      double a = (double)hi[d] - (double)lo[d];
+      if (a > e) e = a;
+    }
+    return e;
+  }
+};
+
+static void box_of(const float* x, int32_t k, uint32_t* dbox, hipStream_t s) {
+  VMO_LAUNCH(k_box_init, 1, 64, 0, s, dbox);
+  VMO_LAUNCH(k_box, nblocks(k, kLT), kLT, 0, s, x, k, dbox);
 }
+static HostBox read_box(const uint32_t* dbox, hipStream_t s) {
+  uint32_t b[8];
+  VMO_HIP(hipMemcpyAsync(b, dbox, sizeof b, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  HostBox h;
+  for (int d = 0; d < 4; ++d) { h.lo[d] = fkey_inv(b[d]); h.hi[d] = fkey_inv(b[4 + d]); }
+  return h;
+}
+
+// =================================================================== tree ===
+// Grid coordinate of a point: floor((x - lo) * 65536 / ext), clamped to
+// 65535; ext = largest side of the bounding box (FP64).
+__device__ __forceinline__ void grid_coords(const float* x, int32_t k, int64_t v, const uint32_t* box, uint32_t* kq) {
+  double ext = 0.0;
+  float lo[4];
+  for (int d = 0; d < 4; ++d) {
+    lo[d] = fkey_inv(box[d]);
+    double e = (double)fkey_inv(box[4 + d]) - (double)lo[d];
+    if (e > ext) ext = e;
+  }
+  double sc = ext > 0.0 ? 65536.0 / ext : 0.0;
+  for (int d = 0; d < 4; ++d) {
+    uint32_t a = 0;
+    if (sc > 0.0) {
+      double f = floor(((double)x[(int64_t)d * k + v] - (double)lo[d]) * sc);
+      a = f >= 65535.0 ? 65535u : (uint32_t)f;
+    }
+    kq[d] = a;
+  }
+}
+
+// Morton key: digit at depth L (1..16) = bits (16-L) of the four coordinates,
+// dimension 0 most significant; depth-1 digit in the top nibble.
+__global__ void k_tree_keys(const float* x, int32_t k, const uint32_t* box, uint64_t* key, int32_t* val) {
+  GRID_STRIDE(v, k) {
+    uint32_t kq[4];
+    grid_coords(x, k, v, box, kq);
+    uint64_t m = 0;
+    for (int b = 15; b >= 0; --b)
+      for (int d = 0; d < 4; ++d) m = (m << 1) | ((kq[d] >> b) & 1u);
+    key[v] = m;
+    val[v] = (int32_t)v;
+  }
+}
+
+// Points in tree order: coordinates, weights and 2 kq + 1 (doubled grid units).
+__global__ void k_tree_points(const float* x, const float* w, int32_t k, const uint32_t* box, const int32_t* order,
+                              float* xs, float* ws, int32_t* p2) {
+  GRID_STRIDE(j, k) {
+    int32_t v = order[j];
+    uint32_t kq[4];
+    grid_coords(x, k, v, box, kq);
+    for (int d = 0; d < 4; ++d) {
+      xs[(int64_t)d * k + j] = x[(int64_t)d * k + v];
+      p2[(int64_t)d * k + j] = 2 * (int32_t)kq[d] + 1;
+    }
+    ws[j] = w ? w[v] : 1.0f;
+  }
+}
+
+constexpr int kCplB = 256;
+// cpl[i] = number of leading equal digits of keys i-1 and i (16 if equal);
+// cpl[0] = cpl[k] = -1.  bmin = minimum per block of 256 positions.
+__global__ __launch_bounds__(kCplB) void k_cpl(const uint64_t* key, int32_t k, int8_t* cpl, int8_t* bmin) {
+  __shared__ int sm[kCplB];
+  int64_t i = (int64_t)blockIdx.x * kCplB + threadIdx.x;
+  int c = 127;
+  if (i <= k) {
+    if (i == 0 || i == k) c = -1;
+    else {
+      uint64_t d = key[i - 1] ^ key[i];
+      c = d == 0 ? 16 : (__clzll(d) >> 2);
+    }
+    cpl[i] = (int8_t)c;
+  }
+  sm[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = kCplB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sm[threadIdx.x] = min(sm[threadIdx.x], sm[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bmin[blockIdx.x] = (int8_t)sm[0];
+}
+
+// First j > i with cpl[j] < L (exists: cpl[k] = -1).
+__device__ int32_t nsv(const int8_t* cpl, const int8_t* bmin, int32_t k, int32_t i, int L) {
+  int32_t j = i + 1;
+  int32_t bend = ((j / kCplB) + 1) * kCplB;
+  for (; j < bend && j <= k; ++j)
+    if (cpl[j] < L) return j;
+  int32_t nb = k / kCplB + 1;
+  for (int32_t b = j / kCplB; b < nb; ++b) {
+    if (bmin[b] < L) {
+      int32_t e = min(k + 1, (b + 1) * kCplB);
+      for (int32_t t = b * kCplB; t < e; ++t)
+        if (cpl[t] < L) return t;
+    }
+  }
+  return k;
+}
+
+// Depth of the leaf holding point i: the smallest L whose run (the maximal
+// interval of equal L-digit prefixes around i) has <= cap points, else 16.  A
+// run of <= cap points lies inside [i-cap+1, i+cap].  Nodes beginning at i
+// have depths cpl[i]+1 .. leaf depth.
+__global__ void k_tree_ell(const int8_t* cpl, int32_t k, int32_t cap, int8_t* ell, int32_t* nn) {
+  GRID_STRIDE(i64, (int64_t)k + 1) {
+    int32_t i = (int32_t)i64;
+    if (i == k) { nn[k] = 0; continue; }
+    int lo = i - cap + 1 < 0 ? 0 : i - cap + 1;
+    int hi = i + cap > k ? k : i + cap;
+    int L = 0;
+    for (; L <= 16; ++L) {
+      int b = -1, e = -1;
+      for (int j = i; j >= lo; --j)
+        if (cpl[j] < L) { b = j; break; }
+      for (int j = i + 1; j <= hi; ++j)
+        if (cpl[j] < L) { e = j; break; }
+      if (b >= 0 && e >= 0 && e - b <= cap) break;
+    }
+    if (L > 16) L = 16;
+    ell[i] = (int8_t)L;
+    int ci = cpl[i];
+    nn[i] = L >= ci + 1 ? L - ci : 0;
+  }
+}
+
+struct NodeView {
+  int4* a;    // cell centre x 2 (grid units)
+  int4* b;    // next, first, count, depth | leaf << 8
+  float4* X;  // charge centre
+  float* W;   // charge
+  double* Wd;
+  double* Sd;  // [n][4]
+  int32_t* parent;
+  int32_t* nch;
+  int32_t* ctr;
+};
+
+// Nodes in pre-order: index = base[i] + (L - cpl[i] - 1) for the node of
+// depth L beginning at point i; next = first node beginning at its end.
+__global__ void k_tree_nodes(const int8_t* cpl, const int8_t* bmin, const int8_t* ell, const int32_t* base,
+                             const int32_t* p2, int32_t k, NodeView nd) {
+  GRID_STRIDE(i64, k) {
+    int32_t i = (int32_t)i64;
+    int ci = cpl[i], li = ell[i];
+    if (li < ci + 1) continue;
+    for (int L = ci + 1; L <= li; ++L) {
+      int32_t t = base[i] + (L - ci - 1);
+      int32_t end = nsv(cpl, bmin, k, i, L);
+      int side = 1 << (16 - L);
+      int4 cc;
+      int kq0 = (p2[i] - 1) >> 1, kq1 = (p2[(int64_t)k + i] - 1) >> 1;
+      int kq2 = (p2[2 * (int64_t)k + i] - 1) >> 1, kq3 = (p2[3 * (int64_t)k + i] - 1) >> 1;
+      cc.x = 2 * ((kq0 >> (16 - L)) << (16 - L)) + side;
+      cc.y = 2 * ((kq1 >> (16 - L)) << (16 - L)) + side;
+      cc.z = 2 * ((kq2 >> (16 - L)) << (16 - L)) + side;
+      cc.w = 2 * ((kq3 >> (16 - L)) << (16 - L)) + side;
+      nd.a[t] = cc;
+      nd.b[t] = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
+      nd.parent[t] = -1;
+      nd.ctr[t] = 0;
+    }
+  }
+}
+
+__global__ void k_tree_links(int32_t n, NodeView nd) {
+  GRID_STRIDE(t64, n) {
+    int32_t t = (int32_t)t64;
+    int4 b = nd.b[t];
+    int cnt = 0;
+    if (!((b.w >> 8) & 1)) {
+      int32_t ch = t + 1;
+      while (ch != b.x) {
+        nd.parent[ch] = t;
+        ++cnt;
+        ch = nd.b[ch].x;
+      }
+    }
+    nd.nch[t] = cnt;
+  }
+}
+
+__device__ __forceinline__ void node_finish(NodeView nd, int32_t t, double Wd, const double* Sd) {
+  nd.Wd[t] = Wd;
+  for (int d = 0; d < 4; ++d) nd.Sd[4 * (int64_t)t + d] = Sd[d];
+  nd.W[t] = (float)Wd;
+  nd.X[t] = make_float4((float)(Sd[0] / Wd), (float)(Sd[1] / Wd), (float)(Sd[2] / Wd), (float)(Sd[3] / Wd));
+}
+
+// Charges bottom-up: a leaf sums its points in tree order (FP64); the last
+// child to finish sums its parent's children in child order.
+__global__ void k_tree_moments(int32_t n, int32_t k, const float* xs, const float* ws, NodeView nd) {
+  GRID_STRIDE(t64, n) {
+    int32_t t = (int32_t)t64;
+    int4 b = nd.b[t];
+    if (!((b.w >> 8) & 1)) continue;
+    double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t j = b.y; j < b.y + b.z; ++j) {
+      double wv = (double)ws[j];
+      Wd += wv;
+      for (int d = 0; d < 4; ++d) Sd[d] += wv * (double)xs[(int64_t)d * k + j];
+    }
+    node_finish(nd, t, Wd, Sd);
+    int32_t cur = t;
+    while (true) {
+      int32_t p = nd.parent[cur];
+      if (p < 0) break;
+      __threadfence();
+      int old = atomicAdd(&nd.ctr[p], 1);
+      if (old != nd.nch[p] - 1) break;
+      __threadfence();
+      double W2 = 0.0, S2[4] = {0.0, 0.0, 0.0, 0.0};
+      int32_t nx = nd.b[p].x;
+      for (int32_t ch = p + 1; ch != nx; ch = nd.b[ch].x) {
+        W2 += __hip_atomic_load(&nd.Wd[ch], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int d = 0; d < 4; ++d)
+          S2[d] += __hip_atomic_load(&nd.Sd[4 * (int64_t)ch + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      node_finish(nd, p, W2, S2);
+      cur = p;
+    }
+  }
+}
+
+struct Tree {
+  int32_t k = 0, n = 0;
+  Buf<uint64_t> key;
+  Buf<int32_t> order, p2, nn;
+  Buf<float> xs, ws;
+  Buf<int8_t> cpl, bmin, ell;
+  Buf<int4> a, b;
+  Buf<float4> X;
+  Buf<float> W;
+  Buf<double> Wd, Sd;
+  Buf<int32_t> parent, nch, ctr;
+  NodeView view() {
+    NodeView v;
+    v.a = a.p; v.b = b.p; v.X = X.p; v.W = W.p; v.Wd = Wd.p; v.Sd = Sd.p;
+    v.parent = parent.p; v.nch = nch.p; v.ctr = ctr.p;
+    return v;
+  }
+};
+
+// Build the tree of x [4][k] (weights w or 1) with the bounding box dbox.
+static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t k, int32_t cap, const uint32_t* dbox,
+                       hipStream_t s) {
+  T.k = k;
+  T.key = Buf<uint64_t>(C.pool, k);
+  T.order = Buf<int32_t>(C.pool, k);
+  VMO_LAUNCH(k_tree_keys, gsz(k), kLT, 0, s, x, k, dbox, T.key.p, T.order.p);
+  radix_sort<uint64_t>(C, T.key.p, T.order.p, k, 64, s);
+  T.xs = Buf<float>(C.pool, 4 * (size_t)k);
+  T.ws = Buf<float>(C.pool, k);
+  T.p2 = Buf<int32_t>(C.pool, 4 * (size_t)k);
+  VMO_LAUNCH(k_tree_points, gsz(k), kLT, 0, s, x, w, k, dbox, T.order.p, T.xs.p, T.ws.p, T.p2.p);
+  int32_t nb = k / kCplB + 1;
+  T.cpl = Buf<int8_t>(C.pool, (size_t)nb * kCplB);
+  T.bmin = Buf<int8_t>(C.pool, nb);
+  VMO_LAUNCH(k_cpl, nb, kCplB, 0, s, T.key.p, k, T.cpl.p, T.bmin.p);
+  T.ell = Buf<int8_t>(C.pool, k + 1);
+  T.nn = Buf<int32_t>(C.pool, (size_t)k + 1);
+  VMO_LAUNCH(k_tree_ell, gsz((int64_t)k + 1), kLT, 0, s, T.cpl.p, k, cap, T.ell.p, T.nn.p);
+  scan_exclusive<int32_t>(C, T.nn.p, T.nn.p, (int64_t)k + 1, nullptr, s);
+  int32_t n = read1(T.nn.p + k, s);
+  T.n = n;
+  T.a = Buf<int4>(C.pool, n);
+  T.b = Buf<int4>(C.pool, n);
+  T.X = Buf<float4>(C.pool, n);
+  T.W = Buf<float>(C.pool, n);
+  T.Wd = Buf<double>(C.pool, n);
+  T.Sd = Buf<double>(C.pool, 4 * (size_t)n);
+  T.parent = Buf<int32_t>(C.pool, n);
+  T.nch = Buf<int32_t>(C.pool, n);
+  T.ctr = Buf<int32_t>(C.pool, n);
+  NodeView nd = T.view();
+  VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.bmin.p, T.ell.p, T.nn.p, T.p2.p, k, nd);
+  VMO_LAUNCH(k_tree_links, gsz(n), kLT, 0, s, n, nd);
+  VMO_LAUNCH(k_tree_moments, gsz(n), kLT, 0, s, n, k, T.xs.p, T.ws.p, nd);
+}
+
+// ============================================================ gradient ====
+// Net centres: pins summed in CSR order, divided by the net size.
+__global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, const float* x, int32_t k, float* z) {
+  GRID_STRIDE(e, l) {
+    int64_t b = ptr[e], n = ptr[e + 1] - b;
+    for (int d = 0; d < 4; ++d) {
+      float a = 0.0f;
+      for (int64_t p = b; p < b + n; ++p) a = a + x[(int64_t)d * k + pins[p]];
+      z[(int64_t)d * l + e] = n > 0 ? a / (float)n : 0.0f;
+    }
+  }
+}
+// Attraction of eq. (7): sum over the vertex's nets in ascending net order.
+__global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, const float* c, const float* x,
+                          const float* z, int32_t l, float* y) {
+  GRID_STRIDE(v, k) {
+    int64_t b = dptr[v], e = dptr[v + 1];
+    for (int d = 0; d < 4; ++d) {
+      float a = 0.0f;
+      float xv = x[(int64_t)d * k + v];
+      for (int64_t t = b; t < e; ++t) {
+        int32_t n = dpins[t];
+        float ce = c ? c[n] : 1.0f;
+        float df = xv - z[(int64_t)d * l + n];
+        a = a + ce * df;
+      }
+      y[(int64_t)d * k + v] = a;
+    }
+  }
+}
+
+// (d-2) W w_n |X - x|^-4 (X - x), d = 4, operation by operation.
+__device__ __forceinline__ void interact(float* y, const float* xn, float wn, float X0, float X1, float X2, float X3,
+                                         float W) {
+  float dx0 = X0 - xn[0], dx1 = X1 - xn[1], dx2 = X2 - xn[2], dx3 = X3 - xn[3];
+  float r2 = dx0 * dx0;
+  r2 = r2 + dx1 * dx1;
+  r2 = r2 + dx2 * dx2;
+  r2 = r2 + dx3 * dx3;
+  if (!(r2 > 0.0f)) return;
+  float num = 2.0f * W;
+  num = num * wn;
+  float den = r2 * r2;
+  float f = num / den;
+  y[0] = y[0] + f * dx0;
+  y[1] = y[1] + f * dx1;
+  y[2] = y[2] + f * dx2;
+  y[3] = y[3] + f * dx3;
+}
+
+// Repulsion by the stackless walk of Algorithm 3: a far node acts as one charge
+// and the walk jumps to its sibling link; a near internal node is entered; a
+// near leaf acts point by point.  One thread per point, points in tree order.
+__global__ __launch_bounds__(kLT) void k_walk(int32_t k, int32_t n, const int32_t* order, const float* xs,
+                                              const float* ws, const int32_t* p2, const int4* na, const int4* nb,
+                                              const float4* nX, const float* nW, double th2, float* y,
+                                              unsigned long long* nint) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long cnt = 0;
+  if (j < k) {
+    int32_t v = order[j];
+    float xn[4], yn[4];
+    int32_t q[4];
+    for (int d = 0; d < 4; ++d) {
+      xn[d] = xs[(int64_t)d * k + j];
+      q[d] = p2[(int64_t)d * k + j];
+      yn[d] = y[(int64_t)d * k + v];
+    }
+    float wn = ws[j];
+    int32_t t = 0;
+    while (t < n) {
+      int4 a = na[t];
+      int4 b = nb[t];
+      int depth = b.w & 255;
+      bool far = false;
+      if (th2 > 0.0) {
+        int64_t d0 = q[0] - a.x, d1 = q[1] - a.y, d2 = q[2] - a.z, d3 = q[3] - a.w;
+        int64_t D2 = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+        int64_t s2 = (int64_t)2 << (16 - depth);
+        far = (double)(s2 * s2) < th2 * (double)D2;
+      }
+      if (far) {
+        float4 X = nX[t];
+        interact(yn, xn, wn, X.x, X.y, X.z, X.w, nW[t]);
+        ++cnt;
+        t = b.x;
+      } else if (!((b.w >> 8) & 1)) {
+        t = t + 1;
+      } else {
+        for (int32_t i = b.y; i < b.y + b.z; ++i) {
+          if (i == j) continue;
+          interact(yn, xn, wn, xs[i], xs[(int64_t)k + i], xs[2 * (int64_t)k + i], xs[3 * (int64_t)k + i], ws[i]);
+          ++cnt;
+        }
+        t = b.x;
+      }
+    }
+    for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yn[d];
+  }
+  if (nint) {
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nint, cnt);
+  }
+}
+
+// x_n <- x_n - (alpha / |y_n|) y_n.
+__global__ void k_step(int32_t k, const float* y, float* x, double alpha) {
+  GRID_STRIDE(v, k) {
+    float y0 = y[v], y1 = y[(int64_t)k + v], y2 = y[2 * (int64_t)k + v], y3 = y[3 * (int64_t)k + v];
+    float n2 = y0 * y0;
+    n2 = n2 + y1 * y1;
+    n2 = n2 + y2 * y2;
+    n2 = n2 + y3 * y3;
+    if (!(n2 > 0.0f)) continue;
+    float f = (float)(alpha / sqrt((double)n2));
+    float t0 = f * y0, t1 = f * y1, t2 = f * y2, t3 = f * y3;
+    x[v] = x[v] - t0;
+    x[(int64_t)k + v] = x[(int64_t)k + v] - t1;
+    x[2 * (int64_t)k + v] = x[2 * (int64_t)k + v] - t2;
+    x[3 * (int64_t)k + v] = x[3 * (int64_t)k + v] - t3;
+  }
+}
+
+struct GradWork {
+  Buf<float> z;
+  Buf<uint32_t> box;
+  Tree T;
+};
+
+// y = gradient of eq. (6) at x (attraction + tree repulsion); box of x in gw.box.
+static void gradient_level(Ctx& C, const Level& L, const float* x, double th2, int32_t cap, float* y, GradWork& gw,
+                           unsigned long long* nint, hipStream_t s) {
+  if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
+  box_of(x, L.k, gw.box.p, s);
+  gw.z = Buf<float>(C.pool, 4 * (size_t)(L.l > 0 ? L.l : 1));
+  if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, L.k, gw.z.p);
+  VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, L.l, y);
+  build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, s);
+  VMO_LAUNCH(k_walk, nblocks(L.k, kLT), kLT, 0, s, L.k, gw.T.n, gw.T.order.p, gw.T.xs.p, gw.T.ws.p, gw.T.p2.p, gw.T.a.p,
+             gw.T.b.p, gw.T.X.p, gw.T.W.p, th2, y, nint);
+}
+
+// One descent step (Algorithm 3).  alpha: step length (host); at it == 0 it
+// is set from the box, alpha = step0 * V^(1/4) (V = 0: largest side).
+static void descent_step(Ctx& C, const Level& L, float* x, const vmo_layout_params* p, int32_t it, double* alpha,
+                         float* y, GradWork& gw, hipStream_t s) {
+  double th2 = (double)p->theta * (double)p->theta;
+  gradient_level(C, L, x, th2, p->leaf_cap, y, gw, nullptr, s);
+  if (it == 0) {
+    HostBox hb = read_box(gw.box.p, s);
+    double V = 1.0, ext = 0.0;
+    for (int d = 0; d < 4; ++d) {
+      double e = (double)hb.hi[d] - (double)hb.lo[d];
+      V = V * e;
+      if (e > ext) ext = e;
+    }
+    double side = V > 0.0 ? sqrt(sqrt(V)) : ext;
+    *alpha = (double)p->step0_frac * side;
+  } else {
+    *alpha = *alpha * (double)p->decay;
+  }
+  VMO_LAUNCH(k_step, gsz(L.k), kLT, 0, s, L.k, y, x, *alpha);
+}
+
+// ================================================================ coarsen ===
+struct Prio {
+  double om;
+  uint64_t hs;
+  int32_t a, b;
+};
+__device__ __forceinline__ bool prio_gt(const Prio& x, const Prio& y) {
+  if (x.om != y.om) return x.om > y.om;
+  if (x.hs != y.hs) return x.hs > y.hs;
+  if (x.a != y.a) return x.a < y.a;
+  return x.b < y.b;
+}
+
+// Best unmatched candidate partner of every unmatched vertex: the pair of
+// highest priority (cost/(|e|-1) over a shared net of 2..mm pins, then the
+// keyed hash, then the smaller ids).
+__global__ void k_match_best(const int64_t* ptr, const int32_t* pins, const int64_t* dptr, const int32_t* dpins,
+                             const float* c, int32_t k, int32_t mm, const int32_t* mate, uint64_t seed, uint64_t mkey,
+                             int32_t* best) {
+  GRID_STRIDE(u64, k) {
+    int32_t u = (int32_t)u64;
+    if (mate[u] >= 0) { best[u] = -1; continue; }
+    Prio bp;
+    bp.om = -1.0; bp.hs = 0; bp.a = 0x7fffffff; bp.b = 0x7fffffff;
+    int32_t bv = -1;
+    for (int64_t t = dptr[u]; t < dptr[u + 1]; ++t) {
+      int32_t e = dpins[t];
+      int64_t b = ptr[e], n = ptr[e + 1] - b;
+      if (n < 2 || n > mm) continue;
+      double om = (double)(c ? c[e] : 1.0f) / (double)(n - 1);
+      for (int64_t p = b; p < b + n; ++p) {
+        int32_t v = pins[p];
+        if (v == u || mate[v] >= 0) continue;
+        Prio q;
+        q.om = om;
+        q.a = u < v ? u : v;
+        q.b = u < v ? v : u;
+        q.hs = rng3(seed, mkey, (uint64_t)q.a, (uint64_t)q.b);
+        if (bv < 0 || prio_gt(q, bp)) { bp = q; bv = v; }
+      }
+    }
+    best[u] = bv;
+  }
+}
+__global__ void k_match_pair(const int32_t* best, int32_t k, int32_t* mate, int32_t* changed) {
+  GRID_STRIDE(u64, k) {
+    int32_t u = (int32_t)u64;
+    int32_t v = best[u];
+    if (mate[u] < 0 && v >= 0 && best[v] == u) {
+      mate[u] = v;
+      atomicAdd(changed, 1);
+    }
+  }
+}
+// Group root: the smaller vertex of a matched pair; an unmatched vertex with
+// exactly one candidate neighbour joins that neighbour's group.
+__global__ void k_group_root(const int64_t* ptr, const int32_t* pins, const int64_t* dptr, const int32_t* dpins,
+                             int32_t k, int32_t mm, const int32_t* mate, int32_t* root, int32_t* gmin) {
+  GRID_STRIDE(u64, k) {
+    int32_t u = (int32_t)u64;
+    int32_t m = mate[u];
+    int32_t r = u;
+    if (m >= 0) r = u < m ? u : m;
+    else {
+      int32_t v0 = -1;
+      bool multi = false;
+      for (int64_t t = dptr[u]; t < dptr[u + 1] && !multi; ++t) {
+        int32_t e = dpins[t];
+        int64_t b = ptr[e], n = ptr[e + 1] - b;
+        if (n < 2 || n > mm) continue;
+        for (int64_t p = b; p < b + n; ++p) {
+          int32_t v = pins[p];
+          if (v == u) continue;
+          if (v0 < 0) v0 = v;
+          else if (v != v0) { multi = true; break; }
+        }
+      }
+      if (v0 >= 0 && !multi) {
+        int32_t mv = mate[v0];
+        r = mv >= 0 ? (v0 < mv ? v0 : mv) : v0;
+      }
+    }
+    root[u] = r;
+  }
+}
+__global__ void k_group_min(const int32_t* root, int32_t k, int32_t* gmin) {
+  GRID_STRIDE(u, k) atomicMin(&gmin[root[u]], (int32_t)u);
+}
+__global__ void k_group_flag(const int32_t* root, const int32_t* gmin, int32_t k, int32_t* flag) {
+  GRID_STRIDE(u, k) flag[u] = gmin[root[u]] == (int32_t)u ? 1 : 0;
+}
+__global__ void k_group_pi(const int32_t* root, const int32_t* gmin, const int32_t* rank, int32_t k, int32_t* pi,
+                           uint32_t* key) {
+  GRID_STRIDE(u, k) {
+    int32_t g = rank[gmin[root[u]]];
+    pi[u] = g;
+    key[u] = (uint32_t)g;
+  }
+}
+__global__ void k_count_i32(const int32_t* idx, int64_t n, int64_t* cnt) {
+  GRID_STRIDE(i, n) atomicAdd((unsigned long long*)&cnt[idx[i]], 1ull);
+}
+// Coarse weight = member weights summed in ascending member id.
+__global__ void k_coarse_w(const int64_t* gstart, const int32_t* members, const float* w, int32_t kc, float* cw) {
+  GRID_STRIDE(g, kc) {
+    float a = 0.0f;
+    for (int64_t t = gstart[g]; t < gstart[g + 1]; ++t) a = a + (w ? w[members[t]] : 1.0f);
+    cw[g] = a;
+  }
+}
+// Net images: key (net, coarse pin) per pin.
+__global__ void k_img_keys(const int64_t* ptr, const int32_t* pins, int32_t l, const int32_t* pi, uint64_t* key) {
+  GRID_STRIDE(e, l) {
+    for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) key[p] = ((uint64_t)e << 32) | (uint32_t)pi[pins[p]];
+  }
+}
+__global__ void k_img_uniq(const uint64_t* key, int64_t np, int32_t* ufl, int64_t* ilen) {
+  GRID_STRIDE(p, np) {
+    bool u = p == 0 || key[p] != key[p - 1];
+    ufl[p] = u ? 1 : 0;
+    if (u) atomicAdd((unsigned long long*)&ilen[key[p] >> 32], 1ull);
+  }
+}
+__global__ void k_img_keep(const int64_t* ilen, int32_t l, int32_t* kf) {
+  GRID_STRIDE(e, l) kf[e] = ilen[e] >= 2 ? 1 : 0;
+}
+__global__ void k_img_len(const int64_t* ilen, const int32_t* kf, const int32_t* kidx, int32_t l, int64_t* klen) {
+  GRID_STRIDE(e, l) if (kf[e]) klen[kidx[e]] = ilen[e];
+}
+__global__ void k_img_pins(const uint64_t* key, const int32_t* ufl, const int32_t* uscan, const int64_t* ptr,
+                           const int32_t* kf, const int32_t* kidx, const int64_t* iptr, int64_t np, int32_t* ipins) {
+  GRID_STRIDE(p, np) {
+    if (!ufl[p]) continue;
+    int32_t e = (int32_t)(key[p] >> 32);
+    if (!kf[e]) continue;
+    int64_t r = uscan[p] - uscan[ptr[e]];
+    ipins[iptr[kidx[e]] + r] = (int32_t)(key[p] & 0xffffffffu);
+  }
+}
+__global__ void k_img_hash(const int64_t* iptr, const int32_t* ipins, int32_t nk, uint64_t* hs, int32_t* val) {
+  GRID_STRIDE(i, nk) {
+    uint64_t h = 0x5851F42D4C957F2DULL;
+    for (int64_t p = iptr[i]; p < iptr[i + 1]; ++p) h = sm_mix(h + kGamma * ((uint64_t)(uint32_t)ipins[p] + 1));
+    hs[i] = sm_mix(h + (uint64_t)(iptr[i + 1] - iptr[i]));
+    val[i] = (int32_t)i;
+  }
+}
+__device__ bool img_equal(const int64_t* iptr, const int32_t* ipins, int32_t a, int32_t b) {
+  int64_t la = iptr[a + 1] - iptr[a], lb = iptr[b + 1] - iptr[b];
+  if (la != lb) return false;
+  for (int64_t t = 0; t < la; ++t)
+    if (ipins[iptr[a] + t] != ipins[iptr[b] + t]) return false;
+  return true;
+}
+// Representative of each kept net: the first net (in net order) of its run of
+// equal hashes with the same image.
+__global__ void k_img_rep(const uint64_t* hs, const int32_t* val, const int64_t* iptr, const int32_t* ipins, int32_t nk,
+                          int32_t* repflag, int32_t* reppos) {
+  GRID_STRIDE(i, nk) {
+    int32_t me = val[i];
+    int64_t r = i;
+    for (int64_t j = i - 1; j >= 0 && hs[j] == hs[i]; --j)
+      if (img_equal(iptr, ipins, val[j], me)) r = j;
+    reppos[i] = (int32_t)r;
+    repflag[me] = r == i ? 1 : 0;
+  }
+}
+// Merged cost (members in ascending net order) and length of each coarse net.
+__global__ void k_img_cost(const uint64_t* hs, const int32_t* val, const int32_t* reppos, const int32_t* kept_net,
+                           const float* c, const int64_t* iptr, const int32_t* cidx, int32_t nk, float* cc,
+                           int64_t* clen) {
+  GRID_STRIDE(i, nk) {
+    if (reppos[i] != i) continue;
+    int32_t me = val[i];
+    float a = c ? c[kept_net[me]] : 1.0f;
+    for (int64_t j = i + 1; j < nk && hs[j] == hs[i]; ++j)
+      if (reppos[j] == i) a = a + (c ? c[kept_net[val[j]]] : 1.0f);
+    cc[cidx[me]] = a;
+    clen[cidx[me]] = iptr[me + 1] - iptr[me];
+  }
+}
+__global__ void k_kept_net(const int32_t* kf, const int32_t* kidx, int32_t l, int32_t* kept_net) {
+  GRID_STRIDE(e, l) if (kf[e]) kept_net[kidx[e]] = (int32_t)e;
+}
+__global__ void k_coarse_pins(const int32_t* repflag, const int32_t* cidx, const int64_t* iptr, const int32_t* ipins,
+                              const int64_t* cptr, int32_t nk, int32_t* cpins) {
+  GRID_STRIDE(i, nk) {
+    if (!repflag[i]) continue;
+    int64_t o = cptr[cidx[i]];
+    for (int64_t p = iptr[i]; p < iptr[i + 1]; ++p) cpins[o + (p - iptr[i])] = ipins[p];
+  }
+}
+
+// One coarsening step of level F into C (pi written to F.pi).
+static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t comp, int32_t level, int32_t mm,
+                          hipStream_t s) {
+  int32_t k = F.k, l = F.l;
+  int64_t np = F.np;
+  uint64_t mkey = kTagMatch | ((uint64_t)level << 8) | (comp << 32);
+  Buf<int32_t> mate(Cx.pool, k), best(Cx.pool, k), chg(Cx.pool, 1);
+  fill_i32(mate.p, -1, k, s);
+  // every round matches at least the best remaining pair, so at most k/2 + 1
+  for (int64_t round = 0;; ++round) {
+    VMO_REQUIRE(round <= (int64_t)k / 2 + 1, "matching did not settle");
+    VMO_LAUNCH(k_match_best, gsz(k), kLT, 0, s, F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, F.c.p, k, mm, mate.p, seed,
+               mkey, best.p);
+    VMO_HIP(hipMemsetAsync(chg.p, 0, 4, s));
+    VMO_LAUNCH(k_match_pair, gsz(k), kLT, 0, s, best.p, k, mate.p, chg.p);
+    if (read1(chg.p, s) == 0) break;
+  }
+  Buf<int32_t> root(Cx.pool, k), gmin(Cx.pool, k), flag(Cx.pool, (size_t)k + 1), rank(Cx.pool, (size_t)k + 1);
+  VMO_LAUNCH(k_group_root, gsz(k), kLT, 0, s, F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, k, mm, mate.p, root.p, gmin.p);
+  fill_i32(gmin.p, k, k, s);
+  VMO_LAUNCH(k_group_min, gsz(k), kLT, 0, s, root.p, k, gmin.p);
+  VMO_LAUNCH(k_group_flag, gsz(k), kLT, 0, s, root.p, gmin.p, k, flag.p);
+  scan_exclusive<int32_t>(Cx, flag.p, rank.p, k, rank.p + k, s);
+  int32_t kc = read1(rank.p + k, s);
+  F.pi = Buf<int32_t>(Cx.pool, k);
+  Buf<uint32_t> gkey(Cx.pool, k);
+  Buf<int32_t> members(Cx.pool, k);
+  VMO_LAUNCH(k_group_pi, gsz(k), kLT, 0, s, root.p, gmin.p, rank.p, k, F.pi.p, gkey.p);
+  iota_i32(members.p, k, s);
+  radix_sort<uint32_t>(Cx, gkey.p, members.p, k, bits_for((uint64_t)(kc > 0 ? kc - 1 : 0)), s);
+  Buf<int64_t> gstart(Cx.pool, (size_t)kc + 1);
+  fill_i64(gstart.p, 0, (int64_t)kc + 1, s);
+  VMO_LAUNCH(k_count_i32, gsz(k), kLT, 0, s, F.pi.p, (int64_t)k, gstart.p);
+  scan_exclusive<int64_t>(Cx, gstart.p, gstart.p, kc, gstart.p + kc, s);
+  Cl.k = kc;
+  Cl.w = Buf<float>(Cx.pool, kc);
+  VMO_LAUNCH(k_coarse_w, gsz(kc), kLT, 0, s, gstart.p, members.p, F.w.p, kc, Cl.w.p);
+  // net images
+  int32_t lc = 0;
+  int64_t cnp = 0;
+  Cl.ptr = Buf<int64_t>(Cx.pool, (size_t)(l > 0 ? l : 0) + 1);
+  if (l > 0 && np > 0) {
+    Buf<uint64_t> key(Cx.pool, np);
+    VMO_LAUNCH(k_img_keys, gsz(l), kLT, 0, s, F.ptr.p, F.pins.p, l, F.pi.p, key.p);
+    radix_sort<uint64_t>(Cx, key.p, nullptr, np, 32 + bits_for((uint64_t)l), s);
+    Buf<int32_t> ufl(Cx.pool, np + 1), uscan(Cx.pool, np + 1);
+    Buf<int64_t> ilen(Cx.pool, l);
+    fill_i64(ilen.p, 0, l, s);
+    VMO_LAUNCH(k_img_uniq, gsz(np), kLT, 0, s, key.p, np, ufl.p, ilen.p);
+    scan_exclusive<int32_t>(Cx, ufl.p, uscan.p, np, uscan.p + np, s);
+    Buf<int32_t> kf(Cx.pool, (size_t)l + 1), kidx(Cx.pool, (size_t)l + 1);
+    VMO_LAUNCH(k_img_keep, gsz(l), kLT, 0, s, ilen.p, l, kf.p);
+    scan_exclusive<int32_t>(Cx, kf.p, kidx.p, l, kidx.p + l, s);
+    int32_t nk = read1(kidx.p + l, s);
+    if (nk > 0) {
+      Buf<int64_t> iptr(Cx.pool, (size_t)nk + 1);
+      VMO_LAUNCH(k_img_len, gsz(l), kLT, 0, s, ilen.p, kf.p, kidx.p, l, iptr.p);
+      scan_exclusive<int64_t>(Cx, iptr.p, iptr.p, nk, iptr.p + nk, s);
+      int64_t inp = read1(iptr.p + nk, s);
+      Buf<int32_t> ipins(Cx.pool, inp);
+      VMO_LAUNCH(k_img_pins, gsz(np), kLT, 0, s, key.p, ufl.p, uscan.p, F.ptr.p, kf.p, kidx.p, iptr.p, np, ipins.p);
+      Buf<uint64_t> hs(Cx.pool, nk);
+      Buf<int32_t> val(Cx.pool, nk), repflag(Cx.pool, (size_t)nk + 1), reppos(Cx.pool, nk), cidx(Cx.pool, (size_t)nk + 1);
+      Buf<int32_t> kept_net(Cx.pool, nk);
+      VMO_LAUNCH(k_kept_net, gsz(l), kLT, 0, s, kf.p, kidx.p, l, kept_net.p);
+      VMO_LAUNCH(k_img_hash, gsz(nk), kLT, 0, s, iptr.p, ipins.p, nk, hs.p, val.p);
+      radix_sort<uint64_t>(Cx, hs.p, val.p, nk, 64, s);
+      VMO_LAUNCH(k_img_rep, gsz(nk), kLT, 0, s, hs.p, val.p, iptr.p, ipins.p, nk, repflag.p, reppos.p);
+      scan_exclusive<int32_t>(Cx, repflag.p, cidx.p, nk, cidx.p + nk, s);
+      lc = read1(cidx.p + nk, s);
+      Cl.c = Buf<float>(Cx.pool, lc > 0 ? lc : 1);
+      Buf<int64_t> clen(Cx.pool, (size_t)lc + 1);
+      VMO_LAUNCH(k_img_cost, gsz(nk), kLT, 0, s, hs.p, val.p, reppos.p, kept_net.p, F.c.p, iptr.p, cidx.p, nk, Cl.c.p,
+                 clen.p);
+      scan_exclusive<int64_t>(Cx, clen.p, Cl.ptr.p, lc, Cl.ptr.p + lc, s);
+      cnp = read1(Cl.ptr.p + lc, s);
+      Cl.pins = Buf<int32_t>(Cx.pool, cnp > 0 ? cnp : 1);
+      VMO_LAUNCH(k_coarse_pins, gsz(nk), kLT, 0, s, repflag.p, cidx.p, iptr.p, ipins.p, Cl.ptr.p, nk, Cl.pins.p);
+    }
+  }
+  if (lc == 0) {
+    fill_i64(Cl.ptr.p, 0, 1, s);
+    Cl.c = Buf<float>(Cx.pool, 1);
+    Cl.pins = Buf<int32_t>(Cx.pool, 1);
+  }
+  Cl.l = lc;
+  Cl.np = cnp;
+  VMO_HIP(hipStreamSynchronize(s));
+}
+
+// ======================================================= init / prolong ====
+__global__ void k_init_x(int32_t k, uint64_t seed, uint64_t key, float a, float* x) {
+  GRID_STRIDE(v, k) {
+    for (int d = 0; d < 4; ++d) {
+      uint64_t r = rng3(seed, key, (uint64_t)v, (uint64_t)d);
+      float u = (float)(uint32_t)(r >> 40) * 0x1p-24f;
+      x[(int64_t)d * k + v] = (u - 0.5f) * a;
+    }
+  }
+}
+__global__ void k_prolong(int32_t kf, const int32_t* pi, const float* xc, int32_t kc, uint64_t seed, uint64_t key,
+                          float sigma, float eps, float* xf) {
+  GRID_STRIDE(v, kf) {
+    for (int d = 0; d < 4; ++d) {
+      uint64_t r = rng3(seed, key, (uint64_t)v, (uint64_t)d);
+      float u = (float)(uint32_t)(r >> 40) * 0x1p-23f;
+      u = u - 1.0f;
+      float a = sigma * xc[(int64_t)d * kc + pi[v]];
+      float b = eps * u;
+      xf[(int64_t)d * kf + v] = a + b;
+    }
+  }
+}
+
+// Multilevel layout of one connected hypergraph (Algorithm 2).  L[0] is the
+// finest level (with its dual); x [4][k0] output.
+static void layout_component(Ctx& C, std::vector<Level>& L, const vmo_layout_params* p, uint64_t comp, float* xout,
+                             hipStream_t s) {
+  int32_t J = 0;
+  while (L[J].k > p->min_coarse && J < p->max_levels) {
+    Level Cl;
+    coarsen_level(C, L[J], Cl, p->seed, comp, J, p->match_max_net, s);
+    if ((double)Cl.k > (double)p->stall * (double)L[J].k) {
+      L[J].pi = Buf<int32_t>();
+      break;
+    }
+    make_dual(C, Cl, s);
+    L.push_back(std::move(Cl));
+    ++J;
+  }
+  Buf<float> x(C.pool, 4 * (size_t)L[J].k);
+  {
+    float a = (float)sqrt(sqrt((double)L[J].k));
+    uint64_t key = kTagInit | ((uint64_t)J << 8) | (comp << 32);
+    VMO_LAUNCH(k_init_x, gsz(L[J].k), kLT, 0, s, L[J].k, p->seed, key, a, x.p);
+  }
+  GradWork gw;
+  for (int32_t j = J; j >= 0; --j) {
+    int32_t iters = j == J ? p->coarsest_iters : p->level_iters;
+    double alpha = 0.0;
+    Buf<float> y(C.pool, 4 * (size_t)L[j].k);
+    for (int32_t it = 0; it < iters; ++it) descent_step(C, L[j], x.p, p, it, &alpha, y.p, gw, s);
+    if (j > 0) {
+      if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
+      box_of(x.p, L[j].k, gw.box.p, s);
+      HostBox hb = read_box(gw.box.p, s);
+      double ext = hb.ext();
+      int32_t kf = L[j - 1].k, kc = L[j].k;
+      float sigma = (float)sqrt(sqrt((double)kf / (double)kc));
+      double epsd = (double)p->jitter * ext;
+      float eps = (float)(epsd / sqrt(sqrt((double)kc)));
+      uint64_t key = kTagProlong | ((uint64_t)(j - 1) << 8) | (comp << 32);
+      Buf<float> xf(C.pool, 4 * (size_t)kf);
+      VMO_LAUNCH(k_prolong, gsz(kf), kLT, 0, s, kf, L[j - 1].pi.p, x.p, kc, p->seed, key, sigma, eps, xf.p);
+      x = std::move(xf);
+    }
+  }
+  VMO_HIP(hipMemcpyAsync(xout, x.p, sizeof(float) * 4 * (size_t)L[0].k, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipStreamSynchronize(s));
+}
+
+// ============================================================ components ===
+__global__ void k_comp_flag(const uint32_t* lab_sorted, int32_t k, int32_t* flag) {
+  GRID_STRIDE(i, k) flag[i] = (i == 0 || lab_sorted[i] != lab_sorted[i - 1]) ? 1 : 0;
+}
+__global__ void k_comp_index(const int32_t* vorder, const int32_t* cscan, const int32_t* flag, int32_t k,
+                             int32_t* comp_of, int32_t* cstart) {
+  GRID_STRIDE(i, k) {
+    int32_t c = cscan[i] + flag[i] - 1;  // inclusive count - 1
+    comp_of[vorder[i]] = c;
+    if (flag[i]) cstart[c] = (int32_t)i;
+  }
+}
+__global__ void k_local_id(const int32_t* vorder, const int32_t* comp_of, const int32_t* cstart, int32_t k,
+                           int32_t* loc) {
+  GRID_STRIDE(i, k) loc[vorder[i]] = (int32_t)i - cstart[comp_of[vorder[i]]];
+}
+__global__ void k_net_comp(const int64_t* ptr, const int32_t* pins, int32_t l, const int32_t* comp_of, int32_t ncomp,
+                           uint32_t* key, int32_t* val) {
+  GRID_STRIDE(e, l) {
+    key[e] = ptr[e + 1] > ptr[e] ? (uint32_t)comp_of[pins[ptr[e]]] : (uint32_t)ncomp;
+    val[e] = (int32_t)e;
+  }
+}
+__global__ void k_net_len(const int64_t* ptr, const int32_t* order, int32_t l, int64_t* len) {
+  GRID_STRIDE(t, l) len[t] = ptr[order[t] + 1] - ptr[order[t]];
+}
+__global__ void k_net_fill(const int64_t* ptr, const int32_t* pins, const int32_t* order, const int64_t* optr,
+                           const int32_t* loc, const float* c, int32_t l, int32_t* opins, float* oc) {
+  GRID_STRIDE(t, l) {
+    int32_t e = order[t];
+    int64_t o = optr[t];
+    for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) opins[o + (p - ptr[e])] = loc[pins[p]];
+    oc[t] = c ? c[e] : 1.0f;
+  }
+}
+__global__ void k_gather_w(const int32_t* vorder, const float* w, int32_t k, float* ow) {
+  GRID_STRIDE(i, k) ow[i] = w ? w[vorder[i]] : 1.0f;
+}
+__global__ void k_sub_ptr(const int64_t* in, int64_t n, int64_t sub, int64_t* out) {
+  GRID_STRIDE(i, n) out[i] = in[i] - sub;
+}
+__global__ void k_comp_box(const float* xl, int32_t k, const int32_t* comp_of_pos, uint32_t* boxes) {
+  GRID_STRIDE(i, k) {
+    int32_t c = comp_of_pos[i];
+    for (int d = 0; d < 4; ++d) {
+      uint32_t f = fkey(xl[(int64_t)d * k + i]);
+      atomicMin(&boxes[8 * (int64_t)c + d], f);
+      atomicMax(&boxes[8 * (int64_t)c + 4 + d], f);
+    }
+  }
+}
+__global__ void k_comp_pos(const int32_t* vorder, const int32_t* comp_of, int32_t k, int32_t* cpos) {
+  GRID_STRIDE(i, k) cpos[i] = comp_of[vorder[i]];
+}
+__global__ void k_boxes_init(uint32_t* b, int64_t n) {
+  GRID_STRIDE(i, n) b[i] = (i & 7) < 4 ? 0xffffffffu : 0u;
+}
+// Packing: component c is shifted so its box minimum sits at (off_c, 0, 0, 0).
+__global__ void k_pack(const float* xl, const int32_t* vorder, const int32_t* cpos, const float* clo,
+                       const double* coff, int32_t k, float* x) {
+  GRID_STRIDE(i, k) {
+    int32_t v = vorder[i], c = cpos[i];
+    double t0 = (double)xl[i] - (double)clo[4 * (int64_t)c];
+    x[v] = (float)(t0 + coff[c]);
+    for (int d = 1; d < 4; ++d)
+      x[(int64_t)d * k + v] = (float)((double)xl[(int64_t)d * k + i] - (double)clo[4 * (int64_t)c + d]);
+  }
+}
+// Copy component c's SoA block (k_c points at offset o of xl) from x_c.
+__global__ void k_put_comp(const float* xc, int32_t kc, int32_t o, int32_t k, float* xl) {
+  GRID_STRIDE(i, kc) for (int d = 0; d < 4; ++d) xl[(int64_t)d * k + o + i] = xc[(int64_t)d * kc + i];
+}
+
+static void check_params(const vmo_layout_params* p) {
+  VMO_REQUIRE(p != nullptr, "layout parameters are NULL");
+  VMO_REQUIRE(p->coarsest_iters >= 0 && p->level_iters >= 0, "iteration counts must be >= 0");
+  VMO_REQUIRE(p->min_coarse >= 1 && p->max_levels >= 0, "min_coarse >= 1 and max_levels >= 0");
+  VMO_REQUIRE(p->leaf_cap >= 1 && p->leaf_cap <= 64, "leaf_cap must be in [1, 64]");
+  VMO_REQUIRE(p->match_max_net >= 2, "match_max_net must be >= 2");
+  VMO_REQUIRE(p->theta >= 0.0f && p->step0_frac > 0.0f && p->decay > 0.0f, "theta >= 0, step0_frac > 0, decay > 0");
+  VMO_REQUIRE(p->jitter >= 0.0f && p->stall > 0.0f && p->pack_gap >= 0.0f, "jitter, stall, pack_gap out of range");
+}
+
+// Host copy of one level from device arrays (the finest level of a component).
+static Level level_from(Ctx& C, int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+                        const float* c, hipStream_t s) {
+  Level L;
+  L.k = k;
+  L.l = l;
+  L.np = read1(ptr + l, s) - read1(ptr, s);
+  int64_t base = read1(ptr, s);
+  L.ptr = Buf<int64_t>(C.pool, (size_t)l + 1);
+  VMO_LAUNCH(k_sub_ptr, gsz((int64_t)l + 1), kLT, 0, s, ptr, (int64_t)l + 1, base, L.ptr.p);
+  L.pins = Buf<int32_t>(C.pool, L.np > 0 ? L.np : 1);
+  if (L.np > 0) VMO_HIP(hipMemcpyAsync(L.pins.p, pins + base, 4 * L.np, hipMemcpyDeviceToDevice, s));
+  L.w = Buf<float>(C.pool, k);
+  if (w) VMO_HIP(hipMemcpyAsync(L.w.p, w, 4 * (size_t)k, hipMemcpyDeviceToDevice, s));
+  else VMO_LAUNCH(k_gather_w, gsz(k), kLT, 0, s, (const int32_t*)nullptr, (const float*)nullptr, k, L.w.p);
+  L.c = Buf<float>(C.pool, l > 0 ? l : 1);
+  if (l > 0) {
+    if (c) VMO_HIP(hipMemcpyAsync(L.c.p, c, 4 * (size_t)l, hipMemcpyDeviceToDevice, s));
+    else fill_i32(reinterpret_cast<int32_t*>(L.c.p), 0x3f800000, l, s);
+  }
+  make_dual(C, L, s);
+  return L;
+}
+
+// =========================================================== entry points ==
+void layout(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, hipStream_t s) {
+  check_params(p);
+  validate_hypergraph(C, h, true, s);
+  VMO_REQUIRE(x != nullptr, "x is NULL");
+  int32_t k = h->k, l = h->l;
+  Buf<int32_t> label(C.pool, k);
+  components(C, k, l, h->net_ptr, h->pins, label.p, s);
+  // vertices grouped by component (ascending label, ascending id)
+  Buf<uint32_t> lkey(C.pool, k);
+  Buf<int32_t> vorder(C.pool, k);
+  VMO_HIP(hipMemcpyAsync(lkey.p, label.p, 4 * (size_t)k, hipMemcpyDeviceToDevice, s));
+  iota_i32(vorder.p, k, s);
+  radix_sort<uint32_t>(C, lkey.p, vorder.p, k, bits_for((uint64_t)(k - 1)), s);
+  Buf<int32_t> cflag(C.pool, (size_t)k + 1), cscan(C.pool, (size_t)k + 1);
+  VMO_LAUNCH(k_comp_flag, gsz(k), kLT, 0, s, lkey.p, k, cflag.p);
+  scan_exclusive<int32_t>(C, cflag.p, cscan.p, k, cscan.p + k, s);
+  int32_t ncomp = read1(cscan.p + k, s);
+  Buf<int32_t> comp_of(C.pool, k), cstart(C.pool, (size_t)ncomp + 1), loc(C.pool, k);
+  VMO_LAUNCH(k_comp_index, gsz(k), kLT, 0, s, vorder.p, cscan.p, cflag.p, k, comp_of.p, cstart.p);
+  VMO_LAUNCH(k_local_id, gsz(k), kLT, 0, s, vorder.p, comp_of.p, cstart.p, k, loc.p);
+  std::vector<int32_t> hstart(ncomp + 1), hlabel(ncomp);
+  VMO_HIP(hipMemcpyAsync(hstart.data(), cstart.p, 4 * (size_t)ncomp, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  hstart[ncomp] = k;
+  {
+    std::vector<int32_t> hv(k);
+    VMO_HIP(hipMemcpyAsync(hv.data(), vorder.p, 4 * (size_t)k, hipMemcpyDeviceToHost, s));
+    VMO_HIP(hipStreamSynchronize(s));
+    for (int32_t c = 0; c < ncomp; ++c) hlabel[c] = hv[hstart[c]];  // smallest id of the component
+  }
+  // nets grouped by component, local pins
+  Buf<uint32_t> nkey(C.pool, l > 0 ? l : 1);
+  Buf<int32_t> norder(C.pool, l > 0 ? l : 1);
+  Buf<int64_t> optr(C.pool, (size_t)l + 1);
+  Buf<int32_t> opins;
+  Buf<float> oc(C.pool, l > 0 ? l : 1), ow(C.pool, k);
+  std::vector<int64_t> hnstart(ncomp + 2, 0);
+  if (l > 0) {
+    VMO_LAUNCH(k_net_comp, gsz(l), kLT, 0, s, h->net_ptr, h->pins, l, comp_of.p, ncomp, nkey.p, norder.p);
+    radix_sort<uint32_t>(C, nkey.p, norder.p, l, bits_for((uint64_t)ncomp), s);
+    Buf<int64_t> len(C.pool, (size_t)l + 1);
+    VMO_LAUNCH(k_net_len, gsz(l), kLT, 0, s, h->net_ptr, norder.p, l, len.p);
+    scan_exclusive<int64_t>(C, len.p, optr.p, l, optr.p + l, s);
+    int64_t np = read1(optr.p + l, s);
+    opins = Buf<int32_t>(C.pool, np > 0 ? np : 1);
+    VMO_LAUNCH(k_net_fill, gsz(l), kLT, 0, s, h->net_ptr, h->pins, norder.p, optr.p, loc.p, h->c, l, opins.p, oc.p);
+    std::vector<uint32_t> hk(l);
+    VMO_HIP(hipMemcpyAsync(hk.data(), nkey.p, 4 * (size_t)l, hipMemcpyDeviceToHost, s));
+    VMO_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> cnt(ncomp + 1, 0);
+    for (int32_t e = 0; e < l; ++e) cnt[hk[e]]++;
+    for (int32_t c = 0; c <= ncomp; ++c) hnstart[c + 1] = hnstart[c] + cnt[c];
+  } else {
+    opins = Buf<int32_t>(C.pool, 1);
+    fill_i64(optr.p, 0, 1, s);
+  }
+  VMO_LAUNCH(k_gather_w, gsz(k), kLT, 0, s, vorder.p, h->w, k, ow.p);
+  // per component layout into xl (component-grouped positions)
+  Buf<float> xl(C.pool, 4 * (size_t)k);
+  VMO_HIP(hipMemsetAsync(xl.p, 0, 4 * 4 * (size_t)k, s));
+  for (int32_t c = 0; c < ncomp; ++c) {
+    int32_t kc = hstart[c + 1] - hstart[c];
+    if (kc < 2) continue;
+    int32_t lc = (int32_t)(hnstart[c + 1] - hnstart[c]);
+    std::vector<Level> L;
+    L.push_back(level_from(C, kc, lc, optr.p + hnstart[c], opins.p, ow.p + hstart[c], oc.p + hnstart[c], s));
+    Buf<float> xc(C.pool, 4 * (size_t)kc);
+    layout_component(C, L, p, (uint64_t)hlabel[c], xc.p, s);
+    VMO_LAUNCH(k_put_comp, gsz(kc), kLT, 0, s, xc.p, kc, hstart[c], k, xl.p);
+  }
+  // packing along the first axis, components in label order
+  Buf<int32_t> cpos(C.pool, k);
+  VMO_LAUNCH(k_comp_pos, gsz(k), kLT, 0, s, vorder.p, comp_of.p, k, cpos.p);
+  Buf<uint32_t> boxes(C.pool, 8 * (size_t)ncomp);
+  VMO_LAUNCH(k_boxes_init, gsz(8 * (int64_t)ncomp), kLT, 0, s, boxes.p, 8 * (int64_t)ncomp);
+  VMO_LAUNCH(k_comp_box, gsz(k), kLT, 0, s, xl.p, k, cpos.p, boxes.p);
+  std::vector<uint32_t> hb(8 * (size_t)ncomp);
+  VMO_HIP(hipMemcpyAsync(hb.data(), boxes.p, 4 * hb.size(), hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  std::vector<float> clo(4 * (size_t)ncomp);
+  std::vector<double> cext(ncomp), coff(ncomp);
+  double maxext = 0.0;
+  for (int32_t c = 0; c < ncomp; ++c) {
+    double e = 0.0;
+    for (int d = 0; d < 4; ++d) {
+      float lo = fkey_inv(hb[8 * c + d]), hi = fkey_inv(hb[8 * c + 4 + d]);
+      clo[4 * c + d] = lo;
+      double a = (double)hi - (double)lo;
+      if (a > e) e = a;
+    }
+    cext[c] = e;
+    if (e > maxext) maxext = e;
+  }
+  double gap = (double)p->pack_gap * maxext;
+  double off = 0.0;
+  for (int32_t c = 0; c < ncomp; ++c) {
+    coff[c] = off;
+    off = off + cext[c];
+    off = off + gap;
+  }
+  Buf<float> dlo(C.pool, clo.size());
+  Buf<double> doff(C.pool, coff.size());
+  VMO_HIP(hipMemcpyAsync(dlo.p, clo.data(), 4 * clo.size(), hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(doff.p, coff.data(), 8 * coff.size(), hipMemcpyHostToDevice, s));
+  VMO_LAUNCH(k_pack, gsz(k), kLT, 0, s, xl.p, vorder.p, cpos.p, dlo.p, doff.p, k, x);
+  VMO_HIP(hipStreamSynchronize(s));
+}
+
+void coarsen(Ctx& C, const vmo_hypergraph* h, uint64_t seed, uint64_t comp, int32_t level, int32_t mm, int32_t* pi,
+             int64_t* cptr, int32_t* cpins, float* cw, float* cc, int32_t* kc, int32_t* lc, hipStream_t s) {
+  validate_hypergraph(C, h, false, s);
+  VMO_REQUIRE(pi && cptr && cpins && cw && cc && kc && lc, "NULL output");
+  VMO_REQUIRE(mm >= 2, "match_max_net must be >= 2");
+  Level F = level_from(C, h->k, h->l, h->net_ptr, h->pins, h->w, h->c, s);
+  Level Cl;
+  coarsen_level(C, F, Cl, seed, comp, level, mm, s);
+  VMO_HIP(hipMemcpyAsync(pi, F.pi.p, 4 * (size_t)h->k, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cptr, Cl.ptr.p, 8 * ((size_t)Cl.l + 1), hipMemcpyDeviceToDevice, s));
+  if (Cl.np > 0) VMO_HIP(hipMemcpyAsync(cpins, Cl.pins.p, 4 * (size_t)Cl.np, hipMemcpyDeviceToDevice, s));
+  if (Cl.k > 0) VMO_HIP(hipMemcpyAsync(cw, Cl.w.p, 4 * (size_t)Cl.k, hipMemcpyDeviceToDevice, s));
+  if (Cl.l > 0) VMO_HIP(hipMemcpyAsync(cc, Cl.c.p, 4 * (size_t)Cl.l, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  *kc = Cl.k;
+  *lc = Cl.l;
+}
+
+__global__ void k_tree_out(int32_t n, NodeView nd, int32_t* ints, int32_t* cell2, float* flt) {
+  GRID_STRIDE(t, n) {
+    int4 b = nd.b[t];
+    int4 a = nd.a[t];
+    float4 X = nd.X[t];
+    int32_t* r = ints + 8 * t;
+    r[0] = b.y; r[1] = b.z; r[2] = b.w & 255; r[3] = (b.w >> 8) & 1; r[4] = b.x; r[5] = r[6] = r[7] = 0;
+    cell2[4 * t] = a.x; cell2[4 * t + 1] = a.y; cell2[4 * t + 2] = a.z; cell2[4 * t + 3] = a.w;
+    flt[5 * t] = nd.W[t];
+    flt[5 * t + 1] = X.x; flt[5 * t + 2] = X.y; flt[5 * t + 3] = X.z; flt[5 * t + 4] = X.w;
+  }
+}
+
+void tree(Ctx& C, const float* x, const float* w, int32_t k, int32_t cap, int32_t* ints, int32_t* cell2, float* flt,
+          int32_t* order, int32_t max_nodes, int32_t* n_nodes, hipStream_t s) {
+  VMO_REQUIRE(k >= 1, "k must be >= 1");
+  VMO_REQUIRE(cap >= 1 && cap <= 64, "leaf_cap must be in [1, 64]");
+  VMO_REQUIRE(ints && cell2 && flt && order && n_nodes, "NULL output");
+  validate_finite(C, x, 4 * (int64_t)k, "x", s);
+  Buf<uint32_t> box(C.pool, 8);
+  box_of(x, k, box.p, s);
+  Tree T;
+  build_tree(C, T, x, w, k, cap, box.p, s);
+  VMO_REQUIRE(T.n <= max_nodes, "max_nodes is too small");
+  VMO_LAUNCH(k_tree_out, gsz(T.n), kLT, 0, s, T.n, T.view(), ints, cell2, flt);
+  VMO_HIP(hipMemcpyAsync(order, T.order.p, 4 * (size_t)k, hipMemcpyDeviceToDevice, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  *n_nodes = T.n;
+}
+
+void gradient(Ctx& C, const vmo_hypergraph* h, const float* x, float theta, int32_t cap, float* y, float* z,
+              int64_t* nint, hipStream_t s) {
+  validate_hypergraph(C, h, false, s);
+  VMO_REQUIRE(cap >= 1 && cap <= 64, "leaf_cap must be in [1, 64]");
+  VMO_REQUIRE(y != nullptr, "y is NULL");
+  validate_finite(C, x, 4 * (int64_t)h->k, "x", s);
+  Level L = level_from(C, h->k, h->l, h->net_ptr, h->pins, h->w, h->c, s);
+  GradWork gw;
+  Buf<unsigned long long> cnt(C.pool, 1);
+  VMO_HIP(hipMemsetAsync(cnt.p, 0, 8, s));
+  gradient_level(C, L, x, (double)theta * (double)theta, cap, y, gw, cnt.p, s);
+  if (z && L.l > 0) VMO_HIP(hipMemcpyAsync(z, gw.z.p, 16 * (size_t)L.l, hipMemcpyDeviceToDevice, s));
+  unsigned long long c = read1(cnt.p, s);
+  if (nint) *nint = (int64_t)c;
+}
+
+void layout_steps(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, int32_t it0, int32_t iters,
+                  double* alpha, hipStream_t s) {
+  check_params(p);
+  validate_hypergraph(C, h, false, s);
+  VMO_REQUIRE(x && alpha && it0 >= 0 && iters >= 0, "bad arguments");
+  Level L = level_from(C, h->k, h->l, h->net_ptr, h->pins, h->w, h->c, s);
+  GradWork gw;
+  Buf<float> y(C.pool, 4 * (size_t)h->k);
+  double a = *alpha;
+  for (int32_t t = 0; t < iters; ++t) descent_step(C, L, x, p, it0 + t, &a, y.p, gw, s);
+  VMO_HIP(hipStreamSynchronize(s));
+  *alpha = a;
+}
+
 }  // namespace vmo
