@@ -248,6 +248,27 @@ vmo_status vmo_order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs /* (h
 vmo_status vmo_order_batch_plain(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, int32_t t_max,
                                  vmo_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Live kernel timing for measurement tools.  While enabled, the library
+ * brackets every launch of its main kernels with HIP events recorded on the
+ * launch stream and accumulates, per kernel name, the summed durations, the
+ * launch count and the algorithmic work:
+ *   "walk"   tree walk of the layout; work = charge interactions evaluated
+ *            (counted by the kernel);
+ *   "assign" Lloyd assignment pass; work = bytes of the positions it scans
+ *            (16 B of grid coordinates + 1 B side each).
+ * Enabling adds one atomic per wavefront to the walk.  Disabling clears the
+ * totals.  vmo_profile_read of a name never launched returns zeros.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double total_ms;
+  int64_t launches;
+  double work;
+} vmo_profile_entry;
+vmo_status vmo_profile(vmo_ctx ctx, int enable);
+vmo_status vmo_profile_read(vmo_ctx ctx, const char* kernel, vmo_profile_entry* out /* (host) */);
+vmo_status vmo_profile_reset(vmo_ctx ctx);
+
 #ifdef __cplusplus
 }
 #endif

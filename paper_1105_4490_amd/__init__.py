@@ -51,6 +51,10 @@ class Job(C.Structure):
                 ("seed", C.c_uint64), ("job_index", C.c_uint64), ("out", OrderOut)]
 
 
+class ProfileEntry(C.Structure):
+    _fields_ = [("total_ms", C.c_double), ("launches", C.c_int64), ("work", C.c_double)]
+
+
 class CutResult(C.Structure):
     _fields_ = [("lambda_minus_one", C.c_double), ("cut_net", C.c_double), ("nets_cut", C.c_int64)]
 
@@ -145,6 +149,18 @@ class Context:
 
     def pool_bytes(self) -> int:
         return int(lib().vmo_pool_bytes(self.h))
+
+    def profile(self, enable: bool):
+        """Live kernel timing with HIP events on the launch stream."""
+        self._check(lib().vmo_profile(self.h, C.c_int(1 if enable else 0)))
+
+    def profile_reset(self):
+        self._check(lib().vmo_profile_reset(self.h))
+
+    def profile_read(self, kernel: str):
+        e = ProfileEntry()
+        self._check(lib().vmo_profile_read(self.h, kernel.encode(), C.byref(e)))
+        return {"total_ms": e.total_ms, "launches": e.launches, "work": e.work}
 
     # --------------------------------------------------------------- models --
     def model(self, kind: int, m: int, n: int, rowptr: torch.Tensor, col: torch.Tensor) -> DeviceHypergraph:

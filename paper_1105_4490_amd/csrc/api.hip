@@ -32,17 +32,20 @@ void layout_steps(Ctx& c, const vmo_hypergraph* h, const vmo_layout_params* p, f
     VMO_HIP(hipSetDevice(C.device));
 
 #define API_END                                                   \
+    vmo::prof_flush(C);                                           \
   }                                                               \
   catch (vmo::Error & e) {                                        \
     C.err = e.what();                                             \
     (void)hipStreamSynchronize(S);                                \
     (void)hipGetLastError();                                      \
+    vmo::prof_discard(C);                                         \
     return e.status;                                              \
   }                                                               \
   catch (std::exception & e) {                                    \
     C.err = e.what();                                             \
     (void)hipStreamSynchronize(S);                                \
     (void)hipGetLastError();                                      \
+    vmo::prof_discard(C);                                         \
     return VMO_E_DEVICE;                                          \
   }                                                               \
   return VMO_OK;
@@ -285,6 +288,37 @@ vmo_status vmo_layout_steps(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layo
   API_BEGIN(ctx, stream)
   vmo::layout_steps(C, h, p, x, it0, iters, alpha, S);
   API_END
+}
+
+vmo_status vmo_profile(vmo_ctx ctx, int enable) {
+  if (!ctx) return VMO_E_INVALID;
+  ctx->prof.on = enable != 0;
+  if (!enable) {
+    vmo::prof_discard(*ctx);
+    ctx->prof.acc.clear();
+  }
+  return VMO_OK;
+}
+
+vmo_status vmo_profile_read(vmo_ctx ctx, const char* kernel, vmo_profile_entry* out) {
+  if (!ctx || !kernel || !out) return VMO_E_INVALID;
+  auto it = ctx->prof.acc.find(kernel);
+  if (it == ctx->prof.acc.end()) {
+    out->total_ms = 0.0;
+    out->launches = 0;
+    out->work = 0.0;
+    return VMO_OK;
+  }
+  out->total_ms = it->second.ms;
+  out->launches = it->second.launches;
+  out->work = it->second.work;
+  return VMO_OK;
+}
+
+vmo_status vmo_profile_reset(vmo_ctx ctx) {
+  if (!ctx) return VMO_E_INVALID;
+  ctx->prof.acc.clear();
+  return VMO_OK;
 }
 
 }  // extern "C"

@@ -37,25 +37,32 @@ static void make_dual(Ctx& C, Level& L, hipStream_t s) {
 }
 
 // ============================================================ bounding box ==
-__global__ void k_box(const float* x, int32_t k, uint32_t* box) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kLT) void k_box(const float* x, int32_t k, uint32_t* box) {
+  __shared__ uint32_t sm[kLT / 64][8];
   uint32_t mn[4], mx[4];
-  for (int d = 0; d < 4; ++d) {
-    uint32_t f = v < k ? fkey(x[(int64_t)d * k + v]) : 0xffffffffu;
-    mn[d] = f;
-    mx[d] = v < k ? f : 0u;
-  }
+  for (int d = 0; d < 4; ++d) { mn[d] = 0xffffffffu; mx[d] = 0u; }
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x)
+    for (int d = 0; d < 4; ++d) {
+      uint32_t f = fkey(x[(int64_t)d * k + v]);
+      mn[d] = f < mn[d] ? f : mn[d];
+      mx[d] = f > mx[d] ? f : mx[d];
+    }
   for (int off = 32; off > 0; off >>= 1)
     for (int d = 0; d < 4; ++d) {
       uint32_t a = __shfl_xor(mn[d], off, 64), b = __shfl_xor(mx[d], off, 64);
       mn[d] = a < mn[d] ? a : mn[d];
       mx[d] = b > mx[d] ? b : mx[d];
     }
+  int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
-    for (int d = 0; d < 4; ++d) {
-      atomicMin(&box[d], mn[d]);
-      atomicMax(&box[4 + d], mx[d]);
-    }
+    for (int d = 0; d < 4; ++d) { sm[w][d] = mn[d]; sm[w][4 + d] = mx[d]; }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    int f = threadIdx.x;
+    uint32_t r = sm[0][f];
+    for (int i = 1; i < kLT / 64; ++i) r = f < 4 ? (sm[i][f] < r ? sm[i][f] : r) : (sm[i][f] > r ? sm[i][f] : r);
+    if (f < 4) atomicMin(&box[f], r); else atomicMax(&box[f], r);
+  }
 }
 __global__ void k_box_init(uint32_t* box) {
   int t = threadIdx.x;
@@ -77,7 +84,8 @@ struct HostBox {
 
 static void box_of(const float* x, int32_t k, uint32_t* dbox, hipStream_t s) {
   VMO_LAUNCH(k_box_init, 1, 64, 0, s, dbox);
-  VMO_LAUNCH(k_box, nblocks(k, kLT), kLT, 0, s, x, k, dbox);
+  int64_t nb = nblocks(k, kLT);
+  VMO_LAUNCH(k_box, (unsigned)(nb < 1024 ? nb : 1024), kLT, 0, s, x, k, dbox);
 }
 static HostBox read_box(const uint32_t* dbox, hipStream_t s) {
   uint32_t b[8];
@@ -126,15 +134,18 @@ __global__ void k_tree_keys(const float* x, int32_t k, const uint32_t* box, uint
 
 // Points in tree order: coordinates, weights and 2 kq + 1 (doubled grid units).
 __global__ void k_tree_points(const float* x, const float* w, int32_t k, const uint32_t* box, const int32_t* order,
-                              float* xs, float* ws, int32_t* p2) {
+                              float* xs, float* ws, int32_t* p2, float4* P) {
   GRID_STRIDE(j, k) {
     int32_t v = order[j];
     uint32_t kq[4];
     grid_coords(x, k, v, box, kq);
+    float c[4];
     for (int d = 0; d < 4; ++d) {
-      xs[(int64_t)d * k + j] = x[(int64_t)d * k + v];
+      c[d] = x[(int64_t)d * k + v];
+      xs[(int64_t)d * k + j] = c[d];
       p2[(int64_t)d * k + j] = 2 * (int32_t)kq[d] + 1;
     }
+    P[j] = make_float4(c[0], c[1], c[2], c[3]);
     ws[j] = w ? w[v] : 1.0f;
   }
 }
@@ -206,11 +217,17 @@ __global__ void k_tree_ell(const int8_t* cpl, int32_t k, int32_t cap, int8_t* el
   }
 }
 
+// One tree node as the walk reads it (64 bytes).
+struct alignas(16) TNode {
+  int4 a;    // cell centre x 2 (grid units)
+  int4 b;    // next, first, count, depth | leaf << 8
+  float4 X;  // charge centre
+  float W;   // charge
+  float pad[3];
+};
+
 struct NodeView {
-  int4* a;    // cell centre x 2 (grid units)
-  int4* b;    // next, first, count, depth | leaf << 8
-  float4* X;  // charge centre
-  float* W;   // charge
+  TNode* t;
   double* Wd;
   double* Sd;  // [n][4]
   int32_t* parent;
@@ -237,8 +254,8 @@ __global__ void k_tree_nodes(const int8_t* cpl, const int8_t* bmin, const int8_t
       cc.y = 2 * ((kq1 >> (16 - L)) << (16 - L)) + side;
       cc.z = 2 * ((kq2 >> (16 - L)) << (16 - L)) + side;
       cc.w = 2 * ((kq3 >> (16 - L)) << (16 - L)) + side;
-      nd.a[t] = cc;
-      nd.b[t] = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
+      nd.t[t].a = cc;
+      nd.t[t].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
       nd.parent[t] = -1;
       nd.ctr[t] = 0;
     }
@@ -248,14 +265,14 @@ __global__ void k_tree_nodes(const int8_t* cpl, const int8_t* bmin, const int8_t
 __global__ void k_tree_links(int32_t n, NodeView nd) {
   GRID_STRIDE(t64, n) {
     int32_t t = (int32_t)t64;
-    int4 b = nd.b[t];
+    int4 b = nd.t[t].b;
     int cnt = 0;
     if (!((b.w >> 8) & 1)) {
       int32_t ch = t + 1;
       while (ch != b.x) {
         nd.parent[ch] = t;
         ++cnt;
-        ch = nd.b[ch].x;
+        ch = nd.t[ch].b.x;
       }
     }
     nd.nch[t] = cnt;
@@ -265,8 +282,8 @@ __global__ void k_tree_links(int32_t n, NodeView nd) {
 __device__ __forceinline__ void node_finish(NodeView nd, int32_t t, double Wd, const double* Sd) {
   nd.Wd[t] = Wd;
   for (int d = 0; d < 4; ++d) nd.Sd[4 * (int64_t)t + d] = Sd[d];
-  nd.W[t] = (float)Wd;
-  nd.X[t] = make_float4((float)(Sd[0] / Wd), (float)(Sd[1] / Wd), (float)(Sd[2] / Wd), (float)(Sd[3] / Wd));
+  nd.t[t].W = (float)Wd;
+  nd.t[t].X = make_float4((float)(Sd[0] / Wd), (float)(Sd[1] / Wd), (float)(Sd[2] / Wd), (float)(Sd[3] / Wd));
 }
 
 // Charges bottom-up: a leaf sums its points in tree order (FP64); the last
@@ -274,7 +291,7 @@ __device__ __forceinline__ void node_finish(NodeView nd, int32_t t, double Wd, c
 __global__ void k_tree_moments(int32_t n, int32_t k, const float* xs, const float* ws, NodeView nd) {
   GRID_STRIDE(t64, n) {
     int32_t t = (int32_t)t64;
-    int4 b = nd.b[t];
+    int4 b = nd.t[t].b;
     if (!((b.w >> 8) & 1)) continue;
     double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
     for (int32_t j = b.y; j < b.y + b.z; ++j) {
@@ -292,8 +309,8 @@ __global__ void k_tree_moments(int32_t n, int32_t k, const float* xs, const floa
       if (old != nd.nch[p] - 1) break;
       __threadfence();
       double W2 = 0.0, S2[4] = {0.0, 0.0, 0.0, 0.0};
-      int32_t nx = nd.b[p].x;
-      for (int32_t ch = p + 1; ch != nx; ch = nd.b[ch].x) {
+      int32_t nx = nd.t[p].b.x;
+      for (int32_t ch = p + 1; ch != nx; ch = nd.t[ch].b.x) {
         W2 += __hip_atomic_load(&nd.Wd[ch], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int d = 0; d < 4; ++d)
           S2[d] += __hip_atomic_load(&nd.Sd[4 * (int64_t)ch + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -310,14 +327,13 @@ struct Tree {
   Buf<int32_t> order, p2, nn;
   Buf<float> xs, ws;
   Buf<int8_t> cpl, bmin, ell;
-  Buf<int4> a, b;
-  Buf<float4> X;
-  Buf<float> W;
+  Buf<TNode> nodes;
+  Buf<float4> P;  // points in tree order
   Buf<double> Wd, Sd;
   Buf<int32_t> parent, nch, ctr;
   NodeView view() {
     NodeView v;
-    v.a = a.p; v.b = b.p; v.X = X.p; v.W = W.p; v.Wd = Wd.p; v.Sd = Sd.p;
+    v.t = nodes.p; v.Wd = Wd.p; v.Sd = Sd.p;
     v.parent = parent.p; v.nch = nch.p; v.ctr = ctr.p;
     return v;
   }
@@ -334,7 +350,8 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
   T.xs = Buf<float>(C.pool, 4 * (size_t)k);
   T.ws = Buf<float>(C.pool, k);
   T.p2 = Buf<int32_t>(C.pool, 4 * (size_t)k);
-  VMO_LAUNCH(k_tree_points, gsz(k), kLT, 0, s, x, w, k, dbox, T.order.p, T.xs.p, T.ws.p, T.p2.p);
+  T.P = Buf<float4>(C.pool, k);
+  VMO_LAUNCH(k_tree_points, gsz(k), kLT, 0, s, x, w, k, dbox, T.order.p, T.xs.p, T.ws.p, T.p2.p, T.P.p);
   int32_t nb = k / kCplB + 1;
   T.cpl = Buf<int8_t>(C.pool, (size_t)nb * kCplB);
   T.bmin = Buf<int8_t>(C.pool, nb);
@@ -345,10 +362,7 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
   scan_exclusive<int32_t>(C, T.nn.p, T.nn.p, (int64_t)k + 1, nullptr, s);
   int32_t n = read1(T.nn.p + k, s);
   T.n = n;
-  T.a = Buf<int4>(C.pool, n);
-  T.b = Buf<int4>(C.pool, n);
-  T.X = Buf<float4>(C.pool, n);
-  T.W = Buf<float>(C.pool, n);
+  T.nodes = Buf<TNode>(C.pool, n);
   T.Wd = Buf<double>(C.pool, n);
   T.Sd = Buf<double>(C.pool, 4 * (size_t)n);
   T.parent = Buf<int32_t>(C.pool, n);
@@ -361,15 +375,24 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
 }
 
 // ============================================================ gradient ====
-// Net centres: pins summed in CSR order, divided by the net size.
+// Net centres: pins summed in CSR order (each coordinate on its own), then
+// divided by the net size.
 __global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, const float* x, int32_t k, float* z) {
   GRID_STRIDE(e, l) {
     int64_t b = ptr[e], n = ptr[e + 1] - b;
-    for (int d = 0; d < 4; ++d) {
-      float a = 0.0f;
-      for (int64_t p = b; p < b + n; ++p) a = a + x[(int64_t)d * k + pins[p]];
-      z[(int64_t)d * l + e] = n > 0 ? a / (float)n : 0.0f;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    for (int64_t p = b; p < b + n; ++p) {
+      int32_t v = pins[p];
+      a0 = a0 + x[v];
+      a1 = a1 + x[(int64_t)k + v];
+      a2 = a2 + x[2 * (int64_t)k + v];
+      a3 = a3 + x[3 * (int64_t)k + v];
     }
+    float fn = (float)n;
+    z[e] = n > 0 ? a0 / fn : 0.0f;
+    z[(int64_t)l + e] = n > 0 ? a1 / fn : 0.0f;
+    z[2 * (int64_t)l + e] = n > 0 ? a2 / fn : 0.0f;
+    z[3 * (int64_t)l + e] = n > 0 ? a3 / fn : 0.0f;
   }
 }
 // Attraction of eq. (7): sum over the vertex's nets in ascending net order.
@@ -377,17 +400,21 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
                           const float* z, int32_t l, float* y) {
   GRID_STRIDE(v, k) {
     int64_t b = dptr[v], e = dptr[v + 1];
-    for (int d = 0; d < 4; ++d) {
-      float a = 0.0f;
-      float xv = x[(int64_t)d * k + v];
-      for (int64_t t = b; t < e; ++t) {
-        int32_t n = dpins[t];
-        float ce = c ? c[n] : 1.0f;
-        float df = xv - z[(int64_t)d * l + n];
-        a = a + ce * df;
-      }
-      y[(int64_t)d * k + v] = a;
+    float x0 = x[v], x1 = x[(int64_t)k + v], x2 = x[2 * (int64_t)k + v], x3 = x[3 * (int64_t)k + v];
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    for (int64_t t = b; t < e; ++t) {
+      int32_t n = dpins[t];
+      float ce = c ? c[n] : 1.0f;
+      float d0 = x0 - z[n], d1 = x1 - z[(int64_t)l + n], d2 = x2 - z[2 * (int64_t)l + n], d3 = x3 - z[3 * (int64_t)l + n];
+      a0 = a0 + ce * d0;
+      a1 = a1 + ce * d1;
+      a2 = a2 + ce * d2;
+      a3 = a3 + ce * d3;
     }
+    y[v] = a0;
+    y[(int64_t)k + v] = a1;
+    y[2 * (int64_t)k + v] = a2;
+    y[3 * (int64_t)k + v] = a3;
   }
 }
 
@@ -410,55 +437,150 @@ __device__ __forceinline__ void interact(float* y, const float* xn, float wn, fl
   y[3] = y[3] + f * dx3;
 }
 
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 // Repulsion by the stackless walk of Algorithm 3: a far node acts as one charge
 // and the walk jumps to its sibling link; a near internal node is entered; a
-// near leaf acts point by point.  One thread per point, points in tree order.
-__global__ __launch_bounds__(kLT) void k_walk(int32_t k, int32_t n, const int32_t* order, const float* xs,
-                                              const float* ws, const int32_t* p2, const int4* na, const int4* nb,
-                                              const float4* nX, const float* nW, double th2, float* y,
-                                              unsigned long long* nint) {
+// near leaf acts point by point.  One lane per point, points in tree order.
+//
+// The 64 lanes of a wavefront step through the nodes in pre-order together:
+// node t is read once for the wave, and a lane takes part only if its own
+// walk reaches t (t >= its skip mark).  Every jump of a single walk moves
+// forward in pre-order, so each lane performs exactly the interactions of its
+// own walk, in the same order.  The wave moves to t + 1 while some lane is
+// still descending, else to the smallest skip mark.  Nodes are staged through
+// a per-wavefront LDS window of 64 consecutive nodes (one 64-byte node per
+// lane per refill).
+constexpr int kWin = 64;
+// Far-field thresholds per depth: the node at depth L is far iff D2 >= T[L],
+// D2 = squared distance point-to-cell-centre in doubled grid units (an exact
+// integer below 2^40, so exact in FP64).  T[L] is the smallest integer D2
+// for which s^2 < theta^2 D2 holds in FP64 (s = doubled cell side); the
+// predicate is monotone in D2, so both forms decide every node alike.
+struct FarTable {
+  double T[17];
+};
+static FarTable far_table(double th2) {
+  FarTable f;
+  for (int L = 0; L <= 16; ++L) {
+    int64_t s2 = (int64_t)2 << (16 - L);
+    double lhs = (double)(s2 * s2);
+    if (!(th2 > 0.0)) { f.T[L] = 1e300; continue; }
+    int64_t lo = 0, hi = (int64_t)1 << 42;  // hi always satisfies the predicate
+    while (lo < hi) {
+      int64_t mid = lo + (hi - lo) / 2;
+      if (lhs < th2 * (double)mid) hi = mid; else lo = mid + 1;
+    }
+    f.T[L] = (double)lo;
+  }
+  return f;
+}
+
+constexpr int kWT = 256;    // threads per block of the walk
+__global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_t* __restrict__ order,
+                                              const float4* __restrict__ P, const float* __restrict__ ws,
+                                              const int32_t* __restrict__ p2, const TNode* __restrict__ nodes,
+                                              FarTable ft, float* __restrict__ y, unsigned long long* nint) {
+  constexpr int NW = kWT / 64;
+  __shared__ int4 win[NW][kWin][4];
+  __shared__ float4 lp[NW][64];
+  __shared__ float lw[NW][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = j < k;
   unsigned long long cnt = 0;
-  if (j < k) {
-    int32_t v = order[j];
-    float xn[4], yn[4];
-    int32_t q[4];
+  float xn[4] = {0.f, 0.f, 0.f, 0.f}, yn[4] = {0.f, 0.f, 0.f, 0.f};
+  int32_t q[4] = {0, 0, 0, 0};
+  float wn = 0.0f;
+  int32_t v = 0;
+  if (valid) {
+    v = order[j];
+    float4 pj = P[j];
+    xn[0] = pj.x; xn[1] = pj.y; xn[2] = pj.z; xn[3] = pj.w;
     for (int d = 0; d < 4; ++d) {
-      xn[d] = xs[(int64_t)d * k + j];
       q[d] = p2[(int64_t)d * k + j];
       yn[d] = y[(int64_t)d * k + v];
     }
-    float wn = ws[j];
-    int32_t t = 0;
-    while (t < n) {
-      int4 a = na[t];
-      int4 b = nb[t];
-      int depth = b.w & 255;
-      bool far = false;
-      if (th2 > 0.0) {
-        int64_t d0 = q[0] - a.x, d1 = q[1] - a.y, d2 = q[2] - a.z, d3 = q[3] - a.w;
-        int64_t D2 = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
-        int64_t s2 = (int64_t)2 << (16 - depth);
-        far = (double)(s2 * s2) < th2 * (double)D2;
-      }
-      if (far) {
-        float4 X = nX[t];
-        interact(yn, xn, wn, X.x, X.y, X.z, X.w, nW[t]);
-        ++cnt;
-        t = b.x;
-      } else if (!((b.w >> 8) & 1)) {
-        t = t + 1;
-      } else {
-        for (int32_t i = b.y; i < b.y + b.z; ++i) {
-          if (i == j) continue;
-          interact(yn, xn, wn, xs[i], xs[(int64_t)k + i], xs[2 * (int64_t)k + i], xs[3 * (int64_t)k + i], ws[i]);
-          ++cnt;
-        }
-        t = b.x;
-      }
-    }
-    for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yn[d];
+    wn = ws[j];
   }
+  auto wave_sync = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  int32_t skip = valid ? 0 : 0x7fffffff;
+  int32_t t = __builtin_amdgcn_readfirstlane(wave_min(skip));
+  int32_t wb = -2 * kWin;
+  while (t < n) {
+    if (t < wb || t >= wb + kWin) {
+      wb = t;
+      int32_t tt = t + lane;
+      if (tt < n) {
+        const int4* src = reinterpret_cast<const int4*>(nodes + tt);
+        win[wv][lane][0] = src[0];
+        win[wv][lane][1] = src[1];
+        win[wv][lane][2] = src[2];
+        win[wv][lane][3] = src[3];
+      }
+      wave_sync();
+    }
+    const int o = t - wb;
+    int4 a = win[wv][o][0];
+    int4 b = win[wv][o][1];
+    bool act = skip <= t;
+    bool far = false;
+    if (act) {
+      double d0 = (double)(q[0] - a.x), d1 = (double)(q[1] - a.y), d2 = (double)(q[2] - a.z), d3 = (double)(q[3] - a.w);
+      double D2 = d0 * d0;
+      D2 = D2 + d1 * d1;
+      D2 = D2 + d2 * d2;
+      D2 = D2 + d3 * d3;
+      far = D2 >= ft.T[b.w & 255];
+    }
+    if (far) {
+      int4 xi = win[wv][o][2];
+      int4 wi = win[wv][o][3];
+      interact(yn, xn, wn, __int_as_float(xi.x), __int_as_float(xi.y), __int_as_float(xi.z), __int_as_float(xi.w),
+               __int_as_float(wi.x));
+      ++cnt;
+      skip = b.x;
+    }
+    bool near = act && !far;
+    if ((b.w >> 8) & 1) {
+      if (__any(near)) {
+        int32_t f0 = b.y, f1 = b.y + b.z;
+        for (int32_t base = f0; base < f1; base += 64) {
+          int32_t ii = base + lane;
+          if (ii < f1) {
+            lp[wv][lane] = P[ii];
+            lw[wv][lane] = ws[ii];
+          }
+          wave_sync();
+          int32_t m = f1 - base < 64 ? f1 - base : 64;
+          if (near) {
+            for (int32_t i = 0; i < m; ++i) {
+              if (base + i == (int32_t)j) continue;
+              float4 pi = lp[wv][i];
+              interact(yn, xn, wn, pi.x, pi.y, pi.z, pi.w, lw[wv][i]);
+              ++cnt;
+            }
+          }
+          wave_sync();
+        }
+      }
+      if (near) skip = b.x;
+    } else if (near) {
+      skip = t + 1;
+    }
+    int32_t nt = t + 1;
+    if (!__any(skip <= nt)) nt = wave_min(skip);
+    t = __builtin_amdgcn_readfirstlane(nt);
+  }
+  if (valid)
+    for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yn[d];
   if (nint) {
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nint, cnt);
@@ -498,8 +620,11 @@ static void gradient_level(Ctx& C, const Level& L, const float* x, double th2, i
   if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, L.k, gw.z.p);
   VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, L.l, y);
   build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, s);
-  VMO_LAUNCH(k_walk, nblocks(L.k, kLT), kLT, 0, s, L.k, gw.T.n, gw.T.order.p, gw.T.xs.p, gw.T.ws.p, gw.T.p2.p, gw.T.a.p,
-             gw.T.b.p, gw.T.X.p, gw.T.W.p, th2, y, nint);
+  unsigned long long* pc = nullptr;
+  int ph = prof_begin(C, "walk", 0.0, s, nint ? nullptr : &pc);
+  VMO_LAUNCH(k_walk, nblocks(L.k, kWT), kWT, 0, s, L.k, gw.T.n, gw.T.order.p, gw.T.P.p, gw.T.ws.p, gw.T.p2.p,
+             gw.T.nodes.p, far_table(th2), y, nint ? nint : pc);
+  prof_end(C, ph, s);
 }
 
 // One descent step (Algorithm 3).  alpha: step length (host); at it == 0 it
@@ -920,14 +1045,31 @@ __global__ void k_sub_ptr(const int64_t* in, int64_t n, int64_t sub, int64_t* ou
   GRID_STRIDE(i, n) out[i] = in[i] - sub;
 }
 __global__ void k_comp_box(const float* xl, int32_t k, const int32_t* comp_of_pos, uint32_t* boxes) {
-  GRID_STRIDE(i, k) {
-    int32_t c = comp_of_pos[i];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = -1;
+  uint32_t mn[4], mx[4];
+  for (int d = 0; d < 4; ++d) { mn[d] = 0xffffffffu; mx[d] = 0u; }
+  if (i < k) {
+    key = comp_of_pos[i];
+    for (int d = 0; d < 4; ++d) mn[d] = mx[d] = fkey(xl[(int64_t)d * k + i]);
+  }
+  int lane = threadIdx.x & 63;
+  for (int off = 1; off < 64; off <<= 1) {
+    int ok = __shfl_down(key, off, 64);
     for (int d = 0; d < 4; ++d) {
-      uint32_t f = fkey(xl[(int64_t)d * k + i]);
-      atomicMin(&boxes[8 * (int64_t)c + d], f);
-      atomicMax(&boxes[8 * (int64_t)c + 4 + d], f);
+      uint32_t a = __shfl_down(mn[d], off, 64), b = __shfl_down(mx[d], off, 64);
+      if (lane + off < 64 && ok == key) {
+        mn[d] = a < mn[d] ? a : mn[d];
+        mx[d] = b > mx[d] ? b : mx[d];
+      }
     }
   }
+  int prev = __shfl_up(key, 1, 64);
+  if (key >= 0 && (lane == 0 || prev != key))
+    for (int d = 0; d < 4; ++d) {
+      atomicMin(&boxes[8 * (int64_t)key + d], mn[d]);
+      atomicMax(&boxes[8 * (int64_t)key + 4 + d], mx[d]);
+    }
 }
 __global__ void k_comp_pos(const int32_t* vorder, const int32_t* comp_of, int32_t k, int32_t* cpos) {
   GRID_STRIDE(i, k) cpos[i] = comp_of[vorder[i]];
@@ -1061,7 +1203,7 @@ void layout(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, float* 
   VMO_LAUNCH(k_comp_pos, gsz(k), kLT, 0, s, vorder.p, comp_of.p, k, cpos.p);
   Buf<uint32_t> boxes(C.pool, 8 * (size_t)ncomp);
   VMO_LAUNCH(k_boxes_init, gsz(8 * (int64_t)ncomp), kLT, 0, s, boxes.p, 8 * (int64_t)ncomp);
-  VMO_LAUNCH(k_comp_box, gsz(k), kLT, 0, s, xl.p, k, cpos.p, boxes.p);
+  VMO_LAUNCH(k_comp_box, nblocks(k, kLT), kLT, 0, s, xl.p, k, cpos.p, boxes.p);
   std::vector<uint32_t> hb(8 * (size_t)ncomp);
   VMO_HIP(hipMemcpyAsync(hb.data(), boxes.p, 4 * hb.size(), hipMemcpyDeviceToHost, s));
   VMO_HIP(hipStreamSynchronize(s));
@@ -1114,13 +1256,13 @@ void coarsen(Ctx& C, const vmo_hypergraph* h, uint64_t seed, uint64_t comp, int3
 
 __global__ void k_tree_out(int32_t n, NodeView nd, int32_t* ints, int32_t* cell2, float* flt) {
   GRID_STRIDE(t, n) {
-    int4 b = nd.b[t];
-    int4 a = nd.a[t];
-    float4 X = nd.X[t];
+    int4 b = nd.t[t].b;
+    int4 a = nd.t[t].a;
+    float4 X = nd.t[t].X;
     int32_t* r = ints + 8 * t;
     r[0] = b.y; r[1] = b.z; r[2] = b.w & 255; r[3] = (b.w >> 8) & 1; r[4] = b.x; r[5] = r[6] = r[7] = 0;
     cell2[4 * t] = a.x; cell2[4 * t + 1] = a.y; cell2[4 * t + 2] = a.z; cell2[4 * t + 3] = a.w;
-    flt[5 * t] = nd.W[t];
+    flt[5 * t] = nd.t[t].W;
     flt[5 * t + 1] = X.x; flt[5 * t + 2] = X.y; flt[5 * t + 3] = X.z; flt[5 * t + 4] = X.w;
   }
 }

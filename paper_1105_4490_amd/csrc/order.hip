@@ -828,7 +828,9 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
   VMO_LAUNCH(k_seed2, nblocks(Sn, kT), kT, 0, s, dj.p, sg, s0, Sn, dd.p, q.p, Np);
   Buf<int32_t> active(c.pool, 1);
   for (int it = 0; it <= t_max; ++it) {
+    int ph = prof_begin(c, "assign", 17.0 * (double)np, s, nullptr);
     VMO_LAUNCH(k_assign, nblocks(np, kT), kT, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p);
+    prof_end(c, ph, s);
     VMO_HIP(hipMemsetAsync(active.p, 0, 4, s));
     VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p);
     if (read1(active.p, s) == 0) break;

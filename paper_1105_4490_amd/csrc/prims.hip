@@ -55,6 +55,73 @@ Pool::~Pool() {
   for (auto& kv : size_) (void)hipFree(kv.first);
 }
 
+// --------------------------------------------------------------- profile ----
+Ctx::~Ctx() {
+  prof_discard(*this);
+  if (prof.dcnt) (void)hipFree(prof.dcnt);
+}
+
+int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned long long** dwork) {
+  if (dwork) *dwork = nullptr;
+  if (!c.prof.on) return -1;
+  ProfPending p;
+  p.name = name;
+  p.work = work;
+  p.dslot = -1;
+  if (dwork) {
+    if (c.prof.nslot == c.prof.cap) {
+      VMO_HIP(hipStreamSynchronize(s));
+      prof_flush(c);
+      if (c.prof.cap == 0) {
+        c.prof.cap = 4096;
+        VMO_HIP(hipMalloc(&c.prof.dcnt, sizeof(unsigned long long) * c.prof.cap));
+      }
+    }
+    p.dslot = c.prof.nslot++;
+    *dwork = c.prof.dcnt + p.dslot;
+    VMO_HIP(hipMemsetAsync(*dwork, 0, sizeof(unsigned long long), s));
+  }
+  VMO_HIP(hipEventCreate(&p.a));
+  VMO_HIP(hipEventCreate(&p.b));
+  VMO_HIP(hipEventRecord(p.a, s));
+  c.prof.pend.push_back(p);
+  return (int)c.prof.pend.size() - 1;
+}
+
+void prof_end(Ctx& c, int h, hipStream_t s) {
+  if (h < 0) return;
+  VMO_HIP(hipEventRecord(c.prof.pend[h].b, s));
+}
+
+void prof_flush(Ctx& c) {
+  if (c.prof.pend.empty()) return;
+  std::vector<unsigned long long> cnt(c.prof.nslot);
+  if (c.prof.nslot > 0)
+    VMO_HIP(hipMemcpy(cnt.data(), c.prof.dcnt, sizeof(unsigned long long) * c.prof.nslot, hipMemcpyDeviceToHost));
+  for (auto& p : c.prof.pend) {
+    float ms = 0.0f;
+    VMO_HIP(hipEventSynchronize(p.b));
+    VMO_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    ProfAcc& a = c.prof.acc[p.name];
+    a.ms += ms;
+    a.launches += 1;
+    a.work += p.dslot >= 0 ? (double)cnt[p.dslot] : p.work;
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  c.prof.pend.clear();
+  c.prof.nslot = 0;
+}
+
+void prof_discard(Ctx& c) {
+  for (auto& p : c.prof.pend) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  c.prof.pend.clear();
+  c.prof.nslot = 0;
+}
+
 // ------------------------------------------------------------------ scan ----
 constexpr int kScanT = 256, kScanI = 8, kScanTile = kScanT * kScanI;
 

@@ -81,11 +81,43 @@ struct Buf {
   T* operator()() const { return p; }
 };
 
+// Live kernel timing: when on, selected launches are bracketed with HIP events
+// on their stream; durations and algorithmic work (bytes or interactions,
+// host-known or counted on the device) accumulate per kernel name.
+struct ProfAcc {
+  double ms = 0.0;
+  int64_t launches = 0;
+  double work = 0.0;
+};
+struct ProfPending {
+  std::string name;
+  hipEvent_t a, b;
+  double work;
+  int dslot;  // device counter slot, -1 if none
+};
+struct Prof {
+  bool on = false;
+  std::map<std::string, ProfAcc> acc;
+  std::vector<ProfPending> pend;
+  unsigned long long* dcnt = nullptr;
+  int nslot = 0, cap = 0;
+};
+
 struct Ctx {
   int device = 0;
   std::string err;
   Pool pool;
+  Prof prof;
+  ~Ctx();
 };
+
+// Returns a handle for prof_end (-1 when profiling is off).  If dwork is not
+// NULL it receives a zeroed device counter the kernel adds its work to.
+int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned long long** dwork);
+void prof_end(Ctx& c, int h, hipStream_t s);
+// Collect finished events (call after the stream is synchronised).
+void prof_flush(Ctx& c);
+void prof_discard(Ctx& c);
 
 // Device scalar readback (synchronises `s`).
 template <class T>
