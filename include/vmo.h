@@ -249,6 +249,52 @@ vmo_status vmo_order_batch_plain(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs
                                  vmo_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Serving: continuous batching of ordering jobs on one GPU.  A server owns a
+ * worker thread, its own HIP stream and fixed device arenas sized from
+ * budget_bytes (vertices, tree nodes, edges, nets, pins).  Jobs are admitted
+ * in arrival order when a slot and contiguous arena ranges are free, which
+ * bounds the device memory the server holds; their state then stays resident
+ * on the device.  Every tick runs one recursion level for the segments of all
+ * resident jobs in the same launches; a job submitted while others run joins
+ * at the next tick, and a finished job is written to its output buffers and
+ * leaves, freeing its ranges.  A job's result does not depend on the other
+ * jobs in the mix (its random draws are keyed by seed and job_index).
+ * Jobs with x == NULL are laid out (vmo_layout with *lp) when admitted.
+ * The caller keeps every buffer of a job valid and unchanged until the job is
+ * done.  Submit, poll and wait may be called from any host thread.
+ * ------------------------------------------------------------------------- */
+typedef struct vmo_server_s* vmo_server;
+typedef struct {
+  int device;
+  size_t budget_bytes; /* device memory of the arenas                        */
+  int32_t max_jobs;    /* resident jobs at most                              */
+  int32_t t_max;       /* Lloyd updates per split                            */
+} vmo_serve_params;
+typedef struct {
+  int64_t submitted, completed, ticks, resident, pending;
+  double busy_ms;      /* worker time spent in admission, ticks and emission */
+  int64_t capacity_vertices, capacity_pins, capacity_edges;
+} vmo_serve_stats;
+void vmo_serve_defaults(vmo_serve_params* p /* (host) */);
+vmo_status vmo_serve_create(vmo_server* out /* (host) */, const vmo_serve_params* p /* (host) */);
+/* Non-blocking.  VMO_E_UNSUPPORTED if the job can never fit the arenas. */
+vmo_status vmo_serve_submit(vmo_server s, const vmo_job* job /* (host) */, const vmo_layout_params* lp /* (host) */,
+                            uint64_t* ticket /* (host) */);
+/* *done = 1 once the job's outputs are written; then *job_status and
+   *latency_ms (submission to completion, host clock) are set. */
+vmo_status vmo_serve_poll(vmo_server s, uint64_t ticket, int32_t* done, vmo_status* job_status,
+                          double* latency_ms);
+vmo_status vmo_serve_wait(vmo_server s, uint64_t ticket, vmo_status* job_status, double* latency_ms);
+/* Drops the record of a finished ticket. */
+vmo_status vmo_serve_forget(vmo_server s, uint64_t ticket);
+vmo_status vmo_serve_get_stats(vmo_server s, vmo_serve_stats* out /* (host) */);
+/* Message of a failed job (host string owned by the server). */
+const char* vmo_serve_error(vmo_server s, uint64_t ticket);
+/* Stops after the running tick; jobs not finished by then are marked done
+   with VMO_E_BUSY.  No other thread may use the server once this is called. */
+vmo_status vmo_serve_destroy(vmo_server s);
+
+/* ---------------------------------------------------------------------------
  * Live kernel timing for measurement tools.  While enabled, the library
  * brackets every launch of its main kernels with HIP events recorded on the
  * launch stream and accumulates, per kernel name, the summed durations, the

@@ -55,6 +55,16 @@ class ProfileEntry(C.Structure):
     _fields_ = [("total_ms", C.c_double), ("launches", C.c_int64), ("work", C.c_double)]
 
 
+class ServeParams(C.Structure):
+    _fields_ = [("device", C.c_int), ("budget_bytes", C.c_size_t), ("max_jobs", C.c_int32), ("t_max", C.c_int32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("ticks", C.c_int64), ("resident", C.c_int64),
+                ("pending", C.c_int64), ("busy_ms", C.c_double), ("capacity_vertices", C.c_int64),
+                ("capacity_pins", C.c_int64), ("capacity_edges", C.c_int64)]
+
+
 class CutResult(C.Structure):
     _fields_ = [("lambda_minus_one", C.c_double), ("cut_net", C.c_double), ("nets_cut", C.c_int64)]
 
@@ -71,6 +81,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.vmo_last_error.restype = C.c_char_p
         L.vmo_pool_bytes.restype = C.c_size_t
+        L.vmo_serve_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -311,3 +322,71 @@ class Context:
         self._check(lib().vmo_layout_steps(self.h, C.byref(hs), C.byref(params), _ptr(x), C.c_int32(it0),
                                            C.c_int32(iters), C.byref(a), _stream()))
         return a.value
+
+
+class Server:
+    """Continuous-batching ordering server (vmo_serve_*).  Jobs are dicts as
+    for Context.order_batch; their tensors must stay alive until done."""
+
+    def __init__(self, budget_bytes: int = 8 << 30, max_jobs: int = 1024, t_max: int = 32, device: int = 0):
+        p = ServeParams()
+        lib().vmo_serve_defaults(C.byref(p))
+        p.device, p.budget_bytes, p.max_jobs, p.t_max = device, budget_bytes, max_jobs, t_max
+        h = C.c_void_p()
+        st = lib().vmo_serve_create(C.byref(h), C.byref(p))
+        if st != VMO_OK:
+            raise VmoError(st, "vmo_serve_create failed")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, job: dict, lp: LayoutParams | None = None) -> int:
+        h = job["h"]
+        mode = job.get("mode", NET)
+        o, s = Context._out(h, job["P"], mode, h.net_ptr.device)
+        hs = h.cstruct()
+        x = job.get("x")
+        jb = Job(hs, mode, job.get("order", SBD), _ptr(x).value if x is not None else None, job["P"], job["seed"],
+                 job.get("job_index", 0), s)
+        t = C.c_uint64()
+        torch.cuda.current_stream().synchronize()   # inputs written by torch are visible to the server's stream
+        st = lib().vmo_serve_submit(self.h, C.byref(jb), C.byref(lp) if lp is not None else None, C.byref(t))
+        if st != VMO_OK:
+            raise VmoError(st, "vmo_serve_submit rejected the job")
+        self._keep[t.value] = (job, o, s, hs, jb, lp)
+        return t.value
+
+    def poll(self, ticket: int):
+        done, st, lat = C.c_int32(), C.c_int32(), C.c_double()
+        r = lib().vmo_serve_poll(self.h, C.c_uint64(ticket), C.byref(done), C.byref(st), C.byref(lat))
+        if r != VMO_OK:
+            raise VmoError(r, "unknown ticket")
+        return bool(done.value), st.value, lat.value
+
+    def wait(self, ticket: int):
+        st, lat = C.c_int32(), C.c_double()
+        r = lib().vmo_serve_wait(self.h, C.c_uint64(ticket), C.byref(st), C.byref(lat))
+        if r != VMO_OK:
+            raise VmoError(r, "unknown ticket")
+        if st.value != VMO_OK:
+            raise VmoError(st.value, lib().vmo_serve_error(self.h, C.c_uint64(ticket)).decode())
+        job, o, *_ = self._keep.pop(ticket)
+        lib().vmo_serve_forget(self.h, C.c_uint64(ticket))
+        if o["nperm"] is not None:
+            o["nperm"] = o["nperm"][:job["h"].l]
+        return o, lat.value
+
+    def stats(self):
+        s = ServeStats()
+        lib().vmo_serve_get_stats(self.h, C.byref(s))
+        return {f: getattr(s, f) for f, _ in ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vmo_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,6 +6,8 @@
 // Every level of the recursion, for every job of a batch, is one segment list;
 // each kernel below covers all segments of a level in one launch (the plain
 // per-subproblem form reuses the same kernels with one segment per launch).
+#include <algorithm>
+
 #include "order_engine.h"
 
 namespace vmo {
@@ -52,6 +54,17 @@ __device__ __forceinline__ int32_t find_job(const JobDev* jobs, int32_t nj, int6
   while (hi - lo > 1) {
     int32_t mid = (lo + hi) >> 1;
     if (jobs[mid].voff <= pos) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Job of a virtual index u (emission): the last job whose base is <= u.
+__device__ __forceinline__ int32_t find_v(const JobDev* jobs, int32_t nj, int64_t u, int which) {
+  int32_t lo = 0, hi = nj;
+  while (hi - lo > 1) {
+    int32_t mid = (lo + hi) >> 1;
+    int64_t b = which == 0 ? jobs[mid].vk0 : (which == 1 ? jobs[mid].vn0 : jobs[mid].ve0);
+    if (b <= u) lo = mid; else hi = mid;
   }
   return lo;
 }
@@ -487,20 +500,17 @@ __global__ void k_children_write(SegArrays sg, int64_t s0, int64_t S, const int3
 
 // ------------------------------------------------------------- emission ----
 // Leaf vertices get the leaf's first part; separator vertices P + heap id.
-__global__ void k_node_fill(const JobDev* jobs, int32_t nj, NodeArrays nd, int64_t NT, const int32_t* id,
+__global__ void k_node_fill(const JobDev* jobs, int32_t nj, NodeArrays nd, int64_t NTv, const int32_t* id,
                             int32_t* const* part_out, int32_t* leafh) {
-  for (int64_t g = blockIdx.x; g < NT; g += gridDim.x) {
+  for (int64_t u = blockIdx.x; u < NTv; u += gridDim.x) {
+    int32_t j = find_v(jobs, nj, u, 1);
+    const JobDev& J = jobs[j];
+    int64_t g = J.node_base + (u - J.vn0);
     int32_t st = nd.state[g];
     if (st != kNodeLeaf && st != kNodeInternal) continue;
-    int32_t lo = 0, hi = nj;
-    while (hi - lo > 1) {
-      int32_t mid = (lo + hi) >> 1;
-      if (jobs[mid].node_base <= g) lo = mid; else hi = mid;
-    }
-    const JobDev& J = jobs[lo];
     int32_t h = (int32_t)(g - J.node_base);
     int32_t pv = st == kNodeLeaf ? nd.p0[g] : J.P + h;
-    int32_t* part = part_out[lo];
+    int32_t* part = part_out[j];
     for (int64_t i = nd.beg[g] + threadIdx.x; i < nd.end[g]; i += blockDim.x) {
       int32_t v = id[i];
       if (part) part[v - J.voff] = pv;
@@ -509,10 +519,11 @@ __global__ void k_node_fill(const JobDev* jobs, int32_t nj, NodeArrays nd, int64
   }
 }
 
-__global__ void k_vperm(const JobDev* jobs, int32_t nj, const int32_t* id, int64_t N, int32_t* const* vperm) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t j = find_job(jobs, nj, i);
-    vperm[j][i - jobs[j].voff] = (int32_t)(id[i] - jobs[j].voff);
+__global__ void k_vperm(const JobDev* jobs, int32_t nj, const int32_t* id, int64_t Nv, int32_t* const* vperm) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < Nv; u += (int64_t)gridDim.x * blockDim.x) {
+    int32_t j = find_v(jobs, nj, u, 0);
+    int64_t i = jobs[j].voff + (u - jobs[j].vk0);
+    vperm[j][u - jobs[j].vk0] = (int32_t)(id[i] - jobs[j].voff);
   }
 }
 
@@ -575,72 +586,60 @@ __device__ __forceinline__ int32_t heap_lca(int32_t a, int32_t b) {
 }
 
 // Net mode: a net belongs to the lowest common ancestor of its pins' leaves.
-__global__ void k_net_node(const JobDev* jobs, int32_t nj, const int64_t* nptr, const int32_t* npins, int64_t L,
-                           const int64_t* jnoff, const int32_t* leafh, const int32_t* rank_of, const OutPtrs* outs,
-                           const int64_t* keybase, uint32_t* key, int32_t* val, int32_t* node_of_net) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < L; g += (int64_t)gridDim.x * blockDim.x) {
-    int32_t lo = 0, hi = nj;
-    while (hi - lo > 1) {
-      int32_t mid = (lo + hi) >> 1;
-      if (jnoff[mid] <= g) lo = mid; else hi = mid;
-    }
-    const JobDev& J = jobs[lo];
+__global__ void k_net_node(const JobDev* jobs, int32_t nj, const int64_t* nptr, const int32_t* npins, int64_t Lv,
+                           const int32_t* leafh, const int32_t* rank_of, const OutPtrs* outs, const int64_t* keybase,
+                           uint32_t* key, int32_t* val, int32_t* node_of_net) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < Lv; u += (int64_t)gridDim.x * blockDim.x) {
+    int32_t j = find_v(jobs, nj, u, 2);
+    const JobDev& J = jobs[j];
+    int64_t g = J.noff + (u - J.ve0);
     int64_t b = nptr[g], e = nptr[g + 1];
     int32_t rk;
     int32_t node = 0;
-    if (b == e) rk = outs[lo].n_nodes[0];
+    if (b == e) rk = outs[j].n_nodes[0];
     else {
       node = leafh[npins[b]];
       for (int64_t p = b + 1; p < e; ++p) node = heap_lca(node, leafh[npins[p]]);
       rk = rank_of[J.node_base + node];
     }
-    node_of_net[g] = node;
-    key[g] = (uint32_t)(keybase[lo] + rk);
-    val[g] = (int32_t)(g - jnoff[lo]);
+    node_of_net[u] = node;
+    key[u] = (uint32_t)(keybase[j] + rk);
+    val[u] = (int32_t)(u - J.ve0);
   }
 }
 
-__global__ void k_net_cut(const JobDev* jobs, int32_t nj, const int64_t* jnoff, int64_t L, const int32_t* node_of_net,
-                          NodeArrays nd, const int32_t* rank_of, float* const* costs, const OutPtrs* outs,
-                          const uint32_t* key, const int64_t* keybase, int64_t* keycount) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < L; g += (int64_t)gridDim.x * blockDim.x) {
-    int32_t lo = 0, hi = nj;
-    while (hi - lo > 1) {
-      int32_t mid = (lo + hi) >> 1;
-      if (jnoff[mid] <= g) lo = mid; else hi = mid;
-    }
-    atomicAdd((unsigned long long*)&keycount[key[g]], 1ull);
-    int32_t node = node_of_net[g];
+__global__ void k_net_cut(const JobDev* jobs, int32_t nj, int64_t Lv, const int32_t* node_of_net, NodeArrays nd,
+                          const int32_t* rank_of, float* const* costs, const OutPtrs* outs, const uint32_t* key,
+                          int64_t* keycount) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < Lv; u += (int64_t)gridDim.x * blockDim.x) {
+    int32_t j = find_v(jobs, nj, u, 2);
+    atomicAdd((unsigned long long*)&keycount[key[u]], 1ull);
+    int32_t node = node_of_net[u];
     if (node == 0) continue;
-    const JobDev& J = jobs[lo];
+    const JobDev& J = jobs[j];
     if (nd.state[J.node_base + node] != kNodeInternal) continue;
-    const float* c = costs[lo];
-    double cv = c ? (double)c[g - jnoff[lo]] : 1.0;
-    atomicAdd(&outs[lo].split_cut[rank_of[J.node_base + node]], cv);
+    const float* c = costs[j];
+    double cv = c ? (double)c[u - J.ve0] : 1.0;
+    atomicAdd(&outs[j].split_cut[rank_of[J.node_base + node]], cv);
   }
 }
 
-__global__ void k_net_out(const JobDev* jobs, int32_t nj, const int64_t* jnoff, int64_t L, const int32_t* val,
-                          const OutPtrs* outs) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < L; g += (int64_t)gridDim.x * blockDim.x) {
-    int32_t lo = 0, hi = nj;
-    while (hi - lo > 1) {
-      int32_t mid = (lo + hi) >> 1;
-      if (jnoff[mid] <= g) lo = mid; else hi = mid;
-    }
-    if (outs[lo].nperm) outs[lo].nperm[g - jnoff[lo]] = val[g];
+__global__ void k_net_out(const JobDev* jobs, int32_t nj, int64_t Lv, const int32_t* val, const OutPtrs* outs) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < Lv; u += (int64_t)gridDim.x * blockDim.x) {
+    int32_t j = find_v(jobs, nj, u, 2);
+    if (outs[j].nperm) outs[j].nperm[u - jobs[j].ve0] = val[u];
   }
 }
 
 __global__ void k_net_ptr(const JobDev* jobs, int32_t nj, const int64_t* keyscan, const int64_t* keybase,
-                          const int64_t* jnoff, const OutPtrs* outs) {
+                          const OutPtrs* outs) {
   int32_t j = blockIdx.x;
   if (j >= nj) return;
   const OutPtrs& O = outs[j];
   if (!O.node_nptr) return;
   int32_t n = O.n_nodes[0];
   for (int32_t r = threadIdx.x; r <= n; r += blockDim.x)
-    O.node_nptr[r] = (int32_t)(keyscan[keybase[j] + r] - jnoff[j]);
+    O.node_nptr[r] = (int32_t)(keyscan[keybase[j] + r] - jobs[j].ve0);
 }
 
 __global__ void k_bisect_out(const JobDev* jobs, SegArrays sg, const uint8_t* side, int64_t k, uint8_t* out,
@@ -939,53 +938,69 @@ void Engine::run_levels(int t_max, bool plain) {
 }
 
 void Engine::finish(const std::vector<JobHost>& jobs) {
-  std::vector<OutPtrs> ho(nj);
-  std::vector<int32_t*> hpart(nj), hvperm(nj);
-  std::vector<float*> hcost(nj);
-  for (int32_t j = 0; j < nj; ++j) {
-    const vmo_order_out& o = jobs[j].out;
-    ho[j].vperm = o.vperm; ho[j].nperm = o.nperm; ho[j].part = o.part; ho[j].node_heap = o.node_heap;
-    ho[j].node_vptr = o.node_vptr; ho[j].node_nptr = jobs[j].mode == VMO_NET ? o.node_nptr : nullptr;
-    ho[j].split_cut = o.split_cut; ho[j].n_nodes = o.n_nodes;
-    hpart[j] = o.part; hvperm[j] = o.vperm;
-    hcost[j] = const_cast<float*>(jobs[j].h.c);
+  std::vector<int32_t> all(nj);
+  for (int32_t j = 0; j < nj; ++j) all[j] = j;
+  emit(all, jobs);
+}
+
+// Emission of the jobs `slots` (indices into the job table); jobs[i] holds the
+// outputs of slots[i].
+void Engine::emit(const std::vector<int32_t>& slots, const std::vector<JobHost>& jobs) {
+  int32_t m = (int32_t)slots.size();
+  if (m == 0) return;
+  std::vector<JobDev> sub(m);
+  std::vector<OutPtrs> ho(m);
+  std::vector<int32_t*> hpart(m), hvperm(m);
+  std::vector<float*> hcost(m);
+  std::vector<int64_t> kb(m);
+  int64_t Nv = 0, NTv = 0, Lv = 0, kt = 0;
+  for (int32_t i = 0; i < m; ++i) {
+    JobDev J = hj[slots[i]];
+    J.vk0 = Nv; J.vn0 = NTv; J.ve0 = Lv;
+    Nv += J.k;
+    NTv += 4 * (int64_t)J.P;
+    if (J.mode == VMO_NET) Lv += J.nnets;
+    sub[i] = J;
+    kb[i] = kt;
+    kt += J.mode == VMO_NET ? 4 * (int64_t)J.P + 1 : 0;
+    const vmo_order_out& o = jobs[i].out;
+    ho[i].vperm = o.vperm; ho[i].nperm = o.nperm; ho[i].part = o.part; ho[i].node_heap = o.node_heap;
+    ho[i].node_vptr = o.node_vptr; ho[i].node_nptr = J.mode == VMO_NET ? o.node_nptr : nullptr;
+    ho[i].split_cut = o.split_cut; ho[i].n_nodes = o.n_nodes;
+    hpart[i] = o.part; hvperm[i] = o.vperm;
+    hcost[i] = const_cast<float*>(jobs[i].h.c);
   }
-  Buf<OutPtrs> douts(c.pool, nj);
-  Buf<int32_t*> dpart(c.pool, nj), dvperm(c.pool, nj);
-  Buf<float*> dcost(c.pool, nj);
-  VMO_HIP(hipMemcpyAsync(douts.p, ho.data(), sizeof(OutPtrs) * nj, hipMemcpyHostToDevice, s));
-  VMO_HIP(hipMemcpyAsync(dpart.p, hpart.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
-  VMO_HIP(hipMemcpyAsync(dvperm.p, hvperm.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
-  VMO_HIP(hipMemcpyAsync(dcost.p, hcost.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
+  VMO_REQUIRE(kt < (int64_t(1) << 32), "too many tree nodes in one call");
+  Buf<JobDev> dsub(c.pool, m);
+  Buf<OutPtrs> douts(c.pool, m);
+  Buf<int32_t*> dpart(c.pool, m), dvperm(c.pool, m);
+  Buf<float*> dcost(c.pool, m);
+  Buf<int64_t> keybase(c.pool, m);
+  VMO_HIP(hipMemcpyAsync(dsub.p, sub.data(), sizeof(JobDev) * m, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(douts.p, ho.data(), sizeof(OutPtrs) * m, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(dpart.p, hpart.data(), sizeof(void*) * m, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(dvperm.p, hvperm.data(), sizeof(void*) * m, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(dcost.p, hcost.data(), sizeof(void*) * m, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(keybase.p, kb.data(), 8 * m, hipMemcpyHostToDevice, s));
   NodeArrays nd = nodes();
   Buf<int32_t> leafh(c.pool, Np);
-  VMO_LAUNCH(k_node_fill, (unsigned)(NT < 65536 ? (NT > 0 ? NT : 1) : 65536), kT, 0, s, dj.p, nj, nd, NT, id.p,
+  VMO_LAUNCH(k_node_fill, (unsigned)(NTv < 65536 ? (NTv > 0 ? NTv : 1) : 65536), kT, 0, s, dsub.p, m, nd, NTv, id.p,
              dpart.p, leafh.p);
-  VMO_LAUNCH(k_vperm, gsz(N), kT, 0, s, dj.p, nj, id.p, N, dvperm.p);
+  VMO_LAUNCH(k_vperm, gsz(Nv), kT, 0, s, dsub.p, m, id.p, Nv, dvperm.p);
   Buf<int32_t> rank_of(c.pool, NT);
-  VMO_LAUNCH(k_emit, nblocks(nj, 64), 64, 0, s, dj.p, nj, nd, douts.p, rank_of.p);
-  if (L > 0) {
-    // key space per job: 4P + 1 (ranks, then the empty-net bucket)
-    std::vector<int64_t> kb(nj);
-    int64_t kt = 0;
-    for (int32_t j = 0; j < nj; ++j) { kb[j] = kt; kt += hj[j].mode == VMO_NET ? 4 * (int64_t)hj[j].P + 1 : 0; }
-    VMO_REQUIRE(kt < (int64_t(1) << 32), "too many tree nodes in one call");
-    Buf<int64_t> keybase(c.pool, nj);
-    VMO_HIP(hipMemcpyAsync(keybase.p, kb.data(), 8 * nj, hipMemcpyHostToDevice, s));
-    // only net-mode jobs own nets; jnoff of graph jobs equals the next job's, so
-    // the binary search below always lands on the net-mode job owning net g
-    Buf<uint32_t> key(c.pool, L);
-    Buf<int32_t> val(c.pool, L), nnode(c.pool, L);
-    VMO_LAUNCH(k_net_node, gsz(L), kT, 0, s, dj.p, nj, nptr.p, npins_buf.p, L, jnoff.p, leafh.p, rank_of.p, douts.p,
+  VMO_LAUNCH(k_emit, nblocks(m, 64), 64, 0, s, dsub.p, m, nd, douts.p, rank_of.p);
+  if (Lv > 0) {
+    Buf<uint32_t> key(c.pool, Lv);
+    Buf<int32_t> val(c.pool, Lv), nnode(c.pool, Lv);
+    VMO_LAUNCH(k_net_node, gsz(Lv), kT, 0, s, dsub.p, m, nptr.p, npins_buf.p, Lv, leafh.p, rank_of.p, douts.p,
                keybase.p, key.p, val.p, nnode.p);
     Buf<int64_t> kc(c.pool, kt + 1);
     fill_i64(kc.p, 0, kt + 1, s);
-    VMO_LAUNCH(k_net_cut, gsz(L), kT, 0, s, dj.p, nj, jnoff.p, L, nnode.p, nd, rank_of.p, dcost.p, douts.p, key.p,
-               keybase.p, kc.p);
+    VMO_LAUNCH(k_net_cut, gsz(Lv), kT, 0, s, dsub.p, m, Lv, nnode.p, nd, rank_of.p, dcost.p, douts.p, key.p, kc.p);
     scan_exclusive<int64_t>(c, kc.p, kc.p, kt, kc.p + kt, s);
-    radix_sort<uint32_t>(c, key.p, val.p, L, bits_for((uint64_t)kt), s);
-    VMO_LAUNCH(k_net_out, gsz(L), kT, 0, s, dj.p, nj, jnoff.p, L, val.p, douts.p);
-    VMO_LAUNCH(k_net_ptr, nj, kT, 0, s, dj.p, nj, kc.p, keybase.p, jnoff.p, douts.p);
+    radix_sort<uint32_t>(c, key.p, val.p, Lv, bits_for((uint64_t)kt), s);
+    VMO_LAUNCH(k_net_out, gsz(Lv), kT, 0, s, dsub.p, m, Lv, val.p, douts.p);
+    VMO_LAUNCH(k_net_ptr, m, kT, 0, s, dsub.p, m, kc.p, keybase.p, douts.p);
   }
   VMO_HIP(hipStreamSynchronize(s));
 }
@@ -998,4 +1013,181 @@ void bisect_outputs(Engine& e, uint8_t* side, float* centres, int split) {
   VMO_LAUNCH(k_bisect_out, gsz(e.N), kT, 0, e.s, e.dj.p, sg, e.side.p, e.N, side, split);
   VMO_LAUNCH(k_bisect_centres, 1, 64, 0, e.s, e.dj.p, sg, centres, split);
 }
+}  // namespace vmo
+
+// ============================================================ serving ====
+namespace vmo {
+
+__global__ void k_quantize_range(const JobDev* jd, const float* x, int32_t k, int64_t voff, int64_t Np, uint32_t* q,
+                                 int32_t* id, int32_t* pos) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = jd->scale;
+    for (int d = 0; d < 4; ++d) {
+      uint32_t v = 0;
+      if (s > 0.0) {
+        double t = ((double)x[(int64_t)d * k + i] - (double)jd->lo[d]) * s;
+        double f = floor(t);
+        v = f >= (double)kQMax ? kQMax : (uint32_t)f;
+      }
+      q[d * Np + voff + i] = v;
+    }
+    id[voff + i] = (int32_t)(voff + i);
+    pos[voff + i] = (int32_t)(voff + i);
+  }
+}
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+void Engine::arena_init(int64_t max_v, int64_t max_nodes, int64_t max_edges, int64_t max_nets, int64_t max_pins,
+                        int32_t max_jobs) {
+  N = max_v;
+  Np = (N + 3) & ~int64_t(3);
+  NT = max_nodes;
+  E = max_edges;
+  L = max_nets;
+  npins_ = max_pins;
+  nj = max_jobs;
+  hj.assign(nj, JobDev());
+  for (auto& J : hj) memset(&J, 0, sizeof J);
+  dj = Buf<JobDev>(c.pool, nj);
+  VMO_HIP(hipMemcpyAsync(dj.p, hj.data(), sizeof(JobDev) * nj, hipMemcpyHostToDevice, s));
+  q = Buf<uint32_t>(c.pool, 4 * Np);
+  q2 = Buf<uint32_t>(c.pool, 4 * Np);
+  id = Buf<int32_t>(c.pool, Np);
+  id2 = Buf<int32_t>(c.pool, Np);
+  pos = Buf<int32_t>(c.pool, Np);
+  side = Buf<uint8_t>(c.pool, Np);
+  segpos = Buf<int32_t>(c.pool, Np);
+  VMO_LAUNCH(k_fill_u32, gsz(4 * Np), kT, 0, s, q.p, 0u, 4 * Np);
+  iota_i32(id.p, Np, s);
+  iota_i32(pos.p, Np, s);
+  nd_state = Buf<int32_t>(c.pool, NT);
+  nd_K = Buf<int32_t>(c.pool, NT);
+  nd_p0 = Buf<int32_t>(c.pool, NT);
+  nd_beg = Buf<int64_t>(c.pool, NT);
+  nd_end = Buf<int64_t>(c.pool, NT);
+  fill_i32(nd_state.p, kNodeNone, NT, s);
+  edges = Buf<int32_t>(c.pool, 2 * (E > 0 ? E : 1));
+  fill_i32(edges.p, 0, 2 * (E > 0 ? E : 1), s);
+  nptr = Buf<int64_t>(c.pool, L + 1);
+  fill_i64(nptr.p, 0, L + 1, s);
+  npins_buf = Buf<int32_t>(c.pool, max_pins > 0 ? max_pins : 1);
+  alloc_segments(cur, 1024);
+  S = 0;
+  VMO_HIP(hipStreamSynchronize(s));
+}
+
+void Engine::append_root(int32_t slot) {
+  const JobDev& J = hj[slot];
+  if (S + 1 > cur.cap) {
+    SegBufs bigger;
+    alloc_segments(bigger, 2 * (S + 1));
+    if (S > 0) copy_segments(cur, bigger, S);
+    cur = std::move(bigger);
+  }
+  int64_t b = J.voff, e = J.voff + J.k;
+  int32_t jb = slot, h = 1, K = J.P, p0 = 0;
+  VMO_HIP(hipMemcpyAsync(cur.beg.p + S, &b, 8, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.end.p + S, &e, 8, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.job.p + S, &jb, 4, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.h.p + S, &h, 4, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.K.p + S, &K, 4, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.p0.p + S, &p0, 4, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  ++S;
+  // the level kernels find a position's segment by binary search over the
+  // segment starts: keep the list sorted (a reused low range may come last)
+  std::vector<int64_t> hb(S), he(S);
+  std::vector<int32_t> hjb(S), hh(S), hK(S), hp(S);
+  VMO_HIP(hipMemcpyAsync(hb.data(), cur.beg.p, 8 * S, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipMemcpyAsync(he.data(), cur.end.p, 8 * S, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipMemcpyAsync(hjb.data(), cur.job.p, 4 * S, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipMemcpyAsync(hh.data(), cur.h.p, 4 * S, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipMemcpyAsync(hK.data(), cur.K.p, 4 * S, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipMemcpyAsync(hp.data(), cur.p0.p, 4 * S, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> idx(S);
+  for (int64_t i = 0; i < S; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return hb[a] < hb[b]; });
+  std::vector<int64_t> sb(S), se(S);
+  std::vector<int32_t> sj(S), sh(S), sK(S), sp(S);
+  for (int64_t i = 0; i < S; ++i) {
+    sb[i] = hb[idx[i]]; se[i] = he[idx[i]]; sj[i] = hjb[idx[i]]; sh[i] = hh[idx[i]]; sK[i] = hK[idx[i]];
+    sp[i] = hp[idx[i]];
+  }
+  VMO_HIP(hipMemcpyAsync(cur.beg.p, sb.data(), 8 * S, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.end.p, se.data(), 8 * S, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.job.p, sj.data(), 4 * S, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.h.p, sh.data(), 4 * S, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.K.p, sK.data(), 4 * S, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cur.p0.p, sp.data(), 4 * S, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipStreamSynchronize(s));
+}
+
+void Engine::arena_admit(int32_t slot, const JobHost& H, int64_t voff, int64_t node_base, int64_t eoff, int64_t noff,
+                         int64_t pinoff) {
+  JobDev D;
+  memset(&D, 0, sizeof D);
+  D.voff = voff; D.k = H.h.k; D.P = H.P; D.mode = H.mode; D.ord = H.order;
+  D.seed = H.seed; D.job_index = H.job_index; D.node_base = node_base; D.nnets = H.h.l;
+  D.eoff = eoff; D.noff = noff;
+  // quantization of this job alone
+  Buf<JobDev> one(c.pool, 1);
+  D.voff = 0;
+  VMO_HIP(hipMemcpyAsync(one.p, &D, sizeof D, hipMemcpyHostToDevice, s));
+  Buf<uint32_t> box(c.pool, 8);
+  uint32_t hb[8] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u};
+  VMO_HIP(hipMemcpyAsync(box.p, hb, sizeof hb, hipMemcpyHostToDevice, s));
+  VMO_LAUNCH(k_bbox, nblocks(D.k, kT), kT, 0, s, one.p, 1, H.x, (int64_t)D.k, (int64_t)D.k, box.p);
+  VMO_LAUNCH(k_job_scale, 1, 64, 0, s, one.p, 1, box.p);
+  VMO_LAUNCH(k_quantize_range, gsz(D.k), kT, 0, s, one.p, H.x, D.k, voff, Np, q.p, id.p, pos.p);
+  VMO_HIP(hipMemcpyAsync(&D, one.p, sizeof D, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  D.voff = voff;
+  hj[slot] = D;
+  VMO_HIP(hipMemcpyAsync(dj.p + slot, &D, sizeof D, hipMemcpyHostToDevice, s));
+  // node table of the job, root node
+  fill_i32(nd_state.p + node_base, kNodeNone, 4 * (int64_t)D.P, s);
+  VMO_LAUNCH(k_init_roots, 1, 64, 0, s, dj.p + slot, 1, nodes());
+  // edges or nets with global (arena) vertex ids
+  if (H.mode == VMO_GRAPH) {
+    if (H.h.l > 0) launch_offset_copy_i32(H.h.pins, edges.p + 2 * eoff, 2 * (int64_t)H.h.l, (int32_t)voff);
+  } else if (H.h.l > 0) {
+    launch_offset_copy_ptr(H.h.net_ptr, nptr.p + noff, (int64_t)H.h.l + 1, pinoff);
+    int64_t np = read1(H.h.net_ptr + H.h.l, s);
+    if (np > 0) launch_offset_copy_i32(H.h.pins, npins_buf.p + pinoff, np, (int32_t)voff);
+  }
+  VMO_HIP(hipStreamSynchronize(s));
+  if (D.k >= 2 && D.P > 1) append_root(slot);
+}
+
+void Engine::arena_release(int32_t slot) {
+  const JobDev& J = hj[slot];
+  if (J.mode == VMO_GRAPH && J.nnets > 0) fill_i32(edges.p + 2 * J.eoff, 0, 2 * (int64_t)J.nnets, s);
+  fill_i32(nd_state.p + J.node_base, kNodeNone, 4 * (int64_t)J.P, s);
+  VMO_HIP(hipStreamSynchronize(s));
+  memset(&hj[slot], 0, sizeof(JobDev));
+}
+
+void Engine::tick(int t_max) {
+  if (S == 0) return;
+  SegBufs nx;
+  alloc_segments(nx, 2 * S);
+  two_means(0, S, 0, Np, t_max);
+  separator(0, S, 0, Np, 0, E);
+  int64_t nn = partition(0, S, 0, Np, nx, 0);
+  cur = std::move(nx);
+  S = nn;
+}
+
+std::vector<int32_t> Engine::segment_jobs() {
+  std::vector<int32_t> v(S);
+  if (S > 0) {
+    VMO_HIP(hipMemcpyAsync(v.data(), cur.job.p, 4 * S, hipMemcpyDeviceToHost, s));
+    VMO_HIP(hipStreamSynchronize(s));
+  }
+  return v;
+}
+
 }  // namespace vmo

@@ -21,6 +21,10 @@ struct JobDev {
   int64_t noff;        // first net (net mode)
   int32_t nnets;
   int32_t pad;
+  // bases of this job in the index spaces of one emission call (vertices,
+  // tree nodes, nets): a subset of jobs is emitted over the concatenation of
+  // their ranges
+  int64_t vk0, vn0, ve0;
 };
 
 struct JobHost {
@@ -78,6 +82,8 @@ class Engine {
   void set_edges(const std::vector<JobHost>& jobs);
   void run_levels(int t_max, bool plain);
   void finish(const std::vector<JobHost>& jobs);
+  // emission for the jobs `slots` of the job table (their work is done)
+  void emit(const std::vector<int32_t>& slots, const std::vector<JobHost>& jobs);
   // single split of the level-0 segments (vmo_bisect)
   void two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max);
 
@@ -99,6 +105,15 @@ class Engine {
   SegArrays view(SegBufs& b);
   NodeArrays nodes();
 
+  // serving: fixed arenas, jobs admitted into ranges, one level per tick
+  void arena_init(int64_t max_v, int64_t max_nodes, int64_t max_edges, int64_t max_nets, int64_t max_pins,
+                  int32_t max_jobs);
+  void arena_admit(int32_t slot, const JobHost& h, int64_t voff, int64_t node_base, int64_t eoff, int64_t noff,
+                   int64_t pinoff);
+  void arena_release(int32_t slot);
+  void tick(int t_max);
+  std::vector<int32_t> segment_jobs();
+
  private:
   void alloc_segments(SegBufs& b, int64_t cap);
   void copy_segments(SegBufs& a, SegBufs& b, int64_t n);
@@ -106,6 +121,7 @@ class Engine {
   int64_t partition(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, SegBufs& nx, int64_t t0);
   void launch_offset_copy_i32(const int32_t* in, int32_t* out, int64_t n, int32_t add);
   void launch_offset_copy_ptr(const int64_t* in, int64_t* out, int64_t n, int64_t add);
+  void append_root(int32_t slot);
 };
 
 // bisect output helpers (order.hip)

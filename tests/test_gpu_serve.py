@@ -1,0 +1,96 @@
+"""Serving with continuous batching (vmo_serve_*): each job's result equals
+the oracle's ordering of that job alone, whatever else is resident; jobs that
+do not fit the memory budget wait for room; jobs laid out at admission match
+the whole-path ordering; impossible jobs are refused."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import vmo_gen
+from gpu_util import compare_order, dev_h, dev_x
+
+pytestmark = pytest.mark.gpu
+
+
+def job_set(n, seed, scale=1):
+    r = vmo_gen.rng(seed, 31)
+    out = []
+    for j in range(n):
+        kind = j % 3
+        if kind == 0:
+            g = vmo_gen.banded(int(r.integers(300, 2500)) * scale, int(r.integers(5, 30)), seed * 97 + j)
+            h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+            mode, ordr = 0, 0
+        elif kind == 1:
+            g = vmo_gen.grid3d(int(r.integers(4, 11)), seed=j + 1)
+            h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
+            mode, ordr = 1, 1
+        else:
+            g = vmo_gen.zipf_rect(int(r.integers(300, 3000)) * scale, 600, seed * 97 + j)
+            h = oracle.colnet(g.m, g.n, g.rowptr, g.col)
+            mode, ordr = 0, 1
+        x = vmo_gen.random_points(h.k, seed * 1000 + j, clusters=3)
+        P = int(r.integers(2, 33))
+        ref = oracle.order(h, x, P, 9, mode=mode, ord=ordr, job=100 + j)
+        out.append(({"h": dev_h(h), "x": dev_x(x), "P": P, "seed": 9, "mode": mode, "order": ordr,
+                     "job_index": 100 + j}, (h, ref, mode)))
+    return out
+
+
+def test_serve_mix_equals_alone_and_oracle():
+    import paper_1105_4490_amd as P
+    jobs = job_set(12, 3)
+    srv = P.Server(budget_bytes=256 << 20, max_jobs=64)
+    tickets = [srv.submit(j) for j, _ in jobs[:6]]
+    time.sleep(0.01)
+    tickets += [srv.submit(j) for j, _ in jobs[6:]]      # arrive while the first ones run
+    for t, (_, (h, ref, mode)) in zip(tickets, jobs):
+        o, lat = srv.wait(t)
+        compare_order(o, ref, mode, h.k, h.l)
+        assert lat > 0
+    st = srv.stats()
+    assert st["completed"] == 12 and st["ticks"] > 0
+    srv.close()
+    # the same job alone on a fresh server
+    srv = P.Server(budget_bytes=64 << 20, max_jobs=4)
+    j, (h, ref, mode) = jobs[4]
+    o, _ = srv.wait(srv.submit(j))
+    compare_order(o, ref, mode, h.k, h.l)
+    srv.close()
+
+
+def test_serve_admission_waits_for_room():
+    """A budget that holds only a few jobs at a time: the rest queue and all finish right."""
+    import paper_1105_4490_amd as P
+    jobs = job_set(9, 5)
+    srv = P.Server(budget_bytes=4 << 20, max_jobs=3)
+    tickets = [srv.submit(j) for j, _ in jobs]
+    for t, (_, (h, ref, mode)) in zip(tickets, jobs):
+        o, _ = srv.wait(t)
+        compare_order(o, ref, mode, h.k, h.l)
+    srv.close()
+
+
+def test_serve_refuses_jobs_larger_than_the_arena():
+    import paper_1105_4490_amd as P
+    srv = P.Server(budget_bytes=1 << 20, max_jobs=2)    # about 4k vertex slots
+    g = vmo_gen.grid2d(128)
+    h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+    with pytest.raises(P.VmoError):
+        srv.submit({"h": dev_h(h), "x": dev_x(vmo_gen.random_points(h.k, 1)), "P": 4, "seed": 1})
+    srv.close()
+
+
+def test_serve_with_layout_at_admission():
+    import paper_1105_4490_amd as P
+    g = vmo_gen.grid2d(24)
+    h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+    lp = P.layout_params(seed=4)
+    srv = P.Server(budget_bytes=64 << 20, max_jobs=8)
+    t = srv.submit({"h": dev_h(h), "x": None, "P": 8, "seed": 2, "job_index": 0}, lp=lp)
+    o, _ = srv.wait(t)
+    x = oracle.layout(h, oracle.layout_params(seed=4))
+    compare_order(o, oracle.order(h, x, 8, 2), oracle.NET_MODE, h.k, h.l)
+    srv.close()
