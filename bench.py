@@ -10,6 +10,17 @@ prolongation, packing), recursive 2-means ordering with separators and
 emission, and the cut metrics of the result.
 
 Prints one JSON line (see the field list at the end of main()).
+
+Two more workloads are measured by their own modes (one JSON line each):
+  --mode batch   512 banded matrices (rows log-uniform in [1e3, 5e4], half
+                 bandwidth 5-40, 0.1 % off-band entries, 8-32 parts each,
+                 row-net, SBD), coordinates laid out beforehand: recursive
+                 ordering of all of them by one segmented launch sequence per
+                 level, against the same work done one subproblem at a time.
+  --mode serve   a Poisson stream of ordering jobs (nnz log-uniform in
+                 [1e3, 1e7], uniform over the three matrix shapes), submitted to
+                 the continuous-batching server at their arrival times; p50/p99
+                 latency and nnz/s.
 """
 import argparse
 import json
@@ -38,6 +49,11 @@ def main():
     ap.add_argument("--side", type=int, default=N_SIDE, help="grid side of the workload (64 = the 64^3 case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=28, help="grid side of the oracle's timed sample")
+    ap.add_argument("--mode", choices=("path", "batch", "serve"), default="path")
+    ap.add_argument("--jobs", type=int, default=512, help="batch mode: number of matrices")
+    ap.add_argument("--requests", type=int, default=40, help="serve mode: number of requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve mode: arrivals per second")
+    ap.add_argument("--nnz-max", type=float, default=1e7, help="serve mode: largest nnz of a request")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -55,6 +71,10 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = P.Context(0)
+    if args.mode == "batch":
+        return bench_batch(args, ctx)
+    if args.mode == "serve":
+        return bench_serve(args, ctx)
     g = vmo_gen.grid3d(args.side, seed=SEED)
     nnz = g.nnz
     rowptr = torch.as_tensor(g.rowptr).cuda()
@@ -122,6 +142,142 @@ def main():
                          "frac": round(a_gbs / PEAK_HBM_GBS, 4), "launches": assign["launches"],
                          "share_of_step": round(assign["total_ms"] / (1e3 * dt), 4)},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def _pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, max(0, math.ceil(q * len(v)) - 1))]
+
+
+def bench_batch(args, ctx):
+    """Recursive ordering of many banded matrices: batched against plain."""
+    import torch
+    import paper_1105_4490_amd as P
+    import vmo_gen
+    t = time.perf_counter()
+    mats = vmo_gen.batch_banded(args.jobs, seed=SEED)
+    gen_s = time.perf_counter() - t
+    print(f"bench: generated {len(mats)} matrices in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    jobs = []
+    t = time.perf_counter()
+    for i, (g, parts) in enumerate(mats):
+        h = ctx.model(P.ROW_NET, g.m, g.n, torch.as_tensor(g.rowptr).cuda(), torch.as_tensor(g.col).cuda())
+        x = ctx.layout(h, P.layout_params(seed=SEED + i))
+        jobs.append({"h": h, "x": x, "P": parts, "seed": SEED, "mode": P.NET, "order": P.SBD, "job_index": i})
+        if (i + 1) % 64 == 0:
+            print(f"bench: laid out {i + 1} matrices", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    lay_s = time.perf_counter() - t
+    nnz = sum(g.nnz for g, _ in mats)
+    rows = sum(g.m for g, _ in mats)
+
+    def run(plain, steps):
+        ctx.profile(True)
+        ctx.profile_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            outs = ctx.order_batch(jobs, plain=plain)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        a = ctx.profile_read("assign")
+        ctx.profile(False)
+        return outs, dt, a
+
+    for _ in range(args.warmup):
+        run(False, 1)
+    outs, dt_b, a_b = run(False, args.steps)
+    print(f"bench: batched {1e3 * dt_b:.1f} ms", file=sys.stderr, flush=True)
+    outs_p, dt_p, _ = run(True, 1)
+    print(f"bench: plain {1e3 * dt_p:.1f} ms", file=sys.stderr, flush=True)
+    same = all(torch.equal(a["vperm"], b["vperm"]) and torch.equal(a["part"], b["part"])
+               for a, b in zip(outs, outs_p))
+    a_gbs = a_b["work"] / (a_b["total_ms"] * 1e-3) / 1e9 if a_b["total_ms"] > 0 else 0.0
+    line = {
+        "metric": "matrix nnz ordered/sec (batched recursive SBD, coordinates given)",
+        "value": nnz / dt_b, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt_b, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 grid / f64 plane", "data": "synthetic",
+        "config": {"workload": f"{len(mats)} banded matrices ({rows} rows, {nnz} nnz), rows log-uniform "
+                               "1e3-5e4, half bandwidth 5-40, 0.1% off-band, 8-32 parts, row-net, recursive SBD; "
+                               "coordinates from the layout, computed before the timed region",
+                   "jobs": len(mats), "seed": SEED},
+        "plain": {"value": nnz / dt_p, "unit": "nnz/s", "ms": 1e3 * dt_p,
+                  "form": "one launch sequence per subproblem"},
+        "batched_over_plain": dt_p / dt_b, "identical_results": same,
+        "lloyd_assign": {"bound": "hbm", "achieved": round(a_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(a_gbs / PEAK_HBM_GBS, 4), "launches": a_b["launches"],
+                         "share_of_step": round(a_b["total_ms"] / (1e3 * dt_b * args.steps), 4)},
+        "untimed": {"generate_s": round(gen_s, 1), "layout_s": round(lay_s, 1)},
+    }
+    print(json.dumps(line))
+
+
+def _serve_matrix(spec):
+    import vmo_gen
+    if spec["kind"] == "grid2d":
+        return vmo_gen.grid2d(spec["N"]), 0
+    if spec["kind"] == "grid3d":
+        return vmo_gen.grid3d(spec["N"], seed=spec["seed"]), 1
+    return vmo_gen.zipf_rect(spec["m"], spec["n"], spec["seed"]), 2
+
+
+def bench_serve(args, ctx):
+    """A Poisson stream of whole-path ordering jobs through the server."""
+    import torch
+    import paper_1105_4490_amd as P
+    import vmo_gen
+    # model, parts and order of each shape: 2-D grid row-net 16 SBD; 3-D grid
+    # symmetric 64 BBD with separators; rectangular column-net 256 SBD
+    shapes = {0: (P.ROW_NET, 16, P.NET, P.SBD), 1: (P.SYMMETRIC, 64, P.GRAPH, P.BBD), 2: (P.COLUMN_NET, 256, P.NET, P.SBD)}
+    reqs = vmo_gen.serve_stream(args.requests, seed=SEED, rate=args.rate, nnz_max=args.nnz_max)
+    jobs = []
+    t = time.perf_counter()
+    for i, spec in enumerate(reqs):
+        g, kind = _serve_matrix(spec)
+        model, parts, mode, order = shapes[kind]
+        h = ctx.model(model, g.m, g.n, torch.as_tensor(g.rowptr).cuda(), torch.as_tensor(g.col).cuda())
+        jobs.append(({"h": h, "x": None, "P": parts, "seed": SEED, "mode": mode, "order": order, "job_index": i},
+                     spec["arrival"], g.nnz))
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t
+    print(f"bench: prepared {len(jobs)} requests ({sum(j[2] for j in jobs)} nnz) in {prep_s:.1f} s",
+          file=sys.stderr, flush=True)
+    lp = P.layout_params(seed=SEED)
+    srv = P.Server(budget_bytes=16 << 30, max_jobs=256)
+    tickets = []
+    t0 = time.perf_counter()
+    for jb, at, nz in jobs:
+        now = time.perf_counter() - t0
+        if at > now:
+            time.sleep(at - now)
+        tickets.append((srv.submit(jb, lp), time.perf_counter() - t0, nz))
+    lat = []
+    done_at = 0.0
+    for i, (tk, sub, nz) in enumerate(tickets):
+        o, ms = srv.wait(tk)
+        lat.append(ms)
+        done_at = max(done_at, time.perf_counter() - t0)
+        if (i + 1) % 10 == 0:
+            print(f"bench: {i + 1} requests done", file=sys.stderr, flush=True)
+    st = srv.stats()
+    srv.close()
+    total = sum(j[2] for j in jobs)
+    span = done_at
+    line = {
+        "metric": "matrix nnz ordered/sec (served, full recursive SBD/BBD) + p50/p99 latency",
+        "value": total / span, "unit": "nnz/s", "n_gpus": 1, "steps": len(jobs), "warmup": 0,
+        "ms_per_step": 1e3 * span / len(jobs), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Poisson stream of {len(jobs)} requests at {args.rate}/s, nnz log-uniform "
+                               f"[1e3, {args.nnz_max:.0e}], uniform over 2-D grid (row-net, 16, SBD), 3-D grid "
+                               "(symmetric, 64, BBD), rectangular Zipf (column-net, 256, SBD); layout + order",
+                   "seed": SEED},
+        "latency_ms": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99), "max": max(lat)},
+        "offered_nnz_per_s": total / max(jobs[-1][1], 1e-9),
+        "busy_ms": st["busy_ms"], "ticks": st["ticks"],
     }
     print(json.dumps(line))
 
