@@ -217,13 +217,38 @@ __global__ void k_tree_ell(const int8_t* cpl, int32_t k, int32_t cap, int8_t* el
   }
 }
 
+// Far-field thresholds per depth: the node at depth L is far iff D2 >= T[L],
+// D2 = squared distance point-to-cell-centre in doubled grid units (an exact
+// integer below 2^40, so exact in FP64).  T[L] is the smallest integer D2
+// for which s^2 < theta^2 D2 holds in FP64 (s = doubled cell side); the
+// predicate is monotone in D2, so both forms decide every node alike.
+struct FarTable {
+  double T[17];
+};
+static FarTable far_table(double th2) {
+  FarTable f;
+  for (int L = 0; L <= 16; ++L) {
+    int64_t s2 = (int64_t)2 << (16 - L);
+    double lhs = (double)(s2 * s2);
+    if (!(th2 > 0.0)) { f.T[L] = 1e300; continue; }
+    int64_t lo = 0, hi = (int64_t)1 << 42;  // hi always satisfies the predicate
+    while (lo < hi) {
+      int64_t mid = lo + (hi - lo) / 2;
+      if (lhs < th2 * (double)mid) hi = mid; else lo = mid + 1;
+    }
+    f.T[L] = (double)lo;
+  }
+  return f;
+}
+
 // One tree node as the walk reads it (64 bytes).
 struct alignas(16) TNode {
   int4 a;    // cell centre x 2 (grid units)
   int4 b;    // next, first, count, depth | leaf << 8
   float4 X;  // charge centre
   float W;   // charge
-  float pad[3];
+  float pad;
+  double T;  // far threshold of the node's depth (FarTable)
 };
 
 struct NodeView {
@@ -238,7 +263,7 @@ struct NodeView {
 // Nodes in pre-order: index = base[i] + (L - cpl[i] - 1) for the node of
 // depth L beginning at point i; next = first node beginning at its end.
 __global__ void k_tree_nodes(const int8_t* cpl, const int8_t* bmin, const int8_t* ell, const int32_t* base,
-                             const int32_t* p2, int32_t k, NodeView nd) {
+                             const int32_t* p2, int32_t k, FarTable ft, NodeView nd) {
   GRID_STRIDE(i64, k) {
     int32_t i = (int32_t)i64;
     int ci = cpl[i], li = ell[i];
@@ -256,6 +281,7 @@ __global__ void k_tree_nodes(const int8_t* cpl, const int8_t* bmin, const int8_t
       cc.w = 2 * ((kq3 >> (16 - L)) << (16 - L)) + side;
       nd.t[t].a = cc;
       nd.t[t].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
+      nd.t[t].T = ft.T[L];
       nd.parent[t] = -1;
       nd.ctr[t] = 0;
     }
@@ -341,7 +367,7 @@ struct Tree {
 
 // Build the tree of x [4][k] (weights w or 1) with the bounding box dbox.
 static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t k, int32_t cap, const uint32_t* dbox,
-                       hipStream_t s) {
+                       double th2, hipStream_t s) {
   T.k = k;
   T.key = Buf<uint64_t>(C.pool, k);
   T.order = Buf<int32_t>(C.pool, k);
@@ -369,7 +395,7 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
   T.nch = Buf<int32_t>(C.pool, n);
   T.ctr = Buf<int32_t>(C.pool, n);
   NodeView nd = T.view();
-  VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.bmin.p, T.ell.p, T.nn.p, T.p2.p, k, nd);
+  VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.bmin.p, T.ell.p, T.nn.p, T.p2.p, k, far_table(th2), nd);
   VMO_LAUNCH(k_tree_links, gsz(n), kLT, 0, s, n, nd);
   VMO_LAUNCH(k_tree_moments, gsz(n), kLT, 0, s, n, k, T.xs.p, T.ws.p, nd);
 }
@@ -419,7 +445,7 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
 }
 
 // (d-2) W w_n |X - x|^-4 (X - x), d = 4, operation by operation.
-__device__ __forceinline__ void interact(float* y, const float* xn, float wn, float X0, float X1, float X2, float X3,
+__device__ __forceinline__ void interact(float* y, const float* xn, float wn2, float X0, float X1, float X2, float X3,
                                          float W) {
   float dx0 = X0 - xn[0], dx1 = X1 - xn[1], dx2 = X2 - xn[2], dx3 = X3 - xn[3];
   float r2 = dx0 * dx0;
@@ -427,8 +453,7 @@ __device__ __forceinline__ void interact(float* y, const float* xn, float wn, fl
   r2 = r2 + dx2 * dx2;
   r2 = r2 + dx3 * dx3;
   if (!(r2 > 0.0f)) return;
-  float num = 2.0f * W;
-  num = num * wn;
+  float num = W * wn2;  // (2 W) w_n = W (2 w_n) exactly
   float den = r2 * r2;
   float f = num / den;
   y[0] = y[0] + f * dx0;
@@ -437,9 +462,16 @@ __device__ __forceinline__ void interact(float* y, const float* xn, float wn, fl
   y[3] = y[3] + f * dx3;
 }
 
+// Minimum over the 64 lanes (all active), by DPP row shifts and row
+// broadcasts; lane 63 ends with the minimum of the wavefront.
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
-  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-  return v;
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Repulsion by the stackless walk of Algorithm 3: a far node acts as one charge
@@ -455,35 +487,11 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // a per-wavefront LDS window of 64 consecutive nodes (one 64-byte node per
 // lane per refill).
 constexpr int kWin = 64;
-// Far-field thresholds per depth: the node at depth L is far iff D2 >= T[L],
-// D2 = squared distance point-to-cell-centre in doubled grid units (an exact
-// integer below 2^40, so exact in FP64).  T[L] is the smallest integer D2
-// for which s^2 < theta^2 D2 holds in FP64 (s = doubled cell side); the
-// predicate is monotone in D2, so both forms decide every node alike.
-struct FarTable {
-  double T[17];
-};
-static FarTable far_table(double th2) {
-  FarTable f;
-  for (int L = 0; L <= 16; ++L) {
-    int64_t s2 = (int64_t)2 << (16 - L);
-    double lhs = (double)(s2 * s2);
-    if (!(th2 > 0.0)) { f.T[L] = 1e300; continue; }
-    int64_t lo = 0, hi = (int64_t)1 << 42;  // hi always satisfies the predicate
-    while (lo < hi) {
-      int64_t mid = lo + (hi - lo) / 2;
-      if (lhs < th2 * (double)mid) hi = mid; else lo = mid + 1;
-    }
-    f.T[L] = (double)lo;
-  }
-  return f;
-}
-
 constexpr int kWT = 256;    // threads per block of the walk
 __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_t* __restrict__ order,
                                               const float4* __restrict__ P, const float* __restrict__ ws,
                                               const int32_t* __restrict__ p2, const TNode* __restrict__ nodes,
-                                              FarTable ft, float* __restrict__ y, unsigned long long* nint) {
+                                              float* __restrict__ y, unsigned long long* nint) {
   constexpr int NW = kWT / 64;
   __shared__ int4 win[NW][kWin][4];
   __shared__ float4 lp[NW][64];
@@ -506,6 +514,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_
     }
     wn = ws[j];
   }
+  const float wn2 = 2.0f * wn;
   auto wave_sync = [&]() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -530,20 +539,19 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_
     const int o = t - wb;
     int4 a = win[wv][o][0];
     int4 b = win[wv][o][1];
+    int4 wi = win[wv][o][3];
     bool act = skip <= t;
     bool far = false;
     if (act) {
+      // exact: integers below 2^40, so fused and separate roundings agree
       double d0 = (double)(q[0] - a.x), d1 = (double)(q[1] - a.y), d2 = (double)(q[2] - a.z), d3 = (double)(q[3] - a.w);
-      double D2 = d0 * d0;
-      D2 = D2 + d1 * d1;
-      D2 = D2 + d2 * d2;
-      D2 = D2 + d3 * d3;
-      far = D2 >= ft.T[b.w & 255];
+      double D2 = __builtin_fma(d3, d3, __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0)));
+      double T = __hiloint2double(wi.w, wi.z);
+      far = D2 >= T;
     }
     if (far) {
       int4 xi = win[wv][o][2];
-      int4 wi = win[wv][o][3];
-      interact(yn, xn, wn, __int_as_float(xi.x), __int_as_float(xi.y), __int_as_float(xi.z), __int_as_float(xi.w),
+      interact(yn, xn, wn2, __int_as_float(xi.x), __int_as_float(xi.y), __int_as_float(xi.z), __int_as_float(xi.w),
                __int_as_float(wi.x));
       ++cnt;
       skip = b.x;
@@ -564,7 +572,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_
             for (int32_t i = 0; i < m; ++i) {
               if (base + i == (int32_t)j) continue;
               float4 pi = lp[wv][i];
-              interact(yn, xn, wn, pi.x, pi.y, pi.z, pi.w, lw[wv][i]);
+              interact(yn, xn, wn2, pi.x, pi.y, pi.z, pi.w, lw[wv][i]);
               ++cnt;
             }
           }
@@ -576,7 +584,10 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_
       skip = t + 1;
     }
     int32_t nt = t + 1;
-    if (!__any(skip <= nt)) nt = wave_min(skip);
+    if (!__any(skip <= nt)) {
+      nt = wave_min(skip);
+      if (nt <= t) nt = t + 1;  // every walk mark lies beyond t; keeps the loop advancing
+    }
     t = __builtin_amdgcn_readfirstlane(nt);
   }
   if (valid)
@@ -619,11 +630,11 @@ static void gradient_level(Ctx& C, const Level& L, const float* x, double th2, i
   gw.z = Buf<float>(C.pool, 4 * (size_t)(L.l > 0 ? L.l : 1));
   if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, L.k, gw.z.p);
   VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, L.l, y);
-  build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, s);
+  build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, th2, s);
   unsigned long long* pc = nullptr;
   int ph = prof_begin(C, "walk", 0.0, s, nint ? nullptr : &pc);
   VMO_LAUNCH(k_walk, nblocks(L.k, kWT), kWT, 0, s, L.k, gw.T.n, gw.T.order.p, gw.T.P.p, gw.T.ws.p, gw.T.p2.p,
-             gw.T.nodes.p, far_table(th2), y, nint ? nint : pc);
+             gw.T.nodes.p, y, nint ? nint : pc);
   prof_end(C, ph, s);
 }
 
@@ -1276,7 +1287,7 @@ void tree(Ctx& C, const float* x, const float* w, int32_t k, int32_t cap, int32_
   Buf<uint32_t> box(C.pool, 8);
   box_of(x, k, box.p, s);
   Tree T;
-  build_tree(C, T, x, w, k, cap, box.p, s);
+  build_tree(C, T, x, w, k, cap, box.p, 0.25, s);
   VMO_REQUIRE(T.n <= max_nodes, "max_nodes is too small");
   VMO_LAUNCH(k_tree_out, gsz(T.n), kLT, 0, s, T.n, T.view(), ints, cell2, flt);
   VMO_HIP(hipMemcpyAsync(order, T.order.p, 4 * (size_t)k, hipMemcpyDeviceToDevice, s));

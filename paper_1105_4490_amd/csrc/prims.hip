@@ -207,17 +207,19 @@ template void scan_exclusive<uint64_t>(Ctx&, const uint64_t*, uint64_t*, int64_t
 template void scan_exclusive<U128>(Ctx&, const U128*, U128*, int64_t, U128*, hipStream_t);
 
 // ------------------------------------------------------------ radix sort ----
-constexpr int kRsT = 256, kRsI = 16, kRsTile = kRsT * kRsI;
+// A tile is `ri` rounds of 256 keys; ri is chosen per sort so that large
+// inputs give about 512 tiles (enough blocks to fill the chip).
+constexpr int kRsT = 256, kRsMaxI = 16;
 
 template <class K>
 __global__ __launch_bounds__(kRsT) void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift,
-                                                  int32_t* hist, int ntiles) {
+                                                  int32_t* hist, int ntiles, int ri) {
   __shared__ int cnt[256];
   int t = threadIdx.x;
   cnt[t] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kRsTile;
-  for (int i = 0; i < kRsI; ++i) {
+  int64_t base = (int64_t)blockIdx.x * kRsT * ri;
+  for (int i = 0; i < ri; ++i) {
     int64_t idx = base + i * kRsT + t;
     if (idx < n) atomicAdd(&cnt[(int)((keys[idx] >> shift) & 255u)], 1);
   }
@@ -231,14 +233,15 @@ __global__ __launch_bounds__(kRsT) void k_rs_hist(const K* __restrict__ keys, in
 template <class K>
 __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, const int32_t* __restrict__ vin,
                                                      K* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
-                                                     int shift, const int32_t* __restrict__ offs, int ntiles) {
+                                                     int shift, const int32_t* __restrict__ offs, int ntiles,
+                                                     int ri) {
   __shared__ int run[256];
   __shared__ int wc[4][256];
   int t = threadIdx.x, lane = t & 63, w = t >> 6;
   run[t] = offs[(int64_t)t * ntiles + blockIdx.x];
-  int64_t base = (int64_t)blockIdx.x * kRsTile;
+  int64_t base = (int64_t)blockIdx.x * kRsT * ri;
   const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
-  for (int r = 0; r < kRsI; ++r) {
+  for (int r = 0; r < ri; ++r) {
     wc[0][t] = 0; wc[1][t] = 0; wc[2][t] = 0; wc[3][t] = 0;
     __syncthreads();
     int64_t idx = base + r * kRsT + t;
@@ -272,7 +275,10 @@ template <class K>
 void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t s) {
   if (n <= 1 || bits <= 0) return;
   int passes = (bits + 7) / 8;
-  int ntiles = (int)((n + kRsTile - 1) / kRsTile);
+  int ri = 1;
+  while (ri < kRsMaxI && n > (int64_t)512 * kRsT * ri) ri *= 2;
+  int64_t tile = (int64_t)kRsT * ri;
+  int ntiles = (int)((n + tile - 1) / tile);
   Buf<K> k2(c.pool, n);
   Buf<int32_t> v2(c.pool, vals ? n : 1);
   Buf<int32_t> hist(c.pool, (size_t)256 * ntiles);
@@ -280,9 +286,9 @@ void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t
   int32_t* va = vals; int32_t* vb = vals ? v2.p : nullptr;
   for (int ps = 0; ps < passes; ++ps) {
     int shift = 8 * ps;
-    VMO_LAUNCH((k_rs_hist<K>), ntiles, kRsT, 0, s, ka, n, shift, hist.p, ntiles);
+    VMO_LAUNCH((k_rs_hist<K>), ntiles, kRsT, 0, s, ka, n, shift, hist.p, ntiles, ri);
     scan_exclusive<int32_t>(c, hist.p, hist.p, (int64_t)256 * ntiles, nullptr, s);
-    VMO_LAUNCH((k_rs_scatter<K>), ntiles, kRsT, 0, s, ka, va, kb, vb, n, shift, hist.p, ntiles);
+    VMO_LAUNCH((k_rs_scatter<K>), ntiles, kRsT, 0, s, ka, va, kb, vb, n, shift, hist.p, ntiles, ri);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
