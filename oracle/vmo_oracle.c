@@ -7,8 +7,9 @@
  * library behind include/vmo.h) shares no code, header, table or helper with
  * it.  Everything here is written sequentially, in the order the paper
  * states its steps, with the free choices the paper leaves open fixed as
- * listed below.  Compile with -O2 -ffp-contract=off (no fused multiply-add,
- * so every float and double operation is a single IEEE rounding).
+ * listed below.  Compile with -O2 -ffp-contract=off (no contraction: every
+ * float and double operation is a single IEEE rounding; the few fused
+ * multiply-adds are explicit fmaf calls).
  *
  * Contents (paper passage in brackets):
  *   o_rng             counter-based SplitMix64 (Steele, Lea, Flood 2014).
@@ -817,20 +818,22 @@ int o_tree(int32_t k, const float* x, const float* w, int32_t cap, int32_t* ints
   return n;
 }
 
-/* Interaction of point n with charge W at X: (d-2) W w_n |X-x|^-4 (X-x). */
+/* Interaction of point n with charge W at X: (d-2) W w_n |X-x|^-4 (X-x).
+   The squared distance and the accumulation into y use fused multiply-adds
+   (fmaf: one rounding each), the rest one rounding per operation. */
 static void interact(float* y, const float* xn, float wn, const float* X, float W) {
   float dx[4];
   for (int d = 0; d < 4; ++d) dx[d] = X[d] - xn[d];
   float r2 = dx[0] * dx[0];
-  r2 = r2 + dx[1] * dx[1];
-  r2 = r2 + dx[2] * dx[2];
-  r2 = r2 + dx[3] * dx[3];
+  r2 = fmaf(dx[1], dx[1], r2);
+  r2 = fmaf(dx[2], dx[2], r2);
+  r2 = fmaf(dx[3], dx[3], r2);
   if (!(r2 > 0.0f)) return;
   float num = 2.0f * W;
   num = num * wn;
   float den = r2 * r2;
   float f = num / den;
-  for (int d = 0; d < 4; ++d) y[d] = y[d] + f * dx[d];
+  for (int d = 0; d < 4; ++d) y[d] = fmaf(f, dx[d], y[d]);
 }
 
 static int node_far(const OTNode* N, const int32_t* p2, double th2) {
@@ -858,6 +861,27 @@ static void walk_rec(const OTree* T, int32_t t, int32_t n, const float* xn, floa
     float xv[4];
     for (int d = 0; d < 4; ++d) xv[d] = x[(size_t)d * T->k + v];
     interact(y, xn, wn, xv, w[v]);
+  }
+}
+
+/* Repulsion of point n, added to yn.  The walk's interactions are summed in
+   parts: the walk over the subtree of each child of the root starts from
+   zero, and these partial sums are added to yn in child order.  A root that
+   is far or a leaf forms the single part.  (The paper fixes no summation
+   order; this one lets the parts be computed independently.) */
+static void repulsion(const OTree* T, int32_t n, const float* xn, float wn, const int32_t* p2, double th2,
+                      const float* x, const float* w, float* yn) {
+  const OTNode* R = &T->nd[0];
+  if (R->leaf || node_far(R, p2, th2)) {
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    walk_rec(T, 0, n, xn, wn, p2, th2, x, w, acc);
+    for (int d = 0; d < 4; ++d) yn[d] = yn[d] + acc[d];
+    return;
+  }
+  for (int32_t ch = 1; ch != R->next; ch = T->nd[ch].next) {
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    walk_rec(T, ch, n, xn, wn, p2, th2, x, w, acc);
+    for (int d = 0; d < 4; ++d) yn[d] = yn[d] + acc[d];
   }
 }
 
@@ -906,7 +930,7 @@ static int gradient(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pin
       yn[d] = y[(size_t)d * k + n];
       p2[d] = 2 * (int32_t)T.kq[(size_t)d * k + n] + 1;
     }
-    walk_rec(&T, 0, n, xn, w[n], p2, th2, x, w, yn);
+    repulsion(&T, n, xn, w[n], p2, th2, x, w, yn);
     for (int d = 0; d < 4; ++d) y[(size_t)d * k + n] = yn[d];
   }
   otree_free(&T);
@@ -1201,7 +1225,7 @@ int o_gradient_sample(int32_t k, int32_t l, const int64_t* ptr, const int32_t* p
       xn[d] = x[(size_t)d * k + n];
       p2[d] = 2 * (int32_t)T.kq[(size_t)d * k + n] + 1;
     }
-    walk_rec(&T, 0, n, xn, w[n], p2, th2, x, w, yn);
+    repulsion(&T, n, xn, w[n], p2, th2, x, w, yn);
     for (int d = 0; d < 4; ++d) y[(size_t)d * ns + s] = yn[d];
     if (nint) { g_walk_count = 0; walk_count_rec(&T, 0, n, p2, th2); nint[s] = g_walk_count; }
   }

@@ -32,6 +32,7 @@ void layout_steps(Ctx& c, const vmo_hypergraph* h, const vmo_layout_params* p, f
     VMO_HIP(hipSetDevice(C.device));
 
 #define API_END                                                   \
+    vmo::check_device_flag(C, S);                                 \
     vmo::prof_flush(C);                                           \
   }                                                               \
   catch (vmo::Error & e) {                                        \

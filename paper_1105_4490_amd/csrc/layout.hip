@@ -152,12 +152,11 @@ __global__ void k_tree_points(const float* x, const float* w, int32_t k, const u
 
 constexpr int kCplB = 256;
 // cpl[i] = number of leading equal digits of keys i-1 and i (16 if equal);
-// cpl[0] = cpl[k] = -1.  bmin = minimum per block of 256 positions.
-__global__ __launch_bounds__(kCplB) void k_cpl(const uint64_t* key, int32_t k, int8_t* cpl, int8_t* bmin) {
-  __shared__ int sm[kCplB];
+// cpl[0] = cpl[k] = -1.
+__global__ __launch_bounds__(kCplB) void k_cpl(const uint64_t* key, int32_t k, int8_t* cpl) {
   int64_t i = (int64_t)blockIdx.x * kCplB + threadIdx.x;
-  int c = 127;
   if (i <= k) {
+    int c;
     if (i == 0 || i == k) c = -1;
     else {
       uint64_t d = key[i - 1] ^ key[i];
@@ -165,30 +164,30 @@ __global__ __launch_bounds__(kCplB) void k_cpl(const uint64_t* key, int32_t k, i
     }
     cpl[i] = (int8_t)c;
   }
-  sm[threadIdx.x] = c;
-  __syncthreads();
-  for (int off = kCplB / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sm[threadIdx.x] = min(sm[threadIdx.x], sm[threadIdx.x + off]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) bmin[blockIdx.x] = (int8_t)sm[0];
 }
 
-// First j > i with cpl[j] < L (exists: cpl[k] = -1).
-__device__ int32_t nsv(const int8_t* cpl, const int8_t* bmin, int32_t k, int32_t i, int L) {
-  int32_t j = i + 1;
-  int32_t bend = ((j / kCplB) + 1) * kCplB;
-  for (; j < bend && j <= k; ++j)
-    if (cpl[j] < L) return j;
-  int32_t nb = k / kCplB + 1;
-  for (int32_t b = j / kCplB; b < nb; ++b) {
-    if (bmin[b] < L) {
-      int32_t e = min(k + 1, (b + 1) * kCplB);
-      for (int32_t t = b * kCplB; t < e; ++t)
-        if (cpl[t] < L) return t;
-    }
+// End of the node of depth L beginning at position i: the first j > i whose
+// key differs from key[i] in its first L digits (keys are sorted, so these
+// positions form a suffix), found by doubling then bisection.
+__device__ int32_t node_end(const uint64_t* key, int32_t k, int32_t i, int L) {
+  if (L == 0) return k;
+  const int sh = 64 - 4 * L;
+  const uint64_t pre = key[i] >> sh;
+  int32_t lo = i;  // key[lo] has the prefix
+  int64_t step = 1;
+  int32_t hi;
+  while (true) {
+    int64_t h = lo + step;
+    if (h >= k) { hi = k; break; }
+    if ((key[h] >> sh) != pre) { hi = (int32_t)h; break; }
+    lo = (int32_t)h;
+    step <<= 1;
   }
-  return k;
+  while (hi - lo > 1) {
+    int32_t mid = lo + (hi - lo) / 2;
+    if ((key[mid] >> sh) == pre) lo = mid; else hi = mid;
+  }
+  return hi;
 }
 
 // Depth of the leaf holding point i: the smallest L whose run (the maximal
@@ -258,11 +257,12 @@ struct NodeView {
   int32_t* parent;
   int32_t* nch;
   int32_t* ctr;
+  int32_t* cid;  // [n][16] children in order (a cell has at most 16 sub-cells)
 };
 
 // Nodes in pre-order: index = base[i] + (L - cpl[i] - 1) for the node of
 // depth L beginning at point i; next = first node beginning at its end.
-__global__ void k_tree_nodes(const int8_t* cpl, const int8_t* bmin, const int8_t* ell, const int32_t* base,
+__global__ void k_tree_nodes(const int8_t* cpl, const uint64_t* key, const int8_t* ell, const int32_t* base,
                              const int32_t* p2, int32_t k, FarTable ft, NodeView nd) {
   GRID_STRIDE(i64, k) {
     int32_t i = (int32_t)i64;
@@ -270,7 +270,7 @@ __global__ void k_tree_nodes(const int8_t* cpl, const int8_t* bmin, const int8_t
     if (li < ci + 1) continue;
     for (int L = ci + 1; L <= li; ++L) {
       int32_t t = base[i] + (L - ci - 1);
-      int32_t end = nsv(cpl, bmin, k, i, L);
+      int32_t end = node_end(key, k, i, L);
       int side = 1 << (16 - L);
       int4 cc;
       int kq0 = (p2[i] - 1) >> 1, kq1 = (p2[(int64_t)k + i] - 1) >> 1;
@@ -297,6 +297,7 @@ __global__ void k_tree_links(int32_t n, NodeView nd) {
       int32_t ch = t + 1;
       while (ch != b.x) {
         nd.parent[ch] = t;
+        if (cnt < 16) nd.cid[16 * (int64_t)t + cnt] = ch;  // a cell has at most 16 sub-cells
         ++cnt;
         ch = nd.t[ch].b.x;
       }
@@ -335,11 +336,29 @@ __global__ void k_tree_moments(int32_t n, int32_t k, const float* xs, const floa
       if (old != nd.nch[p] - 1) break;
       __threadfence();
       double W2 = 0.0, S2[4] = {0.0, 0.0, 0.0, 0.0};
-      int32_t nx = nd.t[p].b.x;
-      for (int32_t ch = p + 1; ch != nx; ch = nd.t[ch].b.x) {
-        W2 += __hip_atomic_load(&nd.Wd[ch], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int d = 0; d < 4; ++d)
-          S2[d] += __hip_atomic_load(&nd.Sd[4 * (int64_t)ch + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int32_t nc = nd.nch[p];
+      const int4* cq = reinterpret_cast<const int4*>(nd.cid + 16 * (int64_t)p);
+      for (int32_t r0 = 0; r0 < nc; r0 += 4) {
+        // four children per round: their loads are issued together, the sums
+        // stay in child order
+        const int4 c4 = cq[r0 >> 2];
+        const int32_t cc[4] = {c4.x, c4.y, c4.z, c4.w};
+        double wv[4], sv[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (r0 + u < nc) {
+            wv[u] = __hip_atomic_load(&nd.Wd[cc[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int d = 0; d < 4; ++d)
+              sv[u][d] = __hip_atomic_load(&nd.Sd[4 * (int64_t)cc[u] + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (r0 + u < nc) {
+            W2 += wv[u];
+            for (int d = 0; d < 4; ++d) S2[d] += sv[u][d];
+          }
+        }
       }
       node_finish(nd, p, W2, S2);
       cur = p;
@@ -352,15 +371,15 @@ struct Tree {
   Buf<uint64_t> key;
   Buf<int32_t> order, p2, nn;
   Buf<float> xs, ws;
-  Buf<int8_t> cpl, bmin, ell;
+  Buf<int8_t> cpl, ell;
   Buf<TNode> nodes;
   Buf<float4> P;  // points in tree order
   Buf<double> Wd, Sd;
-  Buf<int32_t> parent, nch, ctr;
+  Buf<int32_t> parent, nch, ctr, cid;
   NodeView view() {
     NodeView v;
     v.t = nodes.p; v.Wd = Wd.p; v.Sd = Sd.p;
-    v.parent = parent.p; v.nch = nch.p; v.ctr = ctr.p;
+    v.parent = parent.p; v.nch = nch.p; v.ctr = ctr.p; v.cid = cid.p;
     return v;
   }
 };
@@ -380,8 +399,7 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
   VMO_LAUNCH(k_tree_points, gsz(k), kLT, 0, s, x, w, k, dbox, T.order.p, T.xs.p, T.ws.p, T.p2.p, T.P.p);
   int32_t nb = k / kCplB + 1;
   T.cpl = Buf<int8_t>(C.pool, (size_t)nb * kCplB);
-  T.bmin = Buf<int8_t>(C.pool, nb);
-  VMO_LAUNCH(k_cpl, nb, kCplB, 0, s, T.key.p, k, T.cpl.p, T.bmin.p);
+  VMO_LAUNCH(k_cpl, nb, kCplB, 0, s, T.key.p, k, T.cpl.p);
   T.ell = Buf<int8_t>(C.pool, k + 1);
   T.nn = Buf<int32_t>(C.pool, (size_t)k + 1);
   VMO_LAUNCH(k_tree_ell, gsz((int64_t)k + 1), kLT, 0, s, T.cpl.p, k, cap, T.ell.p, T.nn.p);
@@ -394,8 +412,9 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
   T.parent = Buf<int32_t>(C.pool, n);
   T.nch = Buf<int32_t>(C.pool, n);
   T.ctr = Buf<int32_t>(C.pool, n);
+  T.cid = Buf<int32_t>(C.pool, 16 * (size_t)n);
   NodeView nd = T.view();
-  VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.bmin.p, T.ell.p, T.nn.p, T.p2.p, k, far_table(th2), nd);
+  VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.key.p, T.ell.p, T.nn.p, T.p2.p, k, far_table(th2), nd);
   VMO_LAUNCH(k_tree_links, gsz(n), kLT, 0, s, n, nd);
   VMO_LAUNCH(k_tree_moments, gsz(n), kLT, 0, s, n, k, T.xs.p, T.ws.p, nd);
 }
@@ -444,22 +463,23 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
   }
 }
 
-// (d-2) W w_n |X - x|^-4 (X - x), d = 4, operation by operation.
+// (d-2) W w_n |X - x|^-4 (X - x), d = 4, operation by operation; the squared
+// distance and the accumulation are fused multiply-adds (one rounding each).
 __device__ __forceinline__ void interact(float* y, const float* xn, float wn2, float X0, float X1, float X2, float X3,
                                          float W) {
   float dx0 = X0 - xn[0], dx1 = X1 - xn[1], dx2 = X2 - xn[2], dx3 = X3 - xn[3];
   float r2 = dx0 * dx0;
-  r2 = r2 + dx1 * dx1;
-  r2 = r2 + dx2 * dx2;
-  r2 = r2 + dx3 * dx3;
+  r2 = __builtin_fmaf(dx1, dx1, r2);
+  r2 = __builtin_fmaf(dx2, dx2, r2);
+  r2 = __builtin_fmaf(dx3, dx3, r2);
   if (!(r2 > 0.0f)) return;
   float num = W * wn2;  // (2 W) w_n = W (2 w_n) exactly
   float den = r2 * r2;
   float f = num / den;
-  y[0] = y[0] + f * dx0;
-  y[1] = y[1] + f * dx1;
-  y[2] = y[2] + f * dx2;
-  y[3] = y[3] + f * dx3;
+  y[0] = __builtin_fmaf(f, dx0, y[0]);
+  y[1] = __builtin_fmaf(f, dx1, y[1]);
+  y[2] = __builtin_fmaf(f, dx2, y[2]);
+  y[3] = __builtin_fmaf(f, dx3, y[3]);
 }
 
 // Minimum over the 64 lanes (all active), by DPP row shifts and row
@@ -478,40 +498,51 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // and the walk jumps to its sibling link; a near internal node is entered; a
 // near leaf acts point by point.  One lane per point, points in tree order.
 //
-// The 64 lanes of a wavefront step through the nodes in pre-order together:
-// node t is read once for the wave, and a lane takes part only if its own
-// walk reaches t (t >= its skip mark).  Every jump of a single walk moves
-// forward in pre-order, so each lane performs exactly the interactions of its
-// own walk, in the same order.  The wave moves to t + 1 while some lane is
-// still descending, else to the smallest skip mark.  Nodes are staged through
-// a per-wavefront LDS window of 64 consecutive nodes (one 64-byte node per
-// lane per refill).
+// The walk of a point is split into parts that run as separate wavefronts:
+// the root is near every point it holds (for theta < 1), so the walk is the
+// concatenation of the walks over the root's children; part s is the walk
+// over child s, summed from zero.  The parts are added in child order by
+// k_combine.  A root that is a leaf, or far from the point, gives one part.
+//
+// The 64 lanes of a wavefront step through the nodes of their part in
+// pre-order together: node t is read once for the wave, and a lane takes
+// part only if its own walk reaches t (t >= its skip mark).  Every jump of a
+// single walk moves forward in pre-order, so each lane performs exactly the
+// interactions of its own walk, in the same order.  The wave moves to t + 1
+// while some lane is still descending, else to the smallest skip mark.
+// Nodes are staged through a per-wavefront LDS window of 64 consecutive nodes
+// (one 64-byte node per lane per refill), and the points of near leaves
+// through a second window of 64 consecutive points: the walk meets leaves in
+// tree order, so one refill serves several leaves.
 constexpr int kWin = 64;
 constexpr int kWT = 256;    // threads per block of the walk
-__global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_t* __restrict__ order,
-                                              const float4* __restrict__ P, const float* __restrict__ ws,
-                                              const int32_t* __restrict__ p2, const TNode* __restrict__ nodes,
-                                              float* __restrict__ y, unsigned long long* nint) {
+constexpr int kParts = 16;  // at most 16 children of the root
+__global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const float4* __restrict__ P,
+                                              const float* __restrict__ ws, const int32_t* __restrict__ p2,
+                                              const TNode* __restrict__ nodes, const int32_t* __restrict__ root_cid,
+                                              const int32_t* __restrict__ root_nch, float* __restrict__ part,
+                                              int32_t* __restrict__ nparts_out, unsigned long long* nint) {
   constexpr int NW = kWT / 64;
   __shared__ int4 win[NW][kWin][4];
-  __shared__ float4 lp[NW][64];
-  __shared__ float lw[NW][64];
+  __shared__ float4 lp[NW][kWin];
+  __shared__ float lw[NW][kWin];
+  const int seg = blockIdx.y;
+  const int4 rb = nodes[0].b;
+  const bool rleaf = (rb.w >> 8) & 1;
+  const int nparts = rleaf ? 1 : *root_nch;
+  if (seg >= nparts) return;  // the whole block
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool valid = j < k;
+  // interactions of the wavefront (uniform: counted from lane masks)
   unsigned long long cnt = 0;
   float xn[4] = {0.f, 0.f, 0.f, 0.f}, yn[4] = {0.f, 0.f, 0.f, 0.f};
   int32_t q[4] = {0, 0, 0, 0};
   float wn = 0.0f;
-  int32_t v = 0;
   if (valid) {
-    v = order[j];
     float4 pj = P[j];
     xn[0] = pj.x; xn[1] = pj.y; xn[2] = pj.z; xn[3] = pj.w;
-    for (int d = 0; d < 4; ++d) {
-      q[d] = p2[(int64_t)d * k + j];
-      yn[d] = y[(int64_t)d * k + v];
-    }
+    for (int d = 0; d < 4; ++d) q[d] = p2[(int64_t)d * k + j];
     wn = ws[j];
   }
   const float wn2 = 2.0f * wn;
@@ -520,10 +551,33 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  int32_t skip = valid ? 0 : 0x7fffffff;
+  auto far_from = [&](const int4& a, double T) {
+    // exact: integers below 2^40, so fused and separate roundings agree
+    double d0 = (double)(q[0] - a.x), d1 = (double)(q[1] - a.y), d2 = (double)(q[2] - a.z), d3 = (double)(q[3] - a.w);
+    double D2 = __builtin_fma(d3, d3, __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0)));
+    return D2 >= T;
+  };
+  // a root far from the point: its single interaction is part 0
+  bool rootfar = false;
+  if (valid) rootfar = far_from(nodes[0].a, nodes[0].T);
+  if (seg == 0 && rootfar) {
+    const float4 X = nodes[0].X;
+    interact(yn, xn, wn2, X.x, X.y, X.z, X.w, nodes[0].W);
+  }
+  if (seg == 0) cnt += (unsigned long long)__popcll(__ballot(rootfar));
+  int32_t t1 = n;
+  int32_t skip = 0x7fffffff;
+  if (rleaf) {
+    if (valid && !rootfar) skip = 0;
+  } else {
+    const int32_t t0 = root_cid[seg];
+    t1 = nodes[t0].b.x;
+    if (valid && !rootfar) skip = t0;
+  }
   int32_t t = __builtin_amdgcn_readfirstlane(wave_min(skip));
-  int32_t wb = -2 * kWin;
-  while (t < n) {
+  int32_t wb = -2 * kWin;  // node window: nodes [wb, wb + 64)
+  int32_t pb = -2 * kWin;  // point window: points [pb, pb + 64) in tree order
+  while (t < t1) {
     if (t < wb || t >= wb + kWin) {
       wb = t;
       int32_t tt = t + lane;
@@ -541,42 +595,41 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_
     int4 b = win[wv][o][1];
     int4 wi = win[wv][o][3];
     bool act = skip <= t;
-    bool far = false;
-    if (act) {
-      // exact: integers below 2^40, so fused and separate roundings agree
-      double d0 = (double)(q[0] - a.x), d1 = (double)(q[1] - a.y), d2 = (double)(q[2] - a.z), d3 = (double)(q[3] - a.w);
-      double D2 = __builtin_fma(d3, d3, __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0)));
-      double T = __hiloint2double(wi.w, wi.z);
-      far = D2 >= T;
-    }
+    bool far = act && far_from(a, __hiloint2double(wi.w, wi.z));
     if (far) {
       int4 xi = win[wv][o][2];
       interact(yn, xn, wn2, __int_as_float(xi.x), __int_as_float(xi.y), __int_as_float(xi.z), __int_as_float(xi.w),
                __int_as_float(wi.x));
-      ++cnt;
       skip = b.x;
     }
+    cnt += (unsigned long long)__popcll(__ballot(far));
     bool near = act && !far;
     if ((b.w >> 8) & 1) {
       if (__any(near)) {
-        int32_t f0 = b.y, f1 = b.y + b.z;
-        for (int32_t base = f0; base < f1; base += 64) {
-          int32_t ii = base + lane;
-          if (ii < f1) {
-            lp[wv][lane] = P[ii];
-            lw[wv][lane] = ws[ii];
+        const int32_t f1 = b.y + b.z;
+        for (int32_t base = b.y; base < f1; base += kWin) {
+          const int32_t e = f1 - base < kWin ? f1 : base + kWin;
+          if (base < pb || e > pb + kWin) {
+            // slide the point window to start at this leaf
+            wave_sync();
+            pb = base;
+            const int32_t ii = base + lane;
+            if (ii < k) {
+              lp[wv][lane] = P[ii];
+              lw[wv][lane] = ws[ii];
+            }
+            wave_sync();
           }
-          wave_sync();
-          int32_t m = f1 - base < 64 ? f1 - base : 64;
+          const int32_t m = e - base, o2 = base - pb;
           if (near) {
             for (int32_t i = 0; i < m; ++i) {
               if (base + i == (int32_t)j) continue;
-              float4 pi = lp[wv][i];
-              interact(yn, xn, wn2, pi.x, pi.y, pi.z, pi.w, lw[wv][i]);
-              ++cnt;
+              float4 pi = lp[wv][o2 + i];
+              interact(yn, xn, wn2, pi.x, pi.y, pi.z, pi.w, lw[wv][o2 + i]);
             }
           }
-          wave_sync();
+          cnt += (unsigned long long)m * __popcll(__ballot(near)) -
+                 __popcll(__ballot(near && j >= base && j < base + m));
         }
       }
       if (near) skip = b.x;
@@ -590,52 +643,76 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const int32_
     }
     t = __builtin_amdgcn_readfirstlane(nt);
   }
-  if (valid)
-    for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yn[d];
+  if (valid) {
+    for (int d = 0; d < 4; ++d) part[((int64_t)seg * 4 + d) * k + j] = yn[d];
+    if (seg == 0) nparts_out[j] = rootfar ? 1 : nparts;
+  }
   if (nint) {
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nint, cnt);
   }
 }
 
-// x_n <- x_n - (alpha / |y_n|) y_n.
-__global__ void k_step(int32_t k, const float* y, float* x, double alpha) {
-  GRID_STRIDE(v, k) {
-    float y0 = y[v], y1 = y[(int64_t)k + v], y2 = y[2 * (int64_t)k + v], y3 = y[3 * (int64_t)k + v];
-    float n2 = y0 * y0;
-    n2 = n2 + y1 * y1;
-    n2 = n2 + y2 * y2;
-    n2 = n2 + y3 * y3;
+// y_v = attraction + the walk's parts in order (point j in tree order is
+// vertex order[j]).  xmove == NULL: y receives the gradient; else the descent
+// step of Algorithm 3 is applied to xmove: x_v <- x_v - (alpha / |y_v|) y_v.
+__global__ void k_combine(int32_t k, const int32_t* __restrict__ order, const float* __restrict__ part,
+                          const int32_t* __restrict__ nparts, float* y, float* xmove, double alpha) {
+  GRID_STRIDE(j, k) {
+    const int32_t v = order[j];
+    float yv[4];
+    for (int d = 0; d < 4; ++d) yv[d] = y[(int64_t)d * k + v];
+    const int np = nparts[j];
+    for (int s2 = 0; s2 < np; ++s2)
+      for (int d = 0; d < 4; ++d) yv[d] = yv[d] + part[((int64_t)s2 * 4 + d) * k + j];
+    if (!xmove) {
+      for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yv[d];
+      continue;
+    }
+    float n2 = yv[0] * yv[0];
+    n2 = n2 + yv[1] * yv[1];
+    n2 = n2 + yv[2] * yv[2];
+    n2 = n2 + yv[3] * yv[3];
     if (!(n2 > 0.0f)) continue;
     float f = (float)(alpha / sqrt((double)n2));
-    float t0 = f * y0, t1 = f * y1, t2 = f * y2, t3 = f * y3;
-    x[v] = x[v] - t0;
-    x[(int64_t)k + v] = x[(int64_t)k + v] - t1;
-    x[2 * (int64_t)k + v] = x[2 * (int64_t)k + v] - t2;
-    x[3 * (int64_t)k + v] = x[3 * (int64_t)k + v] - t3;
+    for (int d = 0; d < 4; ++d) {
+      float td = f * yv[d];
+      xmove[(int64_t)d * k + v] = xmove[(int64_t)d * k + v] - td;
+    }
   }
 }
 
 struct GradWork {
   Buf<float> z;
   Buf<uint32_t> box;
+  Buf<float> part;      // [kParts][4][k] partial repulsions, tree order
+  Buf<int32_t> nparts;  // [k] parts of each point's walk
   Tree T;
 };
 
-// y = gradient of eq. (6) at x (attraction + tree repulsion); box of x in gw.box.
-static void gradient_level(Ctx& C, const Level& L, const float* x, double th2, int32_t cap, float* y, GradWork& gw,
-                           unsigned long long* nint, hipStream_t s) {
+// Attraction into y, net centres, box of x (gw.box) and the tree of x.
+static void gradient_prepare(Ctx& C, const Level& L, const float* x, double th2, int32_t cap, float* y, GradWork& gw,
+                             hipStream_t s) {
   if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
   box_of(x, L.k, gw.box.p, s);
   gw.z = Buf<float>(C.pool, 4 * (size_t)(L.l > 0 ? L.l : 1));
   if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, L.k, gw.z.p);
   VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, L.l, y);
   build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, th2, s);
+}
+
+// Repulsion by the tree walk, added to the attraction in y.  xmove == NULL:
+// y receives the gradient of eq. (6); else the descent step of length alpha
+// is applied to xmove (the layout being descended) and y is left as is.
+static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double alpha, GradWork& gw,
+                          unsigned long long* nint, hipStream_t s) {
+  if (gw.part.n < (size_t)kParts * 4 * L.k) gw.part = Buf<float>(C.pool, (size_t)kParts * 4 * L.k);
+  if (gw.nparts.n < (size_t)L.k) gw.nparts = Buf<int32_t>(C.pool, L.k);
   unsigned long long* pc = nullptr;
   int ph = prof_begin(C, "walk", 0.0, s, nint ? nullptr : &pc);
-  VMO_LAUNCH(k_walk, nblocks(L.k, kWT), kWT, 0, s, L.k, gw.T.n, gw.T.order.p, gw.T.P.p, gw.T.ws.p, gw.T.p2.p,
-             gw.T.nodes.p, y, nint ? nint : pc);
+  VMO_LAUNCH(k_walk, dim3(nblocks(L.k, kWT), kParts), kWT, 0, s, L.k, gw.T.n, gw.T.P.p, gw.T.ws.p, gw.T.p2.p,
+             gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p, gw.part.p, gw.nparts.p, nint ? nint : pc);
   prof_end(C, ph, s);
+  VMO_LAUNCH(k_combine, gsz(L.k), kLT, 0, s, L.k, gw.T.order.p, gw.part.p, gw.nparts.p, y, xmove, alpha);
 }
 
 // One descent step (Algorithm 3).  alpha: step length (host); at it == 0 it
@@ -643,7 +720,7 @@ static void gradient_level(Ctx& C, const Level& L, const float* x, double th2, i
 static void descent_step(Ctx& C, const Level& L, float* x, const vmo_layout_params* p, int32_t it, double* alpha,
                          float* y, GradWork& gw, hipStream_t s) {
   double th2 = (double)p->theta * (double)p->theta;
-  gradient_level(C, L, x, th2, p->leaf_cap, y, gw, nullptr, s);
+  gradient_prepare(C, L, x, th2, p->leaf_cap, y, gw, s);
   if (it == 0) {
     HostBox hb = read_box(gw.box.p, s);
     double V = 1.0, ext = 0.0;
@@ -657,7 +734,7 @@ static void descent_step(Ctx& C, const Level& L, float* x, const vmo_layout_para
   } else {
     *alpha = *alpha * (double)p->decay;
   }
-  VMO_LAUNCH(k_step, gsz(L.k), kLT, 0, s, L.k, y, x, *alpha);
+  gradient_walk(C, L, y, x, *alpha, gw, nullptr, s);
 }
 
 // ================================================================ coarsen ===
@@ -1305,7 +1382,8 @@ void gradient(Ctx& C, const vmo_hypergraph* h, const float* x, float theta, int3
   GradWork gw;
   Buf<unsigned long long> cnt(C.pool, 1);
   VMO_HIP(hipMemsetAsync(cnt.p, 0, 8, s));
-  gradient_level(C, L, x, (double)theta * (double)theta, cap, y, gw, cnt.p, s);
+  gradient_prepare(C, L, x, (double)theta * (double)theta, cap, y, gw, s);
+  gradient_walk(C, L, y, nullptr, 0.0, gw, cnt.p, s);
   if (z && L.l > 0) VMO_HIP(hipMemcpyAsync(z, gw.z.p, 16 * (size_t)L.l, hipMemcpyDeviceToDevice, s));
   unsigned long long c = read1(cnt.p, s);
   if (nint) *nint = (int64_t)c;

@@ -59,6 +59,7 @@ Pool::~Pool() {
 Ctx::~Ctx() {
   prof_discard(*this);
   if (prof.dcnt) (void)hipFree(prof.dcnt);
+  if (dflag) (void)hipFree(dflag);
 }
 
 int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned long long** dwork) {
@@ -207,63 +208,127 @@ template void scan_exclusive<uint64_t>(Ctx&, const uint64_t*, uint64_t*, int64_t
 template void scan_exclusive<U128>(Ctx&, const U128*, U128*, int64_t, U128*, hipStream_t);
 
 // ------------------------------------------------------------ radix sort ----
-// A tile is `ri` rounds of 256 keys; ri is chosen per sort so that large
-// inputs give about 512 tiles (enough blocks to fill the chip).
+// LSD radix sort, 8-bit digits, one histogram launch for all digit positions
+// and one scatter launch per digit.  A scatter block takes the next tile in
+// start order (an atomic counter), counts its digits, publishes the counts,
+// and finds the keys of its digits in earlier tiles by looking back over the
+// published words of those tiles (decoupled look-back): a word is 0 (not
+// ready), an aggregate of that tile alone, or an inclusive prefix.  Earlier
+// tiles belong to blocks that already run, so every wait ends; the wait is
+// still bounded, and a bound that runs out sets the context's device error
+// flag.  A tile is `ri` rounds of 256 keys, ri chosen so that large inputs
+// give about 512 tiles.
 constexpr int kRsT = 256, kRsMaxI = 16;
+constexpr uint64_t kStA = 1ull << 62, kStP = 2ull << 62, kStMask = (1ull << 62) - 1;
+constexpr int kSpinLimit = 1 << 24;
 
 template <class K>
-__global__ __launch_bounds__(kRsT) void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift,
-                                                  int32_t* hist, int ntiles, int ri) {
-  __shared__ int cnt[256];
-  int t = threadIdx.x;
-  cnt[t] = 0;
+__global__ __launch_bounds__(kRsT) void k_rs_hist(const K* __restrict__ keys, int64_t n, int passes,
+                                                  uint32_t* ghist) {
+  __shared__ uint32_t h[8][256];
+  const int t = threadIdx.x;
+  for (int p = 0; p < 8; ++p) h[p][t] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kRsT * ri;
-  for (int i = 0; i < ri; ++i) {
-    int64_t idx = base + i * kRsT + t;
-    if (idx < n) atomicAdd(&cnt[(int)((keys[idx] >> shift) & 255u)], 1);
+  for (int64_t i = (int64_t)blockIdx.x * kRsT + t; i < n; i += (int64_t)gridDim.x * kRsT) {
+    const K key = keys[i];
+    for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(int)((key >> (8 * p)) & 255u)], 1u);
   }
   __syncthreads();
-  hist[(int64_t)t * ntiles + blockIdx.x] = cnt[t];
+  for (int p = 0; p < passes; ++p)
+    if (h[p][t]) atomicAdd(&ghist[p * 256 + t], h[p][t]);
 }
 
-// Stable scatter: keys of one tile are ranked in their original order; within
-// a round of 256 keys, lanes of a wave with equal digits are found with eight
-// ballots, waves are ordered through LDS.
 template <class K>
 __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, const int32_t* __restrict__ vin,
                                                      K* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
-                                                     int shift, const int32_t* __restrict__ offs, int ntiles,
-                                                     int ri) {
+                                                     int shift, int ri, const uint32_t* __restrict__ ghist,
+                                                     uint64_t* status, uint32_t* tile_ctr, int* err) {
   __shared__ int run[256];
+  __shared__ int cnt[256];
   __shared__ int wc[4][256];
-  int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  run[t] = offs[(int64_t)t * ntiles + blockIdx.x];
-  int64_t base = (int64_t)blockIdx.x * kRsT * ri;
+  __shared__ uint32_t scan[256];
+  __shared__ int tile_sh;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t == 0) tile_sh = (int)atomicAdd(tile_ctr, 1u);
+  cnt[t] = 0;
+  __syncthreads();
+  const int64_t tile = tile_sh;
+  const int64_t base = tile * kRsT * ri;
+  K key[kRsMaxI];
+  int dig[kRsMaxI];
+#pragma unroll
+  for (int r = 0; r < kRsMaxI; ++r) {
+    const int64_t idx = base + (int64_t)r * kRsT + t;
+    const bool valid = r < ri && idx < n;
+    key[r] = valid ? kin[idx] : K(0);
+    dig[r] = valid ? (int)((key[r] >> shift) & 255u) : -1;
+    if (valid) atomicAdd(&cnt[dig[r]], 1);
+  }
+  __syncthreads();
+  // publish this tile's count of digit t, then look back for the keys of
+  // digit t in earlier tiles
+  const int c = cnt[t];
+  uint64_t* st = status + tile * 256 + t;
+  uint64_t excl = 0;
+  if (tile == 0) {
+    __hip_atomic_store(st, kStP | (uint64_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(st, kStA | (uint64_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int64_t pt = tile - 1;
+    int spins = 0;
+    while (true) {
+      const uint64_t v = __hip_atomic_load(status + pt * 256 + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t f = v & ~kStMask;
+      if (f == 0) {
+        if (++spins > kSpinLimit) {
+          atomicExch(err, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += v & kStMask;
+      if (f == kStP || pt == 0) break;
+      --pt;
+    }
+    __hip_atomic_store(st, kStP | (excl + (uint64_t)c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // exclusive scan of the digit totals of this pass
+  scan[t] = ghist[t];
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t a = t >= off ? scan[t - off] : 0u;
+    __syncthreads();
+    scan[t] += a;
+    __syncthreads();
+  }
+  run[t] = (int)((t > 0 ? scan[t - 1] : 0u) + excl);
   const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
-  for (int r = 0; r < ri; ++r) {
+  // stable ranks: rounds in order; in a round, waves in order, lanes with the
+  // same digit found by eight ballots
+#pragma unroll
+  for (int r = 0; r < kRsMaxI; ++r) {
+    if (r >= ri) break;
     wc[0][t] = 0; wc[1][t] = 0; wc[2][t] = 0; wc[3][t] = 0;
     __syncthreads();
-    int64_t idx = base + r * kRsT + t;
-    bool valid = idx < n;
-    K key = valid ? kin[idx] : K(0);
-    int dig = (int)((key >> shift) & 255u);
+    const bool valid = dig[r] >= 0;
+    const int d = valid ? dig[r] : 0;
     uint64_t m = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      bool bit = (dig >> b) & 1;
-      uint64_t bb = __ballot(valid && bit);
+      const bool bit = (d >> b) & 1;
+      const uint64_t bb = __ballot(valid && bit);
       m &= bit ? bb : ~bb;
     }
-    int rank = __popcll(m & below);
-    if (valid && rank == 0) wc[w][dig] = __popcll(m);
+    const int rank = __popcll(m & below);
+    if (valid && rank == 0) wc[w][d] = __popcll(m);
     __syncthreads();
     if (valid) {
-      int off = run[dig];
-      for (int ww = 0; ww < w; ++ww) off += wc[ww][dig];
-      int dest = off + rank;
-      kout[dest] = key;
-      if (vin) vout[dest] = vin[idx];
+      int off = run[d];
+      for (int ww = 0; ww < w; ++ww) off += wc[ww][d];
+      const int dest = off + rank;
+      kout[dest] = key[r];
+      if (vin) vout[dest] = vin[base + (int64_t)r * kRsT + t];
     }
     __syncthreads();
     run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
@@ -271,24 +336,51 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
   }
 }
 
+int* device_flag(Ctx& c) {
+  if (!c.dflag) {
+    VMO_HIP(hipMalloc(&c.dflag, sizeof(int)));
+    VMO_HIP(hipMemset(c.dflag, 0, sizeof(int)));
+  }
+  return c.dflag;
+}
+
+void check_device_flag(Ctx& c, hipStream_t s) {
+  if (!c.dflag) return;
+  int v = 0;
+  VMO_HIP(hipMemcpyAsync(&v, c.dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  if (v) {
+    VMO_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int), s));
+    VMO_HIP(hipStreamSynchronize(s));
+    throw Error(VMO_E_DEVICE, "a device-side wait ran out of its bound (internal error)");
+  }
+}
+
 template <class K>
 void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t s) {
   if (n <= 1 || bits <= 0) return;
-  int passes = (bits + 7) / 8;
+  const int passes = (bits + 7) / 8;
   int ri = 1;
   while (ri < kRsMaxI && n > (int64_t)512 * kRsT * ri) ri *= 2;
-  int64_t tile = (int64_t)kRsT * ri;
-  int ntiles = (int)((n + tile - 1) / tile);
+  const int64_t tile = (int64_t)kRsT * ri;
+  const int64_t ntiles = (n + tile - 1) / tile;
+  int* err = device_flag(c);
   Buf<K> k2(c.pool, n);
   Buf<int32_t> v2(c.pool, vals ? n : 1);
-  Buf<int32_t> hist(c.pool, (size_t)256 * ntiles);
+  // [passes][256] digit totals, [passes] tile counters, [passes][ntiles][256] words
+  const size_t zbytes = sizeof(uint32_t) * (256 * 8 + 8) + sizeof(uint64_t) * (size_t)passes * ntiles * 256;
+  Buf<uint8_t> z(c.pool, zbytes);
+  uint32_t* ghist = reinterpret_cast<uint32_t*>(z.p);
+  uint32_t* ctr = ghist + 256 * 8;
+  uint64_t* status = reinterpret_cast<uint64_t*>(ctr + 8);
+  VMO_HIP(hipMemsetAsync(z.p, 0, zbytes, s));
+  const int64_t hb = (n + kRsT - 1) / kRsT;
+  VMO_LAUNCH((k_rs_hist<K>), (unsigned)(hb < 512 ? hb : 512), kRsT, 0, s, keys, n, passes, ghist);
   K* ka = keys; K* kb = k2.p;
   int32_t* va = vals; int32_t* vb = vals ? v2.p : nullptr;
   for (int ps = 0; ps < passes; ++ps) {
-    int shift = 8 * ps;
-    VMO_LAUNCH((k_rs_hist<K>), ntiles, kRsT, 0, s, ka, n, shift, hist.p, ntiles, ri);
-    scan_exclusive<int32_t>(c, hist.p, hist.p, (int64_t)256 * ntiles, nullptr, s);
-    VMO_LAUNCH((k_rs_scatter<K>), ntiles, kRsT, 0, s, ka, va, kb, vb, n, shift, hist.p, ntiles, ri);
+    VMO_LAUNCH((k_rs_scatter<K>), (unsigned)ntiles, kRsT, 0, s, ka, va, kb, vb, n, 8 * ps, ri, ghist + 256 * ps,
+               status + (size_t)ps * ntiles * 256, ctr + ps, err);
     std::swap(ka, kb);
     std::swap(va, vb);
   }

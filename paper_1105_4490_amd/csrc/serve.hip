@@ -227,6 +227,7 @@ static void serve_loop(vmo_server_s* S) {
         if (!T->job.x) {
           T->xbuf = Buf<float>(S->ctx.pool, 4 * (size_t)T->job.h.k);
           layout(S->ctx, &T->job.h, &T->lp, T->xbuf.p, S->stream);
+          check_device_flag(S->ctx, S->stream);
         }
         JobHost H = host_job(*T);
         E.arena_admit(T->slot, H, T->voff, T->nbase, T->eoff, T->noff, T->poff);
@@ -246,6 +247,7 @@ static void serve_loop(vmo_server_s* S) {
       double t0 = now_ms();
       if (E.S > 0) {
         E.tick(S->prm.t_max);
+        check_device_flag(S->ctx, S->stream);
         std::lock_guard<std::mutex> g(S->mu);
         S->st.ticks += 1;
       }
@@ -272,6 +274,7 @@ static void serve_loop(vmo_server_s* S) {
       }
       if (!fin.empty()) {
         E.emit(slots, hosts);
+        check_device_flag(S->ctx, S->stream);
         for (size_t i = 0; i < fin.size(); ++i) {
           E.arena_release(slots[i]);
           {

@@ -108,8 +108,14 @@ struct Ctx {
   std::string err;
   Pool pool;
   Prof prof;
+  int* dflag = nullptr;  // device error flag of bounded device-side waits
   ~Ctx();
 };
+
+// The context's device error flag (allocated and zeroed on first use), and
+// its check after the stream's work: throws VMO_E_DEVICE if a kernel set it.
+int* device_flag(Ctx& c);
+void check_device_flag(Ctx& c, hipStream_t s);
 
 // Returns a handle for prof_end (-1 when profiling is off).  If dwork is not
 // NULL it receives a zeroed device counter the kernel adds its work to.

@@ -190,3 +190,51 @@ def test_order_full_size_graph_mode(ctx):
     got = ctx.order(dev_h(h), dev_x(x), 64, 1, mode=1, order=1)
     ref = oracle.order(h, x, 64, 1, mode=oracle.GRAPH_MODE, ord=oracle.BBD)
     compare_order(got, ref, oracle.GRAPH_MODE, h.k, h.l)
+
+
+def test_order_full_size_column_net(ctx):
+    """200,000 x 100,000, Zipf(2) row degrees clipped to 2000, column-net, 256
+    parts, SBD: ordering, permutations, split cuts and the cut metrics of the
+    result exact at full size (clustered synthetic coordinates)."""
+    g = vmo_gen.zipf_rect(200000, 100000, seed=3)
+    h = oracle.colnet(g.m, g.n, g.rowptr, g.col)
+    assert (h.k, h.l) == (200000, 100000)
+    x = vmo_gen.random_points(h.k, 3, clusters=64, spread=0.3)
+    dh = dev_h(h)
+    got = ctx.order(dh, dev_x(x), 256, 3, mode=0, order=0)
+    ref = oracle.order(h, x, 256, 3, mode=oracle.NET_MODE, ord=oracle.SBD)
+    compare_order(got, ref, oracle.NET_MODE, h.k, h.l)
+    c = ctx.cut(dh, got["part"], 256)
+    cr = oracle.cut(h, ref.part, 256)
+    assert c["lambda_minus_one"] == cr["lambda_minus_one"] and c["cut_net"] == cr["cut_net"]
+    assert c["nets_cut"] == cr["nets_cut"]
+
+
+def test_order_batch_full_count_sampled(ctx):
+    """512 banded matrices of the batched mix (rows log-uniform in
+    [1e3, 5e4], half bandwidth 5-40, 0.1 % off-band, 8-32 parts, row-net,
+    SBD) ordered by one batched call; 32 jobs of at most 1e4 rows are
+    checked against the oracle, every job's permutation is a bijection with
+    parts in range."""
+    mats = vmo_gen.batch_banded(512, seed=2)
+    jobs = []
+    for i, (g, parts) in enumerate(mats):
+        rp, cl = csr_dev(g)
+        dh = ctx.model(0, g.m, g.n, rp, cl)
+        x = vmo_gen.random_points(g.m, 7000 + i, clusters=3)
+        jobs.append({"h": dh, "x": dev_x(x), "P": parts, "seed": 4, "mode": 0, "order": 0, "job_index": i})
+    outs = ctx.order_batch(jobs)
+    for (g, parts), o in zip(mats, outs):
+        vp = host(o["vperm"])
+        assert np.array_equal(np.sort(vp), np.arange(g.m))
+        pa = host(o["part"])
+        assert pa.min() >= 0 and pa.max() < parts
+    small = [i for i, (g, _) in enumerate(mats) if g.m <= 10000]
+    sample = small[:: max(1, len(small) // 32)][:32]
+    assert len(sample) >= 16
+    for i in sample:
+        g, parts = mats[i]
+        h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+        x = vmo_gen.random_points(g.m, 7000 + i, clusters=3)
+        ref = oracle.order(h, x, parts, 4, mode=oracle.NET_MODE, ord=oracle.SBD, job=i)
+        compare_order(outs[i], ref, oracle.NET_MODE, h.k, h.l)
