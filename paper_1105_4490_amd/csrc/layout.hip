@@ -366,6 +366,274 @@ __global__ void k_tree_moments(int32_t n, int32_t k, const float* xs, const floa
   }
 }
 
+// ------------------------------------------------- one-block tree build ----
+// Levels with k <= 4096 build their tree in one 1024-thread block: the same
+// keys, stable order, nodes and FP64 charges as the multi-kernel build, with
+// the node count written to device memory, so an iteration of a small level
+// needs no host round trip and a handful of launches.
+constexpr int kSTB = 1024;
+constexpr int kSmallK = 4096;
+
+// grid coordinate of dimension d back from a Morton key (inverse of k_tree_keys)
+__device__ __forceinline__ int32_t key_coord(uint64_t m, int d) {
+  int32_t a = 0;
+  for (int b = 15; b >= 0; --b) a |= (int32_t)((m >> (4 * b + 3 - d)) & 1u) << b;
+  return a;
+}
+
+__global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x, const float* __restrict__ w,
+                                                     int32_t k, int32_t cap, const uint32_t* __restrict__ box,
+                                                     FarTable ft, int32_t* __restrict__ order, float* __restrict__ xs,
+                                                     float* __restrict__ ws, int32_t* __restrict__ p2,
+                                                     float4* __restrict__ P, NodeView nd, int32_t* __restrict__ nn) {
+  __shared__ uint64_t key[kSmallK];
+  __shared__ __align__(16) unsigned char rb[32768];
+  // during the sort
+  int32_t* val = reinterpret_cast<int32_t*>(rb);                // [4096]
+  uint16_t* wc = reinterpret_cast<uint16_t*>(rb + 16384);       // [16][256]
+  int32_t* run = reinterpret_cast<int32_t*>(rb + 24576);        // [256]
+  int32_t* hist = reinterpret_cast<int32_t*>(rb + 25600);       // [256]
+  // after the sort
+  int8_t* cpl = reinterpret_cast<int8_t*>(rb);                  // [k + 1]
+  int8_t* ell = reinterpret_cast<int8_t*>(rb + 4112);           // [k]
+  int32_t* base = reinterpret_cast<int32_t*>(rb + 8224);        // [k + 1]
+  int32_t* tsum = reinterpret_cast<int32_t*>(rb + 24640);       // [1024]
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+
+  for (int v = t; v < k; v += kSTB) {
+    uint32_t kq[4];
+    grid_coords(x, k, v, box, kq);
+    uint64_t m = 0;
+    for (int b = 15; b >= 0; --b)
+      for (int d = 0; d < 4; ++d) m = (m << 1) | ((kq[d] >> b) & 1u);
+    key[v] = m;
+    val[v] = v;
+  }
+  __syncthreads();
+
+  // stable LSD radix sort, 8-bit digits; item r of thread t is position
+  // r * 1024 + t, ranks as in the multi-block sort (rounds in order, waves in
+  // order, lanes with equal digits found by ballots)
+  const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+  const int rounds = (k + kSTB - 1) / kSTB;
+  for (int pass = 0; pass < 8; ++pass) {
+    const int sh = 8 * pass;
+    uint64_t mk[4];
+    int32_t mv[4];
+    int md[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = r * kSTB + t;
+      const bool ok = i < k;
+      mk[r] = ok ? key[i] : 0ull;
+      mv[r] = ok ? val[i] : 0;
+      md[r] = ok ? (int)((mk[r] >> sh) & 255u) : -1;
+    }
+    if (t < 256) hist[t] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (md[r] >= 0) atomicAdd(&hist[md[r]], 1);
+    __syncthreads();
+    if (t < 256) run[t] = hist[t];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int a = (t < 256 && t >= off) ? run[t - off] : 0;
+      __syncthreads();
+      if (t < 256) run[t] += a;
+      __syncthreads();
+    }
+    if (t < 256) run[t] -= hist[t];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r >= rounds) break;
+      for (int e = t; e < 16 * 256; e += kSTB) wc[e] = 0;
+      __syncthreads();
+      const bool valid = md[r] >= 0;
+      const int d = valid ? md[r] : 0;
+      uint64_t m = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t bb = __ballot(valid && bit);
+        m &= bit ? bb : ~bb;
+      }
+      const int rank = __popcll(m & below);
+      if (valid && rank == 0) wc[wv * 256 + d] = (uint16_t)__popcll(m);
+      __syncthreads();
+      if (valid) {
+        int off = run[d];
+        for (int ww = 0; ww < wv; ++ww) off += wc[ww * 256 + d];
+        key[off + rank] = mk[r];
+        val[off + rank] = mv[r];
+      }
+      __syncthreads();
+      if (t < 256) {
+        int s2 = 0;
+        for (int ww = 0; ww < 16; ++ww) s2 += wc[ww * 256 + t];
+        run[t] += s2;
+      }
+      __syncthreads();
+    }
+  }
+
+  // points in tree order
+  for (int j = t; j < k; j += kSTB) {
+    const int32_t v = val[j];
+    order[j] = v;
+    uint32_t kq[4];
+    grid_coords(x, k, v, box, kq);
+    float c[4];
+    for (int d = 0; d < 4; ++d) {
+      c[d] = x[(int64_t)d * k + v];
+      xs[(int64_t)d * k + j] = c[d];
+      p2[(int64_t)d * k + j] = 2 * (int32_t)kq[d] + 1;
+    }
+    P[j] = make_float4(c[0], c[1], c[2], c[3]);
+    ws[j] = w ? w[v] : 1.0f;
+  }
+  __syncthreads();  // val is dead from here
+
+  for (int i = t; i <= k; i += kSTB) {
+    int c;
+    if (i == 0 || i == k) c = -1;
+    else {
+      const uint64_t dd = key[i - 1] ^ key[i];
+      c = dd == 0 ? 16 : (__clzll(dd) >> 2);
+    }
+    cpl[i] = (int8_t)c;
+  }
+  __syncthreads();
+  // leaf depth and the number of nodes beginning at each position (as k_tree_ell)
+  for (int i = t; i <= k; i += kSTB) {
+    if (i == k) { base[k] = 0; continue; }
+    const int lo = i - cap + 1 < 0 ? 0 : i - cap + 1;
+    const int hi = i + cap > k ? k : i + cap;
+    int L = 0;
+    for (; L <= 16; ++L) {
+      int b = -1, e = -1;
+      for (int jj = i; jj >= lo; --jj)
+        if (cpl[jj] < L) { b = jj; break; }
+      for (int jj = i + 1; jj <= hi; ++jj)
+        if (cpl[jj] < L) { e = jj; break; }
+      if (b >= 0 && e >= 0 && e - b <= cap) break;
+    }
+    if (L > 16) L = 16;
+    ell[i] = (int8_t)L;
+    const int ci = cpl[i];
+    base[i] = L >= ci + 1 ? L - ci : 0;
+  }
+  __syncthreads();
+  // exclusive scan of base[0..k]: five consecutive entries per thread
+  {
+    const int b0 = 5 * t;
+    int loc = 0;
+    for (int e = 0; e < 5; ++e)
+      if (b0 + e <= k) loc += base[b0 + e];
+    tsum[t] = loc;
+    __syncthreads();
+    for (int off = 1; off < kSTB; off <<= 1) {
+      const int a = t >= off ? tsum[t - off] : 0;
+      __syncthreads();
+      tsum[t] += a;
+      __syncthreads();
+    }
+    int run2 = tsum[t] - loc;
+    for (int e = 0; e < 5; ++e)
+      if (b0 + e <= k) {
+        const int c = base[b0 + e];
+        base[b0 + e] = run2;
+        run2 += c;
+      }
+  }
+  __syncthreads();
+  const int32_t n = base[k];
+  if (t == 0) nn[k] = n;
+  // nodes in pre-order (as k_tree_nodes)
+  for (int i = t; i < k; i += kSTB) {
+    const int ci = cpl[i], li = ell[i];
+    if (li < ci + 1) continue;
+    const uint64_t ki = key[i];
+    int32_t kq[4];
+    for (int d = 0; d < 4; ++d) kq[d] = key_coord(ki, d);
+    for (int L = ci + 1; L <= li; ++L) {
+      const int32_t tn = base[i] + (L - ci - 1);
+      int32_t end = k;
+      if (L > 0) {
+        const int shf = 64 - 4 * L;
+        const uint64_t pre = ki >> shf;
+        int32_t lo2 = i, hi2;
+        int64_t step = 1;
+        while (true) {
+          const int64_t h = lo2 + step;
+          if (h >= k) { hi2 = k; break; }
+          if ((key[h] >> shf) != pre) { hi2 = (int32_t)h; break; }
+          lo2 = (int32_t)h;
+          step <<= 1;
+        }
+        while (hi2 - lo2 > 1) {
+          const int32_t mid = lo2 + (hi2 - lo2) / 2;
+          if ((key[mid] >> shf) == pre) lo2 = mid; else hi2 = mid;
+        }
+        end = hi2;
+      }
+      const int side = 1 << (16 - L);
+      int4 cc;
+      cc.x = 2 * ((kq[0] >> (16 - L)) << (16 - L)) + side;
+      cc.y = 2 * ((kq[1] >> (16 - L)) << (16 - L)) + side;
+      cc.z = 2 * ((kq[2] >> (16 - L)) << (16 - L)) + side;
+      cc.w = 2 * ((kq[3] >> (16 - L)) << (16 - L)) + side;
+      nd.t[tn].a = cc;
+      nd.t[tn].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
+      nd.t[tn].T = ft.T[L];
+      nd.parent[tn] = -1;
+      nd.ctr[tn] = 0;
+    }
+  }
+  __syncthreads();
+  // children lists (as k_tree_links)
+  for (int32_t tn = t; tn < n; tn += kSTB) {
+    const int4 b = nd.t[tn].b;
+    int cnt = 0;
+    if (!((b.w >> 8) & 1)) {
+      int32_t ch = tn + 1;
+      while (ch != b.x) {
+        nd.parent[ch] = tn;
+        if (cnt < 16) nd.cid[16 * (int64_t)tn + cnt] = ch;
+        ++cnt;
+        ch = nd.t[ch].b.x;
+      }
+    }
+    nd.nch[tn] = cnt;
+  }
+  __syncthreads();
+  // charges depth by depth, deepest first (same sums and order as k_tree_moments)
+  for (int L = 16; L >= 0; --L) {
+    for (int32_t tn = t; tn < n; tn += kSTB) {
+      const int4 b = nd.t[tn].b;
+      if ((b.w & 255) != L) continue;
+      double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+      if ((b.w >> 8) & 1) {
+        for (int32_t jj = b.y; jj < b.y + b.z; ++jj) {
+          const double wv2 = (double)ws[jj];
+          Wd += wv2;
+          for (int d = 0; d < 4; ++d) Sd[d] += wv2 * (double)xs[(int64_t)d * k + jj];
+        }
+      } else {
+        const int32_t nc = nd.nch[tn];
+        for (int32_t r = 0; r < nc; ++r) {
+          const int32_t ch = nd.cid[16 * (int64_t)tn + r];
+          Wd += nd.Wd[ch];
+          for (int d = 0; d < 4; ++d) Sd[d] += nd.Sd[4 * (int64_t)ch + d];
+        }
+      }
+      node_finish(nd, tn, Wd, Sd);
+    }
+    __syncthreads();
+  }
+}
+
 struct Tree {
   int32_t k = 0, n = 0;
   Buf<uint64_t> key;
@@ -384,18 +652,40 @@ struct Tree {
   }
 };
 
-// Build the tree of x [4][k] (weights w or 1) with the bounding box dbox.
+// Build the tree of x [4][k] (weights w or 1) with the bounding box dbox.  The
+// node count is left on the device at T.nn[k]; T.n holds it on the host
+// only after the multi-kernel build (small_ok = false or k > 4096).
 static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t k, int32_t cap, const uint32_t* dbox,
-                       double th2, hipStream_t s) {
+                       double th2, hipStream_t s, bool small_ok = true) {
   T.k = k;
+  if (small_ok && k > 0 && k <= kSmallK) {
+    const size_t nmax = 17 * (size_t)k + 1;  // at most 17 nodes begin at a position
+    T.order = Buf<int32_t>(C.pool, k);
+    T.xs = Buf<float>(C.pool, 4 * (size_t)k);
+    T.ws = Buf<float>(C.pool, (size_t)k);
+    T.p2 = Buf<int32_t>(C.pool, 4 * (size_t)k);
+    T.P = Buf<float4>(C.pool, (size_t)k);
+    T.nn = Buf<int32_t>(C.pool, (size_t)k + 1);
+    T.nodes = Buf<TNode>(C.pool, nmax);
+    T.Wd = Buf<double>(C.pool, nmax);
+    T.Sd = Buf<double>(C.pool, 4 * nmax);
+    T.parent = Buf<int32_t>(C.pool, nmax);
+    T.nch = Buf<int32_t>(C.pool, nmax);
+    T.ctr = Buf<int32_t>(C.pool, nmax);
+    T.cid = Buf<int32_t>(C.pool, 16 * nmax);
+    T.n = -1;
+    VMO_LAUNCH(k_tree_small, 1, kSTB, 0, s, x, w, k, cap, dbox, far_table(th2), T.order.p, T.xs.p, T.ws.p, T.p2.p,
+               T.P.p, T.view(), T.nn.p);
+    return;
+  }
   T.key = Buf<uint64_t>(C.pool, k);
   T.order = Buf<int32_t>(C.pool, k);
   VMO_LAUNCH(k_tree_keys, gsz(k), kLT, 0, s, x, k, dbox, T.key.p, T.order.p);
   radix_sort<uint64_t>(C, T.key.p, T.order.p, k, 64, s);
   T.xs = Buf<float>(C.pool, 4 * (size_t)k);
-  T.ws = Buf<float>(C.pool, k);
+  T.ws = Buf<float>(C.pool, (size_t)k);
   T.p2 = Buf<int32_t>(C.pool, 4 * (size_t)k);
-  T.P = Buf<float4>(C.pool, k);
+  T.P = Buf<float4>(C.pool, (size_t)k);
   VMO_LAUNCH(k_tree_points, gsz(k), kLT, 0, s, x, w, k, dbox, T.order.p, T.xs.p, T.ws.p, T.p2.p, T.P.p);
   int32_t nb = k / kCplB + 1;
   T.cpl = Buf<int8_t>(C.pool, (size_t)nb * kCplB);
@@ -517,7 +807,7 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 constexpr int kWin = 64;
 constexpr int kWT = 256;    // threads per block of the walk
 constexpr int kParts = 16;  // at most 16 children of the root
-__global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const float4* __restrict__ P,
+__global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restrict__ n_dev, const float4* __restrict__ P,
                                               const float* __restrict__ ws, const int32_t* __restrict__ p2,
                                               const TNode* __restrict__ nodes, const int32_t* __restrict__ root_cid,
                                               const int32_t* __restrict__ root_nch, float* __restrict__ part,
@@ -527,6 +817,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, int32_t n, const float4
   __shared__ float4 lp[NW][kWin];
   __shared__ float lw[NW][kWin];
   const int seg = blockIdx.y;
+  const int32_t n = *n_dev;
   const int4 rb = nodes[0].b;
   const bool rleaf = (rb.w >> 8) & 1;
   const int nparts = rleaf ? 1 : *root_nch;
@@ -709,7 +1000,7 @@ static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double
   if (gw.nparts.n < (size_t)L.k) gw.nparts = Buf<int32_t>(C.pool, L.k);
   unsigned long long* pc = nullptr;
   int ph = prof_begin(C, "walk", 0.0, s, nint ? nullptr : &pc);
-  VMO_LAUNCH(k_walk, dim3(nblocks(L.k, kWT), kParts), kWT, 0, s, L.k, gw.T.n, gw.T.P.p, gw.T.ws.p, gw.T.p2.p,
+  VMO_LAUNCH(k_walk, dim3(nblocks(L.k, kWT), kParts), kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p,
              gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p, gw.part.p, gw.nparts.p, nint ? nint : pc);
   prof_end(C, ph, s);
   VMO_LAUNCH(k_combine, gsz(L.k), kLT, 0, s, L.k, gw.T.order.p, gw.part.p, gw.nparts.p, y, xmove, alpha);
@@ -1364,7 +1655,7 @@ void tree(Ctx& C, const float* x, const float* w, int32_t k, int32_t cap, int32_
   Buf<uint32_t> box(C.pool, 8);
   box_of(x, k, box.p, s);
   Tree T;
-  build_tree(C, T, x, w, k, cap, box.p, 0.25, s);
+  build_tree(C, T, x, w, k, cap, box.p, 0.25, s, false);
   VMO_REQUIRE(T.n <= max_nodes, "max_nodes is too small");
   VMO_LAUNCH(k_tree_out, gsz(T.n), kLT, 0, s, T.n, T.view(), ints, cell2, flt);
   VMO_HIP(hipMemcpyAsync(order, T.order.p, 4 * (size_t)k, hipMemcpyDeviceToDevice, s));

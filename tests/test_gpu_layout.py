@@ -58,7 +58,8 @@ def weighted_case(seed, k, l, maxdeg=5):
     return h
 
 
-@pytest.mark.parametrize("seed,k,l,theta", [(1, 300, 200, 0.0), (2, 3000, 2500, 0.5), (3, 40000, 30000, 0.5)])
+@pytest.mark.parametrize("seed,k,l,theta", [(1, 300, 200, 0.0), (2, 3000, 2500, 0.5), (4, 4096, 3000, 0.5),
+                                           (5, 4097, 3000, 0.5), (3, 40000, 30000, 0.5)])
 def test_gradient(ctx, seed, k, l, theta):
     h = weighted_case(seed, k, l)
     x = vmo_gen.random_points(k, seed, clusters=6)
@@ -69,6 +70,18 @@ def test_gradient(ctx, seed, k, l, theta):
     if k <= 3000:
         _, cnt = oracle.gradient_sample(h, x, np.arange(k), theta=theta)
         assert nint == int(cnt.sum())
+
+
+@pytest.mark.parametrize("k", [3000, 9000])
+def test_gradient_coincident_points(ctx, k):
+    """Many coincident points: leaves at depth 16 hold more than leaf_cap
+    points (one-block tree build below 4097 points, multi-kernel above)."""
+    h = weighted_case(11, k, k // 2)
+    x = np.round(vmo_gen.random_points(k, 11, clusters=3)).astype(np.float32)
+    y, z = oracle.gradient(h, x, theta=0.5)
+    gy, gz, _ = ctx.gradient(dev_h(h), dev_x(x), theta=0.5)
+    assert np.array_equal(host(gz), z)
+    assert np.array_equal(host(gy), y)
 
 
 @pytest.mark.parametrize("case", ["grid", "weighted"])
