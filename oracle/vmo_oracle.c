@@ -865,10 +865,13 @@ static void walk_rec(const OTree* T, int32_t t, int32_t n, const float* xn, floa
 }
 
 /* Repulsion of point n, added to yn.  The walk's interactions are summed in
-   parts: the walk over the subtree of each child of the root starts from
-   zero, and these partial sums are added to yn in child order.  A root that
-   is far or a leaf forms the single part.  (The paper fixes no summation
-   order; this one lets the parts be computed independently.) */
+   two levels of parts.  A root that is a leaf or far from the point is a
+   single part.  Otherwise each child c of the root gives one part, added to
+   yn in child order; the part of a child that is a leaf or far from the point
+   is its walk summed from zero, and the part of any other child is the sum,
+   in child order and from zero, of the walks over its own children, each
+   summed from zero.  (The paper fixes no summation order; this one lets the
+   walks over the cells of the first two levels run independently.) */
 static void repulsion(const OTree* T, int32_t n, const float* xn, float wn, const int32_t* p2, double th2,
                       const float* x, const float* w, float* yn) {
   const OTNode* R = &T->nd[0];
@@ -878,10 +881,19 @@ static void repulsion(const OTree* T, int32_t n, const float* xn, float wn, cons
     for (int d = 0; d < 4; ++d) yn[d] = yn[d] + acc[d];
     return;
   }
-  for (int32_t ch = 1; ch != R->next; ch = T->nd[ch].next) {
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    walk_rec(T, ch, n, xn, wn, p2, th2, x, w, acc);
-    for (int d = 0; d < 4; ++d) yn[d] = yn[d] + acc[d];
+  for (int32_t c1 = 1; c1 != R->next; c1 = T->nd[c1].next) {
+    const OTNode* N1 = &T->nd[c1];
+    float acc1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (N1->leaf || node_far(N1, p2, th2)) {
+      walk_rec(T, c1, n, xn, wn, p2, th2, x, w, acc1);
+    } else {
+      for (int32_t c2 = c1 + 1; c2 != N1->next; c2 = T->nd[c2].next) {
+        float acc2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        walk_rec(T, c2, n, xn, wn, p2, th2, x, w, acc2);
+        for (int d = 0; d < 4; ++d) acc1[d] = acc1[d] + acc2[d];
+      }
+    }
+    for (int d = 0; d < 4; ++d) yn[d] = yn[d] + acc1[d];
   }
 }
 

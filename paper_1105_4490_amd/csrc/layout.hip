@@ -788,46 +788,65 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // and the walk jumps to its sibling link; a near internal node is entered; a
 // near leaf acts point by point.  One lane per point, points in tree order.
 //
-// The walk of a point is split into parts that run as separate wavefronts:
-// the root is near every point it holds (for theta < 1), so the walk is the
-// concatenation of the walks over the root's children; part s is the walk
-// over child s, summed from zero.  The parts are added in child order by
-// k_combine.  A root that is a leaf, or far from the point, gives one part.
+// Parts.  The walk of a point is summed in two levels of parts (the same
+// order as the oracle): a root that is a leaf or far from the point is one
+// part; otherwise each child c1 of the root is a part, added in child order;
+// the part of a c1 that is a leaf or far from the point ("single") is its walk
+// from zero, and the part of any other c1 is the sum, from zero and in child
+// order, of the walks over the children c2 of c1, each from zero.  Block row
+// blockIdx.y = i1 * spread + i2 handles child i1 of the root and, with
+// spread = 16, only child i2 of c1 (each such walk is then stored and
+// k_combine adds them up); with spread = 1 the wavefront walks every c2 of c1
+// in turn and stores the part of c1.  Spreading gives small levels 16 times
+// more wavefronts; both layouts give the same sums.
 //
-// The 64 lanes of a wavefront step through the nodes of their part in
+// The 64 lanes of a wavefront step through the nodes of their range in
 // pre-order together: node t is read once for the wave, and a lane takes
 // part only if its own walk reaches t (t >= its skip mark).  Every jump of a
 // single walk moves forward in pre-order, so each lane performs exactly the
 // interactions of its own walk, in the same order.  The wave moves to t + 1
 // while some lane is still descending, else to the smallest skip mark.
 // Nodes are staged through a per-wavefront LDS window of 64 consecutive nodes
-// (one 64-byte node per lane per refill), and the points of near leaves
-// through a second window of 64 consecutive points: the walk meets leaves in
-// tree order, so one refill serves several leaves.
+// (one 64-byte node per lane per refill, stored chunk-major so that refills
+// are free of bank conflicts), and the points of near leaves through a second
+// window of 64 consecutive points: the walk meets leaves in tree order, so
+// one refill serves several leaves.
 constexpr int kWin = 64;
 constexpr int kWT = 256;    // threads per block of the walk
-constexpr int kParts = 16;  // at most 16 children of the root
+constexpr int kParts = 16;  // a cell has at most 16 children
+
+__device__ __forceinline__ bool far_from(const int32_t* q, const int4& a, double T) {
+  // exact: integers below 2^40, so fused and separate roundings agree
+  double d0 = (double)(q[0] - a.x), d1 = (double)(q[1] - a.y), d2 = (double)(q[2] - a.z), d3 = (double)(q[3] - a.w);
+  double D2 = __builtin_fma(d3, d3, __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0)));
+  return D2 >= T;
+}
+
 __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restrict__ n_dev, const float4* __restrict__ P,
                                               const float* __restrict__ ws, const int32_t* __restrict__ p2,
-                                              const TNode* __restrict__ nodes, const int32_t* __restrict__ root_cid,
-                                              const int32_t* __restrict__ root_nch, float* __restrict__ part,
-                                              int32_t* __restrict__ nparts_out, unsigned long long* nint) {
+                                              const TNode* __restrict__ nodes, const int32_t* __restrict__ cid,
+                                              const int32_t* __restrict__ nch, int spread, float* __restrict__ part,
+                                              unsigned long long* nint) {
   constexpr int NW = kWT / 64;
-  __shared__ int4 win[NW][kWin][4];
+  __shared__ int4 win[NW][4][kWin];
   __shared__ float4 lp[NW][kWin];
   __shared__ float lw[NW][kWin];
-  const int seg = blockIdx.y;
+  const int i1 = blockIdx.y / spread, i2s = blockIdx.y % spread;
   const int32_t n = *n_dev;
-  const int4 rb = nodes[0].b;
-  const bool rleaf = (rb.w >> 8) & 1;
-  const int nparts = rleaf ? 1 : *root_nch;
-  if (seg >= nparts) return;  // the whole block
+  const bool rleaf = (nodes[0].b.w >> 8) & 1;
+  const int n1 = rleaf ? 1 : min(nch[0], kParts);
+  if (i1 >= n1) return;  // the whole block
+  const int32_t c1 = rleaf ? 0 : cid[i1];
+  const int4 b1 = nodes[c1].b;
+  const bool c1leaf = (b1.w >> 8) & 1;
+  const int n2 = c1leaf ? 0 : min(nch[c1], kParts);
+  if (i2s > 0 && i2s >= n2) return;  // the whole block
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = j < k;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = j < k;
   // interactions of the wavefront (uniform: counted from lane masks)
   unsigned long long cnt = 0;
-  float xn[4] = {0.f, 0.f, 0.f, 0.f}, yn[4] = {0.f, 0.f, 0.f, 0.f};
+  float xn[4] = {0.f, 0.f, 0.f, 0.f};
   int32_t q[4] = {0, 0, 0, 0};
   float wn = 0.0f;
   if (valid) {
@@ -842,129 +861,166 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  auto far_from = [&](const int4& a, double T) {
-    // exact: integers below 2^40, so fused and separate roundings agree
-    double d0 = (double)(q[0] - a.x), d1 = (double)(q[1] - a.y), d2 = (double)(q[2] - a.z), d3 = (double)(q[3] - a.w);
-    double D2 = __builtin_fma(d3, d3, __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0)));
-    return D2 >= T;
-  };
-  // a root far from the point: its single interaction is part 0
-  bool rootfar = false;
-  if (valid) rootfar = far_from(nodes[0].a, nodes[0].T);
-  if (seg == 0 && rootfar) {
-    const float4 X = nodes[0].X;
-    interact(yn, xn, wn2, X.x, X.y, X.z, X.w, nodes[0].W);
-  }
-  if (seg == 0) cnt += (unsigned long long)__popcll(__ballot(rootfar));
-  int32_t t1 = n;
-  int32_t skip = 0x7fffffff;
-  if (rleaf) {
-    if (valid && !rootfar) skip = 0;
-  } else {
-    const int32_t t0 = root_cid[seg];
-    t1 = nodes[t0].b.x;
-    if (valid && !rootfar) skip = t0;
-  }
-  int32_t t = __builtin_amdgcn_readfirstlane(wave_min(skip));
+  const bool rootfar = valid && far_from(q, nodes[0].a, nodes[0].T);
+  const bool single = valid && (rootfar || c1leaf || far_from(q, nodes[c1].a, nodes[c1].T));
+
   int32_t wb = -2 * kWin;  // node window: nodes [wb, wb + 64)
   int32_t pb = -2 * kWin;  // point window: points [pb, pb + 64) in tree order
-  while (t < t1) {
-    if (t < wb || t >= wb + kWin) {
-      wb = t;
-      int32_t tt = t + lane;
-      if (tt < n) {
-        const int4* src = reinterpret_cast<const int4*>(nodes + tt);
-        win[wv][lane][0] = src[0];
-        win[wv][lane][1] = src[1];
-        win[wv][lane][2] = src[2];
-        win[wv][lane][3] = src[3];
-      }
-      wave_sync();
-    }
-    const int o = t - wb;
-    int4 a = win[wv][o][0];
-    int4 b = win[wv][o][1];
-    int4 wi = win[wv][o][3];
-    bool act = skip <= t;
-    bool far = act && far_from(a, __hiloint2double(wi.w, wi.z));
-    if (far) {
-      int4 xi = win[wv][o][2];
-      interact(yn, xn, wn2, __int_as_float(xi.x), __int_as_float(xi.y), __int_as_float(xi.z), __int_as_float(xi.w),
-               __int_as_float(wi.x));
-      skip = b.x;
-    }
-    cnt += (unsigned long long)__popcll(__ballot(far));
-    bool near = act && !far;
-    if ((b.w >> 8) & 1) {
-      if (__any(near)) {
-        const int32_t f1 = b.y + b.z;
-        for (int32_t base = b.y; base < f1; base += kWin) {
-          const int32_t e = f1 - base < kWin ? f1 : base + kWin;
-          if (base < pb || e > pb + kWin) {
-            // slide the point window to start at this leaf
-            wave_sync();
-            pb = base;
-            const int32_t ii = base + lane;
-            if (ii < k) {
-              lp[wv][lane] = P[ii];
-              lw[wv][lane] = ws[ii];
-            }
-            wave_sync();
-          }
-          const int32_t m = e - base, o2 = base - pb;
-          if (near) {
-            for (int32_t i = 0; i < m; ++i) {
-              if (base + i == (int32_t)j) continue;
-              float4 pi = lp[wv][o2 + i];
-              interact(yn, xn, wn2, pi.x, pi.y, pi.z, pi.w, lw[wv][o2 + i]);
-            }
-          }
-          cnt += (unsigned long long)m * __popcll(__ballot(near)) -
-                 __popcll(__ballot(near && j >= base && j < base + m));
+  // the union walk of the lanes with skip marks < t1 over [.., t1), into y
+  auto run = [&](int32_t skip, int32_t t1, float* y) {
+    int32_t t = __builtin_amdgcn_readfirstlane(wave_min(skip));
+    while (t < t1) {
+      if (t < wb || t >= wb + kWin) {
+        wb = t;
+        const int32_t tt = t + lane;
+        if (tt < n) {
+          const int4* src = reinterpret_cast<const int4*>(nodes + tt);
+          win[wv][0][lane] = src[0];
+          win[wv][1][lane] = src[1];
+          win[wv][2][lane] = src[2];
+          win[wv][3][lane] = src[3];
         }
+        wave_sync();
       }
-      if (near) skip = b.x;
-    } else if (near) {
-      skip = t + 1;
+      const int o = t - wb;
+      const int4 a = win[wv][0][o];
+      const int4 b = win[wv][1][o];
+      const int4 wi = win[wv][3][o];
+      const bool act = skip <= t;
+      const bool far = act && far_from(q, a, __hiloint2double(wi.w, wi.z));
+      if (far) {
+        const int4 xi = win[wv][2][o];
+        interact(y, xn, wn2, __int_as_float(xi.x), __int_as_float(xi.y), __int_as_float(xi.z), __int_as_float(xi.w),
+                 __int_as_float(wi.x));
+        skip = b.x;
+      }
+      cnt += (unsigned long long)__popcll(__ballot(far));
+      const bool near = act && !far;
+      if ((b.w >> 8) & 1) {
+        if (__any(near)) {
+          const int32_t f1 = b.y + b.z;
+          for (int32_t base = b.y; base < f1; base += kWin) {
+            const int32_t e = f1 - base < kWin ? f1 : base + kWin;
+            if (base < pb || e > pb + kWin) {
+              // slide the point window to start at this leaf
+              wave_sync();
+              pb = base;
+              const int32_t ii = base + lane;
+              if (ii < k) {
+                lp[wv][lane] = P[ii];
+                lw[wv][lane] = ws[ii];
+              }
+              wave_sync();
+            }
+            const int32_t m = e - base, o2 = base - pb;
+            if (near) {
+              for (int32_t i = 0; i < m; ++i) {
+                if (base + i == (int32_t)j) continue;
+                const float4 pi = lp[wv][o2 + i];
+                interact(y, xn, wn2, pi.x, pi.y, pi.z, pi.w, lw[wv][o2 + i]);
+              }
+            }
+            cnt += (unsigned long long)m * __popcll(__ballot(near)) -
+                   __popcll(__ballot(near && j >= base && j < base + m));
+          }
+        }
+        if (near) skip = b.x;
+      } else if (near) {
+        skip = t + 1;
+      }
+      int32_t nt = t + 1;
+      if (!__any(skip <= nt)) {
+        nt = wave_min(skip);
+        if (nt <= t) nt = t + 1;  // every walk mark lies beyond t; keeps the loop advancing
+      }
+      t = __builtin_amdgcn_readfirstlane(nt);
     }
-    int32_t nt = t + 1;
-    if (!__any(skip <= nt)) {
-      nt = wave_min(skip);
-      if (nt <= t) nt = t + 1;  // every walk mark lies beyond t; keeps the loop advancing
+  };
+
+  float acc1[4] = {0.f, 0.f, 0.f, 0.f};
+  if (i2s == 0) {
+    // single parts: the root's interaction (part 0 only), or the walk of c1
+    if (rootfar && i1 == 0) {
+      const float4 X = nodes[0].X;
+      interact(acc1, xn, wn2, X.x, X.y, X.z, X.w, nodes[0].W);
     }
-    t = __builtin_amdgcn_readfirstlane(nt);
+    if (i1 == 0) cnt += (unsigned long long)__popcll(__ballot(rootfar));
+    run(single && !rootfar ? c1 : 0x7fffffff, c1 + 1, acc1);
+  }
+  // children of c1 walked here (none when c1 is a leaf: n2 = 0)
+  const int i2b = spread > 1 ? i2s : 0, i2e = spread > 1 ? (i2s < n2 ? i2s + 1 : i2s) : n2;
+  float acc2[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int i2 = i2b; i2 < i2e; ++i2) {
+    const int32_t c2 = cid[16 * (int64_t)c1 + i2];
+    for (int d = 0; d < 4; ++d) acc2[d] = 0.0f;
+    run(valid && !single ? c2 : 0x7fffffff, nodes[c2].b.x, acc2);
+    if (spread == 1 && !single)
+      for (int d = 0; d < 4; ++d) acc1[d] = acc1[d] + acc2[d];
   }
   if (valid) {
-    for (int d = 0; d < 4; ++d) part[((int64_t)seg * 4 + d) * k + j] = yn[d];
-    if (seg == 0) nparts_out[j] = rootfar ? 1 : nparts;
+    if (spread == 1) {
+      for (int d = 0; d < 4; ++d) part[((int64_t)i1 * 4 + d) * k + j] = acc1[d];
+    } else if (single) {
+      if (i2s == 0)
+        for (int d = 0; d < 4; ++d) part[(((int64_t)i1 * kParts) * 4 + d) * k + j] = acc1[d];
+    } else {
+      for (int d = 0; d < 4; ++d) part[(((int64_t)i1 * kParts + i2s) * 4 + d) * k + j] = acc2[d];
+    }
   }
   if (nint) {
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nint, cnt);
   }
 }
 
-// y_v = attraction + the walk's parts in order (point j in tree order is
+// y_v = attraction + the parts of the walk in order (point j in tree order is
 // vertex order[j]).  xmove == NULL: y receives the gradient; else the descent
 // step of Algorithm 3 is applied to xmove: x_v <- x_v - (alpha / |y_v|) y_v.
-__global__ void k_combine(int32_t k, const int32_t* __restrict__ order, const float* __restrict__ part,
-                          const int32_t* __restrict__ nparts, float* y, float* xmove, double alpha) {
+__global__ void k_combine(int32_t k, const int32_t* __restrict__ order, const int32_t* __restrict__ p2,
+                          const TNode* __restrict__ nodes, const int32_t* __restrict__ cid,
+                          const int32_t* __restrict__ nch, int spread, const float* __restrict__ part, float* y,
+                          float* xmove, double alpha) {
   GRID_STRIDE(j, k) {
     const int32_t v = order[j];
+    int32_t q[4];
     float yv[4];
-    for (int d = 0; d < 4; ++d) yv[d] = y[(int64_t)d * k + v];
-    const int np = nparts[j];
-    for (int s2 = 0; s2 < np; ++s2)
-      for (int d = 0; d < 4; ++d) yv[d] = yv[d] + part[((int64_t)s2 * 4 + d) * k + j];
+    for (int d = 0; d < 4; ++d) {
+      yv[d] = y[(int64_t)d * k + v];
+      q[d] = p2[(int64_t)d * k + j];
+    }
+    const bool rleaf = (nodes[0].b.w >> 8) & 1;
+    if (rleaf || far_from(q, nodes[0].a, nodes[0].T)) {
+      for (int d = 0; d < 4; ++d) yv[d] = yv[d] + part[(int64_t)d * k + j];
+    } else {
+      const int n1 = min(nch[0], kParts);
+      for (int i1 = 0; i1 < n1; ++i1) {
+        float a1[4];
+        if (spread == 1) {
+          for (int d = 0; d < 4; ++d) a1[d] = part[((int64_t)i1 * 4 + d) * k + j];
+        } else {
+          const int32_t c1 = cid[i1];
+          const bool c1leaf = (nodes[c1].b.w >> 8) & 1;
+          if (c1leaf || far_from(q, nodes[c1].a, nodes[c1].T)) {
+            for (int d = 0; d < 4; ++d) a1[d] = part[(((int64_t)i1 * kParts) * 4 + d) * k + j];
+          } else {
+            for (int d = 0; d < 4; ++d) a1[d] = 0.0f;
+            const int n2 = min(nch[c1], kParts);
+            for (int i2 = 0; i2 < n2; ++i2)
+              for (int d = 0; d < 4; ++d) a1[d] = a1[d] + part[(((int64_t)i1 * kParts + i2) * 4 + d) * k + j];
+          }
+        }
+        for (int d = 0; d < 4; ++d) yv[d] = yv[d] + a1[d];
+      }
+    }
     if (!xmove) {
       for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yv[d];
       continue;
     }
-    float n2 = yv[0] * yv[0];
-    n2 = n2 + yv[1] * yv[1];
-    n2 = n2 + yv[2] * yv[2];
-    n2 = n2 + yv[3] * yv[3];
-    if (!(n2 > 0.0f)) continue;
-    float f = (float)(alpha / sqrt((double)n2));
+    float n2s = yv[0] * yv[0];
+    n2s = n2s + yv[1] * yv[1];
+    n2s = n2s + yv[2] * yv[2];
+    n2s = n2s + yv[3] * yv[3];
+    if (!(n2s > 0.0f)) continue;
+    float f = (float)(alpha / sqrt((double)n2s));
     for (int d = 0; d < 4; ++d) {
       float td = f * yv[d];
       xmove[(int64_t)d * k + v] = xmove[(int64_t)d * k + v] - td;
@@ -975,8 +1031,7 @@ __global__ void k_combine(int32_t k, const int32_t* __restrict__ order, const fl
 struct GradWork {
   Buf<float> z;
   Buf<uint32_t> box;
-  Buf<float> part;      // [kParts][4][k] partial repulsions, tree order
-  Buf<int32_t> nparts;  // [k] parts of each point's walk
+  Buf<float> part;  // partial repulsions, tree order: [16][4][k], or [16][16][4][k] when spread
   Tree T;
 };
 
@@ -996,14 +1051,19 @@ static void gradient_prepare(Ctx& C, const Level& L, const float* x, double th2,
 // is applied to xmove (the layout being descended) and y is left as is.
 static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double alpha, GradWork& gw,
                           unsigned long long* nint, hipStream_t s) {
-  if (gw.part.n < (size_t)kParts * 4 * L.k) gw.part = Buf<float>(C.pool, (size_t)kParts * 4 * L.k);
-  if (gw.nparts.n < (size_t)L.k) gw.nparts = Buf<int32_t>(C.pool, L.k);
+  // levels of up to 65536 points spread each part of the walk over the
+  // children of its cell (16 times the wavefronts)
+  if (L.k <= 0) return;
+  const int spread = L.k <= 65536 ? kParts : 1;
+  const size_t np = (size_t)kParts * spread * 4 * L.k;
+  if (gw.part.n < np) gw.part = Buf<float>(C.pool, np);
   unsigned long long* pc = nullptr;
   int ph = prof_begin(C, "walk", 0.0, s, nint ? nullptr : &pc);
-  VMO_LAUNCH(k_walk, dim3(nblocks(L.k, kWT), kParts), kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p,
-             gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p, gw.part.p, gw.nparts.p, nint ? nint : pc);
+  VMO_LAUNCH(k_walk, dim3(nblocks(L.k, kWT), kParts * spread), kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p,
+             gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, nint ? nint : pc);
   prof_end(C, ph, s);
-  VMO_LAUNCH(k_combine, gsz(L.k), kLT, 0, s, L.k, gw.T.order.p, gw.part.p, gw.nparts.p, y, xmove, alpha);
+  VMO_LAUNCH(k_combine, gsz(L.k), kLT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p,
+             spread, gw.part.p, y, xmove, alpha);
 }
 
 // One descent step (Algorithm 3).  alpha: step length (host); at it == 0 it
