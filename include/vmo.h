@@ -259,16 +259,21 @@ vmo_status vmo_order_batch_plain(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs
  * at the next tick, and a finished job is written to its output buffers and
  * leaves, freeing its ranges.  A job's result does not depend on the other
  * jobs in the mix (its random draws are keyed by seed and job_index).
- * Jobs with x == NULL are laid out (vmo_layout with *lp) when admitted.
+ * Jobs with x == NULL are laid out (vmo_layout with *lp) after admission, by
+ * layout threads that run beside the ticks; memory of those layouts is not
+ * part of budget_bytes.
  * The caller keeps every buffer of a job valid and unchanged until the job is
  * done.  Submit, poll and wait may be called from any host thread.
  * ------------------------------------------------------------------------- */
 typedef struct vmo_server_s* vmo_server;
 typedef struct {
   int device;
-  size_t budget_bytes; /* device memory of the arenas                        */
-  int32_t max_jobs;    /* resident jobs at most                              */
-  int32_t t_max;       /* Lloyd updates per split                            */
+  size_t budget_bytes;    /* device memory of the arenas                     */
+  int32_t max_jobs;       /* resident jobs at most                           */
+  int32_t t_max;          /* Lloyd updates per split                         */
+  int32_t layout_threads; /* host threads, each with its own stream, laying
+                             out jobs that come without coordinates (0..64;
+                             0: the serving thread lays them out itself)     */
 } vmo_serve_params;
 typedef struct {
   int64_t submitted, completed, ticks, resident, pending;

@@ -56,7 +56,8 @@ class ProfileEntry(C.Structure):
 
 
 class ServeParams(C.Structure):
-    _fields_ = [("device", C.c_int), ("budget_bytes", C.c_size_t), ("max_jobs", C.c_int32), ("t_max", C.c_int32)]
+    _fields_ = [("device", C.c_int), ("budget_bytes", C.c_size_t), ("max_jobs", C.c_int32), ("t_max", C.c_int32),
+                ("layout_threads", C.c_int32)]
 
 
 class ServeStats(C.Structure):
@@ -328,10 +329,13 @@ class Server:
     """Continuous-batching ordering server (vmo_serve_*).  Jobs are dicts as
     for Context.order_batch; their tensors must stay alive until done."""
 
-    def __init__(self, budget_bytes: int = 8 << 30, max_jobs: int = 1024, t_max: int = 32, device: int = 0):
+    def __init__(self, budget_bytes: int = 8 << 30, max_jobs: int = 1024, t_max: int = 32, device: int = 0,
+                 layout_threads: int | None = None):
         p = ServeParams()
         lib().vmo_serve_defaults(C.byref(p))
         p.device, p.budget_bytes, p.max_jobs, p.t_max = device, budget_bytes, max_jobs, t_max
+        if layout_threads is not None:
+            p.layout_threads = layout_threads
         h = C.c_void_p()
         st = lib().vmo_serve_create(C.byref(h), C.byref(p))
         if st != VMO_OK:

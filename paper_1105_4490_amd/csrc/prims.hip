@@ -13,6 +13,7 @@ size_t Pool::size_class(size_t b) {
 }
 
 void* Pool::get(size_t bytes) {
+  std::lock_guard<std::mutex> g(mu_);
   size_t cls = size_class(bytes);
   auto it = free_.lower_bound(cls);
   if (it != free_.end() && it->first <= 2 * cls) {
@@ -24,7 +25,7 @@ void* Pool::get(size_t bytes) {
   hipError_t e = hipMalloc(&p, cls);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    trim();
+    trim_locked();
     e = hipMalloc(&p, cls);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -37,12 +38,18 @@ void* Pool::get(size_t bytes) {
 }
 
 void Pool::put(void* p) {
+  std::lock_guard<std::mutex> g(mu_);
   auto it = size_.find(p);
   if (it == size_.end()) return;
   free_.emplace(it->second, p);
 }
 
 void Pool::trim() {
+  std::lock_guard<std::mutex> g(mu_);
+  trim_locked();
+}
+
+void Pool::trim_locked() {
   for (auto& kv : free_) {
     (void)hipFree(kv.second);
     held_ -= size_[kv.second];

@@ -7,7 +7,10 @@
 // in the arenas.  Each tick runs one recursion level for the segments of every
 // resident job in the same launches; jobs admitted meanwhile join at the next
 // tick, and a job whose last segment finished is emitted and leaves, freeing
-// its ranges.
+// its ranges.  Jobs that come without coordinates are laid out by a set of
+// layout threads, each with its own context and stream, so several layouts
+// run on the device at once and beside the ticks; a laid-out job joins the
+// engine at the next tick.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -81,6 +84,12 @@ static double now_ms() {
 
 }  // namespace vmo
 
+struct vmo_layout_worker {
+  vmo::Ctx ctx;  // its pool holds the coordinates of the jobs it laid out
+  hipStream_t stream = nullptr;
+  std::thread th;
+};
+
 struct vmo_server_s {
   vmo::Ctx ctx;
   hipStream_t stream = nullptr;
@@ -89,9 +98,14 @@ struct vmo_server_s {
   vmo::Ranges rv, rn, re, rl, rp;
   std::vector<int32_t> free_slots;
   std::thread worker;
+  std::vector<vmo_layout_worker*> lw;
   std::mutex mu;
-  std::condition_variable cv, done_cv;
+  std::condition_variable cv, done_cv, lcv;
   std::deque<uint64_t> pending;
+  std::deque<uint64_t> lqueue;  // admitted, waiting for a layout thread
+  std::deque<uint64_t> ready;   // laid out, waiting to join the engine
+  std::deque<std::pair<uint64_t, std::pair<vmo_status, std::string>>> lfailed;
+  bool blocked = false;         // the head of `pending` did not fit; cleared when ranges are released
   std::map<uint64_t, vmo::Ticket> tickets;
   std::vector<uint64_t> resident;
   uint64_t next_id = 1;
@@ -149,6 +163,7 @@ static void release_ranges(vmo_server_s* S, Ticket& T) {
     S->rp.release(T.poff, T.npins);
   }
   S->free_slots.push_back(T.slot);
+  S->blocked = false;
 }
 
 static JobHost host_job(const Ticket& T) {
@@ -177,14 +192,50 @@ static void finish_ticket(vmo_server_s* S, uint64_t id, vmo_status st, const std
   S->done_cv.notify_all();
 }
 
+// A layout thread: lays out admitted jobs that came without coordinates.
+static void layout_loop(vmo_server_s* S, vmo_layout_worker* W) {
+  hipSetDevice(S->ctx.device);
+  while (true) {
+    uint64_t id;
+    Ticket* T;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->lcv.wait(lk, [&] { return S->stop || !S->lqueue.empty(); });
+      if (S->stop) break;
+      id = S->lqueue.front();
+      S->lqueue.pop_front();
+      T = &S->tickets[id];
+    }
+    try {
+      T->xbuf = Buf<float>(W->ctx.pool, 4 * (size_t)T->job.h.k);
+      layout(W->ctx, &T->job.h, &T->lp, T->xbuf.p, W->stream);
+      check_device_flag(W->ctx, W->stream);
+      VMO_HIP(hipStreamSynchronize(W->stream));
+      std::lock_guard<std::mutex> g(S->mu);
+      S->ready.push_back(id);
+    } catch (Error& e) {
+      (void)hipStreamSynchronize(W->stream);
+      (void)hipGetLastError();
+      std::lock_guard<std::mutex> g(S->mu);
+      S->lfailed.push_back({id, {e.status, e.what()}});
+    }
+    S->cv.notify_all();
+  }
+}
+
 static void serve_loop(vmo_server_s* S) {
   hipSetDevice(S->ctx.device);
   Engine& E = *S->eng;
+  const bool threads = !S->lw.empty();
   while (true) {
     std::vector<uint64_t> admit;
+    std::vector<std::pair<uint64_t, std::pair<vmo_status, std::string>>> failed;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv.wait(lk, [&] { return S->stop || !S->pending.empty() || E.S > 0 || !S->resident.empty(); });
+      S->cv.wait(lk, [&] {
+        return S->stop || (!S->pending.empty() && !S->blocked) || !S->ready.empty() || !S->lfailed.empty() ||
+               E.S > 0 || !S->resident.empty();
+      });
       if (S->stop) break;
       // admit in arrival order while slots and ranges are free
       while (!S->pending.empty()) {
@@ -210,12 +261,31 @@ static void serve_loop(vmo_server_s* S) {
           S->done_cv.notify_all();
           continue;
         }
-        if (!try_admit(S, T, npins)) break;
+        if (!try_admit(S, T, npins)) {
+          S->blocked = true;
+          break;
+        }
         S->pending.pop_front();
         T.state = 1;
         T.t_admit = now_ms();
-        admit.push_back(id);
+        if (T.layout && threads) {
+          S->lqueue.push_back(id);
+          S->lcv.notify_one();
+        } else {
+          admit.push_back(id);
+        }
       }
+      for (uint64_t id : S->ready) admit.push_back(id);
+      S->ready.clear();
+      for (auto& f : S->lfailed) failed.push_back(f);
+      S->lfailed.clear();
+    }
+    for (auto& f : failed) {
+      {
+        std::lock_guard<std::mutex> g(S->mu);
+        release_ranges(S, S->tickets[f.first]);
+      }
+      finish_ticket(S, f.first, f.second.first, f.second.second);
     }
     for (uint64_t id : admit) {
       Ticket* T;
@@ -224,7 +294,7 @@ static void serve_loop(vmo_server_s* S) {
         T = &S->tickets[id];
       }
       try {
-        if (!T->job.x) {
+        if (!T->job.x && !T->xbuf.p) {
           T->xbuf = Buf<float>(S->ctx.pool, 4 * (size_t)T->job.h.k);
           layout(S->ctx, &T->job.h, &T->lp, T->xbuf.p, S->stream);
           check_device_flag(S->ctx, S->stream);
@@ -315,10 +385,13 @@ void vmo_serve_defaults(vmo_serve_params* p) {
   p->budget_bytes = (size_t)8 << 30;
   p->max_jobs = 1024;
   p->t_max = 32;
+  p->layout_threads = 4;
 }
 
 vmo_status vmo_serve_create(vmo_server* out, const vmo_serve_params* p) {
-  if (!out || !p || p->max_jobs < 1 || p->t_max < 0 || p->budget_bytes < ((size_t)1 << 20)) return VMO_E_INVALID;
+  if (!out || !p || p->max_jobs < 1 || p->t_max < 0 || p->budget_bytes < ((size_t)1 << 20) || p->layout_threads < 0 ||
+      p->layout_threads > 64)
+    return VMO_E_INVALID;
   vmo_server_s* S = new (std::nothrow) vmo_server_s();
   if (!S) return VMO_E_NOMEM;
   S->prm = *p;
@@ -340,12 +413,23 @@ vmo_status vmo_serve_create(vmo_server* out, const vmo_serve_params* p) {
     S->st.capacity_vertices = V;
     S->st.capacity_pins = Pn;
     S->st.capacity_edges = En;
+    for (int32_t i = 0; i < p->layout_threads; ++i) {
+      vmo_layout_worker* W = new vmo_layout_worker();
+      W->ctx.device = p->device;
+      S->lw.push_back(W);
+      VMO_HIP(hipStreamCreate(&W->stream));
+    }
   } catch (vmo::Error& e) {
+    for (vmo_layout_worker* W : S->lw) {
+      if (W->stream) (void)hipStreamDestroy(W->stream);
+      delete W;
+    }
     delete S->eng;
     if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
     return e.status;
   }
+  for (vmo_layout_worker* W : S->lw) W->th = std::thread(vmo::layout_loop, S, W);
   S->worker = std::thread(vmo::serve_loop, S);
   *out = S;
   return VMO_OK;
@@ -443,8 +527,11 @@ vmo_status vmo_serve_destroy(vmo_server S) {
     std::lock_guard<std::mutex> g(S->mu);
     S->stop = true;
     S->cv.notify_all();
+    S->lcv.notify_all();
   }
   if (S->worker.joinable()) S->worker.join();
+  for (vmo_layout_worker* W : S->lw)
+    if (W->th.joinable()) W->th.join();
   {
     std::lock_guard<std::mutex> g(S->mu);
     for (auto& kv : S->tickets)
@@ -459,6 +546,13 @@ vmo_status vmo_serve_destroy(vmo_server S) {
   (void)hipStreamSynchronize(S->stream);
   delete S->eng;
   (void)hipStreamDestroy(S->stream);
+  // coordinates still held by tickets go back to their layout pools first
+  S->tickets.clear();
+  for (vmo_layout_worker* W : S->lw) {
+    (void)hipStreamSynchronize(W->stream);
+    (void)hipStreamDestroy(W->stream);
+    delete W;
+  }
   delete S;
   return VMO_OK;
 }

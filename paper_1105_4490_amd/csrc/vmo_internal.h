@@ -39,18 +39,24 @@ struct Error : std::runtime_error {
 
 // ------------------------------------------------------------------ pool ----
 // Caching device allocator: blocks are kept after release and handed out
-// again for requests of at most the same size class.  Calls synchronise their
-// stream before returning, so a released block is idle when reused.
+// again for requests of at most the same size class.  A pool serves one
+// stream: calls synchronise that stream before returning, so a released
+// block is idle when reused.  Its methods may be called from any thread.
 class Pool {
  public:
   ~Pool();
   void* get(size_t bytes);
   void put(void* p);
-  size_t held() const { return held_; }
+  size_t held() const {
+    std::lock_guard<std::mutex> g(mu_);
+    return held_;
+  }
   void trim();
 
  private:
   static size_t size_class(size_t bytes);
+  void trim_locked();
+  mutable std::mutex mu_;
   std::multimap<size_t, void*> free_;
   std::unordered_map<void*, size_t> size_;
   size_t held_ = 0;

@@ -83,14 +83,22 @@ def test_serve_refuses_jobs_larger_than_the_arena():
     srv.close()
 
 
-def test_serve_with_layout_at_admission():
+@pytest.mark.parametrize("threads", [0, 4])
+def test_serve_with_layout_at_admission(threads):
+    """Jobs without coordinates are laid out after admission (by the serving
+    thread, or by layout threads running beside the ticks); every result
+    equals the oracle's whole path (layout, then ordering)."""
     import paper_1105_4490_amd as P
-    g = vmo_gen.grid2d(24)
-    h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
-    lp = P.layout_params(seed=4)
-    srv = P.Server(budget_bytes=64 << 20, max_jobs=8)
-    t = srv.submit({"h": dev_h(h), "x": None, "P": 8, "seed": 2, "job_index": 0}, lp=lp)
-    o, _ = srv.wait(t)
-    x = oracle.layout(h, oracle.layout_params(seed=4))
-    compare_order(o, oracle.order(h, x, 8, 2), oracle.NET_MODE, h.k, h.l)
+    srv = P.Server(budget_bytes=64 << 20, max_jobs=8, layout_threads=threads)
+    jobs = []
+    for i, side in enumerate((24, 13, 18, 9, 21, 16)):
+        g = vmo_gen.grid2d(side, side + i % 3)
+        h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+        seed = 4 + i
+        t = srv.submit({"h": dev_h(h), "x": None, "P": 8, "seed": 2, "job_index": i}, lp=P.layout_params(seed=seed))
+        jobs.append((t, h, seed, i))
+    for t, h, seed, i in jobs:
+        o, _ = srv.wait(t)
+        x = oracle.layout(h, oracle.layout_params(seed=seed))
+        compare_order(o, oracle.order(h, x, 8, 2, job=i), oracle.NET_MODE, h.k, h.l)
     srv.close()
