@@ -435,15 +435,21 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     for (int r = 0; r < 4; ++r)
       if (md[r] >= 0) atomicAdd(&hist[md[r]], 1);
     __syncthreads();
-    if (t < 256) run[t] = hist[t];
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const int a = (t < 256 && t >= off) ? run[t - off] : 0;
-      __syncthreads();
-      if (t < 256) run[t] += a;
-      __syncthreads();
+    if (t < 64) {
+      // exclusive scan of the 256 digit counts by one wavefront, 4 per lane
+      const int h0 = hist[4 * t], h1 = hist[4 * t + 1], h2 = hist[4 * t + 2], h3 = hist[4 * t + 3];
+      const int tot = h0 + h1 + h2 + h3;
+      int inc = tot;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(inc, off, 64);
+        if (t >= off) inc += u;
+      }
+      const int ex = inc - tot;
+      run[4 * t] = ex;
+      run[4 * t + 1] = ex + h0;
+      run[4 * t + 2] = ex + h0 + h1;
+      run[4 * t + 3] = ex + h0 + h1 + h2;
     }
-    if (t < 256) run[t] -= hist[t];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -588,7 +594,6 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       nd.t[tn].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
       nd.t[tn].T = ft.T[L];
       nd.parent[tn] = -1;
-      nd.ctr[tn] = 0;
     }
   }
   __syncthreads();
@@ -608,11 +613,34 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     nd.nch[tn] = cnt;
   }
   __syncthreads();
+  // nodes grouped by depth (any order within a depth): counts, offsets, lists
+  int32_t* dcnt = tsum;        // [17] after the scan above, tsum is free
+  int32_t* doff = tsum + 32;   // [18]
+  int32_t* dpos = tsum + 64;   // [17]
+  if (t < 17) dcnt[t] = 0;
+  __syncthreads();
+  for (int32_t tn = t; tn < n; tn += kSTB) atomicAdd(&dcnt[nd.t[tn].b.w & 255], 1);
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int L = 0; L <= 16; ++L) {
+      doff[L] = acc;
+      dpos[L] = acc;
+      acc += dcnt[L];
+    }
+    doff[17] = acc;
+  }
+  __syncthreads();
+  for (int32_t tn = t; tn < n; tn += kSTB) {
+    const int L = nd.t[tn].b.w & 255;
+    nd.ctr[atomicAdd(&dpos[L], 1)] = tn;  // ctr is unused by this build: the depth lists
+  }
+  __syncthreads();
   // charges depth by depth, deepest first (same sums and order as k_tree_moments)
   for (int L = 16; L >= 0; --L) {
-    for (int32_t tn = t; tn < n; tn += kSTB) {
+    for (int32_t e = doff[L] + t; e < doff[L + 1]; e += kSTB) {
+      const int32_t tn = nd.ctr[e];
       const int4 b = nd.t[tn].b;
-      if ((b.w & 255) != L) continue;
       double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
       if ((b.w >> 8) & 1) {
         for (int32_t jj = b.y; jj < b.y + b.z; ++jj) {
