@@ -34,6 +34,7 @@ void layout_steps(Ctx& c, const vmo_hypergraph* h, const vmo_layout_params* p, f
 #define API_END                                                   \
     vmo::check_device_flag(C, S);                                 \
     vmo::prof_flush(C);                                           \
+    vmo::tune_flush(C);                                           \
   }                                                               \
   catch (vmo::Error & e) {                                        \
     C.err = e.what();                                             \
@@ -128,7 +129,7 @@ vmo_status vmo_bisect(vmo_ctx ctx, const float* x, int32_t k, uint64_t seed, int
   e.setup(jobs);
   int sp = 0, it = 0;
   if (e.S > 0) {
-    e.two_means(0, e.S, 0, e.Np, t_max);
+    e.two_means(0, e.S, 0, e.Np, t_max, true);
     int32_t st = vmo::read1(e.cur.state.p, S);
     sp = st == vmo::kStDone ? 1 : 0;
     it = vmo::read1(e.cur.iters.p, S);

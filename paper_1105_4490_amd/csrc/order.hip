@@ -263,9 +263,11 @@ __global__ void k_seed2(const JobDev* jobs, SegArrays sg, int64_t s0, int64_t S,
 
 // One Lloyd assignment: side by the plane, sums of side 1, count of side 1,
 // and the number of changed assignments.
-__global__ __launch_bounds__(kT) void k_assign(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
-                                               int64_t p0, int64_t p1, int it, uint8_t* side) {
-  int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One Lloyd assignment of position i (i < p1): side by the plane, and its
+// share of the segment's side-1 sums, side-1 count and changed count.  Every
+// lane of the wavefront calls it (segmented wavefront sums).
+__device__ __forceinline__ void assign_pos(const SegArrays& sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
+                                           int64_t i, int64_t p1, int it, uint8_t* side) {
   int key = -1;
   int64_t v[6] = {0, 0, 0, 0, 0, 0};
   if (i < p1) {
@@ -285,11 +287,18 @@ __global__ __launch_bounds__(kT) void k_assign(SegArrays sg, const int32_t* segp
       if (v[f]) atomicAdd((unsigned long long*)&sg.acc[key * kAccF + kAccS1 + f], (unsigned long long)v[f]);
 }
 
-// After assignment `it`: empty side -> leaf; unchanged or t_max -> done;
-// else new centres (FP64 means of the exact sums) for the next assignment.
-__global__ void k_lloyd_fin(SegArrays sg, int64_t s0, int64_t S, int it, int t_max, int32_t* active) {
-  int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= s0 + S || sg.state[s] != kStIter) return;
+// work (tuner, optional) += 17 bytes per position: grid coordinates read, side written.
+__global__ __launch_bounds__(1024) void k_assign(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
+                                                 int64_t p0, int64_t p1, int it, uint8_t* side,
+                                                 unsigned long long* work) {
+  assign_pos(sg, segpos, q, Np, p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x, p1, it, side);
+  if (work && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(work, 17ull * (unsigned long long)(p1 - p0));
+}
+
+// End of a Lloyd iteration for segment s: new centres and plane, or the
+// segment stops (converged, t_max reached, or a side came out empty).
+__device__ __forceinline__ void lloyd_fin_seg(const SegArrays& sg, int64_t s, int it, int t_max, int32_t* active) {
+  if (sg.state[s] != kStIter) return;
   int64_t* a = &sg.acc[s * kAccF];
   int64_t n = sg.end[s] - sg.beg[s];
   int64_t n1 = a[kAccS1 + 4], n2 = n - n1, ch = a[kAccS1 + 5];
@@ -308,6 +317,11 @@ __global__ void k_lloyd_fin(SegArrays sg, int64_t s0, int64_t S, int it, int t_m
   sg.iters[s] = it + 1;
   for (int f = 0; f < 6; ++f) a[kAccS1 + f] = 0;
   atomicAdd(active, 1);
+}
+
+__global__ void k_lloyd_fin(SegArrays sg, int64_t s0, int64_t S, int it, int t_max, int32_t* active) {
+  int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < s0 + S) lloyd_fin_seg(sg, s, it, t_max, active);
 }
 
 // ------------------------------------------------------------- separator ----
@@ -816,7 +830,7 @@ void Engine::launch_offset_copy_ptr(const int64_t* in, int64_t* out, int64_t n, 
 }
 
 // Seeding and Lloyd iterations for segments [s0, s0+Sn) over positions [p0, p1).
-void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max) {
+void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max, bool tuned) {
   SegArrays sg = view(cur);
   int64_t np = p1 - p0;
   VMO_LAUNCH(k_segpos, gsz(np), kT, 0, s, cur.beg.p, cur.end.p, s0, Sn, p0, p1, segpos.p);
@@ -825,11 +839,19 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
   VMO_LAUNCH(k_d2, nblocks(np, kT), kT, 0, s, sg, segpos.p, q.p, Np, p0, p1, dd.p);
   scan_exclusive<U128>(c, dd.p + p0, dd.p + p0, np, dd.p + p1, s);
   VMO_LAUNCH(k_seed2, nblocks(Sn, kT), kT, 0, s, dj.p, sg, s0, Sn, dd.p, q.p, Np);
+  // The block size of the assignment is tuned online per size bucket in the
+  // batched form (every candidate gives the same result).
+  static const int kBlocks[4] = {128, 256, 512, 1024};
+  const int bucket = bits_for((uint64_t)np);
   Buf<int32_t> active(c.pool, 1);
   for (int it = 0; it <= t_max; ++it) {
+    const int cfg = tuned ? tune_pick(c, kTuneAssign, bucket, 4) : 1;
+    const int B = kBlocks[cfg];
+    unsigned long long* tw = tuned ? tune_begin(c, kTuneAssign, bucket, cfg, s) : nullptr;
     int ph = prof_begin(c, "assign", 17.0 * (double)np, s, nullptr);
-    VMO_LAUNCH(k_assign, nblocks(np, kT), kT, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p);
+    VMO_LAUNCH(k_assign, nblocks(np, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw);
     prof_end(c, ph, s);
+    if (tuned) tune_end(c, s);
     VMO_HIP(hipMemsetAsync(active.p, 0, 4, s));
     VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p);
     if (read1(active.p, s) == 0) break;
@@ -914,7 +936,7 @@ void Engine::run_levels(int t_max, bool plain) {
     alloc_segments(nx, 2 * S);
     int64_t nn = 0;
     if (!plain) {
-      two_means(0, S, 0, Np, t_max);
+      two_means(0, S, 0, Np, t_max, true);
       separator(0, S, 0, Np, 0, E);
       nn = partition(0, S, 0, Np, nx, 0);
     } else {
@@ -927,7 +949,7 @@ void Engine::run_levels(int t_max, bool plain) {
       VMO_HIP(hipStreamSynchronize(s));
       for (int64_t t = 0; t < S; ++t) {
         const JobDev& J = hj[hjob[t]];
-        two_means(t, 1, hb[t], he[t], t_max);
+        two_means(t, 1, hb[t], he[t], t_max, false);
         if (J.mode == VMO_GRAPH) separator(t, 1, hb[t], he[t], J.eoff, J.eoff + J.nnets);
         nn += partition(t, 1, hb[t], he[t], nx, nn);
       }
@@ -1174,7 +1196,7 @@ void Engine::tick(int t_max) {
   if (S == 0) return;
   SegBufs nx;
   alloc_segments(nx, 2 * S);
-  two_means(0, S, 0, Np, t_max);
+  two_means(0, S, 0, Np, t_max, true);
   separator(0, S, 0, Np, 0, E);
   int64_t nn = partition(0, S, 0, Np, nx, 0);
   cur = std::move(nx);

@@ -48,6 +48,7 @@ struct OutPtrs {
 };
 
 enum : int32_t { kStIter = 0, kStDone = 1, kStLeaf = 2 };
+enum : int { kTuneAssign = 1 };  // tuner families
 enum : int32_t { kNodeNone = 0, kNodeLeaf = 1, kNodeInternal = 2, kNodePending = 3 };
 // segment accumulators: sums of q (4), side-1 sums (4), side-1 count,
 // changed count
@@ -84,8 +85,10 @@ class Engine {
   void finish(const std::vector<JobHost>& jobs);
   // emission for the jobs `slots` of the job table (their work is done)
   void emit(const std::vector<int32_t>& slots, const std::vector<JobHost>& jobs);
-  // single split of the level-0 segments (vmo_bisect)
-  void two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max);
+  // k-means++ seeding and Lloyd iterations of segments [s0, s0+Sn) over
+  // positions [p0, p1); tuned: the assignment's block size comes from the
+  // context's online tuner (else 256)
+  void two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max, bool tuned);
 
   Ctx& c;
   hipStream_t s;

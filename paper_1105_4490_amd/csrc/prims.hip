@@ -66,8 +66,69 @@ Pool::~Pool() {
 Ctx::~Ctx() {
   prof_discard(*this);
   if (prof.dcnt) (void)hipFree(prof.dcnt);
+  for (auto& r : tune.pend) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (tune.dwork) (void)hipFree(tune.dwork);
   if (dflag) (void)hipFree(dflag);
 }
+
+// ----------------------------------------------------------------- tuner ----
+int tune_pick(Ctx& c, int family, int bucket, int ncfg) {
+  TuneStat& st = c.tune.stat[{family, bucket}];
+  for (int i = 0; i < ncfg; ++i)
+    if (st.n[i] < 2) return i;
+  int best = 0;
+  for (int i = 1; i < ncfg; ++i)
+    if (st.ms_per_work[i] / st.n[i] < st.ms_per_work[best] / st.n[best]) best = i;
+  return best;
+}
+
+unsigned long long* tune_begin(Ctx& c, int family, int bucket, int cfg, hipStream_t s) {
+  Tuner& t = c.tune;
+  if (t.nslot == t.cap) {
+    VMO_HIP(hipStreamSynchronize(s));
+    tune_flush(c);
+    if (t.cap == 0) {
+      t.cap = 1024;
+      VMO_HIP(hipMalloc(&t.dwork, sizeof(unsigned long long) * t.cap));
+    }
+  }
+  TuneRec r;
+  r.family = family; r.bucket = bucket; r.cfg = cfg;
+  r.dslot = t.nslot++;
+  VMO_HIP(hipMemsetAsync(t.dwork + r.dslot, 0, sizeof(unsigned long long), s));
+  VMO_HIP(hipEventCreate(&r.a));
+  VMO_HIP(hipEventCreate(&r.b));
+  VMO_HIP(hipEventRecord(r.a, s));
+  t.pend.push_back(r);
+  return t.dwork + r.dslot;
+}
+
+void tune_end(Ctx& c, hipStream_t s) { VMO_HIP(hipEventRecord(c.tune.pend.back().b, s)); }
+
+void tune_flush(Ctx& c) {
+  Tuner& t = c.tune;
+  if (t.pend.empty()) return;
+  std::vector<unsigned long long> w(t.nslot);
+  VMO_HIP(hipMemcpy(w.data(), t.dwork, sizeof(unsigned long long) * t.nslot, hipMemcpyDeviceToHost));
+  for (auto& r : t.pend) {
+    float ms = 0.0f;
+    VMO_HIP(hipEventSynchronize(r.b));
+    VMO_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    if (w[r.dslot] > 0) {
+      TuneStat& st = t.stat[{r.family, r.bucket}];
+      st.ms_per_work[r.cfg] += (double)ms / (double)w[r.dslot];
+      st.n[r.cfg] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  t.pend.clear();
+  t.nslot = 0;
+}
+
 
 int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned long long** dwork) {
   if (dwork) *dwork = nullptr;

@@ -318,6 +318,8 @@ static void serve_loop(vmo_server_s* S) {
       if (E.S > 0) {
         E.tick(S->prm.t_max);
         check_device_flag(S->ctx, S->stream);
+        tune_flush(S->ctx);
+        prof_discard(S->ctx);
         std::lock_guard<std::mutex> g(S->mu);
         S->st.ticks += 1;
       }

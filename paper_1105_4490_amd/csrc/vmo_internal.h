@@ -109,14 +109,46 @@ struct Prof {
   int nslot = 0, cap = 0;
 };
 
+// Online launch-configuration tuner.  A kernel family has a few candidate
+// configurations that give identical results; the first calls in each size
+// bucket try every candidate (twice), timed with HIP events and normalised
+// by the work the kernel reports on the device; later calls use the fastest.
+struct TuneRec {
+  int family, bucket, cfg;
+  hipEvent_t a, b;
+  int dslot;
+};
+struct TuneStat {
+  double ms_per_work[8] = {};
+  int n[8] = {};
+};
+struct Tuner {
+  static constexpr int kMaxCfg = 8;
+  std::map<std::pair<int, int>, TuneStat> stat;
+  std::vector<TuneRec> pend;
+  unsigned long long* dwork = nullptr;
+  int nslot = 0, cap = 0;
+};
+
 struct Ctx {
   int device = 0;
   std::string err;
   Pool pool;
   Prof prof;
+  Tuner tune;
   int* dflag = nullptr;  // device error flag of bounded device-side waits
   ~Ctx();
 };
+
+// Tuner: the configuration to use for (family, bucket) among ncfg; begin
+// records the start event and returns a zeroed device work counter for the
+// kernel; end records the stop event.  Flushed with the profile (after the
+// stream is synchronised).
+int tune_pick(Ctx& c, int family, int bucket, int ncfg);
+unsigned long long* tune_begin(Ctx& c, int family, int bucket, int cfg, hipStream_t s);
+void tune_end(Ctx& c, hipStream_t s);
+void tune_flush(Ctx& c);
+
 
 // The context's device error flag (allocated and zeroed on first use), and
 // its check after the stream's work: throws VMO_E_DEVICE if a kernel set it.
