@@ -839,7 +839,7 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // are free of bank conflicts), and the points of near leaves through a second
 // window of 64 consecutive points: the walk meets leaves in tree order, so
 // one refill serves several leaves.
-constexpr int kWin = 64;
+constexpr int kWin = 32;
 constexpr int kWT = 256;    // threads per block of the walk
 constexpr int kParts = 16;  // a cell has at most 16 children
 
@@ -892,8 +892,8 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
   const bool rootfar = valid && far_from(q, nodes[0].a, nodes[0].T);
   const bool single = valid && (rootfar || c1leaf || far_from(q, nodes[c1].a, nodes[c1].T));
 
-  int32_t wb = -2 * kWin;  // node window: nodes [wb, wb + 64)
-  int32_t pb = -2 * kWin;  // point window: points [pb, pb + 64) in tree order
+  int32_t wb = -2 * kWin;  // node window: nodes [wb, wb + kWin)
+  int32_t pb = -2 * kWin;  // point window: points [pb, pb + kWin) in tree order
   // the union walk of the lanes with skip marks < t1 over [.., t1), into y
   auto run = [&](int32_t skip, int32_t t1, float* y) {
     int32_t t = __builtin_amdgcn_readfirstlane(wave_min(skip));
@@ -901,7 +901,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
       if (t < wb || t >= wb + kWin) {
         wb = t;
         const int32_t tt = t + lane;
-        if (tt < n) {
+        if (lane < kWin && tt < n) {
           const int4* src = reinterpret_cast<const int4*>(nodes + tt);
           win[wv][0][lane] = src[0];
           win[wv][1][lane] = src[1];
@@ -934,7 +934,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
               wave_sync();
               pb = base;
               const int32_t ii = base + lane;
-              if (ii < k) {
+              if (lane < kWin && ii < k) {
                 lp[wv][lane] = P[ii];
                 lw[wv][lane] = ws[ii];
               }
