@@ -69,6 +69,18 @@ __device__ __forceinline__ int32_t find_v(const JobDev* jobs, int32_t nj, int64_
   return lo;
 }
 
+// Sum over the 64 lanes (all active) by DPP row shifts and row broadcasts;
+// lane 63 ends with the total.
+__device__ __forceinline__ int32_t wave_sum_dpp(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
 // Segmented sum across a wavefront.  Lanes hold (key, v[F]); equal keys form
 // contiguous lane runs.  Afterwards the first lane of each run holds the run's
 // total and returns true.  key < 0 = no segment.
@@ -281,6 +293,19 @@ __device__ __forceinline__ void assign_pos(const SegArrays& sg, const int32_t* s
       side[i] = sd;
       if (sd == 1) { v[0] = a0; v[1] = a1; v[2] = a2; v[3] = a3; v[4] = 1; }
     }
+  }
+  // one segment across the wavefront (the usual case): 32-bit DPP sums (each
+  // total is below 64 * 2^20); else the general segmented sum
+  const int k0 = __builtin_amdgcn_readfirstlane(key);
+  if (__all(key == k0)) {
+    if (k0 < 0) return;
+    int32_t t[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) t[f] = wave_sum_dpp((int32_t)v[f]);
+    if (lane_id() == 63)
+      for (int f = 0; f < 6; ++f)
+        if (t[f]) atomicAdd((unsigned long long*)&sg.acc[k0 * kAccF + kAccS1 + f], (unsigned long long)t[f]);
+    return;
   }
   if (wave_seg_sum<6>(key, v))
     for (int f = 0; f < 6; ++f)

@@ -48,7 +48,6 @@ struct OutPtrs {
 };
 
 enum : int32_t { kStIter = 0, kStDone = 1, kStLeaf = 2 };
-enum : int { kTuneAssign = 1 };  // tuner families
 enum : int32_t { kNodeNone = 0, kNodeLeaf = 1, kNodeInternal = 2, kNodePending = 3 };
 // segment accumulators: sums of q (4), side-1 sums (4), side-1 count,
 // changed count

@@ -98,6 +98,7 @@ unsigned long long* tune_begin(Ctx& c, int family, int bucket, int cfg, hipStrea
   TuneRec r;
   r.family = family; r.bucket = bucket; r.cfg = cfg;
   r.dslot = t.nslot++;
+  r.hwork = 0.0;
   VMO_HIP(hipMemsetAsync(t.dwork + r.dslot, 0, sizeof(unsigned long long), s));
   VMO_HIP(hipEventCreate(&r.a));
   VMO_HIP(hipEventCreate(&r.b));
@@ -106,20 +107,33 @@ unsigned long long* tune_begin(Ctx& c, int family, int bucket, int cfg, hipStrea
   return t.dwork + r.dslot;
 }
 
+void tune_begin_host(Ctx& c, int family, int bucket, int cfg, double work, hipStream_t s) {
+  TuneRec r;
+  r.family = family; r.bucket = bucket; r.cfg = cfg;
+  r.dslot = -1;
+  r.hwork = work;
+  VMO_HIP(hipEventCreate(&r.a));
+  VMO_HIP(hipEventCreate(&r.b));
+  VMO_HIP(hipEventRecord(r.a, s));
+  c.tune.pend.push_back(r);
+}
+
 void tune_end(Ctx& c, hipStream_t s) { VMO_HIP(hipEventRecord(c.tune.pend.back().b, s)); }
 
 void tune_flush(Ctx& c) {
   Tuner& t = c.tune;
   if (t.pend.empty()) return;
   std::vector<unsigned long long> w(t.nslot);
-  VMO_HIP(hipMemcpy(w.data(), t.dwork, sizeof(unsigned long long) * t.nslot, hipMemcpyDeviceToHost));
+  if (t.nslot > 0)
+    VMO_HIP(hipMemcpy(w.data(), t.dwork, sizeof(unsigned long long) * t.nslot, hipMemcpyDeviceToHost));
   for (auto& r : t.pend) {
     float ms = 0.0f;
     VMO_HIP(hipEventSynchronize(r.b));
     VMO_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-    if (w[r.dslot] > 0) {
+    const double wk = r.dslot >= 0 ? (double)w[r.dslot] : r.hwork;
+    if (wk > 0) {
       TuneStat& st = t.stat[{r.family, r.bucket}];
-      st.ms_per_work[r.cfg] += (double)ms / (double)w[r.dslot];
+      st.ms_per_work[r.cfg] += (double)ms / wk;
       st.n[r.cfg] += 1;
     }
     (void)hipEventDestroy(r.a);
@@ -428,8 +442,15 @@ template <class K>
 void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t s) {
   if (n <= 1 || bits <= 0) return;
   const int passes = (bits + 7) / 8;
+  // tiles of ri rounds: the target tile count is tuned online per size bucket
+  // (fewer tiles: shorter look-back chains; more: more blocks in flight)
+  static const int kTarget[4] = {64, 128, 256, 512};
+  const int bucket = bits_for((uint64_t)n);
+  const int cfg = n > (int64_t)64 * kRsT ? tune_pick(c, kTuneSort, bucket, 4) : 3;
   int ri = 1;
-  while (ri < kRsMaxI && n > (int64_t)512 * kRsT * ri) ri *= 2;
+  while (ri < kRsMaxI && n > (int64_t)kTarget[cfg] * kRsT * ri) ri *= 2;
+  const bool tuned = n > (int64_t)64 * kRsT;
+  if (tuned) tune_begin_host(c, kTuneSort, bucket, cfg, (double)n * passes, s);
   const int64_t tile = (int64_t)kRsT * ri;
   const int64_t ntiles = (n + tile - 1) / tile;
   int* err = device_flag(c);
@@ -456,6 +477,7 @@ void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t
     VMO_HIP(hipMemcpyAsync(keys, ka, sizeof(K) * n, hipMemcpyDeviceToDevice, s));
     if (vals) VMO_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
   }
+  if (tuned) tune_end(c, s);
 }
 template void radix_sort<uint32_t>(Ctx&, uint32_t*, int32_t*, int64_t, int, hipStream_t);
 template void radix_sort<uint64_t>(Ctx&, uint64_t*, int32_t*, int64_t, int, hipStream_t);

@@ -211,6 +211,7 @@ static void layout_loop(vmo_server_s* S, vmo_layout_worker* W) {
       layout(W->ctx, &T->job.h, &T->lp, T->xbuf.p, W->stream);
       check_device_flag(W->ctx, W->stream);
       VMO_HIP(hipStreamSynchronize(W->stream));
+      tune_flush(W->ctx);
       std::lock_guard<std::mutex> g(S->mu);
       S->ready.push_back(id);
     } catch (Error& e) {

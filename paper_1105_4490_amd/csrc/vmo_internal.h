@@ -116,7 +116,8 @@ struct Prof {
 struct TuneRec {
   int family, bucket, cfg;
   hipEvent_t a, b;
-  int dslot;
+  int dslot;     // device work counter, or -1: work known on the host
+  double hwork;
 };
 struct TuneStat {
   double ms_per_work[8] = {};
@@ -146,8 +147,10 @@ struct Ctx {
 // stream is synchronised).
 int tune_pick(Ctx& c, int family, int bucket, int ncfg);
 unsigned long long* tune_begin(Ctx& c, int family, int bucket, int cfg, hipStream_t s);
+void tune_begin_host(Ctx& c, int family, int bucket, int cfg, double work, hipStream_t s);
 void tune_end(Ctx& c, hipStream_t s);
 void tune_flush(Ctx& c);
+enum : int { kTuneAssign = 1, kTuneSort = 2 };  // tuner families: Lloyd assignment, radix sort
 
 
 // The context's device error flag (allocated and zeroed on first use), and
