@@ -45,7 +45,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2,
+                    help="untimed steps (the launch tuner settles during the first steps)")
     ap.add_argument("--side", type=int, default=N_SIDE, help="grid side of the workload (64 = the 64^3 case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=28, help="grid side of the oracle's timed sample")
@@ -54,6 +55,8 @@ def main():
     ap.add_argument("--requests", type=int, default=40, help="serve mode: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve mode: arrivals per second")
     ap.add_argument("--nnz-max", type=float, default=1e7, help="serve mode: largest nnz of a request")
+    ap.add_argument("--no-stable", action="store_true",
+                    help="serve mode: skip the second stream at half the measured capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -160,15 +163,30 @@ def bench_batch(args, ctx):
     mats = vmo_gen.batch_banded(args.jobs, seed=SEED)
     gen_s = time.perf_counter() - t
     print(f"bench: generated {len(mats)} matrices in {gen_s:.1f} s", file=sys.stderr, flush=True)
-    jobs = []
     t = time.perf_counter()
-    for i, (g, parts) in enumerate(mats):
-        h = ctx.model(P.ROW_NET, g.m, g.n, torch.as_tensor(g.rowptr).cuda(), torch.as_tensor(g.col).cuda())
-        x = ctx.layout(h, P.layout_params(seed=SEED + i))
-        jobs.append({"h": h, "x": x, "P": parts, "seed": SEED, "mode": P.NET, "order": P.SBD, "job_index": i})
-        if (i + 1) % 64 == 0:
-            print(f"bench: laid out {i + 1} matrices", file=sys.stderr, flush=True)
+    hs = [ctx.model(P.ROW_NET, g.m, g.n, torch.as_tensor(g.rowptr).cuda(), torch.as_tensor(g.col).cuda())
+          for g, _ in mats]
     torch.cuda.synchronize()
+    # coordinates (untimed): layouts run on four streams at once, one context each
+    import concurrent.futures
+    xs = [None] * len(mats)
+
+    def lay(w):
+        c = P.Context(0)
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            for i in range(w, len(mats), 4):
+                xs[i] = c.layout(hs[i], P.layout_params(seed=SEED + i))
+                if (i + 1) % 64 == 0:
+                    print(f"bench: laid out {i + 1} matrices", file=sys.stderr, flush=True)
+        st.synchronize()
+        c.close()
+
+    with concurrent.futures.ThreadPoolExecutor(4) as ex:
+        list(ex.map(lay, range(4)))
+    torch.cuda.synchronize()
+    jobs = [{"h": hs[i], "x": xs[i], "P": parts, "seed": SEED, "mode": P.NET, "order": P.SBD, "job_index": i}
+            for i, (g, parts) in enumerate(mats)]
     lay_s = time.perf_counter() - t
     nnz = sum(g.nnz for g, _ in mats)
     rows = sum(g.m for g, _ in mats)
@@ -226,6 +244,7 @@ def _serve_matrix(spec):
 
 def bench_serve(args, ctx):
     """A Poisson stream of whole-path ordering jobs through the server."""
+    import numpy as np
     import torch
     import paper_1105_4490_amd as P
     import vmo_gen
@@ -246,29 +265,35 @@ def bench_serve(args, ctx):
     print(f"bench: prepared {len(jobs)} requests ({sum(j[2] for j in jobs)} nnz) in {prep_s:.1f} s",
           file=sys.stderr, flush=True)
     lp = P.layout_params(seed=SEED)
-    srv = P.Server(budget_bytes=16 << 30, max_jobs=256)
-    tickets = []
-    t0 = time.perf_counter()
-    for jb, at, nz in jobs:
-        now = time.perf_counter() - t0
-        if at > now:
-            time.sleep(at - now)
-        tickets.append((srv.submit(jb, lp), time.perf_counter() - t0, nz))
-    lat = []
-    done_at = 0.0
-    for i, (tk, sub, nz) in enumerate(tickets):
-        o, ms = srv.wait(tk)
-        lat.append(ms)
-        done_at = max(done_at, time.perf_counter() - t0)
-        if (i + 1) % 10 == 0:
-            print(f"bench: {i + 1} requests done", file=sys.stderr, flush=True)
-    st = srv.stats()
-    srv.close()
+
+    def stream(arrivals):
+        """Submit the jobs at the given arrival times; (latencies ms, span s, stats)."""
+        srv = P.Server(budget_bytes=16 << 30, max_jobs=256)
+        tickets = []
+        t0 = time.perf_counter()
+        for (jb, _, nz), at in zip(jobs, arrivals):
+            now = time.perf_counter() - t0
+            if at > now:
+                time.sleep(at - now)
+            tickets.append(srv.submit(jb, lp))
+        lat = []
+        done_at = 0.0
+        for i, tk in enumerate(tickets):
+            o, ms = srv.wait(tk)
+            lat.append(ms)
+            done_at = max(done_at, time.perf_counter() - t0)
+            if (i + 1) % 10 == 0:
+                print(f"bench: {i + 1} requests done", file=sys.stderr, flush=True)
+        st = srv.stats()
+        srv.close()
+        return lat, done_at, st
+
     total = sum(j[2] for j in jobs)
-    span = done_at
+    lat, span, st = stream([j[1] for j in jobs])
+    capacity = total / span
     line = {
         "metric": "matrix nnz ordered/sec (served, full recursive SBD/BBD) + p50/p99 latency",
-        "value": total / span, "unit": "nnz/s", "n_gpus": 1, "steps": len(jobs), "warmup": 0,
+        "value": capacity, "unit": "nnz/s", "n_gpus": 1, "steps": len(jobs), "warmup": 0,
         "ms_per_step": 1e3 * span / len(jobs), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"Poisson stream of {len(jobs)} requests at {args.rate}/s, nnz log-uniform "
@@ -279,6 +304,15 @@ def bench_serve(args, ctx):
         "offered_nnz_per_s": total / max(jobs[-1][1], 1e-9),
         "busy_ms": st["busy_ms"], "ticks": st["ticks"],
     }
+    if not args.no_stable and capacity < line["offered_nnz_per_s"]:
+        # the same jobs again as a Poisson stream at half the measured capacity
+        rate = 0.5 * capacity / (total / len(jobs))
+        g = vmo_gen.rng(SEED, 61)
+        arr = list(np.cumsum(g.exponential(1.0 / rate, size=len(jobs))))
+        print(f"bench: stable run at {rate:.2f} requests/s", file=sys.stderr, flush=True)
+        lat2, span2, _ = stream(arr)
+        line["stable"] = {"rate_per_s": rate, "nnz_per_s": total / span2,
+                          "latency_ms": {"p50": _pct(lat2, 0.5), "p99": _pct(lat2, 0.99), "max": max(lat2)}}
     print(json.dumps(line))
 
 

@@ -275,48 +275,77 @@ __global__ void k_seed2(const JobDev* jobs, SegArrays sg, int64_t s0, int64_t S,
 
 // One Lloyd assignment: side by the plane, sums of side 1, count of side 1,
 // and the number of changed assignments.
-// One Lloyd assignment of position i (i < p1): side by the plane, and its
-// share of the segment's side-1 sums, side-1 count and changed count.  Every
-// lane of the wavefront calls it (segmented wavefront sums).
-__device__ __forceinline__ void assign_pos(const SegArrays& sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
-                                           int64_t i, int64_t p1, int it, uint8_t* side) {
-  int key = -1;
-  int64_t v[6] = {0, 0, 0, 0, 0, 0};
-  if (i < p1) {
-    int32_t s = segpos[i];
-    if (s >= 0 && sg.state[s] == kStIter) {
-      key = s;
-      uint32_t a0 = q[i], a1 = q[Np + i], a2 = q[2 * Np + i], a3 = q[3 * Np + i];
-      double sv = plane_eval(a0, a1, a2, a3, &sg.plane[s * 5]);
-      uint8_t sd = sv <= 0.0 ? 1 : 2;
-      if (it > 0 && sd != side[i]) v[5] = 1;
-      side[i] = sd;
-      if (sd == 1) { v[0] = a0; v[1] = a1; v[2] = a2; v[3] = a3; v[4] = 1; }
+// One Lloyd assignment: side by the plane, and the segment's side-1 sums,
+// side-1 count and changed count.  Four consecutive positions per thread (Np is
+// a multiple of 4 and the arrays are 16-byte aligned): 16-byte loads of each grid
+// coordinate and of the segment ids, 4-byte loads and stores of the sides.
+// Bytes of the pack outside [p0, p1) or in segments that do not iterate are
+// written back unchanged (one thread owns each pack).
+__global__ __launch_bounds__(1024) void k_assign4(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
+                                                  int64_t p0, int64_t p1, int it, uint8_t* side,
+                                                  unsigned long long* work) {
+  const int64_t b = (p0 & ~int64_t(3)) + 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const bool inb = b < p1;
+  int key[4] = {-1, -1, -1, -1};
+  int64_t v[4][6];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int f = 0; f < 6; ++f) v[u][f] = 0;
+  if (inb) {
+    const int4 sp = *reinterpret_cast<const int4*>(segpos + b);
+    const uint4 q0 = *reinterpret_cast<const uint4*>(q + b);
+    const uint4 q1 = *reinterpret_cast<const uint4*>(q + Np + b);
+    const uint4 q2 = *reinterpret_cast<const uint4*>(q + 2 * Np + b);
+    const uint4 q3 = *reinterpret_cast<const uint4*>(q + 3 * Np + b);
+    uchar4 so = *reinterpret_cast<const uchar4*>(side + b);
+    const int spa[4] = {sp.x, sp.y, sp.z, sp.w};
+    const uint32_t a0[4] = {q0.x, q0.y, q0.z, q0.w}, a1[4] = {q1.x, q1.y, q1.z, q1.w};
+    const uint32_t a2[4] = {q2.x, q2.y, q2.z, q2.w}, a3[4] = {q3.x, q3.y, q3.z, q3.w};
+    uint8_t sv[4] = {so.x, so.y, so.z, so.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = b + u;
+      const int32_t s = spa[u];
+      if (i < p0 || i >= p1 || s < 0 || sg.state[s] != kStIter) continue;
+      key[u] = s;
+      const double e = plane_eval(a0[u], a1[u], a2[u], a3[u], &sg.plane[s * 5]);
+      const uint8_t sd = e <= 0.0 ? 1 : 2;
+      if (it > 0 && sd != sv[u]) v[u][5] = 1;
+      sv[u] = sd;
+      if (sd == 1) { v[u][0] = a0[u]; v[u][1] = a1[u]; v[u][2] = a2[u]; v[u][3] = a3[u]; v[u][4] = 1; }
+    }
+    *reinterpret_cast<uchar4*>(side + b) = make_uchar4(sv[0], sv[1], sv[2], sv[3]);
+  }
+  // one key for the thread's pack: -1 none, -2 mixed
+  int kt = -1;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (key[u] >= 0) kt = (kt == -1 || kt == key[u]) ? key[u] : -2;
+  const int k0 = __builtin_amdgcn_readfirstlane(kt);
+  if (k0 != -2 && __all(kt == k0)) {
+    // one segment across the wavefront: 32-bit DPP sums (totals below 256 * 2^20)
+    if (k0 >= 0) {
+      int32_t t[6];
+#pragma unroll
+      for (int f = 0; f < 6; ++f)
+        t[f] = wave_sum_dpp((int32_t)(v[0][f] + v[1][f] + v[2][f] + v[3][f]));
+      if (lane_id() == 63)
+        for (int f = 0; f < 6; ++f)
+          if (t[f]) atomicAdd((unsigned long long*)&sg.acc[k0 * kAccF + kAccS1 + f], (unsigned long long)t[f]);
+    }
+  } else {
+    // the u-th positions of the lanes increase with the lane: equal keys are runs
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int64_t w6[6];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) w6[f] = v[u][f];
+      if (wave_seg_sum<6>(key[u], w6))
+        for (int f = 0; f < 6; ++f)
+          if (w6[f]) atomicAdd((unsigned long long*)&sg.acc[key[u] * kAccF + kAccS1 + f], (unsigned long long)w6[f]);
     }
   }
-  // one segment across the wavefront (the usual case): 32-bit DPP sums (each
-  // total is below 64 * 2^20); else the general segmented sum
-  const int k0 = __builtin_amdgcn_readfirstlane(key);
-  if (__all(key == k0)) {
-    if (k0 < 0) return;
-    int32_t t[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) t[f] = wave_sum_dpp((int32_t)v[f]);
-    if (lane_id() == 63)
-      for (int f = 0; f < 6; ++f)
-        if (t[f]) atomicAdd((unsigned long long*)&sg.acc[k0 * kAccF + kAccS1 + f], (unsigned long long)t[f]);
-    return;
-  }
-  if (wave_seg_sum<6>(key, v))
-    for (int f = 0; f < 6; ++f)
-      if (v[f]) atomicAdd((unsigned long long*)&sg.acc[key * kAccF + kAccS1 + f], (unsigned long long)v[f]);
-}
-
-// work (tuner, optional) += 17 bytes per position: grid coordinates read, side written.
-__global__ __launch_bounds__(1024) void k_assign(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
-                                                 int64_t p0, int64_t p1, int it, uint8_t* side,
-                                                 unsigned long long* work) {
-  assign_pos(sg, segpos, q, Np, p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x, p1, it, side);
   if (work && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(work, 17ull * (unsigned long long)(p1 - p0));
 }
 
@@ -874,7 +903,8 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
     const int B = kBlocks[cfg];
     unsigned long long* tw = tuned ? tune_begin(c, kTuneAssign, bucket, cfg, s) : nullptr;
     int ph = prof_begin(c, "assign", 17.0 * (double)np, s, nullptr);
-    VMO_LAUNCH(k_assign, nblocks(np, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw);
+    const int64_t packs = (p1 - (p0 & ~int64_t(3)) + 3) / 4;
+    VMO_LAUNCH(k_assign4, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw);
     prof_end(c, ph, s);
     if (tuned) tune_end(c, s);
     VMO_HIP(hipMemsetAsync(active.p, 0, 4, s));
