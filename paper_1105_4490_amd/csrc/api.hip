@@ -141,32 +141,21 @@ vmo_status vmo_bisect(vmo_ctx ctx, const float* x, int32_t k, uint64_t seed, int
   API_END
 }
 
-static void check_order_args(vmo::Ctx& C, const vmo_hypergraph* h, int mode, int order, int32_t P, int32_t t_max,
-                             const vmo_order_out* out, hipStream_t S) {
+// Host checks of an ordering job's scalars and output pointers.
+static void check_order_scalars(int mode, int order, int32_t P, int32_t t_max, const vmo_order_out* out) {
   VMO_REQUIRE(mode == VMO_NET || mode == VMO_GRAPH, "mode must be VMO_NET or VMO_GRAPH");
   VMO_REQUIRE(order == VMO_SBD || order == VMO_BBD, "order must be VMO_SBD or VMO_BBD");
   VMO_REQUIRE(P >= 1 && P <= (1 << 24), "P must be in [1, 2^24]");
   VMO_REQUIRE(t_max >= 0, "t_max must be >= 0");
   VMO_REQUIRE(out && out->vperm && out->part && out->node_heap && out->node_vptr && out->split_cut && out->n_nodes,
               "NULL output array");
-  vmo::validate_hypergraph(C, h, false, S);
-  if (mode == VMO_GRAPH) {
-    int64_t np = vmo::read1(h->net_ptr + h->l, S);
-    VMO_REQUIRE(np == 2 * (int64_t)h->l, "graph mode needs every net to be an edge {v, w}");
-    // each net of exactly two pins: net_ptr[e] = 2e is checked by the ascending
-    // pin check plus the total; a net of 1 and one of 3 pins would pass the
-    // total, so check the pointer array itself
-    std::vector<int64_t> hp((size_t)h->l + 1);
-    VMO_HIP(hipMemcpyAsync(hp.data(), h->net_ptr, 8 * hp.size(), hipMemcpyDeviceToHost, S));
-    VMO_HIP(hipStreamSynchronize(S));
-    for (int64_t e = 0; e <= h->l; ++e) VMO_REQUIRE(hp[e] == 2 * e, "graph mode needs every net to be an edge {v, w}");
-  }
 }
 
-static void run_order(vmo::Ctx& C, std::vector<vmo::JobHost>& jobs, int32_t t_max, bool plain, hipStream_t S) {
+static void run_order(vmo::Ctx& C, std::vector<vmo::JobHost>& jobs, const std::vector<int64_t>& npins, int32_t t_max,
+                      bool plain, hipStream_t S) {
   vmo::Engine e(C, S);
   e.setup(jobs);
-  e.set_edges(jobs);
+  e.set_edges(jobs, npins);
   e.run_levels(t_max, plain);
   e.finish(jobs);
 }
@@ -175,15 +164,15 @@ vmo_status vmo_order(vmo_ctx ctx, const vmo_hypergraph* h, int mode, int order, 
                      const vmo_layout_params* lp, int32_t P, uint64_t seed, int32_t t_max, const vmo_order_out* out,
                      vmo_stream stream) {
   API_BEGIN(ctx, stream)
-  check_order_args(C, h, mode, order, P, t_max, out, S);
+  check_order_scalars(mode, order, P, t_max, out);
+  VMO_REQUIRE(x || lp, "x is NULL and no layout parameters were given");
+  std::vector<int64_t> npins;
+  vmo::validate_jobs(C, {vmo::JobCheck{h, x, false, mode == VMO_GRAPH}}, npins, S);
   vmo::Buf<float> xl;
   if (!x) {
-    VMO_REQUIRE(lp != nullptr, "x is NULL and no layout parameters were given");
     xl = vmo::Buf<float>(C.pool, 4 * (size_t)h->k);
     vmo::layout(C, h, lp, xl.p, S);
     x = xl.p;
-  } else {
-    vmo::validate_finite(C, x, 4 * (int64_t)h->k, "x", S);
   }
   std::vector<vmo::JobHost> jobs(1);
   memset(&jobs[0], 0, sizeof(vmo::JobHost));
@@ -195,7 +184,7 @@ vmo_status vmo_order(vmo_ctx ctx, const vmo_hypergraph* h, int mode, int order, 
   jobs[0].seed = seed;
   jobs[0].job_index = 0;
   jobs[0].out = *out;
-  run_order(C, jobs, t_max, false, S);
+  run_order(C, jobs, npins, t_max, false, S);
   API_END
 }
 
@@ -213,11 +202,16 @@ static vmo_status order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, i
   API_BEGIN(ctx, stream)
   VMO_REQUIRE(njobs >= 1 && jobs != nullptr, "need at least one job");
   std::vector<vmo::JobHost> J(njobs);
+  std::vector<vmo::JobCheck> chk(njobs);
   for (int32_t i = 0; i < njobs; ++i) {
     const vmo_job& a = jobs[i];
-    check_order_args(C, &a.h, a.mode, a.order, a.P, t_max, &a.out, S);
-    VMO_REQUIRE(a.x != nullptr, "batch jobs need coordinates");
-    vmo::validate_finite(C, a.x, 4 * (int64_t)a.h.k, "x", S);
+    check_order_scalars(a.mode, a.order, a.P, t_max, &a.out);
+    chk[i] = vmo::JobCheck{&a.h, a.x, true, a.mode == VMO_GRAPH};
+  }
+  std::vector<int64_t> npins;
+  vmo::validate_jobs(C, chk, npins, S);
+  for (int32_t i = 0; i < njobs; ++i) {
+    const vmo_job& a = jobs[i];
     memset(&J[i], 0, sizeof(vmo::JobHost));
     J[i].h = a.h;
     J[i].mode = a.mode;
@@ -228,7 +222,7 @@ static vmo_status order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, i
     J[i].job_index = a.job_index;
     J[i].out = a.out;
   }
-  run_order(C, J, t_max, plain, S);
+  run_order(C, J, npins, t_max, plain, S);
   API_END
 }
 

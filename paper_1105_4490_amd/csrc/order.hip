@@ -840,13 +840,13 @@ void Engine::setup(const std::vector<JobHost>& jobs) {
   VMO_HIP(hipStreamSynchronize(s));
 }
 
-void Engine::set_edges(const std::vector<JobHost>& jobs) {
+void Engine::set_edges(const std::vector<JobHost>& jobs, const std::vector<int64_t>& jpins) {
   // graph-mode edges, global vertex ids; net-mode nets, global pins
   edges = Buf<int32_t>(c.pool, 2 * (E > 0 ? E : 1));
   nptr = Buf<int64_t>(c.pool, L + 1);
   int64_t npins = 0;
   for (int32_t j = 0; j < nj; ++j)
-    if (jobs[j].mode == VMO_NET) npins += read1(jobs[j].h.net_ptr + jobs[j].h.l, s);
+    if (jobs[j].mode == VMO_NET) npins += jpins[j];
   npins_ = npins;
   npins_buf = Buf<int32_t>(c.pool, npins > 0 ? npins : 1);
   jnoff = Buf<int64_t>(c.pool, nj);
@@ -860,7 +860,7 @@ void Engine::set_edges(const std::vector<JobHost>& jobs) {
         launch_offset_copy_i32(H.h.pins, edges.p + 2 * hj[j].eoff, 2 * (int64_t)H.h.l, (int32_t)hj[j].voff);
     } else {
       launch_offset_copy_ptr(H.h.net_ptr, nptr.p + hj[j].noff, (int64_t)H.h.l + 1, pinoff);
-      int64_t np = read1(H.h.net_ptr + H.h.l, s);
+      const int64_t np = jpins[j];
       if (np > 0) launch_offset_copy_i32(H.h.pins, npins_buf.p + pinoff, np, (int32_t)hj[j].voff);
       pinoff += np;
     }
@@ -897,7 +897,8 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
   // batched form (every candidate gives the same result).
   static const int kBlocks[4] = {128, 256, 512, 1024};
   const int bucket = bits_for((uint64_t)np);
-  Buf<int32_t> active(c.pool, 1);
+  Buf<int32_t> active(c.pool, (size_t)t_max + 1);  // one counter per iteration, cleared once
+  fill_i32(active.p, 0, (int64_t)t_max + 1, s);
   for (int it = 0; it <= t_max; ++it) {
     const int cfg = tuned ? tune_pick(c, kTuneAssign, bucket, 4) : 1;
     const int B = kBlocks[cfg];
@@ -907,9 +908,8 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
     VMO_LAUNCH(k_assign4, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw);
     prof_end(c, ph, s);
     if (tuned) tune_end(c, s);
-    VMO_HIP(hipMemsetAsync(active.p, 0, 4, s));
-    VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p);
-    if (read1(active.p, s) == 0) break;
+    VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p + it);
+    if (read1(active.p + it, s) == 0) break;
   }
 }
 

@@ -79,7 +79,8 @@ class Engine {
  public:
   Engine(Ctx& c, hipStream_t s) : c(c), s(s) {}
   void setup(const std::vector<JobHost>& jobs);
-  void set_edges(const std::vector<JobHost>& jobs);
+  // jpins[j]: net_ptr[l] of job j (its pin count)
+  void set_edges(const std::vector<JobHost>& jobs, const std::vector<int64_t>& jpins);
   void run_levels(int t_max, bool plain);
   void finish(const std::vector<JobHost>& jobs);
   // emission for the jobs `slots` of the job table (their work is done)

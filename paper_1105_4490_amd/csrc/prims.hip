@@ -564,6 +564,76 @@ void validate_hypergraph(Ctx& c, const vmo_hypergraph* h, bool positive_wc, hipS
   VMO_REQUIRE(!(b & 8), positive_wc ? "weights and costs must be finite and > 0" : "weights and costs must be finite and >= 0");
 }
 
+// ----------------------------------------------------- batched validation ----
+__global__ void k_net_ends(const int64_t* const* ptrs, const int32_t* ls, int32_t nj, int64_t* ends) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nj; j += gridDim.x * blockDim.x)
+    ends[j] = ptrs[j][ls[j]];
+}
+// graph mode: every net is an edge, net_ptr[e] = 2e
+__global__ void k_check_edges(const int64_t* ptr, int32_t l, int* bad) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= l; e += (int64_t)gridDim.x * blockDim.x)
+    if (ptr[e] != 2 * e) atomicOr(bad, 32);
+}
+
+void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_t>& npins, hipStream_t s) {
+  const int32_t nj = (int32_t)jobs.size();
+  npins.assign(nj, 0);
+  for (int32_t j = 0; j < nj; ++j) {
+    const vmo_hypergraph* h = jobs[j].h;
+    const std::string who = nj > 1 ? "job " + std::to_string(j) + ": " : "";
+    VMO_REQUIRE(h != nullptr, who + "hypergraph is NULL");
+    VMO_REQUIRE(h->k >= 1, who + "hypergraph needs k >= 1");
+    VMO_REQUIRE(h->l >= 0, who + "hypergraph needs l >= 0");
+    VMO_REQUIRE(h->net_ptr != nullptr, who + "net_ptr is NULL");
+  }
+  Buf<int> bad(c.pool, nj);
+  Buf<int64_t> ends(c.pool, nj);
+  Buf<const int64_t*> dptr(c.pool, nj);
+  Buf<int32_t> dl(c.pool, nj);
+  std::vector<const int64_t*> hptr(nj);
+  std::vector<int32_t> hl(nj);
+  for (int32_t j = 0; j < nj; ++j) { hptr[j] = jobs[j].h->net_ptr; hl[j] = jobs[j].h->l; }
+  VMO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int) * nj, s));
+  VMO_HIP(hipMemcpyAsync(dptr.p, hptr.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(dl.p, hl.data(), sizeof(int32_t) * nj, hipMemcpyHostToDevice, s));
+  // 1: pointer arrays (start at 0, non-decreasing) and their ends
+  for (int32_t j = 0; j < nj; ++j)
+    if (hl[j] > 0) VMO_LAUNCH(k_check_ptr, gs_blocks(hl[j]), 256, 0, s, hptr[j], hl[j], bad.p + j);
+  VMO_LAUNCH(k_net_ends, (unsigned)((nj + 255) / 256), 256, 0, s, dptr.p, dl.p, nj, ends.p);
+  std::vector<int> hb(nj);
+  VMO_HIP(hipMemcpyAsync(hb.data(), bad.p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipMemcpyAsync(npins.data(), ends.p, sizeof(int64_t) * nj, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  for (int32_t j = 0; j < nj; ++j) {
+    const std::string who = nj > 1 ? "job " + std::to_string(j) + ": " : "";
+    VMO_REQUIRE(hb[j] == 0, who + "net_ptr must start at 0 and be non-decreasing");
+    VMO_REQUIRE(npins[j] >= 0 && npins[j] < (int64_t(1) << 31) * 2, who + "too many pins");
+    VMO_REQUIRE(npins[j] == 0 || jobs[j].h->pins != nullptr, who + "pins is NULL");
+    VMO_REQUIRE(!jobs[j].x_required || jobs[j].x != nullptr, who + "x is NULL");
+  }
+  // 2: pins, weights, costs, coordinates, graph-mode edges
+  for (int32_t j = 0; j < nj; ++j) {
+    const vmo_hypergraph* h = jobs[j].h;
+    int* bj = bad.p + j;
+    if (npins[j] > 0) VMO_LAUNCH(k_check_pins, gs_blocks(npins[j]), 256, 0, s, h->net_ptr, h->pins, h->l, h->k, npins[j], bj);
+    if (h->w) VMO_LAUNCH(k_check_vals, gs_blocks(h->k), 256, 0, s, h->w, (int64_t)h->k, 0, bj);
+    if (h->c && h->l > 0) VMO_LAUNCH(k_check_vals, gs_blocks(h->l), 256, 0, s, h->c, (int64_t)h->l, 0, bj);
+    if (jobs[j].x) VMO_LAUNCH(k_check_finite, gs_blocks(4 * (int64_t)h->k), 256, 0, s, jobs[j].x, 4 * (int64_t)h->k, bj);
+    if (jobs[j].graph) VMO_LAUNCH(k_check_edges, gs_blocks((int64_t)h->l + 1), 256, 0, s, h->net_ptr, h->l, bj);
+  }
+  VMO_HIP(hipMemcpyAsync(hb.data(), bad.p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
+  VMO_HIP(hipStreamSynchronize(s));
+  for (int32_t j = 0; j < nj; ++j) {
+    const std::string who = nj > 1 ? "job " + std::to_string(j) + ": " : "";
+    const int b = hb[j];
+    VMO_REQUIRE(!(b & 2), who + "a pin is out of range [0, k)");
+    VMO_REQUIRE(!(b & 4), who + "pins of a net must be strictly ascending");
+    VMO_REQUIRE(!(b & 8), who + "weights and costs must be finite and >= 0");
+    VMO_REQUIRE(!(b & 16), who + "x must be finite");
+    VMO_REQUIRE(!(b & 32), who + "graph mode needs every net to be an edge {v, w}");
+  }
+}
+
 void validate_finite(Ctx& c, const float* x, int64_t n, const char* what, hipStream_t s) {
   VMO_REQUIRE(x != nullptr, std::string(what) + " is NULL");
   Buf<int> bad(c.pool, 1);

@@ -258,6 +258,18 @@ void iota_i32(int32_t* p, int64_t n, hipStream_t s);
 void validate_hypergraph(Ctx& c, const vmo_hypergraph* h, bool positive_wc, hipStream_t s);
 void validate_finite(Ctx& c, const float* x, int64_t n, const char* what, hipStream_t s);
 
+// Validation of several ordering jobs with two host round trips in all:
+// hypergraph structure, weights and costs (>= 0), coordinates (finite, if
+// given), graph-mode edges (net_ptr[e] = 2e).  npins receives net_ptr[l] of
+// each job.  Errors name the job.
+struct JobCheck {
+  const vmo_hypergraph* h;
+  const float* x;       // coordinates to check, or NULL
+  bool x_required;
+  bool graph;
+};
+void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_t>& npins, hipStream_t s);
+
 // Transpose of a CSR incidence (rows -> columns): out row j lists, ascending,
 // the input rows containing j.  nrows, ncols, ptr [nrows+1], idx -> optr
 // [ncols+1], oidx [ptr[nrows]].

@@ -238,3 +238,14 @@ def test_order_batch_full_count_sampled(ctx):
         x = vmo_gen.random_points(g.m, 7000 + i, clusters=3)
         ref = oracle.order(h, x, parts, 4, mode=oracle.NET_MODE, ord=oracle.SBD, job=i)
         compare_order(outs[i], ref, oracle.NET_MODE, h.k, h.l)
+
+
+def test_order_batch_rejects_bad_job(ctx):
+    """One invalid job (a pin out of range) fails the batch and is named."""
+    import paper_1105_4490_amd as P
+    jobs, _ = mixed_jobs(5, 8)
+    bad = oracle.Hypergraph(3, 1, np.array([0, 2], np.int64), np.array([0, 7], np.int32))
+    jobs[3] = {"h": dev_h(bad), "x": dev_x(np.zeros((4, 3), np.float32)), "P": 2, "seed": 1, "mode": 0, "order": 0,
+               "job_index": 3}
+    with pytest.raises(P.VmoError, match="job 3"):
+        ctx.order_batch(jobs)
