@@ -840,6 +840,41 @@ void Engine::setup(const std::vector<JobHost>& jobs) {
   VMO_HIP(hipStreamSynchronize(s));
 }
 
+// Copies of many arrays with an offset added, one launch per element type: a
+// table of (source, destination offset, count, add) with cumulative counts.
+struct OffCopy {
+  const void* src;
+  int64_t dst, n, add;
+};
+template <class T>
+__global__ void k_offset_copy_all(const OffCopy* tab, const int64_t* cum, int32_t nt, int64_t total, T* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nt;  // last t with cum[t] <= i
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (cum[mid] <= i) lo = mid; else hi = mid;
+    }
+    const OffCopy& c = tab[lo];
+    const int64_t e = i - cum[lo];
+    out[c.dst + e] = static_cast<const T*>(c.src)[e] + (T)c.add;
+  }
+}
+
+template <class T>
+static void offset_copy_all(Ctx& c, const std::vector<OffCopy>& tab, T* out, hipStream_t s) {
+  if (tab.empty()) return;
+  const int32_t nt = (int32_t)tab.size();
+  std::vector<int64_t> cum(nt);
+  int64_t tot = 0;
+  for (int32_t t = 0; t < nt; ++t) { cum[t] = tot; tot += tab[t].n; }
+  if (tot == 0) return;
+  Buf<OffCopy> dt(c.pool, nt);
+  Buf<int64_t> dc(c.pool, nt);
+  VMO_HIP(hipMemcpyAsync(dt.p, tab.data(), sizeof(OffCopy) * nt, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(dc.p, cum.data(), 8 * nt, hipMemcpyHostToDevice, s));
+  VMO_LAUNCH((k_offset_copy_all<T>), gsz(tot), kT, 0, s, dt.p, dc.p, nt, tot, out);
+}
+
 void Engine::set_edges(const std::vector<JobHost>& jobs, const std::vector<int64_t>& jpins) {
   // graph-mode edges, global vertex ids; net-mode nets, global pins
   edges = Buf<int32_t>(c.pool, 2 * (E > 0 ? E : 1));
@@ -851,20 +886,24 @@ void Engine::set_edges(const std::vector<JobHost>& jobs, const std::vector<int64
   npins_buf = Buf<int32_t>(c.pool, npins > 0 ? npins : 1);
   jnoff = Buf<int64_t>(c.pool, nj);
   std::vector<int64_t> hnoff(nj);
+  std::vector<OffCopy> c32, c64, cpin;
   int64_t pinoff = 0;
   for (int32_t j = 0; j < nj; ++j) {
     const JobHost& H = jobs[j];
     hnoff[j] = hj[j].noff;
     if (H.mode == VMO_GRAPH) {
-      if (H.h.l > 0)
-        launch_offset_copy_i32(H.h.pins, edges.p + 2 * hj[j].eoff, 2 * (int64_t)H.h.l, (int32_t)hj[j].voff);
+      if (H.h.l > 0) c32.push_back(OffCopy{H.h.pins, 2 * hj[j].eoff, 2 * (int64_t)H.h.l, hj[j].voff});
     } else {
-      launch_offset_copy_ptr(H.h.net_ptr, nptr.p + hj[j].noff, (int64_t)H.h.l + 1, pinoff);
+      // l + 1 pointer entries; the last one equals the next job's first
+      c64.push_back(OffCopy{H.h.net_ptr, hj[j].noff, (int64_t)H.h.l + 1, pinoff});
       const int64_t np = jpins[j];
-      if (np > 0) launch_offset_copy_i32(H.h.pins, npins_buf.p + pinoff, np, (int32_t)hj[j].voff);
+      if (np > 0) cpin.push_back(OffCopy{H.h.pins, pinoff, np, hj[j].voff});
       pinoff += np;
     }
   }
+  offset_copy_all<int32_t>(c, c32, edges.p, s);
+  offset_copy_all<int64_t>(c, c64, nptr.p, s);
+  offset_copy_all<int32_t>(c, cpin, npins_buf.p, s);
   VMO_HIP(hipMemcpyAsync(jnoff.p, hnoff.data(), 8 * nj, hipMemcpyHostToDevice, s));
 }
 

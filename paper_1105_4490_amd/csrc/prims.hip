@@ -565,19 +565,90 @@ void validate_hypergraph(Ctx& c, const vmo_hypergraph* h, bool positive_wc, hipS
 }
 
 // ----------------------------------------------------- batched validation ----
-__global__ void k_net_ends(const int64_t* const* ptrs, const int32_t* ls, int32_t nj, int64_t* ends) {
-  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nj; j += gridDim.x * blockDim.x)
-    ends[j] = ptrs[j][ls[j]];
+// Checks of many jobs in one launch each: a table of jobs with cumulative
+// element offsets; a thread finds its job by bisection.
+struct CheckJob {
+  const int64_t* ptr;
+  const int32_t* pins;
+  const float* w;
+  const float* c;
+  const float* x;
+  int32_t k, l;
+  int32_t graph, pad;
+  int64_t np;
+};
+__device__ __forceinline__ int32_t job_of(const int64_t* cum, int32_t nj, int64_t i) {
+  int32_t lo = 0, hi = nj;  // last j with cum[j] <= i
+  while (hi - lo > 1) {
+    int32_t mid = (lo + hi) >> 1;
+    if (cum[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
 }
-// graph mode: every net is an edge, net_ptr[e] = 2e
-__global__ void k_check_edges(const int64_t* ptr, int32_t l, int* bad) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= l; e += (int64_t)gridDim.x * blockDim.x)
-    if (ptr[e] != 2 * e) atomicOr(bad, 32);
+// pass 1: pointer arrays (start at 0, non-decreasing) over cum = prefix of l
+__global__ void k_check_ptr_all(const CheckJob* jb, const int64_t* cum, int32_t nj, int64_t total, int* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = job_of(cum, nj, i);
+    const int64_t e = i - cum[j];
+    const int64_t* ptr = jb[j].ptr;
+    if (ptr[e + 1] < ptr[e] || (e == 0 && ptr[0] != 0)) atomicOr(&bad[j], 1);
+  }
+}
+// pass 2: pins (range, ascending in a net) over cum = prefix of np
+__global__ void k_check_pins_all(const CheckJob* jb, const int64_t* cum, int32_t nj, int64_t total, int* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = job_of(cum, nj, i);
+    const CheckJob& J = jb[j];
+    const int64_t p = i - cum[j];
+    const int32_t v = J.pins[p];
+    if (v < 0 || v >= J.k) { atomicOr(&bad[j], 2); continue; }
+    int32_t lo = 0, hi = J.l;  // last e with ptr[e] <= p
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (J.ptr[mid] <= p) lo = mid; else hi = mid;
+    }
+    if (p > J.ptr[lo] && J.pins[p - 1] >= v) atomicOr(&bad[j], 4);
+  }
+}
+// pass 2: per vertex (weights, 4 coordinates) over cum = prefix of k
+__global__ void k_check_vertices_all(const CheckJob* jb, const int64_t* cum, int32_t nj, int64_t total, int* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = job_of(cum, nj, i);
+    const CheckJob& J = jb[j];
+    const int64_t v = i - cum[j];
+    if (J.w) {
+      const float a = J.w[v];
+      if (!(a >= 0.0f) || !(a < __builtin_inff())) atomicOr(&bad[j], 8);
+    }
+    if (J.x)
+      for (int d = 0; d < 4; ++d) {
+        const float a = J.x[(int64_t)d * J.k + v];
+        if (!(a == a) || a == __builtin_inff() || a == -__builtin_inff()) atomicOr(&bad[j], 16);
+      }
+  }
+}
+// pass 2: per net (costs, graph-mode edge pointers) over cum = prefix of l + 1
+__global__ void k_check_nets_all(const CheckJob* jb, const int64_t* cum, int32_t nj, int64_t total, int* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = job_of(cum, nj, i);
+    const CheckJob& J = jb[j];
+    const int64_t e = i - cum[j];  // 0..l
+    if (J.c && e < J.l) {
+      const float a = J.c[e];
+      if (!(a >= 0.0f) || !(a < __builtin_inff())) atomicOr(&bad[j], 8);
+    }
+    if (J.graph && J.ptr[e] != 2 * e) atomicOr(&bad[j], 32);
+  }
+}
+__global__ void k_net_ends_all(const CheckJob* jb, int32_t nj, int64_t* ends) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nj; j += gridDim.x * blockDim.x)
+    ends[j] = jb[j].ptr[jb[j].l];
 }
 
 void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_t>& npins, hipStream_t s) {
   const int32_t nj = (int32_t)jobs.size();
   npins.assign(nj, 0);
+  std::vector<CheckJob> hj(nj);
   for (int32_t j = 0; j < nj; ++j) {
     const vmo_hypergraph* h = jobs[j].h;
     const std::string who = nj > 1 ? "job " + std::to_string(j) + ": " : "";
@@ -585,21 +656,21 @@ void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_
     VMO_REQUIRE(h->k >= 1, who + "hypergraph needs k >= 1");
     VMO_REQUIRE(h->l >= 0, who + "hypergraph needs l >= 0");
     VMO_REQUIRE(h->net_ptr != nullptr, who + "net_ptr is NULL");
+    VMO_REQUIRE(!jobs[j].x_required || jobs[j].x != nullptr, who + "x is NULL");
+    hj[j] = CheckJob{h->net_ptr, h->pins, h->w, h->c, jobs[j].x, h->k, h->l, jobs[j].graph ? 1 : 0, 0, 0};
   }
+  Buf<CheckJob> dj(c.pool, nj);
   Buf<int> bad(c.pool, nj);
-  Buf<int64_t> ends(c.pool, nj);
-  Buf<const int64_t*> dptr(c.pool, nj);
-  Buf<int32_t> dl(c.pool, nj);
-  std::vector<const int64_t*> hptr(nj);
-  std::vector<int32_t> hl(nj);
-  for (int32_t j = 0; j < nj; ++j) { hptr[j] = jobs[j].h->net_ptr; hl[j] = jobs[j].h->l; }
+  Buf<int64_t> ends(c.pool, nj), cum(c.pool, nj);
+  std::vector<int64_t> hc(nj);
   VMO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int) * nj, s));
-  VMO_HIP(hipMemcpyAsync(dptr.p, hptr.data(), sizeof(void*) * nj, hipMemcpyHostToDevice, s));
-  VMO_HIP(hipMemcpyAsync(dl.p, hl.data(), sizeof(int32_t) * nj, hipMemcpyHostToDevice, s));
-  // 1: pointer arrays (start at 0, non-decreasing) and their ends
-  for (int32_t j = 0; j < nj; ++j)
-    if (hl[j] > 0) VMO_LAUNCH(k_check_ptr, gs_blocks(hl[j]), 256, 0, s, hptr[j], hl[j], bad.p + j);
-  VMO_LAUNCH(k_net_ends, (unsigned)((nj + 255) / 256), 256, 0, s, dptr.p, dl.p, nj, ends.p);
+  VMO_HIP(hipMemcpyAsync(dj.p, hj.data(), sizeof(CheckJob) * nj, hipMemcpyHostToDevice, s));
+  // pass 1: pointer arrays and their ends
+  int64_t tot = 0;
+  for (int32_t j = 0; j < nj; ++j) { hc[j] = tot; tot += hj[j].l; }
+  VMO_HIP(hipMemcpyAsync(cum.p, hc.data(), 8 * nj, hipMemcpyHostToDevice, s));
+  if (tot > 0) VMO_LAUNCH(k_check_ptr_all, gs_blocks(tot), 256, 0, s, dj.p, cum.p, nj, tot, bad.p);
+  VMO_LAUNCH(k_net_ends_all, (unsigned)((nj + 255) / 256), 256, 0, s, dj.p, nj, ends.p);
   std::vector<int> hb(nj);
   VMO_HIP(hipMemcpyAsync(hb.data(), bad.p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
   VMO_HIP(hipMemcpyAsync(npins.data(), ends.p, sizeof(int64_t) * nj, hipMemcpyDeviceToHost, s));
@@ -609,18 +680,24 @@ void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_
     VMO_REQUIRE(hb[j] == 0, who + "net_ptr must start at 0 and be non-decreasing");
     VMO_REQUIRE(npins[j] >= 0 && npins[j] < (int64_t(1) << 31) * 2, who + "too many pins");
     VMO_REQUIRE(npins[j] == 0 || jobs[j].h->pins != nullptr, who + "pins is NULL");
-    VMO_REQUIRE(!jobs[j].x_required || jobs[j].x != nullptr, who + "x is NULL");
+    hj[j].np = npins[j];
   }
-  // 2: pins, weights, costs, coordinates, graph-mode edges
+  VMO_HIP(hipMemcpyAsync(dj.p, hj.data(), sizeof(CheckJob) * nj, hipMemcpyHostToDevice, s));
+  // pass 2: pins, then vertices (weights, coordinates), then nets (costs, edges)
+  Buf<int64_t> cum2(c.pool, nj), cum3(c.pool, nj), cum4(c.pool, nj);
+  std::vector<int64_t> h2(nj), h3(nj), h4(nj);
+  int64_t t2 = 0, t3 = 0, t4 = 0;
   for (int32_t j = 0; j < nj; ++j) {
-    const vmo_hypergraph* h = jobs[j].h;
-    int* bj = bad.p + j;
-    if (npins[j] > 0) VMO_LAUNCH(k_check_pins, gs_blocks(npins[j]), 256, 0, s, h->net_ptr, h->pins, h->l, h->k, npins[j], bj);
-    if (h->w) VMO_LAUNCH(k_check_vals, gs_blocks(h->k), 256, 0, s, h->w, (int64_t)h->k, 0, bj);
-    if (h->c && h->l > 0) VMO_LAUNCH(k_check_vals, gs_blocks(h->l), 256, 0, s, h->c, (int64_t)h->l, 0, bj);
-    if (jobs[j].x) VMO_LAUNCH(k_check_finite, gs_blocks(4 * (int64_t)h->k), 256, 0, s, jobs[j].x, 4 * (int64_t)h->k, bj);
-    if (jobs[j].graph) VMO_LAUNCH(k_check_edges, gs_blocks((int64_t)h->l + 1), 256, 0, s, h->net_ptr, h->l, bj);
+    h2[j] = t2; t2 += npins[j];
+    h3[j] = t3; t3 += hj[j].k;
+    h4[j] = t4; t4 += (int64_t)hj[j].l + 1;
   }
+  VMO_HIP(hipMemcpyAsync(cum2.p, h2.data(), 8 * nj, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cum3.p, h3.data(), 8 * nj, hipMemcpyHostToDevice, s));
+  VMO_HIP(hipMemcpyAsync(cum4.p, h4.data(), 8 * nj, hipMemcpyHostToDevice, s));
+  if (t2 > 0) VMO_LAUNCH(k_check_pins_all, gs_blocks(t2), 256, 0, s, dj.p, cum2.p, nj, t2, bad.p);
+  VMO_LAUNCH(k_check_vertices_all, gs_blocks(t3), 256, 0, s, dj.p, cum3.p, nj, t3, bad.p);
+  VMO_LAUNCH(k_check_nets_all, gs_blocks(t4), 256, 0, s, dj.p, cum4.p, nj, t4, bad.p);
   VMO_HIP(hipMemcpyAsync(hb.data(), bad.p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
   VMO_HIP(hipStreamSynchronize(s));
   for (int32_t j = 0; j < nj; ++j) {
