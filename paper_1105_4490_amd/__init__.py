@@ -8,6 +8,7 @@ there is no fallback.
 from __future__ import annotations
 
 import ctypes as C
+import functools
 import os
 from dataclasses import dataclass
 
@@ -49,6 +50,27 @@ class OrderOut(C.Structure):
 class Job(C.Structure):
     _fields_ = [("h", Hypergraph), ("mode", C.c_int32), ("order", C.c_int32), ("x", C.c_void_p), ("P", C.c_int32),
                 ("seed", C.c_uint64), ("job_index", C.c_uint64), ("out", OrderOut)]
+
+
+@functools.lru_cache(maxsize=1)
+def _job_dtype():
+    """numpy record type with the memory layout of vmo_job (from the ctypes
+    definition), for filling many jobs at once."""
+    import numpy as np
+    names, fmts, offsets = [], [], []
+    for f, t in Hypergraph._fields_:
+        names.append(f)
+        fmts.append(np.int32 if t is C.c_int32 else np.uint64)
+        offsets.append(Job.h.offset + getattr(Hypergraph, f).offset)
+    for f in ("mode", "order", "x", "P", "seed", "job_index"):
+        names.append(f)
+        fmts.append(np.int32 if f in ("mode", "order", "P") else np.uint64)
+        offsets.append(getattr(Job, f).offset)
+    for f, _ in OrderOut._fields_:
+        names.append("o_" + f)
+        fmts.append(np.uint64)
+        offsets.append(Job.out.offset + getattr(OrderOut, f).offset)
+    return np.dtype({"names": names, "formats": fmts, "offsets": offsets, "itemsize": C.sizeof(Job)})
 
 
 class ProfileEntry(C.Structure):
@@ -119,6 +141,11 @@ class DeviceHypergraph:
     def cstruct(self) -> Hypergraph:
         return Hypergraph(self.k, self.l, _ptr(self.net_ptr), _ptr(self.pins) if self.pins.numel() else None,
                           _ptr(self.w), _ptr(self.c))
+
+    def cptrs(self):
+        """Device addresses (net_ptr, pins, w, c); 0 for an absent array."""
+        return (self.net_ptr.data_ptr(), self.pins.data_ptr() if self.pins.numel() else 0,
+                self.w.data_ptr() if self.w is not None else 0, self.c.data_ptr() if self.c is not None else 0)
 
     @staticmethod
     def from_host(h, device="cuda"):
@@ -249,23 +276,53 @@ class Context:
         return o
 
     def order_batch(self, jobs, t_max: int = 32, plain: bool = False):
-        """jobs: list of dicts with h, x, P, seed, mode, order, job_index."""
-        outs = []
-        arr = (Job * len(jobs))()
-        keep = []
-        for i, jb in enumerate(jobs):
-            h = jb["h"]
-            o, s = self._out(h, jb["P"], jb.get("mode", NET), h.net_ptr.device)
-            hs = h.cstruct()
-            keep.append((o, s, hs))
-            arr[i] = Job(hs, jb.get("mode", NET), jb.get("order", SBD), _ptr(jb["x"]).value, jb["P"], jb["seed"],
-                         jb.get("job_index", i), s)
-            outs.append(o)
+        """jobs: list of dicts with h, x, P, seed, mode, order, job_index.  Outputs
+        of all jobs share one allocation per array kind (views per job)."""
+        import numpy as np
+        nj = len(jobs)
+        dev = jobs[0]["h"].net_ptr.device
+        k = np.array([jb["h"].k for jb in jobs], np.int64)
+        l = np.array([jb["h"].l for jb in jobs], np.int64)
+        P = np.array([jb["P"] for jb in jobs], np.int64)
+        mode = np.array([jb.get("mode", NET) for jb in jobs], np.int64)
+        net = mode == NET
+        nl = np.where(net, np.maximum(l, 1), 0)
+        sizes = {"vperm": k, "part": k, "nperm": nl, "node_heap": 4 * P, "node_vptr": 4 * P + 1,
+                 "node_nptr": np.where(net, 4 * P + 2, 0), "split_cut": 4 * P, "n_nodes": np.ones(nj, np.int64)}
+        flat, offs = {}, {}
+        for f, sz in sizes.items():
+            dt = torch.float64 if f == "split_cut" else torch.int32
+            flat[f] = torch.empty(max(int(sz.sum()), 1), dtype=dt, device=dev)
+            offs[f] = np.concatenate([[0], np.cumsum(sz)[:-1]])
+        arr = np.zeros(nj, dtype=_job_dtype())
+        hp = [jb["h"].cptrs() for jb in jobs]
+        arr["k"], arr["l"] = k, l
+        arr["net_ptr"] = [a[0] for a in hp]
+        arr["pins"] = [a[1] for a in hp]
+        arr["w"] = [a[2] for a in hp]
+        arr["c"] = [a[3] for a in hp]
+        arr["mode"] = mode
+        arr["order"] = [jb.get("order", SBD) for jb in jobs]
+        arr["x"] = [jb["x"].data_ptr() for jb in jobs]
+        arr["P"] = P
+        arr["seed"] = [jb["seed"] for jb in jobs]
+        arr["job_index"] = [jb.get("job_index", i) for i, jb in enumerate(jobs)]
+        for f in sizes:
+            ptrs = flat[f].data_ptr() + offs[f] * flat[f].element_size()
+            if f in ("nperm", "node_nptr"):
+                ptrs = np.where(net, ptrs, 0)
+            arr["o_" + f] = ptrs
         fn = lib().vmo_order_batch_plain if plain else lib().vmo_order_batch
-        self._check(fn(self.h, C.c_int32(len(jobs)), arr, C.c_int32(t_max), _stream()))
-        for jb, o in zip(jobs, outs):
-            if o["nperm"] is not None:
-                o["nperm"] = o["nperm"][:jb["h"].l]
+        self._check(fn(self.h, C.c_int32(nj), C.c_void_p(arr.ctypes.data), C.c_int32(t_max), _stream()))
+        views = {f: torch.split(flat[f][:int(sizes[f].sum())], sizes[f].tolist()) for f in sizes}
+        outs = []
+        for i in range(nj):
+            o = {f: views[f][i] for f in sizes}
+            if net[i]:
+                o["nperm"] = o["nperm"][:int(l[i])]
+            else:
+                o["nperm"] = o["node_nptr"] = None
+            outs.append(o)
         return outs
 
     # ---------------------------------------------------------------- layout --

@@ -846,17 +846,29 @@ struct OffCopy {
   const void* src;
   int64_t dst, n, add;
 };
+// A wavefront copies 64 * 16 consecutive elements of the concatenation: one
+// table lookup per lane for its first element, then forward steps.
 template <class T>
 __global__ void k_offset_copy_all(const OffCopy* tab, const int64_t* cum, int32_t nt, int64_t total, T* out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+  constexpr int kPer = 16;
+  const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  for (int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63)) * kPer; w0 < total;
+       w0 += nthr * kPer) {
+    int64_t i = w0 + lane;  // elements w0 + lane + 64 r, r < kPer: coalesced across the lanes
+    if (i >= total) continue;
     int32_t lo = 0, hi = nt;  // last t with cum[t] <= i
     while (hi - lo > 1) {
       int32_t mid = (lo + hi) >> 1;
       if (cum[mid] <= i) lo = mid; else hi = mid;
     }
-    const OffCopy& c = tab[lo];
-    const int64_t e = i - cum[lo];
-    out[c.dst + e] = static_cast<const T*>(c.src)[e] + (T)c.add;
+    int32_t t = lo;
+    for (int r = 0; r < kPer && i < total; ++r, i += 64) {
+      while (t + 1 < nt && cum[t + 1] <= i) ++t;
+      const OffCopy& c = tab[t];
+      const int64_t e = i - cum[t];
+      out[c.dst + e] = static_cast<const T*>(c.src)[e] + (T)c.add;
+    }
   }
 }
 
@@ -872,7 +884,7 @@ static void offset_copy_all(Ctx& c, const std::vector<OffCopy>& tab, T* out, hip
   Buf<int64_t> dc(c.pool, nt);
   VMO_HIP(hipMemcpyAsync(dt.p, tab.data(), sizeof(OffCopy) * nt, hipMemcpyHostToDevice, s));
   VMO_HIP(hipMemcpyAsync(dc.p, cum.data(), 8 * nt, hipMemcpyHostToDevice, s));
-  VMO_LAUNCH((k_offset_copy_all<T>), gsz(tot), kT, 0, s, dt.p, dc.p, nt, tot, out);
+  VMO_LAUNCH((k_offset_copy_all<T>), nblocks((tot + 15) / 16, kT), kT, 0, s, dt.p, dc.p, nt, tot, out);
 }
 
 void Engine::set_edges(const std::vector<JobHost>& jobs, const std::vector<int64_t>& jpins) {

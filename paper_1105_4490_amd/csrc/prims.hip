@@ -602,12 +602,15 @@ __global__ void k_check_pins_all(const CheckJob* jb, const int64_t* cum, int32_t
     const int64_t p = i - cum[j];
     const int32_t v = J.pins[p];
     if (v < 0 || v >= J.k) { atomicOr(&bad[j], 2); continue; }
+    // a descent from the previous pin is an error unless p starts a net:
+    // only then is the net of p looked up
+    if (p == 0 || J.pins[p - 1] < v) continue;
     int32_t lo = 0, hi = J.l;  // last e with ptr[e] <= p
     while (hi - lo > 1) {
       int32_t mid = (lo + hi) >> 1;
       if (J.ptr[mid] <= p) lo = mid; else hi = mid;
     }
-    if (p > J.ptr[lo] && J.pins[p - 1] >= v) atomicOr(&bad[j], 4);
+    if (p > J.ptr[lo]) atomicOr(&bad[j], 4);
   }
 }
 // pass 2: per vertex (weights, 4 coordinates) over cum = prefix of k

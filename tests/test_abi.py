@@ -38,3 +38,20 @@ def test_binding_refuses_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(P, "_lib", None)
     with pytest.raises(ImportError):
         P.lib()
+
+
+def test_batch_job_records_match_the_c_layout():
+    """The numpy records order_batch fills are byte-identical to ctypes vmo_job structs."""
+    import ctypes as C
+    import numpy as np
+    import paper_1105_4490_amd as P
+    vals = []
+    arr = np.zeros(3, dtype=P._job_dtype())
+    cj = (P.Job * 3)()
+    for i in range(3):
+        h = P.Hypergraph(10 + i, 20 + i, 0x1000 + i, 0x2000 + i, 0, 0x3000 + i)
+        o = P.OrderOut(0x4000 + i, 0, 0x5000 + i, 0x6000 + i, 0x7000 + i, 0, 0x8000 + i, 0x9000 + i)
+        cj[i] = P.Job(h, i % 2, 1 - i % 2, 0xA000 + i, 7 + i, 99 + i, 5 + i, o)
+        arr[i] = (10 + i, 20 + i, 0x1000 + i, 0x2000 + i, 0, 0x3000 + i, i % 2, 1 - i % 2, 0xA000 + i, 7 + i,
+                  99 + i, 5 + i, 0x4000 + i, 0, 0x5000 + i, 0x6000 + i, 0x7000 + i, 0, 0x8000 + i, 0x9000 + i)
+    assert arr.tobytes() == C.string_at(cj, C.sizeof(cj))
