@@ -36,7 +36,11 @@ sys.path.insert(0, ROOT)
 P_PARTS = 64
 N_SIDE = 64
 SEED = 1
-FLOPS_PER_INTERACTION = 23   # 4 sub, 4 mul + 3 add (r^2), 2 mul (2 W w), 1 mul (r^4), 1 div, 4 mul + 4 add
+FLOPS_PER_INTERACTION = 23   # 4 sub, r^2 (1 mul + 3 fma), 2 mul (2 W w), 1 mul (r^4), 1 div, 4 fma
+# HBM bytes per walk launch (average over one step of this workload), from two
+# rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
+# plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
+WALK_TRAFFIC_BYTES = 43.99e6 + 9.40e6
 PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
@@ -117,7 +121,8 @@ def main():
     flops = FLOPS_PER_INTERACTION * walk["work"]
     w_tflops = flops / (walk["total_ms"] * 1e-3) / 1e12 if walk["total_ms"] > 0 else 0.0
     roof = {"bound": "alu", "kernel": "k_walk", "achieved": round(w_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(w_tflops / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(w_tflops / PEAK_FP32_VALU_TFLOPS, 4),
+            "traffic": WALK_TRAFFIC_BYTES if args.side == N_SIDE else None,
             "launches": walk["launches"], "avg_launch_ms": round(walk["total_ms"] / max(walk["launches"], 1), 4),
             "share_of_step": round(walk["total_ms"] / (1e3 * dt), 4),
             "interactions_per_step": walk["work"] / args.steps}
