@@ -388,11 +388,12 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
                                                      float4* __restrict__ P, NodeView nd, int32_t* __restrict__ nn) {
   __shared__ uint64_t key[kSmallK];
   __shared__ __align__(16) unsigned char rb[32768];
+  // per (round, wavefront, digit) counts of the sort, then their offsets
+  __shared__ uint16_t cnt[4][16][256];
+  __shared__ int32_t run[256];
+  __shared__ int32_t rtot[4][256];
   // during the sort
   int32_t* val = reinterpret_cast<int32_t*>(rb);                // [4096]
-  uint16_t* wc = reinterpret_cast<uint16_t*>(rb + 16384);       // [16][256]
-  int32_t* run = reinterpret_cast<int32_t*>(rb + 24576);        // [256]
-  int32_t* hist = reinterpret_cast<int32_t*>(rb + 25600);       // [256]
   // after the sort
   int8_t* cpl = reinterpret_cast<int8_t*>(rb);                  // [k + 1]
   int8_t* ell = reinterpret_cast<int8_t*>(rb + 4112);           // [k]
@@ -411,16 +412,19 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
   }
   __syncthreads();
 
-  // stable LSD radix sort, 8-bit digits; item r of thread t is position
-  // r * 1024 + t, ranks as in the multi-block sort (rounds in order, waves in
-  // order, lanes with equal digits found by ballots)
+  // stable LSD radix sort, 8-bit digits.  Item r of thread t is position
+  // r * 1024 + t.  Each pass ranks all four rounds at once: lanes of a wave
+  // with equal digits are found by ballots, the (round, wave, digit) counts
+  // are turned into offsets by one scan per digit in (round, wave) order, and
+  // the digit bases by a scan over the digits: a stable order.
   const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
-  const int rounds = (k + kSTB - 1) / kSTB;
+  uint32_t* cnt32 = reinterpret_cast<uint32_t*>(&cnt[0][0][0]);
+  const int rounds = (k + kSTB - 1) / kSTB;  // rounds holding items (uniform)
   for (int pass = 0; pass < 8; ++pass) {
     const int sh = 8 * pass;
     uint64_t mk[4];
     int32_t mv[4];
-    int md[4];
+    int md[4], rk[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = r * kSTB + t;
@@ -429,15 +433,47 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       mv[r] = ok ? val[i] : 0;
       md[r] = ok ? (int)((mk[r] >> sh) & 255u) : -1;
     }
-    if (t < 256) hist[t] = 0;
+    for (int e = t; e < rounds * 16 * 256 / 2; e += kSTB) cnt32[e] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (md[r] >= 0) atomicAdd(&hist[md[r]], 1);
+    for (int r = 0; r < 4; ++r) {
+      if (r >= rounds) break;
+      const bool valid = md[r] >= 0;
+      const int d = valid ? md[r] : 0;
+      uint64_t m = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t bb = __ballot(valid && bit);
+        m &= bit ? bb : ~bb;
+      }
+      rk[r] = __popcll(m & below);
+      if (valid && rk[r] == 0) cnt[r][wv][d] = (uint16_t)__popcll(m);
+    }
+    __syncthreads();
+    {
+      // digit d = t % 256, round r = t / 256: exclusive offsets over the
+      // waves of round r, then the totals of the earlier rounds are added
+      const int d = t & 255, r = t >> 8;
+      int acc = 0;
+      if (r < rounds)
+        for (int ww = 0; ww < 16; ++ww) {
+          const int c = cnt[r][ww][d];
+          cnt[r][ww][d] = (uint16_t)acc;
+          acc += c;
+        }
+      rtot[r][d] = acc;
+      __syncthreads();
+      int pre = 0;
+      for (int r2 = 0; r2 < r; ++r2) pre += rtot[r2][d];
+      if (pre && r < rounds)
+        for (int ww = 0; ww < 16; ++ww) cnt[r][ww][d] = (uint16_t)(cnt[r][ww][d] + pre);
+      if (r == 3) run[d] = pre + acc;
+    }
     __syncthreads();
     if (t < 64) {
       // exclusive scan of the 256 digit counts by one wavefront, 4 per lane
-      const int h0 = hist[4 * t], h1 = hist[4 * t + 1], h2 = hist[4 * t + 2], h3 = hist[4 * t + 3];
+      const int h0 = run[4 * t], h1 = run[4 * t + 1], h2 = run[4 * t + 2], h3 = run[4 * t + 3];
       const int tot = h0 + h1 + h2 + h3;
       int inc = tot;
       for (int off = 1; off < 64; off <<= 1) {
@@ -453,35 +489,12 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      if (r >= rounds) break;
-      for (int e = t; e < 16 * 256; e += kSTB) wc[e] = 0;
-      __syncthreads();
-      const bool valid = md[r] >= 0;
-      const int d = valid ? md[r] : 0;
-      uint64_t m = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1;
-        const uint64_t bb = __ballot(valid && bit);
-        m &= bit ? bb : ~bb;
-      }
-      const int rank = __popcll(m & below);
-      if (valid && rank == 0) wc[wv * 256 + d] = (uint16_t)__popcll(m);
-      __syncthreads();
-      if (valid) {
-        int off = run[d];
-        for (int ww = 0; ww < wv; ++ww) off += wc[ww * 256 + d];
-        key[off + rank] = mk[r];
-        val[off + rank] = mv[r];
-      }
-      __syncthreads();
-      if (t < 256) {
-        int s2 = 0;
-        for (int ww = 0; ww < 16; ++ww) s2 += wc[ww * 256 + t];
-        run[t] += s2;
-      }
-      __syncthreads();
+      if (md[r] < 0) continue;
+      const int dst = run[md[r]] + cnt[r][wv][md[r]] + rk[r];
+      key[dst] = mk[r];
+      val[dst] = mv[r];
     }
+    __syncthreads();
   }
 
   // points in tree order
@@ -517,13 +530,33 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     const int lo = i - cap + 1 < 0 ? 0 : i - cap + 1;
     const int hi = i + cap > k ? k : i + cap;
     int L = 0;
-    for (; L <= 16; ++L) {
-      int b = -1, e = -1;
-      for (int jj = i; jj >= lo; --jj)
-        if (cpl[jj] < L) { b = jj; break; }
-      for (int jj = i + 1; jj <= hi; ++jj)
-        if (cpl[jj] < L) { e = jj; break; }
-      if (b >= 0 && e >= 0 && e - b <= cap) break;
+    if (cap <= 16) {
+      // the window's common-prefix lengths in registers: cl[u] = cpl[i - u],
+      // cr[u] = cpl[i + 1 + u] (127 outside the window)
+      int cl[16], cr[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        cl[u] = (u < cap && i - u >= lo) ? cpl[i - u] : 127;
+        cr[u] = (u < cap && i + 1 + u <= hi) ? cpl[i + 1 + u] : 127;
+      }
+      for (; L <= 16; ++L) {
+        int bu = 99, eu = 99;
+#pragma unroll
+        for (int u = 15; u >= 0; --u) {
+          if (cl[u] < L) bu = u;
+          if (cr[u] < L) eu = u;
+        }
+        if (bu != 99 && eu != 99 && eu + 1 + bu <= cap) break;
+      }
+    } else {
+      for (; L <= 16; ++L) {
+        int b = -1, e = -1;
+        for (int jj = i; jj >= lo; --jj)
+          if (cpl[jj] < L) { b = jj; break; }
+        for (int jj = i + 1; jj <= hi; ++jj)
+          if (cpl[jj] < L) { e = jj; break; }
+        if (b >= 0 && e >= 0 && e - b <= cap) break;
+      }
     }
     if (L > 16) L = 16;
     ell[i] = (int8_t)L;
@@ -636,25 +669,31 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     nd.ctr[atomicAdd(&dpos[L], 1)] = tn;  // ctr is unused by this build: the depth lists
   }
   __syncthreads();
-  // charges depth by depth, deepest first (same sums and order as k_tree_moments)
+  // charges (same sums and order as k_tree_moments): every leaf first, then
+  // the internal nodes depth by depth, deepest first, skipping empty depths
+  for (int32_t tn = t; tn < n; tn += kSTB) {
+    const int4 b = nd.t[tn].b;
+    if (!((b.w >> 8) & 1)) continue;
+    double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t jj = b.y; jj < b.y + b.z; ++jj) {
+      const double wv2 = (double)ws[jj];
+      Wd += wv2;
+      for (int d = 0; d < 4; ++d) Sd[d] += wv2 * (double)xs[(int64_t)d * k + jj];
+    }
+    node_finish(nd, tn, Wd, Sd);
+  }
+  __syncthreads();
   for (int L = 16; L >= 0; --L) {
+    if (doff[L] == doff[L + 1]) continue;  // uniform: doff is in LDS
     for (int32_t e = doff[L] + t; e < doff[L + 1]; e += kSTB) {
       const int32_t tn = nd.ctr[e];
-      const int4 b = nd.t[tn].b;
+      if ((nd.t[tn].b.w >> 8) & 1) continue;
       double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
-      if ((b.w >> 8) & 1) {
-        for (int32_t jj = b.y; jj < b.y + b.z; ++jj) {
-          const double wv2 = (double)ws[jj];
-          Wd += wv2;
-          for (int d = 0; d < 4; ++d) Sd[d] += wv2 * (double)xs[(int64_t)d * k + jj];
-        }
-      } else {
-        const int32_t nc = nd.nch[tn];
-        for (int32_t r = 0; r < nc; ++r) {
-          const int32_t ch = nd.cid[16 * (int64_t)tn + r];
-          Wd += nd.Wd[ch];
-          for (int d = 0; d < 4; ++d) Sd[d] += nd.Sd[4 * (int64_t)ch + d];
-        }
+      const int32_t nc = nd.nch[tn];
+      for (int32_t r = 0; r < nc; ++r) {
+        const int32_t ch = nd.cid[16 * (int64_t)tn + r];
+        Wd += nd.Wd[ch];
+        for (int d = 0; d < 4; ++d) Sd[d] += nd.Sd[4 * (int64_t)ch + d];
       }
       node_finish(nd, tn, Wd, Sd);
     }
