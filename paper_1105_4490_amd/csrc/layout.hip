@@ -778,8 +778,9 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
 
 // ============================================================ gradient ====
 // Net centres: pins summed in CSR order (each coordinate on its own), then
-// divided by the net size.
-__global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, const float* x, int32_t k, float* z) {
+// divided by the net size.  z is AoS (one 16-byte record per net) so that the
+// attraction gathers a centre with one load.
+__global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, const float* x, int32_t k, float4* z) {
   GRID_STRIDE(e, l) {
     int64_t b = ptr[e], n = ptr[e + 1] - b;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
@@ -791,15 +792,12 @@ __global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, co
       a3 = a3 + x[3 * (int64_t)k + v];
     }
     float fn = (float)n;
-    z[e] = n > 0 ? a0 / fn : 0.0f;
-    z[(int64_t)l + e] = n > 0 ? a1 / fn : 0.0f;
-    z[2 * (int64_t)l + e] = n > 0 ? a2 / fn : 0.0f;
-    z[3 * (int64_t)l + e] = n > 0 ? a3 / fn : 0.0f;
+    z[e] = n > 0 ? make_float4(a0 / fn, a1 / fn, a2 / fn, a3 / fn) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
 }
 // Attraction of eq. (7): sum over the vertex's nets in ascending net order.
 __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, const float* c, const float* x,
-                          const float* z, int32_t l, float* y) {
+                          const float4* z, float* y) {
   GRID_STRIDE(v, k) {
     int64_t b = dptr[v], e = dptr[v + 1];
     float x0 = x[v], x1 = x[(int64_t)k + v], x2 = x[2 * (int64_t)k + v], x3 = x[3 * (int64_t)k + v];
@@ -807,7 +805,8 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
     for (int64_t t = b; t < e; ++t) {
       int32_t n = dpins[t];
       float ce = c ? c[n] : 1.0f;
-      float d0 = x0 - z[n], d1 = x1 - z[(int64_t)l + n], d2 = x2 - z[2 * (int64_t)l + n], d3 = x3 - z[3 * (int64_t)l + n];
+      const float4 zn = z[n];
+      float d0 = x0 - zn.x, d1 = x1 - zn.y, d2 = x2 - zn.z, d3 = x3 - zn.w;
       a0 = a0 + ce * d0;
       a1 = a1 + ce * d1;
       a2 = a2 + ce * d2;
@@ -817,6 +816,15 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
     y[(int64_t)k + v] = a1;
     y[2 * (int64_t)k + v] = a2;
     y[3 * (int64_t)k + v] = a3;
+  }
+}
+__global__ void k_z_soa(const float4* z, int32_t l, float* out) {
+  GRID_STRIDE(e, l) {
+    const float4 a = z[e];
+    out[e] = a.x;
+    out[(int64_t)l + e] = a.y;
+    out[2 * (int64_t)l + e] = a.z;
+    out[3 * (int64_t)l + e] = a.w;
   }
 }
 
@@ -1096,7 +1104,7 @@ __global__ void k_combine(int32_t k, const int32_t* __restrict__ order, const in
 }
 
 struct GradWork {
-  Buf<float> z;
+  Buf<float4> z;  // net centres, one record per net
   Buf<uint32_t> box;
   Buf<float> part;  // partial repulsions, tree order: [16][4][k], or [16][16][4][k] when spread
   Tree T;
@@ -1107,9 +1115,9 @@ static void gradient_prepare(Ctx& C, const Level& L, const float* x, double th2,
                              hipStream_t s) {
   if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
   box_of(x, L.k, gw.box.p, s);
-  gw.z = Buf<float>(C.pool, 4 * (size_t)(L.l > 0 ? L.l : 1));
+  gw.z = Buf<float4>(C.pool, (size_t)(L.l > 0 ? L.l : 1));
   if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, L.k, gw.z.p);
-  VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, L.l, y);
+  VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y);
   build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, th2, s);
 }
 
@@ -1802,7 +1810,7 @@ void gradient(Ctx& C, const vmo_hypergraph* h, const float* x, float theta, int3
   VMO_HIP(hipMemsetAsync(cnt.p, 0, 8, s));
   gradient_prepare(C, L, x, (double)theta * (double)theta, cap, y, gw, s);
   gradient_walk(C, L, y, nullptr, 0.0, gw, cnt.p, s);
-  if (z && L.l > 0) VMO_HIP(hipMemcpyAsync(z, gw.z.p, 16 * (size_t)L.l, hipMemcpyDeviceToDevice, s));
+  if (z && L.l > 0) VMO_LAUNCH(k_z_soa, gsz(L.l), kLT, 0, s, gw.z.p, L.l, z);
   unsigned long long c = read1(cnt.p, s);
   if (nint) *nint = (int64_t)c;
 }
