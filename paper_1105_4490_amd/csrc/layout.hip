@@ -849,13 +849,16 @@ __device__ __forceinline__ void interact(float* y, const float* xn, float wn2, f
 
 // Minimum over the 64 lanes (all active), by DPP row shifts and row
 // broadcasts; lane 63 ends with the minimum of the wavefront.
+// Lanes without a source (and rows the mask leaves out) take INT_MAX, the
+// identity of min, so that each step folds into one v_min_i32 with DPP.
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));  // row_shr:1
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));  // row_shr:2
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));  // row_shr:4
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));  // row_shr:8
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  constexpr int32_t I = 0x7fffffff;
+  v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
   return __builtin_amdgcn_readlane(v, 63);
 }
 
@@ -960,21 +963,30 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
       const int o = t - wb;
       const int4 a = win[wv][0][o];
       const int4 b = win[wv][1][o];
+      const int4 xi = win[wv][2][o];
       const int4 wi = win[wv][3][o];
+      // all four reads in flight together, one wait for them
+      asm volatile("" ::"v"(a.x), "v"(a.y), "v"(a.z), "v"(a.w), "v"(xi.x), "v"(xi.y), "v"(xi.z), "v"(xi.w), "v"(wi.x),
+                   "v"(wi.z), "v"(wi.w));
+      // the link fields are the same on every lane: scalar registers, so that
+      // the leaf loops below are scalar loops
+      const int32_t bnext = __builtin_amdgcn_readfirstlane(b.x);
+      const int32_t bfirst = __builtin_amdgcn_readfirstlane(b.y);
+      const int32_t bcount = __builtin_amdgcn_readfirstlane(b.z);
+      const int32_t bflags = __builtin_amdgcn_readfirstlane(b.w);
       const bool act = skip <= t;
-      const bool far = act && far_from(q, a, __hiloint2double(wi.w, wi.z));
+      const bool far = act & far_from(q, a, __hiloint2double(wi.w, wi.z));
       if (far) {
-        const int4 xi = win[wv][2][o];
         interact(y, xn, wn2, __int_as_float(xi.x), __int_as_float(xi.y), __int_as_float(xi.z), __int_as_float(xi.w),
                  __int_as_float(wi.x));
-        skip = b.x;
+        skip = bnext;
       }
       cnt += (unsigned long long)__popcll(__ballot(far));
       const bool near = act && !far;
-      if ((b.w >> 8) & 1) {
+      if ((bflags >> 8) & 1) {
         if (__any(near)) {
-          const int32_t f1 = b.y + b.z;
-          for (int32_t base = b.y; base < f1; base += kWin) {
+          const int32_t f1 = bfirst + bcount;
+          for (int32_t base = bfirst; base < f1; base += kWin) {
             const int32_t e = f1 - base < kWin ? f1 : base + kWin;
             if (base < pb || e > pb + kWin) {
               // slide the point window to start at this leaf
@@ -989,8 +1001,9 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
             }
             const int32_t m = e - base, o2 = base - pb;
             if (near) {
+              // the point itself is not skipped by index: its distance is
+              // zero, and interact() leaves y unchanged at zero distance
               for (int32_t i = 0; i < m; ++i) {
-                if (base + i == (int32_t)j) continue;
                 const float4 pi = lp[wv][o2 + i];
                 interact(y, xn, wn2, pi.x, pi.y, pi.z, pi.w, lw[wv][o2 + i]);
               }
@@ -999,7 +1012,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
                    __popcll(__ballot(near && j >= base && j < base + m));
           }
         }
-        if (near) skip = b.x;
+        if (near) skip = bnext;
       } else if (near) {
         skip = t + 1;
       }
