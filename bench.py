@@ -40,7 +40,7 @@ FLOPS_PER_INTERACTION = 23   # 4 sub, r^2 (1 mul + 3 fma), 2 mul (2 W w), 1 mul 
 # HBM bytes per walk launch (average over one step of this workload), from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
 # plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
-WALK_TRAFFIC_BYTES = 43.99e6 + 9.40e6
+WALK_TRAFFIC_BYTES = 42.39e6 + 9.40e6
 PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
@@ -54,7 +54,8 @@ def main():
     ap.add_argument("--side", type=int, default=N_SIDE, help="grid side of the workload (64 = the 64^3 case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=28, help="grid side of the oracle's timed sample")
-    ap.add_argument("--mode", choices=("path", "batch", "serve"), default="path")
+    ap.add_argument("--mode", choices=("path", "batch", "serve", "copy"), default="path",
+                    help="copy: a plain 256 MiB device copy, three times (calibrates the HBM byte counters)")
     ap.add_argument("--jobs", type=int, default=512, help="batch mode: number of matrices")
     ap.add_argument("--layout-threads", type=int, default=4, help="batch mode: streams laying out the matrices")
     ap.add_argument("--no-plain", action="store_true", help="batch mode: skip the plain per-subproblem form")
@@ -71,6 +72,9 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.mode == "copy":
+        return copy_calibration()
 
     import paper_1105_4490_amd as P
     if not os.path.exists(P.LIB_PATH):
@@ -325,6 +329,20 @@ def bench_serve(args, ctx):
         line["stable"] = {"rate_per_s": rate, "nnz_per_s": total / span2,
                           "latency_ms": {"p50": _pct(lat2, 0.5), "p99": _pct(lat2, 0.99), "max": max(lat2)}}
     print(json.dumps(line))
+
+
+def copy_calibration():
+    """A device copy of known size (256 MiB read and 256 MiB written per
+    dispatch, three dispatches): what FETCH_SIZE and WRITE_SIZE read for it
+    scales the counts taken on the walk."""
+    import torch
+    a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_per_copy": a.numel() * 4, "copies": 3}))
 
 
 def cpu_baseline(side):

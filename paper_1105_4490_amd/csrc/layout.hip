@@ -288,7 +288,8 @@ __global__ void k_tree_nodes(const int8_t* cpl, const uint64_t* key, const int8_
   }
 }
 
-__global__ void k_tree_links(int32_t n, NodeView nd) {
+__global__ void k_tree_links(const int32_t* __restrict__ n_dev, NodeView nd) {
+  const int32_t n = *n_dev;
   GRID_STRIDE(t64, n) {
     int32_t t = (int32_t)t64;
     int4 b = nd.t[t].b;
@@ -313,19 +314,74 @@ __device__ __forceinline__ void node_finish(NodeView nd, int32_t t, double Wd, c
   nd.t[t].X = make_float4((float)(Sd[0] / Wd), (float)(Sd[1] / Wd), (float)(Sd[2] / Wd), (float)(Sd[3] / Wd));
 }
 
+// Charge of a leaf: its points [first, first + count) in tree order, in FP64;
+// point loads are issued eight points at a time.
+__device__ __forceinline__ void leaf_sums(int32_t first, int32_t count, int32_t k, const float* xs, const float* ws,
+                                          double& Wd, double* Sd) {
+  for (int32_t j0 = first; j0 < first + count; j0 += 8) {
+    float wb[8], xb[8][4];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (j0 + u < first + count) {
+        wb[u] = ws[j0 + u];
+        for (int d = 0; d < 4; ++d) xb[u][d] = xs[(int64_t)d * k + j0 + u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (j0 + u < first + count) {
+        const double wv = (double)wb[u];
+        Wd += wv;
+        for (int d = 0; d < 4; ++d) Sd[d] += wv * (double)xb[u][d];
+      }
+    }
+  }
+}
+
+// Charge of an internal node: its nc children's charges in child order.  The
+// children are loaded four at a time (with coherent loads when other
+// workgroups wrote them in this launch).
+__device__ __forceinline__ void child_sums(NodeView nd, int32_t p, int32_t nc, bool coherent, double& W2,
+                                           double* S2) {
+  const int4* cq = reinterpret_cast<const int4*>(nd.cid + 16 * (int64_t)p);
+  for (int32_t r0 = 0; r0 < nc; r0 += 4) {
+    const int4 c4 = cq[r0 >> 2];
+    const int32_t cc[4] = {c4.x, c4.y, c4.z, c4.w};
+    double wv[4], sv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (r0 + u < nc) {
+        if (coherent) {
+          wv[u] = __hip_atomic_load(&nd.Wd[cc[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int d = 0; d < 4; ++d)
+            sv[u][d] = __hip_atomic_load(&nd.Sd[4 * (int64_t)cc[u] + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          wv[u] = nd.Wd[cc[u]];
+          for (int d = 0; d < 4; ++d) sv[u][d] = nd.Sd[4 * (int64_t)cc[u] + d];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (r0 + u < nc) {
+        W2 += wv[u];
+        for (int d = 0; d < 4; ++d) S2[d] += sv[u][d];
+      }
+    }
+  }
+}
+
 // Charges bottom-up: a leaf sums its points in tree order (FP64); the last
 // child to finish sums its parent's children in child order.
-__global__ void k_tree_moments(int32_t n, int32_t k, const float* xs, const float* ws, NodeView nd) {
+__global__ void k_tree_moments(const int32_t* __restrict__ n_dev, int32_t k, const float* xs, const float* ws,
+                               NodeView nd) {
+  const int32_t n = *n_dev;
   GRID_STRIDE(t64, n) {
     int32_t t = (int32_t)t64;
     int4 b = nd.t[t].b;
     if (!((b.w >> 8) & 1)) continue;
     double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t j = b.y; j < b.y + b.z; ++j) {
-      double wv = (double)ws[j];
-      Wd += wv;
-      for (int d = 0; d < 4; ++d) Sd[d] += wv * (double)xs[(int64_t)d * k + j];
-    }
+    leaf_sums(b.y, b.z, k, xs, ws, Wd, Sd);
     node_finish(nd, t, Wd, Sd);
     int32_t cur = t;
     while (true) {
@@ -336,30 +392,7 @@ __global__ void k_tree_moments(int32_t n, int32_t k, const float* xs, const floa
       if (old != nd.nch[p] - 1) break;
       __threadfence();
       double W2 = 0.0, S2[4] = {0.0, 0.0, 0.0, 0.0};
-      const int32_t nc = nd.nch[p];
-      const int4* cq = reinterpret_cast<const int4*>(nd.cid + 16 * (int64_t)p);
-      for (int32_t r0 = 0; r0 < nc; r0 += 4) {
-        // four children per round: their loads are issued together, the sums
-        // stay in child order
-        const int4 c4 = cq[r0 >> 2];
-        const int32_t cc[4] = {c4.x, c4.y, c4.z, c4.w};
-        double wv[4], sv[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (r0 + u < nc) {
-            wv[u] = __hip_atomic_load(&nd.Wd[cc[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int d = 0; d < 4; ++d)
-              sv[u][d] = __hip_atomic_load(&nd.Sd[4 * (int64_t)cc[u] + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (r0 + u < nc) {
-            W2 += wv[u];
-            for (int d = 0; d < 4; ++d) S2[d] += sv[u][d];
-          }
-        }
-      }
+      child_sums(nd, p, nd.nch[p], true, W2, S2);
       node_finish(nd, p, W2, S2);
       cur = p;
     }
@@ -589,6 +622,11 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
   __syncthreads();
   const int32_t n = base[k];
   if (t == 0) nn[k] = n;
+  // the next links, kept in LDS for the children lists when they fit (the
+  // sort's count area is free from here)
+  int32_t* nxt = reinterpret_cast<int32_t*>(&cnt[0][0][0]);
+  constexpr int32_t kNxtCap = (int32_t)(sizeof(cnt) / sizeof(int32_t));
+  const bool nxt_lds = n <= kNxtCap;
   // nodes in pre-order (as k_tree_nodes)
   for (int i = t; i < k; i += kSTB) {
     const int ci = cpl[i], li = ell[i];
@@ -627,23 +665,37 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       nd.t[tn].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
       nd.t[tn].T = ft.T[L];
       nd.parent[tn] = -1;
+      if (nxt_lds) nxt[tn] = base[end] | (L == li ? (int32_t)0x80000000 : 0);
     }
   }
   __syncthreads();
-  // children lists (as k_tree_links)
+  // children lists (as k_tree_links), the sibling chain followed in LDS
   for (int32_t tn = t; tn < n; tn += kSTB) {
-    const int4 b = nd.t[tn].b;
-    int cnt = 0;
-    if (!((b.w >> 8) & 1)) {
-      int32_t ch = tn + 1;
-      while (ch != b.x) {
-        nd.parent[ch] = tn;
-        if (cnt < 16) nd.cid[16 * (int64_t)tn + cnt] = ch;
-        ++cnt;
-        ch = nd.t[ch].b.x;
+    int cnt2 = 0;
+    if (nxt_lds) {
+      const int32_t bx = nxt[tn];
+      if (bx >= 0) {
+        int32_t ch = tn + 1;
+        while (ch != bx) {
+          nd.parent[ch] = tn;
+          if (cnt2 < 16) nd.cid[16 * (int64_t)tn + cnt2] = ch;
+          ++cnt2;
+          ch = nxt[ch] & 0x7fffffff;
+        }
+      }
+    } else {
+      const int4 b = nd.t[tn].b;
+      if (!((b.w >> 8) & 1)) {
+        int32_t ch = tn + 1;
+        while (ch != b.x) {
+          nd.parent[ch] = tn;
+          if (cnt2 < 16) nd.cid[16 * (int64_t)tn + cnt2] = ch;
+          ++cnt2;
+          ch = nd.t[ch].b.x;
+        }
       }
     }
-    nd.nch[tn] = cnt;
+    nd.nch[tn] = cnt2;
   }
   __syncthreads();
   // nodes grouped by depth (any order within a depth): counts, offsets, lists
@@ -675,11 +727,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     const int4 b = nd.t[tn].b;
     if (!((b.w >> 8) & 1)) continue;
     double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t jj = b.y; jj < b.y + b.z; ++jj) {
-      const double wv2 = (double)ws[jj];
-      Wd += wv2;
-      for (int d = 0; d < 4; ++d) Sd[d] += wv2 * (double)xs[(int64_t)d * k + jj];
-    }
+    leaf_sums(b.y, b.z, k, xs, ws, Wd, Sd);
     node_finish(nd, tn, Wd, Sd);
   }
   __syncthreads();
@@ -689,12 +737,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       const int32_t tn = nd.ctr[e];
       if ((nd.t[tn].b.w >> 8) & 1) continue;
       double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
-      const int32_t nc = nd.nch[tn];
-      for (int32_t r = 0; r < nc; ++r) {
-        const int32_t ch = nd.cid[16 * (int64_t)tn + r];
-        Wd += nd.Wd[ch];
-        for (int d = 0; d < 4; ++d) Sd[d] += nd.Sd[4 * (int64_t)ch + d];
-      }
+      child_sums(nd, tn, nd.nch[tn], false, Wd, Sd);
       node_finish(nd, tn, Wd, Sd);
     }
     __syncthreads();
@@ -720,13 +763,14 @@ struct Tree {
 };
 
 // Build the tree of x [4][k] (weights w or 1) with the bounding box dbox.  The
-// node count is left on the device at T.nn[k]; T.n holds it on the host
-// only after the multi-kernel build (small_ok = false or k > 4096).
+// node count is left on the device at T.nn[k] (no host round trip): node
+// arrays are sized for the largest possible tree, 17 nodes per position.
 static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t k, int32_t cap, const uint32_t* dbox,
                        double th2, hipStream_t s, bool small_ok = true) {
   T.k = k;
+  T.n = -1;
+  const size_t nmax = 17 * (size_t)k + 1;  // at most 17 nodes begin at a position
   if (small_ok && k > 0 && k <= kSmallK) {
-    const size_t nmax = 17 * (size_t)k + 1;  // at most 17 nodes begin at a position
     T.order = Buf<int32_t>(C.pool, k);
     T.xs = Buf<float>(C.pool, 4 * (size_t)k);
     T.ws = Buf<float>(C.pool, (size_t)k);
@@ -740,7 +784,6 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
     T.nch = Buf<int32_t>(C.pool, nmax);
     T.ctr = Buf<int32_t>(C.pool, nmax);
     T.cid = Buf<int32_t>(C.pool, 16 * nmax);
-    T.n = -1;
     VMO_LAUNCH(k_tree_small, 1, kSTB, 0, s, x, w, k, cap, dbox, far_table(th2), T.order.p, T.xs.p, T.ws.p, T.p2.p,
                T.P.p, T.view(), T.nn.p);
     return;
@@ -761,19 +804,20 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
   T.nn = Buf<int32_t>(C.pool, (size_t)k + 1);
   VMO_LAUNCH(k_tree_ell, gsz((int64_t)k + 1), kLT, 0, s, T.cpl.p, k, cap, T.ell.p, T.nn.p);
   scan_exclusive<int32_t>(C, T.nn.p, T.nn.p, (int64_t)k + 1, nullptr, s);
-  int32_t n = read1(T.nn.p + k, s);
-  T.n = n;
-  T.nodes = Buf<TNode>(C.pool, n);
-  T.Wd = Buf<double>(C.pool, n);
-  T.Sd = Buf<double>(C.pool, 4 * (size_t)n);
-  T.parent = Buf<int32_t>(C.pool, n);
-  T.nch = Buf<int32_t>(C.pool, n);
-  T.ctr = Buf<int32_t>(C.pool, n);
-  T.cid = Buf<int32_t>(C.pool, 16 * (size_t)n);
+  T.nodes = Buf<TNode>(C.pool, nmax);
+  T.Wd = Buf<double>(C.pool, nmax);
+  T.Sd = Buf<double>(C.pool, 4 * nmax);
+  T.parent = Buf<int32_t>(C.pool, nmax);
+  T.nch = Buf<int32_t>(C.pool, nmax);
+  T.ctr = Buf<int32_t>(C.pool, nmax);
+  T.cid = Buf<int32_t>(C.pool, 16 * nmax);
   NodeView nd = T.view();
   VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.key.p, T.ell.p, T.nn.p, T.p2.p, k, far_table(th2), nd);
-  VMO_LAUNCH(k_tree_links, gsz(n), kLT, 0, s, n, nd);
-  VMO_LAUNCH(k_tree_moments, gsz(n), kLT, 0, s, n, k, T.xs.p, T.ws.p, nd);
+  // the node count stays on the device: grids sized for the usual count
+  // (below 2 k), grid-stride loops up to the count
+  const int32_t* n_dev = T.nn.p + k;
+  VMO_LAUNCH(k_tree_links, gsz(2 * (int64_t)k), kLT, 0, s, n_dev, nd);
+  VMO_LAUNCH(k_tree_moments, gsz(2 * (int64_t)k), kLT, 0, s, n_dev, k, T.xs.p, T.ws.p, nd);
 }
 
 // ============================================================ gradient ====
@@ -796,26 +840,86 @@ __global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, co
   }
 }
 // Attraction of eq. (7): sum over the vertex's nets in ascending net order.
+// Nets are taken eight at a time: their loads are issued together (vertices of
+// coarse levels meet many nets), the sums stay in net order.
 __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, const float* c, const float* x,
                           const float4* z, float* y) {
+  constexpr int B = 8;
   GRID_STRIDE(v, k) {
     int64_t b = dptr[v], e = dptr[v + 1];
     float x0 = x[v], x1 = x[(int64_t)k + v], x2 = x[2 * (int64_t)k + v], x3 = x[3 * (int64_t)k + v];
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    for (int64_t t = b; t < e; ++t) {
-      int32_t n = dpins[t];
-      float ce = c ? c[n] : 1.0f;
-      const float4 zn = z[n];
-      float d0 = x0 - zn.x, d1 = x1 - zn.y, d2 = x2 - zn.z, d3 = x3 - zn.w;
-      a0 = a0 + ce * d0;
-      a1 = a1 + ce * d1;
-      a2 = a2 + ce * d2;
-      a3 = a3 + ce * d3;
+    for (int64_t t0 = b; t0 < e; t0 += B) {
+      int32_t nb[B];
+      float cb[B];
+      float4 zb[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) nb[u] = t0 + u < e ? dpins[t0 + u] : -1;
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (nb[u] >= 0) {
+          cb[u] = c ? c[nb[u]] : 1.0f;
+          zb[u] = z[nb[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (nb[u] < 0) break;
+        const float ce = cb[u];
+        const float d0 = x0 - zb[u].x, d1 = x1 - zb[u].y, d2 = x2 - zb[u].z, d3 = x3 - zb[u].w;
+        a0 = a0 + ce * d0;
+        a1 = a1 + ce * d1;
+        a2 = a2 + ce * d2;
+        a3 = a3 + ce * d3;
+      }
     }
     y[v] = a0;
     y[(int64_t)k + v] = a1;
     y[2 * (int64_t)k + v] = a2;
     y[3 * (int64_t)k + v] = a3;
+  }
+}
+// The same attraction with one wavefront per vertex, for small levels, whose
+// coarse vertices can meet hundreds of nets: the lanes form the terms
+// c_e (x - z_e) of 64 nets at a time, and the sum runs over them in net order.
+__global__ __launch_bounds__(256) void k_attract_wave(const int64_t* dptr, const int32_t* dpins, int32_t k,
+                                                      const float* c, const float* x, const float4* z, float* y) {
+  __shared__ float4 tb[4][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + wv; v < k; v += (int64_t)gridDim.x * 4) {
+    const int64_t b = dptr[v], e = dptr[v + 1];
+    const float x0 = x[v], x1 = x[(int64_t)k + v], x2 = x[2 * (int64_t)k + v], x3 = x[3 * (int64_t)k + v];
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    for (int64_t t0 = b; t0 < e; t0 += 64) {
+      const int m = e - t0 < 64 ? (int)(e - t0) : 64;
+      float4 term = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (lane < m) {
+        const int32_t n = dpins[t0 + lane];
+        const float ce = c ? c[n] : 1.0f;
+        const float4 zn = z[n];
+        const float d0 = x0 - zn.x, d1 = x1 - zn.y, d2 = x2 - zn.z, d3 = x3 - zn.w;
+        term = make_float4(ce * d0, ce * d1, ce * d2, ce * d3);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      tb[wv][lane] = term;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int i = 0; i < m; ++i) {
+        const float4 tt = tb[wv][i];
+        a0 = a0 + tt.x;
+        a1 = a1 + tt.y;
+        a2 = a2 + tt.z;
+        a3 = a3 + tt.w;
+      }
+    }
+    if (lane == 0) {
+      y[v] = a0;
+      y[(int64_t)k + v] = a1;
+      y[2 * (int64_t)k + v] = a2;
+      y[3 * (int64_t)k + v] = a3;
+    }
   }
 }
 __global__ void k_z_soa(const float4* z, int32_t l, float* out) {
@@ -1063,56 +1167,78 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
 // y_v = attraction + the parts of the walk in order (point j in tree order is
 // vertex order[j]).  xmove == NULL: y receives the gradient; else the descent
 // step of Algorithm 3 is applied to xmove: x_v <- x_v - (alpha / |y_v|) y_v.
-__global__ void k_combine(int32_t k, const int32_t* __restrict__ order, const int32_t* __restrict__ p2,
-                          const TNode* __restrict__ nodes, const int32_t* __restrict__ cid,
-                          const int32_t* __restrict__ nch, int spread, const float* __restrict__ part, float* y,
-                          float* xmove, double alpha) {
-  GRID_STRIDE(j, k) {
-    const int32_t v = order[j];
-    int32_t q[4];
-    float yv[4];
-    for (int d = 0; d < 4; ++d) {
-      yv[d] = y[(int64_t)d * k + v];
-      q[d] = p2[(int64_t)d * k + j];
-    }
-    const bool rleaf = (nodes[0].b.w >> 8) & 1;
-    if (rleaf || far_from(q, nodes[0].a, nodes[0].T)) {
-      for (int d = 0; d < 4; ++d) yv[d] = yv[d] + part[(int64_t)d * k + j];
+// A block takes 64 points; wavefront i1 forms part i1 of each of them (its
+// loads coalesced over the points, the sub-parts of a spread part loaded
+// together and summed in child order), and wavefront 0 adds the parts to the
+// attraction in part order.
+constexpr int kCombT = 64 * kParts;
+__global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __restrict__ order,
+                                                    const int32_t* __restrict__ p2, const TNode* __restrict__ nodes,
+                                                    const int32_t* __restrict__ cid, const int32_t* __restrict__ nch,
+                                                    int spread, const float* __restrict__ part, float* y,
+                                                    float* xmove, double alpha) {
+  __shared__ float4 sh[kParts][64];
+  const int i1 = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = j < k;
+  const bool rleaf = (nodes[0].b.w >> 8) & 1;
+  const int n1 = rleaf ? 1 : min(nch[0], kParts);
+  int32_t q[4] = {0, 0, 0, 0};
+  if (valid)
+    for (int d = 0; d < 4; ++d) q[d] = p2[(int64_t)d * k + j];
+  // a root that is a leaf or far from the point: one part, in slot 0
+  const bool one = rleaf || (valid && far_from(q, nodes[0].a, nodes[0].T));
+  const int np = one ? 1 : n1;
+  float a1[4] = {0.f, 0.f, 0.f, 0.f};
+  if (valid && i1 < np) {
+    if (one || spread == 1) {
+      const int64_t slot = one ? 0 : (spread == 1 ? i1 : (int64_t)i1 * kParts);
+      for (int d = 0; d < 4; ++d) a1[d] = part[(slot * 4 + d) * k + j];
     } else {
-      const int n1 = min(nch[0], kParts);
-      for (int i1 = 0; i1 < n1; ++i1) {
-        float a1[4];
-        if (spread == 1) {
-          for (int d = 0; d < 4; ++d) a1[d] = part[((int64_t)i1 * 4 + d) * k + j];
-        } else {
-          const int32_t c1 = cid[i1];
-          const bool c1leaf = (nodes[c1].b.w >> 8) & 1;
-          if (c1leaf || far_from(q, nodes[c1].a, nodes[c1].T)) {
-            for (int d = 0; d < 4; ++d) a1[d] = part[(((int64_t)i1 * kParts) * 4 + d) * k + j];
-          } else {
-            for (int d = 0; d < 4; ++d) a1[d] = 0.0f;
-            const int n2 = min(nch[c1], kParts);
-            for (int i2 = 0; i2 < n2; ++i2)
-              for (int d = 0; d < 4; ++d) a1[d] = a1[d] + part[(((int64_t)i1 * kParts + i2) * 4 + d) * k + j];
-          }
-        }
-        for (int d = 0; d < 4; ++d) yv[d] = yv[d] + a1[d];
+      const int32_t c1 = cid[i1];
+      const bool c1leaf = (nodes[c1].b.w >> 8) & 1;
+      if (c1leaf || far_from(q, nodes[c1].a, nodes[c1].T)) {
+        for (int d = 0; d < 4; ++d) a1[d] = part[(((int64_t)i1 * kParts) * 4 + d) * k + j];
+      } else {
+        const int n2 = min(nch[c1], kParts);
+        float v[kParts][4];
+#pragma unroll
+        for (int i2 = 0; i2 < kParts; ++i2)
+          if (i2 < n2)
+            for (int d = 0; d < 4; ++d) v[i2][d] = part[(((int64_t)i1 * kParts + i2) * 4 + d) * k + j];
+#pragma unroll
+        for (int i2 = 0; i2 < kParts; ++i2)
+          if (i2 < n2)
+            for (int d = 0; d < 4; ++d) a1[d] = a1[d] + v[i2][d];
       }
     }
-    if (!xmove) {
-      for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yv[d];
-      continue;
-    }
-    float n2s = yv[0] * yv[0];
-    n2s = n2s + yv[1] * yv[1];
-    n2s = n2s + yv[2] * yv[2];
-    n2s = n2s + yv[3] * yv[3];
-    if (!(n2s > 0.0f)) continue;
-    float f = (float)(alpha / sqrt((double)n2s));
-    for (int d = 0; d < 4; ++d) {
-      float td = f * yv[d];
-      xmove[(int64_t)d * k + v] = xmove[(int64_t)d * k + v] - td;
-    }
+  }
+  sh[i1][lane] = make_float4(a1[0], a1[1], a1[2], a1[3]);
+  __syncthreads();
+  if (i1 != 0 || !valid) return;
+  const int32_t v = order[j];
+  float yv[4];
+  for (int d = 0; d < 4; ++d) yv[d] = y[(int64_t)d * k + v];
+  for (int i = 0; i < np; ++i) {
+    const float4 a = sh[i][lane];
+    yv[0] = yv[0] + a.x;
+    yv[1] = yv[1] + a.y;
+    yv[2] = yv[2] + a.z;
+    yv[3] = yv[3] + a.w;
+  }
+  if (!xmove) {
+    for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yv[d];
+    return;
+  }
+  float n2s = yv[0] * yv[0];
+  n2s = n2s + yv[1] * yv[1];
+  n2s = n2s + yv[2] * yv[2];
+  n2s = n2s + yv[3] * yv[3];
+  if (!(n2s > 0.0f)) return;
+  float f = (float)(alpha / sqrt((double)n2s));
+  for (int d = 0; d < 4; ++d) {
+    float td = f * yv[d];
+    xmove[(int64_t)d * k + v] = xmove[(int64_t)d * k + v] - td;
   }
 }
 
@@ -1130,7 +1256,10 @@ static void gradient_prepare(Ctx& C, const Level& L, const float* x, double th2,
   box_of(x, L.k, gw.box.p, s);
   gw.z = Buf<float4>(C.pool, (size_t)(L.l > 0 ? L.l : 1));
   if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, L.k, gw.z.p);
-  VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y);
+  if (L.k <= 16384)
+    VMO_LAUNCH(k_attract_wave, nblocks(L.k, 4), 256, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y);
+  else
+    VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y);
   build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, th2, s);
 }
 
@@ -1150,8 +1279,8 @@ static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double
   VMO_LAUNCH(k_walk, dim3(nblocks(L.k, kWT), kParts * spread), kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p,
              gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, nint ? nint : pc);
   prof_end(C, ph, s);
-  VMO_LAUNCH(k_combine, gsz(L.k), kLT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p,
-             spread, gw.part.p, y, xmove, alpha);
+  VMO_LAUNCH(k_combine, nblocks(L.k, 64), kCombT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p,
+             gw.T.nch.p, spread, gw.part.p, y, xmove, alpha);
 }
 
 // One descent step (Algorithm 3).  alpha: step length (host); at it == 0 it
@@ -1804,11 +1933,12 @@ void tree(Ctx& C, const float* x, const float* w, int32_t k, int32_t cap, int32_
   box_of(x, k, box.p, s);
   Tree T;
   build_tree(C, T, x, w, k, cap, box.p, 0.25, s, false);
-  VMO_REQUIRE(T.n <= max_nodes, "max_nodes is too small");
-  VMO_LAUNCH(k_tree_out, gsz(T.n), kLT, 0, s, T.n, T.view(), ints, cell2, flt);
+  const int32_t n = read1(T.nn.p + k, s);
+  VMO_REQUIRE(n <= max_nodes, "max_nodes is too small");
+  VMO_LAUNCH(k_tree_out, gsz(n), kLT, 0, s, n, T.view(), ints, cell2, flt);
   VMO_HIP(hipMemcpyAsync(order, T.order.p, 4 * (size_t)k, hipMemcpyDeviceToDevice, s));
   VMO_HIP(hipStreamSynchronize(s));
-  *n_nodes = T.n;
+  *n_nodes = n;
 }
 
 void gradient(Ctx& C, const vmo_hypergraph* h, const float* x, float theta, int32_t cap, float* y, float* z,
