@@ -42,6 +42,11 @@ FLOPS_PER_INTERACTION = 23   # 4 sub, r^2 (1 mul + 3 fma), 2 mul (2 W w), 1 mul 
 # plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
 WALK_TRAFFIC_BYTES = 42.39e6 + 9.40e6
 PEAK_FP32_VALU_TFLOPS = 157.3
+# live timing brackets every PROFILE_EVERY-th launch of a kernel with HIP
+# events: an event pair costs about 13 us of stream time, 2.5 % of a step when
+# every walk is timed.  3 is prime to the 700 walk launches of a step, so over
+# the timed steps the timed launches cover every launch position of the step.
+PROFILE_EVERY = 3
 PEAK_HBM_GBS = 8000.0
 
 
@@ -103,7 +108,7 @@ def main():
     for _ in range(args.warmup):
         o, c = step()
     torch.cuda.synchronize()
-    ctx.profile(True)
+    ctx.profile(True, every=PROFILE_EVERY)
     ctx.profile_reset()
     lat = []
     torch.cuda.synchronize()
@@ -127,9 +132,10 @@ def main():
     roof = {"bound": "alu", "kernel": "k_walk", "achieved": round(w_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s", "frac": round(w_tflops / PEAK_FP32_VALU_TFLOPS, 4),
             "traffic": WALK_TRAFFIC_BYTES if args.side == N_SIDE else None,
-            "launches": walk["launches"], "avg_launch_ms": round(walk["total_ms"] / max(walk["launches"], 1), 4),
-            "share_of_step": round(walk["total_ms"] / (1e3 * dt), 4),
-            "interactions_per_step": walk["work"] / args.steps}
+            "launches_timed": walk["launches"], "timed_every": PROFILE_EVERY,
+            "avg_launch_ms": round(walk["total_ms"] / max(walk["launches"], 1), 4),
+            "share_of_step": round(walk["total_ms"] * PROFILE_EVERY / (1e3 * dt), 4),
+            "interactions_per_timed_launch": walk["work"] / max(walk["launches"], 1)}
     a_gbs = assign["work"] / (assign["total_ms"] * 1e-3) / 1e9 if assign["total_ms"] > 0 else 0.0
 
     cpu = None
@@ -153,8 +159,8 @@ def main():
                    "cut_net": c["cut_net"], "lambda_minus_one": c["lambda_minus_one"], "tree_nodes": n_nodes},
         "roofline": roof,
         "lloyd_assign": {"bound": "hbm", "achieved": round(a_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": round(a_gbs / PEAK_HBM_GBS, 4), "launches": assign["launches"],
-                         "share_of_step": round(assign["total_ms"] / (1e3 * dt), 4)},
+                         "frac": round(a_gbs / PEAK_HBM_GBS, 4), "launches_timed": assign["launches"],
+                         "share_of_step": round(assign["total_ms"] * PROFILE_EVERY / (1e3 * dt), 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
@@ -204,7 +210,9 @@ def bench_batch(args, ctx):
     rows = sum(g.m for g, _ in mats)
 
     def run(plain, steps):
-        ctx.profile(True)
+        # the plain form is not timed per launch (its many small launches
+        # would each carry an event pair)
+        ctx.profile(not plain, every=4)
         ctx.profile_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -241,8 +249,9 @@ def bench_batch(args, ctx):
                   "form": "one launch sequence per subproblem"},
         "batched_over_plain": dt_p / dt_b, "identical_results": same,
         "lloyd_assign": {"bound": "hbm", "achieved": round(a_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": round(a_gbs / PEAK_HBM_GBS, 4), "launches": a_b["launches"],
-                         "share_of_step": round(a_b["total_ms"] / (1e3 * dt_b * args.steps), 4)},
+                         "frac": round(a_gbs / PEAK_HBM_GBS, 4), "launches_timed": a_b["launches"],
+                         "timed_every": 4,
+                         "share_of_step": round(4 * a_b["total_ms"] / (1e3 * dt_b * args.steps), 4)},
         "untimed": {"generate_s": round(gen_s, 1), "layout_s": round(lay_s, 1)},
     }
     print(json.dumps(line))

@@ -301,9 +301,12 @@ vmo_status vmo_serve_destroy(vmo_server s);
 
 /* ---------------------------------------------------------------------------
  * Live kernel timing for measurement tools.  While enabled, the library
- * brackets every launch of its main kernels with HIP events recorded on the
+ * brackets launches of its main kernels with HIP events recorded on the
  * launch stream and accumulates, per kernel name, the summed durations, the
- * launch count and the algorithmic work:
+ * count of timed launches and their algorithmic work.  vmo_profile(ctx, n):
+ * n = 0 disables; n >= 1 times every n-th launch of each kernel name (n = 1:
+ * every launch; a larger n keeps the events' own cost, tens of microseconds
+ * of stream time per timed launch, off most launches).  Kernels:
  *   "walk"   tree walk of the layout; work = charge interactions evaluated
  *            (counted by the kernel);
  *   "assign" Lloyd assignment pass; work = bytes of the positions it scans
@@ -316,7 +319,7 @@ typedef struct {
   int64_t launches;
   double work;
 } vmo_profile_entry;
-vmo_status vmo_profile(vmo_ctx ctx, int enable);
+vmo_status vmo_profile(vmo_ctx ctx, int every /* 0: off; n >= 1: every n-th launch */);
 vmo_status vmo_profile_read(vmo_ctx ctx, const char* kernel, vmo_profile_entry* out /* (host) */);
 vmo_status vmo_profile_reset(vmo_ctx ctx);
 

@@ -189,9 +189,10 @@ class Context:
     def pool_bytes(self) -> int:
         return int(lib().vmo_pool_bytes(self.h))
 
-    def profile(self, enable: bool):
-        """Live kernel timing with HIP events on the launch stream."""
-        self._check(lib().vmo_profile(self.h, C.c_int(1 if enable else 0)))
+    def profile(self, enable, every: int = 1):
+        """Live kernel timing with HIP events on the launch stream: off when
+        enable is false, else every `every`-th launch of each kernel is timed."""
+        self._check(lib().vmo_profile(self.h, C.c_int(int(every) if enable else 0)))
 
     def profile_reset(self):
         self._check(lib().vmo_profile_reset(self.h))

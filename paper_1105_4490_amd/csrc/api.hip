@@ -286,10 +286,12 @@ vmo_status vmo_layout_steps(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layo
   API_END
 }
 
-vmo_status vmo_profile(vmo_ctx ctx, int enable) {
-  if (!ctx) return VMO_E_INVALID;
-  ctx->prof.on = enable != 0;
-  if (!enable) {
+vmo_status vmo_profile(vmo_ctx ctx, int every) {
+  if (!ctx || every < 0) return VMO_E_INVALID;
+  ctx->prof.on = every != 0;
+  ctx->prof.every = every > 0 ? every : 1;
+  ctx->prof.seen.clear();
+  if (!every) {
     vmo::prof_discard(*ctx);
     ctx->prof.acc.clear();
   }

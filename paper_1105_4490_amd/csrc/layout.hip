@@ -84,8 +84,9 @@ struct HostBox {
 
 static void box_of(const float* x, int32_t k, uint32_t* dbox, hipStream_t s) {
   VMO_LAUNCH(k_box_init, 1, 64, 0, s, dbox);
+  // at most 128 blocks: the 8 atomics of every block meet on one cache line
   int64_t nb = nblocks(k, kLT);
-  VMO_LAUNCH(k_box, (unsigned)(nb < 1024 ? nb : 1024), kLT, 0, s, x, k, dbox);
+  VMO_LAUNCH(k_box, (unsigned)(nb < 128 ? nb : 128), kLT, 0, s, x, k, dbox);
 }
 static HostBox read_box(const uint32_t* dbox, hipStream_t s) {
   uint32_t b[8];
@@ -995,6 +996,7 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // one refill serves several leaves.
 constexpr int kWin = 32;
 constexpr int kWT = 256;    // threads per block of the walk
+constexpr int kCntSlots = 256;  // interaction counters of the walk (16 words apart)
 constexpr int kParts = 16;  // a cell has at most 16 children
 
 __device__ __forceinline__ bool far_from(const int32_t* q, const int4& a, double T) {
@@ -1160,8 +1162,26 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
     }
   }
   if (nint) {
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nint, cnt);
+    // kCntSlots counters, 128 bytes apart, so that the wavefronts' atomics
+    // (finishing at about the same time) do not queue on one address
+    const unsigned slot = ((unsigned)blockIdx.x * (kWT / 64) + wv + (unsigned)blockIdx.y * 61u) % kCntSlots;
+    if (lane == 0 && cnt) atomicAdd(&nint[16 * slot], cnt);
   }
+}
+
+// *out = sum of the walk's interaction counters, which are cleared for the
+// next walk (one block of kCntSlots threads).
+__global__ __launch_bounds__(kCntSlots) void k_sum_slots(unsigned long long* slots, unsigned long long* out) {
+  __shared__ unsigned long long sm[kCntSlots];
+  const int t = threadIdx.x;
+  sm[t] = slots[16 * t];
+  slots[16 * t] = 0ull;
+  __syncthreads();
+  for (int off = kCntSlots / 2; off > 0; off >>= 1) {
+    if (t < off) sm[t] += sm[t + off];
+    __syncthreads();
+  }
+  if (t == 0) *out = sm[0];
 }
 
 // y_v = attraction + the parts of the walk in order (point j in tree order is
@@ -1276,9 +1296,18 @@ static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double
   if (gw.part.n < np) gw.part = Buf<float>(C.pool, np);
   unsigned long long* pc = nullptr;
   int ph = prof_begin(C, "walk", 0.0, s, nint ? nullptr : &pc);
+  unsigned long long* target = nint ? nint : pc;
+  if (target && !C.wslots) {
+    // the counters are zero before every counting walk: cleared here once,
+    // then by k_sum_slots after each reading
+    VMO_HIP(hipMalloc(&C.wslots, sizeof(unsigned long long) * 16 * kCntSlots));
+    VMO_HIP(hipMemsetAsync(C.wslots, 0, sizeof(unsigned long long) * 16 * kCntSlots, s));
+    if (ph >= 0) prof_restart(C, ph, s);
+  }
   VMO_LAUNCH(k_walk, dim3(nblocks(L.k, kWT), kParts * spread), kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p,
-             gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, nint ? nint : pc);
+             gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, target ? C.wslots : nullptr);
   prof_end(C, ph, s);
+  if (target) VMO_LAUNCH(k_sum_slots, 1, kCntSlots, 0, s, C.wslots, target);
   VMO_LAUNCH(k_combine, nblocks(L.k, 64), kCombT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p,
              gw.T.nch.p, spread, gw.part.p, y, xmove, alpha);
 }
@@ -1504,16 +1533,22 @@ static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t 
   int32_t k = F.k, l = F.l;
   int64_t np = F.np;
   uint64_t mkey = kTagMatch | ((uint64_t)level << 8) | (comp << 32);
-  Buf<int32_t> mate(Cx.pool, k), best(Cx.pool, k), chg(Cx.pool, 1);
+  // Rounds run in groups of kRounds with one host check per group: a round
+  // after the one that matched nothing changes nothing, so the extra rounds
+  // of the last group leave the matching as it is.
+  constexpr int kRounds = 4;
+  Buf<int32_t> mate(Cx.pool, k), best(Cx.pool, k), chg(Cx.pool, kRounds);
   fill_i32(mate.p, -1, k, s);
   // every round matches at least the best remaining pair, so at most k/2 + 1
-  for (int64_t round = 0;; ++round) {
+  for (int64_t round = 0;; round += kRounds) {
     VMO_REQUIRE(round <= (int64_t)k / 2 + 1, "matching did not settle");
-    VMO_LAUNCH(k_match_best, gsz(k), kLT, 0, s, F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, F.c.p, k, mm, mate.p, seed,
-               mkey, best.p);
-    VMO_HIP(hipMemsetAsync(chg.p, 0, 4, s));
-    VMO_LAUNCH(k_match_pair, gsz(k), kLT, 0, s, best.p, k, mate.p, chg.p);
-    if (read1(chg.p, s) == 0) break;
+    VMO_HIP(hipMemsetAsync(chg.p, 0, 4 * kRounds, s));
+    for (int r = 0; r < kRounds; ++r) {
+      VMO_LAUNCH(k_match_best, gsz(k), kLT, 0, s, F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, F.c.p, k, mm, mate.p, seed,
+                 mkey, best.p);
+      VMO_LAUNCH(k_match_pair, gsz(k), kLT, 0, s, best.p, k, mate.p, chg.p + r);
+    }
+    if (read1(chg.p + kRounds - 1, s) == 0) break;
   }
   Buf<int32_t> root(Cx.pool, k), gmin(Cx.pool, k), flag(Cx.pool, (size_t)k + 1), rank(Cx.pool, (size_t)k + 1);
   VMO_LAUNCH(k_group_root, gsz(k), kLT, 0, s, F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, k, mm, mate.p, root.p, gmin.p);
@@ -1949,12 +1984,11 @@ void gradient(Ctx& C, const vmo_hypergraph* h, const float* x, float theta, int3
   validate_finite(C, x, 4 * (int64_t)h->k, "x", s);
   Level L = level_from(C, h->k, h->l, h->net_ptr, h->pins, h->w, h->c, s);
   GradWork gw;
-  Buf<unsigned long long> cnt(C.pool, 1);
-  VMO_HIP(hipMemsetAsync(cnt.p, 0, 8, s));
+  Buf<unsigned long long> cnt(C.pool, 1);  // written by the walk's counter sum
   gradient_prepare(C, L, x, (double)theta * (double)theta, cap, y, gw, s);
   gradient_walk(C, L, y, nullptr, 0.0, gw, cnt.p, s);
   if (z && L.l > 0) VMO_LAUNCH(k_z_soa, gsz(L.l), kLT, 0, s, gw.z.p, L.l, z);
-  unsigned long long c = read1(cnt.p, s);
+  const unsigned long long c = L.k > 0 ? read1(cnt.p, s) : 0ull;
   if (nint) *nint = (int64_t)c;
 }
 

@@ -934,6 +934,8 @@ void Engine::launch_offset_copy_ptr(const int64_t* in, int64_t* out, int64_t n, 
   VMO_LAUNCH(k_offset_copy_ptr, gsz(n), kT, 0, s, in, out, n, add);
 }
 
+constexpr int kLloydCheck = 4;
+
 // Seeding and Lloyd iterations for segments [s0, s0+Sn) over positions [p0, p1).
 void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max, bool tuned) {
   SegArrays sg = view(cur);
@@ -951,16 +953,19 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
   Buf<int32_t> active(c.pool, (size_t)t_max + 1);  // one counter per iteration, cleared once
   fill_i32(active.p, 0, (int64_t)t_max + 1, s);
   for (int it = 0; it <= t_max; ++it) {
-    const int cfg = tuned ? tune_pick(c, kTuneAssign, bucket, 4) : 1;
+    bool timed = false;
+    const int cfg = tuned ? tune_pick(c, kTuneAssign, bucket, 4, &timed) : 1;
     const int B = kBlocks[cfg];
-    unsigned long long* tw = tuned ? tune_begin(c, kTuneAssign, bucket, cfg, s) : nullptr;
+    unsigned long long* tw = timed ? tune_begin(c, kTuneAssign, bucket, cfg, s) : nullptr;
     int ph = prof_begin(c, "assign", 17.0 * (double)np, s, nullptr);
     const int64_t packs = (p1 - (p0 & ~int64_t(3)) + 3) / 4;
     VMO_LAUNCH(k_assign4, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw);
     prof_end(c, ph, s);
-    if (tuned) tune_end(c, s);
+    if (timed) tune_end(c, s);
     VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p + it);
-    if (read1(active.p + it, s) == 0) break;
+    // one host check every kLloydCheck iterations: an iteration after the
+    // last segment stopped skips every segment, so the extra ones change nothing
+    if ((it % kLloydCheck == kLloydCheck - 1 || it == t_max) && read1(active.p + it, s) == 0) break;
   }
 }
 

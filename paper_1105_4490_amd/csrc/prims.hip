@@ -65,7 +65,9 @@ Pool::~Pool() {
 // --------------------------------------------------------------- profile ----
 Ctx::~Ctx() {
   prof_discard(*this);
+  for (hipEvent_t e : prof.spare) (void)hipEventDestroy(e);
   if (prof.dcnt) (void)hipFree(prof.dcnt);
+  if (wslots) (void)hipFree(wslots);
   for (auto& r : tune.pend) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -75,14 +77,30 @@ Ctx::~Ctx() {
 }
 
 // ----------------------------------------------------------------- tuner ----
-int tune_pick(Ctx& c, int family, int bucket, int ncfg) {
-  TuneStat& st = c.tune.stat[{family, bucket}];
+int tune_pick(Ctx& c, int family, int bucket, int ncfg, bool* timed) {
+  int tot[Tuner::kMaxCfg] = {};
+  bool pending = false;
+  {
+    const TuneStat& st = c.tune.stat[{family, bucket}];
+    for (int i = 0; i < ncfg; ++i) tot[i] = st.n[i];
+  }
+  for (const TuneRec& r : c.tune.pend)
+    if (r.family == family && r.bucket == bucket) {
+      ++tot[r.cfg];
+      pending = true;
+    }
   for (int i = 0; i < ncfg; ++i)
-    if (st.n[i] < 2) return i;
-  int best = 0;
-  for (int i = 1; i < ncfg; ++i)
-    if (st.ms_per_work[i] / st.n[i] < st.ms_per_work[best] / st.n[best]) best = i;
-  return best;
+    if (tot[i] < 2) {
+      *timed = true;
+      return i;
+    }
+  if (pending) tune_flush(c);
+  *timed = false;
+  const TuneStat& st = c.tune.stat[{family, bucket}];
+  int best = -1;
+  for (int i = 0; i < ncfg; ++i)
+    if (st.n[i] > 0 && (best < 0 || st.ms_per_work[i] / st.n[i] < st.ms_per_work[best] / st.n[best])) best = i;
+  return best < 0 ? 0 : best;
 }
 
 unsigned long long* tune_begin(Ctx& c, int family, int bucket, int cfg, hipStream_t s) {
@@ -123,12 +141,14 @@ void tune_end(Ctx& c, hipStream_t s) { VMO_HIP(hipEventRecord(c.tune.pend.back()
 void tune_flush(Ctx& c) {
   Tuner& t = c.tune;
   if (t.pend.empty()) return;
+  // the timed launches have finished (and written their work counts) before
+  // the counts are read
+  for (auto& r : t.pend) VMO_HIP(hipEventSynchronize(r.b));
   std::vector<unsigned long long> w(t.nslot);
   if (t.nslot > 0)
     VMO_HIP(hipMemcpy(w.data(), t.dwork, sizeof(unsigned long long) * t.nslot, hipMemcpyDeviceToHost));
   for (auto& r : t.pend) {
     float ms = 0.0f;
-    VMO_HIP(hipEventSynchronize(r.b));
     VMO_HIP(hipEventElapsedTime(&ms, r.a, r.b));
     const double wk = r.dslot >= 0 ? (double)w[r.dslot] : r.hwork;
     if (wk > 0) {
@@ -147,6 +167,7 @@ void tune_flush(Ctx& c) {
 int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned long long** dwork) {
   if (dwork) *dwork = nullptr;
   if (!c.prof.on) return -1;
+  if (c.prof.seen[name]++ % c.prof.every != 0) return -1;
   ProfPending p;
   p.name = name;
   p.work = work;
@@ -162,13 +183,23 @@ int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned lo
     }
     p.dslot = c.prof.nslot++;
     *dwork = c.prof.dcnt + p.dslot;
-    VMO_HIP(hipMemsetAsync(*dwork, 0, sizeof(unsigned long long), s));
   }
-  VMO_HIP(hipEventCreate(&p.a));
-  VMO_HIP(hipEventCreate(&p.b));
+  for (hipEvent_t* e : {&p.a, &p.b}) {
+    if (!c.prof.spare.empty()) {
+      *e = c.prof.spare.back();
+      c.prof.spare.pop_back();
+    } else {
+      VMO_HIP(hipEventCreate(e));
+    }
+  }
   VMO_HIP(hipEventRecord(p.a, s));
   c.prof.pend.push_back(p);
   return (int)c.prof.pend.size() - 1;
+}
+
+void prof_restart(Ctx& c, int h, hipStream_t s) {
+  if (h < 0) return;
+  VMO_HIP(hipEventRecord(c.prof.pend[h].a, s));
 }
 
 void prof_end(Ctx& c, int h, hipStream_t s) {
@@ -178,19 +209,19 @@ void prof_end(Ctx& c, int h, hipStream_t s) {
 
 void prof_flush(Ctx& c) {
   if (c.prof.pend.empty()) return;
+  for (auto& p : c.prof.pend) VMO_HIP(hipEventSynchronize(p.b));
   std::vector<unsigned long long> cnt(c.prof.nslot);
   if (c.prof.nslot > 0)
     VMO_HIP(hipMemcpy(cnt.data(), c.prof.dcnt, sizeof(unsigned long long) * c.prof.nslot, hipMemcpyDeviceToHost));
   for (auto& p : c.prof.pend) {
     float ms = 0.0f;
-    VMO_HIP(hipEventSynchronize(p.b));
     VMO_HIP(hipEventElapsedTime(&ms, p.a, p.b));
     ProfAcc& a = c.prof.acc[p.name];
     a.ms += ms;
     a.launches += 1;
     a.work += p.dslot >= 0 ? (double)cnt[p.dslot] : p.work;
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
+    c.prof.spare.push_back(p.a);
+    c.prof.spare.push_back(p.b);
   }
   c.prof.pend.clear();
   c.prof.nslot = 0;
@@ -446,10 +477,10 @@ void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t
   // (fewer tiles: shorter look-back chains; more: more blocks in flight)
   static const int kTarget[4] = {64, 128, 256, 512};
   const int bucket = bits_for((uint64_t)n);
-  const int cfg = n > (int64_t)64 * kRsT ? tune_pick(c, kTuneSort, bucket, 4) : 3;
+  bool tuned = false;
+  const int cfg = n > (int64_t)64 * kRsT ? tune_pick(c, kTuneSort, bucket, 4, &tuned) : 3;
   int ri = 1;
   while (ri < kRsMaxI && n > (int64_t)kTarget[cfg] * kRsT * ri) ri *= 2;
-  const bool tuned = n > (int64_t)64 * kRsT;
   if (tuned) tune_begin_host(c, kTuneSort, bucket, cfg, (double)n * passes, s);
   const int64_t tile = (int64_t)kRsT * ri;
   const int64_t ntiles = (n + tile - 1) / tile;

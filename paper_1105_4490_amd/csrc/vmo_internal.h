@@ -103,10 +103,13 @@ struct ProfPending {
 };
 struct Prof {
   bool on = false;
+  int every = 1;                          // time every n-th launch of a name
+  std::map<std::string, int64_t> seen;    // launches per name since enabled
   std::map<std::string, ProfAcc> acc;
   std::vector<ProfPending> pend;
   unsigned long long* dcnt = nullptr;
   int nslot = 0, cap = 0;
+  std::vector<hipEvent_t> spare;          // events of flushed records, reused
 };
 
 // Online launch-configuration tuner.  A kernel family has a few candidate
@@ -138,14 +141,18 @@ struct Ctx {
   Prof prof;
   Tuner tune;
   int* dflag = nullptr;  // device error flag of bounded device-side waits
+  unsigned long long* wslots = nullptr;  // the walk's interaction counters (kept zero between walks)
   ~Ctx();
 };
 
-// Tuner: the configuration to use for (family, bucket) among ncfg; begin
+// Tuner: the configuration to use for (family, bucket) among ncfg.  *timed is
+// set while some candidate has fewer than two timed launches (pending ones
+// included): the caller then brackets the launch with begin/end.  Once every
+// candidate has two, the bucket's pending timings are read (one wait on their
+// events) and the fastest candidate is used, untimed, from then on.  begin
 // records the start event and returns a zeroed device work counter for the
-// kernel; end records the stop event.  Flushed with the profile (after the
-// stream is synchronised).
-int tune_pick(Ctx& c, int family, int bucket, int ncfg);
+// kernel; end records the stop event; flush reads what is pending.
+int tune_pick(Ctx& c, int family, int bucket, int ncfg, bool* timed);
 unsigned long long* tune_begin(Ctx& c, int family, int bucket, int cfg, hipStream_t s);
 void tune_begin_host(Ctx& c, int family, int bucket, int cfg, double work, hipStream_t s);
 void tune_end(Ctx& c, hipStream_t s);
@@ -160,8 +167,11 @@ void check_device_flag(Ctx& c, hipStream_t s);
 
 // Returns a handle for prof_end (-1 when profiling is off).  If dwork is not
 // NULL it receives a zeroed device counter the kernel adds its work to.
+// dwork != NULL: *dwork receives a device counter slot for the launch's work,
+// which the caller's kernels write (it is not cleared).
 int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned long long** dwork);
 void prof_end(Ctx& c, int h, hipStream_t s);
+void prof_restart(Ctx& c, int h, hipStream_t s);  // records the start event of h again
 // Collect finished events (call after the stream is synchronised).
 void prof_flush(Ctx& c);
 void prof_discard(Ctx& c);

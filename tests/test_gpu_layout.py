@@ -104,6 +104,30 @@ def test_descent_steps(ctx, case):
     assert np.array_equal(host(gx), xo)
 
 
+def test_profile_times_every_nth_walk(ctx):
+    """Live timing with sampling: six descent steps (one walk each) time six
+    walks with every = 1 and the first and fourth with every = 3; the sampled
+    interaction counts are part of the full ones, and the steps' results do
+    not depend on the timing."""
+    import paper_1105_4490_amd as P
+    h = weighted_case(7, 2000, 1500)
+    gp = P.layout_params(seed=3)
+    x0 = oracle.layout_init(h.k, 3)
+    dh = dev_h(h)
+    res = {}
+    for every in (1, 3):
+        ctx.profile(True, every=every)
+        ctx.profile_reset()
+        gx = dev_x(x0)
+        ctx.layout_steps(dh, gx, gp, 0, 6, 0.0)
+        res[every] = (ctx.profile_read("walk"), host(gx))
+        ctx.profile(False)
+    full, part = res[1][0], res[3][0]
+    assert full["launches"] == 6 and part["launches"] == 2
+    assert 0 < part["work"] < full["work"] and part["total_ms"] > 0
+    assert np.array_equal(res[1][1], res[3][1])
+
+
 @pytest.mark.parametrize("case", ["random", "grid3d", "star", "weighted"])
 def test_coarsen(ctx, case):
     if case == "random":
