@@ -13,6 +13,7 @@
 namespace vmo {
 
 constexpr int kLT = 256;
+constexpr int kParts = 16;  // a cell has at most 16 children
 static unsigned gsz(int64_t n) {
   int64_t b = (n + kLT - 1) / kLT;
   return (unsigned)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
@@ -255,9 +256,8 @@ struct NodeView {
   TNode* t;
   double* Wd;
   double* Sd;  // [n][4]
-  int32_t* parent;
   int32_t* nch;
-  int32_t* ctr;
+  int32_t* ctr;  // depth lists of the one-block build
   int32_t* cid;  // [n][16] children in order (a cell has at most 16 sub-cells)
 };
 
@@ -283,8 +283,6 @@ __global__ void k_tree_nodes(const int8_t* cpl, const uint64_t* key, const int8_
       nd.t[t].a = cc;
       nd.t[t].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
       nd.t[t].T = ft.T[L];
-      nd.parent[t] = -1;
-      nd.ctr[t] = 0;
     }
   }
 }
@@ -298,7 +296,6 @@ __global__ void k_tree_links(const int32_t* __restrict__ n_dev, NodeView nd) {
     if (!((b.w >> 8) & 1)) {
       int32_t ch = t + 1;
       while (ch != b.x) {
-        nd.parent[ch] = t;
         if (cnt < 16) nd.cid[16 * (int64_t)t + cnt] = ch;  // a cell has at most 16 sub-cells
         ++cnt;
         ch = nd.t[ch].b.x;
@@ -340,30 +337,22 @@ __device__ __forceinline__ void leaf_sums(int32_t first, int32_t count, int32_t 
 }
 
 // Charge of an internal node: its nc children's charges in child order.  The
-// children are loaded four at a time (with coherent loads when other
-// workgroups wrote them in this launch).
-__device__ __forceinline__ void child_sums(NodeView nd, int32_t p, int32_t nc, bool coherent, double& W2,
-                                           double* S2) {
+// children are loaded eight at a time.
+__device__ __forceinline__ void child_sums(NodeView nd, int32_t p, int32_t nc, double& W2, double* S2) {
   const int4* cq = reinterpret_cast<const int4*>(nd.cid + 16 * (int64_t)p);
-  for (int32_t r0 = 0; r0 < nc; r0 += 4) {
-    const int4 c4 = cq[r0 >> 2];
-    const int32_t cc[4] = {c4.x, c4.y, c4.z, c4.w};
-    double wv[4], sv[4][4];
+  for (int32_t r0 = 0; r0 < nc; r0 += 8) {
+    const int4 c4a = cq[r0 >> 2], c4b = cq[(r0 >> 2) + 1];
+    const int32_t cc[8] = {c4a.x, c4a.y, c4a.z, c4a.w, c4b.x, c4b.y, c4b.z, c4b.w};
+    double wv[8], sv[8][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       if (r0 + u < nc) {
-        if (coherent) {
-          wv[u] = __hip_atomic_load(&nd.Wd[cc[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          for (int d = 0; d < 4; ++d)
-            sv[u][d] = __hip_atomic_load(&nd.Sd[4 * (int64_t)cc[u] + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          wv[u] = nd.Wd[cc[u]];
-          for (int d = 0; d < 4; ++d) sv[u][d] = nd.Sd[4 * (int64_t)cc[u] + d];
-        }
+        wv[u] = nd.Wd[cc[u]];
+        for (int d = 0; d < 4; ++d) sv[u][d] = nd.Sd[4 * (int64_t)cc[u] + d];
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       if (r0 + u < nc) {
         W2 += wv[u];
         for (int d = 0; d < 4; ++d) S2[d] += sv[u][d];
@@ -372,31 +361,87 @@ __device__ __forceinline__ void child_sums(NodeView nd, int32_t p, int32_t nc, b
   }
 }
 
-// Charges bottom-up: a leaf sums its points in tree order (FP64); the last
-// child to finish sums its parent's children in child order.
-__global__ void k_tree_moments(const int32_t* __restrict__ n_dev, int32_t k, const float* xs, const float* ws,
-                               NodeView nd) {
-  const int32_t n = *n_dev;
-  GRID_STRIDE(t64, n) {
-    int32_t t = (int32_t)t64;
-    int4 b = nd.t[t].b;
-    if (!((b.w >> 8) & 1)) continue;
-    double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
-    leaf_sums(b.y, b.z, k, xs, ws, Wd, Sd);
-    node_finish(nd, t, Wd, Sd);
-    int32_t cur = t;
-    while (true) {
-      int32_t p = nd.parent[cur];
-      if (p < 0) break;
-      __threadfence();
-      int old = atomicAdd(&nd.ctr[p], 1);
-      if (old != nd.nch[p] - 1) break;
-      __threadfence();
-      double W2 = 0.0, S2[4] = {0.0, 0.0, 0.0, 0.0};
-      child_sums(nd, p, nd.nch[p], true, W2, S2);
-      node_finish(nd, p, W2, S2);
-      cur = p;
+// Charges without cross-workgroup waits: workgroup (i1, i2, i3) takes the
+// subtree of the node reached from the root through child i1, then child i2,
+// then child i3 (a node range [r, next(r)) in pre-order), or the leaf met on
+// the way when i1..i3 below it are zero, and forms its charges bottom-up:
+// leaves first, then the internal nodes depth by depth, deepest first, with a
+// barrier between depths.  k_moments_top then forms the charges of the
+// internal nodes of depths 2, 1 and 0.  The sums and their order are those of
+// the one-block build: a leaf sums its points in tree order, an internal node
+// its children's charges in child order, in FP64.
+constexpr int kMomT = 256;
+constexpr int kMomD = 3;  // depth of the subtree roots
+__global__ __launch_bounds__(kMomT) void k_moments_sub(int32_t k, const float* xs, const float* ws, NodeView nd) {
+  __shared__ int maxd;
+  const int idx[kMomD] = {(int)blockIdx.x / (kParts * kParts), (int)(blockIdx.x / kParts) % kParts,
+                          (int)blockIdx.x % kParts};
+  int32_t r = 0;
+  for (int lv = 0; lv < kMomD; ++lv) {
+    if ((nd.t[r].b.w >> 8) & 1) {
+      for (int u = lv; u < kMomD; ++u)
+        if (idx[u] != 0) return;  // the whole block
+      break;
     }
+    if (idx[lv] >= min(nd.nch[r], kParts)) return;  // the whole block
+    r = nd.cid[16 * (int64_t)r + idx[lv]];
+  }
+  const int32_t lo = r, hi = nd.t[r].b.x;
+  if (threadIdx.x == 0) maxd = -1;
+  __syncthreads();
+  int md = -1;
+  for (int32_t t = lo + threadIdx.x; t < hi; t += kMomT) {
+    const int4 b = nd.t[t].b;
+    if ((b.w >> 8) & 1) {
+      double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+      leaf_sums(b.y, b.z, k, xs, ws, Wd, Sd);
+      node_finish(nd, t, Wd, Sd);
+    } else {
+      md = max(md, b.w & 255);
+    }
+  }
+  if (md >= 0) atomicMax(&maxd, md);
+  __syncthreads();
+  const int top = maxd;  // deepest internal node of the range (uniform)
+  const int L0 = nd.t[lo].b.w & 255;
+  for (int L = top; L >= L0; --L) {
+    for (int32_t t = lo + threadIdx.x; t < hi; t += kMomT) {
+      const int4 b = nd.t[t].b;
+      if ((b.w & 0x1ff) != L) continue;  // internal (leaf bit clear) at depth L
+      double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+      child_sums(nd, t, nd.nch[t], Wd, Sd);
+      node_finish(nd, t, Wd, Sd);
+    }
+    __syncthreads();
+  }
+}
+
+// Internal nodes of depths 2, 1, 0 (one block of kParts^2 threads).
+__global__ __launch_bounds__(kParts * kParts) void k_moments_top(NodeView nd) {
+  if ((nd.t[0].b.w >> 8) & 1) return;
+  const int i1 = threadIdx.x / kParts, i2 = threadIdx.x % kParts;
+  const int n1 = min(nd.nch[0], kParts);
+  const int32_t c1 = i1 < n1 ? nd.cid[i1] : -1;
+  const bool c1int = c1 >= 0 && !((nd.t[c1].b.w >> 8) & 1);
+  if (c1int && i2 < min(nd.nch[c1], kParts)) {
+    const int32_t c2 = nd.cid[16 * (int64_t)c1 + i2];
+    if (!((nd.t[c2].b.w >> 8) & 1)) {
+      double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+      child_sums(nd, c2, nd.nch[c2], Wd, Sd);
+      node_finish(nd, c2, Wd, Sd);
+    }
+  }
+  __syncthreads();
+  if (i2 == 0 && c1int) {
+    double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+    child_sums(nd, c1, nd.nch[c1], Wd, Sd);
+    node_finish(nd, c1, Wd, Sd);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+    child_sums(nd, 0, nd.nch[0], Wd, Sd);
+    node_finish(nd, 0, Wd, Sd);
   }
 }
 
@@ -665,7 +710,6 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       nd.t[tn].a = cc;
       nd.t[tn].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
       nd.t[tn].T = ft.T[L];
-      nd.parent[tn] = -1;
       if (nxt_lds) nxt[tn] = base[end] | (L == li ? (int32_t)0x80000000 : 0);
     }
   }
@@ -678,7 +722,6 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       if (bx >= 0) {
         int32_t ch = tn + 1;
         while (ch != bx) {
-          nd.parent[ch] = tn;
           if (cnt2 < 16) nd.cid[16 * (int64_t)tn + cnt2] = ch;
           ++cnt2;
           ch = nxt[ch] & 0x7fffffff;
@@ -689,7 +732,6 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       if (!((b.w >> 8) & 1)) {
         int32_t ch = tn + 1;
         while (ch != b.x) {
-          nd.parent[ch] = tn;
           if (cnt2 < 16) nd.cid[16 * (int64_t)tn + cnt2] = ch;
           ++cnt2;
           ch = nd.t[ch].b.x;
@@ -719,7 +761,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
   __syncthreads();
   for (int32_t tn = t; tn < n; tn += kSTB) {
     const int L = nd.t[tn].b.w & 255;
-    nd.ctr[atomicAdd(&dpos[L], 1)] = tn;  // ctr is unused by this build: the depth lists
+    nd.ctr[atomicAdd(&dpos[L], 1)] = tn;  // ctr: the depth lists (this build only)
   }
   __syncthreads();
   // charges (same sums and order as k_tree_moments): every leaf first, then
@@ -738,7 +780,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       const int32_t tn = nd.ctr[e];
       if ((nd.t[tn].b.w >> 8) & 1) continue;
       double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
-      child_sums(nd, tn, nd.nch[tn], false, Wd, Sd);
+      child_sums(nd, tn, nd.nch[tn], Wd, Sd);
       node_finish(nd, tn, Wd, Sd);
     }
     __syncthreads();
@@ -754,11 +796,11 @@ struct Tree {
   Buf<TNode> nodes;
   Buf<float4> P;  // points in tree order
   Buf<double> Wd, Sd;
-  Buf<int32_t> parent, nch, ctr, cid;
+  Buf<int32_t> nch, ctr, cid;
   NodeView view() {
     NodeView v;
     v.t = nodes.p; v.Wd = Wd.p; v.Sd = Sd.p;
-    v.parent = parent.p; v.nch = nch.p; v.ctr = ctr.p; v.cid = cid.p;
+    v.nch = nch.p; v.ctr = ctr.p; v.cid = cid.p;
     return v;
   }
 };
@@ -781,7 +823,6 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
     T.nodes = Buf<TNode>(C.pool, nmax);
     T.Wd = Buf<double>(C.pool, nmax);
     T.Sd = Buf<double>(C.pool, 4 * nmax);
-    T.parent = Buf<int32_t>(C.pool, nmax);
     T.nch = Buf<int32_t>(C.pool, nmax);
     T.ctr = Buf<int32_t>(C.pool, nmax);
     T.cid = Buf<int32_t>(C.pool, 16 * nmax);
@@ -808,9 +849,7 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
   T.nodes = Buf<TNode>(C.pool, nmax);
   T.Wd = Buf<double>(C.pool, nmax);
   T.Sd = Buf<double>(C.pool, 4 * nmax);
-  T.parent = Buf<int32_t>(C.pool, nmax);
   T.nch = Buf<int32_t>(C.pool, nmax);
-  T.ctr = Buf<int32_t>(C.pool, nmax);
   T.cid = Buf<int32_t>(C.pool, 16 * nmax);
   NodeView nd = T.view();
   VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.key.p, T.ell.p, T.nn.p, T.p2.p, k, far_table(th2), nd);
@@ -818,7 +857,8 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
   // (below 2 k), grid-stride loops up to the count
   const int32_t* n_dev = T.nn.p + k;
   VMO_LAUNCH(k_tree_links, gsz(2 * (int64_t)k), kLT, 0, s, n_dev, nd);
-  VMO_LAUNCH(k_tree_moments, gsz(2 * (int64_t)k), kLT, 0, s, n_dev, k, T.xs.p, T.ws.p, nd);
+  VMO_LAUNCH(k_moments_sub, kParts * kParts * kParts, kMomT, 0, s, k, T.xs.p, T.ws.p, nd);
+  VMO_LAUNCH(k_moments_top, 1, kParts * kParts, 0, s, nd);
 }
 
 // ============================================================ gradient ====
@@ -997,7 +1037,6 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 constexpr int kWin = 32;
 constexpr int kWT = 256;    // threads per block of the walk
 constexpr int kCntSlots = 256;  // interaction counters of the walk (16 words apart)
-constexpr int kParts = 16;  // a cell has at most 16 children
 
 __device__ __forceinline__ bool far_from(const int32_t* q, const int4& a, double T) {
   // exact: integers below 2^40, so fused and separate roundings agree
