@@ -356,31 +356,53 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
                                                      K* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
                                                      int shift, int ri, const uint32_t* __restrict__ ghist,
                                                      uint64_t* status, uint32_t* tile_ctr, int* err) {
+  // per (round, wavefront, digit): count, then exclusive offset in the tile
+  __shared__ uint16_t cnt[kRsMaxI][kRsT / 64][256];
   __shared__ int run[256];
-  __shared__ int cnt[256];
-  __shared__ int wc[4][256];
-  __shared__ uint32_t scan[256];
+  __shared__ int wsum[kRsT / 64];
   __shared__ int tile_sh;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (t == 0) tile_sh = (int)atomicAdd(tile_ctr, 1u);
-  cnt[t] = 0;
+  uint32_t* cnt32 = reinterpret_cast<uint32_t*>(&cnt[0][0][0]);
+  for (int e = t; e < ri * (kRsT / 64) * 256 / 2; e += kRsT) cnt32[e] = 0u;
   __syncthreads();
   const int64_t tile = tile_sh;
   const int64_t base = tile * kRsT * ri;
+  const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
   K key[kRsMaxI];
-  int dig[kRsMaxI];
+  int dig[kRsMaxI], rk[kRsMaxI];
+  // ranks of every round at once: lanes of a wavefront with equal digits are
+  // found by eight ballots; each (round, wavefront, digit) count is written by
+  // the first such lane
 #pragma unroll
   for (int r = 0; r < kRsMaxI; ++r) {
+    if (r >= ri) break;
     const int64_t idx = base + (int64_t)r * kRsT + t;
-    const bool valid = r < ri && idx < n;
+    const bool valid = idx < n;
     key[r] = valid ? kin[idx] : K(0);
     dig[r] = valid ? (int)((key[r] >> shift) & 255u) : -1;
-    if (valid) atomicAdd(&cnt[dig[r]], 1);
+    const int d = valid ? dig[r] : 0;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    rk[r] = __popcll(m & below);
+    if (valid && rk[r] == 0) cnt[r][w][d] = (uint16_t)__popcll(m);
   }
   __syncthreads();
+  // digit t: offsets over (round, wavefront) in order; c = its count in the tile
+  int c = 0;
+  for (int r = 0; r < ri; ++r)
+    for (int ww = 0; ww < kRsT / 64; ++ww) {
+      const int v = cnt[r][ww][t];
+      cnt[r][ww][t] = (uint16_t)c;
+      c += v;
+    }
   // publish this tile's count of digit t, then look back for the keys of
   // digit t in earlier tiles
-  const int c = cnt[t];
   uint64_t* st = status + tile * 256 + t;
   uint64_t excl = 0;
   if (tile == 0) {
@@ -406,46 +428,28 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
     }
     __hip_atomic_store(st, kStP | (excl + (uint64_t)c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  // exclusive scan of the digit totals of this pass
-  scan[t] = ghist[t];
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t a = t >= off ? scan[t - off] : 0u;
-    __syncthreads();
-    scan[t] += a;
-    __syncthreads();
+  // exclusive scan of the digit totals of this pass: within each wavefront by
+  // shuffles, then the totals of the earlier wavefronts
+  const int g = (int)ghist[t];
+  int inc = g;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += u;
   }
-  run[t] = (int)((t > 0 ? scan[t - 1] : 0u) + excl);
-  const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
-  // stable ranks: rounds in order; in a round, waves in order, lanes with the
-  // same digit found by eight ballots
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int pre = inc - g;
+  for (int ww = 0; ww < w; ++ww) pre += wsum[ww];
+  run[t] = (int)(pre + excl);
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRsMaxI; ++r) {
     if (r >= ri) break;
-    wc[0][t] = 0; wc[1][t] = 0; wc[2][t] = 0; wc[3][t] = 0;
-    __syncthreads();
-    const bool valid = dig[r] >= 0;
-    const int d = valid ? dig[r] : 0;
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1;
-      const uint64_t bb = __ballot(valid && bit);
-      m &= bit ? bb : ~bb;
-    }
-    const int rank = __popcll(m & below);
-    if (valid && rank == 0) wc[w][d] = __popcll(m);
-    __syncthreads();
-    if (valid) {
-      int off = run[d];
-      for (int ww = 0; ww < w; ++ww) off += wc[ww][d];
-      const int dest = off + rank;
-      kout[dest] = key[r];
-      if (vin) vout[dest] = vin[base + (int64_t)r * kRsT + t];
-    }
-    __syncthreads();
-    run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
-    __syncthreads();
+    if (dig[r] < 0) continue;
+    const int d = dig[r];
+    const int dest = run[d] + cnt[r][w][d] + rk[r];
+    kout[dest] = key[r];
+    if (vin) vout[dest] = vin[base + (int64_t)r * kRsT + t];
   }
 }
 
