@@ -461,7 +461,7 @@ __device__ __forceinline__ int32_t key_coord(uint64_t m, int d) {
 }
 
 __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x, const float* __restrict__ w,
-                                                     int32_t k, int32_t cap, const uint32_t* __restrict__ box,
+                                                     int32_t k, int32_t cap, uint32_t* __restrict__ box,
                                                      FarTable ft, int32_t* __restrict__ order, float* __restrict__ xs,
                                                      float* __restrict__ ws, int32_t* __restrict__ p2,
                                                      float4* __restrict__ P, NodeView nd, int32_t* __restrict__ nn) {
@@ -480,9 +480,36 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
   int32_t* tsum = reinterpret_cast<int32_t*>(rb + 24640);       // [1024]
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
+  // the bounding box of x (as k_box), kept in LDS and written to box
+  __shared__ uint32_t sbox[8];
+  {
+    if (t < 8) sbox[t] = t < 4 ? 0xffffffffu : 0u;
+    uint32_t mn[4], mx[4];
+    for (int d = 0; d < 4; ++d) { mn[d] = 0xffffffffu; mx[d] = 0u; }
+    for (int v = t; v < k; v += kSTB)
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t f = fkey(x[(int64_t)d * k + v]);
+        mn[d] = min(mn[d], f);
+        mx[d] = max(mx[d], f);
+      }
+    for (int off = 32; off > 0; off >>= 1)
+      for (int d = 0; d < 4; ++d) {
+        mn[d] = min(mn[d], (uint32_t)__shfl_xor((int)mn[d], off, 64));
+        mx[d] = max(mx[d], (uint32_t)__shfl_xor((int)mx[d], off, 64));
+      }
+    __syncthreads();
+    if (lane == 0)
+      for (int d = 0; d < 4; ++d) {
+        atomicMin(&sbox[d], mn[d]);
+        atomicMax(&sbox[4 + d], mx[d]);
+      }
+    __syncthreads();
+    if (t < 8) box[t] = sbox[t];
+  }
+
   for (int v = t; v < k; v += kSTB) {
     uint32_t kq[4];
-    grid_coords(x, k, v, box, kq);
+    grid_coords(x, k, v, sbox, kq);
     uint64_t m = 0;
     for (int b = 15; b >= 0; --b)
       for (int d = 0; d < 4; ++d) m = (m << 1) | ((kq[d] >> b) & 1u);
@@ -535,18 +562,25 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       // waves of round r, then the totals of the earlier rounds are added
       const int d = t & 255, r = t >> 8;
       int acc = 0;
-      if (r < rounds)
-        for (int ww = 0; ww < 16; ++ww) {
-          const int c = cnt[r][ww][d];
-          cnt[r][ww][d] = (uint16_t)acc;
-          acc += c;
-        }
+      int cv[16];  // the counts of (r, every wave, d), read before any write
+      if (r < rounds) {
+#pragma unroll
+        for (int ww = 0; ww < 16; ++ww) cv[ww] = cnt[r][ww][d];
+#pragma unroll
+        for (int ww = 0; ww < 16; ++ww) acc += cv[ww];
+      }
       rtot[r][d] = acc;
       __syncthreads();
       int pre = 0;
       for (int r2 = 0; r2 < r; ++r2) pre += rtot[r2][d];
-      if (pre && r < rounds)
-        for (int ww = 0; ww < 16; ++ww) cnt[r][ww][d] = (uint16_t)(cnt[r][ww][d] + pre);
+      if (r < rounds) {
+        int a = pre;
+#pragma unroll
+        for (int ww = 0; ww < 16; ++ww) {
+          cnt[r][ww][d] = (uint16_t)a;
+          a += cv[ww];
+        }
+      }
       if (r == 3) run[d] = pre + acc;
     }
     __syncthreads();
@@ -581,7 +615,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     const int32_t v = val[j];
     order[j] = v;
     uint32_t kq[4];
-    grid_coords(x, k, v, box, kq);
+    grid_coords(x, k, v, sbox, kq);
     float c[4];
     for (int d = 0; d < 4; ++d) {
       c[d] = x[(int64_t)d * k + v];
@@ -805,10 +839,12 @@ struct Tree {
   }
 };
 
-// Build the tree of x [4][k] (weights w or 1) with the bounding box dbox.  The
-// node count is left on the device at T.nn[k] (no host round trip): node
-// arrays are sized for the largest possible tree, 17 nodes per position.
-static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t k, int32_t cap, const uint32_t* dbox,
+// Build the tree of x [4][k] (weights w or 1) with the bounding box dbox: the
+// one-block build (small_ok, k <= kSmallK) computes the box of x itself into
+// dbox, the multi-kernel build reads it.  The node count is left on the device
+// at T.nn[k] (no host round trip): node arrays are sized for the largest
+// possible tree, 17 nodes per position.
+static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t k, int32_t cap, uint32_t* dbox,
                        double th2, hipStream_t s, bool small_ok = true) {
   T.k = k;
   T.n = -1;
@@ -1312,7 +1348,7 @@ struct GradWork {
 static void gradient_prepare(Ctx& C, const Level& L, const float* x, double th2, int32_t cap, float* y, GradWork& gw,
                              hipStream_t s) {
   if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
-  box_of(x, L.k, gw.box.p, s);
+  if (L.k > kSmallK) box_of(x, L.k, gw.box.p, s);  // else the one-block tree build forms it
   gw.z = Buf<float4>(C.pool, (size_t)(L.l > 0 ? L.l : 1));
   if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, L.k, gw.z.p);
   if (L.k <= 16384)
