@@ -1081,6 +1081,7 @@ __device__ __forceinline__ bool far_from(const int32_t* q, const int4& a, double
   return D2 >= T;
 }
 
+template <bool kCount>  // kCount: count the interactions into nint
 __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restrict__ n_dev, const float4* __restrict__ P,
                                               const float* __restrict__ ws, const int32_t* __restrict__ p2,
                                               const TNode* __restrict__ nodes, const int32_t* __restrict__ cid,
@@ -1125,21 +1126,38 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
 
   int32_t wb = -2 * kWin;  // node window: nodes [wb, wb + kWin)
   int32_t pb = -2 * kWin;  // point window: points [pb, pb + kWin) in tree order
+  // The window that follows the current one is loaded ahead into registers
+  // (lane l holds 16-byte chunks 2 (l & 1) and 2 (l & 1) + 1 of node pf + l / 2):
+  // a walk that leaves the window forward often lands in it, and then the
+  // refill waits for no memory.
+  const int po = lane >> 1, pc = (lane & 1) * 2;
+  int32_t pf = -1;
+  int4 pfa = make_int4(0, 0, 0, 0), pfb = make_int4(0, 0, 0, 0);
+  const int4* nodes4 = reinterpret_cast<const int4*>(nodes);
   // the union walk of the lanes with skip marks < t1 over [.., t1), into y
   auto run = [&](int32_t skip, int32_t t1, float* y) {
     int32_t t = __builtin_amdgcn_readfirstlane(wave_min(skip));
     while (t < t1) {
       if (t < wb || t >= wb + kWin) {
-        wb = t;
-        const int32_t tt = t + lane;
-        if (lane < kWin && tt < n) {
-          const int4* src = reinterpret_cast<const int4*>(nodes + tt);
-          win[wv][0][lane] = src[0];
-          win[wv][1][lane] = src[1];
-          win[wv][2][lane] = src[2];
-          win[wv][3][lane] = src[3];
+        if (pf >= 0 && t >= pf && t < pf + kWin) {
+          wb = pf;  // the window loaded ahead
+        } else {
+          wb = t;
+          if (t + po < n) {
+            pfa = nodes4[4 * (int64_t)(t + po) + pc];
+            pfb = nodes4[4 * (int64_t)(t + po) + pc + 1];
+          }
+        }
+        if (wb + po < n) {
+          win[wv][pc][po] = pfa;
+          win[wv][pc + 1][po] = pfb;
         }
         wave_sync();
+        pf = wb + kWin;
+        if (pf + po < n) {
+          pfa = nodes4[4 * (int64_t)(pf + po) + pc];
+          pfb = nodes4[4 * (int64_t)(pf + po) + pc + 1];
+        }
       }
       const int o = t - wb;
       const int4 a = win[wv][0][o];
@@ -1149,11 +1167,10 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
       // all four reads in flight together, one wait for them
       asm volatile("" ::"v"(a.x), "v"(a.y), "v"(a.z), "v"(a.w), "v"(xi.x), "v"(xi.y), "v"(xi.z), "v"(xi.w), "v"(wi.x),
                    "v"(wi.z), "v"(wi.w));
-      // the link fields are the same on every lane: scalar registers, so that
-      // the leaf loops below are scalar loops
-      const int32_t bnext = __builtin_amdgcn_readfirstlane(b.x);
-      const int32_t bfirst = __builtin_amdgcn_readfirstlane(b.y);
-      const int32_t bcount = __builtin_amdgcn_readfirstlane(b.z);
+      // the link fields are the same on every lane: the flags (and, at a
+      // leaf, the point range) in scalar registers, so that the leaf loops
+      // below are scalar loops
+      const int32_t bnext = b.x;
       const int32_t bflags = __builtin_amdgcn_readfirstlane(b.w);
       const bool act = skip <= t;
       const bool far = act & far_from(q, a, __hiloint2double(wi.w, wi.z));
@@ -1162,11 +1179,12 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
                  __int_as_float(wi.x));
         skip = bnext;
       }
-      cnt += (unsigned long long)__popcll(__ballot(far));
+      if (kCount) cnt += (unsigned long long)__popcll(__ballot(far));
       const bool near = act && !far;
       if ((bflags >> 8) & 1) {
         if (__any(near)) {
-          const int32_t f1 = bfirst + bcount;
+          const int32_t bfirst = __builtin_amdgcn_readfirstlane(b.y);
+          const int32_t f1 = bfirst + __builtin_amdgcn_readfirstlane(b.z);
           for (int32_t base = bfirst; base < f1; base += kWin) {
             const int32_t e = f1 - base < kWin ? f1 : base + kWin;
             if (base < pb || e > pb + kWin) {
@@ -1189,7 +1207,8 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
                 interact(y, xn, wn2, pi.x, pi.y, pi.z, pi.w, lw[wv][o2 + i]);
               }
             }
-            cnt += (unsigned long long)m * __popcll(__ballot(near)) -
+            if (kCount)
+              cnt += (unsigned long long)m * __popcll(__ballot(near)) -
                    __popcll(__ballot(near && j >= base && j < base + m));
           }
         }
@@ -1213,7 +1232,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
       const float4 X = nodes[0].X;
       interact(acc1, xn, wn2, X.x, X.y, X.z, X.w, nodes[0].W);
     }
-    if (i1 == 0) cnt += (unsigned long long)__popcll(__ballot(rootfar));
+    if (kCount && i1 == 0) cnt += (unsigned long long)__popcll(__ballot(rootfar));
     run(single && !rootfar ? c1 : 0x7fffffff, c1 + 1, acc1);
   }
   // children of c1 walked here (none when c1 is a leaf: n2 = 0)
@@ -1236,7 +1255,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
       for (int d = 0; d < 4; ++d) part[(((int64_t)i1 * kParts + i2s) * 4 + d) * k + j] = acc2[d];
     }
   }
-  if (nint) {
+  if (kCount) {
     // kCntSlots counters, 128 bytes apart, so that the wavefronts' atomics
     // (finishing at about the same time) do not queue on one address
     const unsigned slot = ((unsigned)blockIdx.x * (kWT / 64) + wv + (unsigned)blockIdx.y * 61u) % kCntSlots;
@@ -1379,8 +1398,13 @@ static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double
     VMO_HIP(hipMemsetAsync(C.wslots, 0, sizeof(unsigned long long) * 16 * kCntSlots, s));
     if (ph >= 0) prof_restart(C, ph, s);
   }
-  VMO_LAUNCH(k_walk, dim3(nblocks(L.k, kWT), kParts * spread), kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p,
-             gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, target ? C.wslots : nullptr);
+  const dim3 wgrid(nblocks(L.k, kWT), kParts * spread);
+  if (target)
+    VMO_LAUNCH((k_walk<true>), wgrid, kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p, gw.T.nodes.p,
+               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, C.wslots);
+  else
+    VMO_LAUNCH((k_walk<false>), wgrid, kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p, gw.T.nodes.p,
+               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, nullptr);
   prof_end(C, ph, s);
   if (target) VMO_LAUNCH(k_sum_slots, 1, kCntSlots, 0, s, C.wslots, target);
   VMO_LAUNCH(k_combine, nblocks(L.k, 64), kCombT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p,
