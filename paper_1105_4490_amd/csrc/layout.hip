@@ -242,15 +242,41 @@ static FarTable far_table(double th2) {
   return f;
 }
 
-// One tree node as the walk reads it (64 bytes).
+// One tree node as the walk reads it (80 bytes, five 16-byte chunks).  The
+// far test of a point q against the cell centre c (both in doubled grid
+// units), |q - c|^2 >= T (T from the FarTable of the cell's depth), is kept
+// as |q|^2 + A.q >= Tq with A = -2 c and Tq = T - |c|^2: every term is an
+// integer below 2^42, so the FP64 fused multiply-adds are exact and the two
+// forms decide every point alike.
 struct alignas(16) TNode {
-  int4 a;    // cell centre x 2 (grid units)
-  int4 b;    // next, first, count, depth | leaf << 8
-  float4 X;  // charge centre
-  float W;   // charge
+  double A[4];  // -2 c (chunks 0 and 1)
+  int4 b;       // next, first, count, depth | leaf << 8 (chunk 2)
+  float4 X;     // charge centre (chunk 3)
+  double Tq;    // T - |c|^2 (chunk 4)
+  float W;      // charge
   float pad;
-  double T;  // far threshold of the node's depth (FarTable)
 };
+static_assert(sizeof(TNode) == 80, "TNode is five 16-byte chunks");
+
+// The cell geometry of a node: centre cc (doubled grid units), threshold T.
+__device__ __forceinline__ void node_geom(TNode& nd, const int4& cc, double T) {
+  const double c0 = cc.x, c1 = cc.y, c2 = cc.z, c3 = cc.w;
+  nd.A[0] = -2.0 * c0; nd.A[1] = -2.0 * c1; nd.A[2] = -2.0 * c2; nd.A[3] = -2.0 * c3;
+  nd.Tq = T - __builtin_fma(c3, c3, __builtin_fma(c2, c2, __builtin_fma(c1, c1, c0 * c0)));
+}
+
+// Far test of the point with coordinates qd (doubled grid units, as FP64)
+// and q2 = |qd|^2 against a node: exact, as above.
+__device__ __forceinline__ bool far_q(const double* qd, double q2, const double* A, double Tq) {
+  double D = __builtin_fma(A[0], qd[0], q2);
+  D = __builtin_fma(A[1], qd[1], D);
+  D = __builtin_fma(A[2], qd[2], D);
+  D = __builtin_fma(A[3], qd[3], D);
+  return D >= Tq;
+}
+__device__ __forceinline__ double norm2_q(const double* qd) {
+  return __builtin_fma(qd[3], qd[3], __builtin_fma(qd[2], qd[2], __builtin_fma(qd[1], qd[1], qd[0] * qd[0])));
+}
 
 struct NodeView {
   TNode* t;
@@ -280,9 +306,8 @@ __global__ void k_tree_nodes(const int8_t* cpl, const uint64_t* key, const int8_
       cc.y = 2 * ((kq1 >> (16 - L)) << (16 - L)) + side;
       cc.z = 2 * ((kq2 >> (16 - L)) << (16 - L)) + side;
       cc.w = 2 * ((kq3 >> (16 - L)) << (16 - L)) + side;
-      nd.t[t].a = cc;
+      node_geom(nd.t[t], cc, ft.T[L]);
       nd.t[t].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
-      nd.t[t].T = ft.T[L];
     }
   }
 }
@@ -741,9 +766,8 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
       cc.y = 2 * ((kq[1] >> (16 - L)) << (16 - L)) + side;
       cc.z = 2 * ((kq[2] >> (16 - L)) << (16 - L)) + side;
       cc.w = 2 * ((kq[3] >> (16 - L)) << (16 - L)) + side;
-      nd.t[tn].a = cc;
+      node_geom(nd.t[tn], cc, ft.T[L]);
       nd.t[tn].b = make_int4(base[end], i, end - i, L | ((L == li ? 1 : 0) << 8));
-      nd.t[tn].T = ft.T[L];
       if (nxt_lds) nxt[tn] = base[end] | (L == li ? (int32_t)0x80000000 : 0);
     }
   }
@@ -1065,21 +1089,14 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // single walk moves forward in pre-order, so each lane performs exactly the
 // interactions of its own walk, in the same order.  The wave moves to t + 1
 // while some lane is still descending, else to the smallest skip mark.
-// Nodes are staged through a per-wavefront LDS window of 64 consecutive nodes
-// (one 64-byte node per lane per refill, stored chunk-major so that refills
-// are free of bank conflicts), and the points of near leaves through a second
-// window of 64 consecutive points: the walk meets leaves in tree order, so
-// one refill serves several leaves.
+// Nodes are staged through a per-wavefront LDS window of kWin consecutive
+// nodes (the five 16-byte chunks of an 80-byte node stored chunk-major, so
+// that every lane reads one node's chunk with one broadcast read), and the
+// points of near leaves through a second window of kWin consecutive points:
+// the walk meets leaves in tree order, so one refill serves several leaves.
 constexpr int kWin = 32;
 constexpr int kWT = 256;    // threads per block of the walk
 constexpr int kCntSlots = 256;  // interaction counters of the walk (16 words apart)
-
-__device__ __forceinline__ bool far_from(const int32_t* q, const int4& a, double T) {
-  // exact: integers below 2^40, so fused and separate roundings agree
-  double d0 = (double)(q[0] - a.x), d1 = (double)(q[1] - a.y), d2 = (double)(q[2] - a.z), d3 = (double)(q[3] - a.w);
-  double D2 = __builtin_fma(d3, d3, __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0)));
-  return D2 >= T;
-}
 
 template <bool kCount>  // kCount: count the interactions into nint
 __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restrict__ n_dev, const float4* __restrict__ P,
@@ -1088,7 +1105,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
                                               const int32_t* __restrict__ nch, int spread, float* __restrict__ part,
                                               unsigned long long* nint) {
   constexpr int NW = kWT / 64;
-  __shared__ int4 win[NW][4][kWin];
+  __shared__ int4 win[NW][5][kWin];  // the five 16-byte chunks of kWin nodes
   __shared__ float4 lp[NW][kWin];
   __shared__ float lw[NW][kWin];
   const int i1 = blockIdx.y / spread, i2s = blockIdx.y % spread;
@@ -1107,76 +1124,64 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
   // interactions of the wavefront (uniform: counted from lane masks)
   unsigned long long cnt = 0;
   float xn[4] = {0.f, 0.f, 0.f, 0.f};
-  int32_t q[4] = {0, 0, 0, 0};
+  double qd[4] = {0.0, 0.0, 0.0, 0.0};  // doubled grid coordinates
   float wn = 0.0f;
   if (valid) {
     float4 pj = P[j];
     xn[0] = pj.x; xn[1] = pj.y; xn[2] = pj.z; xn[3] = pj.w;
-    for (int d = 0; d < 4; ++d) q[d] = p2[(int64_t)d * k + j];
+    for (int d = 0; d < 4; ++d) qd[d] = (double)p2[(int64_t)d * k + j];
     wn = ws[j];
   }
+  const double q2 = norm2_q(qd);
   const float wn2 = 2.0f * wn;
   auto wave_sync = [&]() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  const bool rootfar = valid && far_from(q, nodes[0].a, nodes[0].T);
-  const bool single = valid && (rootfar || c1leaf || far_from(q, nodes[c1].a, nodes[c1].T));
+  const bool rootfar = valid && far_q(qd, q2, nodes[0].A, nodes[0].Tq);
+  const bool single = valid && (rootfar || c1leaf || far_q(qd, q2, nodes[c1].A, nodes[c1].Tq));
 
   int32_t wb = -2 * kWin;  // node window: nodes [wb, wb + kWin)
   int32_t pb = -2 * kWin;  // point window: points [pb, pb + kWin) in tree order
-  // The window that follows the current one is loaded ahead into registers
-  // (lane l holds 16-byte chunks 2 (l & 1) and 2 (l & 1) + 1 of node pf + l / 2):
-  // a walk that leaves the window forward often lands in it, and then the
-  // refill waits for no memory.
+  // refill: lane l loads chunks 2 (l & 1) and 2 (l & 1) + 1 of node wb + l / 2,
+  // lanes below kWin chunk 4 of node wb + l
   const int po = lane >> 1, pc = (lane & 1) * 2;
-  int32_t pf = -1;
-  int4 pfa = make_int4(0, 0, 0, 0), pfb = make_int4(0, 0, 0, 0);
   const int4* nodes4 = reinterpret_cast<const int4*>(nodes);
   // the union walk of the lanes with skip marks < t1 over [.., t1), into y
   auto run = [&](int32_t skip, int32_t t1, float* y) {
     int32_t t = __builtin_amdgcn_readfirstlane(wave_min(skip));
     while (t < t1) {
       if (t < wb || t >= wb + kWin) {
-        if (pf >= 0 && t >= pf && t < pf + kWin) {
-          wb = pf;  // the window loaded ahead
-        } else {
-          wb = t;
-          if (t + po < n) {
-            pfa = nodes4[4 * (int64_t)(t + po) + pc];
-            pfb = nodes4[4 * (int64_t)(t + po) + pc + 1];
-          }
+        wb = t;
+        if (t + po < n) {
+          win[wv][pc][po] = nodes4[5 * (int64_t)(t + po) + pc];
+          win[wv][pc + 1][po] = nodes4[5 * (int64_t)(t + po) + pc + 1];
         }
-        if (wb + po < n) {
-          win[wv][pc][po] = pfa;
-          win[wv][pc + 1][po] = pfb;
-        }
+        if (lane < kWin && t + lane < n) win[wv][4][lane] = nodes4[5 * (int64_t)(t + lane) + 4];
         wave_sync();
-        pf = wb + kWin;
-        if (pf + po < n) {
-          pfa = nodes4[4 * (int64_t)(pf + po) + pc];
-          pfb = nodes4[4 * (int64_t)(pf + po) + pc + 1];
-        }
       }
       const int o = t - wb;
-      const int4 a = win[wv][0][o];
-      const int4 b = win[wv][1][o];
-      const int4 xi = win[wv][2][o];
-      const int4 wi = win[wv][3][o];
-      // all four reads in flight together, one wait for them
-      asm volatile("" ::"v"(a.x), "v"(a.y), "v"(a.z), "v"(a.w), "v"(xi.x), "v"(xi.y), "v"(xi.z), "v"(xi.w), "v"(wi.x),
-                   "v"(wi.z), "v"(wi.w));
+      const int4 a01 = win[wv][0][o];
+      const int4 a23 = win[wv][1][o];
+      const int4 b = win[wv][2][o];
+      const int4 xi = win[wv][3][o];
+      const int4 tw = win[wv][4][o];
+      // all five reads in flight together, one wait for them
+      asm volatile("" ::"v"(a01.x), "v"(a01.y), "v"(a01.z), "v"(a01.w), "v"(a23.x), "v"(a23.y), "v"(a23.z),
+                   "v"(a23.w), "v"(xi.x), "v"(xi.y), "v"(xi.z), "v"(xi.w), "v"(tw.x), "v"(tw.y), "v"(tw.z));
+      const double A[4] = {__hiloint2double(a01.y, a01.x), __hiloint2double(a01.w, a01.z),
+                           __hiloint2double(a23.y, a23.x), __hiloint2double(a23.w, a23.z)};
       // the link fields are the same on every lane: the flags (and, at a
       // leaf, the point range) in scalar registers, so that the leaf loops
       // below are scalar loops
       const int32_t bnext = b.x;
       const int32_t bflags = __builtin_amdgcn_readfirstlane(b.w);
       const bool act = skip <= t;
-      const bool far = act & far_from(q, a, __hiloint2double(wi.w, wi.z));
+      const bool far = act & far_q(qd, q2, A, __hiloint2double(tw.y, tw.x));
       if (far) {
         interact(y, xn, wn2, __int_as_float(xi.x), __int_as_float(xi.y), __int_as_float(xi.z), __int_as_float(xi.w),
-                 __int_as_float(wi.x));
+                 __int_as_float(tw.z));
         skip = bnext;
       }
       if (kCount) cnt += (unsigned long long)__popcll(__ballot(far));
@@ -1297,11 +1302,12 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
   const bool valid = j < k;
   const bool rleaf = (nodes[0].b.w >> 8) & 1;
   const int n1 = rleaf ? 1 : min(nch[0], kParts);
-  int32_t q[4] = {0, 0, 0, 0};
+  double qd[4] = {0.0, 0.0, 0.0, 0.0};
   if (valid)
-    for (int d = 0; d < 4; ++d) q[d] = p2[(int64_t)d * k + j];
+    for (int d = 0; d < 4; ++d) qd[d] = (double)p2[(int64_t)d * k + j];
+  const double q2 = norm2_q(qd);
   // a root that is a leaf or far from the point: one part, in slot 0
-  const bool one = rleaf || (valid && far_from(q, nodes[0].a, nodes[0].T));
+  const bool one = rleaf || (valid && far_q(qd, q2, nodes[0].A, nodes[0].Tq));
   const int np = one ? 1 : n1;
   float a1[4] = {0.f, 0.f, 0.f, 0.f};
   if (valid && i1 < np) {
@@ -1311,7 +1317,7 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
     } else {
       const int32_t c1 = cid[i1];
       const bool c1leaf = (nodes[c1].b.w >> 8) & 1;
-      if (c1leaf || far_from(q, nodes[c1].a, nodes[c1].T)) {
+      if (c1leaf || far_q(qd, q2, nodes[c1].A, nodes[c1].Tq)) {
         for (int d = 0; d < 4; ++d) a1[d] = part[(((int64_t)i1 * kParts) * 4 + d) * k + j];
       } else {
         const int n2 = min(nch[c1], kParts);
@@ -2047,7 +2053,9 @@ void coarsen(Ctx& C, const vmo_hypergraph* h, uint64_t seed, uint64_t comp, int3
 __global__ void k_tree_out(int32_t n, NodeView nd, int32_t* ints, int32_t* cell2, float* flt) {
   GRID_STRIDE(t, n) {
     int4 b = nd.t[t].b;
-    int4 a = nd.t[t].a;
+    int4 a;  // the cell centre back from A = -2 c (exact)
+    a.x = (int)(-0.5 * nd.t[t].A[0]); a.y = (int)(-0.5 * nd.t[t].A[1]);
+    a.z = (int)(-0.5 * nd.t[t].A[2]); a.w = (int)(-0.5 * nd.t[t].A[3]);
     float4 X = nd.t[t].X;
     int32_t* r = ints + 8 * t;
     r[0] = b.y; r[1] = b.z; r[2] = b.w & 255; r[3] = (b.w >> 8) & 1; r[4] = b.x; r[5] = r[6] = r[7] = 0;
