@@ -243,6 +243,19 @@ def order(h: Hypergraph, x, P: int, seed: int, mode: int = NET_MODE, ord: int = 
     return OrderResult(vperm, None if nperm is None else nperm[:l], part, heap, vptr, nptr, sc, nn.value)
 
 
+def border(h: Hypergraph, vperm, part, node_heap, node_vptr, n_nodes: int, P: int, b: int):
+    """Recursive ordering of the border (Sec. 4.2, cut rows and columns into
+    recursive BBD form): vperm of a graph-mode ordering with every separator
+    block sorted, stably, by b two-bit words (o_border)."""
+    out = np.zeros(h.k, dtype=np.int32)
+    arr = [np.ascontiguousarray(a, dtype=np.int32) for a in (vperm, part, node_heap, node_vptr)]
+    rc = lib().o_border(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(arr[0]), _p(arr[1]), _p(arr[2]),
+                        _p(arr[3]), C.c_int32(n_nodes), C.c_int32(P), C.c_int32(b), _p(out))
+    if rc != 0:
+        raise ValueError("oracle border rejected its input")
+    return out
+
+
 # ---------------------------------------------------------------- layout ----
 
 class LayoutParams(C.Structure):

@@ -26,6 +26,9 @@
  *   o_order           recursive SBD/BBD ordering, net mode and graph mode
  *                     [Algorithm 7; Sec. 4.1 recursive BBD; Sec. 4.2
  *                      permutations; Sec. 5 SBD form].
+ *   o_border          recursive ordering of the border: separator blocks
+ *                     sorted by b two-bit words [Sec. 4.2, cut rows and
+ *                     columns into recursive BBD form].
  *   o_coarsen         one coarsening step [Sec. 2.3, coarsening by greedy
  *                     heavy-net matching, single-neighbour rule, net merge].
  *   o_tree            2^d-tree with cluster charges [Sec. 2.1 tree
@@ -522,6 +525,74 @@ int o_order(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const
   *n_nodes_out = nnodes;
   for (int32_t h = 0; h < nmax; ++h) { free(nd[h].verts); free(nd[h].sep); free(nd[h].nets); }
   free(nd); free(order); free(q); free(netnode); free(mark); free(sd_of); free(s_of); free(in_sep);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Recursive ordering of the border [Sec. 4.2, the paragraphs on the freedom
+   left in the cut rows and columns; the rightmost partitioning of the figure
+   on matrix partitionings for recursive BBD].  Input: a graph-mode ordering
+   (vperm, part, node_heap, node_vptr, n_nodes as o_order writes them; nets
+   are edges {v, w}).  Every vertex w of the separator V3 of a node h (heap id,
+   depth d = floor(log2 h)) gets b two-bit words, first word most significant,
+   all 00 at the start.  Word i (i = 1..b) records the split of the nodes at
+   depth d + i below h: when such a node Vj splits into Vj1, Vj2 and its own
+   separator, every edge {v, w} with v in Vj1 sets the first bit (value 1) of
+   w's word i and every edge with v in Vj2 its second bit (value 2); a v in a
+   separator or a leaf at depth <= d + i sets nothing.  The vertices of each
+   separator block are then sorted by their words, stably (equal words keep
+   their order).  Leaf blocks and the part ids do not change.  b = 0 copies
+   vperm.  Returns 0 or <0. */
+static int32_t heap_depth(int32_t h) {
+  int32_t d = 0;
+  while (h > 1) { h >>= 1; ++d; }
+  return d;
+}
+int o_border(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const int32_t* vperm,
+             const int32_t* part, const int32_t* node_heap, const int32_t* node_vptr, int32_t n_nodes, int32_t P,
+             int32_t b, int32_t* vperm_out) {
+  if (k < 1 || P < 1 || b < 0 || b > 15 || n_nodes < 1 || n_nodes > 4 * P) return -1;
+  for (int32_t i = 0; i < k; ++i) vperm_out[i] = vperm[i];
+  if (b == 0) return 0;
+  /* the node (heap id) each vertex ends in */
+  int32_t* leaf_heap = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+  int32_t* vh = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  uint32_t* word = (uint32_t*)calloc((size_t)k, sizeof(uint32_t));
+  for (int32_t p = 0; p < P; ++p) leaf_heap[p] = 0;
+  for (int32_t r = 0; r < n_nodes; ++r)
+    for (int32_t i = node_vptr[r]; i < node_vptr[r + 1]; ++i)
+      if (part[vperm[i]] < P) leaf_heap[part[vperm[i]]] = node_heap[r];
+  for (int32_t v = 0; v < k; ++v) vh[v] = part[v] >= P ? part[v] - P : leaf_heap[part[v]];
+  /* the words: every edge, seen from each end that lies in a separator */
+  for (int32_t e = 0; e < l; ++e) {
+    if (ptr[e + 1] - ptr[e] != 2) continue;
+    for (int s = 0; s < 2; ++s) {
+      const int32_t w = pins[ptr[e] + s], v = pins[ptr[e] + 1 - s];
+      if (part[w] < P) continue;  /* w is not a separator vertex */
+      const int32_t h = vh[w], d = heap_depth(h);
+      const int32_t hv = vh[v], D = heap_depth(hv);
+      if (D <= d || (hv >> (D - d)) != h) continue;  /* v is not below h */
+      for (int32_t i = 1; i <= b; ++i) {
+        if (D < d + i + 1) break;  /* v stopped at or above depth d + i */
+        const int32_t second = (hv >> (D - d - i - 1)) & 1;  /* which part of the split at depth d + i */
+        word[w] |= (uint32_t)(second ? 2 : 1) << (2 * (b - i));
+      }
+    }
+  }
+  /* stable sort of each separator block by the words (insertion sort) */
+  for (int32_t r = 0; r < n_nodes; ++r) {
+    const int32_t lo = node_vptr[r], hi = node_vptr[r + 1];
+    if (hi - lo < 2 || part[vperm[lo]] < P) continue;
+    for (int32_t i = lo + 1; i < hi; ++i) {
+      const int32_t v = vperm_out[i];
+      int32_t j = i - 1;
+      while (j >= lo && word[vperm_out[j]] > word[v]) { vperm_out[j + 1] = vperm_out[j]; --j; }
+      vperm_out[j + 1] = v;
+    }
+  }
+  free(leaf_heap);
+  free(vh);
+  free(word);
   return 0;
 }
 
