@@ -163,7 +163,38 @@ def main():
                          "share_of_step": round(assign["total_ms"] * PROFILE_EVERY / (1e3 * dt), 4)},
         "cpu_baseline": cpu,
     }
+    h = ctx.model(P.SYMMETRIC, g.m, g.n, rowptr, col)
+    line.update(order_only_and_border(ctx, h, g, lp, o, args.steps))
     print(json.dumps(line))
+
+
+def order_only_and_border(ctx, h, g, lp, o, steps):
+    """The O column (ordering from given coordinates: the layout of the same
+    matrix, computed before the timed region) and the recursive ordering of
+    the border (b = 3 two-bit words) of the V+O result, each timed over
+    `steps` calls after one untimed call."""
+    import torch
+    x = ctx.layout(h, lp)
+    ctx.order(h, x, P_PARTS, SEED, mode=1, order=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.order(h, x, P_PARTS, SEED, mode=1, order=1)
+    torch.cuda.synchronize()
+    dt_o = (time.perf_counter() - t0) / steps
+    b = 3
+    ctx.order_border(h, o, P_PARTS, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.order_border(h, o, P_PARTS, b)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / steps
+    return {"order_only": {"metric": "matrix nnz ordered/sec (recursive BBD from given coordinates)",
+                           "value": g.nnz / dt_o, "unit": "nnz/s", "ms": 1e3 * dt_o},
+            "border": {"b": b, "value": g.nnz / dt_b, "unit": "nnz/s", "ms": 1e3 * dt_b,
+                       "what": "recursive ordering of the border of the V+O result (separator blocks sorted by "
+                               "b two-bit words), one call per timing"}}
 
 
 def _pct(v, q):

@@ -227,6 +227,27 @@ vmo_status vmo_order_bbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const f
                          const vmo_layout_params* lp, int32_t P, uint64_t seed, int32_t t_max,
                          const vmo_order_out* out, vmo_stream stream);
 
+/* Recursive ordering of the border (Sec. 4.2: the freedom left in the cut
+ * rows and columns of a recursive BBD, used to bring them into recursive BBD
+ * form as in the rightmost partitioning of the figure on matrix
+ * partitionings).  h: the graph of a VMO_GRAPH ordering (every net an edge
+ * {v, w}, v < w); in: that ordering's vperm, part, node_heap, node_vptr and
+ * n_nodes (device arrays as vmo_order writes them; nperm, node_nptr and
+ * split_cut are not read); P: its part count.  Every vertex w of the
+ * separator of a node h (depth d = floor(log2 h)) gets b two-bit words, the
+ * first the most significant: word i has bit 1 (value 1) if an edge joins w to
+ * a vertex in the first part (heap 2g) of the split of a node g at depth
+ * d + i below h, and bit 2 (value 2) for the second part (2g + 1); vertices in
+ * separators or leaves at depth <= d + i set nothing.  vperm_out[k] (device;
+ * may be in->vperm) receives vperm with every separator block sorted stably by
+ * the words; leaf blocks, part ids and the node tables are unchanged.  b in
+ * [0, 15] (0: a copy).  VMO_E_INVALID if h is not a graph or the ordering
+ * arrays are inconsistent (heap ids outside [1, 4P), block boundaries not
+ * non-decreasing from 0 to k, part ids neither in [0, P) nor P + heap id,
+ * vperm not a permutation). */
+vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_order_out* in /* (host) */, int32_t P,
+                            int32_t b, int32_t* vperm_out, vmo_stream stream);
+
 /* Many orderings in one pass: every level of every job is processed by the
    same launches over one segment list (jobs[i].job_index keys its random
    draws as the job number).  Results equal those of vmo_order per job with

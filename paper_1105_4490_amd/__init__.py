@@ -276,6 +276,19 @@ class Context:
             o["nperm"] = o["nperm"][:h.l]
         return o
 
+    def order_border(self, h: DeviceHypergraph, o: dict, P: int, b: int, out: torch.Tensor | None = None):
+        """Recursive ordering of the border (vmo_order_border): o is the dict
+        order() returned for a graph-mode ordering of h; returns vperm with every
+        separator block sorted by b two-bit words."""
+        if out is None:
+            out = torch.empty_like(o["vperm"])
+        s = OrderOut(_ptr(o["vperm"]), None, _ptr(o["part"]), _ptr(o["node_heap"]), _ptr(o["node_vptr"]), None, None,
+                     _ptr(o["n_nodes"]))
+        hs = h.cstruct()
+        self._check(lib().vmo_order_border(self.h, C.byref(hs), C.byref(s), C.c_int32(P), C.c_int32(b), _ptr(out),
+                                           _stream()))
+        return out
+
     def order_batch(self, jobs, t_max: int = 32, plain: bool = False):
         """jobs: list of dicts with h, x, P, seed, mode, order, job_index.  Outputs
         of all jobs share one allocation per array kind (views per job)."""

@@ -21,6 +21,8 @@ void gradient(Ctx& c, const vmo_hypergraph* h, const float* x, float theta, int3
               int64_t* nint, hipStream_t s);
 void layout_steps(Ctx& c, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, int32_t it0, int32_t iters,
                   double* alpha, hipStream_t s);
+void order_border(Ctx& c, const vmo_hypergraph* h, const vmo_order_out* in, int32_t P, int32_t b, int32_t* vperm_out,
+                  hipStream_t s);
 }  // namespace vmo
 
 #define API_BEGIN(ctx, stream)                                    \
@@ -195,6 +197,13 @@ vmo_status vmo_order_sbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const f
 vmo_status vmo_order_bbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const float* x, const vmo_layout_params* lp,
                          int32_t P, uint64_t seed, int32_t t_max, const vmo_order_out* out, vmo_stream stream) {
   return vmo_order(ctx, h, mode, VMO_BBD, x, lp, P, seed, t_max, out, stream);
+}
+
+vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_order_out* in, int32_t P, int32_t b,
+                            int32_t* vperm_out, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::order_border(C, h, in, P, b, vperm_out, S);
+  API_END
 }
 
 static vmo_status order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, int32_t t_max, bool plain,
