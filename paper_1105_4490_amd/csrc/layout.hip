@@ -532,7 +532,11 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     if (t < 8) box[t] = sbox[t];
   }
 
-  for (int v = t; v < k; v += kSTB) {
+  // (the four rounds unrolled: their loads are issued together)
+#pragma unroll
+  for (int r = 0; r < kSmallK / kSTB; ++r) {
+    const int v = r * kSTB + t;
+    if (v >= k) break;
     uint32_t kq[4];
     grid_coords(x, k, v, sbox, kq);
     uint64_t m = 0;
@@ -635,8 +639,11 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     __syncthreads();
   }
 
-  // points in tree order
-  for (int j = t; j < k; j += kSTB) {
+  // points in tree order (the four rounds unrolled)
+#pragma unroll
+  for (int r = 0; r < kSmallK / kSTB; ++r) {
+    const int j = r * kSTB + t;
+    if (j >= k) break;
     const int32_t v = val[j];
     order[j] = v;
     uint32_t kq[4];
@@ -732,15 +739,21 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
   int32_t* nxt = reinterpret_cast<int32_t*>(&cnt[0][0][0]);
   constexpr int32_t kNxtCap = (int32_t)(sizeof(cnt) / sizeof(int32_t));
   const bool nxt_lds = n <= kNxtCap;
-  // nodes in pre-order (as k_tree_nodes)
-  for (int i = t; i < k; i += kSTB) {
+  // nodes in pre-order (as k_tree_nodes), one thread per node: node tn
+  // begins at the last position i with base[i] <= tn, at depth
+  // cpl[i] + 1 + (tn - base[i])
+  for (int32_t tn = t; tn < n; tn += kSTB) {
+    int32_t i = 0, hb = k;  // the last i in [0, k) with base[i] <= tn
+    while (hb - i > 1) {
+      const int32_t mid = (i + hb) >> 1;
+      if (base[mid] <= tn) i = mid; else hb = mid;
+    }
     const int ci = cpl[i], li = ell[i];
-    if (li < ci + 1) continue;
+    const int L = ci + 1 + (tn - base[i]);
     const uint64_t ki = key[i];
     int32_t kq[4];
     for (int d = 0; d < 4; ++d) kq[d] = key_coord(ki, d);
-    for (int L = ci + 1; L <= li; ++L) {
-      const int32_t tn = base[i] + (L - ci - 1);
+    {
       int32_t end = k;
       if (L > 0) {
         const int shf = 64 - 4 * L;

@@ -796,13 +796,18 @@ void csr_transpose(Ctx& c, int32_t nrows, int32_t ncols, const int64_t* ptr, con
 __device__ __forceinline__ int32_t uf_parent(int32_t* par, int32_t x) {
   return __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Root of x with path halving: a vertex that is not a root is pointed at its
+// grandparent (still one of its ancestors; links only ever change roots, so
+// the shortcut never undoes a link) and the search continues from there.
 __device__ __forceinline__ int32_t uf_find(int32_t* par, int32_t x) {
-  int32_t p = uf_parent(par, x);
-  while (p != x) {
-    x = p;
-    p = uf_parent(par, x);
+  while (true) {
+    const int32_t p = uf_parent(par, x);
+    if (p == x) return x;
+    const int32_t gp = uf_parent(par, p);
+    if (gp == p) return p;
+    __hip_atomic_store(&par[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = gp;
   }
-  return x;
 }
 // Link the pins of each net (consecutive pairs) into one tree; a root is
 // always hooked under a smaller root, so every final root is its tree's
