@@ -191,15 +191,17 @@ def test_order_with_layout_inside(ctx):
     compare_order(o, ref, oracle.NET_MODE, h.k, h.l)
 
 
-def test_full_size_gradient_sampled(ctx):
-    """64^3 7-point pattern, symmetric model: the gradient at the layout the
-    GPU computes, checked at 2000 sampled vertices against the oracle."""
-    import paper_1105_4490_amd as P
-    g = vmo_gen.grid3d(64, seed=1)
+@pytest.mark.parametrize("side", [64, 104])
+def test_full_size_gradient_sampled(ctx, side):
+    """The 7-point pattern of side^3 vertices, symmetric model (64: the
+    benchmark size, walk parts spread over the children of their cells;
+    104: 1,124,864 vertices, above the 2^20 points where the walk stops
+    spreading), at clustered synthetic coordinates: the gradient checked at
+    2000 sampled vertices against the oracle."""
+    g = vmo_gen.grid3d(side, seed=1)
     h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
     dh = dev_h(h)
-    x = host(ctx.layout(dh, P.layout_params(seed=1)))
-    assert np.isfinite(x).all()
+    x = vmo_gen.random_points(h.k, side, clusters=64, spread=0.3)
     gy, _, nint = ctx.gradient(dh, dev_x(x))
     ids = vmo_gen.rng(1, 77).choice(h.k, size=2000, replace=False).astype(np.int32)
     y, cnt = oracle.gradient_sample(h, x, ids)
