@@ -194,7 +194,8 @@ static void finish_ticket(vmo_server_s* S, uint64_t id, vmo_status st, const std
 
 // A layout thread: lays out admitted jobs that came without coordinates.
 static void layout_loop(vmo_server_s* S, vmo_layout_worker* W) {
-  hipSetDevice(S->ctx.device);
+  // a thread whose device cannot be selected fails every layout it takes
+  const hipError_t dev = hipSetDevice(S->ctx.device);
   while (true) {
     uint64_t id;
     Ticket* T;
@@ -207,6 +208,7 @@ static void layout_loop(vmo_server_s* S, vmo_layout_worker* W) {
       T = &S->tickets[id];
     }
     try {
+      VMO_HIP(dev);
       T->xbuf = Buf<float>(W->ctx.pool, 4 * (size_t)T->job.h.k);
       layout(W->ctx, &T->job.h, &T->lp, T->xbuf.p, W->stream);
       check_device_flag(W->ctx, W->stream);
@@ -225,7 +227,8 @@ static void layout_loop(vmo_server_s* S, vmo_layout_worker* W) {
 }
 
 static void serve_loop(vmo_server_s* S) {
-  hipSetDevice(S->ctx.device);
+  // the same device that vmo_serve_create selected (and checked) on its thread
+  (void)hipSetDevice(S->ctx.device);
   Engine& E = *S->eng;
   const bool threads = !S->lw.empty();
   while (true) {
