@@ -1401,11 +1401,14 @@ static void gradient_prepare(Ctx& C, const Level& L, const float* x, double th2,
 // is applied to xmove (the layout being descended) and y is left as is.
 static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double alpha, GradWork& gw,
                           unsigned long long* nint, hipStream_t s) {
-  // levels of up to 2^20 points spread each part of the walk over the
-  // children of its cell (16 times the wavefronts; the parts then take
-  // 4 KB per point, 4 GB at the limit)
+  // Levels of up to kSpreadMax points spread each part of the walk over the
+  // children of its cell: 16 times the wavefronts, and up to 16 times the
+  // parts to write and add up.  Above it the unspread walk already has more
+  // than six wavefronts per resident slot of the chip (256 CUs x 32), and
+  // spreading only adds traffic.
+  constexpr int32_t kSpreadMax = 200000;
   if (L.k <= 0) return;
-  const int spread = L.k <= (1 << 20) ? kParts : 1;
+  const int spread = L.k <= kSpreadMax ? kParts : 1;
   const size_t np = (size_t)kParts * spread * 4 * L.k;
   if (gw.part.n < np) gw.part = Buf<float>(C.pool, np);
   unsigned long long* pc = nullptr;

@@ -191,13 +191,13 @@ def test_order_with_layout_inside(ctx):
     compare_order(o, ref, oracle.NET_MODE, h.k, h.l)
 
 
-@pytest.mark.parametrize("side", [64, 104])
+@pytest.mark.parametrize("side", [48, 64, 104])
 def test_full_size_gradient_sampled(ctx, side):
-    """The 7-point pattern of side^3 vertices, symmetric model (64: the
-    benchmark size, walk parts spread over the children of their cells;
-    104: 1,124,864 vertices, above the 2^20 points where the walk stops
-    spreading), at clustered synthetic coordinates: the gradient checked at
-    2000 sampled vertices against the oracle."""
+    """The 7-point pattern of side^3 vertices, symmetric model (48: 110,592
+    vertices, walk parts spread; 64: the benchmark size, and 104: 1,124,864
+    vertices, both above the 200,000 points where the walk stops spreading),
+    at clustered synthetic coordinates: the gradient checked at 2000 sampled
+    vertices against the oracle."""
     g = vmo_gen.grid3d(side, seed=1)
     h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
     dh = dev_h(h)
