@@ -323,6 +323,13 @@ __global__ __launch_bounds__(1024) void k_assign4(SegArrays sg, const int32_t* s
   for (int u = 0; u < 4; ++u)
     if (key[u] >= 0) kt = (kt == -1 || kt == key[u]) ? key[u] : -2;
   const int k0 = __builtin_amdgcn_readfirstlane(kt);
+  // wavefronts with one segment leave their sums here; the block adds those
+  // of equal segments before the atomics (a level's first segments hold
+  // hundreds of thousands of positions, whose per-wavefront atomics would
+  // queue on the same six words)
+  __shared__ int skey[32];
+  __shared__ long long ssum[32][6];
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if (k0 != -2 && __all(kt == k0)) {
     // one segment across the wavefront: 32-bit DPP sums (totals below 256 * 2^20)
     if (k0 >= 0) {
@@ -331,10 +338,11 @@ __global__ __launch_bounds__(1024) void k_assign4(SegArrays sg, const int32_t* s
       for (int f = 0; f < 6; ++f)
         t[f] = wave_sum_dpp((int32_t)(v[0][f] + v[1][f] + v[2][f] + v[3][f]));
       if (lane_id() == 63)
-        for (int f = 0; f < 6; ++f)
-          if (t[f]) atomicAdd((unsigned long long*)&sg.acc[k0 * kAccF + kAccS1 + f], (unsigned long long)t[f]);
+        for (int f = 0; f < 6; ++f) ssum[wv][f] = t[f];
     }
+    if (lane_id() == 63) skey[wv] = k0;
   } else {
+    if (lane_id() == 63) skey[wv] = -1;
     // the u-th positions of the lanes increase with the lane: equal keys are runs
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -344,6 +352,22 @@ __global__ __launch_bounds__(1024) void k_assign4(SegArrays sg, const int32_t* s
       if (wave_seg_sum<6>(key[u], w6))
         for (int f = 0; f < 6; ++f)
           if (w6[f]) atomicAdd((unsigned long long*)&sg.acc[key[u] * kAccF + kAccS1 + f], (unsigned long long)w6[f]);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    // field f: one atomic per run of wavefronts with the same segment
+    const int f = threadIdx.x;
+    int cur = -1;
+    long long acc = 0;
+    for (int w = 0; w <= nw; ++w) {
+      const int kw = w < nw ? skey[w] : -1;
+      if (kw != cur) {
+        if (cur >= 0 && acc) atomicAdd((unsigned long long*)&sg.acc[cur * kAccF + kAccS1 + f], (unsigned long long)acc);
+        cur = kw;
+        acc = 0;
+      }
+      if (kw >= 0) acc += ssum[w][f];
     }
   }
   if (work && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(work, 17ull * (unsigned long long)(p1 - p0));
