@@ -475,7 +475,10 @@ __global__ __launch_bounds__(kT) void k_separator(SegArrays sg, int64_t s0, int6
       rem &= ~kill;
     }
     if (valid && ((mask >> lane) & 1ull)) __hip_atomic_store(&sep[ch], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    // the next chunk's reads see these stores: the positions of a segment are
+    // read and written by this wavefront only, so the order is needed among
+    // its own lanes (workgroup scope: a wait for the stores, no cache write-back)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   }
 }
 
@@ -619,53 +622,70 @@ __global__ void k_vperm(const JobDev* jobs, int32_t nj, const int32_t* id, int64
   }
 }
 
-// One thread per job: in-order (SBD) or post-order (BBD) walk of the heap tree.
-__global__ void k_emit(const JobDev* jobs, int32_t nj, NodeArrays nd, const OutPtrs* outs, int32_t* rank_of) {
-  int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nj) return;
+// Emission ranks, one block per job: the order is in-order (SBD: left, node,
+// right) or post-order (BBD: left, right, node) over the heap tree.  Subtree
+// sizes go bottom-up and the rank of each subtree's first node top-down, one
+// heap level per pass (sz and off are scratch, one word per node slot).
+constexpr int kEmitT = 256;
+__global__ __launch_bounds__(kEmitT) void k_emit(const JobDev* jobs, int32_t nj, NodeArrays nd, const OutPtrs* outs,
+                                                 int32_t* rank_of, int32_t* sz, int32_t* off) {
+  const int32_t j = blockIdx.x;
+  if (j >= nj) return;  // the whole block
   const JobDev& J = jobs[j];
   const OutPtrs& O = outs[j];
-  int64_t nb = J.node_base;
-  int32_t nmax = 4 * J.P;
-  int32_t stk[80];
-  int8_t stage[80];
-  int sp = 0;
-  int32_t r = 0;
-  stk[0] = 1; stage[0] = 0; sp = 1;
-  bool post = J.ord == VMO_BBD;
-  while (sp > 0) {
-    int32_t h = stk[sp - 1];
-    int32_t st = nd.state[nb + h];
-    bool leaf = st == kNodeLeaf;
-    bool emit = false;
-    if (leaf) { emit = true; --sp; }
-    else if (stage[sp - 1] == 0) { stage[sp - 1] = 1; stk[sp] = 2 * h; stage[sp] = 0; ++sp; }
-    else if (stage[sp - 1] == 1) {
-      stage[sp - 1] = 2;
-      if (!post) emit = true;
-      stk[sp] = 2 * h + 1; stage[sp] = 0; ++sp;
-    } else {
-      if (post) emit = true;
-      --sp;
+  const int64_t nb = J.node_base;
+  const int32_t nmax = 4 * J.P;
+  const bool post = J.ord == VMO_BBD;
+  const int dmax = 31 - __clz(nmax - 1);  // deepest heap level below nmax
+  auto state = [&](int32_t h) { return h < nmax ? nd.state[nb + h] : kNodeNone; };
+  auto size = [&](int32_t h) { return h < nmax ? sz[nb + h] : 0; };
+  for (int d = dmax; d >= 0; --d) {
+    const int32_t h1 = min(2 << d, nmax);
+    for (int32_t h = (1 << d) + threadIdx.x; h < h1; h += kEmitT) {
+      const int32_t st = state(h);
+      int32_t n = 0;
+      if (st == kNodeLeaf) n = 1;
+      else if (st == kNodeInternal) n = 1 + size(2 * h) + size(2 * h + 1);
+      sz[nb + h] = n;
     }
-    if (emit) {
-      O.node_heap[r] = h;
-      O.node_vptr[r] = (int32_t)(nd.beg[nb + h] - J.voff);
-      O.split_cut[r] = (!leaf && J.mode == VMO_GRAPH) ? (double)(nd.end[nb + h] - nd.beg[nb + h]) : 0.0;
-      rank_of[nb + h] = r;
-      ++r;
-    }
+    __syncthreads();
   }
-  for (int32_t t = r; t < nmax; ++t) {
+  if (threadIdx.x == 0) off[nb + 1] = 0;
+  __syncthreads();
+  for (int d = 0; d < dmax; ++d) {
+    const int32_t h1 = min(2 << d, nmax);
+    for (int32_t h = (1 << d) + threadIdx.x; h < h1; h += kEmitT) {
+      if (state(h) != kNodeInternal) continue;
+      const int32_t o = off[nb + h];
+      if (2 * h < nmax) off[nb + 2 * h] = o;
+      if (2 * h + 1 < nmax) off[nb + 2 * h + 1] = o + size(2 * h) + (post ? 0 : 1);
+    }
+    __syncthreads();
+  }
+  const int32_t nn = sz[nb + 1];
+  for (int32_t h = 1 + threadIdx.x; h < nmax; h += kEmitT) {
+    const int32_t st = state(h);
+    if (st != kNodeLeaf && st != kNodeInternal) continue;
+    const bool leaf = st == kNodeLeaf;
+    const int32_t o = off[nb + h];
+    const int32_t r = leaf ? o : (post ? o + size(2 * h) + size(2 * h + 1) : o + size(2 * h));
+    O.node_heap[r] = h;
+    O.node_vptr[r] = (int32_t)(nd.beg[nb + h] - J.voff);
+    O.split_cut[r] = (!leaf && J.mode == VMO_GRAPH) ? (double)(nd.end[nb + h] - nd.beg[nb + h]) : 0.0;
+    rank_of[nb + h] = r;
+  }
+  for (int32_t t = nn + threadIdx.x; t < nmax; t += kEmitT) {
     O.node_heap[t] = -1;
     O.node_vptr[t] = J.k;
     O.split_cut[t] = 0.0;
   }
-  O.node_vptr[nmax] = J.k;
-  O.n_nodes[0] = r;
+  if (threadIdx.x == 0) {
+    O.node_vptr[nmax] = J.k;
+    O.n_nodes[0] = nn;
+  }
   if (O.node_nptr) {
     // filled after the net sort; pad here
-    for (int32_t t = 0; t <= nmax + 1; ++t) O.node_nptr[t] = J.nnets;
+    for (int32_t t = threadIdx.x; t <= nmax + 1; t += kEmitT) O.node_nptr[t] = J.nnets;
   }
 }
 
@@ -1144,8 +1164,8 @@ void Engine::emit(const std::vector<int32_t>& slots, const std::vector<JobHost>&
   VMO_LAUNCH(k_node_fill, (unsigned)(NTv < 65536 ? (NTv > 0 ? NTv : 1) : 65536), kT, 0, s, dsub.p, m, nd, NTv, id.p,
              dpart.p, leafh.p);
   VMO_LAUNCH(k_vperm, gsz(Nv), kT, 0, s, dsub.p, m, id.p, Nv, dvperm.p);
-  Buf<int32_t> rank_of(c.pool, NT);
-  VMO_LAUNCH(k_emit, nblocks(m, 64), 64, 0, s, dsub.p, m, nd, douts.p, rank_of.p);
+  Buf<int32_t> rank_of(c.pool, NT), esz(c.pool, NT), eoff(c.pool, NT);
+  VMO_LAUNCH(k_emit, m, kEmitT, 0, s, dsub.p, m, nd, douts.p, rank_of.p, esz.p, eoff.p);
   if (Lv > 0) {
     Buf<uint32_t> key(c.pool, Lv);
     Buf<int32_t> val(c.pool, Lv), nnode(c.pool, Lv);
