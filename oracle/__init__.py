@@ -256,6 +256,23 @@ def border(h: Hypergraph, vperm, part, node_heap, node_vptr, n_nodes: int, P: in
     return out
 
 
+def schur(h: Hypergraph, x, vperm, part, node_heap, node_vptr, n_nodes: int, P: int, P3: int, seed: int,
+          t_max: int = 32):
+    """Schur-complement recursion (Sec. 4.2, Algorithm 7 applied to G3 = (V3,
+    E'3)): vperm of a graph-mode ordering with every separator block of at
+    least two vertices reordered by the recursive BBD ordering (P3 parts,
+    draws keyed by the separator's heap id) of its own graph (o_schur)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.zeros(h.k, dtype=np.int32)
+    arr = [np.ascontiguousarray(a, dtype=np.int32) for a in (vperm, part, node_heap, node_vptr)]
+    rc = lib().o_schur(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(x), _p(arr[0]), _p(arr[1]),
+                       _p(arr[2]), _p(arr[3]), C.c_int32(n_nodes), C.c_int32(P), C.c_int32(P3), C.c_uint64(seed),
+                       C.c_int32(t_max), _p(out))
+    if rc != 0:
+        raise ValueError("oracle schur rejected its input")
+    return out
+
+
 # ---------------------------------------------------------------- layout ----
 
 class LayoutParams(C.Structure):

@@ -29,6 +29,9 @@
  *   o_border          recursive ordering of the border: separator blocks
  *                     sorted by b two-bit words [Sec. 4.2, cut rows and
  *                     columns into recursive BBD form].
+ *   o_schur           Schur-complement recursion: every separator block
+ *                     reordered by Algorithm 7 applied to its own graph
+ *                     [Sec. 4.2, recursion on G3 = (V3, E'3)].
  *   o_coarsen         one coarsening step [Sec. 2.3, coarsening by greedy
  *                     heavy-net matching, single-neighbour rule, net merge].
  *   o_tree            2^d-tree with cluster charges [Sec. 2.1 tree
@@ -594,6 +597,70 @@ int o_border(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, cons
   free(vh);
   free(word);
   return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Schur-complement recursion [Sec. 4.2, the paragraph on the freedom in the
+   rows and columns of V3: Algorithm 7 applied recursively to G3 = (V3, E'3),
+   E'3 the edges with both ends in V3, as for G1 and G2; the middle
+   partitioning of the figure on matrix partitionings].  Input: a graph-mode
+   ordering as o_border takes it, its coordinates x [4][k], and P3 >= 1.  The
+   vertex block of every separator S_h (h internal) with at least two
+   vertices is reordered by the recursive graph-mode BBD ordering (o_order,
+   P3 parts, t_max, draws keyed by job = h) of the graph (S_h, edges inside
+   S_h): local vertex i is the i-th vertex of the block as given, the edges
+   keep their net order with local ends ascending, the coordinates are the
+   vertices' own.  One level: the separators of these orderings are not
+   recursed again.  Leaf blocks, part ids and node tables do not change.
+   Returns 0 or <0. */
+int o_schur(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* x, const int32_t* vperm,
+            const int32_t* part, const int32_t* node_heap, const int32_t* node_vptr, int32_t n_nodes, int32_t P,
+            int32_t P3, uint64_t seed, int32_t t_max, int32_t* vperm_out) {
+  if (k < 1 || P < 1 || P3 < 1 || n_nodes < 1 || n_nodes > 4 * P) return -1;
+  for (int32_t i = 0; i < k; ++i) vperm_out[i] = vperm[i];
+  int32_t* loc = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  for (int32_t v = 0; v < k; ++v) loc[v] = -1;
+  int rc = 0;
+  for (int32_t r = 0; r < n_nodes && rc == 0; ++r) {
+    const int32_t lo = node_vptr[r], hi = node_vptr[r + 1], m = hi - lo;
+    if (m < 2 || part[vperm[lo]] < P) continue;  /* a leaf block, or too small */
+    const int32_t h = node_heap[r];
+    for (int32_t i = 0; i < m; ++i) loc[vperm[lo + i]] = i;
+    /* the edges inside the block, in net order */
+    int32_t l3 = 0;
+    for (int32_t e = 0; e < l; ++e)
+      if (ptr[e + 1] - ptr[e] == 2 && loc[pins[ptr[e]]] >= 0 && loc[pins[ptr[e] + 1]] >= 0) ++l3;
+    int64_t* ptr3 = (int64_t*)malloc(sizeof(int64_t) * ((size_t)l3 + 1));
+    int32_t* pins3 = (int32_t*)malloc(sizeof(int32_t) * (2 * (size_t)l3 + 1));
+    int32_t t = 0;
+    ptr3[0] = 0;
+    for (int32_t e = 0; e < l; ++e) {
+      if (ptr[e + 1] - ptr[e] != 2) continue;
+      const int32_t a = loc[pins[ptr[e]]], b = loc[pins[ptr[e] + 1]];
+      if (a < 0 || b < 0) continue;
+      pins3[2 * t] = a < b ? a : b;
+      pins3[2 * t + 1] = a < b ? b : a;
+      ++t;
+      ptr3[t] = 2 * (int64_t)t;
+    }
+    float* x3 = (float*)malloc(sizeof(float) * 4 * (size_t)m);
+    for (int d = 0; d < 4; ++d)
+      for (int32_t i = 0; i < m; ++i) x3[(size_t)d * m + i] = x[(size_t)d * k + vperm[lo + i]];
+    int32_t* v3 = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+    int32_t* p3 = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+    int32_t* heap3 = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)P3);
+    int32_t* vptr3 = (int32_t*)malloc(sizeof(int32_t) * (4 * (size_t)P3 + 1));
+    double* sc3 = (double*)malloc(sizeof(double) * 4 * (size_t)P3);
+    int32_t nn3 = 0;
+    rc = o_order(m, l3, ptr3, pins3, NULL, 1, 1, x3, P3, seed, (uint64_t)h, t_max, v3, NULL, p3, heap3, vptr3, NULL,
+                 sc3, &nn3);
+    if (rc == 0)
+      for (int32_t i = 0; i < m; ++i) vperm_out[lo + i] = vperm[lo + v3[i]];
+    for (int32_t i = 0; i < m; ++i) loc[vperm[lo + i]] = -1;
+    free(ptr3); free(pins3); free(x3); free(v3); free(p3); free(heap3); free(vptr3); free(sc3);
+  }
+  free(loc);
+  return rc;
 }
 
 /* ========================================================================= */
