@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 P_PARTS = 64
 N_SIDE = 64
 SEED = 1
+SCHUR_P3 = 8         # parts of each separator block in the Schur-complement recursion
 FLOPS_PER_INTERACTION = 23   # 4 sub, r^2 (1 mul + 3 fma), 2 mul (2 W w), 1 mul (r^4), 1 div, 4 fma
 # HBM bytes per walk launch (average over one step of this workload), from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
@@ -190,11 +191,23 @@ def order_only_and_border(ctx, h, g, lp, o, steps):
         ctx.order_border(h, o, P_PARTS, b)
     torch.cuda.synchronize()
     dt_b = (time.perf_counter() - t0) / steps
+    # Schur-complement recursion of the ordering from the same coordinates
+    ox = ctx.order(h, x, P_PARTS, SEED, mode=1, order=1)
+    ctx.order_schur(h, x, ox, P_PARTS, SCHUR_P3, SEED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.order_schur(h, x, ox, P_PARTS, SCHUR_P3, SEED)
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / steps
     return {"order_only": {"metric": "matrix nnz ordered/sec (recursive BBD from given coordinates)",
                            "value": g.nnz / dt_o, "unit": "nnz/s", "ms": 1e3 * dt_o},
             "border": {"b": b, "value": g.nnz / dt_b, "unit": "nnz/s", "ms": 1e3 * dt_b,
                        "what": "recursive ordering of the border of the V+O result (separator blocks sorted by "
-                               "b two-bit words), one call per timing"}}
+                               "b two-bit words), one call per timing"},
+            "schur": {"P3": SCHUR_P3, "value": g.nnz / dt_s, "unit": "nnz/s", "ms": 1e3 * dt_s,
+                      "what": "Schur-complement recursion: every separator block of the ordering reordered by the "
+                              "BBD ordering of its induced graph into P3 parts, all blocks in one batched pass"}}
 
 
 def _pct(v, q):

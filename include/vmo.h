@@ -248,6 +248,27 @@ vmo_status vmo_order_bbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const f
 vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_order_out* in /* (host) */, int32_t P,
                             int32_t b, int32_t* vperm_out, vmo_stream stream);
 
+/* Schur-complement recursion (Sec. 4.2: the separator vertices V3 of a BBD
+ * ordering, with the edges among them, E'3, ordered again by the same method).
+ * h, in, P: as for vmo_order_border (h the graph of the ordering, in its
+ * device arrays).  x: the coordinates the ordering used, [4][k] FP32 SoA
+ * (device).  Every separator block of in with at least two vertices (its
+ * first vertex has part >= P) is reordered by the VMO_GRAPH, VMO_BBD ordering
+ * of its induced graph: local vertex i = the block's i-th vertex, with its
+ * coordinates from x; edges = the nets of h with both ends in the block, in
+ * net order, each as {min, max} of its local ends; P3 parts, t_max Lloyd
+ * updates, the same seed, and the heap id of the block's node as the job index
+ * of the random draws.  vperm_out[k] (device; may be in->vperm) receives vperm
+ * with position lo + i of each such block holding the outer vertex at
+ * lo + v3[i], v3 the block ordering's vperm; other blocks, part ids and the
+ * node tables are unchanged.  One level: the blocks' own separators are not
+ * reordered again.  P3 in [1, 2^24] (1: a copy).  All blocks are ordered in
+ * one batched pass.  VMO_E_INVALID as for vmo_order_border, or if x is NULL
+ * or not finite. */
+vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x,
+                           const vmo_order_out* in /* (host) */, int32_t P, int32_t P3, uint64_t seed,
+                           int32_t t_max, int32_t* vperm_out, vmo_stream stream);
+
 /* Many orderings in one pass: every level of every job is processed by the
    same launches over one segment list (jobs[i].job_index keys its random
    draws as the job number).  Results equal those of vmo_order per job with

@@ -289,6 +289,21 @@ class Context:
                                            _stream()))
         return out
 
+    def order_schur(self, h: DeviceHypergraph, x: torch.Tensor, o: dict, P: int, P3: int, seed: int = 0,
+                    t_max: int = 32, out: torch.Tensor | None = None):
+        """Schur-complement recursion (vmo_order_schur): o is the dict order()
+        returned for a graph-mode ordering of h at coordinates x; returns vperm
+        with every separator block reordered by the BBD ordering of its induced
+        graph into P3 parts."""
+        if out is None:
+            out = torch.empty_like(o["vperm"])
+        s = OrderOut(_ptr(o["vperm"]), None, _ptr(o["part"]), _ptr(o["node_heap"]), _ptr(o["node_vptr"]), None, None,
+                     _ptr(o["n_nodes"]))
+        hs = h.cstruct()
+        self._check(lib().vmo_order_schur(self.h, C.byref(hs), _ptr(x), C.byref(s), C.c_int32(P), C.c_int32(P3),
+                                          C.c_uint64(seed), C.c_int32(t_max), _ptr(out), _stream()))
+        return out
+
     def order_batch(self, jobs, t_max: int = 32, plain: bool = False):
         """jobs: list of dicts with h, x, P, seed, mode, order, job_index.  Outputs
         of all jobs share one allocation per array kind (views per job)."""

@@ -23,6 +23,8 @@ void layout_steps(Ctx& c, const vmo_hypergraph* h, const vmo_layout_params* p, f
                   double* alpha, hipStream_t s);
 void order_border(Ctx& c, const vmo_hypergraph* h, const vmo_order_out* in, int32_t P, int32_t b, int32_t* vperm_out,
                   hipStream_t s);
+void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const vmo_order_out* in, int32_t P, int32_t P3,
+                 uint64_t seed, int32_t t_max, int32_t* vperm_out, hipStream_t s);
 }  // namespace vmo
 
 #define API_BEGIN(ctx, stream)                                    \
@@ -203,6 +205,13 @@ vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_orde
                             int32_t* vperm_out, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::order_border(C, h, in, P, b, vperm_out, S);
+  API_END
+}
+
+vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, const vmo_order_out* in, int32_t P,
+                           int32_t P3, uint64_t seed, int32_t t_max, int32_t* vperm_out, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::order_schur(C, h, x, in, P, P3, seed, t_max, vperm_out, S);
   API_END
 }
 

@@ -108,29 +108,32 @@ __global__ void k_bd_keys(const int32_t* vperm, const int32_t* node_vptr, int32_
   }
 }
 
-void order_border(Ctx& c, const vmo_hypergraph* h, const vmo_order_out* in, int32_t P, int32_t b, int32_t* vperm_out,
-                  hipStream_t s) {
+int32_t check_ordering(Ctx& c, int32_t k, int32_t P, const vmo_order_out* in, hipStream_t s) {
   VMO_REQUIRE(in != nullptr, "in is NULL");
   VMO_REQUIRE(in->vperm && in->part && in->node_heap && in->node_vptr && in->n_nodes, "NULL ordering array");
-  VMO_REQUIRE(vperm_out != nullptr, "vperm_out is NULL");
   VMO_REQUIRE(P >= 1, "P must be >= 1");
+  VMO_REQUIRE(k >= 1, "k must be >= 1");
+  const int32_t nn = read1(in->n_nodes, s);
+  VMO_REQUIRE(nn >= 1 && nn <= 4 * P, "n_nodes must be in [1, 4P]");
+  Buf<int> bad(c.pool, 1);
+  Buf<int32_t> mark(c.pool, k);
+  VMO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+  VMO_HIP(hipMemsetAsync(mark.p, 0, sizeof(int32_t) * k, s));
+  VMO_LAUNCH(k_bd_check_nodes, bsz(nn), kBT, 0, s, in->node_heap, in->node_vptr, nn, k, P, bad.p);
+  VMO_LAUNCH(k_bd_check_verts, bsz(k), kBT, 0, s, in->vperm, in->part, k, P, mark.p, bad.p);
+  VMO_LAUNCH(k_bd_check_marks, bsz(k), kBT, 0, s, mark.p, k, bad.p);
+  VMO_REQUIRE(read1(bad.p, s) == 0, "the ordering arrays are inconsistent (vperm, part, node_heap, node_vptr)");
+  return nn;
+}
+
+void order_border(Ctx& c, const vmo_hypergraph* h, const vmo_order_out* in, int32_t P, int32_t b, int32_t* vperm_out,
+                  hipStream_t s) {
+  VMO_REQUIRE(vperm_out != nullptr, "vperm_out is NULL");
   VMO_REQUIRE(b >= 0 && b <= 15, "b must be in [0, 15]");
   std::vector<int64_t> npins;
   validate_jobs(c, {JobCheck{h, nullptr, false, true}}, npins, s);
   const int32_t k = h->k, l = h->l;
-  VMO_REQUIRE(k >= 1, "k must be >= 1");
-  const int32_t nn = read1(in->n_nodes, s);
-  VMO_REQUIRE(nn >= 1 && nn <= 4 * P, "n_nodes must be in [1, 4P]");
-  {
-    Buf<int> bad(c.pool, 1);
-    Buf<int32_t> mark(c.pool, k);
-    VMO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-    VMO_HIP(hipMemsetAsync(mark.p, 0, sizeof(int32_t) * k, s));
-    VMO_LAUNCH(k_bd_check_nodes, bsz(nn), kBT, 0, s, in->node_heap, in->node_vptr, nn, k, P, bad.p);
-    VMO_LAUNCH(k_bd_check_verts, bsz(k), kBT, 0, s, in->vperm, in->part, k, P, mark.p, bad.p);
-    VMO_LAUNCH(k_bd_check_marks, bsz(k), kBT, 0, s, mark.p, k, bad.p);
-    VMO_REQUIRE(read1(bad.p, s) == 0, "the ordering arrays are inconsistent (vperm, part, node_heap, node_vptr)");
-  }
+  const int32_t nn = check_ordering(c, k, P, in, s);
   if (b == 0) {
     VMO_HIP(hipMemcpyAsync(vperm_out, in->vperm, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, s));
     VMO_HIP(hipStreamSynchronize(s));

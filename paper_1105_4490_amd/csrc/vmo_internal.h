@@ -279,6 +279,9 @@ struct JobCheck {
   bool graph;
 };
 void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_t>& npins, hipStream_t s);
+// Consistency of an ordering result of k vertices and P parts (heap ids, block
+// boundaries, part ids, vperm a permutation); returns its node count.
+int32_t check_ordering(Ctx& c, int32_t k, int32_t P, const vmo_order_out* in, hipStream_t s);
 
 // Transpose of a CSR incidence (rows -> columns): out row j lists, ascending,
 // the input rows containing j.  nrows, ncols, ptr [nrows+1], idx -> optr
