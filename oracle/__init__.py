@@ -223,9 +223,12 @@ class OrderResult:
 
 
 def order(h: Hypergraph, x, P: int, seed: int, mode: int = NET_MODE, ord: int = SBD, t_max: int = 32,
-          job: int = 0) -> OrderResult:
-    """Recursive SBD/BBD ordering (Algorithm 7 applied recursively, Sec. 4.2)."""
+          job: int = 0, mu=None) -> OrderResult:
+    """Recursive SBD/BBD ordering (Algorithm 7 applied recursively, Sec. 4.2);
+    mu (graph mode): a strengthened diagonal, mu[v] = v's partner or -1
+    (o_order_mu)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
+    mu = None if mu is None else np.ascontiguousarray(mu, dtype=np.int32)
     k, l = h.k, h.l
     vperm = np.zeros(k, dtype=np.int32)
     part = np.zeros(k, dtype=np.int32)
@@ -235,9 +238,10 @@ def order(h: Hypergraph, x, P: int, seed: int, mode: int = NET_MODE, ord: int = 
     nptr = np.zeros(4 * P + 2, dtype=np.int32) if mode == NET_MODE else None
     sc = np.zeros(4 * P, dtype=np.float64)
     nn = C.c_int32(0)
-    rc = lib().o_order(C.c_int32(k), C.c_int32(l), _p(h.ptr), _p(h.pins), _p(h.c), C.c_int(mode), C.c_int(ord),
-                       _p(x), C.c_int32(P), C.c_uint64(seed), C.c_uint64(job), C.c_int32(t_max), _p(vperm),
-                       _p(nperm), _p(part), _p(heap), _p(vptr), _p(nptr), _p(sc), C.byref(nn))
+    rc = lib().o_order_mu(C.c_int32(k), C.c_int32(l), _p(h.ptr), _p(h.pins), _p(h.c), C.c_int(mode),
+                          C.c_int(ord), _p(x), _p(mu), C.c_int32(P), C.c_uint64(seed), C.c_uint64(job),
+                          C.c_int32(t_max), _p(vperm), _p(nperm), _p(part), _p(heap), _p(vptr), _p(nptr), _p(sc),
+                          C.byref(nn))
     if rc != 0:
         raise ValueError("oracle order rejected its input")
     return OrderResult(vperm, None if nperm is None else nperm[:l], part, heap, vptr, nptr, sc, nn.value)
@@ -257,7 +261,7 @@ def border(h: Hypergraph, vperm, part, node_heap, node_vptr, n_nodes: int, P: in
 
 
 def schur(h: Hypergraph, x, vperm, part, node_heap, node_vptr, n_nodes: int, P: int, P3: int, seed: int,
-          t_max: int = 32):
+          t_max: int = 32, mu=None):
     """Schur-complement recursion (Sec. 4.2, Algorithm 7 applied to G3 = (V3,
     E'3)): vperm of a graph-mode ordering with every separator block of at
     least two vertices reordered by the recursive BBD ordering (P3 parts,
@@ -265,11 +269,100 @@ def schur(h: Hypergraph, x, vperm, part, node_heap, node_vptr, n_nodes: int, P: 
     x = np.ascontiguousarray(x, dtype=np.float32)
     out = np.zeros(h.k, dtype=np.int32)
     arr = [np.ascontiguousarray(a, dtype=np.int32) for a in (vperm, part, node_heap, node_vptr)]
-    rc = lib().o_schur(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(x), _p(arr[0]), _p(arr[1]),
+    mu = None if mu is None else np.ascontiguousarray(mu, dtype=np.int32)
+    rc = lib().o_schur(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(x), _p(mu), _p(arr[0]), _p(arr[1]),
                        _p(arr[2]), _p(arr[3]), C.c_int32(n_nodes), C.c_int32(P), C.c_int32(P3), C.c_uint64(seed),
                        C.c_int32(t_max), _p(out))
     if rc != 0:
         raise ValueError("oracle schur rejected its input")
+    return out
+
+
+# ------------------------------------------------- strengthened diagonal ----
+
+def bipartite(m, n, rowptr, col) -> Hypergraph:
+    """Bipartite model (Table 1): vertices r_0..r_{m-1} (ids 0..m-1) and
+    c_0..c_{n-1} (ids m..m+n-1); one edge {r_i, c_j} per nonzero, in CSR
+    order."""
+    rowptr = np.asarray(rowptr, np.int64)
+    col = np.asarray(col, np.int64)
+    nnz = int(rowptr[-1])
+    rows = np.repeat(np.arange(m, dtype=np.int64), np.diff(rowptr))
+    pins = np.empty(2 * nnz, np.int32)
+    pins[0::2] = rows
+    pins[1::2] = m + col
+    return Hypergraph(int(m) + int(n), nnz, np.arange(0, 2 * nnz + 1, 2, dtype=np.int64), pins)
+
+
+def match_key(a, e: int, seed: int) -> int:
+    """Priority of nonzero e in the heavy edge matching (o_match_key)."""
+    a = None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+    lib().o_match_key.restype = C.c_uint64
+    return int(lib().o_match_key(_p(a), C.c_int64(e), C.c_uint32(seed)))
+
+
+def match_heavy(m, n, rowptr, col, a=None, seed: int = 0):
+    """Heavy edge matching (o_match_heavy): (mrow, mcol, size)."""
+    rowptr = np.ascontiguousarray(rowptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    a = None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+    mrow = np.zeros(max(m, 1), np.int32)
+    mcol = np.zeros(max(n, 1), np.int32)
+    lib().o_match_heavy.restype = C.c_int64
+    size = lib().o_match_heavy(C.c_int32(m), C.c_int32(n), _p(rowptr), _p(col), _p(a), C.c_uint32(seed), _p(mrow),
+                               _p(mcol))
+    if size < 0:
+        raise ValueError("oracle match rejected its input")
+    return mrow[:m], mcol[:n], int(size)
+
+
+def match_augment(m, n, rowptr, col, mrow, mcol):
+    """Hopcroft-Karp augmentation (o_match_augment) of copies of mrow/mcol."""
+    rowptr = np.ascontiguousarray(rowptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    mrow = np.array(mrow, np.int32, copy=True)
+    mcol = np.array(mcol, np.int32, copy=True)
+    lib().o_match_augment.restype = C.c_int64
+    size = lib().o_match_augment(C.c_int32(m), C.c_int32(n), _p(rowptr), _p(col), _p(mrow), _p(mcol))
+    return mrow, mcol, int(size)
+
+
+def match(m, n, rowptr, col, a=None, seed: int = 0, augment: bool = True):
+    """Strengthened diagonal: heavy edge matching, then (augment) Hopcroft-Karp."""
+    mrow, mcol, size = match_heavy(m, n, rowptr, col, a, seed)
+    if augment:
+        mrow, mcol, size = match_augment(m, n, rowptr, col, mrow, mcol)
+    return mrow, mcol, size
+
+
+def mu_of(m, n, mrow, mcol):
+    """mu on the bipartite graph's vertices: partner id or -1."""
+    mu = np.full(m + n, -1, np.int32)
+    mr = np.asarray(mrow)
+    mc = np.asarray(mcol)
+    mu[:m] = np.where(mr >= 0, mr + m, -1)
+    mu[m:] = np.where(mc >= 0, mc, -1)
+    return mu
+
+
+def matched_perms(m, vperm, mu):
+    """Row and column permutations with the matching on the diagonal."""
+    vperm = np.ascontiguousarray(vperm, np.int32)
+    mu = np.ascontiguousarray(mu, np.int32)
+    rp = np.zeros(max(m, 1), np.int32)
+    cp = np.zeros(max(m, 1), np.int32)
+    if lib().o_matched_perms(C.c_int32(m), _p(vperm), _p(mu), _p(rp), _p(cp)) != 0:
+        raise ValueError("oracle matched_perms: a row has no partner column")
+    return rp[:m], cp[:m]
+
+
+def finegrain(m, n, rowptr, col, x):
+    """Nonzero coordinates [4][nnz] from bipartite coordinates [4][m+n]."""
+    rowptr = np.ascontiguousarray(rowptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    x = np.ascontiguousarray(x, np.float32)
+    out = np.zeros((4, int(rowptr[-1])), np.float32)
+    lib().o_finegrain(C.c_int32(m), C.c_int32(n), _p(rowptr), _p(col), _p(x), _p(out))
     return out
 
 

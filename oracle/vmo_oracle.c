@@ -32,6 +32,18 @@
  *   o_schur           Schur-complement recursion: every separator block
  *                     reordered by Algorithm 7 applied to its own graph
  *                     [Sec. 4.2, recursion on G3 = (V3, E'3)].
+ *   o_match_heavy     heavy edge matching of the bipartite representation
+ *                     (priority |a_ij|, ties by a scrambled index)
+ *                     [Sec. 5, strengthened diagonal for the LU runs].
+ *   o_match_augment   Hopcroft-Karp augmentation to a maximum matching
+ *                     [Sec. 5; Hopcroft and Karp 1973].
+ *   o_order_mu        o_order in graph mode with a strengthened diagonal mu:
+ *                     a separator vertex takes its partner along
+ *                     [Algorithm 7, the matched pair lines; Sec. 4.2].
+ *   o_matched_perms   row and column permutations with the matching on the
+ *                     diagonal [Sec. 4.2, permutations from V1, V2, V3].
+ *   o_finegrain       nonzero coordinates = mean of row and column points
+ *                     [Sec. 4.2, layout of the finegrain representation].
  *   o_coarsen         one coarsening step [Sec. 2.3, coarsening by greedy
  *                     heavy-net matching, single-neighbour rule, net merge].
  *   o_tree            2^d-tree with cluster charges [Sec. 2.1 tree
@@ -401,14 +413,37 @@ static void emit_walk(ONode* nd, int32_t nmax, int32_t h, int post, int32_t* ord
    Outputs (caller allocated): vperm[k], nperm[l] (net mode; may be NULL),
    part[k], node_heap[4P], node_vptr[4P+1], node_nptr[4P+2] (net mode; may be
    NULL), split_cut[4P] (by emission rank), n_nodes[1].  Returns 0 or <0. */
-int o_order(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* c,
-            int mode, int ord, const float* x, int32_t P, uint64_t seed, uint64_t job, int32_t t_max,
-            int32_t* vperm, int32_t* nperm, int32_t* part, int32_t* node_heap, int32_t* node_vptr,
-            int32_t* node_nptr, double* split_cut, int32_t* n_nodes_out) {
+/* A strengthened diagonal mu (graph mode only; NULL = none): mu[v] = the
+   vertex matched to v, or -1.  It must be an involution without fixed points
+   whose pairs {v, mu(v)} are edges of the graph. */
+static int check_mu(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const int32_t* mu) {
+  if (k < 1) return -1;
+  for (int32_t v = 0; v < k; ++v) {
+    const int32_t w = mu[v];
+    if (w < -1 || w >= k || w == v) return -1;
+    if (w >= 0 && mu[w] != v) return -1;
+  }
+  char* ok = (char*)calloc((size_t)k, 1);
+  for (int32_t e = 0; e < l; ++e) {
+    const int32_t a = pins[ptr[e]], b = pins[ptr[e] + 1];
+    if (mu[a] == b) ok[a] = ok[b] = 1;
+  }
+  int rc = 0;
+  for (int32_t v = 0; v < k; ++v)
+    if (mu[v] >= 0 && !ok[v]) rc = -1;
+  free(ok);
+  return rc;
+}
+
+int o_order_mu(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* c,
+               int mode, int ord, const float* x, const int32_t* mu, int32_t P, uint64_t seed, uint64_t job,
+               int32_t t_max, int32_t* vperm, int32_t* nperm, int32_t* part, int32_t* node_heap,
+               int32_t* node_vptr, int32_t* node_nptr, double* split_cut, int32_t* n_nodes_out) {
   if (k < 1 || P < 1 || l < 0) return -1;
   if (mode == 1)
     for (int32_t e = 0; e < l; ++e)
       if (ptr[e + 1] - ptr[e] != 2 || pins[ptr[e]] >= pins[ptr[e] + 1]) return -1;
+  if (mu && (mode != 1 || check_mu(k, l, ptr, pins, mu))) return -1;
   int32_t nmax = 4 * P;
   uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * 4 * (size_t)k);
   float lo[4];
@@ -451,14 +486,18 @@ int o_order(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const
     }
     if (mode == 1) {
       /* Algorithm 7 separator: edges in order; a cut edge whose ends are both
-         still in parts 1/2 sends the end nearer the plane into S (ties: v). */
+         still in parts 1/2 sends the end nearer the plane into S (ties: v),
+         together with its partner under mu (Algorithm 7, the matched pair
+         lines), so that every matched pair stays in one of V1, V2, V3. */
       N->sep = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
       for (int32_t e = 0; e < l; ++e) {
         int32_t a = pins[ptr[e]], b = pins[ptr[e] + 1];
         if (mark[a] != h || mark[b] != h) continue;
         if (in_sep[a] || in_sep[b]) continue;
         if (sd_of[a] == sd_of[b]) continue;
-        if (fabs(s_of[a]) <= fabs(s_of[b])) in_sep[a] = 1; else in_sep[b] = 1;
+        const int32_t t = fabs(s_of[a]) <= fabs(s_of[b]) ? a : b;
+        in_sep[t] = 1;
+        if (mu && mu[t] >= 0) in_sep[mu[t]] = 1;
       }
       for (int32_t i = 0; i < n; ++i) if (in_sep[N->verts[i]]) N->sep[N->ns++] = N->verts[i];
     }
@@ -529,6 +568,14 @@ int o_order(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const
   for (int32_t h = 0; h < nmax; ++h) { free(nd[h].verts); free(nd[h].sep); free(nd[h].nets); }
   free(nd); free(order); free(q); free(netnode); free(mark); free(sd_of); free(s_of); free(in_sep);
   return 0;
+}
+
+int o_order(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* c,
+            int mode, int ord, const float* x, int32_t P, uint64_t seed, uint64_t job, int32_t t_max,
+            int32_t* vperm, int32_t* nperm, int32_t* part, int32_t* node_heap, int32_t* node_vptr,
+            int32_t* node_nptr, double* split_cut, int32_t* n_nodes_out) {
+  return o_order_mu(k, l, ptr, pins, c, mode, ord, x, NULL, P, seed, job, t_max, vperm, nperm, part, node_heap,
+                    node_vptr, node_nptr, split_cut, n_nodes_out);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -613,10 +660,11 @@ int o_border(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, cons
    vertices' own.  One level: the separators of these orderings are not
    recursed again.  Leaf blocks, part ids and node tables do not change.
    Returns 0 or <0. */
-int o_schur(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* x, const int32_t* vperm,
-            const int32_t* part, const int32_t* node_heap, const int32_t* node_vptr, int32_t n_nodes, int32_t P,
-            int32_t P3, uint64_t seed, int32_t t_max, int32_t* vperm_out) {
+int o_schur(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* x, const int32_t* mu,
+            const int32_t* vperm, const int32_t* part, const int32_t* node_heap, const int32_t* node_vptr,
+            int32_t n_nodes, int32_t P, int32_t P3, uint64_t seed, int32_t t_max, int32_t* vperm_out) {
   if (k < 1 || P < 1 || P3 < 1 || n_nodes < 1 || n_nodes > 4 * P) return -1;
+  if (mu && check_mu(k, l, ptr, pins, mu)) return -1;
   for (int32_t i = 0; i < k; ++i) vperm_out[i] = vperm[i];
   int32_t* loc = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
   for (int32_t v = 0; v < k; ++v) loc[v] = -1;
@@ -646,18 +694,28 @@ int o_schur(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const
     float* x3 = (float*)malloc(sizeof(float) * 4 * (size_t)m);
     for (int d = 0; d < 4; ++d)
       for (int32_t i = 0; i < m; ++i) x3[(size_t)d * m + i] = x[(size_t)d * k + vperm[lo + i]];
+    /* the strengthened diagonal restricted to the block (partners outside
+       the block are dropped) */
+    int32_t* mu3 = NULL;
+    if (mu) {
+      mu3 = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+      for (int32_t i = 0; i < m; ++i) {
+        const int32_t w = mu[vperm[lo + i]];
+        mu3[i] = w >= 0 ? loc[w] : -1;
+      }
+    }
     int32_t* v3 = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
     int32_t* p3 = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
     int32_t* heap3 = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)P3);
     int32_t* vptr3 = (int32_t*)malloc(sizeof(int32_t) * (4 * (size_t)P3 + 1));
     double* sc3 = (double*)malloc(sizeof(double) * 4 * (size_t)P3);
     int32_t nn3 = 0;
-    rc = o_order(m, l3, ptr3, pins3, NULL, 1, 1, x3, P3, seed, (uint64_t)h, t_max, v3, NULL, p3, heap3, vptr3, NULL,
-                 sc3, &nn3);
+    rc = o_order_mu(m, l3, ptr3, pins3, NULL, 1, 1, x3, mu3, P3, seed, (uint64_t)h, t_max, v3, NULL, p3, heap3,
+                    vptr3, NULL, sc3, &nn3);
     if (rc == 0)
       for (int32_t i = 0; i < m; ++i) vperm_out[lo + i] = vperm[lo + v3[i]];
     for (int32_t i = 0; i < m; ++i) loc[vperm[lo + i]] = -1;
-    free(ptr3); free(pins3); free(x3); free(v3); free(p3); free(heap3); free(vptr3); free(sc3);
+    free(ptr3); free(pins3); free(x3); free(mu3); free(v3); free(p3); free(heap3); free(vptr3); free(sc3);
   }
   free(loc);
   return rc;
@@ -1381,4 +1439,152 @@ int o_gradient_sample(int32_t k, int32_t l, const int64_t* ptr, const int32_t* p
   }
   otree_free(&T); free(z); free(dptr); free(dp);
   return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Strengthened diagonal [Sec. 4.2, permutations with a perfect bipartite
+   matching; Sec. 5, a heavy edge matching of the bipartite representation
+   augmented to a perfect matching by Hopcroft-Karp].  The bipartite graph of
+   an m x n pattern has rows 0..m-1 and columns m..m+n-1; nonzero e = (i, j)
+   is the edge {i, m + j}.  mrow[i] = the column matched to row i or -1,
+   mcol[j] = the row matched to column j or -1. */
+
+/* MurmurHash3's 32-bit finalizer (Appleby): a bijection of 32-bit words. */
+static uint32_t o_fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+/* Priority of nonzero e: the bits of |a_e| (of 1.0 when a is NULL) above the
+   scrambled index fmix32(e + seed).  Non-negative floats order as their bits,
+   and the low word is a bijection of e, so no two nonzeros tie. */
+uint64_t o_match_key(const float* a, int64_t e, uint32_t seed) {
+  const float w = a ? fabsf(a[e]) : 1.0f;
+  uint32_t wb;
+  memcpy(&wb, &w, 4);
+  return ((uint64_t)wb << 32) | o_fmix32((uint32_t)e + seed);
+}
+
+static const uint64_t* g_match_keys;
+static int cmp_key_desc(const void* pa, const void* pb) {
+  const uint64_t a = g_match_keys[*(const int64_t*)pa], b = g_match_keys[*(const int64_t*)pb];
+  return a < b ? 1 : (a > b ? -1 : 0);
+}
+
+/* Heavy edge matching: nonzeros visited by decreasing priority, each taken
+   when its row and its column are both free.  Returns the matching size, or
+   -1 for bad input (a value not finite). */
+int64_t o_match_heavy(int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* a,
+                      uint32_t seed, int32_t* mrow, int32_t* mcol) {
+  const int64_t nnz = rowptr[m];
+  if (a)
+    for (int64_t e = 0; e < nnz; ++e)
+      if (!isfinite(a[e])) return -1;
+  uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1));
+  int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+  int32_t* row = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  for (int32_t i = 0; i < m; ++i)
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) row[e] = i;
+  for (int64_t e = 0; e < nnz; ++e) { key[e] = o_match_key(a, e, seed); idx[e] = e; }
+  g_match_keys = key;
+  qsort(idx, (size_t)nnz, sizeof(int64_t), cmp_key_desc);
+  for (int32_t i = 0; i < m; ++i) mrow[i] = -1;
+  for (int32_t j = 0; j < n; ++j) mcol[j] = -1;
+  int64_t size = 0;
+  for (int64_t t = 0; t < nnz; ++t) {
+    const int64_t e = idx[t];
+    const int32_t i = row[e], j = col[e];
+    if (mrow[i] < 0 && mcol[j] < 0) { mrow[i] = j; mcol[j] = i; ++size; }
+  }
+  free(key); free(idx); free(row);
+  return size;
+}
+
+/* Hopcroft-Karp: each phase layers the rows by breadth-first search from the
+   free rows (ascending) along alternating paths, then takes vertex-disjoint
+   shortest augmenting paths by depth-first search from every free row in
+   ascending order, columns in row order; phases repeat until no augmenting
+   path is left.  Returns the final matching size. */
+typedef struct {
+  const int64_t* rowptr; const int32_t* col;
+  int32_t *mrow, *mcol, *dist; int64_t* it; int32_t found;
+} OHK;
+#define HK_INF 0x7fffffff
+static int hk_dfs(OHK* H, int32_t u) {
+  for (; H->it[u] < H->rowptr[u + 1]; ++H->it[u]) {
+    const int32_t j = H->col[H->it[u]], r = H->mcol[j];
+    int ok;
+    if (r < 0) ok = H->dist[u] + 1 == H->found;
+    else ok = H->dist[r] == H->dist[u] + 1 && hk_dfs(H, r);
+    if (ok) { H->mrow[u] = j; H->mcol[j] = u; ++H->it[u]; return 1; }
+  }
+  H->dist[u] = HK_INF;
+  return 0;
+}
+int64_t o_match_augment(int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* mrow,
+                        int32_t* mcol) {
+  OHK H;
+  H.rowptr = rowptr; H.col = col; H.mrow = mrow; H.mcol = mcol;
+  H.dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+  H.it = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+  for (;;) {
+    int32_t qh = 0, qt = 0;
+    for (int32_t i = 0; i < m; ++i) {
+      H.dist[i] = HK_INF;
+      if (mrow[i] < 0) { H.dist[i] = 0; queue[qt++] = i; }
+    }
+    H.found = HK_INF;
+    while (qh < qt) {
+      const int32_t u = queue[qh++];
+      if (H.dist[u] >= H.found) continue;
+      for (int64_t p = rowptr[u]; p < rowptr[u + 1]; ++p) {
+        const int32_t r = mcol[col[p]];
+        if (r < 0) { if (H.dist[u] + 1 < H.found) H.found = H.dist[u] + 1; }
+        else if (H.dist[r] == HK_INF) { H.dist[r] = H.dist[u] + 1; queue[qt++] = r; }
+      }
+    }
+    if (H.found == HK_INF) break;
+    for (int32_t i = 0; i < m; ++i) H.it[i] = rowptr[i];
+    for (int32_t i = 0; i < m; ++i)
+      if (mrow[i] < 0 && H.dist[i] == 0) hk_dfs(&H, i);
+  }
+  int64_t size = 0;
+  for (int32_t i = 0; i < m; ++i) size += mrow[i] >= 0;
+  (void)n;
+  free(H.dist); free(H.it); free(queue);
+  return size;
+}
+
+/* Row and column permutations of a square matrix from an ordering of its
+   bipartite graph with a perfect strengthened diagonal mu: the rows in the
+   order they appear in vperm, and the column matched to each (so the matching
+   lies on the diagonal and every diagonal block is square).  Returns -1 if a
+   row has no partner column. */
+int o_matched_perms(int32_t m, const int32_t* vperm, const int32_t* mu, int32_t* rperm, int32_t* cperm) {
+  int32_t t = 0;
+  for (int32_t p = 0; p < 2 * m; ++p) {
+    const int32_t v = vperm[p];
+    if (v >= m) continue;
+    if (mu[v] < m || mu[v] >= 2 * m || t >= m) return -1;
+    rperm[t] = v;
+    cperm[t] = mu[v] - m;
+    ++t;
+  }
+  return t == m ? 0 : -1;
+}
+
+/* Finegrain coordinates [Sec. 4.2: each nonzero at the average of the points
+   of its row and its column in a layout of the bipartite graph]: x holds
+   m + n points (rows, then columns), [4][m+n]; xnz[d][e] for nonzero e. */
+void o_finegrain(int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* x, float* xnz) {
+  const size_t k = (size_t)m + (size_t)n, nnz = (size_t)rowptr[m];
+  for (int32_t i = 0; i < m; ++i)
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+      for (int d = 0; d < 4; ++d)
+        xnz[d * nnz + (size_t)e] = (x[d * k + (size_t)i] + x[d * k + (size_t)m + (size_t)col[e]]) * 0.5f;
 }
