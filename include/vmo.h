@@ -77,10 +77,14 @@ typedef struct {
      VMO_SYMMETRIC:  (m == n) vertices = 0..n-1, nets = the distinct pairs
                      {i, j}, i < j, with a_ij != 0 or a_ji != 0, in
                      lexicographic order; diagonal entries are dropped.
+     VMO_BIPARTITE:  vertices = the m rows (0..m-1), then the n columns
+                     (m..m+n-1); one edge {i, m + j} per nonzero a_ij, in
+                     CSR order (a graph: usable in VMO_GRAPH mode).
    Outputs: net_ptr [cap_nets+1], pins [cap_pins]; capacities must be at
    least: row-net l = m, pins = nnz; column-net l = n, pins = nnz; symmetric
-   l <= nnz, pins <= 2 nnz.  *k, *l, *npins (host) receive the sizes. */
-enum { VMO_ROW_NET = 0, VMO_COLUMN_NET = 1, VMO_SYMMETRIC = 2 };
+   l <= nnz, pins <= 2 nnz; bipartite l = nnz, pins = 2 nnz.  *k, *l, *npins
+   (host) receive the sizes. */
+enum { VMO_ROW_NET = 0, VMO_COLUMN_NET = 1, VMO_SYMMETRIC = 2, VMO_BIPARTITE = 3 };
 vmo_status vmo_model(vmo_ctx ctx, int model, int32_t m, int32_t n, const int64_t* rowptr,
                      const int32_t* col, int64_t* net_ptr, int32_t* pins, int32_t cap_nets,
                      int64_t cap_pins, int32_t* k, int32_t* l, int64_t* npins, vmo_stream stream);
@@ -258,16 +262,68 @@ vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_orde
  * coordinates from x; edges = the nets of h with both ends in the block, in
  * net order, each as {min, max} of its local ends; P3 parts, t_max Lloyd
  * updates, the same seed, and the heap id of the block's node as the job index
- * of the random draws.  vperm_out[k] (device; may be in->vperm) receives vperm
+ * of the random draws; mu (device [k], or NULL): a strengthened diagonal as
+ * for vmo_order_matched, restricted to each block (partners outside the block
+ * are dropped), so matched pairs stay together inside the Schur complement.  vperm_out[k] (device; may be in->vperm) receives vperm
  * with position lo + i of each such block holding the outer vertex at
  * lo + v3[i], v3 the block ordering's vperm; other blocks, part ids and the
  * node tables are unchanged.  One level: the blocks' own separators are not
  * reordered again.  P3 in [1, 2^24] (1: a copy).  All blocks are ordered in
  * one batched pass.  VMO_E_INVALID as for vmo_order_border, or if x is NULL
  * or not finite. */
-vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x,
+vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, const int32_t* mu,
                            const vmo_order_out* in /* (host) */, int32_t P, int32_t P3, uint64_t seed,
                            int32_t t_max, int32_t* vperm_out, vmo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Strengthened diagonal (Sec. 4.2: a perfect matching M of the bipartite
+ * graph, kept intact by Algorithm 7; Sec. 5: obtained by a heavy edge matching
+ * augmented to a perfect matching by Hopcroft-Karp).
+ *
+ * vmo_match: matching of the bipartite graph of an m x n pattern (CSR as for
+ * vmo_model; a: [nnz] values or NULL, only |a| is used, must be finite).
+ * Heavy edge matching: nonzero e has the priority bits(|a_e|) << 32 |
+ * fmix32(e + seed) (1.0 for every e when a is NULL; fmix32 = the 32-bit
+ * finalizer of MurmurHash3, a bijection, so priorities are unique); the result
+ * is the greedy matching that visits nonzeros by decreasing priority and takes
+ * those whose row and column are free.  augment != 0: then augmented to a
+ * maximum matching (a perfect one when the pattern has full structural rank)
+ * by phases of breadth-first alternating-path forests from the free rows
+ * (deterministic; which maximum matching is returned is not specified beyond
+ * that).  Outputs (device): mrow[m] = matched column or -1, mcol[n] = matched
+ * row or -1, mu[m+n] (or NULL) = partner in the bipartite model's vertex ids
+ * (rows 0..m-1, columns m..m+n-1) or -1; *size (host) = matched pairs. */
+vmo_status vmo_match(vmo_ctx ctx, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col,
+                     const float* a, uint32_t seed, int augment, int32_t* mrow, int32_t* mcol, int32_t* mu,
+                     int64_t* size /* (host) */, vmo_stream stream);
+
+/* Graph-mode ordering with a strengthened diagonal (Algorithm 7 with its
+ * matched-pair rule): as vmo_order with mode = VMO_GRAPH, but whenever a vertex
+ * v enters a separator, mu[v] enters with it, so every pair {v, mu[v]} ends in
+ * one block (with the bipartite model and a perfect matching: square diagonal
+ * blocks).  mu: device [k], mu[v] = partner or -1; must be an involution
+ * without fixed points whose pairs are edges of h (else VMO_E_INVALID).  An
+ * all -1 mu gives vmo_order's result. */
+vmo_status vmo_order_matched(vmo_ctx ctx, const vmo_hypergraph* h, int order, const float* x,
+                             const vmo_layout_params* lp /* (host) */, const int32_t* mu, int32_t P,
+                             uint64_t seed, int32_t t_max, const vmo_order_out* out /* (host) */,
+                             vmo_stream stream);
+
+/* Row and column permutations of a square m x m matrix from an ordering of its
+ * bipartite model (vperm over 2m vertices) with a perfect strengthened
+ * diagonal mu (Sec. 4.2: the rows and columns of each block are the block's
+ * vertices): rperm[t] = the t-th row in vperm order, cperm[t] = mu[rperm[t]]
+ * - m, so the matching lies on the diagonal.  VMO_E_INVALID if vperm is not a
+ * permutation of 0..2m-1 or a row has no partner column. */
+vmo_status vmo_matched_perms(vmo_ctx ctx, int32_t m, const int32_t* vperm, const int32_t* mu, int32_t* rperm,
+                             int32_t* cperm, vmo_stream stream);
+
+/* Finegrain coordinates (Sec. 4.2: each nonzero mapped to the average of the
+ * points of its row and its column in a layout of the bipartite graph).
+ * x: [4][m+n] (rows, then columns); xnz: [4][nnz], xnz[d][e] = (x[d][i] +
+ * x[d][m+j]) * 0.5 in FP32 for nonzero e = (i, j) in CSR order. */
+vmo_status vmo_finegrain(vmo_ctx ctx, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col,
+                         const float* x, float* xnz, vmo_stream stream);
 
 /* Many orderings in one pass: every level of every job is processed by the
    same launches over one segment list (jobs[i].job_index keys its random

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvmo.so")
 
 VMO_OK, VMO_E_INVALID, VMO_E_NOMEM, VMO_E_DEVICE, VMO_E_UNSUPPORTED, VMO_E_BUSY = 0, -1, -2, -3, -4, -5
-ROW_NET, COLUMN_NET, SYMMETRIC = 0, 1, 2
+ROW_NET, COLUMN_NET, SYMMETRIC, BIPARTITE = 0, 1, 2, 3
 NET, GRAPH = 0, 1
 SBD, BBD = 0, 1
 
@@ -205,8 +205,8 @@ class Context:
     # --------------------------------------------------------------- models --
     def model(self, kind: int, m: int, n: int, rowptr: torch.Tensor, col: torch.Tensor) -> DeviceHypergraph:
         nnz = int(col.numel())
-        cap_nets = {ROW_NET: m, COLUMN_NET: n, SYMMETRIC: max(nnz, 1)}[kind]
-        cap_pins = {ROW_NET: nnz, COLUMN_NET: nnz, SYMMETRIC: 2 * nnz}[kind]
+        cap_nets = {ROW_NET: m, COLUMN_NET: n, SYMMETRIC: max(nnz, 1), BIPARTITE: nnz}[kind]
+        cap_pins = {ROW_NET: nnz, COLUMN_NET: nnz, SYMMETRIC: 2 * nnz, BIPARTITE: 2 * nnz}[kind]
         dev = rowptr.device
         net_ptr = torch.empty(cap_nets + 1, dtype=torch.int64, device=dev)
         pins = torch.empty(max(cap_pins, 1), dtype=torch.int32, device=dev)
@@ -290,19 +290,63 @@ class Context:
         return out
 
     def order_schur(self, h: DeviceHypergraph, x: torch.Tensor, o: dict, P: int, P3: int, seed: int = 0,
-                    t_max: int = 32, out: torch.Tensor | None = None):
+                    t_max: int = 32, out: torch.Tensor | None = None, mu: torch.Tensor | None = None):
         """Schur-complement recursion (vmo_order_schur): o is the dict order()
         returned for a graph-mode ordering of h at coordinates x; returns vperm
         with every separator block reordered by the BBD ordering of its induced
-        graph into P3 parts."""
+        graph into P3 parts (keeping the pairs of the strengthened diagonal mu
+        together, if given)."""
         if out is None:
             out = torch.empty_like(o["vperm"])
         s = OrderOut(_ptr(o["vperm"]), None, _ptr(o["part"]), _ptr(o["node_heap"]), _ptr(o["node_vptr"]), None, None,
                      _ptr(o["n_nodes"]))
         hs = h.cstruct()
-        self._check(lib().vmo_order_schur(self.h, C.byref(hs), _ptr(x), C.byref(s), C.c_int32(P), C.c_int32(P3),
-                                          C.c_uint64(seed), C.c_int32(t_max), _ptr(out), _stream()))
+        self._check(lib().vmo_order_schur(self.h, C.byref(hs), _ptr(x), _ptr(mu), C.byref(s), C.c_int32(P),
+                                          C.c_int32(P3), C.c_uint64(seed), C.c_int32(t_max), _ptr(out), _stream()))
         return out
+
+    # ------------------------------------------------ strengthened diagonal --
+    def match(self, m: int, n: int, rowptr: torch.Tensor, col: torch.Tensor, a: torch.Tensor | None = None,
+              seed: int = 0, augment: bool = True):
+        """Heavy edge matching of the bipartite graph, augmented to a maximum
+        matching (vmo_match): dict with mrow, mcol, mu and size."""
+        assert a is None or a.dtype == torch.float32, "a must be float32"
+        dev = rowptr.device
+        mrow = torch.empty(m, dtype=torch.int32, device=dev)
+        mcol = torch.empty(n, dtype=torch.int32, device=dev)
+        mu = torch.empty(m + n, dtype=torch.int32, device=dev)
+        size = C.c_int64()
+        self._check(lib().vmo_match(self.h, C.c_int32(m), C.c_int32(n), _ptr(rowptr), _ptr(col) if col.numel() else None,
+                                    _ptr(a), C.c_uint32(seed), C.c_int(1 if augment else 0), _ptr(mrow), _ptr(mcol),
+                                    _ptr(mu), C.byref(size), _stream()))
+        return {"mrow": mrow, "mcol": mcol, "mu": mu, "size": size.value}
+
+    def order_matched(self, h: DeviceHypergraph, x: torch.Tensor | None, mu: torch.Tensor, P: int, seed: int,
+                      order: int = BBD, t_max: int = 32, lp: LayoutParams | None = None):
+        """Graph-mode ordering keeping the pairs of mu together
+        (vmo_order_matched)."""
+        o, s = self._out(h, P, GRAPH, h.net_ptr.device)
+        hs = h.cstruct()
+        self._check(lib().vmo_order_matched(self.h, C.byref(hs), C.c_int(order), _ptr(x),
+                                            C.byref(lp) if lp is not None else None, _ptr(mu), C.c_int32(P),
+                                            C.c_uint64(seed), C.c_int32(t_max), C.byref(s), _stream()))
+        return o
+
+    def matched_perms(self, m: int, vperm: torch.Tensor, mu: torch.Tensor):
+        """Row and column permutations with the matching on the diagonal."""
+        rp = torch.empty(m, dtype=torch.int32, device=vperm.device)
+        cp = torch.empty(m, dtype=torch.int32, device=vperm.device)
+        self._check(lib().vmo_matched_perms(self.h, C.c_int32(m), _ptr(vperm), _ptr(mu), _ptr(rp), _ptr(cp),
+                                            _stream()))
+        return rp, cp
+
+    def finegrain(self, m: int, n: int, rowptr: torch.Tensor, col: torch.Tensor, x: torch.Tensor):
+        """Nonzero coordinates [4][nnz] from bipartite coordinates [4][m+n]."""
+        nnz = int(col.numel())
+        xnz = torch.empty((4, max(nnz, 1)), dtype=torch.float32, device=x.device)
+        self._check(lib().vmo_finegrain(self.h, C.c_int32(m), C.c_int32(n), _ptr(rowptr),
+                                        _ptr(col) if nnz else None, _ptr(x), _ptr(xnz), _stream()))
+        return xnz[:, :nnz]
 
     def order_batch(self, jobs, t_max: int = 32, plain: bool = False):
         """jobs: list of dicts with h, x, P, seed, mode, order, job_index.  Outputs

@@ -23,8 +23,15 @@ void layout_steps(Ctx& c, const vmo_hypergraph* h, const vmo_layout_params* p, f
                   double* alpha, hipStream_t s);
 void order_border(Ctx& c, const vmo_hypergraph* h, const vmo_order_out* in, int32_t P, int32_t b, int32_t* vperm_out,
                   hipStream_t s);
-void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const vmo_order_out* in, int32_t P, int32_t P3,
-                 uint64_t seed, int32_t t_max, int32_t* vperm_out, hipStream_t s);
+void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const int32_t* mu, const vmo_order_out* in,
+                 int32_t P, int32_t P3, uint64_t seed, int32_t t_max, int32_t* vperm_out, hipStream_t s);
+void match(Ctx& c, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* a, uint32_t seed,
+           int augment, int32_t* mrow, int32_t* mcol, int32_t* mu, int64_t* size_out, hipStream_t s);
+void validate_mu(Ctx& c, const vmo_hypergraph* h, const int32_t* mu, hipStream_t s);
+void matched_perms(Ctx& c, int32_t m, const int32_t* vperm, const int32_t* mu, int32_t* rperm, int32_t* cperm,
+                   hipStream_t s);
+void finegrain(Ctx& c, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* x, float* xnz,
+               hipStream_t s);
 }  // namespace vmo
 
 #define API_BEGIN(ctx, stream)                                    \
@@ -208,10 +215,63 @@ vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_orde
   API_END
 }
 
-vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, const vmo_order_out* in, int32_t P,
-                           int32_t P3, uint64_t seed, int32_t t_max, int32_t* vperm_out, vmo_stream stream) {
+vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, const int32_t* mu,
+                           const vmo_order_out* in, int32_t P, int32_t P3, uint64_t seed, int32_t t_max,
+                           int32_t* vperm_out, vmo_stream stream) {
   API_BEGIN(ctx, stream)
-  vmo::order_schur(C, h, x, in, P, P3, seed, t_max, vperm_out, S);
+  vmo::order_schur(C, h, x, mu, in, P, P3, seed, t_max, vperm_out, S);
+  API_END
+}
+
+vmo_status vmo_match(vmo_ctx ctx, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* a,
+                     uint32_t seed, int augment, int32_t* mrow, int32_t* mcol, int32_t* mu, int64_t* size,
+                     vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::match(C, m, n, rowptr, col, a, seed, augment, mrow, mcol, mu, size, S);
+  API_END
+}
+
+vmo_status vmo_order_matched(vmo_ctx ctx, const vmo_hypergraph* h, int order, const float* x,
+                             const vmo_layout_params* lp, const int32_t* mu, int32_t P, uint64_t seed, int32_t t_max,
+                             const vmo_order_out* out, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  check_order_scalars(VMO_GRAPH, order, P, t_max, out);
+  VMO_REQUIRE(x || lp, "x is NULL and no layout parameters were given");
+  std::vector<int64_t> npins;
+  vmo::validate_jobs(C, {vmo::JobCheck{h, x, false, true}}, npins, S);
+  vmo::validate_mu(C, h, mu, S);
+  vmo::Buf<float> xl;
+  if (!x) {
+    xl = vmo::Buf<float>(C.pool, 4 * (size_t)h->k);
+    vmo::layout(C, h, lp, xl.p, S);
+    x = xl.p;
+  }
+  std::vector<vmo::JobHost> jobs(1);
+  memset(&jobs[0], 0, sizeof(vmo::JobHost));
+  jobs[0].h = *h;
+  jobs[0].mode = VMO_GRAPH;
+  jobs[0].order = order;
+  jobs[0].x = x;
+  jobs[0].P = P;
+  jobs[0].seed = seed;
+  jobs[0].job_index = 0;
+  jobs[0].out = *out;
+  jobs[0].mu = mu;
+  run_order(C, jobs, npins, t_max, false, S);
+  API_END
+}
+
+vmo_status vmo_matched_perms(vmo_ctx ctx, int32_t m, const int32_t* vperm, const int32_t* mu, int32_t* rperm,
+                             int32_t* cperm, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::matched_perms(C, m, vperm, mu, rperm, cperm, S);
+  API_END
+}
+
+vmo_status vmo_finegrain(vmo_ctx ctx, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* x,
+                         float* xnz, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::finegrain(C, m, n, rowptr, col, x, xnz, S);
   API_END
 }
 

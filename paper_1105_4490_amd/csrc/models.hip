@@ -1,4 +1,5 @@
-// Matrix-to-hypergraph models of Table 1 (row-net, column-net, symmetric) and
+// Matrix-to-hypergraph models of Table 1 (row-net, column-net, symmetric,
+// bipartite) and
 // the dual hypergraph (Definition of the dual, Sec. 1.1).
 #include "vmo_internal.h"
 
@@ -50,11 +51,27 @@ __global__ void k_sym_write(const uint64_t* keys, const int32_t* flag, const int
 }
 __global__ void k_set_last(int64_t* p, int64_t v) { *p = v; }
 
+// Bipartite model: nonzero p = (i, j) is the edge {i, m + j}.
+__global__ void k_bip_write(const int64_t* rowptr, const int32_t* col, int32_t m, int64_t nnz, int64_t* net_ptr,
+                            int32_t* pins) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (rowptr[mid] <= p) lo = mid; else hi = mid;
+    }
+    pins[2 * p] = lo;
+    pins[2 * p + 1] = m + col[p];
+    net_ptr[p] = 2 * p;
+  }
+}
+
 void model(Ctx& c, int model, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, int64_t* net_ptr,
            int32_t* pins, int32_t cap_nets, int64_t cap_pins, int32_t* k_out, int32_t* l_out, int64_t* np_out,
            hipStream_t s) {
   VMO_REQUIRE(m >= 1 && n >= 1, "matrix needs m, n >= 1");
-  VMO_REQUIRE(model == VMO_ROW_NET || model == VMO_COLUMN_NET || model == VMO_SYMMETRIC, "unknown model");
+  VMO_REQUIRE(model == VMO_ROW_NET || model == VMO_COLUMN_NET || model == VMO_SYMMETRIC || model == VMO_BIPARTITE,
+              "unknown model");
   VMO_REQUIRE(rowptr && net_ptr && k_out && l_out && np_out, "NULL argument");
   vmo_hypergraph a{n, m, rowptr, col, nullptr, nullptr};  // rows as nets over columns
   validate_hypergraph(c, &a, false, s);
@@ -68,6 +85,13 @@ void model(Ctx& c, int model, int32_t m, int32_t n, const int64_t* rowptr, const
     VMO_REQUIRE(cap_nets >= n && cap_pins >= nnz, "output capacity too small");
     csr_transpose(c, m, n, rowptr, col, net_ptr, pins, s);
     *k_out = m; *l_out = n; *np_out = nnz;
+  } else if (model == VMO_BIPARTITE) {
+    VMO_REQUIRE((int64_t)m + n < (int64_t(1) << 31), "m + n must be below 2^31");
+    VMO_REQUIRE(nnz < (int64_t(1) << 31), "too many nonzeros for the bipartite model");
+    VMO_REQUIRE(cap_nets >= nnz && cap_pins >= 2 * nnz, "output capacity too small");
+    if (nnz > 0) VMO_LAUNCH(k_bip_write, gsz(nnz), kMT, 0, s, rowptr, col, m, nnz, net_ptr, pins);
+    VMO_LAUNCH(k_set_last, 1, 1, 0, s, net_ptr + nnz, 2 * nnz);
+    *k_out = m + n; *l_out = (int32_t)nnz; *np_out = 2 * nnz;
   } else {
     VMO_REQUIRE(m == n, "the symmetric model needs a square matrix");
     int64_t l = 0;

@@ -434,14 +434,28 @@ __global__ void k_cbounds(const uint32_t* candseg, int64_t nc, int64_t* cbeg, in
   }
 }
 
+// Position of the partner of the vertex at each position of [p0, p1) under
+// the strengthened diagonal (-1: none).
+__global__ void k_mate_pos(const int32_t* id, const int32_t* pos, const int32_t* mu_g, int64_t p0, int64_t p1,
+                           int32_t* mate) {
+  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = id[i];  // -1 at the padding positions
+    const int32_t w = v >= 0 ? mu_g[v] : -1;
+    mate[i] = w >= 0 ? pos[w] : -1;
+  }
+}
+
 // Algorithm 7 separator loop, one wavefront per segment.  Its cut edges come in
 // edge order, 64 at a time; edges already touching S are dropped; inside a
 // chunk, edges are resolved in order with ballots: once an edge puts its end
 // nearer the plane (smaller |s|; ties to the first end) into S, every later
-// edge of the chunk touching that vertex is dropped.
+// edge of the chunk touching that vertex is dropped.  With a strengthened
+// diagonal (mate != NULL) the chosen end's partner enters S with it, and later
+// edges touching either are dropped.
 __global__ __launch_bounds__(kT) void k_separator(SegArrays sg, int64_t s0, int64_t S, const int64_t* cbeg,
                                                   const int64_t* cend, const int32_t* cand, const int32_t* edges,
-                                                  const int32_t* pos, const uint32_t* q, int64_t Np, int32_t* sep) {
+                                                  const int32_t* pos, const uint32_t* q, int64_t Np,
+                                                  const int32_t* mate, int32_t* sep) {
   int64_t s = s0 + (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
   if (s >= s0 + S) return;
   int lane = lane_id();
@@ -451,7 +465,7 @@ __global__ __launch_bounds__(kT) void k_separator(SegArrays sg, int64_t s0, int6
   for (int64_t base = b; base < e; base += 64) {
     int64_t idx = base + lane;
     bool valid = idx < e;
-    int32_t pa = -1, pb = -1, ch = -1;
+    int32_t pa = -1, pb = -1, ch = -1, chm = -1;
     bool alive = false;
     if (valid) {
       int32_t ed = cand[idx];
@@ -460,6 +474,7 @@ __global__ __launch_bounds__(kT) void k_separator(SegArrays sg, int64_t s0, int6
       double sa = fabs(plane_eval(q[pa], q[Np + pa], q[2 * Np + pa], q[3 * Np + pa], pl));
       double sb = fabs(plane_eval(q[pb], q[Np + pb], q[2 * Np + pb], q[3 * Np + pb], pl));
       ch = sa <= sb ? pa : pb;
+      if (mate) chm = mate[ch];
       int ia = __hip_atomic_load(&sep[pa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       int ib = __hip_atomic_load(&sep[pb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       alive = !ia && !ib;
@@ -470,11 +485,15 @@ __global__ __launch_bounds__(kT) void k_separator(SegArrays sg, int64_t s0, int6
       int j = __builtin_ctzll(rem);
       rem &= rem - 1;
       int32_t cj = __shfl(ch, j, 64);
-      uint64_t kill = __ballot(valid && lane > j && (pa == cj || pb == cj));
+      int32_t mj = __shfl(chm, j, 64);
+      uint64_t kill = __ballot(valid && lane > j && (pa == cj || pb == cj || (mj >= 0 && (pa == mj || pb == mj))));
       mask &= ~kill;
       rem &= ~kill;
     }
-    if (valid && ((mask >> lane) & 1ull)) __hip_atomic_store(&sep[ch], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (valid && ((mask >> lane) & 1ull)) {
+      __hip_atomic_store(&sep[ch], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (chm >= 0) __hip_atomic_store(&sep[chm], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     // the next chunk's reads see these stores: the positions of a segment are
     // read and written by this wavefront only, so the order is needed among
     // its own lanes (workgroup scope: a wait for the stores, no cache write-back)
@@ -931,6 +950,11 @@ static void offset_copy_all(Ctx& c, const std::vector<OffCopy>& tab, T* out, hip
   VMO_LAUNCH((k_offset_copy_all<T>), nblocks((tot + 15) / 16, kT), kT, 0, s, dt.p, dc.p, nt, tot, out);
 }
 
+__global__ void k_mu_global(const int32_t* mu, int32_t k, int64_t voff, int32_t* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = mu[i] >= 0 ? (int32_t)(mu[i] + voff) : -1;
+}
+
 void Engine::set_edges(const std::vector<JobHost>& jobs, const std::vector<int64_t>& jpins) {
   // graph-mode edges, global vertex ids; net-mode nets, global pins
   edges = Buf<int32_t>(c.pool, 2 * (E > 0 ? E : 1));
@@ -961,6 +985,16 @@ void Engine::set_edges(const std::vector<JobHost>& jobs, const std::vector<int64
   offset_copy_all<int64_t>(c, c64, nptr.p, s);
   offset_copy_all<int32_t>(c, cpin, npins_buf.p, s);
   VMO_HIP(hipMemcpyAsync(jnoff.p, hnoff.data(), 8 * nj, hipMemcpyHostToDevice, s));
+  // strengthened diagonals, in global vertex ids
+  has_mu = false;
+  for (int32_t j = 0; j < nj; ++j) has_mu = has_mu || (jobs[j].mode == VMO_GRAPH && jobs[j].mu);
+  if (has_mu) {
+    mu_g = Buf<int32_t>(c.pool, N);
+    fill_i32(mu_g.p, -1, N, s);
+    for (int32_t j = 0; j < nj; ++j)
+      if (jobs[j].mode == VMO_GRAPH && jobs[j].mu)
+        VMO_LAUNCH(k_mu_global, gsz(hj[j].k), kT, 0, s, jobs[j].mu, hj[j].k, hj[j].voff, mu_g.p + hj[j].voff);
+  }
 }
 
 __global__ void k_offset_copy_i32(const int32_t* in, int32_t* out, int64_t n, int32_t add) {
@@ -1034,8 +1068,13 @@ void Engine::separator(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int64_t e
     fill_i64(cb.p + s0, 0, Sn, s);
     fill_i64(ce.p + s0, 0, Sn, s);
     VMO_LAUNCH(k_cbounds, gsz(nc), kT, 0, s, cseg.p, (int64_t)nc, cb.p, ce.p);
+    Buf<int32_t> mate;
+    if (has_mu) {
+      mate = Buf<int32_t>(c.pool, Np);
+      VMO_LAUNCH(k_mate_pos, gsz(p1 - p0), kT, 0, s, id.p, pos.p, mu_g.p, p0, p1, mate.p);
+    }
     VMO_LAUNCH(k_separator, nblocks(Sn, kT / 64), kT, 0, s, sg, s0, Sn, cb.p, ce.p, cand.p, edges.p, pos.p, q.p, Np,
-               sep.p);
+               has_mu ? mate.p : nullptr, sep.p);
   }
   VMO_LAUNCH(k_mark_sep, gsz(p1 - p0), kT, 0, s, sep.p, p0, p1, side.p);
 }

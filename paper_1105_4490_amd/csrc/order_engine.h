@@ -34,6 +34,7 @@ struct JobHost {
   int32_t P;
   uint64_t seed, job_index;
   vmo_order_out out;
+  const int32_t* mu;  // graph mode: strengthened diagonal (partner or -1), local ids; NULL = none
 };
 
 struct OutPtrs {
@@ -103,6 +104,8 @@ class Engine {
   Buf<int32_t> nd_state, nd_K, nd_p0;
   Buf<int64_t> nd_beg, nd_end;
   Buf<int32_t> edges, npins_buf;
+  Buf<int32_t> mu_g;  // partners in global vertex ids (-1: none), when a job has a strengthened diagonal
+  bool has_mu = false;
   Buf<int64_t> nptr, jnoff;
 
   SegArrays view(SegBufs& b);

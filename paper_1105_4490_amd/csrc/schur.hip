@@ -5,8 +5,10 @@
 // of a block lists its vertices in block order (local id = position in the
 // block) and the edges with both ends in the block in net order, the smaller
 // local end first; its random draws are keyed by the heap id of the block's
-// node as the job index.  One level of recursion: the result's own separator
-// blocks are left as they come.
+// node as the job index.  With a strengthened diagonal mu, each block's job
+// gets mu restricted to the block (partners outside it dropped), so matched
+// pairs also stay together in the Schur complement.  One level of recursion:
+// the result's own separator blocks are left as they come.
 //
 // All blocks are ordered together, as one batch of jobs of the ordering
 // engine: a device pass marks the separator blocks, the vertices of each block
@@ -63,6 +65,19 @@ __global__ void k_sc_verts(const int32_t* vperm, const int32_t* node_vptr, int32
   }
 }
 
+// The strengthened diagonal of each job in local ids.
+__global__ void k_sc_mu(const int32_t* vperm, const int32_t* node_vptr, int32_t nn, int32_t k, const int32_t* job_of,
+                        const int64_t* jbase, const int32_t* mu, const int32_t* loc, const int32_t* vjob,
+                        int32_t* mu3) {
+  SC_STRIDE(i, k) {
+    const int32_t r = sc_rank(node_vptr, nn, i);
+    const int32_t j = job_of[r];
+    if (j < 0) continue;
+    const int32_t w = mu[vperm[i]];
+    mu3[jbase[j] + (i - node_vptr[r])] = (w >= 0 && vjob[w] == j) ? loc[w] : -1;
+  }
+}
+
 // Edge e goes to job j when both ends lie in j's block (key j, counted), else
 // to the end of the order (key nb).
 __global__ void k_sc_edge_keys(const int32_t* pins, int32_t l, const int32_t* vjob, int32_t nb, uint32_t* key,
@@ -110,13 +125,16 @@ __global__ void k_sc_compose(const int32_t* vperm, const int32_t* node_vptr, int
   }
 }
 
-void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const vmo_order_out* in, int32_t P, int32_t P3,
-                 uint64_t seed, int32_t t_max, int32_t* vperm_out, hipStream_t s) {
+void validate_mu(Ctx& c, const vmo_hypergraph* h, const int32_t* mu, hipStream_t s);
+
+void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const int32_t* mu, const vmo_order_out* in,
+                 int32_t P, int32_t P3, uint64_t seed, int32_t t_max, int32_t* vperm_out, hipStream_t s) {
   VMO_REQUIRE(vperm_out != nullptr, "vperm_out is NULL");
   VMO_REQUIRE(P3 >= 1 && P3 <= (1 << 24), "P3 must be in [1, 2^24]");
   VMO_REQUIRE(t_max >= 0, "t_max must be >= 0");
   std::vector<int64_t> npins;
   validate_jobs(c, {JobCheck{h, x, true, true}}, npins, s);
+  if (mu) validate_mu(c, h, mu, s);
   const int32_t k = h->k, l = h->l;
   const int32_t nn = check_ordering(c, k, P, in, s);
   // the separator blocks, on the host
@@ -156,6 +174,12 @@ void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const vmo_orde
   Buf<float> xs(c.pool, 4 * M);
   VMO_LAUNCH(k_sc_verts, ssz(k), kST, 0, s, in->vperm, in->node_vptr, nn, k, djob.p, djbase.p, x, loc.p, vjob.p,
              xs.p);
+  Buf<int32_t> mu3;
+  if (mu) {
+    mu3 = Buf<int32_t>(c.pool, M);
+    VMO_LAUNCH(k_sc_mu, ssz(k), kST, 0, s, in->vperm, in->node_vptr, nn, k, djob.p, djbase.p, mu, loc.p, vjob.p,
+               mu3.p);
+  }
   // induced edges grouped by job, net order kept
   Buf<int32_t> count(c.pool, nb);
   fill_i32(count.p, 0, nb, s);
@@ -206,6 +230,7 @@ void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const vmo_orde
     J.out.node_vptr = vptr3.p + (nper + 1) * j;
     J.out.split_cut = sc3.p + nper * j;
     J.out.n_nodes = nn3.p + j;
+    J.mu = mu ? mu3.p + jbase[j] : nullptr;
     jp[j] = 2 * (int64_t)hcount[j];
   }
   Engine e(c, s);
