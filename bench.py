@@ -41,7 +41,7 @@ FLOPS_PER_INTERACTION = 23   # 4 sub, r^2 (1 mul + 3 fma), 2 mul (2 W w), 1 mul 
 # HBM bytes per walk launch (average over one step of this workload), from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
 # plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
-WALK_TRAFFIC_BYTES = 64.30e6 + 9.23e6
+WALK_TRAFFIC_BYTES = 78.40e6 + 17.94e6
 PEAK_FP32_VALU_TFLOPS = 157.3
 # live timing brackets every PROFILE_EVERY-th launch of a kernel with HIP
 # events: an event pair costs about 13 us of stream time, 2.5 % of a step when
@@ -59,6 +59,8 @@ def main():
                     help="untimed steps (the launch tuner settles during the first steps)")
     ap.add_argument("--side", type=int, default=N_SIDE, help="grid side of the workload (64 = the 64^3 case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--path-only", action="store_true",
+                    help="only the timed V+O steps (no order-only, border, Schur or LU-ordering fields)")
     ap.add_argument("--cpu-side", type=int, default=28, help="grid side of the oracle's timed sample")
     ap.add_argument("--mode", choices=("path", "batch", "serve", "copy"), default="path",
                     help="copy: a plain 256 MiB device copy, three times (calibrates the HBM byte counters)")
@@ -164,8 +166,10 @@ def main():
                          "share_of_step": round(assign["total_ms"] * PROFILE_EVERY / (1e3 * dt), 4)},
         "cpu_baseline": cpu,
     }
-    h = ctx.model(P.SYMMETRIC, g.m, g.n, rowptr, col)
-    line.update(order_only_and_border(ctx, h, g, lp, o, args.steps))
+    if not args.path_only:
+        h = ctx.model(P.SYMMETRIC, g.m, g.n, rowptr, col)
+        line.update(order_only_and_border(ctx, h, g, lp, o, args.steps))
+        line.update(bench_lu_pipeline(ctx, g, rowptr, col, lp, 2))
     print(json.dumps(line))
 
 
@@ -208,6 +212,72 @@ def order_only_and_border(ctx, h, g, lp, o, steps):
             "schur": {"P3": SCHUR_P3, "value": g.nnz / dt_s, "unit": "nnz/s", "ms": 1e3 * dt_s,
                       "what": "Schur-complement recursion: every separator block of the ordering reordered by the "
                               "BBD ordering of its induced graph into P3 parts, all blocks in one batched pass"}}
+
+
+def bench_lu_pipeline(ctx, g, rowptr, col, lp, steps):
+    """The ordering for LU of the same matrix with a strengthened diagonal:
+    bipartite model, heavy edge matching on synthetic values with a dominant
+    diagonal (|a_ii| about 6, off-diagonal about 1) augmented to a maximum
+    matching, layout of the bipartite graph, BBD ordering that keeps matched
+    pairs together, Schur-complement recursion with the matching, row and
+    column permutations; timed as a whole over `steps` runs after one untimed
+    run, with a per-phase split of one more run.  The pattern-only matching
+    (ties broken by the scrambled index, so the augmentation has work to do)
+    is timed on its own."""
+    import numpy as np
+    import torch
+    import paper_1105_4490_amd as P
+    import vmo_gen
+    rows = np.repeat(np.arange(g.m), np.diff(g.rowptr))
+    a = (np.where(rows == g.col, 6.0, -1.0) + vmo_gen.rng(SEED, 71).uniform(-0.1, 0.1, g.nnz)).astype(np.float32)
+    da = torch.as_tensor(a).cuda()
+    phases = {}
+
+    def run(split=False):
+        marks = [time.perf_counter()]
+
+        def mark(name):
+            if split:
+                torch.cuda.synchronize()
+                marks.append(time.perf_counter())
+                phases[name] = 1e3 * (marks[-1] - marks[-2])
+        hb = ctx.model(P.BIPARTITE, g.m, g.n, rowptr, col)
+        mt = ctx.match(g.m, g.n, rowptr, col, da, seed=SEED)
+        mark("model_match")
+        x = ctx.layout(hb, lp)
+        mark("layout")
+        o = ctx.order_matched(hb, x, mt["mu"], P_PARTS, SEED)
+        mark("order")
+        s = ctx.order_schur(hb, x, o, P_PARTS, SCHUR_P3, SEED, mu=mt["mu"])
+        rp, cp = ctx.matched_perms(g.m, s, mt["mu"])
+        mark("schur_perms")
+        return mt, o
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mt, o = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    run(split=True)
+    n_nodes = int(o["n_nodes"].item())
+    ctx.match(g.m, g.n, rowptr, col, None, seed=SEED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mp = ctx.match(g.m, g.n, rowptr, col, None, seed=SEED)
+    torch.cuda.synchronize()
+    dm = (time.perf_counter() - t0) / steps
+    heavy = ctx.match(g.m, g.n, rowptr, col, None, seed=SEED, augment=False)
+    return {"lu_ordering": {"value": g.nnz / dt, "unit": "nnz/s", "ms": 1e3 * dt, "steps": steps,
+                            "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+                            "bipartite_vertices": g.m + g.n, "matching_size": mt["size"],
+                            "separator_vertices": float(o["split_cut"][:n_nodes].sum().item()),
+                            "what": "bipartite model + strengthened diagonal (heavy edge matching, augmented) + "
+                                    "layout of the bipartite graph + BBD ordering keeping matched pairs together "
+                                    f"+ Schur-complement recursion (P3 = {SCHUR_P3}) + row/column permutations"},
+            "match_pattern_only": {"ms": 1e3 * dm, "size": mp["size"], "heavy_size": heavy["size"]}}
 
 
 def _pct(v, q):
