@@ -366,6 +366,20 @@ def finegrain(m, n, rowptr, col, x):
     return out
 
 
+def refine_kl(h: Hypergraph, label, passes: int):
+    """Kernighan-Lin passes on the bisections of a graph (o_refine_kl):
+    label[v] = 2 g + side, or -1; returns (new labels, cut reduction per
+    bisection)."""
+    label = np.array(label, dtype=np.int32, copy=True)
+    G = max(int(label.max()) // 2 + 1, 1) if label.size else 1
+    gain = np.zeros(G, np.int64)
+    rc = lib().o_refine_kl(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(label), C.c_int32(passes),
+                           _p(gain))
+    if rc != 0:
+        raise ValueError("oracle refine_kl rejected its input")
+    return label, gain
+
+
 # ---------------------------------------------------------------- layout ----
 
 class LayoutParams(C.Structure):

@@ -44,6 +44,9 @@
  *                     diagonal [Sec. 4.2, permutations from V1, V2, V3].
  *   o_finegrain       nonzero coordinates = mean of row and column points
  *                     [Sec. 4.2, layout of the finegrain representation].
+ *   o_refine_kl       Kernighan-Lin passes on bisections of a graph
+ *                     [Sec. 3, partitionings of Algorithm 4 improved by
+ *                     Kernighan-Lin; Kernighan and Lin 1970].
  *   o_coarsen         one coarsening step [Sec. 2.3, coarsening by greedy
  *                     heavy-net matching, single-neighbour rule, net merge].
  *   o_tree            2^d-tree with cluster charges [Sec. 2.1 tree
@@ -1587,4 +1590,116 @@ void o_finegrain(int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
       for (int d = 0; d < 4; ++d)
         xnz[d * nnz + (size_t)e] = (x[d * k + (size_t)i] + x[d * k + (size_t)m + (size_t)col[e]]) * 0.5f;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Kernighan-Lin refinement [Sec. 3, the remark that partitionings made by
+   Algorithm 4 improve under a few Kernighan-Lin iterations; Kernighan and Lin
+   1970].  Graph mode (every net an edge {v, w}); every edge weighs 1, so
+   parallel edges add up.  label[v] = 2 g + s puts v on side s (0 = A, 1 = B)
+   of bisection g; label -1 leaves v out.  Each bisection is refined on its
+   own, only edges inside it counting.  One pass: D(v) = (edges to the other
+   side) - (edges to its own side); then min(|A|, |B|) times the unlocked pair
+   (a in A, b in B) of largest gain D(a) + D(b) - 2 m(a, b) (m = edges joining
+   them) is chosen, ties to the smallest a, then the smallest b; both are
+   locked and the D of the unlocked vertices updated as if they had swapped.
+   With G(j) the sum of the first j gains and j* the smallest j of largest
+   G(j), the first j* pairs are swapped if G(j*) > 0, else the bisection is
+   done.  At most `passes` passes.  gain[g] = the cut reduction (edges) of
+   bisection g over all passes.  Returns -1 for bad input. */
+static int32_t kl_mult(const int64_t* aptr, const int32_t* adj, int32_t a, int32_t b) {
+  int32_t m = 0;
+  for (int64_t p = aptr[a]; p < aptr[a + 1]; ++p) m += adj[p] == b;
+  return m;
+}
+int o_refine_kl(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, int32_t* label, int32_t passes,
+                int64_t* gain) {
+  if (k < 1 || l < 0 || passes < 0) return -1;
+  for (int32_t e = 0; e < l; ++e)
+    if (ptr[e + 1] - ptr[e] != 2 || pins[ptr[e]] >= pins[ptr[e] + 1] || pins[ptr[e]] < 0 || pins[ptr[e] + 1] >= k)
+      return -1;
+  int32_t G = 0;
+  for (int32_t v = 0; v < k; ++v) {
+    if (label[v] < -1) return -1;
+    if (label[v] / 2 + 1 > G) G = label[v] / 2 + 1;
+  }
+  /* adjacency: the other end of every incident edge, edges in ascending order */
+  int64_t* aptr = (int64_t*)calloc((size_t)k + 1, sizeof(int64_t));
+  int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * (2 * (size_t)l + 1));
+  for (int32_t e = 0; e < l; ++e) { aptr[pins[2 * e] + 1]++; aptr[pins[2 * e + 1] + 1]++; }
+  for (int32_t v = 0; v < k; ++v) aptr[v + 1] += aptr[v];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  for (int32_t v = 0; v < k; ++v) fill[v] = aptr[v];
+  for (int32_t e = 0; e < l; ++e) {
+    const int32_t a = pins[2 * e], b = pins[2 * e + 1];
+    adj[fill[a]++] = b;
+    adj[fill[b]++] = a;
+  }
+  int64_t* D = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  char* locked = (char*)malloc((size_t)k);
+  int32_t* mem = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  int32_t* pa = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  int32_t* pb = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  int64_t* pg = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  for (int32_t g = 0; g < G; ++g) {
+    gain[g] = 0;
+    int32_t n = 0, nA = 0, nB = 0;
+    for (int32_t v = 0; v < k; ++v)
+      if (label[v] >= 0 && label[v] / 2 == g) {
+        mem[n++] = v;
+        if (label[v] % 2 == 0) ++nA; else ++nB;
+      }
+    const int32_t steps = nA < nB ? nA : nB;
+    for (int32_t pass = 0; pass < passes && steps > 0; ++pass) {
+      for (int32_t i = 0; i < n; ++i) {
+        const int32_t v = mem[i];
+        locked[v] = 0;
+        D[v] = 0;
+        for (int64_t p = aptr[v]; p < aptr[v + 1]; ++p) {
+          const int32_t w = adj[p];
+          if (label[w] < 0 || label[w] / 2 != g) continue;
+          D[v] += (label[w] % 2 != label[v] % 2) ? 1 : -1;
+        }
+      }
+      for (int32_t st = 0; st < steps; ++st) {
+        int64_t best = INT64_MIN;
+        int32_t ba = -1, bb = -1;
+        for (int32_t i = 0; i < n; ++i) {
+          const int32_t a = mem[i];
+          if (locked[a] || label[a] % 2 != 0) continue;
+          for (int32_t j = 0; j < n; ++j) {
+            const int32_t b = mem[j];
+            if (locked[b] || label[b] % 2 != 1) continue;
+            const int64_t gv = D[a] + D[b] - 2 * (int64_t)kl_mult(aptr, adj, a, b);
+            if (gv > best) { best = gv; ba = a; bb = b; }  /* ascending a, then b: first of equals wins */
+          }
+        }
+        locked[ba] = locked[bb] = 1;
+        pa[st] = ba; pb[st] = bb; pg[st] = best;
+        /* D of the unlocked members as if ba (A -> B) and bb (B -> A) swapped */
+        for (int s = 0; s < 2; ++s) {
+          const int32_t x = s == 0 ? ba : bb;  /* x leaves side label[x] % 2 */
+          for (int64_t p = aptr[x]; p < aptr[x + 1]; ++p) {
+            const int32_t w = adj[p];
+            if (label[w] < 0 || label[w] / 2 != g || locked[w]) continue;
+            D[w] += (label[w] % 2 == label[x] % 2) ? 2 : -2;
+          }
+        }
+      }
+      int64_t run = 0, bestG = INT64_MIN;
+      int32_t jstar = 0;
+      for (int32_t st = 0; st < steps; ++st) {
+        run += pg[st];
+        if (run > bestG) { bestG = run; jstar = st + 1; }
+      }
+      if (bestG <= 0) break;
+      for (int32_t st = 0; st < jstar; ++st) {
+        label[pa[st]] = 2 * g + 1;
+        label[pb[st]] = 2 * g;
+      }
+      gain[g] += bestG;
+    }
+  }
+  free(aptr); free(adj); free(fill); free(D); free(locked); free(mem); free(pa); free(pb); free(pg);
+  return 0;
 }
