@@ -318,6 +318,25 @@ vmo_status vmo_order_matched(vmo_ctx ctx, const vmo_hypergraph* h, int order, co
 vmo_status vmo_matched_perms(vmo_ctx ctx, int32_t m, const int32_t* vperm, const int32_t* mu, int32_t* rperm,
                              int32_t* cperm, vmo_stream stream);
 
+/* Kernighan-Lin refinement of bisections of a graph (Sec. 3: partitionings
+ * made by Algorithm 4 improve under a few Kernighan-Lin iterations; Kernighan
+ * and Lin 1970).  h: a graph (every net an edge {v, w}, v < w); every edge
+ * weighs 1, parallel edges add up.  label (device [k], in/out): 2 g + s puts
+ * v on side s (0 or 1) of bisection g, -1 leaves it out.  Each bisection is
+ * refined on its own with only its inner edges counting: a pass sets D(v) =
+ * (edges to the other side) - (edges to its own side), then min(|A|, |B|)
+ * times locks the unlocked pair (a in A, b in B) of largest gain D(a) + D(b)
+ * - 2 m(a, b) (m = edges joining them; ties to the smallest a, then the
+ * smallest b) and updates D as if they had swapped; the first j pairs, j the
+ * smallest index of largest prefix gain G(j), change sides if G(j) > 0, else
+ * the bisection is done.  At most `passes` passes.  Side sizes are kept.
+ * gain (device [G] or NULL): cut reduction of every bisection;
+ * *ngroups (host, or NULL): G = 1 + the largest g.  One workgroup per
+ * bisection; a pass costs O(|bisection|^2) work.  VMO_E_INVALID for labels
+ * below -1, a hypergraph that is not a graph, degrees above 1024 or k >= 2^25. */
+vmo_status vmo_refine_kl(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, int32_t passes, int64_t* gain,
+                         int32_t* ngroups /* (host) */, vmo_stream stream);
+
 /* Finegrain coordinates (Sec. 4.2: each nonzero mapped to the average of the
  * points of its row and its column in a layout of the bipartite graph).
  * x: [4][m+n] (rows, then columns); xnz: [4][nnz], xnz[d][e] = (x[d][i] +

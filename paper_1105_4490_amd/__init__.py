@@ -340,6 +340,19 @@ class Context:
                                             _stream()))
         return rp, cp
 
+    def refine_kl(self, h: DeviceHypergraph, label: torch.Tensor, passes: int):
+        """Kernighan-Lin passes on the bisections of a graph (vmo_refine_kl):
+        label[v] = 2 g + side or -1; returns (new labels, cut reduction per
+        bisection)."""
+        assert label.dtype == torch.int32
+        out = label.clone()
+        G = C.c_int32()
+        gain = torch.zeros(max(int(out.max().item()) // 2 + 1, 1), dtype=torch.int64, device=out.device)
+        hs = h.cstruct()
+        self._check(lib().vmo_refine_kl(self.h, C.byref(hs), _ptr(out), C.c_int32(passes), _ptr(gain), C.byref(G),
+                                        _stream()))
+        return out, gain[:G.value]
+
     def finegrain(self, m: int, n: int, rowptr: torch.Tensor, col: torch.Tensor, x: torch.Tensor):
         """Nonzero coordinates [4][nnz] from bipartite coordinates [4][m+n]."""
         nnz = int(col.numel())

@@ -32,6 +32,8 @@ void matched_perms(Ctx& c, int32_t m, const int32_t* vperm, const int32_t* mu, i
                    hipStream_t s);
 void finegrain(Ctx& c, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* x, float* xnz,
                hipStream_t s);
+void refine_kl(Ctx& c, const vmo_hypergraph* h, int32_t* label, int32_t passes, int64_t* gain, int32_t* ngroups,
+               hipStream_t s);
 }  // namespace vmo
 
 #define API_BEGIN(ctx, stream)                                    \
@@ -265,6 +267,13 @@ vmo_status vmo_matched_perms(vmo_ctx ctx, int32_t m, const int32_t* vperm, const
                              int32_t* cperm, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::matched_perms(C, m, vperm, mu, rperm, cperm, S);
+  API_END
+}
+
+vmo_status vmo_refine_kl(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, int32_t passes, int64_t* gain,
+                         int32_t* ngroups, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  vmo::refine_kl(C, h, label, passes, gain, ngroups, S);
   API_END
 }
 
