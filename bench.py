@@ -175,9 +175,11 @@ def main():
 
 def order_only_and_border(ctx, h, g, lp, o, steps):
     """The O column (ordering from given coordinates: the layout of the same
-    matrix, computed before the timed region) and the recursive ordering of
-    the border (b = 3 two-bit words) of the V+O result, each timed over
-    `steps` calls after one untimed call."""
+    matrix, computed before the timed region), the recursive ordering of the
+    border (b = 3 two-bit words) of the V+O result, the Schur-complement
+    recursion of the O result and the Kernighan-Lin refinement of 2-means
+    bisections of the leaf blocks, each timed over `steps` calls after one
+    untimed call."""
     import torch
     x = ctx.layout(h, lp)
     ctx.order(h, x, P_PARTS, SEED, mode=1, order=1)
@@ -204,7 +206,8 @@ def order_only_and_border(ctx, h, g, lp, o, steps):
         ctx.order_schur(h, x, ox, P_PARTS, SCHUR_P3, SEED)
     torch.cuda.synchronize()
     dt_s = (time.perf_counter() - t0) / steps
-    return {"order_only": {"metric": "matrix nnz ordered/sec (recursive BBD from given coordinates)",
+    kl = bench_kl(ctx, h, x, o, steps)
+    return {"kl": kl, "order_only": {"metric": "matrix nnz ordered/sec (recursive BBD from given coordinates)",
                            "value": g.nnz / dt_o, "unit": "nnz/s", "ms": 1e3 * dt_o},
             "border": {"b": b, "value": g.nnz / dt_b, "unit": "nnz/s", "ms": 1e3 * dt_b,
                        "what": "recursive ordering of the border of the V+O result (separator blocks sorted by "
@@ -212,6 +215,39 @@ def order_only_and_border(ctx, h, g, lp, o, steps):
             "schur": {"P3": SCHUR_P3, "value": g.nnz / dt_s, "unit": "nnz/s", "ms": 1e3 * dt_s,
                       "what": "Schur-complement recursion: every separator block of the ordering reordered by the "
                               "BBD ordering of its induced graph into P3 parts, all blocks in one batched pass"}}
+
+
+def bench_kl(ctx, h, x, o, steps, passes=4):
+    """Kernighan-Lin refinement of 2-means bisections: every leaf block of
+    the V+O result is split by one 2-means bisection of its layout points
+    (untimed), and the 64 bisections are refined together (one workgroup
+    each), `passes` passes, each timing from the same labels."""
+    import torch
+    part = o["part"].long()
+    label = torch.full((h.k,), -1, dtype=torch.int32, device=part.device)
+    sizes = []
+    for p in range(P_PARTS):
+        verts = torch.nonzero(part == p).flatten()
+        if verts.numel() < 2:
+            continue
+        b = ctx.bisect(x[:, verts].contiguous(), SEED)
+        label[verts] = (2 * p + b["side"].int()).int()
+        sizes.append(int(verts.numel()))
+    ctx.refine_kl(h, label, passes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out, gain = ctx.refine_kl(h, label, passes)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    pins = h.pins.view(-1, 2).long()
+    la, lb = label[pins[:, 0]], label[pins[:, 1]]
+    same = (la >= 0) & (lb >= 0) & ((la >> 1) == (lb >> 1))
+    cut0 = int((same & (la != lb)).sum().item())
+    return {"ms": 1e3 * dt, "passes": passes, "bisections": len(sizes), "mean_vertices": sum(sizes) / max(len(sizes), 1),
+            "cut_before": cut0, "cut_reduction": int(gain.sum().item()),
+            "what": "Kernighan-Lin passes on the 2-means bisection of every leaf block of the V+O result, "
+                    "all bisections in one launch"}
 
 
 def bench_lu_pipeline(ctx, g, rowptr, col, lp, steps):

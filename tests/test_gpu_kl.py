@@ -165,3 +165,18 @@ def test_kl_rejects(ctx):
         ctx.refine_kl(dev_h(h3), dlabel([0, 1, 0, 1]), 1)
     got, gain = ctx.refine_kl(dev_h(h), dlabel([-1, -1, -1, -1]), 3)
     assert host(got).tolist() == [-1] * 4 and host(gain).size == 0
+
+
+def test_kl_large_bisection_in_device_memory(ctx):
+    """A bisection above 9,216 vertices keeps its state in device memory
+    instead of LDS: a 110 x 110 grid, random sides, two passes; side sizes
+    kept and the gain equal to the recounted cut reduction."""
+    side = 110
+    g = vmo_gen.grid2d(side)
+    h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
+    label = vmo_gen.rng(3, 4).integers(0, 2, size=g.m).astype(np.int32)
+    got, gain = ctx.refine_kl(dev_h(h), dlabel(label), 2)
+    out, gain = host(got), host(gain)
+    edges = h.pins.reshape(-1, 2).astype(np.int64)
+    assert int(gain[0]) == int(cut_of(edges, label, 1)[0] - cut_of(edges, out, 1)[0]) > 0
+    assert int((out == 1).sum()) == int((label == 1).sum())
