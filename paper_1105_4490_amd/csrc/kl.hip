@@ -342,6 +342,7 @@ void refine_kl(Ctx& c, const vmo_hypergraph* h, int32_t* label, int32_t passes, 
   VMO_LAUNCH(k_kl_labels, ksz(k), 256, 0, s, label, k, bad.p, gm.p);
   VMO_REQUIRE(read1(bad.p, s) == 0, "labels must be -1 or 2 * bisection + side");
   const int32_t G = read1(gm.p, s) + 1;
+  VMO_REQUIRE(G <= k, "bisection indices must be below k (labels below 2k)");
   if (ngroups) *ngroups = G;
   if (G == 0 || passes == 0) {
     if (gain && G > 0) fill_i64(gain, 0, G, s);
