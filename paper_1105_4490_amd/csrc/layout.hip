@@ -818,7 +818,10 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
   int32_t* dpos = tsum + 64;   // [17]
   if (t < 17) dcnt[t] = 0;
   __syncthreads();
-  for (int32_t tn = t; tn < n; tn += kSTB) atomicAdd(&dcnt[nd.t[tn].b.w & 255], 1);
+  for (int32_t tn = t; tn < n; tn += kSTB) {
+    const int w = nd.t[tn].b.w;
+    if (!((w >> 8) & 1)) atomicAdd(&dcnt[w & 255], 1);  // internal nodes only
+  }
   __syncthreads();
   if (t == 0) {
     int acc = 0;
@@ -830,9 +833,17 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     doff[17] = acc;
   }
   __syncthreads();
+  // Trees of up to kQLds nodes keep the depth lists and the FP64 charges in
+  // LDS (the keys' and the sort counts' space is free from here), so a depth
+  // of the bottom-up pass reads its children's charges from LDS
+  constexpr int32_t kQLds = 1024;
+  const bool qlds = n <= kQLds;
+  int32_t* ctr = qlds ? base : nd.ctr;                        // the depth lists of internal nodes
+  double* qW = reinterpret_cast<double*>(&cnt[0][0][0]);     // [n]
+  double* qS = reinterpret_cast<double*>(key);                // [n][4]
   for (int32_t tn = t; tn < n; tn += kSTB) {
-    const int L = nd.t[tn].b.w & 255;
-    nd.ctr[atomicAdd(&dpos[L], 1)] = tn;  // ctr: the depth lists (this build only)
+    const int w = nd.t[tn].b.w;
+    if (!((w >> 8) & 1)) ctr[atomicAdd(&dpos[w & 255], 1)] = tn;
   }
   __syncthreads();
   // charges (same sums and order as k_tree_moments): every leaf first, then
@@ -843,15 +854,34 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
     leaf_sums(b.y, b.z, k, xs, ws, Wd, Sd);
     node_finish(nd, tn, Wd, Sd);
+    if (qlds) {
+      qW[tn] = Wd;
+      for (int d = 0; d < 4; ++d) qS[4 * tn + d] = Sd[d];
+    }
   }
   __syncthreads();
   for (int L = 16; L >= 0; --L) {
     if (doff[L] == doff[L + 1]) continue;  // uniform: doff is in LDS
     for (int32_t e = doff[L] + t; e < doff[L + 1]; e += kSTB) {
-      const int32_t tn = nd.ctr[e];
-      if ((nd.t[tn].b.w >> 8) & 1) continue;
+      const int32_t tn = ctr[e];
+      const int32_t nc = nd.nch[tn];
       double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
-      child_sums(nd, tn, nd.nch[tn], Wd, Sd);
+      if (qlds) {
+        // children in child order, as child_sums, from LDS
+        const int4* cq = reinterpret_cast<const int4*>(nd.cid + 16 * (int64_t)tn);
+        for (int32_t r0 = 0; r0 < nc; r0 += 4) {
+          const int4 c4 = cq[r0 >> 2];
+          const int32_t cc[4] = {c4.x, c4.y, c4.z, c4.w};
+          for (int u = 0; u < 4 && r0 + u < nc; ++u) {
+            Wd += qW[cc[u]];
+            for (int d = 0; d < 4; ++d) Sd[d] += qS[4 * cc[u] + d];
+          }
+        }
+        qW[tn] = Wd;
+        for (int d = 0; d < 4; ++d) qS[4 * tn + d] = Sd[d];
+      } else {
+        child_sums(nd, tn, nc, Wd, Sd);
+      }
       node_finish(nd, tn, Wd, Sd);
     }
     __syncthreads();
