@@ -18,7 +18,9 @@ def declared():
 def test_header_declares_the_boundary():
     names = declared()
     for want in ["vmo_create", "vmo_destroy", "vmo_layout", "vmo_bisect", "vmo_order_sbd", "vmo_order_bbd",
-                 "vmo_cut", "vmo_order_batch", "vmo_dual", "vmo_model", "vmo_components"]:
+                 "vmo_cut", "vmo_order_batch", "vmo_dual", "vmo_model", "vmo_components", "vmo_order_border",
+                 "vmo_order_schur", "vmo_match", "vmo_order_matched", "vmo_matched_perms", "vmo_finegrain",
+                 "vmo_refine_kl"]:
         assert want in names
 
 
