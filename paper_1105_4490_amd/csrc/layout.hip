@@ -196,6 +196,36 @@ __device__ int32_t node_end(const uint64_t* key, int32_t k, int32_t i, int L) {
 // interval of equal L-digit prefixes around i) has <= cap points, else 16.  A
 // run of <= cap points lies inside [i-cap+1, i+cap].  Nodes beginning at i
 // have depths cpl[i]+1 .. leaf depth.
+// Leaf depth of position i (cap <= 16): the smallest L at which the depth-L
+// cell holding i has at most cap points.  The cell at depth L is bounded by
+// the nearest positions with cpl < L on each side; with ml(u) the minimum of
+// cpl over [i - u, i] and mr(v) that over [i + 1, i + 1 + v] (both
+// non-increasing), the cell fits when ml(u) < L and mr(v) < L for some
+// u + v + 1 <= cap, so L = min over u of max(ml(u), mr(cap - 1 - u)) + 1
+// (positions outside [lo, hi] left out), at most 16.  One pass each way.
+template <class CplAt>
+__device__ __forceinline__ int leaf_depth16(CplAt cpl_at, int32_t i, int32_t lo, int32_t hi, int32_t cap) {
+  int r[16];
+  int run = 127;
+#pragma unroll
+  for (int uu = 15; uu >= 0; --uu) {
+    if (uu < cap) {
+      const int32_t p = i + cap - uu;
+      if (p <= hi) run = min(run, (int)cpl_at(p));
+    }
+    r[uu] = run;
+  }
+  int L = 127, runl = 127;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    if (u < cap && i - u >= lo) {
+      runl = min(runl, (int)cpl_at(i - u));
+      L = min(L, max(runl, r[u]) + 1);
+    }
+  }
+  return L > 16 ? 16 : L;
+}
+
 __global__ void k_tree_ell(const int8_t* cpl, int32_t k, int32_t cap, int8_t* ell, int32_t* nn) {
   GRID_STRIDE(i64, (int64_t)k + 1) {
     int32_t i = (int32_t)i64;
@@ -203,15 +233,19 @@ __global__ void k_tree_ell(const int8_t* cpl, int32_t k, int32_t cap, int8_t* el
     int lo = i - cap + 1 < 0 ? 0 : i - cap + 1;
     int hi = i + cap > k ? k : i + cap;
     int L = 0;
-    for (; L <= 16; ++L) {
-      int b = -1, e = -1;
-      for (int j = i; j >= lo; --j)
-        if (cpl[j] < L) { b = j; break; }
-      for (int j = i + 1; j <= hi; ++j)
-        if (cpl[j] < L) { e = j; break; }
-      if (b >= 0 && e >= 0 && e - b <= cap) break;
+    if (cap <= 16) {
+      L = leaf_depth16([&](int32_t p) { return cpl[p]; }, i, lo, hi, cap);
+    } else {
+      for (; L <= 16; ++L) {
+        int b = -1, e = -1;
+        for (int j = i; j >= lo; --j)
+          if (cpl[j] < L) { b = j; break; }
+        for (int j = i + 1; j <= hi; ++j)
+          if (cpl[j] < L) { e = j; break; }
+        if (b >= 0 && e >= 0 && e - b <= cap) break;
+      }
+      if (L > 16) L = 16;
     }
-    if (L > 16) L = 16;
     ell[i] = (int8_t)L;
     int ci = cpl[i];
     nn[i] = L >= ci + 1 ? L - ci : 0;
@@ -676,23 +710,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     const int hi = i + cap > k ? k : i + cap;
     int L = 0;
     if (cap <= 16) {
-      // the window's common-prefix lengths in registers: cl[u] = cpl[i - u],
-      // cr[u] = cpl[i + 1 + u] (127 outside the window)
-      int cl[16], cr[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        cl[u] = (u < cap && i - u >= lo) ? cpl[i - u] : 127;
-        cr[u] = (u < cap && i + 1 + u <= hi) ? cpl[i + 1 + u] : 127;
-      }
-      for (; L <= 16; ++L) {
-        int bu = 99, eu = 99;
-#pragma unroll
-        for (int u = 15; u >= 0; --u) {
-          if (cl[u] < L) bu = u;
-          if (cr[u] < L) eu = u;
-        }
-        if (bu != 99 && eu != 99 && eu + 1 + bu <= cap) break;
-      }
+      L = leaf_depth16([&](int32_t p) { return cpl[p]; }, i, lo, hi, cap);
     } else {
       for (; L <= 16; ++L) {
         int b = -1, e = -1;
