@@ -167,9 +167,15 @@ def main():
         "cpu_baseline": cpu,
     }
     if not args.path_only:
-        h = ctx.model(P.SYMMETRIC, g.m, g.n, rowptr, col)
-        line.update(order_only_and_border(ctx, h, g, lp, o, args.steps))
-        line.update(bench_lu_pipeline(ctx, g, rowptr, col, lp, 2))
+        # the further rows of the method; a failure there is reported in the
+        # line, which the step's measurement above does not depend on
+        try:
+            h = ctx.model(P.SYMMETRIC, g.m, g.n, rowptr, col)
+            line.update(order_only_and_border(ctx, h, g, lp, o, args.steps))
+            line.update(bench_lu_pipeline(ctx, g, rowptr, col, lp, 2))
+        except Exception as e:  # noqa: BLE001
+            line["extras_error"] = f"{type(e).__name__}: {e}"
+            print(f"bench: extra fields failed: {e}", file=sys.stderr, flush=True)
     print(json.dumps(line))
 
 
