@@ -1156,7 +1156,7 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // points of near leaves through a second window of kWin consecutive points:
 // the walk meets leaves in tree order, so one refill serves several leaves.
 constexpr int kWin = 32;
-constexpr int kWT = 256;    // threads per block of the walk
+constexpr int kWT = 64;     // threads per block of the walk: one wavefront (measured best of 64-512)
 constexpr int kCntSlots = 256;  // interaction counters of the walk (16 words apart)
 
 template <bool kCount>  // kCount: count the interactions into nint
