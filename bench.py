@@ -41,7 +41,7 @@ FLOPS_PER_INTERACTION = 23   # 4 sub, r^2 (1 mul + 3 fma), 2 mul (2 W w), 1 mul 
 # HBM bytes per walk launch (average over one step of this workload), from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
 # plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
-WALK_TRAFFIC_BYTES = 78.40e6 + 17.94e6
+WALK_TRAFFIC_BYTES = 88.23e6 + 18.68e6
 PEAK_FP32_VALU_TFLOPS = 157.3
 # live timing brackets every PROFILE_EVERY-th launch of a kernel with HIP
 # events: an event pair costs about 13 us of stream time, 2.5 % of a step when
