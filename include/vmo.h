@@ -423,12 +423,14 @@ vmo_status vmo_serve_destroy(vmo_server s);
  * count of timed launches and their algorithmic work.  vmo_profile(ctx, n):
  * n = 0 disables; n >= 1 times every n-th launch of each kernel name (n = 1:
  * every launch; a larger n keeps the events' own cost, tens of microseconds
- * of stream time per timed launch, off most launches).  Kernels:
+ * of stream time per timed launch, off most launches); n <= -1 times every
+ * |n|-th launch without the work the kernels count on the device (the walk
+ * then runs its uncounted form and reports work 0).  Kernels:
  *   "walk"   tree walk of the layout; work = charge interactions evaluated
  *            (counted by the kernel);
  *   "assign" Lloyd assignment pass; work = bytes of the positions it scans
  *            (16 B of grid coordinates + 1 B side each).
- * Enabling adds one atomic per wavefront to the walk.  Disabling clears the
+ * Counting adds one atomic per wavefront to the walk.  Disabling clears the
  * totals.  vmo_profile_read of a name never launched returns zeros.
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -436,7 +438,7 @@ typedef struct {
   int64_t launches;
   double work;
 } vmo_profile_entry;
-vmo_status vmo_profile(vmo_ctx ctx, int every /* 0: off; n >= 1: every n-th launch */);
+vmo_status vmo_profile(vmo_ctx ctx, int every /* 0: off; n >= 1: every n-th launch; -n: uncounted */);
 vmo_status vmo_profile_read(vmo_ctx ctx, const char* kernel, vmo_profile_entry* out /* (host) */);
 vmo_status vmo_profile_reset(vmo_ctx ctx);
 

@@ -189,10 +189,13 @@ class Context:
     def pool_bytes(self) -> int:
         return int(lib().vmo_pool_bytes(self.h))
 
-    def profile(self, enable, every: int = 1):
+    def profile(self, enable, every: int = 1, count: bool = True):
         """Live kernel timing with HIP events on the launch stream: off when
-        enable is false, else every `every`-th launch of each kernel is timed."""
-        self._check(lib().vmo_profile(self.h, C.c_int(int(every) if enable else 0)))
+        enable is false, else every `every`-th launch of each kernel is timed;
+        count=False leaves out the work the kernels count on the device (the
+        walk runs uncounted)."""
+        n = int(every) if count else -int(every)
+        self._check(lib().vmo_profile(self.h, C.c_int(n if enable else 0)))
 
     def profile_reset(self):
         self._check(lib().vmo_profile_reset(self.h))

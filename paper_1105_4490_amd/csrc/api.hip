@@ -1,5 +1,7 @@
 // C ABI of include/vmo.h: argument checks, context handling, and dispatch to
 // the device code.  No exception crosses this boundary.
+#include <climits>
+
 #include "order_engine.h"
 
 struct vmo_ctx_s : vmo::Ctx {};
@@ -374,9 +376,10 @@ vmo_status vmo_layout_steps(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layo
 }
 
 vmo_status vmo_profile(vmo_ctx ctx, int every) {
-  if (!ctx || every < 0) return VMO_E_INVALID;
+  if (!ctx || every == INT_MIN) return VMO_E_INVALID;
   ctx->prof.on = every != 0;
-  ctx->prof.every = every > 0 ? every : 1;
+  ctx->prof.every = every > 0 ? every : (every < 0 ? -every : 1);
+  ctx->prof.count = every >= 0;
   ctx->prof.seen.clear();
   if (!every) {
     vmo::prof_discard(*ctx);

@@ -172,7 +172,7 @@ int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned lo
   p.name = name;
   p.work = work;
   p.dslot = -1;
-  if (dwork) {
+  if (dwork && c.prof.count) {
     if (c.prof.nslot == c.prof.cap) {
       VMO_HIP(hipStreamSynchronize(s));
       prof_flush(c);

@@ -104,6 +104,7 @@ struct ProfPending {
 struct Prof {
   bool on = false;
   int every = 1;                          // time every n-th launch of a name
+  bool count = true;                      // kernels count their work on the device
   std::map<std::string, int64_t> seen;    // launches per name since enabled
   std::map<std::string, ProfAcc> acc;
   std::vector<ProfPending> pend;

@@ -126,6 +126,15 @@ def test_profile_times_every_nth_walk(ctx):
     assert full["launches"] == 6 and part["launches"] == 2
     assert 0 < part["work"] < full["work"] and part["total_ms"] > 0
     assert np.array_equal(res[1][1], res[3][1])
+    # uncounted timing: the same launches timed, no work counted, same steps
+    ctx.profile(True, every=3, count=False)
+    ctx.profile_reset()
+    gx = dev_x(x0)
+    ctx.layout_steps(dh, gx, gp, 0, 6, 0.0)
+    unc = ctx.profile_read("walk")
+    ctx.profile(False)
+    assert unc["launches"] == 2 and unc["work"] == 0 and unc["total_ms"] > 0
+    assert np.array_equal(host(gx), res[1][1])
 
 
 @pytest.mark.parametrize("case", ["random", "grid3d", "star", "weighted"])
