@@ -63,6 +63,22 @@ Pool::~Pool() {
 }
 
 // --------------------------------------------------------------- profile ----
+namespace {
+// The pinned scalar buffer of a host thread, released when the thread ends.
+struct PinnedScratch {
+  void* p = nullptr;
+  ~PinnedScratch() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local PinnedScratch t_pinned;
+}  // namespace
+
+void* pinned_scratch() {
+  if (!t_pinned.p) VMO_HIP(hipHostMalloc(&t_pinned.p, 64, hipHostMallocDefault));
+  return t_pinned.p;
+}
+
 Ctx::~Ctx() {
   prof_discard(*this);
   for (hipEvent_t e : prof.spare) (void)hipEventDestroy(e);

@@ -177,13 +177,18 @@ void prof_restart(Ctx& c, int h, hipStream_t s);  // records the start event of 
 void prof_flush(Ctx& c);
 void prof_discard(Ctx& c);
 
-// Device scalar readback (synchronises `s`).
+// Device scalar readback (synchronises `s`).  The value lands in a small
+// pinned host buffer of the calling thread (allocated once): a copy into
+// pageable memory goes through the runtime's staging path, which costs tens
+// of microseconds more per read.
+void* pinned_scratch();  // 64 bytes of pinned host memory per host thread
 template <class T>
 T read1(const T* dptr, hipStream_t s) {
-  T v;
-  VMO_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  static_assert(sizeof(T) <= 64, "read1 reads one scalar");
+  T* h = static_cast<T*>(pinned_scratch());
+  VMO_HIP(hipMemcpyAsync(h, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
   VMO_HIP(hipStreamSynchronize(s));
-  return v;
+  return *h;
 }
 
 inline unsigned nblocks(int64_t n, int per) {
