@@ -129,8 +129,7 @@ void cut(Ctx& c, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, d
     VMO_LAUNCH(k_part_weight, gsz(h->k), kCT, 0, s, part, h->w, h->k, nparts, part_weight);
   }
   double r[3];
-  VMO_HIP(hipMemcpyAsync(r, o3.p, sizeof r, hipMemcpyDeviceToHost, s));
-  VMO_HIP(hipStreamSynchronize(s));
+  read_bytes(r, o3.p, sizeof r, s);
   out->lambda_minus_one = r[0];
   out->cut_net = r[1];
   out->nets_cut = (int64_t)r[2];

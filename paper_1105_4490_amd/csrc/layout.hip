@@ -91,8 +91,7 @@ static void box_of(const float* x, int32_t k, uint32_t* dbox, hipStream_t s) {
 }
 static HostBox read_box(const uint32_t* dbox, hipStream_t s) {
   uint32_t b[8];
-  VMO_HIP(hipMemcpyAsync(b, dbox, sizeof b, hipMemcpyDeviceToHost, s));
-  VMO_HIP(hipStreamSynchronize(s));
+  read_bytes(b, dbox, sizeof b, s);
   HostBox h;
   for (int d = 0; d < 4; ++d) { h.lo[d] = fkey_inv(b[d]); h.hi[d] = fkey_inv(b[4 + d]); }
   return h;
@@ -1887,6 +1886,19 @@ __global__ void k_net_comp(const int64_t* ptr, const int32_t* pins, int32_t l, c
     val[e] = (int32_t)e;
   }
 }
+// start[g] = the first position of the ascending keys with key >= g, for
+// g = 0..G (keys below G; start[G] = n).
+__global__ void k_sorted_starts(const uint32_t* key, int64_t n, uint32_t G, int64_t* start) {
+  GRID_STRIDE(i, n + 1) {
+    const uint32_t cur = i < n ? key[i] : G;
+    const uint32_t from = i > 0 ? key[i - 1] + 1 : 0u;
+    for (uint32_t g = from; g <= cur; ++g) start[g] = i;
+  }
+}
+// The label of component c: its smallest vertex id (the first in id order).
+__global__ void k_comp_label(const int32_t* vorder, const int32_t* cstart, int32_t ncomp, int32_t* lab) {
+  GRID_STRIDE(c, ncomp) lab[c] = vorder[cstart[c]];
+}
 __global__ void k_net_len(const int64_t* ptr, const int32_t* order, int32_t l, int64_t* len) {
   GRID_STRIDE(t, l) len[t] = ptr[order[t] + 1] - ptr[order[t]];
 }
@@ -2010,15 +2022,13 @@ void layout(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, float* 
   VMO_LAUNCH(k_comp_index, gsz(k), kLT, 0, s, vorder.p, cscan.p, cflag.p, k, comp_of.p, cstart.p);
   VMO_LAUNCH(k_local_id, gsz(k), kLT, 0, s, vorder.p, comp_of.p, cstart.p, k, loc.p);
   std::vector<int32_t> hstart(ncomp + 1), hlabel(ncomp);
-  VMO_HIP(hipMemcpyAsync(hstart.data(), cstart.p, 4 * (size_t)ncomp, hipMemcpyDeviceToHost, s));
-  VMO_HIP(hipStreamSynchronize(s));
-  hstart[ncomp] = k;
   {
-    std::vector<int32_t> hv(k);
-    VMO_HIP(hipMemcpyAsync(hv.data(), vorder.p, 4 * (size_t)k, hipMemcpyDeviceToHost, s));
-    VMO_HIP(hipStreamSynchronize(s));
-    for (int32_t c = 0; c < ncomp; ++c) hlabel[c] = hv[hstart[c]];  // smallest id of the component
+    Buf<int32_t> lab(C.pool, ncomp);
+    VMO_LAUNCH(k_comp_label, gsz(ncomp), kLT, 0, s, vorder.p, cstart.p, ncomp, lab.p);
+    read_bytes(hstart.data(), cstart.p, 4 * (size_t)ncomp, s);
+    read_bytes(hlabel.data(), lab.p, 4 * (size_t)ncomp, s);
   }
+  hstart[ncomp] = k;
   // nets grouped by component, local pins
   Buf<uint32_t> nkey(C.pool, l > 0 ? l : 1);
   Buf<int32_t> norder(C.pool, l > 0 ? l : 1);
@@ -2035,12 +2045,11 @@ void layout(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, float* 
     int64_t np = read1(optr.p + l, s);
     opins = Buf<int32_t>(C.pool, np > 0 ? np : 1);
     VMO_LAUNCH(k_net_fill, gsz(l), kLT, 0, s, h->net_ptr, h->pins, norder.p, optr.p, loc.p, h->c, l, opins.p, oc.p);
-    std::vector<uint32_t> hk(l);
-    VMO_HIP(hipMemcpyAsync(hk.data(), nkey.p, 4 * (size_t)l, hipMemcpyDeviceToHost, s));
-    VMO_HIP(hipStreamSynchronize(s));
-    std::vector<int64_t> cnt(ncomp + 1, 0);
-    for (int32_t e = 0; e < l; ++e) cnt[hk[e]]++;
-    for (int32_t c = 0; c <= ncomp; ++c) hnstart[c + 1] = hnstart[c] + cnt[c];
+    // nets of component c: [hnstart[c], hnstart[c + 1]) of the sorted keys
+    // (key ncomp: the empty nets, last)
+    Buf<int64_t> nst(C.pool, (size_t)ncomp + 2);
+    VMO_LAUNCH(k_sorted_starts, gsz((int64_t)l + 1), kLT, 0, s, nkey.p, (int64_t)l, (uint32_t)ncomp + 1, nst.p);
+    read_bytes(hnstart.data(), nst.p, 8 * ((size_t)ncomp + 2), s);
   } else {
     opins = Buf<int32_t>(C.pool, 1);
     fill_i64(optr.p, 0, 1, s);

@@ -1358,8 +1358,7 @@ void Engine::arena_admit(int32_t slot, const JobHost& H, int64_t voff, int64_t n
   VMO_LAUNCH(k_bbox, nblocks(D.k, kT), kT, 0, s, one.p, 1, H.x, (int64_t)D.k, (int64_t)D.k, box.p);
   VMO_LAUNCH(k_job_scale, 1, 64, 0, s, one.p, 1, box.p);
   VMO_LAUNCH(k_quantize_range, gsz(D.k), kT, 0, s, one.p, H.x, D.k, voff, Np, q.p, id.p, pos.p);
-  VMO_HIP(hipMemcpyAsync(&D, one.p, sizeof D, hipMemcpyDeviceToHost, s));
-  VMO_HIP(hipStreamSynchronize(s));
+  read_bytes(&D, one.p, sizeof D, s);
   D.voff = voff;
   hj[slot] = D;
   VMO_HIP(hipMemcpyAsync(dj.p + slot, &D, sizeof D, hipMemcpyHostToDevice, s));

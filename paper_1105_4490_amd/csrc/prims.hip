@@ -75,7 +75,7 @@ thread_local PinnedScratch t_pinned;
 }  // namespace
 
 void* pinned_scratch() {
-  if (!t_pinned.p) VMO_HIP(hipHostMalloc(&t_pinned.p, 64, hipHostMallocDefault));
+  if (!t_pinned.p) VMO_HIP(hipHostMalloc(&t_pinned.p, kPinnedBytes, hipHostMallocDefault));
   return t_pinned.p;
 }
 
@@ -479,9 +479,7 @@ int* device_flag(Ctx& c) {
 
 void check_device_flag(Ctx& c, hipStream_t s) {
   if (!c.dflag) return;
-  int v = 0;
-  VMO_HIP(hipMemcpyAsync(&v, c.dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-  VMO_HIP(hipStreamSynchronize(s));
+  const int v = read1(c.dflag, s);
   if (v) {
     VMO_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int), s));
     VMO_HIP(hipStreamSynchronize(s));
@@ -726,9 +724,8 @@ void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_
   if (tot > 0) VMO_LAUNCH(k_check_ptr_all, gs_blocks(tot), 256, 0, s, dj.p, cum.p, nj, tot, bad.p);
   VMO_LAUNCH(k_net_ends_all, (unsigned)((nj + 255) / 256), 256, 0, s, dj.p, nj, ends.p);
   std::vector<int> hb(nj);
-  VMO_HIP(hipMemcpyAsync(hb.data(), bad.p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
-  VMO_HIP(hipMemcpyAsync(npins.data(), ends.p, sizeof(int64_t) * nj, hipMemcpyDeviceToHost, s));
-  VMO_HIP(hipStreamSynchronize(s));
+  read_bytes(hb.data(), bad.p, sizeof(int) * nj, s);
+  read_bytes(npins.data(), ends.p, sizeof(int64_t) * nj, s);
   for (int32_t j = 0; j < nj; ++j) {
     const std::string who = nj > 1 ? "job " + std::to_string(j) + ": " : "";
     VMO_REQUIRE(hb[j] == 0, who + "net_ptr must start at 0 and be non-decreasing");
@@ -752,8 +749,7 @@ void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_
   if (t2 > 0) VMO_LAUNCH(k_check_pins_all, gs_blocks(t2), 256, 0, s, dj.p, cum2.p, nj, t2, bad.p);
   VMO_LAUNCH(k_check_vertices_all, gs_blocks(t3), 256, 0, s, dj.p, cum3.p, nj, t3, bad.p);
   VMO_LAUNCH(k_check_nets_all, gs_blocks(t4), 256, 0, s, dj.p, cum4.p, nj, t4, bad.p);
-  VMO_HIP(hipMemcpyAsync(hb.data(), bad.p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
-  VMO_HIP(hipStreamSynchronize(s));
+  read_bytes(hb.data(), bad.p, sizeof(int) * nj, s);
   for (int32_t j = 0; j < nj; ++j) {
     const std::string who = nj > 1 ? "job " + std::to_string(j) + ": " : "";
     const int b = hb[j];

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <stdexcept>
@@ -181,14 +182,29 @@ void prof_discard(Ctx& c);
 // pinned host buffer of the calling thread (allocated once): a copy into
 // pageable memory goes through the runtime's staging path, which costs tens
 // of microseconds more per read.
-void* pinned_scratch();  // 64 bytes of pinned host memory per host thread
+constexpr size_t kPinnedBytes = 4096;
+void* pinned_scratch();  // kPinnedBytes of pinned host memory per host thread
 template <class T>
 T read1(const T* dptr, hipStream_t s) {
-  static_assert(sizeof(T) <= 64, "read1 reads one scalar");
+  static_assert(sizeof(T) <= kPinnedBytes, "read1 reads one scalar");
   T* h = static_cast<T*>(pinned_scratch());
   VMO_HIP(hipMemcpyAsync(h, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
   VMO_HIP(hipStreamSynchronize(s));
   return *h;
+}
+// n bytes from the device into host memory dst, through the pinned buffer
+// when they fit (synchronises `s`).
+inline void read_bytes(void* dst, const void* src, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  if (n <= kPinnedBytes) {
+    void* h = pinned_scratch();
+    VMO_HIP(hipMemcpyAsync(h, src, n, hipMemcpyDeviceToHost, s));
+    VMO_HIP(hipStreamSynchronize(s));
+    std::memcpy(dst, h, n);
+  } else {
+    VMO_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s));
+    VMO_HIP(hipStreamSynchronize(s));
+  }
 }
 
 inline unsigned nblocks(int64_t n, int per) {
