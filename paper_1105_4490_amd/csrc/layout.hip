@@ -1606,7 +1606,9 @@ __global__ void k_count_i32(const int32_t* idx, int64_t n, int64_t* cnt) {
   GRID_STRIDE(i, n) atomicAdd((unsigned long long*)&cnt[idx[i]], 1ull);
 }
 // Coarse weight = member weights summed in ascending member id.
-__global__ void k_coarse_w(const int64_t* gstart, const int32_t* members, const float* w, int32_t kc, float* cw) {
+__global__ void k_coarse_w(const int64_t* gstart, const int32_t* members, const float* w, const int32_t* kc_dev,
+                           float* cw) {
+  const int32_t kc = *kc_dev;
   GRID_STRIDE(g, kc) {
     float a = 0.0f;
     for (int64_t t = gstart[g]; t < gstart[g + 1]; ++t) a = a + (w ? w[members[t]] : 1.0f);
@@ -1642,8 +1644,17 @@ __global__ void k_img_pins(const uint64_t* key, const int32_t* ufl, const int32_
     ipins[iptr[kidx[e]] + r] = (int32_t)(key[p] & 0xffffffffu);
   }
 }
-__global__ void k_img_hash(const int64_t* iptr, const int32_t* ipins, int32_t nk, uint64_t* hs, int32_t* val) {
-  GRID_STRIDE(i, nk) {
+// (entries nk..cap-1 get the largest key, which a stable sort leaves after
+// every image)
+__global__ void k_img_hash(const int64_t* iptr, const int32_t* ipins, const int32_t* nk_dev, int32_t cap, uint64_t* hs,
+                           int32_t* val) {
+  const int32_t nk = *nk_dev;
+  GRID_STRIDE(i, cap) {
+    if (i >= nk) {
+      hs[i] = ~0ull;
+      val[i] = (int32_t)i;
+      continue;
+    }
     uint64_t h = 0x5851F42D4C957F2DULL;
     for (int64_t p = iptr[i]; p < iptr[i + 1]; ++p) h = sm_mix(h + kGamma * ((uint64_t)(uint32_t)ipins[p] + 1));
     hs[i] = sm_mix(h + (uint64_t)(iptr[i + 1] - iptr[i]));
@@ -1659,8 +1670,9 @@ __device__ bool img_equal(const int64_t* iptr, const int32_t* ipins, int32_t a, 
 }
 // Representative of each kept net: the first net (in net order) of its run of
 // equal hashes with the same image.
-__global__ void k_img_rep(const uint64_t* hs, const int32_t* val, const int64_t* iptr, const int32_t* ipins, int32_t nk,
-                          int32_t* repflag, int32_t* reppos) {
+__global__ void k_img_rep(const uint64_t* hs, const int32_t* val, const int64_t* iptr, const int32_t* ipins,
+                          const int32_t* nk_dev, int32_t* repflag, int32_t* reppos) {
+  const int32_t nk = *nk_dev;
   GRID_STRIDE(i, nk) {
     int32_t me = val[i];
     int64_t r = i;
@@ -1672,8 +1684,9 @@ __global__ void k_img_rep(const uint64_t* hs, const int32_t* val, const int64_t*
 }
 // Merged cost (members in ascending net order) and length of each coarse net.
 __global__ void k_img_cost(const uint64_t* hs, const int32_t* val, const int32_t* reppos, const int32_t* kept_net,
-                           const float* c, const int64_t* iptr, const int32_t* cidx, int32_t nk, float* cc,
+                           const float* c, const int64_t* iptr, const int32_t* cidx, const int32_t* nk_dev, float* cc,
                            int64_t* clen) {
+  const int32_t nk = *nk_dev;
   GRID_STRIDE(i, nk) {
     if (reppos[i] != i) continue;
     int32_t me = val[i];
@@ -1688,7 +1701,8 @@ __global__ void k_kept_net(const int32_t* kf, const int32_t* kidx, int32_t l, in
   GRID_STRIDE(e, l) if (kf[e]) kept_net[kidx[e]] = (int32_t)e;
 }
 __global__ void k_coarse_pins(const int32_t* repflag, const int32_t* cidx, const int64_t* iptr, const int32_t* ipins,
-                              const int64_t* cptr, int32_t nk, int32_t* cpins) {
+                              const int64_t* cptr, const int32_t* nk_dev, int32_t* cpins) {
+  const int32_t nk = *nk_dev;
   GRID_STRIDE(i, nk) {
     if (!repflag[i]) continue;
     int64_t o = cptr[cidx[i]];
@@ -1696,7 +1710,18 @@ __global__ void k_coarse_pins(const int32_t* repflag, const int32_t* cidx, const
   }
 }
 
-// One coarsening step of level F into C (pi written to F.pi).
+// The sizes of a coarse level, read back once at its end.
+__global__ void k_coarse_sizes(const int32_t* kc, const int32_t* lc, const int64_t* cnp, int64_t* out) {
+  out[0] = *kc;
+  out[1] = lc ? *lc : 0;
+  out[2] = cnp ? *cnp : 0;
+}
+
+// One coarsening step of level F into C (pi written to F.pi).  The counts of
+// the coarse level (vertices, kept nets, image pins, coarse nets and pins)
+// stay on the device until the end: buffers take their upper bounds (the fine
+// level's sizes) and the kernels read the counts from device memory, so the
+// step waits for the device once after the matching.
 static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t comp, int32_t level, int32_t mm,
                           hipStream_t s) {
   int32_t k = F.k, l = F.l;
@@ -1725,24 +1750,24 @@ static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t 
   VMO_LAUNCH(k_group_min, gsz(k), kLT, 0, s, root.p, k, gmin.p);
   VMO_LAUNCH(k_group_flag, gsz(k), kLT, 0, s, root.p, gmin.p, k, flag.p);
   scan_exclusive<int32_t>(Cx, flag.p, rank.p, k, rank.p + k, s);
-  int32_t kc = read1(rank.p + k, s);
+  const int32_t* kc_dev = rank.p + k;  // coarse vertices (groups)
   F.pi = Buf<int32_t>(Cx.pool, k);
   Buf<uint32_t> gkey(Cx.pool, k);
   Buf<int32_t> members(Cx.pool, k);
   VMO_LAUNCH(k_group_pi, gsz(k), kLT, 0, s, root.p, gmin.p, rank.p, k, F.pi.p, gkey.p);
   iota_i32(members.p, k, s);
-  radix_sort<uint32_t>(Cx, gkey.p, members.p, k, bits_for((uint64_t)(kc > 0 ? kc - 1 : 0)), s);
-  Buf<int64_t> gstart(Cx.pool, (size_t)kc + 1);
-  fill_i64(gstart.p, 0, (int64_t)kc + 1, s);
+  radix_sort<uint32_t>(Cx, gkey.p, members.p, k, bits_for((uint64_t)(k - 1)), s);
+  Buf<int64_t> gstart(Cx.pool, (size_t)k + 1);
+  fill_i64(gstart.p, 0, (int64_t)k + 1, s);
   VMO_LAUNCH(k_count_i32, gsz(k), kLT, 0, s, F.pi.p, (int64_t)k, gstart.p);
-  scan_exclusive<int64_t>(Cx, gstart.p, gstart.p, kc, gstart.p + kc, s);
-  Cl.k = kc;
-  Cl.w = Buf<float>(Cx.pool, kc);
-  VMO_LAUNCH(k_coarse_w, gsz(kc), kLT, 0, s, gstart.p, members.p, F.w.p, kc, Cl.w.p);
+  scan_exclusive<int64_t>(Cx, gstart.p, gstart.p, k, gstart.p + k, s);
+  Cl.w = Buf<float>(Cx.pool, k);
+  VMO_LAUNCH(k_coarse_w, gsz(k), kLT, 0, s, gstart.p, members.p, F.w.p, kc_dev, Cl.w.p);
   // net images
-  int32_t lc = 0;
-  int64_t cnp = 0;
   Cl.ptr = Buf<int64_t>(Cx.pool, (size_t)(l > 0 ? l : 0) + 1);
+  const int32_t* lc_dev = nullptr;
+  const int64_t* cnp_dev = nullptr;
+  Buf<int32_t> cidx;
   if (l > 0 && np > 0) {
     Buf<uint64_t> key(Cx.pool, np);
     VMO_LAUNCH(k_img_keys, gsz(l), kLT, 0, s, F.ptr.p, F.pins.p, l, F.pi.p, key.p);
@@ -1755,40 +1780,47 @@ static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t 
     Buf<int32_t> kf(Cx.pool, (size_t)l + 1), kidx(Cx.pool, (size_t)l + 1);
     VMO_LAUNCH(k_img_keep, gsz(l), kLT, 0, s, ilen.p, l, kf.p);
     scan_exclusive<int32_t>(Cx, kf.p, kidx.p, l, kidx.p + l, s);
-    int32_t nk = read1(kidx.p + l, s);
-    if (nk > 0) {
-      Buf<int64_t> iptr(Cx.pool, (size_t)nk + 1);
-      VMO_LAUNCH(k_img_len, gsz(l), kLT, 0, s, ilen.p, kf.p, kidx.p, l, iptr.p);
-      scan_exclusive<int64_t>(Cx, iptr.p, iptr.p, nk, iptr.p + nk, s);
-      int64_t inp = read1(iptr.p + nk, s);
-      Buf<int32_t> ipins(Cx.pool, inp);
-      VMO_LAUNCH(k_img_pins, gsz(np), kLT, 0, s, key.p, ufl.p, uscan.p, F.ptr.p, kf.p, kidx.p, iptr.p, np, ipins.p);
-      Buf<uint64_t> hs(Cx.pool, nk);
-      Buf<int32_t> val(Cx.pool, nk), repflag(Cx.pool, (size_t)nk + 1), reppos(Cx.pool, nk), cidx(Cx.pool, (size_t)nk + 1);
-      Buf<int32_t> kept_net(Cx.pool, nk);
-      VMO_LAUNCH(k_kept_net, gsz(l), kLT, 0, s, kf.p, kidx.p, l, kept_net.p);
-      VMO_LAUNCH(k_img_hash, gsz(nk), kLT, 0, s, iptr.p, ipins.p, nk, hs.p, val.p);
-      radix_sort<uint64_t>(Cx, hs.p, val.p, nk, 64, s);
-      VMO_LAUNCH(k_img_rep, gsz(nk), kLT, 0, s, hs.p, val.p, iptr.p, ipins.p, nk, repflag.p, reppos.p);
-      scan_exclusive<int32_t>(Cx, repflag.p, cidx.p, nk, cidx.p + nk, s);
-      lc = read1(cidx.p + nk, s);
-      Cl.c = Buf<float>(Cx.pool, lc > 0 ? lc : 1);
-      Buf<int64_t> clen(Cx.pool, (size_t)lc + 1);
-      VMO_LAUNCH(k_img_cost, gsz(nk), kLT, 0, s, hs.p, val.p, reppos.p, kept_net.p, F.c.p, iptr.p, cidx.p, nk, Cl.c.p,
-                 clen.p);
-      scan_exclusive<int64_t>(Cx, clen.p, Cl.ptr.p, lc, Cl.ptr.p + lc, s);
-      cnp = read1(Cl.ptr.p + lc, s);
-      Cl.pins = Buf<int32_t>(Cx.pool, cnp > 0 ? cnp : 1);
-      VMO_LAUNCH(k_coarse_pins, gsz(nk), kLT, 0, s, repflag.p, cidx.p, iptr.p, ipins.p, Cl.ptr.p, nk, Cl.pins.p);
-    }
+    const int32_t* nk_dev = kidx.p + l;  // kept nets (images of at least two coarse vertices)
+    Buf<int64_t> iptr(Cx.pool, (size_t)l + 1);
+    fill_i64(iptr.p, 0, (int64_t)l + 1, s);
+    VMO_LAUNCH(k_img_len, gsz(l), kLT, 0, s, ilen.p, kf.p, kidx.p, l, iptr.p);
+    scan_exclusive<int64_t>(Cx, iptr.p, iptr.p, l, iptr.p + l, s);
+    Buf<int32_t> ipins(Cx.pool, np);
+    VMO_LAUNCH(k_img_pins, gsz(np), kLT, 0, s, key.p, ufl.p, uscan.p, F.ptr.p, kf.p, kidx.p, iptr.p, np, ipins.p);
+    Buf<uint64_t> hs(Cx.pool, l);
+    Buf<int32_t> val(Cx.pool, l), repflag(Cx.pool, (size_t)l + 1), reppos(Cx.pool, l);
+    cidx = Buf<int32_t>(Cx.pool, (size_t)l + 1);
+    Buf<int32_t> kept_net(Cx.pool, l);
+    VMO_LAUNCH(k_kept_net, gsz(l), kLT, 0, s, kf.p, kidx.p, l, kept_net.p);
+    VMO_LAUNCH(k_img_hash, gsz(l), kLT, 0, s, iptr.p, ipins.p, nk_dev, l, hs.p, val.p);
+    radix_sort<uint64_t>(Cx, hs.p, val.p, l, 64, s);
+    fill_i32(repflag.p, 0, (int64_t)l + 1, s);
+    VMO_LAUNCH(k_img_rep, gsz(l), kLT, 0, s, hs.p, val.p, iptr.p, ipins.p, nk_dev, repflag.p, reppos.p);
+    scan_exclusive<int32_t>(Cx, repflag.p, cidx.p, l, cidx.p + l, s);
+    lc_dev = cidx.p + l;  // coarse nets
+    Cl.c = Buf<float>(Cx.pool, l);
+    Buf<int64_t> clen(Cx.pool, (size_t)l + 1);
+    fill_i64(clen.p, 0, (int64_t)l + 1, s);
+    VMO_LAUNCH(k_img_cost, gsz(l), kLT, 0, s, hs.p, val.p, reppos.p, kept_net.p, F.c.p, iptr.p, cidx.p, nk_dev, Cl.c.p,
+               clen.p);
+    scan_exclusive<int64_t>(Cx, clen.p, Cl.ptr.p, l, Cl.ptr.p + l, s);
+    cnp_dev = Cl.ptr.p + l;  // coarse pins
+    Cl.pins = Buf<int32_t>(Cx.pool, np);
+    VMO_LAUNCH(k_coarse_pins, gsz(l), kLT, 0, s, repflag.p, cidx.p, iptr.p, ipins.p, Cl.ptr.p, nk_dev, Cl.pins.p);
   }
-  if (lc == 0) {
+  Buf<int64_t> sizes(Cx.pool, 3);
+  VMO_LAUNCH(k_coarse_sizes, 1, 1, 0, s, kc_dev, lc_dev, cnp_dev, sizes.p);
+  int64_t hsz[3];
+  read_bytes(hsz, sizes.p, sizeof hsz, s);
+  Cl.k = (int32_t)hsz[0];
+  Cl.l = (int32_t)hsz[1];
+  Cl.np = hsz[2];
+  if (Cl.l == 0) {
     fill_i64(Cl.ptr.p, 0, 1, s);
     Cl.c = Buf<float>(Cx.pool, 1);
     Cl.pins = Buf<int32_t>(Cx.pool, 1);
+    Cl.np = 0;
   }
-  Cl.l = lc;
-  Cl.np = cnp;
   VMO_HIP(hipStreamSynchronize(s));
 }
 
