@@ -38,16 +38,19 @@ static void make_dual(Ctx& C, Level& L, hipStream_t s) {
 }
 
 // ============================================================ bounding box ==
-__global__ __launch_bounds__(kLT) void k_box(const float* x, int32_t k, uint32_t* box) {
+__global__ __launch_bounds__(kLT) void k_box(const float4* x, int32_t k, uint32_t* box) {
   __shared__ uint32_t sm[kLT / 64][8];
   uint32_t mn[4], mx[4];
   for (int d = 0; d < 4; ++d) { mn[d] = 0xffffffffu; mx[d] = 0u; }
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x) {
+    const float4 xv = x[v];
+    const float c[4] = {xv.x, xv.y, xv.z, xv.w};
     for (int d = 0; d < 4; ++d) {
-      uint32_t f = fkey(x[(int64_t)d * k + v]);
+      uint32_t f = fkey(c[d]);
       mn[d] = f < mn[d] ? f : mn[d];
       mx[d] = f > mx[d] ? f : mx[d];
     }
+  }
   for (int off = 32; off > 0; off >>= 1)
     for (int d = 0; d < 4; ++d) {
       uint32_t a = __shfl_xor(mn[d], off, 64), b = __shfl_xor(mx[d], off, 64);
@@ -83,7 +86,7 @@ struct HostBox {
   }
 };
 
-static void box_of(const float* x, int32_t k, uint32_t* dbox, hipStream_t s) {
+static void box_of(const float4* x, int32_t k, uint32_t* dbox, hipStream_t s) {
   VMO_LAUNCH(k_box_init, 1, 64, 0, s, dbox);
   // at most 128 blocks: the 8 atomics of every block meet on one cache line
   int64_t nb = nblocks(k, kLT);
@@ -100,7 +103,9 @@ static HostBox read_box(const uint32_t* dbox, hipStream_t s) {
 // =================================================================== tree ===
 // Grid coordinate of a point: floor((x - lo) * 65536 / ext), clamped to
 // 65535; ext = largest side of the bounding box (FP64).
-__device__ __forceinline__ void grid_coords(const float* x, int32_t k, int64_t v, const uint32_t* box, uint32_t* kq) {
+__device__ __forceinline__ void grid_coords(const float4* x, int64_t v, const uint32_t* box, uint32_t* kq) {
+  const float4 xv = x[v];
+  const float c[4] = {xv.x, xv.y, xv.z, xv.w};
   double ext = 0.0;
   float lo[4];
   for (int d = 0; d < 4; ++d) {
@@ -112,7 +117,7 @@ __device__ __forceinline__ void grid_coords(const float* x, int32_t k, int64_t v
   for (int d = 0; d < 4; ++d) {
     uint32_t a = 0;
     if (sc > 0.0) {
-      double f = floor(((double)x[(int64_t)d * k + v] - (double)lo[d]) * sc);
+      double f = floor(((double)c[d] - (double)lo[d]) * sc);
       a = f >= 65535.0 ? 65535u : (uint32_t)f;
     }
     kq[d] = a;
@@ -121,10 +126,10 @@ __device__ __forceinline__ void grid_coords(const float* x, int32_t k, int64_t v
 
 // Morton key: digit at depth L (1..16) = bits (16-L) of the four coordinates,
 // dimension 0 most significant; depth-1 digit in the top nibble.
-__global__ void k_tree_keys(const float* x, int32_t k, const uint32_t* box, uint64_t* key, int32_t* val) {
+__global__ void k_tree_keys(const float4* x, int32_t k, const uint32_t* box, uint64_t* key, int32_t* val) {
   GRID_STRIDE(v, k) {
     uint32_t kq[4];
-    grid_coords(x, k, v, box, kq);
+    grid_coords(x, v, box, kq);
     uint64_t m = 0;
     for (int b = 15; b >= 0; --b)
       for (int d = 0; d < 4; ++d) m = (m << 1) | ((kq[d] >> b) & 1u);
@@ -134,15 +139,15 @@ __global__ void k_tree_keys(const float* x, int32_t k, const uint32_t* box, uint
 }
 
 // Points in tree order: coordinates, weights and 2 kq + 1 (doubled grid units).
-__global__ void k_tree_points(const float* x, const float* w, int32_t k, const uint32_t* box, const int32_t* order,
+__global__ void k_tree_points(const float4* x, const float* w, int32_t k, const uint32_t* box, const int32_t* order,
                               float* xs, float* ws, int32_t* p2, float4* P) {
   GRID_STRIDE(j, k) {
     int32_t v = order[j];
     uint32_t kq[4];
-    grid_coords(x, k, v, box, kq);
-    float c[4];
+    grid_coords(x, v, box, kq);
+    const float4 xv = x[v];
+    const float c[4] = {xv.x, xv.y, xv.z, xv.w};
     for (int d = 0; d < 4; ++d) {
-      c[d] = x[(int64_t)d * k + v];
       xs[(int64_t)d * k + j] = c[d];
       p2[(int64_t)d * k + j] = 2 * (int32_t)kq[d] + 1;
     }
@@ -518,7 +523,7 @@ __device__ __forceinline__ int32_t key_coord(uint64_t m, int d) {
   return a;
 }
 
-__global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x, const float* __restrict__ w,
+__global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ x, const float* __restrict__ w,
                                                      int32_t k, int32_t cap, uint32_t* __restrict__ box,
                                                      FarTable ft, int32_t* __restrict__ order, float* __restrict__ xs,
                                                      float* __restrict__ ws, int32_t* __restrict__ p2,
@@ -544,12 +549,15 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     if (t < 8) sbox[t] = t < 4 ? 0xffffffffu : 0u;
     uint32_t mn[4], mx[4];
     for (int d = 0; d < 4; ++d) { mn[d] = 0xffffffffu; mx[d] = 0u; }
-    for (int v = t; v < k; v += kSTB)
+    for (int v = t; v < k; v += kSTB) {
+      const float4 xv = x[v];
+      const float c[4] = {xv.x, xv.y, xv.z, xv.w};
       for (int d = 0; d < 4; ++d) {
-        const uint32_t f = fkey(x[(int64_t)d * k + v]);
+        const uint32_t f = fkey(c[d]);
         mn[d] = min(mn[d], f);
         mx[d] = max(mx[d], f);
       }
+    }
     for (int off = 32; off > 0; off >>= 1)
       for (int d = 0; d < 4; ++d) {
         mn[d] = min(mn[d], (uint32_t)__shfl_xor((int)mn[d], off, 64));
@@ -571,7 +579,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     const int v = r * kSTB + t;
     if (v >= k) break;
     uint32_t kq[4];
-    grid_coords(x, k, v, sbox, kq);
+    grid_coords(x, v, sbox, kq);
     uint64_t m = 0;
     for (int b = 15; b >= 0; --b)
       for (int d = 0; d < 4; ++d) m = (m << 1) | ((kq[d] >> b) & 1u);
@@ -680,10 +688,10 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float* __restrict__ x
     const int32_t v = val[j];
     order[j] = v;
     uint32_t kq[4];
-    grid_coords(x, k, v, sbox, kq);
-    float c[4];
+    grid_coords(x, v, sbox, kq);
+    const float4 xv = x[v];
+    const float c[4] = {xv.x, xv.y, xv.z, xv.w};
     for (int d = 0; d < 4; ++d) {
-      c[d] = x[(int64_t)d * k + v];
       xs[(int64_t)d * k + j] = c[d];
       p2[(int64_t)d * k + j] = 2 * (int32_t)kq[d] + 1;
     }
@@ -923,12 +931,12 @@ struct Tree {
   }
 };
 
-// Build the tree of x [4][k] (weights w or 1) with the bounding box dbox: the
+// Build the tree of x (one record per point; weights w or 1) with the bounding box dbox: the
 // one-block build (small_ok, k <= kSmallK) computes the box of x itself into
 // dbox, the multi-kernel build reads it.  The node count is left on the device
 // at T.nn[k] (no host round trip): node arrays are sized for the largest
 // possible tree, 17 nodes per position.
-static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t k, int32_t cap, uint32_t* dbox,
+static void build_tree(Ctx& C, Tree& T, const float4* x, const float* w, int32_t k, int32_t cap, uint32_t* dbox,
                        double th2, hipStream_t s, bool small_ok = true) {
   T.k = k;
   T.n = -1;
@@ -985,16 +993,16 @@ static void build_tree(Ctx& C, Tree& T, const float* x, const float* w, int32_t 
 // Net centres: pins summed in CSR order (each coordinate on its own), then
 // divided by the net size.  z is AoS (one 16-byte record per net) so that the
 // attraction gathers a centre with one load.
-__global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, const float* x, int32_t k, float4* z) {
+__global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, const float4* x, float4* z) {
   GRID_STRIDE(e, l) {
     int64_t b = ptr[e], n = ptr[e + 1] - b;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
     for (int64_t p = b; p < b + n; ++p) {
-      int32_t v = pins[p];
-      a0 = a0 + x[v];
-      a1 = a1 + x[(int64_t)k + v];
-      a2 = a2 + x[2 * (int64_t)k + v];
-      a3 = a3 + x[3 * (int64_t)k + v];
+      const float4 xv = x[pins[p]];
+      a0 = a0 + xv.x;
+      a1 = a1 + xv.y;
+      a2 = a2 + xv.z;
+      a3 = a3 + xv.w;
     }
     float fn = (float)n;
     z[e] = n > 0 ? make_float4(a0 / fn, a1 / fn, a2 / fn, a3 / fn) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -1003,12 +1011,13 @@ __global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, co
 // Attraction of eq. (7): sum over the vertex's nets in ascending net order.
 // Nets are taken eight at a time: their loads are issued together (vertices of
 // coarse levels meet many nets), the sums stay in net order.
-__global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, const float* c, const float* x,
-                          const float4* z, float* y) {
+__global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, const float* c, const float4* x,
+                          const float4* z, float4* y) {
   constexpr int B = 8;
   GRID_STRIDE(v, k) {
     int64_t b = dptr[v], e = dptr[v + 1];
-    float x0 = x[v], x1 = x[(int64_t)k + v], x2 = x[2 * (int64_t)k + v], x3 = x[3 * (int64_t)k + v];
+    const float4 xv = x[v];
+    const float x0 = xv.x, x1 = xv.y, x2 = xv.z, x3 = xv.w;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
     for (int64_t t0 = b; t0 < e; t0 += B) {
       int32_t nb[B];
@@ -1034,22 +1043,20 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
         a3 = a3 + ce * d3;
       }
     }
-    y[v] = a0;
-    y[(int64_t)k + v] = a1;
-    y[2 * (int64_t)k + v] = a2;
-    y[3 * (int64_t)k + v] = a3;
+    y[v] = make_float4(a0, a1, a2, a3);
   }
 }
 // The same attraction with one wavefront per vertex, for small levels, whose
 // coarse vertices can meet hundreds of nets: the lanes form the terms
 // c_e (x - z_e) of 64 nets at a time, and the sum runs over them in net order.
 __global__ __launch_bounds__(256) void k_attract_wave(const int64_t* dptr, const int32_t* dpins, int32_t k,
-                                                      const float* c, const float* x, const float4* z, float* y) {
+                                                      const float* c, const float4* x, const float4* z, float4* y) {
   __shared__ float4 tb[4][64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int64_t v = (int64_t)blockIdx.x * 4 + wv; v < k; v += (int64_t)gridDim.x * 4) {
     const int64_t b = dptr[v], e = dptr[v + 1];
-    const float x0 = x[v], x1 = x[(int64_t)k + v], x2 = x[2 * (int64_t)k + v], x3 = x[3 * (int64_t)k + v];
+    const float4 xv = x[v];
+    const float x0 = xv.x, x1 = xv.y, x2 = xv.z, x3 = xv.w;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
     for (int64_t t0 = b; t0 < e; t0 += 64) {
       const int m = e - t0 < 64 ? (int)(e - t0) : 64;
@@ -1075,12 +1082,7 @@ __global__ __launch_bounds__(256) void k_attract_wave(const int64_t* dptr, const
         a3 = a3 + tt.w;
       }
     }
-    if (lane == 0) {
-      y[v] = a0;
-      y[(int64_t)k + v] = a1;
-      y[2 * (int64_t)k + v] = a2;
-      y[3 * (int64_t)k + v] = a3;
-    }
+    if (lane == 0) y[v] = make_float4(a0, a1, a2, a3);
   }
 }
 __global__ void k_z_soa(const float4* z, int32_t l, float* out) {
@@ -1354,8 +1356,8 @@ constexpr int kCombT = 64 * kParts;
 __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __restrict__ order,
                                                     const int32_t* __restrict__ p2, const TNode* __restrict__ nodes,
                                                     const int32_t* __restrict__ cid, const int32_t* __restrict__ nch,
-                                                    int spread, const float* __restrict__ part, float* y,
-                                                    float* xmove, double alpha) {
+                                                    int spread, const float* __restrict__ part, float4* y,
+                                                    float4* xmove, double alpha) {
   __shared__ float4 sh[kParts][64];
   const int i1 = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 64 + lane;
@@ -1397,8 +1399,8 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
   __syncthreads();
   if (i1 != 0 || !valid) return;
   const int32_t v = order[j];
-  float yv[4];
-  for (int d = 0; d < 4; ++d) yv[d] = y[(int64_t)d * k + v];
+  const float4 y0 = y[v];
+  float yv[4] = {y0.x, y0.y, y0.z, y0.w};
   for (int i = 0; i < np; ++i) {
     const float4 a = sh[i][lane];
     yv[0] = yv[0] + a.x;
@@ -1407,7 +1409,7 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
     yv[3] = yv[3] + a.w;
   }
   if (!xmove) {
-    for (int d = 0; d < 4; ++d) y[(int64_t)d * k + v] = yv[d];
+    y[v] = make_float4(yv[0], yv[1], yv[2], yv[3]);
     return;
   }
   float n2s = yv[0] * yv[0];
@@ -1416,10 +1418,14 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
   n2s = n2s + yv[3] * yv[3];
   if (!(n2s > 0.0f)) return;
   float f = (float)(alpha / sqrt((double)n2s));
+  const float4 xo = xmove[v];
+  const float xv[4] = {xo.x, xo.y, xo.z, xo.w};
+  float xn[4];
   for (int d = 0; d < 4; ++d) {
     float td = f * yv[d];
-    xmove[(int64_t)d * k + v] = xmove[(int64_t)d * k + v] - td;
+    xn[d] = xv[d] - td;
   }
+  xmove[v] = make_float4(xn[0], xn[1], xn[2], xn[3]);
 }
 
 struct GradWork {
@@ -1430,12 +1436,12 @@ struct GradWork {
 };
 
 // Attraction into y, net centres, box of x (gw.box) and the tree of x.
-static void gradient_prepare(Ctx& C, const Level& L, const float* x, double th2, int32_t cap, float* y, GradWork& gw,
+static void gradient_prepare(Ctx& C, const Level& L, const float4* x, double th2, int32_t cap, float4* y, GradWork& gw,
                              hipStream_t s) {
   if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
   if (L.k > kSmallK) box_of(x, L.k, gw.box.p, s);  // else the one-block tree build forms it
   gw.z = Buf<float4>(C.pool, (size_t)(L.l > 0 ? L.l : 1));
-  if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, L.k, gw.z.p);
+  if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, gw.z.p);
   if (L.k <= 16384)
     VMO_LAUNCH(k_attract_wave, nblocks(L.k, 4), 256, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y);
   else
@@ -1446,7 +1452,7 @@ static void gradient_prepare(Ctx& C, const Level& L, const float* x, double th2,
 // Repulsion by the tree walk, added to the attraction in y.  xmove == NULL:
 // y receives the gradient of eq. (6); else the descent step of length alpha
 // is applied to xmove (the layout being descended) and y is left as is.
-static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double alpha, GradWork& gw,
+static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, double alpha, GradWork& gw,
                           unsigned long long* nint, hipStream_t s) {
   // Levels of up to kSpreadMax points spread each part of the walk over the
   // children of its cell: 16 times the wavefronts, and up to 16 times the
@@ -1483,8 +1489,8 @@ static void gradient_walk(Ctx& C, const Level& L, float* y, float* xmove, double
 
 // One descent step (Algorithm 3).  alpha: step length (host); at it == 0 it
 // is set from the box, alpha = step0 * V^(1/4) (V = 0: largest side).
-static void descent_step(Ctx& C, const Level& L, float* x, const vmo_layout_params* p, int32_t it, double* alpha,
-                         float* y, GradWork& gw, hipStream_t s) {
+static void descent_step(Ctx& C, const Level& L, float4* x, const vmo_layout_params* p, int32_t it, double* alpha,
+                         float4* y, GradWork& gw, hipStream_t s) {
   double th2 = (double)p->theta * (double)p->theta;
   gradient_prepare(C, L, x, th2, p->leaf_cap, y, gw, s);
   if (it == 0) {
@@ -1825,26 +1831,46 @@ static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t 
 }
 
 // ======================================================= init / prolong ====
-__global__ void k_init_x(int32_t k, uint64_t seed, uint64_t key, float a, float* x) {
+__global__ void k_init_x(int32_t k, uint64_t seed, uint64_t key, float a, float4* x) {
   GRID_STRIDE(v, k) {
+    float c[4];
     for (int d = 0; d < 4; ++d) {
       uint64_t r = rng3(seed, key, (uint64_t)v, (uint64_t)d);
       float u = (float)(uint32_t)(r >> 40) * 0x1p-24f;
-      x[(int64_t)d * k + v] = (u - 0.5f) * a;
+      c[d] = (u - 0.5f) * a;
     }
+    x[v] = make_float4(c[0], c[1], c[2], c[3]);
   }
 }
-__global__ void k_prolong(int32_t kf, const int32_t* pi, const float* xc, int32_t kc, uint64_t seed, uint64_t key,
-                          float sigma, float eps, float* xf) {
+__global__ void k_prolong(int32_t kf, const int32_t* pi, const float4* xc, uint64_t seed, uint64_t key, float sigma,
+                          float eps, float4* xf) {
   GRID_STRIDE(v, kf) {
+    const float4 cv = xc[pi[v]];
+    const float cc[4] = {cv.x, cv.y, cv.z, cv.w};
+    float o[4];
     for (int d = 0; d < 4; ++d) {
       uint64_t r = rng3(seed, key, (uint64_t)v, (uint64_t)d);
       float u = (float)(uint32_t)(r >> 40) * 0x1p-23f;
       u = u - 1.0f;
-      float a = sigma * xc[(int64_t)d * kc + pi[v]];
+      float a = sigma * cc[d];
       float b = eps * u;
-      xf[(int64_t)d * kf + v] = a + b;
+      o[d] = a + b;
     }
+    xf[v] = make_float4(o[0], o[1], o[2], o[3]);
+  }
+}
+// Coordinates between the caller's layout ([4][k], one array per dimension)
+// and the descent's (one 16-byte record per vertex).
+__global__ void k_to_rec(const float* x, int32_t k, float4* r) {
+  GRID_STRIDE(v, k) r[v] = make_float4(x[v], x[(int64_t)k + v], x[2 * (int64_t)k + v], x[3 * (int64_t)k + v]);
+}
+__global__ void k_from_rec(const float4* r, int32_t k, float* x) {
+  GRID_STRIDE(v, k) {
+    const float4 a = r[v];
+    x[v] = a.x;
+    x[(int64_t)k + v] = a.y;
+    x[2 * (int64_t)k + v] = a.z;
+    x[3 * (int64_t)k + v] = a.w;
   }
 }
 
@@ -1864,7 +1890,7 @@ static void layout_component(Ctx& C, std::vector<Level>& L, const vmo_layout_par
     L.push_back(std::move(Cl));
     ++J;
   }
-  Buf<float> x(C.pool, 4 * (size_t)L[J].k);
+  Buf<float4> x(C.pool, (size_t)L[J].k);
   {
     float a = (float)sqrt(sqrt((double)L[J].k));
     uint64_t key = kTagInit | ((uint64_t)J << 8) | (comp << 32);
@@ -1874,7 +1900,7 @@ static void layout_component(Ctx& C, std::vector<Level>& L, const vmo_layout_par
   for (int32_t j = J; j >= 0; --j) {
     int32_t iters = j == J ? p->coarsest_iters : p->level_iters;
     double alpha = 0.0;
-    Buf<float> y(C.pool, 4 * (size_t)L[j].k);
+    Buf<float4> y(C.pool, (size_t)L[j].k);
     for (int32_t it = 0; it < iters; ++it) descent_step(C, L[j], x.p, p, it, &alpha, y.p, gw, s);
     if (j > 0) {
       if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
@@ -1886,12 +1912,12 @@ static void layout_component(Ctx& C, std::vector<Level>& L, const vmo_layout_par
       double epsd = (double)p->jitter * ext;
       float eps = (float)(epsd / sqrt(sqrt((double)kc)));
       uint64_t key = kTagProlong | ((uint64_t)(j - 1) << 8) | (comp << 32);
-      Buf<float> xf(C.pool, 4 * (size_t)kf);
-      VMO_LAUNCH(k_prolong, gsz(kf), kLT, 0, s, kf, L[j - 1].pi.p, x.p, kc, p->seed, key, sigma, eps, xf.p);
+      Buf<float4> xf(C.pool, (size_t)kf);
+      VMO_LAUNCH(k_prolong, gsz(kf), kLT, 0, s, kf, L[j - 1].pi.p, x.p, p->seed, key, sigma, eps, xf.p);
       x = std::move(xf);
     }
   }
-  VMO_HIP(hipMemcpyAsync(xout, x.p, sizeof(float) * 4 * (size_t)L[0].k, hipMemcpyDeviceToDevice, s));
+  VMO_LAUNCH(k_from_rec, gsz(L[0].k), kLT, 0, s, x.p, L[0].k, xout);
   VMO_HIP(hipStreamSynchronize(s));
 }
 
@@ -2178,9 +2204,11 @@ void tree(Ctx& C, const float* x, const float* w, int32_t k, int32_t cap, int32_
   VMO_REQUIRE(ints && cell2 && flt && order && n_nodes, "NULL output");
   validate_finite(C, x, 4 * (int64_t)k, "x", s);
   Buf<uint32_t> box(C.pool, 8);
-  box_of(x, k, box.p, s);
+  Buf<float4> xr(C.pool, (size_t)k);
+  VMO_LAUNCH(k_to_rec, gsz(k), kLT, 0, s, x, k, xr.p);
+  box_of(xr.p, k, box.p, s);
   Tree T;
-  build_tree(C, T, x, w, k, cap, box.p, 0.25, s, false);
+  build_tree(C, T, xr.p, w, k, cap, box.p, 0.25, s, false);
   const int32_t n = read1(T.nn.p + k, s);
   VMO_REQUIRE(n <= max_nodes, "max_nodes is too small");
   VMO_LAUNCH(k_tree_out, gsz(n), kLT, 0, s, n, T.view(), ints, cell2, flt);
@@ -2198,8 +2226,11 @@ void gradient(Ctx& C, const vmo_hypergraph* h, const float* x, float theta, int3
   Level L = level_from(C, h->k, h->l, h->net_ptr, h->pins, h->w, h->c, s);
   GradWork gw;
   Buf<unsigned long long> cnt(C.pool, 1);  // written by the walk's counter sum
-  gradient_prepare(C, L, x, (double)theta * (double)theta, cap, y, gw, s);
-  gradient_walk(C, L, y, nullptr, 0.0, gw, cnt.p, s);
+  Buf<float4> xr(C.pool, (size_t)L.k), yr(C.pool, (size_t)L.k);
+  VMO_LAUNCH(k_to_rec, gsz(L.k), kLT, 0, s, x, L.k, xr.p);
+  gradient_prepare(C, L, xr.p, (double)theta * (double)theta, cap, yr.p, gw, s);
+  gradient_walk(C, L, yr.p, nullptr, 0.0, gw, cnt.p, s);
+  VMO_LAUNCH(k_from_rec, gsz(L.k), kLT, 0, s, yr.p, L.k, y);
   if (z && L.l > 0) VMO_LAUNCH(k_z_soa, gsz(L.l), kLT, 0, s, gw.z.p, L.l, z);
   const unsigned long long c = L.k > 0 ? read1(cnt.p, s) : 0ull;
   if (nint) *nint = (int64_t)c;
@@ -2212,9 +2243,11 @@ void layout_steps(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, f
   VMO_REQUIRE(x && alpha && it0 >= 0 && iters >= 0, "bad arguments");
   Level L = level_from(C, h->k, h->l, h->net_ptr, h->pins, h->w, h->c, s);
   GradWork gw;
-  Buf<float> y(C.pool, 4 * (size_t)h->k);
+  Buf<float4> xr(C.pool, (size_t)h->k), y(C.pool, (size_t)h->k);
+  VMO_LAUNCH(k_to_rec, gsz(h->k), kLT, 0, s, x, h->k, xr.p);
   double a = *alpha;
-  for (int32_t t = 0; t < iters; ++t) descent_step(C, L, x, p, it0 + t, &a, y.p, gw, s);
+  for (int32_t t = 0; t < iters; ++t) descent_step(C, L, xr.p, p, it0 + t, &a, y.p, gw, s);
+  VMO_LAUNCH(k_from_rec, gsz(h->k), kLT, 0, s, xr.p, h->k, x);
   VMO_HIP(hipStreamSynchronize(s));
   *alpha = a;
 }
