@@ -38,10 +38,11 @@ N_SIDE = 64
 SEED = 1
 SCHUR_P3 = 8         # parts of each separator block in the Schur-complement recursion
 FLOPS_PER_INTERACTION = 23   # 4 sub, r^2 (1 mul + 3 fma), 2 mul (2 W w), 1 mul (r^4), 1 div, 4 fma
-# HBM bytes per walk launch (average over one step of this workload), from two
+# HBM bytes per walk launch (average over the walk launches of one counting and
+# one timed step of this workload), from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
 # plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
-WALK_TRAFFIC_BYTES = 88.23e6 + 18.68e6
+WALK_TRAFFIC_BYTES = 88.27e6 + 18.77e6
 PEAK_FP32_VALU_TFLOPS = 157.3
 # live timing brackets every PROFILE_EVERY-th launch of a kernel with HIP
 # events: an event pair costs about 13 us of stream time, 2.5 % of a step when
