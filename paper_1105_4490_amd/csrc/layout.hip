@@ -1525,9 +1525,13 @@ __device__ __forceinline__ bool prio_gt(const Prio& x, const Prio& y) {
 // Best unmatched candidate partner of every unmatched vertex: the pair of
 // highest priority (cost/(|e|-1) over a shared net of 2..mm pins, then the
 // keyed hash, then the smaller ids).
+// prev: the match count of the previous round of the group (NULL for its
+// first round); after a round that matched nothing the rounds change nothing,
+// so both kernels return at once.
 __global__ void k_match_best(const int64_t* ptr, const int32_t* pins, const int64_t* dptr, const int32_t* dpins,
                              const float* c, int32_t k, int32_t mm, const int32_t* mate, uint64_t seed, uint64_t mkey,
-                             int32_t* best) {
+                             const int32_t* prev, int32_t* best) {
+  if (prev && *prev == 0) return;
   GRID_STRIDE(u64, k) {
     int32_t u = (int32_t)u64;
     if (mate[u] >= 0) { best[u] = -1; continue; }
@@ -1553,7 +1557,8 @@ __global__ void k_match_best(const int64_t* ptr, const int32_t* pins, const int6
     best[u] = bv;
   }
 }
-__global__ void k_match_pair(const int32_t* best, int32_t k, int32_t* mate, int32_t* changed) {
+__global__ void k_match_pair(const int32_t* best, int32_t k, const int32_t* prev, int32_t* mate, int32_t* changed) {
+  if (prev && *prev == 0) return;
   GRID_STRIDE(u64, k) {
     int32_t u = (int32_t)u64;
     int32_t v = best[u];
@@ -1735,8 +1740,8 @@ static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t 
   uint64_t mkey = kTagMatch | ((uint64_t)level << 8) | (comp << 32);
   // Rounds run in groups of kRounds with one host check per group: a round
   // after the one that matched nothing changes nothing, so the extra rounds
-  // of the last group leave the matching as it is.
-  constexpr int kRounds = 4;
+  // of the last group leave the matching as it is (and return at once).
+  constexpr int kRounds = 8;
   Buf<int32_t> mate(Cx.pool, k), best(Cx.pool, k), chg(Cx.pool, kRounds);
   fill_i32(mate.p, -1, k, s);
   // every round matches at least the best remaining pair, so at most k/2 + 1
@@ -1744,9 +1749,10 @@ static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t 
     VMO_REQUIRE(round <= (int64_t)k / 2 + 1, "matching did not settle");
     VMO_HIP(hipMemsetAsync(chg.p, 0, 4 * kRounds, s));
     for (int r = 0; r < kRounds; ++r) {
+      const int32_t* prev = r > 0 ? chg.p + r - 1 : nullptr;
       VMO_LAUNCH(k_match_best, gsz(k), kLT, 0, s, F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, F.c.p, k, mm, mate.p, seed,
-                 mkey, best.p);
-      VMO_LAUNCH(k_match_pair, gsz(k), kLT, 0, s, best.p, k, mate.p, chg.p + r);
+                 mkey, prev, best.p);
+      VMO_LAUNCH(k_match_pair, gsz(k), kLT, 0, s, best.p, k, prev, mate.p, chg.p + r);
     }
     if (read1(chg.p + kRounds - 1, s) == 0) break;
   }

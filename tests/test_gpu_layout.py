@@ -137,7 +137,7 @@ def test_profile_times_every_nth_walk(ctx):
     assert np.array_equal(host(gx), res[1][1])
 
 
-@pytest.mark.parametrize("case", ["random", "grid3d", "star", "weighted"])
+@pytest.mark.parametrize("case", ["random", "grid3d", "star", "weighted", "pairs", "short_nets"])
 def test_coarsen(ctx, case):
     if case == "random":
         g = vmo_gen.random_hypergraph_csr(3000, 2500, 1, maxdeg=6)
@@ -147,6 +147,12 @@ def test_coarsen(ctx, case):
         h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
     elif case == "star":
         h = oracle.hypergraph(60, [[0, i] for i in range(1, 40)] + [[40, 41, 42], [41, 42, 43], [50, 51], [50, 51]])
+    elif case == "pairs":
+        # every net joins a matched pair (some twice): no net survives
+        h = oracle.hypergraph(8, [[0, 1], [2, 3], [4, 5], [6, 7], [0, 1]])
+    elif case == "short_nets":
+        # empty and one-pin nets only: no image reaches two vertices
+        h = oracle.hypergraph(8, [[], [3], [], [5]])
     else:
         h = weighted_case(4, 5000, 4000, maxdeg=80)
         h.c = vmo_gen.rng(4, 1).integers(1, 4, size=h.l).astype(np.float32)
