@@ -588,6 +588,51 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
   }
   __syncthreads();
 
+  if (k <= kSTB) {
+    // At most one point per thread: a bitonic sort of the (key, index) pairs,
+    // which are all distinct, so the result is the stable order by key.  N
+    // (a power of two, at least 64) positions; those from k on hold (2^64 - 1,
+    // INT_MAX), which sorts after every point.  Partners closer than 64
+    // positions are in the same wavefront (shuffles); farther ones are
+    // exchanged through LDS.  Every thread runs every step (the barriers).
+    int N = 64;
+    while (N < k) N <<= 1;
+    uint64_t mk = t < k ? key[t] : ~0ull;
+    int32_t mv = t < k ? t : 0x7fffffff;
+    for (int kk = 2; kk <= N; kk <<= 1) {
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        uint64_t ok;
+        int32_t ov;
+        if (j >= 64) {
+          key[t] = mk;
+          val[t] = mv;
+          __syncthreads();
+          ok = key[t ^ j];
+          ov = val[t ^ j];
+          __syncthreads();
+        } else {
+          const uint32_t lo = __shfl_xor((uint32_t)mk, j, 64);
+          const uint32_t hi = __shfl_xor((uint32_t)(mk >> 32), j, 64);
+          ok = ((uint64_t)hi << 32) | lo;
+          ov = __shfl_xor(mv, j, 64);
+        }
+        const bool other_less = ok < mk || (ok == mk && ov < mv);
+        // the lower position of a pair keeps the smaller pair in ascending
+        // runs ((t & kk) == 0) and the larger one in descending runs
+        const bool keep_min = ((t & j) == 0) == ((t & kk) == 0);
+        if (t < N && other_less == keep_min) {
+          mk = ok;
+          mv = ov;
+        }
+      }
+    }
+    if (t < k) {
+      key[t] = mk;
+      val[t] = mv;
+    }
+    __syncthreads();
+  }
+
   // stable LSD radix sort, 8-bit digits.  Item r of thread t is position
   // r * 1024 + t.  Each pass ranks all four rounds at once: lanes of a wave
   // with equal digits are found by ballots, the (round, wave, digit) counts
@@ -596,7 +641,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
   const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
   uint32_t* cnt32 = reinterpret_cast<uint32_t*>(&cnt[0][0][0]);
   const int rounds = (k + kSTB - 1) / kSTB;  // rounds holding items (uniform)
-  for (int pass = 0; pass < 8; ++pass) {
+  for (int pass = 0; pass < (k <= kSTB ? 0 : 8); ++pass) {
     const int sh = 8 * pass;
     uint64_t mk[4];
     int32_t mv[4];
