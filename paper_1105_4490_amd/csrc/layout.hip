@@ -785,15 +785,16 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     int loc = 0;
     for (int e = 0; e < 5; ++e)
       if (b0 + e <= k) loc += base[b0 + e];
-    tsum[t] = loc;
-    __syncthreads();
-    for (int off = 1; off < kSTB; off <<= 1) {
-      const int a = t >= off ? tsum[t - off] : 0;
-      __syncthreads();
-      tsum[t] += a;
-      __syncthreads();
+    // inclusive scan within the wavefront, then the earlier wavefronts' totals
+    int inc = loc;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += u;
     }
-    int run2 = tsum[t] - loc;
+    if (lane == 63) tsum[wv] = inc;
+    __syncthreads();
+    int run2 = inc - loc;
+    for (int w2 = 0; w2 < wv; ++w2) run2 += tsum[w2];
     for (int e = 0; e < 5; ++e)
       if (b0 + e <= k) {
         const int c = base[b0 + e];
