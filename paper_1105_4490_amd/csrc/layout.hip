@@ -508,6 +508,56 @@ __global__ __launch_bounds__(kParts * kParts) void k_moments_top(NodeView nd) {
   }
 }
 
+// ------------------------------------------------- attraction, by wavefront ----
+// The attraction of eq. (7) for small levels, whose coarse vertices can meet
+// hundreds of nets: one wavefront per vertex, the lanes form the terms
+// c_e (x - z_e) of 64 nets at a time, and the sum runs over them in net order.
+struct AttractJob {
+  const int64_t* dptr;
+  const int32_t* dpins;
+  int32_t k;
+  const float* c;
+  const float4* x;
+  const float4* z;
+  float4* y;
+};
+// NW wavefronts per block; block blk of nblk (the blocks that take part).
+template <int NW>
+__device__ __forceinline__ void attract_waves(const AttractJob& aj, float4 (*tb)[64], int64_t blk, int64_t nblk) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t v = blk * NW + wv; v < aj.k; v += nblk * NW) {
+    const int64_t b = aj.dptr[v], e = aj.dptr[v + 1];
+    const float4 xv = aj.x[v];
+    const float x0 = xv.x, x1 = xv.y, x2 = xv.z, x3 = xv.w;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    for (int64_t t0 = b; t0 < e; t0 += 64) {
+      const int m = e - t0 < 64 ? (int)(e - t0) : 64;
+      float4 term = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (lane < m) {
+        const int32_t n = aj.dpins[t0 + lane];
+        const float ce = aj.c ? aj.c[n] : 1.0f;
+        const float4 zn = aj.z[n];
+        const float d0 = x0 - zn.x, d1 = x1 - zn.y, d2 = x2 - zn.z, d3 = x3 - zn.w;
+        term = make_float4(ce * d0, ce * d1, ce * d2, ce * d3);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      tb[wv][lane] = term;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int i = 0; i < m; ++i) {
+        const float4 tt = tb[wv][i];
+        a0 = a0 + tt.x;
+        a1 = a1 + tt.y;
+        a2 = a2 + tt.z;
+        a3 = a3 + tt.w;
+      }
+    }
+    if (lane == 0) aj.y[v] = make_float4(a0, a1, a2, a3);
+  }
+}
+
 // ------------------------------------------------- one-block tree build ----
 // Levels with k <= 4096 build their tree in one 1024-thread block: the same
 // keys, stable order, nodes and FP64 charges as the multi-kernel build, with
@@ -527,7 +577,15 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
                                                      int32_t k, int32_t cap, uint32_t* __restrict__ box,
                                                      FarTable ft, int32_t* __restrict__ order, float* __restrict__ xs,
                                                      float* __restrict__ ws, int32_t* __restrict__ p2,
-                                                     float4* __restrict__ P, NodeView nd, int32_t* __restrict__ nn) {
+                                                     float4* __restrict__ P, NodeView nd, int32_t* __restrict__ nn,
+                                                     AttractJob aj) {
+  // blocks after the first form the attraction of the same step (it does
+  // not depend on the tree), on other CUs while block 0 builds the tree
+  if (blockIdx.x > 0) {
+    __shared__ float4 tb[kSTB / 64][64];
+    attract_waves<kSTB / 64>(aj, tb, blockIdx.x - 1, gridDim.x - 1);
+    return;
+  }
   __shared__ uint64_t key[kSmallK];
   __shared__ __align__(16) unsigned char rb[32768];
   // per (round, wavefront, digit) counts of the sort, then their offsets
@@ -983,7 +1041,7 @@ struct Tree {
 // at T.nn[k] (no host round trip): node arrays are sized for the largest
 // possible tree, 17 nodes per position.
 static void build_tree(Ctx& C, Tree& T, const float4* x, const float* w, int32_t k, int32_t cap, uint32_t* dbox,
-                       double th2, hipStream_t s, bool small_ok = true) {
+                       double th2, hipStream_t s, bool small_ok = true, const AttractJob* aj = nullptr) {
   T.k = k;
   T.n = -1;
   const size_t nmax = 17 * (size_t)k + 1;  // at most 17 nodes begin at a position
@@ -1000,8 +1058,10 @@ static void build_tree(Ctx& C, Tree& T, const float4* x, const float* w, int32_t
     T.nch = Buf<int32_t>(C.pool, nmax);
     T.ctr = Buf<int32_t>(C.pool, nmax);
     T.cid = Buf<int32_t>(C.pool, 16 * nmax);
-    VMO_LAUNCH(k_tree_small, 1, kSTB, 0, s, x, w, k, cap, dbox, far_table(th2), T.order.p, T.xs.p, T.ws.p, T.p2.p,
-               T.P.p, T.view(), T.nn.p);
+    AttractJob none{};
+    const int64_t ab = aj && aj->k > 0 ? nblocks(aj->k, kSTB / 64) : 0;
+    VMO_LAUNCH(k_tree_small, (unsigned)(1 + (ab < 256 ? ab : 256)), kSTB, 0, s, x, w, k, cap, dbox, far_table(th2),
+               T.order.p, T.xs.p, T.ws.p, T.p2.p, T.P.p, T.view(), T.nn.p, aj ? *aj : none);
     return;
   }
   T.key = Buf<uint64_t>(C.pool, k);
@@ -1092,44 +1152,11 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
     y[v] = make_float4(a0, a1, a2, a3);
   }
 }
-// The same attraction with one wavefront per vertex, for small levels, whose
-// coarse vertices can meet hundreds of nets: the lanes form the terms
-// c_e (x - z_e) of 64 nets at a time, and the sum runs over them in net order.
-__global__ __launch_bounds__(256) void k_attract_wave(const int64_t* dptr, const int32_t* dpins, int32_t k,
-                                                      const float* c, const float4* x, const float4* z, float4* y) {
+// The same attraction with one wavefront per vertex (attract_waves), four
+// vertices per block.
+__global__ __launch_bounds__(256) void k_attract_wave(AttractJob aj) {
   __shared__ float4 tb[4][64];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int64_t v = (int64_t)blockIdx.x * 4 + wv; v < k; v += (int64_t)gridDim.x * 4) {
-    const int64_t b = dptr[v], e = dptr[v + 1];
-    const float4 xv = x[v];
-    const float x0 = xv.x, x1 = xv.y, x2 = xv.z, x3 = xv.w;
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    for (int64_t t0 = b; t0 < e; t0 += 64) {
-      const int m = e - t0 < 64 ? (int)(e - t0) : 64;
-      float4 term = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (lane < m) {
-        const int32_t n = dpins[t0 + lane];
-        const float ce = c ? c[n] : 1.0f;
-        const float4 zn = z[n];
-        const float d0 = x0 - zn.x, d1 = x1 - zn.y, d2 = x2 - zn.z, d3 = x3 - zn.w;
-        term = make_float4(ce * d0, ce * d1, ce * d2, ce * d3);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      tb[wv][lane] = term;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int i = 0; i < m; ++i) {
-        const float4 tt = tb[wv][i];
-        a0 = a0 + tt.x;
-        a1 = a1 + tt.y;
-        a2 = a2 + tt.z;
-        a3 = a3 + tt.w;
-      }
-    }
-    if (lane == 0) y[v] = make_float4(a0, a1, a2, a3);
-  }
+  attract_waves<4>(aj, tb, blockIdx.x, gridDim.x);
 }
 __global__ void k_z_soa(const float4* z, int32_t l, float* out) {
   GRID_STRIDE(e, l) {
@@ -1488,8 +1515,14 @@ static void gradient_prepare(Ctx& C, const Level& L, const float4* x, double th2
   if (L.k > kSmallK) box_of(x, L.k, gw.box.p, s);  // else the one-block tree build forms it
   gw.z = Buf<float4>(C.pool, (size_t)(L.l > 0 ? L.l : 1));
   if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, gw.z.p);
+  const AttractJob aj{L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y};
+  if (L.k <= kSmallK) {
+    // the one-block tree build runs the attraction in its other blocks
+    build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, th2, s, true, &aj);
+    return;
+  }
   if (L.k <= 16384)
-    VMO_LAUNCH(k_attract_wave, nblocks(L.k, 4), 256, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y);
+    VMO_LAUNCH(k_attract_wave, nblocks(L.k, 4), 256, 0, s, aj);
   else
     VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y);
   build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, th2, s);
