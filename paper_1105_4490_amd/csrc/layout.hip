@@ -103,8 +103,7 @@ static HostBox read_box(const uint32_t* dbox, hipStream_t s) {
 // =================================================================== tree ===
 // Grid coordinate of a point: floor((x - lo) * 65536 / ext), clamped to
 // 65535; ext = largest side of the bounding box (FP64).
-__device__ __forceinline__ void grid_coords(const float4* x, int64_t v, const uint32_t* box, uint32_t* kq) {
-  const float4 xv = x[v];
+__device__ __forceinline__ void grid_coords_of(const float4 xv, const uint32_t* box, uint32_t* kq) {
   const float c[4] = {xv.x, xv.y, xv.z, xv.w};
   double ext = 0.0;
   float lo[4];
@@ -122,6 +121,9 @@ __device__ __forceinline__ void grid_coords(const float4* x, int64_t v, const ui
     }
     kq[d] = a;
   }
+}
+__device__ __forceinline__ void grid_coords(const float4* x, int64_t v, const uint32_t* box, uint32_t* kq) {
+  grid_coords_of(x[v], box, kq);
 }
 
 // Morton key: digit at depth L (1..16) = bits (16-L) of the four coordinates,
@@ -601,15 +603,20 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
   int32_t* tsum = reinterpret_cast<int32_t*>(rb + 24640);       // [1024]
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
-  // the bounding box of x (as k_box), kept in LDS and written to box
+  // the bounding box of x (as k_box), kept in LDS and written to box; the
+  // points stay in registers for their keys
   __shared__ uint32_t sbox[8];
+  float4 xr[kSmallK / kSTB];
   {
     if (t < 8) sbox[t] = t < 4 ? 0xffffffffu : 0u;
     uint32_t mn[4], mx[4];
     for (int d = 0; d < 4; ++d) { mn[d] = 0xffffffffu; mx[d] = 0u; }
-    for (int v = t; v < k; v += kSTB) {
-      const float4 xv = x[v];
-      const float c[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+    for (int r = 0; r < kSmallK / kSTB; ++r) {
+      const int v = r * kSTB + t;
+      if (v >= k) break;
+      xr[r] = x[v];
+      const float c[4] = {xr[r].x, xr[r].y, xr[r].z, xr[r].w};
       for (int d = 0; d < 4; ++d) {
         const uint32_t f = fkey(c[d]);
         mn[d] = min(mn[d], f);
@@ -637,7 +644,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     const int v = r * kSTB + t;
     if (v >= k) break;
     uint32_t kq[4];
-    grid_coords(x, v, sbox, kq);
+    grid_coords_of(xr[r], sbox, kq);
     uint64_t m = 0;
     for (int b = 15; b >= 0; --b)
       for (int d = 0; d < 4; ++d) m = (m << 1) | ((kq[d] >> b) & 1u);
@@ -1468,11 +1475,18 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
       }
     }
   }
+  // the point's own records, loaded by wavefront 0 before the barrier so
+  // that their latency overlaps the other wavefronts' part loads
+  int32_t v = 0;
+  float4 y0 = make_float4(0.f, 0.f, 0.f, 0.f), xo = y0;
+  if (i1 == 0 && valid) {
+    v = order[j];
+    y0 = y[v];
+    if (xmove) xo = xmove[v];
+  }
   sh[i1][lane] = make_float4(a1[0], a1[1], a1[2], a1[3]);
   __syncthreads();
   if (i1 != 0 || !valid) return;
-  const int32_t v = order[j];
-  const float4 y0 = y[v];
   float yv[4] = {y0.x, y0.y, y0.z, y0.w};
   for (int i = 0; i < np; ++i) {
     const float4 a = sh[i][lane];
@@ -1491,7 +1505,6 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
   n2s = n2s + yv[3] * yv[3];
   if (!(n2s > 0.0f)) return;
   float f = (float)(alpha / sqrt((double)n2s));
-  const float4 xo = xmove[v];
   const float xv[4] = {xo.x, xo.y, xo.z, xo.w};
   float xn[4];
   for (int d = 0; d < 4; ++d) {
