@@ -841,6 +841,33 @@ __global__ void k_cc_union(const int64_t* ptr, const int32_t* pins, int32_t l, i
     }
   }
 }
+// Hooking rounds before the union-find: every net's consecutive pins (a, b)
+// lower the parent of the larger of their current parents to the smaller one
+// (atomicMin), then every vertex points at the end of its parent chain.
+// Parents only decrease and stay in the vertex's component, so par[v] <= v
+// holds throughout; after a round without a decrease the ends agree along
+// every net, so every component points at its smallest vertex.
+__global__ void k_cc_hook(const int64_t* ptr, const int32_t* pins, int32_t l, int32_t* par, int32_t* changed) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < l; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = ptr[e], en = ptr[e + 1];
+    for (int64_t p = b + 1; p < en; ++p) {
+      const int32_t ra = par[pins[p - 1]], rb = par[pins[p]];
+      if (ra == rb) continue;
+      const int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+      if (atomicMin(&par[hi], lo) > lo) *changed = 1;
+    }
+  }
+}
+__global__ void k_cc_jump(int32_t* par, int32_t k) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t p = par[v], g = par[p];
+    while (g != p) {  // strictly decreasing ids: ends
+      p = g;
+      g = par[p];
+    }
+    par[v] = p;
+  }
+}
 __global__ void k_cc_final(int32_t* par, int32_t k, int32_t* label) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x)
     label[v] = uf_find(par, (int32_t)v);
@@ -850,7 +877,19 @@ void components(Ctx& c, int32_t k, int32_t l, const int64_t* ptr, const int32_t*
                 hipStream_t s) {
   Buf<int32_t> par(c.pool, k);
   iota_i32(par.p, k, s);
-  if (l > 0) VMO_LAUNCH(k_cc_union, gs_blocks(l), 256, 0, s, ptr, pins, l, par.p);
+  if (l > 0) {
+    // up to kHookRounds hooking rounds (one host check each); the union-find
+    // then finishes from the forest they leave (at once if they converged)
+    constexpr int kHookRounds = 32;
+    Buf<int32_t> changed(c.pool, 1);
+    for (int r = 0; r < kHookRounds; ++r) {
+      fill_i32(changed.p, 0, 1, s);
+      VMO_LAUNCH(k_cc_hook, gs_blocks(l), 256, 0, s, ptr, pins, l, par.p, changed.p);
+      VMO_LAUNCH(k_cc_jump, gs_blocks(k), 256, 0, s, par.p, k);
+      if (read1(changed.p, s) == 0) break;
+    }
+    VMO_LAUNCH(k_cc_union, gs_blocks(l), 256, 0, s, ptr, pins, l, par.p);
+  }
   VMO_LAUNCH(k_cc_final, gs_blocks(k), 256, 0, s, par.p, k, label);
 }
 

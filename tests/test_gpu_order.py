@@ -47,6 +47,21 @@ def test_components(ctx, seed):
     assert np.array_equal(host(lab), oracle.components(h))
 
 
+def test_components_grid(ctx):
+    """One component with long paths and randomly numbered vertices (the
+    symmetric 3-D grid, rows permuted), and the same grid keeping every third
+    edge (many components of all sizes)."""
+    g = vmo_gen.grid3d(40, seed=5)
+    h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
+    lab = host(ctx.components(dev_h(h)))
+    assert np.array_equal(lab, oracle.components(h)) and not lab.any()
+    keep = np.arange(h.l) % 3 == 0
+    nets = [list(h.pins[h.ptr[e]:h.ptr[e + 1]]) for e in range(h.l) if keep[e]]
+    h2 = oracle.hypergraph(h.k, nets)
+    lab2 = host(ctx.components(dev_h(h2)))
+    assert np.array_equal(lab2, oracle.components(h2))
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_cut(ctx, seed):
     g = vmo_gen.random_hypergraph_csr(5000, 4000, seed, maxdeg=9)
