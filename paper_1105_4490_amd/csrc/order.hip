@@ -281,9 +281,12 @@ __global__ void k_seed2(const JobDev* jobs, SegArrays sg, int64_t s0, int64_t S,
 // coordinate and of the segment ids, 4-byte loads and stores of the sides.
 // Bytes of the pack outside [p0, p1) or in segments that do not iterate are
 // written back unchanged (one thread owns each pack).
+// prev: segments still iterating after the previous iteration (NULL: run);
+// when none is, this iteration would skip every segment, so it returns.
 __global__ __launch_bounds__(1024) void k_assign4(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
                                                   int64_t p0, int64_t p1, int it, uint8_t* side,
-                                                  unsigned long long* work) {
+                                                  unsigned long long* work, const int32_t* prev) {
+  if (prev && *prev == 0) return;
   const int64_t b = (p0 & ~int64_t(3)) + 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   const bool inb = b < p1;
   int key[4] = {-1, -1, -1, -1};
@@ -397,7 +400,9 @@ __device__ __forceinline__ void lloyd_fin_seg(const SegArrays& sg, int64_t s, in
   atomicAdd(active, 1);
 }
 
-__global__ void k_lloyd_fin(SegArrays sg, int64_t s0, int64_t S, int it, int t_max, int32_t* active) {
+__global__ void k_lloyd_fin(SegArrays sg, int64_t s0, int64_t S, int it, int t_max, int32_t* active,
+                            const int32_t* prev) {
+  if (prev && *prev == 0) return;
   int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s < s0 + S) lloyd_fin_seg(sg, s, it, t_max, active);
 }
@@ -1012,7 +1017,7 @@ void Engine::launch_offset_copy_ptr(const int64_t* in, int64_t* out, int64_t n, 
   VMO_LAUNCH(k_offset_copy_ptr, gsz(n), kT, 0, s, in, out, n, add);
 }
 
-constexpr int kLloydCheck = 4;
+constexpr int kLloydCheck = 8;
 
 // Seeding and Lloyd iterations for segments [s0, s0+Sn) over positions [p0, p1).
 void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max, bool tuned) {
@@ -1037,10 +1042,14 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
     unsigned long long* tw = timed ? tune_begin(c, kTuneAssign, bucket, cfg, s) : nullptr;
     int ph = prof_begin(c, "assign", 17.0 * (double)np, s, nullptr);
     const int64_t packs = (p1 - (p0 & ~int64_t(3)) + 3) / 4;
-    VMO_LAUNCH(k_assign4, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw);
+    // after an iteration that left no segment iterating the rest return at
+    // once, except the launches that are timed (tuner, profile), which run
+    const int32_t* prev = it > 0 ? active.p + it - 1 : nullptr;
+    VMO_LAUNCH(k_assign4, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw,
+               timed || ph >= 0 ? nullptr : prev);
     prof_end(c, ph, s);
     if (timed) tune_end(c, s);
-    VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p + it);
+    VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p + it, prev);
     // one host check every kLloydCheck iterations: an iteration after the
     // last segment stopped skips every segment, so the extra ones change nothing
     if ((it % kLloydCheck == kLloydCheck - 1 || it == t_max) && read1(active.p + it, s) == 0) break;
