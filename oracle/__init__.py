@@ -33,10 +33,11 @@ SBD, BBD = 0, 1
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle (gcc, -O2, no FP contraction)."""
+    """Compile the C oracle (gcc, -O2, no FP contraction, OpenMP over
+    independent per-vertex loops only)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -172,6 +173,16 @@ def quantize(x):
     rc = lib().o_quantize(C.c_int32(k), _p(x), _p(q), _p(lo), C.byref(s))
     assert rc == 0
     return q, lo, s.value
+
+
+def set_threads(n: int):
+    """Host threads for the oracle's independent per-vertex loops (results do
+    not depend on it)."""
+    lib().o_set_threads(C.c_int(int(n)))
+
+
+def max_threads() -> int:
+    return int(lib().o_max_threads())
 
 
 def splitmix64(seed, n):
@@ -474,6 +485,52 @@ def gradient_sample(h: Hypergraph, x, ids, theta=0.5, leaf_cap=8):
                                  _p(nint))
     assert rc == 0
     return y, nint
+
+
+def gradient_plain(h: Hypergraph, x, theta=0.5, leaf_cap=8, ids=None):
+    """Plain evaluation of eq. (7) (o_gradient_plain): FP64, one running sum
+    per point over the depth-first walk from the root.  Returns (y, s, nint):
+    y [4][n] FP64, s [4][n] the magnitudes that bound an FP32 evaluation's
+    rounding, nint [n] interactions per walk; n = k, or len(ids)."""
+    w, c = _wc(h)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+    n = h.k if ids is None else ids.shape[0]
+    y = np.zeros((4, n), dtype=np.float64)
+    s = np.zeros((4, n), dtype=np.float64)
+    nint = np.zeros(max(n, 1), dtype=np.int64)
+    rc = lib().o_gradient_plain(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(w), _p(c), _p(x),
+                                C.c_float(theta), C.c_int32(leaf_cap), C.c_int32(n), _p(ids), _p(y), _p(s),
+                                _p(nint))
+    assert rc == 0
+    return y, s, nint[:n]
+
+
+def layout_iter_plain(h: Hypergraph, x, params: LayoutParams, it: int, alpha: float = 0.0):
+    """One descent step with the plain gradient (o_layout_iter_plain).
+    Returns (x_new FP32, y FP64, s FP64, alpha)."""
+    w, c = _wc(h)
+    x = np.ascontiguousarray(x, dtype=np.float32).copy()
+    y = np.zeros((4, h.k), dtype=np.float64)
+    s = np.zeros((4, h.k), dtype=np.float64)
+    a = C.c_double(alpha)
+    rc = lib().o_layout_iter_plain(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(w), _p(c), _p(x),
+                                   C.byref(params), C.c_int32(it), C.byref(a), _p(y), _p(s))
+    assert rc == 0
+    return x, y, s, a.value
+
+
+def interactions_reset():
+    """Clears the count of walk interactions kept across strict gradients."""
+    lib().o_interactions_reset()
+
+
+def interactions() -> int:
+    """Walk interactions of every strict gradient since the last reset (e.g.
+    all levels and steps of one layout)."""
+    lib().o_interactions.restype = C.c_int64
+    return int(lib().o_interactions())
 
 
 def layout_iter(h: Hypergraph, x, params: LayoutParams, it: int, alpha: float = 0.0):

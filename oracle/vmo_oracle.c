@@ -7,9 +7,11 @@
  * library behind include/vmo.h) shares no code, header, table or helper with
  * it.  Everything here is written sequentially, in the order the paper
  * states its steps, with the free choices the paper leaves open fixed as
- * listed below.  Compile with -O2 -ffp-contract=off (no contraction: every
- * float and double operation is a single IEEE rounding; the few fused
- * multiply-adds are explicit fmaf calls).
+ * listed below.  Compile with -O2 -ffp-contract=off -fopenmp (no contraction:
+ * every float and double operation is a single IEEE rounding; the few fused
+ * multiply-adds are explicit fmaf calls).  OpenMP runs only loops whose
+ * iterations are independent (one vertex or one sampled point each, its terms
+ * summed in its own fixed order), so the thread count never changes a result.
  *
  * Contents (paper passage in brackets):
  *   o_rng             counter-based SplitMix64 (Steele, Lea, Flood 2014).
@@ -51,7 +53,15 @@
  *                     heavy-net matching, single-neighbour rule, net merge].
  *   o_tree            2^d-tree with cluster charges [Sec. 2.1 tree
  *                     approximation; Algorithm 3 tree and sibling links].
- *   o_layout_iter     one steepest-descent step [Algorithm 3; eq. (7)].
+ *   o_gradient        gradient eq. (7), STRICT mode: FP32, the walk summed in
+ *                     the frozen two-level order of parts that the GPU
+ *                     reproduces bit for bit [Algorithm 3; eq. (7)].
+ *   o_gradient_plain  the same definition evaluated plainly: FP64, one
+ *                     running sum per point over the depth-first walk, no
+ *                     parts, no fused operations; with the magnitudes that
+ *                     bound an FP32 evaluation's rounding [eq. (7)].
+ *   o_layout_iter     one steepest-descent step, strict [Algorithm 3].
+ *   o_layout_iter_plain  one step with the plain gradient, FP64 update.
  *   o_layout          multilevel layout of every component, packed
  *                     [Algorithm 2; Theorem on connectedness].
  *
@@ -82,6 +92,7 @@
  *     SplitMix64.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -103,6 +114,10 @@ uint64_t o_rng(uint64_t seed, uint64_t a, uint64_t b, uint64_t c) {
   h = o_mix64(h + O_GAMMA * (b + 1));
   return o_mix64(h + O_GAMMA * (c + 1));
 }
+
+/* Host threads of the independent per-vertex loops (OpenMP). */
+void o_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int o_max_threads(void) { return omp_get_max_threads(); }
 
 /* n-th output (n >= 1) of the plain SplitMix64 stream started at `seed`. */
 uint64_t o_splitmix64(uint64_t seed, uint64_t n) { return o_mix64(seed + O_GAMMA * n); }
@@ -1046,12 +1061,12 @@ static int node_far(const OTNode* N, const int32_t* p2, double th2) {
 /* Depth-first walk: far node -> one cluster charge; near internal node ->
    its children in order; near leaf -> every other point of the leaf. */
 static void walk_rec(const OTree* T, int32_t t, int32_t n, const float* xn, float wn,
-                     const int32_t* p2, double th2, const float* x, const float* w, float* y) {
+                     const int32_t* p2, double th2, const float* x, const float* w, float* y, int64_t* cnt) {
   const OTNode* N = &T->nd[t];
-  if (node_far(N, p2, th2)) { interact(y, xn, wn, N->X, N->W); return; }
+  if (node_far(N, p2, th2)) { interact(y, xn, wn, N->X, N->W); ++*cnt; return; }
   if (!N->leaf) {
     int32_t ch = t + 1;
-    while (ch != N->next) { walk_rec(T, ch, n, xn, wn, p2, th2, x, w, y); ch = T->nd[ch].next; }
+    while (ch != N->next) { walk_rec(T, ch, n, xn, wn, p2, th2, x, w, y, cnt); ch = T->nd[ch].next; }
     return;
   }
   for (int32_t i = N->first; i < N->first + N->count; ++i) {
@@ -1060,23 +1075,27 @@ static void walk_rec(const OTree* T, int32_t t, int32_t n, const float* xn, floa
     float xv[4];
     for (int d = 0; d < 4; ++d) xv[d] = x[(size_t)d * T->k + v];
     interact(y, xn, wn, xv, w[v]);
+    ++*cnt;
   }
 }
 
-/* Repulsion of point n, added to yn.  The walk's interactions are summed in
-   two levels of parts.  A root that is a leaf or far from the point is a
-   single part.  Otherwise each child c of the root gives one part, added to
-   yn in child order; the part of a child that is a leaf or far from the point
-   is its walk summed from zero, and the part of any other child is the sum,
-   in child order and from zero, of the walks over its own children, each
-   summed from zero.  (The paper fixes no summation order; this one lets the
-   walks over the cells of the first two levels run independently.) */
+/* Repulsion of point n, added to yn (STRICT order).  The walk's
+   interactions are summed in two levels of parts.  A root that is a leaf or
+   far from the point is a single part.  Otherwise each child c of the root
+   gives one part, added to yn in child order; the part of a child that is a
+   leaf or far from the point is its walk summed from zero, and the part of
+   any other child is the sum, in child order and from zero, of the walks over
+   its own children, each summed from zero.  The paper fixes no summation
+   order; this one is frozen as the strict mode that the GPU reproduces bit
+   for bit (it lets the walks over the cells of the first two levels run
+   independently).  The plain evaluation of the same definition, with no
+   parts, is o_gradient_plain below.  *cnt += interactions evaluated. */
 static void repulsion(const OTree* T, int32_t n, const float* xn, float wn, const int32_t* p2, double th2,
-                      const float* x, const float* w, float* yn) {
+                      const float* x, const float* w, float* yn, int64_t* cnt) {
   const OTNode* R = &T->nd[0];
   if (R->leaf || node_far(R, p2, th2)) {
     float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    walk_rec(T, 0, n, xn, wn, p2, th2, x, w, acc);
+    walk_rec(T, 0, n, xn, wn, p2, th2, x, w, acc, cnt);
     for (int d = 0; d < 4; ++d) yn[d] = yn[d] + acc[d];
     return;
   }
@@ -1084,11 +1103,11 @@ static void repulsion(const OTree* T, int32_t n, const float* xn, float wn, cons
     const OTNode* N1 = &T->nd[c1];
     float acc1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (N1->leaf || node_far(N1, p2, th2)) {
-      walk_rec(T, c1, n, xn, wn, p2, th2, x, w, acc1);
+      walk_rec(T, c1, n, xn, wn, p2, th2, x, w, acc1, cnt);
     } else {
       for (int32_t c2 = c1 + 1; c2 != N1->next; c2 = T->nd[c2].next) {
         float acc2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        walk_rec(T, c2, n, xn, wn, p2, th2, x, w, acc2);
+        walk_rec(T, c2, n, xn, wn, p2, th2, x, w, acc2, cnt);
         for (int d = 0; d < 4; ++d) acc1[d] = acc1[d] + acc2[d];
       }
     }
@@ -1108,8 +1127,16 @@ static void centres(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pin
   }
 }
 
+/* Interactions evaluated by the tree walks of every gradient since the last
+   reset (all levels and steps of a layout). */
+static int64_t g_interactions;
+void o_interactions_reset(void) { g_interactions = 0; }
+int64_t o_interactions(void) { return g_interactions; }
+
 /* Gradient (eq. 7): attraction over the vertex's nets in ascending net
-   order, then the tree walk.  y is [4][k]. */
+   order, then the tree walk.  y is [4][k].  The per-vertex loops are
+   independent (each vertex's terms and their order are its own), so they run
+   on all host threads without changing a bit of the result. */
 static int gradient(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
                     const float* c, const float* x, float theta, int32_t cap, float* y) {
   float* z = (float*)malloc(sizeof(float) * 4 * (size_t)(l > 0 ? l : 1));
@@ -1117,6 +1144,7 @@ static int gradient(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pin
   int64_t* dptr = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k + 1));
   int32_t* dp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ptr[l] > 0 ? ptr[l] : 1));
   o_dual(k, l, ptr, pins, dptr, dp);
+#pragma omp parallel for schedule(static)
   for (int32_t n = 0; n < k; ++n) {
     for (int d = 0; d < 4; ++d) {
       float a = 0.0f;
@@ -1133,6 +1161,8 @@ static int gradient(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pin
   OTree T;
   if (otree_build(&T, k, x, w, cap)) { otree_free(&T); return -1; }
   double th2 = (double)theta * (double)theta;
+  int64_t nint = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nint)
   for (int32_t n = 0; n < k; ++n) {
     float xn[4], yn[4];
     int32_t p2[4];
@@ -1141,9 +1171,10 @@ static int gradient(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pin
       yn[d] = y[(size_t)d * k + n];
       p2[d] = 2 * (int32_t)T.kq[(size_t)d * k + n] + 1;
     }
-    repulsion(&T, n, xn, w[n], p2, th2, x, w, yn);
+    repulsion(&T, n, xn, w[n], p2, th2, x, w, yn, &nint);
     for (int d = 0; d < 4; ++d) y[(size_t)d * k + n] = yn[d];
   }
+  g_interactions += nint;
   otree_free(&T);
   return 0;
 }
@@ -1155,41 +1186,43 @@ int o_gradient(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, co
   return gradient(k, l, ptr, pins, w, c, x, theta, cap, y);
 }
 
+/* First step length of a level: step0 * V^(1/4), V = volume of the bounding
+   box of x (if V = 0, the largest side replaces V^(1/4)), in FP64. */
+static double step_length0(int32_t k, const float* x, const o_layout_params* P) {
+  float lo[4], hi[4];
+  for (int d = 0; d < 4; ++d) {
+    lo[d] = hi[d] = x[(size_t)d * k];
+    for (int32_t i = 0; i < k; ++i) {
+      float v = x[(size_t)d * k + i];
+      if (v < lo[d]) lo[d] = v;
+      if (v > hi[d]) hi[d] = v;
+    }
+  }
+  double V = 1.0, ext = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    double e = (double)hi[d] - (double)lo[d];
+    V = V * e;
+    if (e > ext) ext = e;
+  }
+  double side = V > 0.0 ? sqrt(sqrt(V)) : ext;
+  return (double)P->step0_frac * side;
+}
+
 /* One steepest-descent step (Algorithm 3).  it = step index at this level;
-   *alpha carries the step length between calls.  At it == 0 it is set from
-   the bounding box, alpha = step0 * V^(1/4) (V = box volume; if V = 0 the
-   largest side replaces V^(1/4)); afterwards alpha <- decay * alpha.  Each
-   vertex is then moved a distance alpha against its own gradient:
-   x_n <- x_n - (alpha / |y_n|) y_n  (vertices with y_n = 0 stay).  This is
-   the reading of "comparing the bounding box volume to the individual
-   gradients of the vertices" with the step rule of the cited force-directed
-   method (Hu 2005). */
+   *alpha carries the step length between calls: at it == 0 it is set by
+   step_length0, afterwards alpha <- decay * alpha.  Each vertex is then moved
+   a distance alpha against its own gradient: x_n <- x_n - (alpha / |y_n|) y_n
+   (vertices with y_n = 0 stay).  Sec. 2.3 sets the step by weighing the size
+   of the bounding box against the vertices' own gradients; this is read as
+   the step rule of the force-directed method the paper cites (Hu 2005): a
+   fixed length for every vertex, shrinking by a constant factor per step. */
 int o_layout_iter(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
                   const float* c, float* x, const o_layout_params* P, int32_t it, double* alpha,
                   float* y_out) {
   float* y = (float*)malloc(sizeof(float) * 4 * (size_t)k);
   if (gradient(k, l, ptr, pins, w, c, x, P->theta, P->leaf_cap, y)) { free(y); return -1; }
-  if (it == 0) {
-    float lo[4], hi[4];
-    for (int d = 0; d < 4; ++d) {
-      lo[d] = hi[d] = x[(size_t)d * k];
-      for (int32_t i = 0; i < k; ++i) {
-        float v = x[(size_t)d * k + i];
-        if (v < lo[d]) lo[d] = v;
-        if (v > hi[d]) hi[d] = v;
-      }
-    }
-    double V = 1.0, ext = 0.0;
-    for (int d = 0; d < 4; ++d) {
-      double e = (double)hi[d] - (double)lo[d];
-      V = V * e;
-      if (e > ext) ext = e;
-    }
-    double side = V > 0.0 ? sqrt(sqrt(V)) : ext;
-    *alpha = (double)P->step0_frac * side;
-  } else {
-    *alpha = *alpha * (double)P->decay;
-  }
+  if (it == 0) *alpha = step_length0(k, x, P);
+  else *alpha = *alpha * (double)P->decay;
   for (int32_t i = 0; i < k; ++i) {
     float yv[4];
     for (int d = 0; d < 4; ++d) yv[d] = y[(size_t)d * k + i];
@@ -1396,19 +1429,6 @@ int o_layout(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, cons
 /* Gradient at a sample of vertices (for checks at full size): y[4][ns] for
    the vertices ids[0..ns), plus the number of charge interactions each one's
    walk performed (far nodes + leaf pairs, zero-distance pairs included). */
-static int64_t g_walk_count;
-static void walk_count_rec(const OTree* T, int32_t t, int32_t n, const int32_t* p2, double th2) {
-  const OTNode* N = &T->nd[t];
-  if (node_far(N, p2, th2)) { g_walk_count++; return; }
-  if (!N->leaf) {
-    int32_t ch = t + 1;
-    while (ch != N->next) { walk_count_rec(T, ch, n, p2, th2); ch = T->nd[ch].next; }
-    return;
-  }
-  for (int32_t i = N->first; i < N->first + N->count; ++i)
-    if (T->order[i] != n) g_walk_count++;
-}
-
 int o_gradient_sample(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
                       const float* c, const float* x, float theta, int32_t cap, int32_t ns,
                       const int32_t* ids, float* y, int64_t* nint) {
@@ -1420,6 +1440,7 @@ int o_gradient_sample(int32_t k, int32_t l, const int64_t* ptr, const int32_t* p
   OTree T;
   if (otree_build(&T, k, x, w, cap)) { otree_free(&T); free(z); free(dptr); free(dp); return -1; }
   double th2 = (double)theta * (double)theta;
+#pragma omp parallel for schedule(dynamic, 16)
   for (int32_t s = 0; s < ns; ++s) {
     int32_t n = ids[s];
     float xn[4], yn[4];
@@ -1436,11 +1457,155 @@ int o_gradient_sample(int32_t k, int32_t l, const int64_t* ptr, const int32_t* p
       xn[d] = x[(size_t)d * k + n];
       p2[d] = 2 * (int32_t)T.kq[(size_t)d * k + n] + 1;
     }
-    repulsion(&T, n, xn, w[n], p2, th2, x, w, yn);
+    int64_t cnt = 0;
+    repulsion(&T, n, xn, w[n], p2, th2, x, w, yn, &cnt);
     for (int d = 0; d < 4; ++d) y[(size_t)d * ns + s] = yn[d];
-    if (nint) { g_walk_count = 0; walk_count_rec(&T, 0, n, p2, th2); nint[s] = g_walk_count; }
+    if (nint) nint[s] = cnt;
   }
   otree_free(&T); free(z); free(dptr); free(dp);
+  return 0;
+}
+
+/* ---- plain evaluation of eq. (7) ------------------------------------------ */
+/* The gradient of eq. (6) as eq. (7) states it, evaluated plainly: every
+   operation in FP64 (one rounding each, no fused multiply-add), net centres
+   z_e = (sum of the pins' coordinates) / |e|, the attraction
+   sum_e c_e (x_n - z_e) over the vertex's nets in ascending net order, then
+   the repulsion as ONE running sum per point over the depth-first walk of
+   Algorithm 3 from the root: a far node adds one term with the node's charge
+   W at its weighted centre X (the tree as built above: integer far test,
+   theta, leaf size; charges W and X as stored), a near internal node is
+   entered child by child, a near leaf adds a term for each of its other
+   points.  One term is (d - 2) W w_n (X - x_n) / |X - x_n|^4 with d = 4; a
+   term at zero distance is left out (the point itself, coincident points).
+   Nothing here follows the GPU's division of the walk into parts.
+
+   s (per point and coordinate) is the magnitude against which the FP32
+   evaluation's rounding is measured: for each attraction term
+   c_e (|x_n| + mean over the pins of |x_p|) (the operands of the centre and
+   of the difference), and for each repulsion term its absolute value.  An
+   FP32 evaluation of the same terms in any order differs from y by a few
+   units of 2^-24 times s, times a factor that grows with the number of
+   terms. */
+static void plain_term(double* y, double* s, const float* xn, double wn, const float* X, double W) {
+  double dx[4], r2 = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    dx[d] = (double)X[d] - (double)xn[d];
+    r2 = r2 + dx[d] * dx[d];
+  }
+  if (!(r2 > 0.0)) return;
+  double f = 2.0 * W * wn / (r2 * r2);
+  for (int d = 0; d < 4; ++d) {
+    double t = f * dx[d];
+    y[d] = y[d] + t;
+    s[d] = s[d] + fabs(t);
+  }
+}
+
+static void walk_plain(const OTree* T, int32_t t, int32_t n, const float* xn, double wn, const int32_t* p2,
+                       double th2, const float* x, const float* w, double* y, double* s, int64_t* cnt) {
+  const OTNode* N = &T->nd[t];
+  if (node_far(N, p2, th2)) { plain_term(y, s, xn, wn, N->X, (double)N->W); ++*cnt; return; }
+  if (!N->leaf) {
+    for (int32_t ch = t + 1; ch != N->next; ch = T->nd[ch].next)
+      walk_plain(T, ch, n, xn, wn, p2, th2, x, w, y, s, cnt);
+    return;
+  }
+  for (int32_t i = N->first; i < N->first + N->count; ++i) {
+    int32_t v = T->order[i];
+    if (v == n) continue;
+    float xv[4];
+    for (int d = 0; d < 4; ++d) xv[d] = x[(size_t)d * T->k + v];
+    plain_term(y, s, xn, wn, xv, (double)w[v]);
+    ++*cnt;
+  }
+}
+
+/* Plain gradient at the vertices ids[0..ns) (ids == NULL: all k, ns = k).
+   y, s: [4][ns] FP64; nint (or NULL): [ns] interactions of each walk. */
+int o_gradient_plain(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+                     const float* c, const float* x, float theta, int32_t cap, int32_t ns, const int32_t* ids,
+                     double* y, double* s, int64_t* nint) {
+  if (!ids) ns = k;
+  double* z = (double*)malloc(sizeof(double) * 4 * (size_t)(l > 0 ? l : 1));
+  double* za = (double*)malloc(sizeof(double) * 4 * (size_t)(l > 0 ? l : 1));
+  for (int32_t e = 0; e < l; ++e) {
+    double sz = (double)(ptr[e + 1] - ptr[e]);
+    for (int d = 0; d < 4; ++d) {
+      double a = 0.0, b = 0.0;
+      for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) {
+        double v = (double)x[(size_t)d * k + pins[p]];
+        a = a + v;
+        b = b + fabs(v);
+      }
+      z[(size_t)d * l + e] = sz > 0.0 ? a / sz : 0.0;
+      za[(size_t)d * l + e] = sz > 0.0 ? b / sz : 0.0;
+    }
+  }
+  int64_t* dptr = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k + 1));
+  int32_t* dp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ptr[l] > 0 ? ptr[l] : 1));
+  o_dual(k, l, ptr, pins, dptr, dp);
+  OTree T;
+  if (otree_build(&T, k, x, w, cap)) { otree_free(&T); free(z); free(za); free(dptr); free(dp); return -1; }
+  double th2 = (double)theta * (double)theta;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t i = 0; i < ns; ++i) {
+    int32_t n = ids ? ids[i] : i;
+    double yn[4], sn[4];
+    float xn[4];
+    int32_t p2[4];
+    for (int d = 0; d < 4; ++d) {
+      double xv = (double)x[(size_t)d * k + n];
+      double a = 0.0, b = 0.0;
+      for (int64_t t = dptr[n]; t < dptr[n + 1]; ++t) {
+        int32_t e = dp[t];
+        double ce = c ? (double)c[e] : 1.0;
+        a = a + ce * (xv - z[(size_t)d * l + e]);
+        b = b + ce * (fabs(xv) + za[(size_t)d * l + e]);
+      }
+      yn[d] = a;
+      sn[d] = b;
+      xn[d] = x[(size_t)d * k + n];
+      p2[d] = 2 * (int32_t)T.kq[(size_t)d * k + n] + 1;
+    }
+    int64_t cnt = 0;
+    walk_plain(&T, 0, n, xn, (double)w[n], p2, th2, x, w, yn, sn, &cnt);
+    for (int d = 0; d < 4; ++d) {
+      y[(size_t)d * ns + i] = yn[d];
+      s[(size_t)d * ns + i] = sn[d];
+    }
+    if (nint) nint[i] = cnt;
+  }
+  otree_free(&T); free(z); free(za); free(dptr); free(dp);
+  return 0;
+}
+
+/* One descent step (Algorithm 3) with the plain gradient: the step length is
+   set as in o_layout_iter, and each vertex moves by it along -y_n/|y_n| in
+   FP64, the new coordinates rounded to FP32.  y_out (or NULL): [4][k] FP64,
+   s_out (or NULL): the magnitudes of o_gradient_plain. */
+int o_layout_iter_plain(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* w,
+                        const float* c, float* x, const o_layout_params* P, int32_t it, double* alpha,
+                        double* y_out, double* s_out) {
+  double* y = (double*)malloc(sizeof(double) * 4 * (size_t)k);
+  double* s = (double*)malloc(sizeof(double) * 4 * (size_t)k);
+  if (o_gradient_plain(k, l, ptr, pins, w, c, x, P->theta, P->leaf_cap, k, NULL, y, s, NULL)) {
+    free(y); free(s);
+    return -1;
+  }
+  if (it == 0) *alpha = step_length0(k, x, P);
+  else *alpha = *alpha * (double)P->decay;
+  for (int32_t i = 0; i < k; ++i) {
+    double n2 = 0.0;
+    for (int d = 0; d < 4; ++d) n2 = n2 + y[(size_t)d * k + i] * y[(size_t)d * k + i];
+    if (!(n2 > 0.0)) continue;
+    double f = *alpha / sqrt(n2);
+    for (int d = 0; d < 4; ++d)
+      x[(size_t)d * k + i] = (float)((double)x[(size_t)d * k + i] - f * y[(size_t)d * k + i]);
+  }
+  if (y_out) memcpy(y_out, y, sizeof(double) * 4 * (size_t)k);
+  if (s_out) memcpy(s_out, s, sizeof(double) * 4 * (size_t)k);
+  free(y); free(s);
   return 0;
 }
 

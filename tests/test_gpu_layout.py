@@ -1,10 +1,15 @@
 """GPU parity of the layout (Sec. 2) against the CPU oracle, through the C
 ABI: the 2^d-tree (exact node arrays and charges), the gradient of eq. (7)
 (net centres, attraction, tree walk), descent steps of Algorithm 3,
-coarsening (Sec. 2.3), and the full multilevel layout.  The arithmetic is
-specified operation by operation on both sides, so the float results are
-compared bit for bit; where a tolerance is stated it is the coordinate
-tolerance |dx| <= 1e-5 * (bounding-box diagonal)."""
+coarsening (Sec. 2.3), and the full multilevel layout.
+
+Two references.  STRICT: the oracle's FP32 evaluation in the frozen order of
+parts, which the GPU reproduces bit for bit (compared with array_equal).
+PLAIN: eq. (7) evaluated in FP64 as one running sum per point over the
+depth-first walk (oracle.gradient_plain), which shares no order with the
+GPU; gradients are compared element by element at |dy| <= 1e-5 * s (s: the
+magnitudes of the terms, the scale of FP32 rounding), coordinates at
+|dx| <= 1e-5 * max(|x_ref|, bounding-box diagonal)."""
 import numpy as np
 import pytest
 import torch
@@ -222,3 +227,104 @@ def test_full_size_gradient_sampled(ctx, side):
     y, cnt = oracle.gradient_sample(h, x, ids)
     assert np.array_equal(host(gy)[:, ids], y)
     assert nint > 0
+
+
+# --------------------------------------------- plain reference, tolerance ----
+
+def check_plain_gradient(gy, y, s):
+    gy = np.asarray(gy, np.float64)
+    bad = np.abs(gy - y) > 1e-5 * s
+    assert not bad.any(), (int(bad.sum()), float((np.abs(gy - y) / np.maximum(s, 1e-300)).max()))
+
+
+@pytest.mark.parametrize("seed,k,l,theta", [(1, 300, 200, 0.0), (2, 3000, 2500, 0.5), (4, 4096, 3000, 0.5),
+                                           (5, 4097, 3000, 0.5), (3, 40000, 30000, 0.5)])
+def test_gradient_against_plain(ctx, seed, k, l, theta):
+    """vmo_gradient against the plain FP64 evaluation of eq. (7), element by
+    element; the kernel's interaction count equals the plain walks' total at
+    every size."""
+    h = weighted_case(seed, k, l)
+    x = vmo_gen.random_points(k, seed, clusters=6)
+    y, s, nint = oracle.gradient_plain(h, x, theta=theta)
+    gy, _, gcount = ctx.gradient(dev_h(h), dev_x(x), theta=theta)
+    check_plain_gradient(host(gy), y, s)
+    assert gcount == int(nint.sum())
+
+
+@pytest.mark.parametrize("k", [3000, 9000])
+def test_gradient_coincident_points_against_plain(ctx, k):
+    h = weighted_case(11, k, k // 2)
+    x = np.round(vmo_gen.random_points(k, 11, clusters=3)).astype(np.float32)
+    y, s, nint = oracle.gradient_plain(h, x, theta=0.5)
+    gy, _, gcount = ctx.gradient(dev_h(h), dev_x(x), theta=0.5)
+    check_plain_gradient(host(gy), y, s)
+    assert gcount == int(nint.sum())
+
+
+@pytest.mark.parametrize("side", [48, 64])
+def test_full_size_gradient_against_plain(ctx, side):
+    """The 7-point pattern of side^3 vertices (64: the benchmark size), at
+    clustered coordinates: every vertex's gradient against the plain
+    evaluation, and the walk's interaction count (the numerator of the
+    measured flop rate) against the plain walks' total."""
+    g = vmo_gen.grid3d(side, seed=1)
+    h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
+    x = vmo_gen.random_points(h.k, side, clusters=64, spread=0.3)
+    y, s, nint = oracle.gradient_plain(h, x)
+    gy, _, gcount = ctx.gradient(dev_h(h), dev_x(x))
+    check_plain_gradient(host(gy), y, s)
+    assert gcount == int(nint.sum())
+
+
+def check_plain_step(gx, xr):
+    diag = float(np.linalg.norm(xr.max(axis=1).astype(np.float64) - xr.min(axis=1)))
+    tol = 1e-5 * np.maximum(np.abs(xr.astype(np.float64)), diag)
+    err = np.abs(gx.astype(np.float64) - xr)
+    assert (err <= tol).all(), (int((err > tol).sum()), float(err.max()), diag)
+
+
+@pytest.mark.parametrize("case", ["grid", "weighted", "grid3d"])
+def test_descent_steps_against_plain(ctx, case):
+    """Twelve descent steps of Algorithm 3, one call each: every GPU step,
+    from the GPU's own state, against the plain FP64 step from the same FP32
+    state (same tree decisions; only the rounding differs).  The step length
+    is set from the same box in FP64 on both sides and must agree exactly."""
+    import paper_1105_4490_amd as P
+    if case == "grid":
+        g = vmo_gen.grid2d(24)
+        h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+    elif case == "weighted":
+        h = weighted_case(7, 2000, 1500)
+    else:
+        g = vmo_gen.grid3d(34, seed=3)       # 39,304 vertices: the multi-kernel tree, spread walk
+        h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
+    p = oracle.layout_params(seed=3)
+    gp = P.layout_params(seed=3)
+    dh = dev_h(h)
+    gx = dev_x(oracle.layout_init(h.k, 3))
+    ga = 0.0
+    for it in range(12):
+        x0 = host(gx).copy()
+        xr, _, _, a = oracle.layout_iter_plain(h, x0, p, it, ga)
+        ga = ctx.layout_steps(dh, gx, gp, it, 1, ga)
+        assert ga == a
+        check_plain_step(host(gx), xr)
+
+
+def test_descent_steps_40k_strict(ctx):
+    """Twelve strict descent steps at 39,304 points (the multi-kernel tree
+    build, the spread walk, k_attract above 16,384 points, the step applied by
+    k_combine), bit for bit against the oracle's strict steps."""
+    import paper_1105_4490_amd as P
+    g = vmo_gen.grid3d(34, seed=3)
+    h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
+    p = oracle.layout_params(seed=3)
+    gp = P.layout_params(seed=3)
+    x = oracle.layout_init(h.k, 3)
+    xo, a = x.copy(), 0.0
+    for it in range(12):
+        xo, _, a = oracle.layout_iter(h, xo, p, it, a)
+    gx = dev_x(x)
+    ga = ctx.layout_steps(dev_h(h), gx, gp, 0, 12, 0.0)
+    assert ga == a
+    assert np.array_equal(host(gx), xo)

@@ -93,6 +93,22 @@ def test_bisect(ctx, k, seed, clusters):
     assert got["iters"] == ref.iters
 
 
+def test_bisect_d2_draw_hand_derived(ctx):
+    """The k-means++ draw of golden/d2_draw.json (t on a prefix sum exactly):
+    with t_max = 0 vmo_bisect reports the seed points as the centres."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "d2_draw.json")) as f:
+        g = json.load(f)
+    q = np.array(g["points_q"], dtype=np.int64)
+    x = np.ascontiguousarray(q.T.astype(np.float32))
+    got = ctx.bisect(dev_x(x), g["seed"], t_max=0)
+    cen = host(got["centres"])
+    assert got["split"] and got["iters"] == 0
+    assert np.array_equal(cen[0], q[g["i1"]].astype(np.float32))
+    assert np.array_equal(cen[1], q[g["i2"]].astype(np.float32))
+
+
 def test_bisect_degenerate(ctx):
     for x in (np.ones((4, 50), np.float32), np.zeros((4, 1), np.float32)):
         got = ctx.bisect(dev_x(x), 1)

@@ -127,3 +127,32 @@ def test_seed_determinism_and_dependence():
     assert np.array_equal(a.side, b.side) and np.array_equal(a.centres, b.centres)
     sides = {oracle.bisect(x, s).side.tobytes() for s in range(8)}
     assert len(sides) >= 2   # a uniform blob has several Lloyd fixed points
+
+
+def test_d2_draw_index_hand_derived():
+    """k-means++ (Algorithm 4, m = 2): golden/d2_draw.json is a case where t
+    equals an inclusive prefix sum of the D^2 weights exactly, so the draw
+    rule alone decides z2 (the strict rule takes the next point; '>=' or an
+    exclusive prefix would take others).  With t_max = 0 the reported centres
+    are the seeds themselves; the points sit on the 2^20 grid at scale 1, so
+    the centres are the seed points exactly."""
+    with open(os.path.join(GOLD, "d2_draw.json")) as f:
+        g = json.load(f)
+    seed = g["seed"]
+    assert oracle.rng(seed, 16, 1, 0) == int(g["r0"]) and oracle.rng(seed, 16, 1, 1) == int(g["r1"])
+    q = np.array(g["points_q"], dtype=np.int64)
+    # the stored draw, re-derived from its stated definition
+    n = g["n"]
+    i1 = (int(g["r0"]) * n) >> 64
+    d = [int(((q[i] - q[i1]) ** 2).sum()) for i in range(n)]
+    T = sum(d)
+    t = (int(g["r1"]) * T) >> 64
+    assert (i1, [str(v) for v in d], str(T), str(t)) == (g["i1"], g["d"], g["T"], g["t"])
+    x = np.ascontiguousarray(q.T.astype(np.float32))
+    qq, lo, s = oracle.quantize(x)
+    assert s == 1.0 and (lo == 0).all() and np.array_equal(qq, q.T.astype(np.uint32))
+    r = oracle.bisect(x, seed=seed, t_max=0)
+    assert r.split and r.iters == 0
+    assert np.array_equal(r.centres[0], q[g["i1"]].astype(np.float32))
+    assert np.array_equal(r.centres[1], q[g["i2"]].astype(np.float32))
+    assert g["i2"] not in (g["i2_if_ge"], g["i2_if_exclusive_prefix"])

@@ -4,11 +4,16 @@ general form eq. (5); exact scaling laws of its two terms (Sec. 2.1); the
 tree's geometry against an independent Morton ordering; the coarsening
 against the characterisation of the greedy matching; and end-to-end sanity
 (the 2-D grid's optimal first cut, separated components)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import vmo_gen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def energy(h, x, w, c):
@@ -320,3 +325,106 @@ def test_layout_disconnected_components_packed_apart():
     x = oracle.layout(h, oracle.layout_params(seed=2, pack_gap=3.0))
     o = oracle.order(h, x, 2, 1)
     assert o.split_cut[:o.n_nodes].max() == 0
+
+
+# ------------------------------------------------ plain evaluation of eq. (7) ----
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_plain_gradient_theta0_is_the_direct_sum(seed):
+    """theta = 0 opens every node: the plain walk is then the direct O(k^2)
+    sum of eq. (7), here recomputed with numpy in FP64; every walk meets the
+    k - 1 other points."""
+    h, x = small_case(seed, k=60, l=40)
+    y, s, nint = oracle.gradient_plain(h, x, theta=0.0)
+    y7 = grad_eq7(h, x, h.w.astype(np.float64), h.c.astype(np.float64))
+    assert np.abs(y - y7).max() <= 1e-12 * np.abs(y7).max()
+    assert (nint == h.k - 1).all()
+    assert (s >= np.abs(y) * (1 - 1e-12)).all()
+
+
+@pytest.mark.parametrize("seed,k", [(6, 600), (7, 3000)])
+def test_strict_fp32_gradient_within_rounding_of_plain(seed, k):
+    """The strict FP32 evaluation (the order the GPU reproduces) agrees with
+    the plain FP64 one to 1e-5 of the rounding magnitudes s, element by
+    element, and both walks make the same interactions."""
+    g = vmo_gen.random_hypergraph_csr(k, k // 2, seed, maxdeg=5)
+    h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+    h.w = vmo_gen.rng(seed, 5).uniform(0.5, 2.0, size=k).astype(np.float32)
+    x = vmo_gen.random_points(k, seed, clusters=6)
+    y32, _ = oracle.gradient(h, x, theta=0.5)
+    y, s, nint = oracle.gradient_plain(h, x, theta=0.5)
+    assert (np.abs(y32 - y) <= 1e-5 * s).all()
+    _, cnt = oracle.gradient_sample(h, x, np.arange(k), theta=0.5)
+    assert np.array_equal(nint, cnt)
+    ys, ss, ns = oracle.gradient_plain(h, x, theta=0.5, ids=np.array([5, 0, k - 1], np.int32))
+    assert np.array_equal(ys, y[:, [5, 0, k - 1]]) and np.array_equal(ns, nint[[5, 0, k - 1]])
+
+
+def test_plain_step_two_points_by_hand():
+    """Two points joined by one net, unit weights: x0 = 0, x1 = (1,1,1,1).
+    Attraction: z = (1/2)(1,1,1,1), so y0 = -(1/2)(1,1,1,1); repulsion on
+    point 0: 2 w w (x1 - x0) / |x1 - x0|^4 = 2 (1,1,1,1) / 16; hence
+    y0 = -(3/8)(1,1,1,1) and y1 = -y0.  The box is the unit cube, V = 1,
+    so alpha = step0_frac (0.1f); each point moves alpha along -y/|y|:
+    x0 -> (alpha/2)(1,1,1,1), x1 -> (1 - alpha/2)(1,1,1,1)."""
+    h = oracle.hypergraph(2, [[0, 1]])
+    x = np.zeros((4, 2), np.float32)
+    x[:, 1] = 1.0
+    p = oracle.layout_params()
+    xn, y, s, alpha = oracle.layout_iter_plain(h, x, p, 0)
+    assert np.array_equal(y[:, 0], np.full(4, -0.375)) and np.array_equal(y[:, 1], np.full(4, 0.375))
+    a = float(np.float32(0.1))
+    assert alpha == a
+    assert np.array_equal(xn[:, 0], np.full(4, np.float32(a / 2)))
+    assert np.array_equal(xn[:, 1], np.full(4, np.float32(1 - a / 2)))
+    # the strict step takes the same values here (every operation exact or
+    # rounded once to the same float)
+    xs, ys, a2 = oracle.layout_iter(h, x, p, 0)
+    assert a2 == alpha and np.array_equal(ys, y.astype(np.float32))
+    assert np.abs(xs - xn).max() <= 2 ** -24
+
+
+def test_strict_step_two_points_flat_box_by_hand():
+    """x0 = 0, x1 = (2,0,0,0), one net: y0 = (-1,0,0,0) + 2 (2,0,0,0)/16 =
+    (-3/4,0,0,0).  The box is flat (V = 0), so its largest side, 2, replaces
+    V^(1/4): alpha = 0.2 (from 0.1f); the points move to (alpha,0,0,0) and
+    (2 - alpha,0,0,0) up to the FP32 roundings of the step, f = fl(alpha /
+    |y|) then fl(f y), and the next step is 0.9f times as long."""
+    h = oracle.hypergraph(2, [[0, 1]])
+    x = np.zeros((4, 2), np.float32)
+    x[0, 1] = 2.0
+    p = oracle.layout_params()
+    x1, y, alpha = oracle.layout_iter(h, x, p, 0)
+    assert np.array_equal(y[:, 0], np.array([-0.75, 0, 0, 0], np.float32))
+    assert alpha == 2.0 * float(np.float32(0.1))
+    f = np.float32(alpha / 0.75)
+    t = np.float32(f * np.float32(0.75))
+    assert abs(float(t) - alpha) <= 2 ** -24 * 2
+    assert np.array_equal(x1[:, 0], np.array([t, 0, 0, 0], np.float32))
+    assert np.array_equal(x1[:, 1], np.array([np.float32(2.0) - t, 0, 0, 0], np.float32))
+    _, _, a2 = oracle.layout_iter(h, x1, p, 1, alpha)
+    assert a2 == alpha * float(np.float32(0.9))
+
+
+def test_init_and_prolong_values_hand_derived():
+    """Algorithm 2's random start and prolongation at one vertex, against
+    exact values derived by hand from the random words
+    (golden/init_prolong.json): k = 16 gives k^(1/4) = 2, so the start is
+    (top 24 bits - 2^23) / 2^23; the prolongation 16 -> 256 has sigma = 2
+    and eps = 2^-10 * 8 / 2, and its one rounding is that of the final sum."""
+    with open(os.path.join(GOLD, "init_prolong.json")) as f:
+        g = json.load(f)
+    gi = g["init"]
+    x = oracle.layout_init(gi["k"], g["seed"], g["comp"], gi["level"])
+    for d, val in enumerate(gi["values"]):
+        r = int(val["r"])
+        assert oracle.rng(g["seed"], 1 | (gi["level"] << 8) | (g["comp"] << 32), gi["v"], d) == r
+        assert val["top24"] == r >> 40
+        assert x[d, gi["v"]] == np.float32(val["x"])
+    gp = g["prolong"]
+    xc = np.array(gp["xc"], np.float32)
+    pi = np.array(gp["pi"], np.int32)
+    xf = oracle.layout_prolong(pi, xc, g["seed"], g["comp"], gp["fine_level"], jitter=gp["jitter"])
+    for d, val in enumerate(gp["values"]):
+        assert oracle.rng(g["seed"], 2 | (gp["fine_level"] << 8) | (g["comp"] << 32), gp["v"], d) == int(val["r"])
+        assert xf[d, gp["v"]] == np.float32(val["x"])
