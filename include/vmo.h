@@ -103,8 +103,10 @@ vmo_status vmo_components(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, 
    more than one diagonal block; the cut-net metric of the footnote there;
    Table 4 takes the maximum over splits).  lambda(e) = number of distinct
    values of part[] over the pins of net e.  Part ids are >= 0 and below
-   2^30.  part_weight[p] (optional, [nparts]) = sum of w over part p < nparts.
-   Integral costs give exact sums; other costs are summed in FP64. */
+   2^30.  part_weight[p] (optional, [nparts]) = sum of w over part p < nparts,
+   added in FP64 one vertex at a time in ascending vertex id.  Integral costs
+   give exact sums; other costs are summed in FP64 in a fixed order (the same
+   on every run). */
 typedef struct {
   double lambda_minus_one; /* sum_e c(e) max(lambda(e) - 1, 0) */
   double cut_net;          /* sum of c(e) over nets with lambda(e) > 1 */
@@ -112,6 +114,22 @@ typedef struct {
 } vmo_cut_result;
 vmo_status vmo_cut(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, int32_t nparts,
                    double* part_weight, vmo_cut_result* out /* (host) */, vmo_stream stream);
+
+/* vmo_cut for callers that cannot allocate memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the same
+   kernels and the same results as vmo_cut, with every workspace block taken
+   from a static 64 MiB device arena that the library holds on each GPU it
+   runs on until the process ends.  It calls no hipMalloc, hipFree or other
+   allocating routine.  Limits: at most 2^20 vertices and 2^20 nets
+   (VMO_E_UNSUPPORTED beyond, before any work), and the arena must hold the
+   call's blocks (about 12 bytes per net, 16 bytes per vertex when w is given
+   and part_weight is asked for, and 32 bytes per pin of nets with more than 64
+   pins; VMO_E_UNSUPPORTED when it does not).  Every call on a GPU uses that
+   GPU's one arena, which keeps the last call's contents: calls that overlap
+   on one GPU (other threads, other contexts, other streams) race and must not
+   be made.  The call synchronises `stream` before returning. */
+vmo_status vmo_cut_noalloc(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, int32_t nparts,
+                           double* part_weight, vmo_cut_result* out /* (host) */, vmo_stream stream);
 
 /* ---------------------------------------------------------------------------
  * One 2-means split (Algorithm 4 with m = 2; sides by the plane of

@@ -233,12 +233,17 @@ class Context:
         self._check(lib().vmo_components(self.h, C.byref(hs), _ptr(lab), _stream()))
         return lab
 
-    def cut(self, h: DeviceHypergraph, part: torch.Tensor, nparts: int):
-        pw = torch.empty(max(nparts, 1), dtype=torch.float64, device=part.device)
+    def cut(self, h: DeviceHypergraph, part: torch.Tensor, nparts: int, noalloc: bool = False,
+            part_weight: torch.Tensor | None = None):
+        """Cut metrics (vmo_cut; noalloc: vmo_cut_noalloc, whose workspace is
+        the library's static arena).  part_weight: an output buffer of at
+        least nparts doubles (allocated here if None)."""
+        pw = part_weight if part_weight is not None else torch.empty(max(nparts, 1), dtype=torch.float64,
+                                                                     device=part.device)
         r = CutResult()
         hs = h.cstruct()
-        self._check(lib().vmo_cut(self.h, C.byref(hs), _ptr(part), C.c_int32(nparts), _ptr(pw), C.byref(r),
-                                  _stream()))
+        fn = lib().vmo_cut_noalloc if noalloc else lib().vmo_cut
+        self._check(fn(self.h, C.byref(hs), _ptr(part), C.c_int32(nparts), _ptr(pw), C.byref(r), _stream()))
         return {"lambda_minus_one": r.lambda_minus_one, "cut_net": r.cut_net, "nets_cut": r.nets_cut,
                 "part_weight": pw[:nparts]}
 

@@ -79,6 +79,14 @@ vmo_status vmo_create(vmo_ctx* out, int device) {
   vmo_ctx_s* c = new (std::nothrow) vmo_ctx_s();
   if (!c) return VMO_E_NOMEM;
   c->device = device;
+  // the allocation-free entry point's arena: its address on this device,
+  // looked up once per device with the device current (the caller's current
+  // device is restored)
+  int prev = 0;
+  const bool have_prev = hipGetDevice(&prev) == hipSuccess;
+  if (hipSetDevice(device) == hipSuccess) vmo::noalloc_init(device);
+  if (have_prev) (void)hipSetDevice(prev);
+  (void)hipGetLastError();
   *out = c;
   return VMO_OK;
 }
@@ -122,6 +130,29 @@ vmo_status vmo_cut(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, in
   API_BEGIN(ctx, stream)
   vmo::cut(C, h, part, nparts, part_weight, out, S);
   API_END
+}
+
+vmo_status vmo_cut_noalloc(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, int32_t nparts,
+                           double* part_weight, vmo_cut_result* out, vmo_stream stream) {
+  if (!ctx) return VMO_E_INVALID;
+  vmo::Ctx& C = *static_cast<vmo::Ctx*>(ctx);
+  hipStream_t S = static_cast<hipStream_t>(stream);
+  C.err.clear();
+  try {
+    VMO_HIP(hipSetDevice(C.device));
+    vmo::cut_noalloc(C, h, part, nparts, part_weight, out, S);
+  } catch (vmo::Error& e) {
+    C.err = e.what();
+    (void)hipStreamSynchronize(S);
+    (void)hipGetLastError();
+    return e.status;
+  } catch (std::exception& e) {
+    C.err = e.what();
+    (void)hipStreamSynchronize(S);
+    (void)hipGetLastError();
+    return VMO_E_DEVICE;
+  }
+  return VMO_OK;
 }
 
 vmo_status vmo_bisect(vmo_ctx ctx, const float* x, int32_t k, uint64_t seed, int32_t t_max, uint8_t* side,

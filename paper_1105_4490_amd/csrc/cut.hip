@@ -1,6 +1,7 @@
 // Cut metrics of a partition (Sec. 4.1 cut rows/columns; the cut-net metric of
 // its footnote; Table 4's maximum cut per split): per-net counts of distinct
-// part ids, deterministic FP64 sums, part weights.
+// part ids, deterministic FP64 sums, part weights; and the allocation-free
+// variant of the call, whose workspace is a static device arena.
 #include "vmo_internal.h"
 
 namespace vmo {
@@ -73,10 +74,40 @@ __global__ void k_cut_final(const double* part3, int nb, double* out3) {
   for (int i = 0; i < nb; ++i) { a += part3[3 * i]; b += part3[3 * i + 1]; n += part3[3 * i + 2]; }
   out3[0] = a; out3[1] = b; out3[2] = n;
 }
-__global__ void k_part_weight(const int32_t* part, const float* w, int32_t k, int32_t nparts, double* pw) {
+// Unit weights: part sizes (integer counts, exact in FP64 in any order).
+__global__ void k_part_count(const int32_t* part, int32_t k, int32_t nparts, double* pw) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x) {
     int32_t p = part[v];
-    if (p >= 0 && p < nparts) atomicAdd(&pw[p], w ? (double)w[v] : 1.0);
+    if (p >= 0 && p < nparts) atomicAdd(&pw[p], 1.0);
+  }
+}
+// Weighted parts, summed in a fixed order: the vertices grouped by part with
+// a stable sort of their part ids (so each group ascends by vertex id; ids
+// outside [0, nparts) sort last), then each part's weights added one by one
+// in FP64.
+__global__ void k_pw_keys(const int32_t* part, int32_t k, int32_t nparts, uint32_t* key, int32_t* val) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = part[v];
+    key[v] = (p >= 0 && p < nparts) ? (uint32_t)p : (uint32_t)nparts;
+    val[v] = (int32_t)v;
+  }
+}
+__device__ __forceinline__ int32_t lower_bound_u32(const uint32_t* a, int32_t n, uint32_t x) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+__global__ void k_pw_sum(const uint32_t* key, const int32_t* val, int32_t k, int32_t nparts, const float* w,
+                         double* pw) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nparts; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = lower_bound_u32(key, k, (uint32_t)p), e = lower_bound_u32(key, k, (uint32_t)p + 1u);
+    double a = 0.0;
+    for (int32_t i = b; i < e; ++i) a = a + (double)w[val[i]];
+    pw[p] = a;
   }
 }
 __global__ void k_check_part(const int32_t* part, int32_t k, int* bad) {
@@ -125,14 +156,87 @@ void cut(Ctx& c, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, d
   VMO_LAUNCH(k_cut_partial, nb, kCT, 0, s, lam.p, h->c, l, p3.p);
   VMO_LAUNCH(k_cut_final, 1, 64, 0, s, p3.p, nb, o3.p);
   if (part_weight && nparts > 0) {
-    VMO_HIP(hipMemsetAsync(part_weight, 0, sizeof(double) * nparts, s));
-    VMO_LAUNCH(k_part_weight, gsz(h->k), kCT, 0, s, part, h->w, h->k, nparts, part_weight);
+    if (!h->w) {
+      VMO_HIP(hipMemsetAsync(part_weight, 0, sizeof(double) * nparts, s));
+      VMO_LAUNCH(k_part_count, gsz(h->k), kCT, 0, s, part, h->k, nparts, part_weight);
+    } else {
+      Buf<uint32_t> key(c.pool, h->k);
+      Buf<int32_t> val(c.pool, h->k);
+      VMO_LAUNCH(k_pw_keys, gsz(h->k), kCT, 0, s, part, h->k, nparts, key.p, val.p);
+      radix_sort<uint32_t>(c, key.p, val.p, h->k, bits_for((uint64_t)nparts), s);
+      VMO_LAUNCH(k_pw_sum, gsz(nparts), kCT, 0, s, key.p, val.p, h->k, nparts, h->w, part_weight);
+    }
   }
   double r[3];
   read_bytes(r, o3.p, sizeof r, s);
   out->lambda_minus_one = r[0];
   out->cut_net = r[1];
   out->nets_cut = (int64_t)r[2];
+}
+
+// ------------------------------------------------- allocation-free cut ----
+// The workspace of vmo_cut_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes its name to a
+// kernel or a copy (on the host it is only a stand-in, not a device address):
+// its device address is looked up once per device with hipGetSymbolAddress
+// (noalloc_init, called by vmo_create with the device current) and kept in
+// g_arena, and only that address is used.
+constexpr size_t kArenaBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kArenaBytes];
+
+namespace {
+std::mutex g_arena_mu;
+std::map<int, uint8_t*> g_arena;       // device -> address of its copy of scratch
+std::map<int, std::string> g_arena_err;
+}  // namespace
+
+void noalloc_init(int device) {
+  std::lock_guard<std::mutex> g(g_arena_mu);
+  if (g_arena.count(device) || g_arena_err.count(device)) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    g_arena_err[device] = std::string("hipGetSymbolAddress of the static arena failed: ") + hipGetErrorString(e);
+    return;
+  }
+  g_arena[device] = static_cast<uint8_t*>(p);
+}
+
+void cut_noalloc(Ctx& c, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, double* part_weight,
+                 vmo_cut_result* out, hipStream_t s) {
+  VMO_REQUIRE(h != nullptr, "h is NULL");
+  if (h->k > kNoAllocMaxVerts || h->l > kNoAllocMaxNets)
+    throw Error(VMO_E_UNSUPPORTED, "vmo_cut_noalloc takes at most 2^20 vertices and 2^20 nets");
+  uint8_t* base = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_arena_mu);
+    auto it = g_arena.find(c.device);
+    if (it == g_arena.end()) {
+      auto er = g_arena_err.find(c.device);
+      throw Error(VMO_E_DEVICE, er != g_arena_err.end() ? er->second : "static arena not set up on this device");
+    }
+    base = it->second;
+  }
+  // arena layout: [0, 256) the error flag of bounded device-side waits, then
+  // the call's blocks by bump allocation
+  Arena a{base, kArenaBytes, 256};
+  struct Mode {
+    Ctx& c;
+    ~Mode() {
+      c.pool.set_arena(nullptr);
+      c.noalloc = false;
+      c.arena_flag = nullptr;
+      thread_noalloc() = false;
+    }
+  } mode{c};
+  c.noalloc = true;
+  c.arena_flag = reinterpret_cast<int*>(base);
+  thread_noalloc() = true;
+  c.pool.set_arena(&a);
+  VMO_HIP(hipMemsetAsync(c.arena_flag, 0, sizeof(int), s));
+  cut(c, h, part, nparts, part_weight, out, s);
+  check_device_flag(c, s);
 }
 
 }  // namespace vmo

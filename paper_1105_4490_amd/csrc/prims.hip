@@ -14,6 +14,15 @@ size_t Pool::size_class(size_t b) {
 
 void* Pool::get(size_t bytes) {
   std::lock_guard<std::mutex> g(mu_);
+  if (arena_) {
+    const size_t b = (bytes + 255) & ~size_t(255);
+    if (b > arena_->cap - arena_->used)
+      throw Error(VMO_E_UNSUPPORTED, "the input needs more workspace than the " + std::to_string(arena_->cap >> 20) +
+                                         " MiB static arena of the allocation-free call holds");
+    void* p = arena_->base + arena_->used;
+    arena_->used += b;
+    return p;
+  }
   size_t cls = size_class(bytes);
   auto it = free_.lower_bound(cls);
   if (it != free_.end() && it->first <= 2 * cls) {
@@ -39,7 +48,7 @@ void* Pool::get(size_t bytes) {
 
 void Pool::put(void* p) {
   std::lock_guard<std::mutex> g(mu_);
-  auto it = size_.find(p);
+  auto it = size_.find(p);  // arena blocks are not in size_: nothing to do
   if (it == size_.end()) return;
   free_.emplace(it->second, p);
 }
@@ -72,9 +81,14 @@ struct PinnedScratch {
   }
 };
 thread_local PinnedScratch t_pinned;
+thread_local bool t_noalloc = false;
+alignas(256) thread_local uint8_t t_plain[kPinnedBytes];
 }  // namespace
 
+bool& thread_noalloc() { return t_noalloc; }
+
 void* pinned_scratch() {
+  if (t_noalloc) return t_plain;  // plain host memory: copies into it are staged by the runtime
   if (!t_pinned.p) VMO_HIP(hipHostMalloc(&t_pinned.p, kPinnedBytes, hipHostMallocDefault));
   return t_pinned.p;
 }
@@ -94,6 +108,19 @@ Ctx::~Ctx() {
 
 // ----------------------------------------------------------------- tuner ----
 int tune_pick(Ctx& c, int family, int bucket, int ncfg, bool* timed) {
+  if (c.noalloc) {
+    // no timing (it would create events): the best candidate known so far,
+    // else the first (all candidates give the same results)
+    *timed = false;
+    const auto it = c.tune.stat.find({family, bucket});
+    int best = -1;
+    if (it != c.tune.stat.end())
+      for (int i = 0; i < ncfg; ++i)
+        if (it->second.n[i] > 0 &&
+            (best < 0 || it->second.ms_per_work[i] / it->second.n[i] < it->second.ms_per_work[best] / it->second.n[best]))
+          best = i;
+    return best < 0 ? 0 : best;
+  }
   int tot[Tuner::kMaxCfg] = {};
   bool pending = false;
   {
@@ -182,7 +209,7 @@ void tune_flush(Ctx& c) {
 
 int prof_begin(Ctx& c, const char* name, double work, hipStream_t s, unsigned long long** dwork) {
   if (dwork) *dwork = nullptr;
-  if (!c.prof.on) return -1;
+  if (!c.prof.on || c.noalloc) return -1;
   if (c.prof.seen[name]++ % c.prof.every != 0) return -1;
   ProfPending p;
   p.name = name;
@@ -470,6 +497,7 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
 }
 
 int* device_flag(Ctx& c) {
+  if (c.noalloc) return c.arena_flag;
   if (!c.dflag) {
     VMO_HIP(hipMalloc(&c.dflag, sizeof(int)));
     VMO_HIP(hipMemset(c.dflag, 0, sizeof(int)));
@@ -478,10 +506,11 @@ int* device_flag(Ctx& c) {
 }
 
 void check_device_flag(Ctx& c, hipStream_t s) {
-  if (!c.dflag) return;
-  const int v = read1(c.dflag, s);
+  int* f = c.noalloc ? c.arena_flag : c.dflag;
+  if (!f) return;
+  const int v = read1(f, s);
   if (v) {
-    VMO_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int), s));
+    VMO_HIP(hipMemsetAsync(f, 0, sizeof(int), s));
     VMO_HIP(hipStreamSynchronize(s));
     throw Error(VMO_E_DEVICE, "a device-side wait ran out of its bound (internal error)");
   }

@@ -39,10 +39,20 @@ struct Error : std::runtime_error {
   } while (0)
 
 // ------------------------------------------------------------------ pool ----
+// A fixed device region handed out by bump allocation and released all at
+// once (the allocation-free entry points' workspace).
+struct Arena {
+  uint8_t* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
 // Caching device allocator: blocks are kept after release and handed out
 // again for requests of at most the same size class.  A pool serves one
 // stream: calls synchronise that stream before returning, so a released
 // block is idle when reused.  Its methods may be called from any thread.
+// While an arena is set, get() takes blocks from it instead (never calling
+// hipMalloc; VMO_E_UNSUPPORTED when it is exhausted) and put() of such a
+// block does nothing.
 class Pool {
  public:
   ~Pool();
@@ -53,6 +63,10 @@ class Pool {
     return held_;
   }
   void trim();
+  void set_arena(Arena* a) {
+    std::lock_guard<std::mutex> g(mu_);
+    arena_ = a;
+  }
 
  private:
   static size_t size_class(size_t bytes);
@@ -61,6 +75,7 @@ class Pool {
   std::multimap<size_t, void*> free_;
   std::unordered_map<void*, size_t> size_;
   size_t held_ = 0;
+  Arena* arena_ = nullptr;
 };
 
 template <class T>
@@ -144,8 +159,24 @@ struct Ctx {
   Tuner tune;
   int* dflag = nullptr;  // device error flag of bounded device-side waits
   unsigned long long* wslots = nullptr;  // the walk's interaction counters (kept zero between walks)
+  // Allocation-free call in progress: the pool draws from an arena, the
+  // device error flag lives in it (arena_flag), and neither the tuner nor live
+  // timing create events or device counters.
+  bool noalloc = false;
+  int* arena_flag = nullptr;
   ~Ctx();
 };
+
+// Calls of the calling host thread read device scalars into plain host
+// memory instead of its pinned buffer (which the first use would allocate).
+bool& thread_noalloc();
+
+// Allocation-free cut: the static arena's address on `device` (looked up once
+// per device, with the device current), and the call itself.
+constexpr int32_t kNoAllocMaxVerts = 1 << 20, kNoAllocMaxNets = 1 << 20;
+void noalloc_init(int device);
+void cut_noalloc(Ctx& c, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, double* part_weight,
+                 vmo_cut_result* out, hipStream_t s);
 
 // Tuner: the configuration to use for (family, bucket) among ncfg.  *timed is
 // set while some candidate has fewer than two timed launches (pending ones
