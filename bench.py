@@ -37,13 +37,17 @@ P_PARTS = 64
 N_SIDE = 64
 SEED = 1
 SCHUR_P3 = 8         # parts of each separator block in the Schur-complement recursion
-FLOPS_PER_INTERACTION = 23   # 4 sub, r^2 (1 mul + 3 fma), 2 mul (2 W w), 1 mul (r^4), 1 div, 4 fma
+# Algorithmic flops of one interaction (one term of the repulsion in eq. (7)),
+# the count fixed for this measurement; the kernel itself executes 23 (4 sub,
+# r^2 as 1 mul + 3 fma, 1 mul for W (2 w_n), 1 mul for r^4, 1 div, 4 fma).
+FLOPS_PER_INTERACTION = 20
 # HBM bytes per walk launch (average over the walk launches of one counting and
 # one timed step of this workload), from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
 # plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
 WALK_TRAFFIC_BYTES = 88.27e6 + 18.77e6
-PEAK_FP32_VALU_TFLOPS = 157.3
+PEAK_FP32_VALU_TFLOPS = 157.3        # 256 CUs x 128 FP32 lanes (packed) x 2 (fma) x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6     # the same without packed FP32 (this build disables it)
 # live timing brackets every PROFILE_EVERY-th launch of a kernel with HIP
 # events: an event pair costs about 13 us of stream time, 2.5 % of a step when
 # every walk is timed.  3 is prime to the 700 walk launches of a step, so over
@@ -62,7 +66,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path-only", action="store_true",
                     help="only the timed V+O steps (no order-only, border, Schur or LU-ordering fields)")
-    ap.add_argument("--cpu-side", type=int, default=28, help="grid side of the oracle's timed sample")
+    ap.add_argument("--cpu-side", type=int, default=48, help="grid side of the oracle's all-cores V+O sample")
+    ap.add_argument("--cpu-side1", type=int, default=28, help="grid side of the oracle's one-thread V+O sample")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="host threads of the oracle's all-cores leg (capped at the cores this process may use)")
+    ap.add_argument("--no-batch", action="store_true", help="path mode: leave out the batched-ordering field")
+    ap.add_argument("--no-serve", action="store_true", help="path mode: leave out the serving field")
     ap.add_argument("--mode", choices=("path", "batch", "serve", "copy"), default="path",
                     help="copy: a plain 256 MiB device copy, three times (calibrates the HBM byte counters)")
     ap.add_argument("--jobs", type=int, default=512, help="batch mode: number of matrices")
@@ -145,6 +154,8 @@ def main():
     w_tflops = FLOPS_PER_INTERACTION * ipl / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     roof = {"bound": "alu", "kernel": "k_walk", "achieved": round(w_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s", "frac": round(w_tflops / PEAK_FP32_VALU_TFLOPS, 4),
+            "flops_per_interaction": FLOPS_PER_INTERACTION,
+            "frac_of_unpacked_peak": round(w_tflops / PEAK_FP32_UNPACKED_TFLOPS, 4),
             "traffic": WALK_TRAFFIC_BYTES if args.side == N_SIDE else None,
             "launches_timed": walk["launches"], "timed_every": PROFILE_EVERY,
             "avg_launch_ms": round(avg_ms, 4),
@@ -154,7 +165,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_side)
+        cpu = cpu_baseline(args.cpu_side, args.cpu_side1, args.cpu_threads)
 
     n_nodes = int(o["n_nodes"].item())
     sep = float(o["split_cut"][:n_nodes].sum().item())
@@ -183,10 +194,24 @@ def main():
         try:
             h = ctx.model(P.SYMMETRIC, g.m, g.n, rowptr, col)
             line.update(order_only_and_border(ctx, h, g, lp, o, args.steps))
+            if not args.no_cpu_baseline:
+                line["cpu_order_only"] = cpu_order_only(ctx, h, g, args.cpu_threads)
             line.update(bench_lu_pipeline(ctx, g, rowptr, col, lp, 2))
         except Exception as e:  # noqa: BLE001
             line["extras_error"] = f"{type(e).__name__}: {e}"
             print(f"bench: extra fields failed: {e}", file=sys.stderr, flush=True)
+        if not args.no_batch:
+            try:
+                line["batch"] = bench_batch(args, ctx, field=True)
+            except Exception as e:  # noqa: BLE001
+                line["batch_error"] = f"{type(e).__name__}: {e}"
+                print(f"bench: batch field failed: {e}", file=sys.stderr, flush=True)
+        if not args.no_serve:
+            try:
+                line["serve"] = bench_serve(args, ctx, field=True)
+            except Exception as e:  # noqa: BLE001
+                line["serve_error"] = f"{type(e).__name__}: {e}"
+                print(f"bench: serve field failed: {e}", file=sys.stderr, flush=True)
     print(json.dumps(line))
 
 
@@ -338,8 +363,10 @@ def _pct(v, q):
     return v[min(len(v) - 1, max(0, math.ceil(q * len(v)) - 1))]
 
 
-def bench_batch(args, ctx):
-    """Recursive ordering of many banded matrices: batched against plain."""
+def bench_batch(args, ctx, field=False):
+    """Recursive ordering of many banded matrices: batched against plain.
+    field: return the result as a dict (a field of the default line) instead
+    of printing a line of its own."""
     import torch
     import paper_1105_4490_amd as P
     import vmo_gen
@@ -421,6 +448,9 @@ def bench_batch(args, ctx):
                          "share_of_step": round(4 * a_b["total_ms"] / (1e3 * dt_b * args.steps), 4)},
         "untimed": {"generate_s": round(gen_s, 1), "layout_s": round(lay_s, 1)},
     }
+    if field:
+        return {k: line[k] for k in ("metric", "value", "unit", "ms_per_step", "config", "plain",
+                                     "batched_over_plain", "identical_results", "lloyd_assign", "untimed")}
     print(json.dumps(line))
 
 
@@ -433,8 +463,10 @@ def _serve_matrix(spec):
     return vmo_gen.zipf_rect(spec["m"], spec["n"], spec["seed"]), 2
 
 
-def bench_serve(args, ctx):
-    """A Poisson stream of whole-path ordering jobs through the server."""
+def bench_serve(args, ctx, field=False):
+    """A Poisson stream of whole-path ordering jobs through the server (the
+    stream's length scaled down from 3,000 requests to --requests).  field:
+    return the result as a dict instead of printing a line."""
     import numpy as np
     import torch
     import paper_1105_4490_amd as P
@@ -504,6 +536,10 @@ def bench_serve(args, ctx):
         lat2, span2, _ = stream(arr)
         line["stable"] = {"rate_per_s": rate, "nnz_per_s": total / span2,
                           "latency_ms": {"p50": _pct(lat2, 0.5), "p99": _pct(lat2, 0.99), "max": max(lat2)}}
+    if field:
+        line["scaled"] = f"{len(jobs)} requests of the 3,000-request stream"
+        return {k: line[k] for k in ("metric", "value", "unit", "config", "latency_ms", "offered_nnz_per_s",
+                                     "busy_ms", "ticks", "scaled") + (("stable",) if "stable" in line else ())}
     print(json.dumps(line))
 
 
@@ -521,22 +557,99 @@ def copy_calibration():
     print(json.dumps({"mode": "copy", "bytes_per_copy": a.numel() * 4, "copies": 3}))
 
 
-def cpu_baseline(side):
-    """The oracle, single-threaded, on the full path of a smaller instance of
-    the same generator (the 64^3 instance takes it many minutes)."""
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail, os.cpu_count() or avail
+
+
+def _oracle_vo(side):
     import oracle
     import vmo_gen
-    oracle.build()
     g = vmo_gen.grid3d(side, seed=SEED)
     t = time.perf_counter()
     h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
     x = oracle.layout(h, oracle.layout_params(seed=SEED))
     o = oracle.order(h, x, P_PARTS, SEED, mode=oracle.GRAPH_MODE, ord=oracle.BBD)
     oracle.cut(h, o.part, P_PARTS)
-    dt = time.perf_counter() - t
-    return {"value": g.nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+    return g, time.perf_counter() - t
+
+
+def cpu_baseline(side, side1, threads):
+    """The oracle on the full V+O path of smaller instances of the same
+    generator (the 64^3 instance takes it minutes): on all the host cores it
+    may use (OpenMP over the independent per-vertex loops; the result does not
+    depend on the thread count) for the side^3 instance, and on one thread for
+    the side1^3 instance."""
+    import oracle
+    oracle.build()
+    model, avail, nproc = host_cpu()
+    nthr = max(1, min(threads, avail))
+    oracle.set_threads(nthr)
+    g, dt = _oracle_vo(side)
+    oracle.set_threads(1)
+    g1, dt1 = _oracle_vo(side1)
+    oracle.set_threads(nthr)
+    return {"value": g.nnz / dt, "unit": "nnz/s", "cores": nthr, "kind": "oracle",
             "sample": f"full V+O path (model, layout, {P_PARTS}-part BBD, cut) of the {side}^3 instance of the "
-                      f"same generator ({g.m} rows, {g.nnz} nnz) in {dt:.1f} s"}
+                      f"same generator ({g.m} rows, {g.nnz} nnz) in {dt:.1f} s on {nthr} threads",
+            "single_thread": {"value": g1.nnz / dt1, "cores": 1, "seconds": round(dt1, 2),
+                              "sample": f"the {side1}^3 instance ({g1.m} rows, {g1.nnz} nnz)"},
+            "cpu_model": model, "nproc": nproc, "cores_available": avail}
+
+
+def synthetic_grid_coords(n, seed):
+    """Coordinates of the permuted n^3 grid's vertices: vertex v sits at the
+    grid position of the original vertex the generator's permutation sent to
+    v, plus a small seeded jitter."""
+    import numpy as np
+    import vmo_gen
+    perm = vmo_gen.rng(seed, 2).permutation(n ** 3)   # the permutation vmo_gen.grid3d applies
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(n ** 3)
+    x = np.zeros((4, n ** 3), np.float32)
+    x[0], x[1], x[2] = inv % n, (inv // n) % n, inv // (n * n)
+    x += vmo_gen.rng(seed, 9).standard_normal(x.shape).astype(np.float32) * 0.1
+    return x
+
+
+def cpu_order_only(ctx, h, g, threads):
+    """The O column at full size: the oracle's recursive BBD of the 64^3
+    matrix from given coordinates (its grid positions with a seeded jitter),
+    timed on the host, beside the GPU ordering of the same input."""
+    import torch
+    import oracle
+    x = synthetic_grid_coords(round(g.m ** (1 / 3)), SEED)
+    hh = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
+    model, avail, nproc = host_cpu()
+    t = time.perf_counter()
+    oracle.order(hh, x, P_PARTS, SEED, mode=oracle.GRAPH_MODE, ord=oracle.BBD)
+    dt = time.perf_counter() - t
+    dx = torch.as_tensor(x).cuda().contiguous()
+    ctx.order(h, dx, P_PARTS, SEED, mode=1, order=1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        ctx.order(h, dx, P_PARTS, SEED, mode=1, order=1)
+    torch.cuda.synchronize()
+    dg = (time.perf_counter() - t) / 5
+    return {"value": g.nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"O column (recursive {P_PARTS}-part BBD from given coordinates) of the full {g.m}-row instance, "
+                      f"{dt:.2f} s (the ordering's loops are sequential in the oracle)",
+            "gpu_same_input": {"value": g.nnz / dg, "unit": "nnz/s", "ms": round(1e3 * dg, 3)},
+            "cpu_model": model, "nproc": nproc}
 
 
 if __name__ == "__main__":
