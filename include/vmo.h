@@ -4,19 +4,33 @@
  * Approach to Matrix Ordering" (arXiv 1105.4490).
  *
  * Pointer conventions.  Every array argument is a DEVICE pointer unless its
- * comment says (host).  The caller owns every input and output buffer and
- * keeps it alive until the call returns.  The library owns only its
- * workspace, a per-context caching pool of device memory.  Every call runs its
- * kernels on `stream` (a hipStream_t; NULL = the null stream) and returns after
- * that stream has finished the call's work, so outputs are ready on return.
- * Calls on one context must not overlap (one context per host thread).
+ * comment says (host).  The caller owns every input and output buffer.  The
+ * library owns only its workspace, a per-context caching pool of device
+ * memory.  Calls on one context must not overlap (one context per host
+ * thread).
+ *
+ * Streams and completion.  Every call runs its kernels on `stream` (a
+ * hipStream_t; NULL = the null stream).  Calls marked [async] return once
+ * their work is queued: their device outputs are ready when the stream
+ * reaches that point (a later kernel or copy on the same stream sees them;
+ * the host waits with vmo_sync or hipStreamSynchronize), and the caller keeps
+ * the inputs alive and unchanged until then.  Some [async] calls still read a
+ * few sizes back on the way (each says which and why); those waits end before
+ * the call's last kernels.  All other calls return after their work is done
+ * (they have host outputs).  A call on a stream other than the previous
+ * [async] call's first waits for that call's work (the pool's blocks are then
+ * free to reuse).
  *
  * Errors.  No call throws.  A call returns VMO_OK (0) or a negative status;
  * vmo_last_error() then holds a message.  Inputs are validated on the host
  * for scalars and on the device for array contents (pins in range and
- * ascending within a net, weights and coordinates finite); invalid content is
- * reported as VMO_E_INVALID without writing partial results the caller could
- * mistake for output.
+ * ascending within a net, weights and coordinates finite).  Checks whose
+ * result the call needs before its next step are read back at once and
+ * reported by the call itself as VMO_E_INVALID, without writing partial
+ * results the caller could mistake for output.  Checks that [async] calls
+ * make on the device without waiting (those marked "checked on the device")
+ * skip the call's writes when they fail and set the context's error word;
+ * vmo_sync then returns VMO_E_INVALID with a message naming the check.
  *
  * Ids are 0-based (the paper counts from 1).  Permutations are in gather form:
  * perm[new] = old.
@@ -44,10 +58,20 @@ enum {
 typedef struct vmo_ctx_s* vmo_ctx;
 typedef void* vmo_stream; /* hipStream_t */
 
-/* Context on HIP device `device`.  Allocates nothing until first use. */
-vmo_status vmo_create(vmo_ctx* out /* (host) */, int device);
-/* Frees the context and its workspace pool. */
+/* Context on HIP device `device`.  Allocates nothing until first use.
+   pool_bytes bounds the device memory the workspace pool keeps cached between
+   calls: after a call that waits for its work (and in vmo_sync), idle blocks
+   beyond pool_bytes are returned to the device, largest first; 0 = no bound
+   (every block stays cached, so the steady state allocates nothing). */
+vmo_status vmo_create(vmo_ctx* out /* (host) */, int device, size_t pool_bytes);
+/* Waits for the context's pending work, then frees it and its pool. */
 vmo_status vmo_destroy(vmo_ctx ctx);
+/* Waits until `stream` has finished the work queued on it (and the previous
+   [async] call's work, if that ran on another stream), then reports what the
+   device-side checks of [async] calls since the last vmo_sync found:
+   VMO_E_INVALID with a message naming the failed checks (the word is then
+   cleared), VMO_E_DEVICE if a bounded device-side wait ran out, else VMO_OK. */
+vmo_status vmo_sync(vmo_ctx ctx, vmo_stream stream);
 /* Message of the last failed call on this context (host string, owned by the
    context, valid until the next call). */
 const char* vmo_last_error(vmo_ctx ctx);
@@ -89,14 +113,17 @@ vmo_status vmo_model(vmo_ctx ctx, int model, int32_t m, int32_t n, const int64_t
                      const int32_t* col, int64_t* net_ptr, int32_t* pins, int32_t cap_nets,
                      int64_t cap_pins, int32_t* k, int32_t* l, int64_t* npins, vmo_stream stream);
 
-/* Dual hypergraph (Definition of the dual, Sec. 1.1): net v of the dual
-   lists, ascending, the nets of h that contain v.  Outputs dptr [k+1],
-   dpins [net_ptr[l]].  (Weights and costs swap roles; they are not copied.) */
+/* [async] Dual hypergraph (Definition of the dual, Sec. 1.1): net v of the
+   dual lists, ascending, the nets of h that contain v.  Outputs dptr [k+1],
+   dpins [net_ptr[l]].  (Weights and costs swap roles; they are not copied.)
+   Reads back: the pin check and net_ptr[l] (the sort's size). */
 vmo_status vmo_dual(vmo_ctx ctx, const vmo_hypergraph* h, int64_t* dptr, int32_t* dpins,
                     vmo_stream stream);
 
-/* Connected components (Algorithm 1, Sec. 2.3): label[v] = the smallest
-   vertex id in v's component, where nets connect their pins. */
+/* [async] Connected components (Algorithm 1, Sec. 2.3): label[v] = the
+   smallest vertex id in v's component, where nets connect their pins.  Reads
+   back: the pin check, and one changed-flag per hooking round (the loop ends
+   when a round changes nothing). */
 vmo_status vmo_components(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, vmo_stream stream);
 
 /* Cut metrics of a partition (Sec. 4.1: a row/column is cut when it meets
@@ -111,7 +138,18 @@ typedef struct {
   double lambda_minus_one; /* sum_e c(e) max(lambda(e) - 1, 0) */
   double cut_net;          /* sum of c(e) over nets with lambda(e) > 1 */
   int64_t nets_cut;        /* number of nets with lambda(e) > 1 */
+  double max_split;        /* max over the splits h of split_cut[h] (below)  */
+  int32_t max_split_node;  /* heap id of the first split reaching it (0: none) */
+  int32_t separators;      /* 1 if part ids >= nparts occur (graph mode)     */
 } vmo_cut_result;
+/* split_cut[h] reads part[] as the leaves of a recursive bisection into
+   P = nparts parts (Sec. 4.2; Table 4 reports the maximum over splits): node h
+   (heap numbering, root 1) holds a contiguous part range, the root [0, P), its
+   first child the first ceil(K/2) of its K parts, the second child the rest.
+   Without separator ids, split_cut[h] = the sum of c(e), one by one in
+   ascending net id, over the nets cut at h (pins in more than one part, h the
+   deepest node holding all of them).  With separator ids (graph mode: vertex
+   v in the separator S_h has part P + h), split_cut[h] = |S_h|. */
 vmo_status vmo_cut(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, int32_t nparts,
                    double* part_weight, vmo_cut_result* out /* (host) */, vmo_stream stream);
 
@@ -122,7 +160,7 @@ vmo_status vmo_cut(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, in
    runs on until the process ends.  It calls no hipMalloc, hipFree or other
    allocating routine.  Limits: at most 2^20 vertices and 2^20 nets
    (VMO_E_UNSUPPORTED beyond, before any work), and the arena must hold the
-   call's blocks (about 12 bytes per net, 16 bytes per vertex when w is given
+   call's blocks (about 28 bytes per net, 16 bytes per vertex when w is given
    and part_weight is asked for, and 32 bytes per pin of nets with more than 64
    pins; VMO_E_UNSUPPORTED when it does not).  Every call on a GPU uses that
    GPU's one arena, which keeps the last call's contents: calls that overlap
@@ -168,7 +206,11 @@ typedef struct {
 /* Fills p with the defaults above and the given seed. */
 void vmo_layout_defaults(vmo_layout_params* p /* (host) */, uint64_t seed);
 
-/* Full layout.  x [4][k] FP32 SoA output. */
+/* [async] Full layout.  x [4][k] FP32 SoA output.  Reads back: the input
+   checks, the component count and each component's size, each coarse level's
+   sizes (its buffers are sized from them), one matching flag per eight
+   matching rounds, the bounding box at the first step of each level (the
+   step length), and the component boxes (packing offsets). */
 vmo_status vmo_layout(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p /* (host) */,
                       float* x, vmo_stream stream);
 
@@ -190,21 +232,24 @@ vmo_status vmo_coarsen(vmo_ctx ctx, const vmo_hypergraph* h, uint64_t seed, uint
    cell2 [n][4] = cell centre x 2 in grid units; flt [n][5] = W, X0..X3
    (charge and its weighted centre); order [k] = point ids in tree order.
    *n_nodes (host). */
+/* (vmo_tree reads back the node count, a host output; it does not wait for
+   the copy of the node arrays: [async] for ints, cell2, flt and order.) */
 vmo_status vmo_tree(vmo_ctx ctx, const float* x, const float* w, int32_t k, int32_t leaf_cap,
                     int32_t* ints, int32_t* cell2, float* flt, int32_t* order, int32_t max_nodes,
                     int32_t* n_nodes, vmo_stream stream);
 
-/* Gradient eq. (7) of the energy at x: attraction through the net centres,
-   repulsion by the tree walk of Algorithm 3.  y [4][k], z [4][l] (net
-   centres, may be NULL); *interactions (host, may be NULL) = charge
-   interactions evaluated by the walk. */
+/* [async] Gradient eq. (7) of the energy at x: attraction through the net
+   centres, repulsion by the tree walk of Algorithm 3.  y [4][k], z [4][l]
+   (net centres, may be NULL); *interactions (host, may be NULL) = charge
+   interactions evaluated by the walk (reading it back waits for the walk). */
 vmo_status vmo_gradient(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, float theta,
                         int32_t leaf_cap, float* y, float* z, int64_t* interactions,
                         vmo_stream stream);
 
-/* `iters` descent steps of Algorithm 3 on x in place, steps it0 .. it0+iters-1
-   of a level.  *alpha (host) carries the step length: set from the bounding
-   box at step 0, multiplied by p->decay after every step. */
+/* [async] `iters` descent steps of Algorithm 3 on x in place, steps it0 ..
+   it0+iters-1 of a level.  *alpha (host) carries the step length: set from
+   the bounding box at step 0 (read back then), multiplied by p->decay after
+   every step. */
 vmo_status vmo_layout_steps(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p,
                             float* x, int32_t it0, int32_t iters, double* alpha, vmo_stream stream);
 
@@ -237,8 +282,11 @@ typedef struct {
   int32_t* n_nodes;   /* [1] number of tree nodes                             */
 } vmo_order_out;
 
-/* x: coordinates [4][k]; NULL = compute them first with vmo_layout(lp).
-   P >= 1 parts; t_max Lloyd updates per split (32 is the usual value). */
+/* [async] x: coordinates [4][k]; NULL = compute them first with
+   vmo_layout(lp).  P >= 1 parts; t_max Lloyd updates per split (32 is the
+   usual value).  Reads back: the input checks, one convergence flag per eight
+   Lloyd iterations, and each recursion level's segment count (the next
+   level's launches and buffers are sized from it). */
 vmo_status vmo_order(vmo_ctx ctx, const vmo_hypergraph* h, int mode, int order, const float* x,
                      const vmo_layout_params* lp /* (host) */, int32_t P, uint64_t seed,
                      int32_t t_max, const vmo_order_out* out /* (host) */, vmo_stream stream);
@@ -267,6 +315,7 @@ vmo_status vmo_order_bbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const f
  * arrays are inconsistent (heap ids outside [1, 4P), block boundaries not
  * non-decreasing from 0 to k, part ids neither in [0, P) nor P + heap id,
  * vperm not a permutation). */
+/* [async]; reads back the input checks and the node count. */
 vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_order_out* in /* (host) */, int32_t P,
                             int32_t b, int32_t* vperm_out, vmo_stream stream);
 
@@ -289,6 +338,8 @@ vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_orde
  * reordered again.  P3 in [1, 2^24] (1: a copy).  All blocks are ordered in
  * one batched pass.  VMO_E_INVALID as for vmo_order_border, or if x is NULL
  * or not finite. */
+/* [async]; reads back the input checks, the separator blocks' sizes and the
+   batched ordering's level sizes. */
 vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, const int32_t* mu,
                            const vmo_order_out* in /* (host) */, int32_t P, int32_t P3, uint64_t seed,
                            int32_t t_max, int32_t* vperm_out, vmo_stream stream);
@@ -322,6 +373,7 @@ vmo_status vmo_match(vmo_ctx ctx, int32_t m, int32_t n, const int64_t* rowptr, c
  * blocks).  mu: device [k], mu[v] = partner or -1; must be an involution
  * without fixed points whose pairs are edges of h (else VMO_E_INVALID).  An
  * all -1 mu gives vmo_order's result. */
+/* [async]; reads back as vmo_order, and the check of mu. */
 vmo_status vmo_order_matched(vmo_ctx ctx, const vmo_hypergraph* h, int order, const float* x,
                              const vmo_layout_params* lp /* (host) */, const int32_t* mu, int32_t P,
                              uint64_t seed, int32_t t_max, const vmo_order_out* out /* (host) */,
@@ -333,6 +385,9 @@ vmo_status vmo_order_matched(vmo_ctx ctx, const vmo_hypergraph* h, int order, co
  * vertices): rperm[t] = the t-th row in vperm order, cperm[t] = mu[rperm[t]]
  * - m, so the matching lies on the diagonal.  VMO_E_INVALID if vperm is not a
  * permutation of 0..2m-1 or a row has no partner column. */
+/* [async], no readback: the permutation and partner checks are made on the
+   device (checked on the device: a failure leaves rperm and cperm unwritten
+   and vmo_sync returns VMO_E_INVALID). */
 vmo_status vmo_matched_perms(vmo_ctx ctx, int32_t m, const int32_t* vperm, const int32_t* mu, int32_t* rperm,
                              int32_t* cperm, vmo_stream stream);
 
@@ -352,6 +407,8 @@ vmo_status vmo_matched_perms(vmo_ctx ctx, int32_t m, const int32_t* vperm, const
  * *ngroups (host, or NULL): G = 1 + the largest g.  One workgroup per
  * bisection; a pass costs O(|bisection|^2) work.  VMO_E_INVALID for labels
  * below -1, a hypergraph that is not a graph, degrees above 1024 or k >= 2^25. */
+/* [async]; reads back the label check, the bisection count and the local
+   adjacency's sizes. */
 vmo_status vmo_refine_kl(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, int32_t passes, int64_t* gain,
                          int32_t* ngroups /* (host) */, vmo_stream stream);
 
@@ -359,6 +416,9 @@ vmo_status vmo_refine_kl(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, i
  * points of its row and its column in a layout of the bipartite graph).
  * x: [4][m+n] (rows, then columns); xnz: [4][nnz], xnz[d][e] = (x[d][i] +
  * x[d][m+j]) * 0.5 in FP32 for nonzero e = (i, j) in CSR order. */
+/* [async], no readback: rowptr (from 0, non-decreasing) and the columns (in
+   [0, n), ascending within a row) are checked on the device (a failure leaves
+   xnz unwritten and vmo_sync returns VMO_E_INVALID). */
 vmo_status vmo_finegrain(vmo_ctx ctx, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col,
                          const float* x, float* xnz, vmo_stream stream);
 
@@ -375,6 +435,7 @@ typedef struct {
   uint64_t job_index;
   vmo_order_out out;
 } vmo_job;
+/* [async]; reads back as vmo_order. */
 vmo_status vmo_order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs /* (host) */,
                            int32_t t_max, vmo_stream stream);
 

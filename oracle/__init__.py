@@ -164,6 +164,18 @@ def cut(h: Hypergraph, part, nparts: int):
     return {"lambda_minus_one": out[0], "cut_net": out[1], "nets_cut": int(out[2]), "part_weight": pw[:nparts]}
 
 
+def split_cuts(h: Hypergraph, part, P: int):
+    """Per-split cut of a recursive bisection into P parts (o_split_cuts):
+    (split [4P] by heap id, graph) -- the cost of the nets cut at each node
+    (the deepest node whose part range holds all the net's parts), or, when
+    separator ids P + h occur (graph mode), the size of each S_h."""
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    sp = np.zeros(4 * P, dtype=np.float64)
+    g = lib().o_split_cuts(C.c_int32(h.k), C.c_int32(h.l), _p(h.ptr), _p(h.pins), _p(h.c), _p(part), C.c_int32(P),
+                           _p(sp))
+    return sp, bool(g)
+
+
 def quantize(x):
     x = np.ascontiguousarray(x, dtype=np.float32)
     k = x.shape[1]

@@ -21,6 +21,8 @@
  *   o_cut             (lambda-1), cut-net metric, part weights
  *                     [Sec. 4.1 cut rows/columns; footnote on the cut-net
  *                      metric; Table 4 max cut per split].
+ *   o_split_cuts      per-split cut of a recursive bisection's partition
+ *                     [Table 4 maximum cut per split; Sec. 4.1].
  *   o_quantize        20-bit grid for exact 2-means sums (not in the paper;
  *                     an exactness device, see the reading of Alg. 4 below).
  *   o_bisect          one 2-means split [Algorithm 4 with m = 2, Algorithm 7
@@ -215,6 +217,53 @@ int o_cut(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const f
       if (part[v] >= 0 && part[v] < nparts) part_weight[part[v]] += w ? (double)w[v] : 1.0;
   }
   free(buf);
+  return 0;
+}
+
+/* Per-split cut of a partition made by recursive bisection into P parts
+   [Table 4: the maximum over splits of the rows/columns cut there; Sec. 4.1
+   cut nets of the recursive BBD].  Node h (heap numbering, root 1) of the
+   bisection holds the part range [p0, p0 + K): the root [0, P), child 2h the
+   first ceil(K/2) parts, child 2h + 1 the rest.  A net whose pins lie in more
+   than one part, all below P, is cut at the deepest node holding all of them;
+   split[h] = sum of c(e) over the nets cut at h, in ascending net order.  If
+   some part id is P or more (separator vertices of graph mode carry P + h),
+   split[h] = the number of vertices with part id P + h instead.  split has 4P
+   entries (heap ids below 4P); returns 1 in graph mode, 0 in net mode. */
+static int32_t node_of_range(int32_t P, int32_t lo, int32_t hi) {
+  int32_t h = 1, p0 = 0, K = P;
+  while (K > 1) {
+    int32_t K1 = (K + 1) / 2;
+    if (hi < p0 + K1) { h = 2 * h; K = K1; }
+    else if (lo >= p0 + K1) { h = 2 * h + 1; p0 += K1; K -= K1; }
+    else break;
+  }
+  return h;
+}
+
+int o_split_cuts(int32_t k, int32_t l, const int64_t* ptr, const int32_t* pins, const float* c,
+                 const int32_t* part, int32_t P, double* split) {
+  for (int32_t h = 0; h < 4 * P; ++h) split[h] = 0.0;
+  int graph = 0;
+  for (int32_t v = 0; v < k; ++v) if (part[v] >= P) graph = 1;
+  if (graph) {
+    for (int32_t v = 0; v < k; ++v) {
+      int32_t h = part[v] - P;
+      if (h >= 1 && h < 4 * P) split[h] += 1.0;
+    }
+    return 1;
+  }
+  for (int32_t e = 0; e < l; ++e) {
+    if (ptr[e + 1] - ptr[e] < 2) continue;
+    int32_t lo = part[pins[ptr[e]]], hi = lo;
+    for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) {
+      int32_t q = part[pins[p]];
+      if (q < lo) lo = q;
+      if (q > hi) hi = q;
+    }
+    if (lo == hi || lo < 0 || hi >= P) continue;
+    split[node_of_range(P, lo, hi)] += c ? (double)c[e] : 1.0;
+  }
   return 0;
 }
 

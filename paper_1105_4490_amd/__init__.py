@@ -89,7 +89,8 @@ class ServeStats(C.Structure):
 
 
 class CutResult(C.Structure):
-    _fields_ = [("lambda_minus_one", C.c_double), ("cut_net", C.c_double), ("nets_cut", C.c_int64)]
+    _fields_ = [("lambda_minus_one", C.c_double), ("cut_net", C.c_double), ("nets_cut", C.c_int64),
+                ("max_split", C.c_double), ("max_split_node", C.c_int32), ("separators", C.c_int32)]
 
 
 _lib = None
@@ -164,11 +165,17 @@ class DeviceHypergraph:
 class Context:
     """One vmo context on one GPU (calls on it must not overlap)."""
 
-    def __init__(self, device: int | None = None):
+    def __init__(self, device: int | None = None, pool_bytes: int = 0):
         self.device = torch.cuda.current_device() if device is None else device
         h = C.c_void_p()
-        self._check(lib().vmo_create(C.byref(h), C.c_int(self.device)), ctx=None)
+        self._check(lib().vmo_create(C.byref(h), C.c_int(self.device), C.c_size_t(pool_bytes)), ctx=None)
         self.h = h
+
+    def sync(self, stream=None):
+        """vmo_sync: waits for the stream's work and reports what the device-
+        side checks of earlier asynchronous calls found (raises VmoError)."""
+        st = _stream() if stream is None else C.c_void_p(stream.cuda_stream)
+        self._check(lib().vmo_sync(self.h, st))
 
     def close(self):
         if getattr(self, "h", None):
@@ -245,6 +252,7 @@ class Context:
         fn = lib().vmo_cut_noalloc if noalloc else lib().vmo_cut
         self._check(fn(self.h, C.byref(hs), _ptr(part), C.c_int32(nparts), _ptr(pw), C.byref(r), _stream()))
         return {"lambda_minus_one": r.lambda_minus_one, "cut_net": r.cut_net, "nets_cut": r.nets_cut,
+                "max_split": r.max_split, "max_split_node": r.max_split_node, "separators": bool(r.separators),
                 "part_weight": pw[:nparts]}
 
     # ------------------------------------------------------------- bisection --

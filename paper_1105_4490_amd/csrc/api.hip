@@ -38,23 +38,23 @@ void refine_kl(Ctx& c, const vmo_hypergraph* h, int32_t* label, int32_t passes, 
                hipStream_t s);
 }  // namespace vmo
 
+// Every call first waits for the work of the last asynchronous call if that
+// ran on another stream (its pool blocks are then idle).
 #define API_BEGIN(ctx, stream)                                    \
   if (!(ctx)) return VMO_E_INVALID;                               \
   vmo::Ctx& C = *static_cast<vmo::Ctx*>(ctx);                     \
   hipStream_t S = static_cast<hipStream_t>(stream);               \
   C.err.clear();                                                  \
   try {                                                           \
-    VMO_HIP(hipSetDevice(C.device));
+    VMO_HIP(hipSetDevice(C.device));                              \
+    vmo::join_tail(C, S);
 
-#define API_END                                                   \
-    vmo::check_device_flag(C, S);                                 \
-    vmo::prof_flush(C);                                           \
-    vmo::tune_flush(C);                                           \
-  }                                                               \
+#define API_CATCH                                                 \
   catch (vmo::Error & e) {                                        \
     C.err = e.what();                                             \
     (void)hipStreamSynchronize(S);                                \
     (void)hipGetLastError();                                      \
+    C.tail_on = false;                                            \
     vmo::prof_discard(C);                                         \
     return e.status;                                              \
   }                                                               \
@@ -62,14 +62,38 @@ void refine_kl(Ctx& c, const vmo_hypergraph* h, int32_t* label, int32_t passes, 
     C.err = e.what();                                             \
     (void)hipStreamSynchronize(S);                                \
     (void)hipGetLastError();                                      \
+    C.tail_on = false;                                            \
     vmo::prof_discard(C);                                         \
     return VMO_E_DEVICE;                                          \
   }                                                               \
   return VMO_OK;
 
+// A call that returns after its work is done (it has host outputs).
+#define API_END                                                   \
+    vmo::check_device_flag(C, S);                                 \
+    vmo::prof_flush(C);                                           \
+    vmo::tune_flush(C);                                           \
+    vmo::trim_pool(C, S);                                         \
+  }                                                               \
+  API_CATCH
+
+// A call whose outputs are device arrays: it returns once its work is
+// queued (after whatever readbacks it needs on the way); vmo_sync reports
+// what its device-side checks found.  With live timing on it waits, as the
+// timings are read at its end.
+#define API_END_ASYNC                                             \
+    if (C.prof.on) {                                              \
+      vmo::check_device_flag(C, S);                               \
+      vmo::prof_flush(C);                                         \
+    }                                                             \
+    vmo::tune_flush(C);                                           \
+    vmo::mark_tail(C, S);                                         \
+  }                                                               \
+  API_CATCH
+
 extern "C" {
 
-vmo_status vmo_create(vmo_ctx* out, int device) {
+vmo_status vmo_create(vmo_ctx* out, int device, size_t pool_bytes) {
   if (!out) return VMO_E_INVALID;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
@@ -79,6 +103,7 @@ vmo_status vmo_create(vmo_ctx* out, int device) {
   vmo_ctx_s* c = new (std::nothrow) vmo_ctx_s();
   if (!c) return VMO_E_NOMEM;
   c->device = device;
+  c->pool_cap = pool_bytes;
   // the allocation-free entry point's arena: its address on this device,
   // looked up once per device with the device current (the caller's current
   // device is restored)
@@ -94,8 +119,17 @@ vmo_status vmo_create(vmo_ctx* out, int device) {
 vmo_status vmo_destroy(vmo_ctx ctx) {
   if (!ctx) return VMO_E_INVALID;
   (void)hipSetDevice(ctx->device);
+  if (ctx->tail_on) (void)hipEventSynchronize(ctx->tail);  // pending work still uses pool blocks
   delete ctx;
   return VMO_OK;
+}
+
+vmo_status vmo_sync(vmo_ctx ctx, vmo_stream stream) {
+  API_BEGIN(ctx, stream)
+  VMO_HIP(hipStreamSynchronize(S));
+  C.tail_on = false;
+  vmo::check_async_flag(C, S);
+  API_END
 }
 
 const char* vmo_last_error(vmo_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
@@ -113,7 +147,7 @@ vmo_status vmo_model(vmo_ctx ctx, int model, int32_t m, int32_t n, const int64_t
 vmo_status vmo_dual(vmo_ctx ctx, const vmo_hypergraph* h, int64_t* dptr, int32_t* dpins, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::dual(C, h, dptr, dpins, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_components(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, vmo_stream stream) {
@@ -121,8 +155,7 @@ vmo_status vmo_components(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, 
   vmo::validate_hypergraph(C, h, false, S);
   VMO_REQUIRE(label != nullptr, "label is NULL");
   vmo::components(C, h->k, h->l, h->net_ptr, h->pins, label, S);
-  VMO_HIP(hipStreamSynchronize(S));
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_cut(vmo_ctx ctx, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, double* part_weight,
@@ -231,7 +264,7 @@ vmo_status vmo_order(vmo_ctx ctx, const vmo_hypergraph* h, int mode, int order, 
   jobs[0].job_index = 0;
   jobs[0].out = *out;
   run_order(C, jobs, npins, t_max, false, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_order_sbd(vmo_ctx ctx, const vmo_hypergraph* h, int mode, const float* x, const vmo_layout_params* lp,
@@ -247,7 +280,7 @@ vmo_status vmo_order_border(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_orde
                             int32_t* vperm_out, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::order_border(C, h, in, P, b, vperm_out, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, const int32_t* mu,
@@ -255,7 +288,7 @@ vmo_status vmo_order_schur(vmo_ctx ctx, const vmo_hypergraph* h, const float* x,
                            int32_t* vperm_out, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::order_schur(C, h, x, mu, in, P, P3, seed, t_max, vperm_out, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_match(vmo_ctx ctx, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* a,
@@ -293,28 +326,28 @@ vmo_status vmo_order_matched(vmo_ctx ctx, const vmo_hypergraph* h, int order, co
   jobs[0].out = *out;
   jobs[0].mu = mu;
   run_order(C, jobs, npins, t_max, false, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_matched_perms(vmo_ctx ctx, int32_t m, const int32_t* vperm, const int32_t* mu, int32_t* rperm,
                              int32_t* cperm, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::matched_perms(C, m, vperm, mu, rperm, cperm, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_refine_kl(vmo_ctx ctx, const vmo_hypergraph* h, int32_t* label, int32_t passes, int64_t* gain,
                          int32_t* ngroups, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::refine_kl(C, h, label, passes, gain, ngroups, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_finegrain(vmo_ctx ctx, int32_t m, int32_t n, const int64_t* rowptr, const int32_t* col, const float* x,
                          float* xnz, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::finegrain(C, m, n, rowptr, col, x, xnz, S);
-  API_END
+  API_END_ASYNC
 }
 
 static vmo_status order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, int32_t t_max, bool plain,
@@ -343,7 +376,7 @@ static vmo_status order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, i
     J[i].out = a.out;
   }
   run_order(C, J, npins, t_max, plain, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_order_batch(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs, int32_t t_max, vmo_stream stream) {
@@ -373,7 +406,7 @@ void vmo_layout_defaults(vmo_layout_params* p, uint64_t seed) {
 vmo_status vmo_layout(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::layout(C, h, p, x, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_coarsen(vmo_ctx ctx, const vmo_hypergraph* h, uint64_t seed, uint64_t comp, int32_t level,
@@ -389,21 +422,21 @@ vmo_status vmo_tree(vmo_ctx ctx, const float* x, const float* w, int32_t k, int3
                     vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::tree(C, x, w, k, leaf_cap, ints, cell2, flt, order, max_nodes, n_nodes, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_gradient(vmo_ctx ctx, const vmo_hypergraph* h, const float* x, float theta, int32_t leaf_cap, float* y,
                         float* z, int64_t* interactions, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::gradient(C, h, x, theta, leaf_cap, y, z, interactions, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_layout_steps(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, int32_t it0,
                             int32_t iters, double* alpha, vmo_stream stream) {
   API_BEGIN(ctx, stream)
   vmo::layout_steps(C, h, p, x, it0, iters, alpha, S);
-  API_END
+  API_END_ASYNC
 }
 
 vmo_status vmo_profile(vmo_ctx ctx, int every) {

@@ -136,7 +136,6 @@ void order_border(Ctx& c, const vmo_hypergraph* h, const vmo_order_out* in, int3
   const int32_t nn = check_ordering(c, k, P, in, s);
   if (b == 0) {
     VMO_HIP(hipMemcpyAsync(vperm_out, in->vperm, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, s));
-    VMO_HIP(hipStreamSynchronize(s));
     return;
   }
   Buf<int32_t> leaf_heap(c.pool, P), vh(c.pool, k);
@@ -151,7 +150,6 @@ void order_border(Ctx& c, const vmo_hypergraph* h, const vmo_order_out* in, int3
   VMO_LAUNCH(k_bd_keys, bsz(k), kBT, 0, s, in->vperm, in->node_vptr, nn, k, word.p, b, key.p, val.p);
   radix_sort<uint64_t>(c, key.p, val.p, k, 2 * b + bits_for((uint64_t)(nn - 1)), s);
   VMO_HIP(hipMemcpyAsync(vperm_out, val.p, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, s));
-  VMO_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace vmo

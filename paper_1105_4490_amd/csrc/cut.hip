@@ -9,6 +9,17 @@ namespace vmo {
 constexpr int kCT = 256;
 constexpr int kSmallNet = 64;
 
+// first position in the ascending a[0..n) holding a value >= x
+__device__ __forceinline__ int32_t lower_bound_u32(const uint32_t* a, int32_t n, uint32_t x) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // lambda(e) for nets of at most 64 pins: a pin counts if its part id does not
 // occur at an earlier pin of the net.  Larger nets are flagged for the sort path.
 __global__ void k_lambda_small(const int64_t* ptr, const int32_t* pins, int32_t l, const int32_t* part,
@@ -92,15 +103,6 @@ __global__ void k_pw_keys(const int32_t* part, int32_t k, int32_t nparts, uint32
     val[v] = (int32_t)v;
   }
 }
-__device__ __forceinline__ int32_t lower_bound_u32(const uint32_t* a, int32_t n, uint32_t x) {
-  int32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int32_t mid = lo + ((hi - lo) >> 1);
-    if (a[mid] < x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
 __global__ void k_pw_sum(const uint32_t* key, const int32_t* val, int32_t k, int32_t nparts, const float* w,
                          double* pw) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nparts; p += (int64_t)gridDim.x * blockDim.x) {
@@ -110,9 +112,92 @@ __global__ void k_pw_sum(const uint32_t* key, const int32_t* val, int32_t k, int
     pw[p] = a;
   }
 }
-__global__ void k_check_part(const int32_t* part, int32_t k, int* bad) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x)
+
+// bit 1: an id outside [0, 2^30); bit 2: an id >= nparts (separator ids)
+__global__ void k_check_part(const int32_t* part, int32_t k, int32_t nparts, int* bad) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x) {
     if (part[v] < 0 || part[v] >= (1 << 30)) atomicOr(bad, 1);
+    else if (part[v] >= nparts) atomicOr(bad, 2);
+  }
+}
+
+// ------------------------------------------------------ per-split cut ----
+// Node h (heap numbering, root 1) of a recursive bisection into P parts holds
+// a contiguous part range: the root [0, P), child 2h the first ceil(K/2) of
+// its K parts, child 2h + 1 the rest.  A cut net whose parts all lie below P
+// is cut at the deepest node holding its smallest and its largest part.
+__device__ __forceinline__ int32_t node_of_range(int32_t P, int32_t lo, int32_t hi) {
+  int32_t h = 1, p0 = 0, K = P;
+  while (K > 1) {
+    const int32_t K1 = (K + 1) >> 1;
+    if (hi < p0 + K1) { h = 2 * h; K = K1; }
+    else if (lo >= p0 + K1) { h = 2 * h + 1; p0 += K1; K -= K1; }
+    else break;
+  }
+  return h;
+}
+// key[e] = the node cutting net e, or 4P if it is not cut (or meets an id >= P)
+__global__ void k_net_split(const int64_t* ptr, const int32_t* pins, int32_t l, const int32_t* part, const int32_t* lam,
+                            int32_t P, uint32_t* key, int32_t* val) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < l; e += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t node = 4u * (uint32_t)P;
+    if (lam[e] > 1) {
+      int32_t lo = 0x7fffffff, hi = -1;
+      for (int64_t p = ptr[e]; p < ptr[e + 1]; ++p) {
+        const int32_t q = part[pins[p]];
+        lo = min(lo, q);
+        hi = max(hi, q);
+      }
+      if (hi < P) node = (uint32_t)node_of_range(P, lo, hi);
+    }
+    key[e] = node;
+    val[e] = (int32_t)e;
+  }
+}
+// split[h] = costs of the nets cut at h, one by one in ascending net id
+__global__ void k_split_sum(const uint32_t* key, const int32_t* val, int32_t l, int32_t P, const float* c,
+                            double* split) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < 4 * (int64_t)P;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = lower_bound_u32(key, l, (uint32_t)h), e = lower_bound_u32(key, l, (uint32_t)h + 1u);
+    double a = 0.0;
+    for (int32_t i = b; i < e; ++i) a = a + (c ? (double)c[val[i]] : 1.0);
+    split[h] = a;
+  }
+}
+// graph mode: split[h] = |S_h|, the vertices with part id P + h
+__global__ void k_sep_count(const int32_t* part, int32_t k, int32_t P, double* split) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < k; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t h = (int64_t)part[v] - P;
+    if (h >= 1 && h < 4 * (int64_t)P) atomicAdd(&split[h], 1.0);
+  }
+}
+// out[0] = max_h split[h], out[1] = the smallest such h (0: all zero); one block
+__global__ __launch_bounds__(kCT) void k_split_max(const double* split, int32_t n, double* out) {
+  __shared__ double sv[kCT];
+  __shared__ int32_t sh[kCT];
+  double bv = 0.0;
+  int32_t bh = 0x7fffffff;
+  for (int32_t h = threadIdx.x; h < n; h += kCT)
+    if (split[h] > bv || (split[h] == bv && bv > 0.0 && h < bh)) { bv = split[h]; bh = h; }
+  sv[threadIdx.x] = bv;
+  sh[threadIdx.x] = bh;
+  __syncthreads();
+  for (int off = kCT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double ov = sv[threadIdx.x + off];
+      const int32_t oh = sh[threadIdx.x + off];
+      if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oh < sh[threadIdx.x])) {
+        sv[threadIdx.x] = ov;
+        sh[threadIdx.x] = oh;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sv[0];
+    out[1] = sv[0] > 0.0 ? (double)sh[0] : 0.0;
+  }
 }
 
 static unsigned gsz(int64_t n) {
@@ -126,11 +211,14 @@ void cut(Ctx& c, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, d
   VMO_REQUIRE(part != nullptr, "part is NULL");
   VMO_REQUIRE(out != nullptr, "out is NULL");
   VMO_REQUIRE(nparts >= 0, "nparts must be >= 0");
+  bool separators = false;
   {
     Buf<int> bad(c.pool, 1);
     VMO_HIP(hipMemsetAsync(bad.p, 0, 4, s));
-    VMO_LAUNCH(k_check_part, gsz(h->k), kCT, 0, s, part, h->k, bad.p);
-    VMO_REQUIRE(read1(bad.p, s) == 0, "part ids must be in [0, 2^30)");
+    VMO_LAUNCH(k_check_part, gsz(h->k), kCT, 0, s, part, h->k, nparts, bad.p);
+    const int b = read1(bad.p, s);
+    VMO_REQUIRE(!(b & 1), "part ids must be in [0, 2^30)");
+    separators = (b & 2) != 0;
   }
   int32_t l = h->l;
   Buf<int32_t> lam(c.pool, l > 0 ? l : 1), big(c.pool, l + 1), bigrank(c.pool, l + 1);
@@ -167,11 +255,36 @@ void cut(Ctx& c, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, d
       VMO_LAUNCH(k_pw_sum, gsz(nparts), kCT, 0, s, key.p, val.p, h->k, nparts, h->w, part_weight);
     }
   }
-  double r[3];
-  read_bytes(r, o3.p, sizeof r, s);
+  // per-split cut of the recursive bisection into nparts parts
+  Buf<double> res(c.pool, 5);
+  if (nparts >= 1) {
+    const int64_t nh = 4 * (int64_t)nparts;
+    Buf<double> split(c.pool, nh);
+    if (separators) {
+      VMO_HIP(hipMemsetAsync(split.p, 0, sizeof(double) * nh, s));
+      VMO_LAUNCH(k_sep_count, gsz(h->k), kCT, 0, s, part, h->k, nparts, split.p);
+    } else if (l > 0) {
+      Buf<uint32_t> key(c.pool, l);
+      Buf<int32_t> val(c.pool, l);
+      VMO_LAUNCH(k_net_split, gsz(l), kCT, 0, s, h->net_ptr, h->pins, l, part, lam.p, nparts, key.p, val.p);
+      radix_sort<uint32_t>(c, key.p, val.p, l, bits_for((uint64_t)nh), s);
+      VMO_LAUNCH(k_split_sum, gsz(nh), kCT, 0, s, key.p, val.p, l, nparts, h->c, split.p);
+    } else {
+      VMO_HIP(hipMemsetAsync(split.p, 0, sizeof(double) * nh, s));
+    }
+    VMO_LAUNCH(k_split_max, 1, kCT, 0, s, split.p, (int32_t)nh, res.p + 3);
+  } else {
+    VMO_HIP(hipMemsetAsync(res.p + 3, 0, sizeof(double) * 2, s));
+  }
+  VMO_HIP(hipMemcpyAsync(res.p, o3.p, sizeof(double) * 3, hipMemcpyDeviceToDevice, s));
+  double r[5];
+  read_bytes(r, res.p, sizeof r, s);
   out->lambda_minus_one = r[0];
   out->cut_net = r[1];
   out->nets_cut = (int64_t)r[2];
+  out->max_split = r[3];
+  out->max_split_node = (int32_t)r[4];
+  out->separators = separators ? 1 : 0;
 }
 
 // ------------------------------------------------- allocation-free cut ----

@@ -346,7 +346,6 @@ void refine_kl(Ctx& c, const vmo_hypergraph* h, int32_t* label, int32_t passes, 
   if (ngroups) *ngroups = G;
   if (G == 0 || passes == 0) {
     if (gain && G > 0) fill_i64(gain, 0, G, s);
-    VMO_HIP(hipStreamSynchronize(s));
     return;
   }
   // adjacency: the edges at every vertex, ascending
@@ -390,7 +389,6 @@ void refine_kl(Ctx& c, const vmo_hypergraph* h, int32_t* label, int32_t passes, 
                pg.p, passes, maxdeg, gl.p);
   }
   if (gain) VMO_HIP(hipMemcpyAsync(gain, gl.p, sizeof(int64_t) * G, hipMemcpyDeviceToDevice, s));
-  VMO_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace vmo

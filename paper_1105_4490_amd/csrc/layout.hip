@@ -2259,7 +2259,6 @@ void layout(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, float* 
   VMO_HIP(hipMemcpyAsync(dlo.p, clo.data(), 4 * clo.size(), hipMemcpyHostToDevice, s));
   VMO_HIP(hipMemcpyAsync(doff.p, coff.data(), 8 * coff.size(), hipMemcpyHostToDevice, s));
   VMO_LAUNCH(k_pack, gsz(k), kLT, 0, s, xl.p, vorder.p, cpos.p, dlo.p, doff.p, k, x);
-  VMO_HIP(hipStreamSynchronize(s));
 }
 
 void coarsen(Ctx& C, const vmo_hypergraph* h, uint64_t seed, uint64_t comp, int32_t level, int32_t mm, int32_t* pi,
@@ -2311,7 +2310,6 @@ void tree(Ctx& C, const float* x, const float* w, int32_t k, int32_t cap, int32_
   VMO_REQUIRE(n <= max_nodes, "max_nodes is too small");
   VMO_LAUNCH(k_tree_out, gsz(n), kLT, 0, s, n, T.view(), ints, cell2, flt);
   VMO_HIP(hipMemcpyAsync(order, T.order.p, 4 * (size_t)k, hipMemcpyDeviceToDevice, s));
-  VMO_HIP(hipStreamSynchronize(s));
   *n_nodes = n;
 }
 
@@ -2346,7 +2344,6 @@ void layout_steps(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, f
   double a = *alpha;
   for (int32_t t = 0; t < iters; ++t) descent_step(C, L, xr.p, p, it0 + t, &a, y.p, gw, s);
   VMO_LAUNCH(k_from_rec, gsz(h->k), kLT, 0, s, xr.p, h->k, x);
-  VMO_HIP(hipStreamSynchronize(s));
   *alpha = a;
 }
 

@@ -297,8 +297,10 @@ __global__ void k_mp_marks(const int32_t* mark, int32_t m, int* bad) {
     if (mark[v] != 1) atomicOr(bad, 1);
   }
 }
+// writes nothing once the checks above failed (at[] may then exceed m)
 __global__ void k_mp_write(const int32_t* vperm, const int32_t* mu, const int32_t* isrow, const int32_t* at, int32_t m,
-                           int32_t* rperm, int32_t* cperm) {
+                           int32_t* rperm, int32_t* cperm, const int* bad) {
+  if (*bad) return;
   HM_STRIDE(p, 2 * (int64_t)m) {
     if (!isrow[p]) continue;
     const int32_t v = vperm[p];
@@ -318,21 +320,44 @@ void matched_perms(Ctx& c, int32_t m, const int32_t* vperm, const int32_t* mu, i
   VMO_HIP(hipMemsetAsync(mark.p, 0, sizeof(int32_t) * k, s));
   VMO_LAUNCH(k_mp_check, hsz(k), kHT, 0, s, vperm, mu, m, mark.p, isrow.p, bad.p);
   VMO_LAUNCH(k_mp_marks, hsz(k), kHT, 0, s, mark.p, m, bad.p);
-  const int b = read1(bad.p, s);
-  VMO_REQUIRE(!(b & 1), "vperm must be a permutation of the 2m vertices");
-  VMO_REQUIRE(!(b & 2), "every row needs a partner column (mu[i] in [m, 2m))");
+  // checked on the device: bit 1 (kAsyncPermutation) vperm is not a
+  // permutation, bit 2 (kAsyncPartner) a row without a partner column; the
+  // writes are then skipped and vmo_sync reports the failure
   scan_exclusive<int32_t>(c, isrow.p, at.p, k, at.p + k, s);
-  VMO_LAUNCH(k_mp_write, hsz(k), kHT, 0, s, vperm, mu, isrow.p, at.p, m, rperm, cperm);
-  VMO_HIP(hipStreamSynchronize(s));
+  VMO_LAUNCH(k_mp_write, hsz(k), kHT, 0, s, vperm, mu, isrow.p, at.p, m, rperm, cperm, bad.p);
+  post_async_check(c, bad.p, s);
 }
 
 // -------------------------------------------------------------- finegrain ----
-__global__ void k_finegrain(const int32_t* rowid, const int32_t* col, int64_t nnz, int32_t m, int64_t k,
-                            const float* x, float* xnz) {
-  HM_STRIDE(e, nnz) {
-    const int32_t i = rowid[e];
-    const int64_t jc = (int64_t)m + col[e];
-    for (int d = 0; d < 4; ++d) xnz[d * nnz + e] = (x[d * k + i] + x[d * k + jc]) * 0.5f;
+// The pattern's rows checked on the device: rowptr[0] = 0 and non-decreasing,
+// columns in [0, n) and ascending within a row (else kAsyncCsr).
+__global__ void k_fg_check(const int64_t* rowptr, const int32_t* col, int32_t m, int32_t n, int* bad) {
+  HM_STRIDE(i, m) {
+    const int64_t b = rowptr[i], e = rowptr[i + 1];
+    if ((i == 0 && b != 0) || e < b) {
+      atomicOr(bad, kAsyncCsr);
+      continue;
+    }
+    for (int64_t t = b; t < e; ++t) {
+      const int32_t j = col[t];
+      if (j < 0 || j >= n || (t > b && j <= col[t - 1])) {
+        atomicOr(bad, kAsyncCsr);
+        break;
+      }
+    }
+  }
+}
+// One thread per row; nnz = rowptr[m] read on the device (no host round
+// trip).  Writes nothing once the check failed.
+__global__ void k_finegrain(const int64_t* rowptr, const int32_t* col, int32_t m, int32_t n, const float* x,
+                            float* xnz, const int* bad) {
+  if (*bad) return;
+  const int64_t nnz = rowptr[m], k = (int64_t)m + n;
+  HM_STRIDE(i, m) {
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      const int64_t jc = (int64_t)m + col[e];
+      for (int d = 0; d < 4; ++d) xnz[d * nnz + e] = (x[d * k + i] + x[d * k + jc]) * 0.5f;
+    }
   }
 }
 
@@ -340,17 +365,12 @@ void finegrain(Ctx& c, int32_t m, int32_t n, const int64_t* rowptr, const int32_
                hipStream_t s) {
   VMO_REQUIRE(m >= 1 && n >= 1, "matrix needs m, n >= 1");
   VMO_REQUIRE((int64_t)m + n < (int64_t(1) << 31), "m + n must be below 2^31");
-  VMO_REQUIRE(rowptr && x, "NULL argument");
-  vmo_hypergraph rows{n, m, rowptr, col, nullptr, nullptr};
-  validate_hypergraph(c, &rows, false, s);
-  const int64_t nnz = read1(rowptr + m, s);
-  if (nnz > 0) {
-    VMO_REQUIRE(xnz != nullptr, "xnz is NULL");
-    Buf<int32_t> rowid(c.pool, nnz);
-    VMO_LAUNCH(k_rowid, hsz(nnz), kHT, 0, s, rowptr, m, nnz, rowid.p);
-    VMO_LAUNCH(k_finegrain, hsz(nnz), kHT, 0, s, rowid.p, col, nnz, m, (int64_t)m + n, x, xnz);
-  }
-  VMO_HIP(hipStreamSynchronize(s));
+  VMO_REQUIRE(rowptr && x && xnz, "NULL argument");
+  Buf<int> bad(c.pool, 1);
+  VMO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+  VMO_LAUNCH(k_fg_check, hsz(m), kHT, 0, s, rowptr, col, m, n, bad.p);
+  VMO_LAUNCH(k_finegrain, hsz(m), kHT, 0, s, rowptr, col, m, n, x, xnz, bad.p);
+  post_async_check(c, bad.p, s);
 }
 
 }  // namespace vmo

@@ -122,7 +122,6 @@ void dual(Ctx& c, const vmo_hypergraph* h, int64_t* dptr, int32_t* dpins, hipStr
   validate_hypergraph(c, h, false, s);
   VMO_REQUIRE(dptr != nullptr, "dptr is NULL");
   csr_transpose(c, h->l, h->k, h->net_ptr, h->pins, dptr, dpins, s);
-  VMO_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace vmo

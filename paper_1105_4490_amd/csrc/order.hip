@@ -1227,7 +1227,6 @@ void Engine::emit(const std::vector<int32_t>& slots, const std::vector<JobHost>&
     VMO_LAUNCH(k_net_out, gsz(Lv), kT, 0, s, dsub.p, m, Lv, val.p, douts.p);
     VMO_LAUNCH(k_net_ptr, m, kT, 0, s, dsub.p, m, kc.p, keybase.p, douts.p);
   }
-  VMO_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace vmo

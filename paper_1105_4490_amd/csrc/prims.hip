@@ -12,6 +12,18 @@ size_t Pool::size_class(size_t b) {
   return (b + g - 1) & ~(g - 1);
 }
 
+void Pool::trim_to(size_t cap) {
+  std::lock_guard<std::mutex> g(mu_);
+  while (idle_ > cap && !free_.empty()) {
+    auto it = std::prev(free_.end());  // the largest idle block
+    (void)hipFree(it->second);
+    held_ -= it->first;
+    idle_ -= it->first;
+    size_.erase(it->second);
+    free_.erase(it);
+  }
+}
+
 void* Pool::get(size_t bytes) {
   std::lock_guard<std::mutex> g(mu_);
   if (arena_) {
@@ -27,6 +39,7 @@ void* Pool::get(size_t bytes) {
   auto it = free_.lower_bound(cls);
   if (it != free_.end() && it->first <= 2 * cls) {
     void* p = it->second;
+    idle_ -= it->first;
     free_.erase(it);
     return p;
   }
@@ -51,6 +64,7 @@ void Pool::put(void* p) {
   auto it = size_.find(p);  // arena blocks are not in size_: nothing to do
   if (it == size_.end()) return;
   free_.emplace(it->second, p);
+  idle_ += it->second;
 }
 
 void Pool::trim() {
@@ -65,6 +79,7 @@ void Pool::trim_locked() {
     size_.erase(kv.second);
   }
   free_.clear();
+  idle_ = 0;
 }
 
 Pool::~Pool() {
@@ -104,6 +119,60 @@ Ctx::~Ctx() {
   }
   if (tune.dwork) (void)hipFree(tune.dwork);
   if (dflag) (void)hipFree(dflag);
+  if (aflag) (void)hipFree(aflag);
+  if (tail) (void)hipEventDestroy(tail);
+}
+
+// ------------------------------------------------------- asynchronous calls ----
+void join_tail(Ctx& c, hipStream_t s) {
+  if (c.tail_on && c.tail_stream != s) {
+    VMO_HIP(hipEventSynchronize(c.tail));
+    c.tail_on = false;
+  }
+}
+
+void mark_tail(Ctx& c, hipStream_t s) {
+  if (!c.tail) VMO_HIP(hipEventCreateWithFlags(&c.tail, hipEventDisableTiming));
+  VMO_HIP(hipEventRecord(c.tail, s));
+  c.tail_stream = s;
+  c.tail_on = true;
+}
+
+int* async_flag(Ctx& c) {
+  if (!c.aflag) {
+    VMO_HIP(hipMalloc(&c.aflag, sizeof(int)));
+    VMO_HIP(hipMemset(c.aflag, 0, sizeof(int)));
+  }
+  return c.aflag;
+}
+
+__global__ void k_or_word(const int* src, int* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && *src) atomicOr(dst, *src);
+}
+
+void post_async_check(Ctx& c, const int* word, hipStream_t s) {
+  int* f = async_flag(c);
+  VMO_LAUNCH(k_or_word, 1, 64, 0, s, word, f);
+}
+
+void check_async_flag(Ctx& c, hipStream_t s) {
+  if (!c.aflag) return;
+  const int v = read1(c.aflag, s);
+  if (!v) return;
+  VMO_HIP(hipMemsetAsync(c.aflag, 0, sizeof(int), s));
+  VMO_HIP(hipStreamSynchronize(s));
+  std::string m = "an earlier asynchronous call rejected its input:";
+  if (v & kAsyncPermutation) m += " vperm is not a permutation of the vertices;";
+  if (v & kAsyncPartner) m += " a row has no partner column (mu[i] in [m, 2m));";
+  if (v & kAsyncCsr) m += " CSR arrays invalid (rowptr not non-decreasing from 0, or a column outside [0, n) or not ascending);";
+  throw Error(VMO_E_INVALID, m);
+}
+
+void trim_pool(Ctx& c, hipStream_t s) {
+  if (c.pool_cap == 0 || c.pool.idle() <= c.pool_cap) return;
+  VMO_HIP(hipStreamSynchronize(s));
+  c.tail_on = false;
+  c.pool.trim_to(c.pool_cap);
 }
 
 // ----------------------------------------------------------------- tuner ----

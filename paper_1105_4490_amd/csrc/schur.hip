@@ -160,7 +160,6 @@ void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const int32_t*
   const int32_t nb = (int32_t)jrank.size();
   if (nb == 0) {
     VMO_HIP(hipMemcpyAsync(vperm_out, in->vperm, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, s));
-    VMO_HIP(hipStreamSynchronize(s));
     return;
   }
   const int64_t nper = 4 * (int64_t)P3;
@@ -242,7 +241,6 @@ void order_schur(Ctx& c, const vmo_hypergraph* h, const float* x, const int32_t*
   Buf<int32_t> outb(c.pool, k);
   VMO_LAUNCH(k_sc_compose, ssz(k), kST, 0, s, in->vperm, in->node_vptr, nn, k, djob.p, djbase.p, v3.p, outb.p);
   VMO_HIP(hipMemcpyAsync(vperm_out, outb.p, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, s));
-  VMO_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace vmo

@@ -350,6 +350,7 @@ static void serve_loop(vmo_server_s* S) {
       }
       if (!fin.empty()) {
         E.emit(slots, hosts);
+        VMO_HIP(hipStreamSynchronize(S->stream));  // the outputs are complete before their tickets finish
         check_device_flag(S->ctx, S->stream);
         for (size_t i = 0; i < fin.size(); ++i) {
           E.arena_release(slots[i]);

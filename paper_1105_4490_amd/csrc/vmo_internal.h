@@ -63,6 +63,12 @@ class Pool {
     return held_;
   }
   void trim();
+  // Frees idle blocks, largest first, until at most cap bytes stay idle.
+  void trim_to(size_t cap);
+  size_t idle() const {
+    std::lock_guard<std::mutex> g(mu_);
+    return idle_;
+  }
   void set_arena(Arena* a) {
     std::lock_guard<std::mutex> g(mu_);
     arena_ = a;
@@ -74,7 +80,7 @@ class Pool {
   mutable std::mutex mu_;
   std::multimap<size_t, void*> free_;
   std::unordered_map<void*, size_t> size_;
-  size_t held_ = 0;
+  size_t held_ = 0, idle_ = 0;
   Arena* arena_ = nullptr;
 };
 
@@ -164,8 +170,32 @@ struct Ctx {
   // timing create events or device counters.
   bool noalloc = false;
   int* arena_flag = nullptr;
+  // Calls that return before their work is done: the event recorded on the
+  // stream of the last such call (tail_on while it may be pending), which a
+  // call on another stream waits for before reusing pool blocks; and the
+  // sticky word their device-side checks set (kAsync* bits), which vmo_sync
+  // turns into VMO_E_INVALID.
+  hipEvent_t tail = nullptr;
+  hipStream_t tail_stream = nullptr;
+  bool tail_on = false;
+  int* aflag = nullptr;
+  size_t pool_cap = 0;  // idle pool bytes kept after a synchronising call (0: no bound)
   ~Ctx();
 };
+enum : int { kAsyncPermutation = 1, kAsyncPartner = 2, kAsyncCsr = 4 };
+// Waits for the last asynchronous call's work if it ran on another stream.
+void join_tail(Ctx& c, hipStream_t s);
+// Marks the end of an asynchronous call on s.
+void mark_tail(Ctx& c, hipStream_t s);
+// The context's sticky asynchronous-check word (allocated and zeroed on first use).
+int* async_flag(Ctx& c);
+// ORs a call's check word into the sticky word (on the stream, no wait).
+void post_async_check(Ctx& c, const int* word, hipStream_t s);
+// After the stream is synchronised: throws VMO_E_INVALID naming the checks
+// that failed since the last vmo_sync, and clears the word.
+void check_async_flag(Ctx& c, hipStream_t s);
+// Trims the pool to its bound after a synchronising call (waits for s first).
+void trim_pool(Ctx& c, hipStream_t s);
 
 // Calls of the calling host thread read device scalars into plain host
 // memory instead of its pinned buffer (which the first use would allocate).

@@ -220,8 +220,11 @@ def test_matched_rejects_bad_input(ctx):
     bad[0], bad[m + m - 1] = m + m - 1, 0
     with pytest.raises(Pk.VmoError):
         ctx.order_matched(dh, dx, dev(bad, np.int32), 4, 1)
-    with pytest.raises(Pk.VmoError):
-        ctx.matched_perms(m, dev(np.zeros(k), np.int32), dev(mu, np.int32))   # not a permutation
+    # not a permutation: checked on the device, reported by the next sync
+    ctx.matched_perms(m, dev(np.zeros(k), np.int32), dev(mu, np.int32))
+    with pytest.raises(Pk.VmoError, match="not a permutation"):
+        ctx.sync()
+    ctx.sync()   # the word was cleared
     a = np.ones(int(g.rowptr[-1]), np.float32)
     a[3] = np.inf
     with pytest.raises(Pk.VmoError):

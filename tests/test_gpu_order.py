@@ -80,6 +80,40 @@ def test_cut(ctx, seed):
     assert got["cut_net"] == ref["cut_net"]
     assert got["nets_cut"] == ref["nets_cut"]
     assert np.array_equal(host(got["part_weight"]), ref["part_weight"])
+    check_max_split(got, h, part, P)
+
+
+def check_max_split(got, h, part, P):
+    sp, graph = oracle.split_cuts(h, part, P)
+    assert got["separators"] == graph
+    assert got["max_split"] == sp.max()
+    assert got["max_split_node"] == (int(np.argmax(sp)) if sp.max() > 0 else 0)
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_cut_non_integer_weights_and_costs(ctx, seed):
+    """Weights and costs spread over several orders of magnitude: the part
+    weights (added per part in ascending vertex id) and the per-split cut
+    (per node in ascending net id) equal the oracle's bit for bit; the FP64
+    totals, summed in another fixed order, agree within (l + 1) 2^-53 of the
+    total, and are the same on a second run."""
+    g = vmo_gen.random_hypergraph_csr(6000, 5000, seed, maxdeg=9)
+    h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+    r = vmo_gen.rng(seed, 13)
+    h.w = (10.0 ** r.uniform(-4, 4, size=h.k)).astype(np.float32)
+    h.c = (10.0 ** r.uniform(-3, 3, size=h.l)).astype(np.float32)
+    P = 29
+    part = r.integers(0, P, size=h.k).astype(np.int32)
+    dh, dp = dev_h(h), torch.as_tensor(part).cuda()
+    got = ctx.cut(dh, dp, P)
+    again = ctx.cut(dh, dp, P)
+    ref = oracle.cut(h, part, P)
+    assert np.array_equal(host(got["part_weight"]), ref["part_weight"])
+    assert got["nets_cut"] == ref["nets_cut"]
+    for f in ("lambda_minus_one", "cut_net"):
+        assert abs(got[f] - ref[f]) <= (h.l + 1) * 2.0 ** -53 * ref[f], f
+        assert got[f] == again[f]
+    check_max_split(got, h, part, P)
 
 
 @pytest.mark.parametrize("k,seed,clusters", [(2, 1, 0), (1000, 2, 3), (4099, 3, 0), (70001, 4, 5), (262144, 5, 0)])
@@ -130,9 +164,13 @@ def test_order_graph_mode(ctx, N, P, ordr):
     g = vmo_gen.grid3d(N, seed=N)
     h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
     x = grid_coords(N, 1, N)
-    got = ctx.order(dev_h(h), dev_x(x), P, 7, mode=1, order=ordr)
+    dh = dev_h(h)
+    got = ctx.order(dh, dev_x(x), P, 7, mode=1, order=ordr)
     ref = oracle.order(h, x, P, 7, mode=oracle.GRAPH_MODE, ord=ordr)
     compare_order(got, ref, oracle.GRAPH_MODE, h.k, h.l)
+    # the cut call's maximum split cut (|S_h| here) is the ordering's own
+    c = ctx.cut(dh, got["part"], P)
+    assert c["separators"] and c["max_split"] == ref.split_cut[:ref.n_nodes].max()
 
 
 @pytest.mark.parametrize("case", ["grid", "zipf", "tiny"])
@@ -152,9 +190,13 @@ def test_order_net_mode(ctx, case, ordr):
         h = oracle.hypergraph(7, [[0, 1], [], [2, 3, 4], [5, 6], [0, 6], []])
         x = vmo_gen.random_points(7, 4)
         P = 5
-    got = ctx.order(dev_h(h), dev_x(x), P, 11, mode=0, order=ordr)
+    dh = dev_h(h)
+    got = ctx.order(dh, dev_x(x), P, 11, mode=0, order=ordr)
     ref = oracle.order(h, x, P, 11, mode=oracle.NET_MODE, ord=ordr)
     compare_order(got, ref, oracle.NET_MODE, h.k, h.l)
+    # the cut call's maximum split cut (nets cut at each node) is the ordering's own
+    c = ctx.cut(dh, got["part"], P)
+    assert not c["separators"] and c["max_split"] == ref.split_cut[:ref.n_nodes].max()
 
 
 def test_order_degenerate(ctx):

@@ -89,3 +89,44 @@ def test_cut_minimum_over_bisections_small():
     best = min(oracle.cut(h, np.array(p), 2)["cut_net"]
                for p in itertools.product([0, 1], repeat=6) if sum(p) == 3)
     assert best == 1
+
+
+def test_split_cuts_hand_worked():
+    """Recursive bisection into P = 3 parts: the root holds parts [0, 3),
+    child 2 the parts [0, 2), child 3 part 2; node 2's children 4 and 5 hold
+    parts 0 and 1.  Nets {0,1} (parts 0,1) are cut at node 2, {1,2} (parts
+    1,2) at the root, {0,3} (parts 0,0) nowhere, {3,4} (parts 0,1) at node 2;
+    costs 1, 2, 4, 8 give split = {1: 2, 2: 1 + 8}."""
+    h = oracle.hypergraph(5, [[0, 1], [1, 2], [0, 3], [3, 4]], c=[1, 2, 4, 8])
+    part = np.array([0, 1, 2, 0, 1], dtype=np.int32)
+    sp, graph = oracle.split_cuts(h, part, 3)
+    assert not graph
+    want = np.zeros(12)
+    want[1], want[2] = 2, 9
+    assert np.array_equal(sp, want)
+    # with separator ids (P + h): the sizes of the separators
+    part2 = np.array([0, 3 + 1, 2, 3 + 2, 3 + 1], dtype=np.int32)
+    sp2, graph2 = oracle.split_cuts(h, part2, 3)
+    assert graph2 and sp2[1] == 2 and sp2[2] == 1 and sp2.sum() == 3
+
+
+@pytest.mark.parametrize("seed,mode,P", [(1, 0, 13), (2, 0, 64), (3, 1, 16), (4, 1, 7)])
+def test_split_cuts_equal_the_orderings_own(seed, mode, P):
+    """The per-split cut recovered from part ids alone equals the one the
+    recursive ordering records while it splits (nets placed at the node that
+    cuts them, separators at their node), node by node."""
+    if mode == 0:
+        g = vmo_gen.random_hypergraph_csr(600, 400, seed, maxdeg=5)
+        h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
+        h.c = vmo_gen.rng(seed, 12).integers(1, 5, size=h.l).astype(np.float32)
+    else:
+        g = vmo_gen.grid3d(9, seed=seed)
+        h = oracle.symmetric(g.m, g.n, g.rowptr, g.col)
+    x = vmo_gen.random_points(h.k, seed, clusters=5)
+    o = oracle.order(h, x, P, seed, mode=mode, ord=oracle.BBD)
+    sp, graph = oracle.split_cuts(h, o.part, P)
+    assert graph == (mode == 1 and (o.part >= P).any())
+    rec = np.zeros(4 * P)
+    for r in range(o.n_nodes):
+        rec[o.node_heap[r]] = o.split_cut[r]
+    assert np.array_equal(sp, rec)
