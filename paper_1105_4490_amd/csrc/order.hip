@@ -273,58 +273,100 @@ __global__ void k_seed2(const JobDev* jobs, SegArrays sg, int64_t s0, int64_t S,
   plane_from(c1, c2, &sg.plane[s * 5]);
 }
 
-// One Lloyd assignment: side by the plane, sums of side 1, count of side 1,
-// and the number of changed assignments.
+// Segmented sum across a wavefront of int32 values (exact here: every value
+// is below 2^29), as wave_seg_sum.
+template <int F>
+__device__ __forceinline__ bool wave_seg_sum32(int key, int32_t (&v)[F]) {
+  int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int ok = __shfl_down(key, off, 64);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      int32_t o = __shfl_down(v[f], off, 64);
+      if (lane + off < 64 && ok == key) v[f] += o;
+    }
+  }
+  int prev = __shfl_up(key, 1, 64);
+  return key >= 0 && (lane == 0 || prev != key);
+}
+
 // One Lloyd assignment: side by the plane, and the segment's side-1 sums,
-// side-1 count and changed count.  Four consecutive positions per thread (Np is
-// a multiple of 4 and the arrays are 16-byte aligned): 16-byte loads of each grid
-// coordinate and of the segment ids, 4-byte loads and stores of the sides.
-// Bytes of the pack outside [p0, p1) or in segments that do not iterate are
-// written back unchanged (one thread owns each pack).
+// side-1 count and changed count.  PPT (4 or 8) consecutive positions per
+// thread (Np is a multiple of 4 and the arrays are 16-byte aligned): 16-byte
+// loads of each grid coordinate and of the segment ids, 4-byte loads and
+// stores of the sides.  Bytes of a pack outside [p0, p1) or in segments that
+// do not iterate are written back unchanged (one thread owns each pack).
+// A thread sums its positions of the pack's first segment in int32 (at most
+// PPT coordinates below 2^20 each); positions of a later segment in the same
+// pack (a segment boundary inside the pack, once per segment at most) go to
+// the segment's accumulators directly.  A wavefront whose threads all hold
+// one segment adds up by DPP, else by a segmented shuffle sum (int32: below
+// 64 PPT 2^20 = 2^29); the block adds equal segments before the atomics.
 // prev: segments still iterating after the previous iteration (NULL: run);
 // when none is, this iteration would skip every segment, so it returns.
-__global__ __launch_bounds__(1024) void k_assign4(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
-                                                  int64_t p0, int64_t p1, int it, uint8_t* side,
-                                                  unsigned long long* work, const int32_t* prev) {
+template <int PPT>
+__global__ __launch_bounds__(1024) void k_assign(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
+                                                 int64_t p0, int64_t p1, int it, uint8_t* side,
+                                                 unsigned long long* work, const int32_t* prev) {
   if (prev && *prev == 0) return;
-  const int64_t b = (p0 & ~int64_t(3)) + 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-  const bool inb = b < p1;
-  int key[4] = {-1, -1, -1, -1};
-  int64_t v[4][6];
+  const int64_t b = (p0 & ~int64_t(3)) + PPT * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  int kt = -1;          // the pack's first iterating segment
+  int32_t acc[6] = {0, 0, 0, 0, 0, 0};
+  // state and plane of the segment of the previous position (a pack meets
+  // one segment, rarely two): loaded once per segment, not per position
+  int32_t cs = -1;
+  bool citer = false;
+  double pl[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int f = 0; f < 6; ++f) v[u][f] = 0;
-  if (inb) {
-    const int4 sp = *reinterpret_cast<const int4*>(segpos + b);
-    const uint4 q0 = *reinterpret_cast<const uint4*>(q + b);
-    const uint4 q1 = *reinterpret_cast<const uint4*>(q + Np + b);
-    const uint4 q2 = *reinterpret_cast<const uint4*>(q + 2 * Np + b);
-    const uint4 q3 = *reinterpret_cast<const uint4*>(q + 3 * Np + b);
-    uchar4 so = *reinterpret_cast<const uchar4*>(side + b);
+  for (int h = 0; h < PPT / 4; ++h) {
+    const int64_t bh = b + 4 * h;
+    if (bh >= p1) break;
+    const int4 sp = *reinterpret_cast<const int4*>(segpos + bh);
+    const uint4 q0 = *reinterpret_cast<const uint4*>(q + bh);
+    const uint4 q1 = *reinterpret_cast<const uint4*>(q + Np + bh);
+    const uint4 q2 = *reinterpret_cast<const uint4*>(q + 2 * Np + bh);
+    const uint4 q3 = *reinterpret_cast<const uint4*>(q + 3 * Np + bh);
+    const uchar4 so = *reinterpret_cast<const uchar4*>(side + bh);
     const int spa[4] = {sp.x, sp.y, sp.z, sp.w};
     const uint32_t a0[4] = {q0.x, q0.y, q0.z, q0.w}, a1[4] = {q1.x, q1.y, q1.z, q1.w};
     const uint32_t a2[4] = {q2.x, q2.y, q2.z, q2.w}, a3[4] = {q3.x, q3.y, q3.z, q3.w};
     uint8_t sv[4] = {so.x, so.y, so.z, so.w};
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t i = b + u;
-      const int32_t s = spa[u];
-      if (i < p0 || i >= p1 || s < 0 || sg.state[s] != kStIter) continue;
-      key[u] = s;
-      const double e = plane_eval(a0[u], a1[u], a2[u], a3[u], &sg.plane[s * 5]);
+      const int64_t i = bh + u;
+      const int32_t sgm = spa[u];
+      if (i < p0 || i >= p1 || sgm < 0) continue;
+      if (sgm != cs) {
+        cs = sgm;
+        citer = sg.state[sgm] == kStIter;
+        if (citer)
+          for (int f = 0; f < 5; ++f) pl[f] = sg.plane[sgm * 5 + f];
+      }
+      if (!citer) continue;
+      const double e = plane_eval(a0[u], a1[u], a2[u], a3[u], pl);
       const uint8_t sd = e <= 0.0 ? 1 : 2;
-      if (it > 0 && sd != sv[u]) v[u][5] = 1;
+      const int32_t chg = (it > 0 && sd != sv[u]) ? 1 : 0;
       sv[u] = sd;
-      if (sd == 1) { v[u][0] = a0[u]; v[u][1] = a1[u]; v[u][2] = a2[u]; v[u][3] = a3[u]; v[u][4] = 1; }
+      if (kt < 0) kt = sgm;
+      if (sgm == kt) {
+        if (sd == 1) {
+          acc[0] += (int32_t)a0[u]; acc[1] += (int32_t)a1[u]; acc[2] += (int32_t)a2[u]; acc[3] += (int32_t)a3[u];
+          acc[4] += 1;
+        }
+        acc[5] += chg;
+      } else {
+        unsigned long long* g = (unsigned long long*)&sg.acc[sgm * kAccF + kAccS1];
+        if (sd == 1) {
+          atomicAdd(g + 0, (unsigned long long)a0[u]); atomicAdd(g + 1, (unsigned long long)a1[u]);
+          atomicAdd(g + 2, (unsigned long long)a2[u]); atomicAdd(g + 3, (unsigned long long)a3[u]);
+          atomicAdd(g + 4, 1ull);
+        }
+        if (chg) atomicAdd(g + 5, 1ull);
+      }
     }
-    *reinterpret_cast<uchar4*>(side + b) = make_uchar4(sv[0], sv[1], sv[2], sv[3]);
+    *reinterpret_cast<uchar4*>(side + bh) = make_uchar4(sv[0], sv[1], sv[2], sv[3]);
   }
-  // one key for the thread's pack: -1 none, -2 mixed
-  int kt = -1;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-    if (key[u] >= 0) kt = (kt == -1 || kt == key[u]) ? key[u] : -2;
   const int k0 = __builtin_amdgcn_readfirstlane(kt);
   // wavefronts with one segment leave their sums here; the block adds those
   // of equal segments before the atomics (a level's first segments hold
@@ -333,44 +375,36 @@ __global__ __launch_bounds__(1024) void k_assign4(SegArrays sg, const int32_t* s
   __shared__ int skey[32];
   __shared__ long long ssum[32][6];
   const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (k0 != -2 && __all(kt == k0)) {
-    // one segment across the wavefront: 32-bit DPP sums (totals below 256 * 2^20)
+  if (__all(kt == k0)) {
     if (k0 >= 0) {
       int32_t t[6];
 #pragma unroll
-      for (int f = 0; f < 6; ++f)
-        t[f] = wave_sum_dpp((int32_t)(v[0][f] + v[1][f] + v[2][f] + v[3][f]));
+      for (int f = 0; f < 6; ++f) t[f] = wave_sum_dpp(acc[f]);
       if (lane_id() == 63)
         for (int f = 0; f < 6; ++f) ssum[wv][f] = t[f];
     }
     if (lane_id() == 63) skey[wv] = k0;
   } else {
     if (lane_id() == 63) skey[wv] = -1;
-    // the u-th positions of the lanes increase with the lane: equal keys are runs
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int64_t w6[6];
-#pragma unroll
-      for (int f = 0; f < 6; ++f) w6[f] = v[u][f];
-      if (wave_seg_sum<6>(key[u], w6))
-        for (int f = 0; f < 6; ++f)
-          if (w6[f]) atomicAdd((unsigned long long*)&sg.acc[key[u] * kAccF + kAccS1 + f], (unsigned long long)w6[f]);
-    }
+    // the lanes' packs increase with the lane: equal keys are runs
+    if (wave_seg_sum32<6>(kt, acc))
+      for (int f = 0; f < 6; ++f)
+        if (acc[f]) atomicAdd((unsigned long long*)&sg.acc[kt * kAccF + kAccS1 + f], (unsigned long long)acc[f]);
   }
   __syncthreads();
   if (threadIdx.x < 6) {
     // field f: one atomic per run of wavefronts with the same segment
     const int f = threadIdx.x;
     int cur = -1;
-    long long acc = 0;
+    long long a = 0;
     for (int w = 0; w <= nw; ++w) {
       const int kw = w < nw ? skey[w] : -1;
       if (kw != cur) {
-        if (cur >= 0 && acc) atomicAdd((unsigned long long*)&sg.acc[cur * kAccF + kAccS1 + f], (unsigned long long)acc);
+        if (cur >= 0 && a) atomicAdd((unsigned long long*)&sg.acc[cur * kAccF + kAccS1 + f], (unsigned long long)a);
         cur = kw;
-        acc = 0;
+        a = 0;
       }
-      if (kw >= 0) acc += ssum[w][f];
+      if (kw >= 0) a += ssum[w][f];
     }
   }
   if (work && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(work, 17ull * (unsigned long long)(p1 - p0));
@@ -1029,24 +1063,30 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
   VMO_LAUNCH(k_d2, nblocks(np, kT), kT, 0, s, sg, segpos.p, q.p, Np, p0, p1, dd.p);
   scan_exclusive<U128>(c, dd.p + p0, dd.p + p0, np, dd.p + p1, s);
   VMO_LAUNCH(k_seed2, nblocks(Sn, kT), kT, 0, s, dj.p, sg, s0, Sn, dd.p, q.p, Np);
-  // The block size of the assignment is tuned online per size bucket in the
-  // batched form (every candidate gives the same result).
+  // The assignment's launch shape is tuned online per size bucket in the
+  // batched form (every candidate gives the same result): block size x
+  // positions per thread (4 or 8, so 256 or 512 positions per wavefront,
+  // which sets how many small segments share one wavefront's reduction).
   static const int kBlocks[4] = {128, 256, 512, 1024};
   const int bucket = bits_for((uint64_t)np);
   Buf<int32_t> active(c.pool, (size_t)t_max + 1);  // one counter per iteration, cleared once
   fill_i32(active.p, 0, (int64_t)t_max + 1, s);
   for (int it = 0; it <= t_max; ++it) {
     bool timed = false;
-    const int cfg = tuned ? tune_pick(c, kTuneAssign, bucket, 4, &timed) : 1;
-    const int B = kBlocks[cfg];
+    const int cfg = tuned ? tune_pick(c, kTuneAssign, bucket, 8, &timed) : 1;
+    const int B = kBlocks[cfg & 3], ppt = cfg < 4 ? 4 : 8;
     unsigned long long* tw = timed ? tune_begin(c, kTuneAssign, bucket, cfg, s) : nullptr;
     int ph = prof_begin(c, "assign", 17.0 * (double)np, s, nullptr);
-    const int64_t packs = (p1 - (p0 & ~int64_t(3)) + 3) / 4;
+    const int64_t packs = (p1 - (p0 & ~int64_t(3)) + ppt - 1) / ppt;
     // after an iteration that left no segment iterating the rest return at
     // once, except the launches that are timed (tuner, profile), which run
     const int32_t* prev = it > 0 ? active.p + it - 1 : nullptr;
-    VMO_LAUNCH(k_assign4, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw,
-               timed || ph >= 0 ? nullptr : prev);
+    if (ppt == 4)
+      VMO_LAUNCH(k_assign<4>, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw,
+                 timed || ph >= 0 ? nullptr : prev);
+    else
+      VMO_LAUNCH(k_assign<8>, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw,
+                 timed || ph >= 0 ? nullptr : prev);
     prof_end(c, ph, s);
     if (timed) tune_end(c, s);
     VMO_LAUNCH(k_lloyd_fin, nblocks(Sn, kT), kT, 0, s, sg, s0, Sn, it, t_max, active.p + it, prev);
