@@ -463,13 +463,17 @@ __global__ __launch_bounds__(kRsT) void k_rs_hist(const K* __restrict__ keys, in
     if (h[p][t]) atomicAdd(&ghist[p * 256 + t], h[p][t]);
 }
 
-template <class K>
+// RI: rounds per tile (a power of two up to kRsMaxI); the LDS counts and the
+// key registers are sized for it, so that short tiles leave room for more
+// blocks per CU.
+template <class K, int RI>
 __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, const int32_t* __restrict__ vin,
                                                      K* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
-                                                     int shift, int ri, const uint32_t* __restrict__ ghist,
+                                                     int shift, const uint32_t* __restrict__ ghist,
                                                      uint64_t* status, uint32_t* tile_ctr, int* err) {
+  constexpr int ri = RI;
   // per (round, wavefront, digit): count, then exclusive offset in the tile
-  __shared__ uint16_t cnt[kRsMaxI][kRsT / 64][256];
+  __shared__ uint16_t cnt[RI][kRsT / 64][256];
   __shared__ int run[256];
   __shared__ int wsum[kRsT / 64];
   __shared__ int tile_sh;
@@ -481,14 +485,13 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
   const int64_t tile = tile_sh;
   const int64_t base = tile * kRsT * ri;
   const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
-  K key[kRsMaxI];
-  int dig[kRsMaxI], rk[kRsMaxI];
+  K key[RI];
+  int dig[RI], rk[RI];
   // ranks of every round at once: lanes of a wavefront with equal digits are
   // found by eight ballots; each (round, wavefront, digit) count is written by
   // the first such lane
 #pragma unroll
-  for (int r = 0; r < kRsMaxI; ++r) {
-    if (r >= ri) break;
+  for (int r = 0; r < RI; ++r) {
     const int64_t idx = base + (int64_t)r * kRsT + t;
     const bool valid = idx < n;
     key[r] = valid ? kin[idx] : K(0);
@@ -555,8 +558,7 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
   run[t] = (int)(pre + excl);
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kRsMaxI; ++r) {
-    if (r >= ri) break;
+  for (int r = 0; r < RI; ++r) {
     if (dig[r] < 0) continue;
     const int d = dig[r];
     const int dest = run[d] + cnt[r][w][d] + rk[r];
@@ -615,8 +617,17 @@ void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t
   K* ka = keys; K* kb = k2.p;
   int32_t* va = vals; int32_t* vb = vals ? v2.p : nullptr;
   for (int ps = 0; ps < passes; ++ps) {
-    VMO_LAUNCH((k_rs_scatter<K>), (unsigned)ntiles, kRsT, 0, s, ka, va, kb, vb, n, 8 * ps, ri, ghist + 256 * ps,
-               status + (size_t)ps * ntiles * 256, ctr + ps, err);
+#define VMO_RS_SCATTER(R)                                                                                     \
+  VMO_LAUNCH((k_rs_scatter<K, R>), (unsigned)ntiles, kRsT, 0, s, ka, va, kb, vb, n, 8 * ps, ghist + 256 * ps, \
+             status + (size_t)ps * ntiles * 256, ctr + ps, err)
+    switch (ri) {
+      case 1: VMO_RS_SCATTER(1); break;
+      case 2: VMO_RS_SCATTER(2); break;
+      case 4: VMO_RS_SCATTER(4); break;
+      case 8: VMO_RS_SCATTER(8); break;
+      default: VMO_RS_SCATTER(16); break;
+    }
+#undef VMO_RS_SCATTER
     std::swap(ka, kb);
     std::swap(va, vb);
   }
