@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--requests", type=int, default=40, help="serve mode: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve mode: arrivals per second")
     ap.add_argument("--nnz-max", type=float, default=1e7, help="serve mode: largest nnz of a request")
+    ap.add_argument("--serve-budget-gib", type=int, default=64,
+                    help="serve mode: device memory of the server (40 %% arenas, 60 %% layouts)")
+    ap.add_argument("--serve-threads", type=int, default=4, help="serve mode: layout threads")
     ap.add_argument("--no-stable", action="store_true",
                     help="serve mode: skip the second stream at half the measured capacity")
     args = ap.parse_args()
@@ -491,7 +494,7 @@ def bench_serve(args, ctx, field=False):
 
     def stream(arrivals):
         """Submit the jobs at the given arrival times; (latencies ms, span s, stats)."""
-        srv = P.Server(budget_bytes=16 << 30, max_jobs=256)
+        srv = P.Server(budget_bytes=args.serve_budget_gib << 30, max_jobs=256, layout_threads=args.serve_threads)
         tickets = []
         t0 = time.perf_counter()
         for (jb, _, nz), at in zip(jobs, arrivals):
@@ -525,7 +528,8 @@ def bench_serve(args, ctx, field=False):
                    "seed": SEED},
         "latency_ms": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99), "max": max(lat)},
         "offered_nnz_per_s": total / max(jobs[-1][1], 1e-9),
-        "busy_ms": st["busy_ms"], "ticks": st["ticks"],
+        "busy_ms": st["busy_ms"], "ticks": st["ticks"], "max_tick_jobs": st["max_tick_jobs"],
+        "mean_tick_jobs": st["tick_jobs"] / max(st["ticks"], 1), "layout_bytes_peak": st["layout_bytes_peak"],
     }
     if not args.no_stable and capacity < line["offered_nnz_per_s"]:
         # the same jobs again as a Poisson stream at half the measured capacity
@@ -539,7 +543,8 @@ def bench_serve(args, ctx, field=False):
     if field:
         line["scaled"] = f"{len(jobs)} requests of the 3,000-request stream"
         return {k: line[k] for k in ("metric", "value", "unit", "config", "latency_ms", "offered_nnz_per_s",
-                                     "busy_ms", "ticks", "scaled") + (("stable",) if "stable" in line else ())}
+                                     "busy_ms", "ticks", "max_tick_jobs", "mean_tick_jobs", "layout_bytes_peak",
+                                     "scaled") + (("stable",) if "stable" in line else ())}
     print(json.dumps(line))
 
 

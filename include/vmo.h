@@ -206,6 +206,11 @@ typedef struct {
 /* Fills p with the defaults above and the given seed. */
 void vmo_layout_defaults(vmo_layout_params* p /* (host) */, uint64_t seed);
 
+/* Upper bound of the device memory the workspace of vmo_layout takes for a
+   hypergraph of k vertices, l nets and npins pins (the serving loop admits
+   layouts by it). */
+size_t vmo_layout_bytes(int32_t k, int32_t l, int64_t npins);
+
 /* [async] Full layout.  x [4][k] FP32 SoA output.  Reads back: the input
    checks, the component count and each component's size, each coarse level's
    sizes (its buffers are sized from them), one matching flag per eight
@@ -455,9 +460,14 @@ vmo_status vmo_order_batch_plain(vmo_ctx ctx, int32_t njobs, const vmo_job* jobs
  * at the next tick, and a finished job is written to its output buffers and
  * leaves, freeing its ranges.  A job's result does not depend on the other
  * jobs in the mix (its random draws are keyed by seed and job_index).
- * Jobs with x == NULL are laid out (vmo_layout with *lp) after admission, by
- * layout threads that run beside the ticks; memory of those layouts is not
- * part of budget_bytes.
+ * budget_bytes bounds all the device memory the server holds: 40 % sizes the
+ * arenas, 60 % the layouts of jobs with x == NULL, which are laid out
+ * (vmo_layout with *lp) after admission by layout threads that run beside the
+ * ticks.  Such a job is admitted only when its layout's footprint
+ * (vmo_layout_bytes) fits in half of the layout share beside the layouts in
+ * flight; the layout threads' cached workspace is trimmed to the other half
+ * after each layout.  A job whose layout could never fit is refused
+ * (VMO_E_UNSUPPORTED).
  * The caller keeps every buffer of a job valid and unchanged until the job is
  * done.  Submit, poll and wait may be called from any host thread.
  * ------------------------------------------------------------------------- */
@@ -475,6 +485,10 @@ typedef struct {
   int64_t submitted, completed, ticks, resident, pending;
   double busy_ms;      /* worker time spent in admission, ticks and emission */
   int64_t capacity_vertices, capacity_pins, capacity_edges;
+  int64_t max_tick_jobs;      /* most jobs whose segments one tick ran together */
+  int64_t tick_jobs;          /* sum over ticks of the jobs each ran          */
+  int64_t layout_budget_bytes;/* budget share of the layouts (see above)      */
+  int64_t layout_bytes_peak;  /* largest estimated footprint of the layouts in flight */
 } vmo_serve_stats;
 void vmo_serve_defaults(vmo_serve_params* p /* (host) */);
 vmo_status vmo_serve_create(vmo_server* out /* (host) */, const vmo_serve_params* p /* (host) */);

@@ -85,7 +85,8 @@ class ServeParams(C.Structure):
 class ServeStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("ticks", C.c_int64), ("resident", C.c_int64),
                 ("pending", C.c_int64), ("busy_ms", C.c_double), ("capacity_vertices", C.c_int64),
-                ("capacity_pins", C.c_int64), ("capacity_edges", C.c_int64)]
+                ("capacity_pins", C.c_int64), ("capacity_edges", C.c_int64), ("max_tick_jobs", C.c_int64),
+                ("tick_jobs", C.c_int64), ("layout_budget_bytes", C.c_int64), ("layout_bytes_peak", C.c_int64)]
 
 
 class CutResult(C.Structure):
@@ -192,6 +193,12 @@ class Context:
         if st != VMO_OK:
             msg = lib().vmo_last_error(self.h).decode() if ctx is not None else "vmo_create failed"
             raise VmoError(st, msg)
+
+    @staticmethod
+    def layout_bytes(k: int, l: int, npins: int) -> int:
+        """vmo_layout_bytes: bound of vmo_layout's workspace for these sizes."""
+        lib().vmo_layout_bytes.restype = C.c_size_t
+        return int(lib().vmo_layout_bytes(C.c_int32(k), C.c_int32(l), C.c_int64(npins)))
 
     def pool_bytes(self) -> int:
         return int(lib().vmo_pool_bytes(self.h))

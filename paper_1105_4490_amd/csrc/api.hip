@@ -1,5 +1,6 @@
 // C ABI of include/vmo.h: argument checks, context handling, and dispatch to
 // the device code.  No exception crosses this boundary.
+#include <algorithm>
 #include <climits>
 
 #include "order_engine.h"
@@ -401,6 +402,24 @@ void vmo_layout_defaults(vmo_layout_params* p, uint64_t seed) {
   p->jitter = 1e-3f;
   p->stall = 0.95f;
   p->pack_gap = 0.1f;
+}
+
+size_t vmo_layout_bytes(int32_t k, int32_t l, int64_t npins) {
+  if (k < 0 || l < 0 || npins < 0) return 0;
+  // What the pool holds after a layout: the tree's node arrays, requested
+  // once for the largest level (17 nodes per point: 80 B record, FP64 charges
+  // 40 B, child lists 64 B, counts 8 B), the walk's parts, requested once for
+  // the most any level needs (4 KiB per point up to 200,000 points, 256 B
+  // above), per point the descent's records (32 B) and coarsening scratch
+  // (64 B); per level the tree's point arrays (70 B), 16 B per vertex, 12 B
+  // per net and 8 B per pin (x 2.5 for all levels, which shrink about twofold
+  // each); the layout's own 16 B per net and 24 B per pin; and a quarter more
+  // for the pool's size classes.
+  const double kd = (double)k, ld = (double)l, pd = (double)npins;
+  const double parts = std::max(256.0 * kd, 4096.0 * std::min(kd, 200000.0));
+  const double per_v = 17.0 * 192.0 + 32.0 + 64.0 + 2.5 * (70.0 + 16.0);
+  const double lvl = 2.5 * (12.0 * ld + 8.0 * pd);
+  return (size_t)(1.25 * (kd * per_v + parts + lvl + 16.0 * ld + 24.0 * pd)) + ((size_t)1 << 20);
 }
 
 vmo_status vmo_layout(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p, float* x, vmo_stream stream) {

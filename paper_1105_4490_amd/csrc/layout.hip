@@ -8,6 +8,9 @@
 // net centres and attraction sum in CSR order, the walk visits nodes in
 // pre-order, tree charges sum bottom-up in FP64, so one descent step gives the
 // same bits as a sequential evaluation of the same definition.
+#include <algorithm>
+#include <type_traits>
+
 #include "vmo_internal.h"
 
 namespace vmo {
@@ -1051,47 +1054,46 @@ static void build_tree(Ctx& C, Tree& T, const float4* x, const float* w, int32_t
                        double th2, hipStream_t s, bool small_ok = true, const AttractJob* aj = nullptr) {
   T.k = k;
   T.n = -1;
-  const size_t nmax = 17 * (size_t)k + 1;  // at most 17 nodes begin at a position
+  // at most 17 nodes begin at a position.  The buffers are kept from one
+  // build to the next and only grow; during a layout they are sized for its
+  // largest level at once, so every level and iteration uses the same blocks.
+  const size_t kk = (size_t)std::max<int64_t>(k, C.layout_kmax);
+  const size_t nmax = 17 * kk + 1;
+  auto grow = [&](auto& b, size_t n) {
+    if (!b.p || b.n < n) {
+      b.release();
+      b = std::remove_reference_t<decltype(b)>(C.pool, n);
+    }
+  };
+  grow(T.order, kk);
+  grow(T.xs, 4 * kk);
+  grow(T.ws, kk);
+  grow(T.p2, 4 * kk);
+  grow(T.P, kk);
+  grow(T.nn, kk + 1);
+  grow(T.nodes, nmax);
+  grow(T.Wd, nmax);
+  grow(T.Sd, 4 * nmax);
+  grow(T.nch, nmax);
+  grow(T.cid, 16 * nmax);
   if (small_ok && k > 0 && k <= kSmallK) {
-    T.order = Buf<int32_t>(C.pool, k);
-    T.xs = Buf<float>(C.pool, 4 * (size_t)k);
-    T.ws = Buf<float>(C.pool, (size_t)k);
-    T.p2 = Buf<int32_t>(C.pool, 4 * (size_t)k);
-    T.P = Buf<float4>(C.pool, (size_t)k);
-    T.nn = Buf<int32_t>(C.pool, (size_t)k + 1);
-    T.nodes = Buf<TNode>(C.pool, nmax);
-    T.Wd = Buf<double>(C.pool, nmax);
-    T.Sd = Buf<double>(C.pool, 4 * nmax);
-    T.nch = Buf<int32_t>(C.pool, nmax);
-    T.ctr = Buf<int32_t>(C.pool, nmax);
-    T.cid = Buf<int32_t>(C.pool, 16 * nmax);
+    grow(T.ctr, nmax);
     AttractJob none{};
     const int64_t ab = aj && aj->k > 0 ? nblocks(aj->k, kSTB / 64) : 0;
     VMO_LAUNCH(k_tree_small, (unsigned)(1 + (ab < 256 ? ab : 256)), kSTB, 0, s, x, w, k, cap, dbox, far_table(th2),
                T.order.p, T.xs.p, T.ws.p, T.p2.p, T.P.p, T.view(), T.nn.p, aj ? *aj : none);
     return;
   }
-  T.key = Buf<uint64_t>(C.pool, k);
-  T.order = Buf<int32_t>(C.pool, k);
+  grow(T.key, kk);
   VMO_LAUNCH(k_tree_keys, gsz(k), kLT, 0, s, x, k, dbox, T.key.p, T.order.p);
   radix_sort<uint64_t>(C, T.key.p, T.order.p, k, 64, s);
-  T.xs = Buf<float>(C.pool, 4 * (size_t)k);
-  T.ws = Buf<float>(C.pool, (size_t)k);
-  T.p2 = Buf<int32_t>(C.pool, 4 * (size_t)k);
-  T.P = Buf<float4>(C.pool, (size_t)k);
   VMO_LAUNCH(k_tree_points, gsz(k), kLT, 0, s, x, w, k, dbox, T.order.p, T.xs.p, T.ws.p, T.p2.p, T.P.p);
   int32_t nb = k / kCplB + 1;
-  T.cpl = Buf<int8_t>(C.pool, (size_t)nb * kCplB);
+  grow(T.cpl, (kk / kCplB + 1) * kCplB);
   VMO_LAUNCH(k_cpl, nb, kCplB, 0, s, T.key.p, k, T.cpl.p);
-  T.ell = Buf<int8_t>(C.pool, k + 1);
-  T.nn = Buf<int32_t>(C.pool, (size_t)k + 1);
+  grow(T.ell, kk + 1);
   VMO_LAUNCH(k_tree_ell, gsz((int64_t)k + 1), kLT, 0, s, T.cpl.p, k, cap, T.ell.p, T.nn.p);
   scan_exclusive<int32_t>(C, T.nn.p, T.nn.p, (int64_t)k + 1, nullptr, s);
-  T.nodes = Buf<TNode>(C.pool, nmax);
-  T.Wd = Buf<double>(C.pool, nmax);
-  T.Sd = Buf<double>(C.pool, 4 * nmax);
-  T.nch = Buf<int32_t>(C.pool, nmax);
-  T.cid = Buf<int32_t>(C.pool, 16 * nmax);
   NodeView nd = T.view();
   VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.key.p, T.ell.p, T.nn.p, T.p2.p, k, far_table(th2), nd);
   // the node count stays on the device: grids sized for the usual count
@@ -1555,7 +1557,13 @@ static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, doub
   if (L.k <= 0) return;
   const int spread = L.k <= kSpreadMax ? kParts : 1;
   const size_t np = (size_t)kParts * spread * 4 * L.k;
-  if (gw.part.n < np) gw.part = Buf<float>(C.pool, np);
+  // during a layout: the most any of its levels needs, so that every level
+  // takes the same block
+  const int64_t km = C.layout_kmax;
+  const size_t np_all = km > 0 ? std::max((size_t)kParts * 4 * km, (size_t)kParts * kParts * 4 *
+                                                                        std::min<int64_t>(km, kSpreadMax))
+                               : 0;
+  if (gw.part.n < np) gw.part = Buf<float>(C.pool, std::max(np, np_all));
   unsigned long long* pc = nullptr;
   int ph = prof_begin(C, "walk", 0.0, s, nint ? nullptr : &pc);
   unsigned long long* target = nint ? nint : pc;
@@ -2162,6 +2170,11 @@ void layout(Ctx& C, const vmo_hypergraph* h, const vmo_layout_params* p, float* 
   validate_hypergraph(C, h, true, s);
   VMO_REQUIRE(x != nullptr, "x is NULL");
   int32_t k = h->k, l = h->l;
+  struct KmaxScope {
+    Ctx& c;
+    ~KmaxScope() { c.layout_kmax = 0; }
+  } kmax_scope{C};
+  C.layout_kmax = k;
   Buf<int32_t> label(C.pool, k);
   components(C, k, l, h->net_ptr, h->pins, label.p, s);
   // vertices grouped by component (ascending label, ascending id)

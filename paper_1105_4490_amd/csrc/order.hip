@@ -1435,11 +1435,31 @@ void Engine::arena_release(int32_t slot) {
 
 void Engine::tick(int t_max) {
   if (S == 0) return;
+  // the arenas are sized for the whole budget: the level runs over the hull
+  // of the position and edge ranges of the jobs that have segments, not over
+  // the arenas (positions and edges inside the hull that belong to no segment
+  // are passed over as in any level)
+  std::vector<int32_t> sj = segment_jobs();
+  std::sort(sj.begin(), sj.end());
+  sj.erase(std::unique(sj.begin(), sj.end()), sj.end());
+  int64_t p0 = Np, p1 = 0, e0 = E, e1 = 0;
+  for (int32_t j : sj) {
+    const JobDev& J = hj[j];
+    p0 = std::min(p0, J.voff);
+    p1 = std::max(p1, J.voff + (int64_t)J.k);
+    if (J.mode == VMO_GRAPH && J.nnets > 0) {
+      e0 = std::min(e0, J.eoff);
+      e1 = std::max(e1, J.eoff + (int64_t)J.nnets);
+    }
+  }
+  if (p1 <= p0) { p0 = 0; p1 = Np; }
+  p1 = std::min(Np, (p1 + 3) & ~int64_t(3));
+  if (e1 <= e0) { e0 = 0; e1 = 0; }
   SegBufs nx;
   alloc_segments(nx, 2 * S);
-  two_means(0, S, 0, Np, t_max, true);
-  separator(0, S, 0, Np, 0, E);
-  int64_t nn = partition(0, S, 0, Np, nx, 0);
+  two_means(0, S, p0, p1, t_max, true);
+  separator(0, S, p0, p1, e0, e1);
+  int64_t nn = partition(0, S, p0, p1, nx, 0);
   cur = std::move(nx);
   S = nn;
 }

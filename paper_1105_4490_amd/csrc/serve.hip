@@ -11,6 +11,7 @@
 // layout threads, each with its own context and stream, so several layouts
 // run on the device at once and beside the ticks; a laid-out job joins the
 // engine at the next tick.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -75,6 +76,7 @@ struct Ticket {
   double t_submit = 0, t_admit = 0, t_done = 0;
   int32_t slot = -1;
   int64_t voff = 0, nbase = 0, eoff = 0, noff = 0, poff = 0, npins = 0;
+  int64_t lbytes = 0;  // estimated layout footprint while the layout is in flight
   Buf<float> xbuf;
 };
 
@@ -85,7 +87,7 @@ static double now_ms() {
 }  // namespace vmo
 
 struct vmo_layout_worker {
-  vmo::Ctx ctx;  // its pool holds the coordinates of the jobs it laid out
+  vmo::Ctx ctx;  // its pool holds the workspace of the layouts it runs
   hipStream_t stream = nullptr;
   std::thread th;
 };
@@ -112,15 +114,23 @@ struct vmo_server_s {
   bool stop = false;
   std::string fatal;
   vmo_serve_stats st;
+  // layouts: their workspace is counted against lbudget (half for the
+  // layouts in flight, by their estimated footprint; half for the blocks the
+  // layout contexts keep cached between layouts)
+  int64_t lbudget = 0, lbusy = 0;
 };
 
 namespace vmo {
+
+// The budget: 40 % for the ordering arenas, 60 % for the layouts of jobs
+// that come without coordinates.
+constexpr double kArenaShare = 0.40;
 
 // Arena capacities from the budget: per vertex 4 x 4 B grid coordinates
 // twice, ids, positions, segment ids, sides and per-level scratch (~100 B);
 // per tree node 24 B; per edge 8 B; per net 8 B; per pin 4 B.
 static void arena_sizes(const vmo_serve_params& p, int64_t* V, int64_t* NTn, int64_t* En, int64_t* Ln, int64_t* Pn) {
-  double b = (double)p.budget_bytes;
+  double b = (double)p.budget_bytes * kArenaShare;
   int64_t v = (int64_t)(b * 0.40 / 100.0);
   *V = v;
   *NTn = (int64_t)(b * 0.05 / 24.0);
@@ -132,6 +142,8 @@ static void arena_sizes(const vmo_serve_params& p, int64_t* V, int64_t* NTn, int
 static bool try_admit(vmo_server_s* S, Ticket& T, int64_t npins) {
   const vmo_job& J = T.job;
   if (S->free_slots.empty()) return false;
+  const int64_t lf = T.layout ? (int64_t)vmo_layout_bytes(J.h.k, J.h.l, npins) : 0;
+  if (T.layout && S->lbusy + lf > S->lbudget / 2) return false;
   int64_t voff, nb, eo = 0, no = 0, po = 0;
   if (!S->rv.alloc(J.h.k, &voff)) return false;
   if (!S->rn.alloc(4 * (int64_t)J.P, &nb)) { S->rv.release(voff, J.h.k); return false; }
@@ -150,7 +162,18 @@ static bool try_admit(vmo_server_s* S, Ticket& T, int64_t npins) {
   T.slot = S->free_slots.back();
   S->free_slots.pop_back();
   T.voff = voff; T.nbase = nb; T.eoff = eo; T.noff = no; T.poff = po; T.npins = npins;
+  T.lbytes = lf;
+  S->lbusy += lf;
+  S->st.layout_bytes_peak = std::max(S->st.layout_bytes_peak, S->lbusy);
   return true;
+}
+
+// A job's layout is over (done or failed): its estimated footprint leaves
+// the layouts in flight.  Called with S->mu held.
+static void layout_done(vmo_server_s* S, Ticket& T) {
+  S->lbusy -= T.lbytes;
+  T.lbytes = 0;
+  S->blocked = false;
 }
 
 static void release_ranges(vmo_server_s* S, Ticket& T) {
@@ -214,12 +237,15 @@ static void layout_loop(vmo_server_s* S, vmo_layout_worker* W) {
       check_device_flag(W->ctx, W->stream);
       VMO_HIP(hipStreamSynchronize(W->stream));
       tune_flush(W->ctx);
+      trim_pool(W->ctx, W->stream);  // the cached blocks stay within this thread's share
       std::lock_guard<std::mutex> g(S->mu);
+      layout_done(S, *T);
       S->ready.push_back(id);
     } catch (Error& e) {
       (void)hipStreamSynchronize(W->stream);
       (void)hipGetLastError();
       std::lock_guard<std::mutex> g(S->mu);
+      layout_done(S, *T);
       S->lfailed.push_back({id, {e.status, e.what()}});
     }
     S->cv.notify_all();
@@ -302,6 +328,9 @@ static void serve_loop(vmo_server_s* S) {
           T->xbuf = Buf<float>(S->ctx.pool, 4 * (size_t)T->job.h.k);
           layout(S->ctx, &T->job.h, &T->lp, T->xbuf.p, S->stream);
           check_device_flag(S->ctx, S->stream);
+          trim_pool(S->ctx, S->stream);
+          std::lock_guard<std::mutex> g(S->mu);
+          layout_done(S, *T);
         }
         JobHost H = host_job(*T);
         E.arena_admit(T->slot, H, T->voff, T->nbase, T->eoff, T->noff, T->poff);
@@ -320,6 +349,15 @@ static void serve_loop(vmo_server_s* S) {
     try {
       double t0 = now_ms();
       if (E.S > 0) {
+        {
+          // jobs whose segments this tick runs together
+          std::vector<int32_t> in = E.segment_jobs();
+          std::sort(in.begin(), in.end());
+          const int64_t nj = (int64_t)(std::unique(in.begin(), in.end()) - in.begin());
+          std::lock_guard<std::mutex> g(S->mu);
+          S->st.max_tick_jobs = std::max(S->st.max_tick_jobs, nj);
+          S->st.tick_jobs += nj;
+        }
         E.tick(S->prm.t_max);
         check_device_flag(S->ctx, S->stream);
         tune_flush(S->ctx);
@@ -420,9 +458,14 @@ vmo_status vmo_serve_create(vmo_server* out, const vmo_serve_params* p) {
     S->st.capacity_vertices = V;
     S->st.capacity_pins = Pn;
     S->st.capacity_edges = En;
+    S->lbudget = (int64_t)((double)p->budget_bytes * (1.0 - vmo::kArenaShare));
+    S->st.layout_budget_bytes = S->lbudget;
+    const int nl = p->layout_threads > 0 ? p->layout_threads : 1;
+    if (p->layout_threads == 0) S->ctx.pool_cap = (size_t)(S->lbudget / 2);
     for (int32_t i = 0; i < p->layout_threads; ++i) {
       vmo_layout_worker* W = new vmo_layout_worker();
       W->ctx.device = p->device;
+      W->ctx.pool_cap = (size_t)(S->lbudget / (2 * nl));
       S->lw.push_back(W);
       VMO_HIP(hipStreamCreate(&W->stream));
     }
@@ -462,7 +505,10 @@ vmo_status vmo_serve_submit(vmo_server S, const vmo_job* job, const vmo_layout_p
       return VMO_E_INVALID;
     }
     if (np > S->rp.cap()) return VMO_E_UNSUPPORTED;
+    if (!J.x && (int64_t)vmo_layout_bytes(J.h.k, J.h.l, np) > S->lbudget / 2) return VMO_E_UNSUPPORTED;
   }
+  if (!J.x && J.mode == VMO_GRAPH && (int64_t)vmo_layout_bytes(J.h.k, J.h.l, 2 * (int64_t)J.h.l) > S->lbudget / 2)
+    return VMO_E_UNSUPPORTED;
   std::lock_guard<std::mutex> g(S->mu);
   if (S->stop) return VMO_E_DEVICE;
   uint64_t id = S->next_id++;

@@ -180,6 +180,11 @@ struct Ctx {
   bool tail_on = false;
   int* aflag = nullptr;
   size_t pool_cap = 0;  // idle pool bytes kept after a synchronising call (0: no bound)
+  // While a layout runs: the largest level's vertex count, so that the tree's
+  // node arrays and the walk's parts are requested at one size for every
+  // level (the pool then hands the same blocks to each level instead of
+  // keeping one set per level).
+  int64_t layout_kmax = 0;
   ~Ctx();
 };
 enum : int { kAsyncPermutation = 1, kAsyncPartner = 2, kAsyncCsr = 4 };

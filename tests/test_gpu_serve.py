@@ -52,6 +52,8 @@ def test_serve_mix_equals_alone_and_oracle():
         assert lat > 0
     st = srv.stats()
     assert st["completed"] == 12 and st["ticks"] > 0
+    # continuous batching: ticks ran the segments of several jobs together
+    assert st["max_tick_jobs"] > 1 and st["tick_jobs"] > st["ticks"]
     srv.close()
     # the same job alone on a fresh server
     srv = P.Server(budget_bytes=64 << 20, max_jobs=4)
@@ -65,7 +67,7 @@ def test_serve_admission_waits_for_room():
     """A budget that holds only a few jobs at a time: the rest queue and all finish right."""
     import paper_1105_4490_amd as P
     jobs = job_set(9, 5)
-    srv = P.Server(budget_bytes=4 << 20, max_jobs=3)
+    srv = P.Server(budget_bytes=10 << 20, max_jobs=3)
     tickets = [srv.submit(j) for j, _ in jobs]
     for t, (_, (h, ref, mode)) in zip(tickets, jobs):
         o, _ = srv.wait(t)
@@ -75,7 +77,7 @@ def test_serve_admission_waits_for_room():
 
 def test_serve_refuses_jobs_larger_than_the_arena():
     import paper_1105_4490_amd as P
-    srv = P.Server(budget_bytes=1 << 20, max_jobs=2)    # about 4k vertex slots
+    srv = P.Server(budget_bytes=1 << 20, max_jobs=2)    # about 1.6k vertex slots
     g = vmo_gen.grid2d(128)
     h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
     with pytest.raises(P.VmoError):
@@ -101,4 +103,54 @@ def test_serve_with_layout_at_admission(threads):
         o, _ = srv.wait(t)
         x = oracle.layout(h, oracle.layout_params(seed=seed))
         compare_order(o, oracle.order(h, x, 8, 2, job=i), oracle.NET_MODE, h.k, h.l)
+    srv.close()
+
+
+def test_layout_bytes_bounds_the_layout_workspace():
+    """The footprint the server admits layouts by (vmo_layout_bytes) bounds
+    what a layout's workspace takes: a fresh context's pool after one layout."""
+    import paper_1105_4490_amd as P
+    cases = []
+    g = vmo_gen.grid3d(20, seed=1)
+    cases.append(oracle.symmetric(g.m, g.n, g.rowptr, g.col))
+    g = vmo_gen.zipf_rect(20000, 10000, 2)
+    cases.append(oracle.colnet(g.m, g.n, g.rowptr, g.col))
+    g = vmo_gen.grid2d(32)
+    cases.append(oracle.rownet(g.m, g.n, g.rowptr, g.col))
+    g = vmo_gen.grid3d(64, seed=1)
+    cases.append(oracle.symmetric(g.m, g.n, g.rowptr, g.col))
+    for h in cases:
+        ctx = P.Context(0)
+        dh = dev_h(h)
+        ctx.layout(dh, P.layout_params(seed=1))
+        ctx.sync()
+        held = ctx.pool_bytes()
+        bound = P.Context.layout_bytes(h.k, h.l, int(h.ptr[-1]))
+        print("layout workspace k", h.k, "held", held, "bound", bound, flush=True)
+        assert 0 < held <= bound, (h.k, held, bound)
+        ctx.close()
+
+
+def test_serve_layouts_admitted_by_footprint():
+    """A layout share that holds one layout at a time: the layouts of the
+    jobs wait for one another, the peak footprint in flight stays within the
+    share, and every result equals the oracle's whole path."""
+    import paper_1105_4490_amd as P
+    jobs_h = []
+    for i, side in enumerate((20, 14, 17, 11)):
+        g = vmo_gen.grid2d(side, side + 1)
+        jobs_h.append(oracle.rownet(g.m, g.n, g.rowptr, g.col))
+    need = max(P.Context.layout_bytes(h.k, h.l, int(h.ptr[-1])) for h in jobs_h)
+    budget = int(need / 0.6 * 2 * 1.2)          # half of the 60 % layout share holds one layout
+    srv = P.Server(budget_bytes=max(budget, 2 << 20), max_jobs=8, layout_threads=4)
+    tickets = []
+    for i, h in enumerate(jobs_h):
+        t = srv.submit({"h": dev_h(h), "x": None, "P": 8, "seed": 2, "job_index": i}, lp=P.layout_params(seed=3 + i))
+        tickets.append(t)
+    for i, (t, h) in enumerate(zip(tickets, jobs_h)):
+        o, _ = srv.wait(t)
+        x = oracle.layout(h, oracle.layout_params(seed=3 + i))
+        compare_order(o, oracle.order(h, x, 8, 2, job=i), oracle.NET_MODE, h.k, h.l)
+    st = srv.stats()
+    assert 0 < st["layout_bytes_peak"] <= st["layout_budget_bytes"] // 2
     srv.close()
