@@ -32,12 +32,39 @@ struct Level {
   Buf<int32_t> pins, dpins;
   Buf<float> w, c;
   Buf<int32_t> pi;  // map to the next coarser level
+  // vertices of more than kHeavyDeg nets: [0] their count, then the vertices
+  // (in no particular order); heavy_cap bounds the count (np / (kHeavyDeg+1))
+  Buf<int32_t> heavy;
+  int64_t heavy_cap = 0;
 };
+
+// A vertex of more than kHeavyDeg nets takes a wavefront of its own in the
+// attraction and the matching: with one thread per vertex, the thread of a
+// vertex of thousands of nets would hold its wavefront (and its kernel) long
+// after the others are done.  The per-vertex results do not depend on which
+// form computes them.
+constexpr int32_t kHeavyDeg = 32;
+constexpr int64_t kHeavyBlocks = 1024;  // most blocks of kLT / 64 wavefronts given to them
+__global__ void k_heavy_list(const int64_t* dptr, int32_t k, int32_t* heavy) {
+  GRID_STRIDE(v, k) {
+    if (dptr[v + 1] - dptr[v] > kHeavyDeg) heavy[1 + atomicAdd(heavy, 1)] = (int32_t)v;
+  }
+}
+// blocks of kLT threads for the heavy vertices of L (0: none can exist)
+static int64_t heavy_blocks(const Level& L) {
+  const int64_t nw = kLT / 64;
+  return std::min(kHeavyBlocks, (L.heavy_cap + nw - 1) / nw);
+}
 
 static void make_dual(Ctx& C, Level& L, hipStream_t s) {
   L.dptr = Buf<int64_t>(C.pool, (size_t)L.k + 1);
   L.dpins = Buf<int32_t>(C.pool, L.np > 0 ? L.np : 1);
   csr_transpose(C, L.l, L.k, L.ptr.p, L.pins.p, L.dptr.p, L.dpins.p, s);
+  // the degrees sum to np, so at most np / (kHeavyDeg + 1) vertices exceed it
+  L.heavy_cap = std::min<int64_t>(L.k, L.np / (kHeavyDeg + 1));
+  L.heavy = Buf<int32_t>(C.pool, (size_t)L.heavy_cap + 1);
+  fill_i32(L.heavy.p, 0, 1, s);
+  if (L.heavy_cap > 0) VMO_LAUNCH(k_heavy_list, gsz(L.k), kLT, 0, s, L.dptr.p, L.k, L.heavy.p);
 }
 
 // ============================================================ bounding box ==
@@ -514,9 +541,12 @@ __global__ __launch_bounds__(kParts * kParts) void k_moments_top(NodeView nd) {
 }
 
 // ------------------------------------------------- attraction, by wavefront ----
-// The attraction of eq. (7) for small levels, whose coarse vertices can meet
-// hundreds of nets: one wavefront per vertex, the lanes form the terms
-// c_e (x - z_e) of 64 nets at a time, and the sum runs over them in net order.
+// The attraction of eq. (7) for vertices that meet many nets (all the
+// vertices of small levels, whose coarse vertices can meet thousands): one
+// wavefront per vertex, the lanes form the terms c_e (x - z_e) of 64 nets at a
+// time, and lanes 0..3 then sum one coordinate each over them in net order.
+// The sum is one dependent chain per coordinate, so its cost per net is one
+// add once the terms are staged (the 16-byte LDS reads run ahead of it).
 struct AttractJob {
   const int64_t* dptr;
   const int32_t* dpins;
@@ -525,16 +555,23 @@ struct AttractJob {
   const float4* x;
   const float4* z;
   float4* y;
+  const int32_t* heavy;  // NULL: every vertex; else the listed ones ([0]: count)
 };
+// staging of one wavefront: the 64 terms by coordinate, rows padded so that
+// the four summing lanes read different banks
+constexpr int kTbRow = 68;
+using AttractStage = float[4][kTbRow];
 // NW wavefronts per block; block blk of nblk (the blocks that take part).
 template <int NW>
-__device__ __forceinline__ void attract_waves(const AttractJob& aj, float4 (*tb)[64], int64_t blk, int64_t nblk) {
+__device__ __forceinline__ void attract_waves(const AttractJob& aj, AttractStage* tb, int64_t blk, int64_t nblk) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int64_t v = blk * NW + wv; v < aj.k; v += nblk * NW) {
+  const int64_t nv = aj.heavy ? aj.heavy[0] : aj.k;
+  const float* row = tb[wv][lane & 3];
+  for (int64_t i = blk * NW + wv; i < nv; i += nblk * NW) {
+    const int64_t v = aj.heavy ? aj.heavy[1 + i] : i;
     const int64_t b = aj.dptr[v], e = aj.dptr[v + 1];
     const float4 xv = aj.x[v];
-    const float x0 = xv.x, x1 = xv.y, x2 = xv.z, x3 = xv.w;
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    float acc = 0.0f;
     for (int64_t t0 = b; t0 < e; t0 += 64) {
       const int m = e - t0 < 64 ? (int)(e - t0) : 64;
       float4 term = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -542,24 +579,36 @@ __device__ __forceinline__ void attract_waves(const AttractJob& aj, float4 (*tb)
         const int32_t n = aj.dpins[t0 + lane];
         const float ce = aj.c ? aj.c[n] : 1.0f;
         const float4 zn = aj.z[n];
-        const float d0 = x0 - zn.x, d1 = x1 - zn.y, d2 = x2 - zn.z, d3 = x3 - zn.w;
+        const float d0 = xv.x - zn.x, d1 = xv.y - zn.y, d2 = xv.z - zn.z, d3 = xv.w - zn.w;
         term = make_float4(ce * d0, ce * d1, ce * d2, ce * d3);
       }
+      // the previous chunk's reads are done before its rows are overwritten
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      tb[wv][lane] = term;
+      tb[wv][0][lane] = term.x;
+      tb[wv][1][lane] = term.y;
+      tb[wv][2][lane] = term.z;
+      tb[wv][3][lane] = term.w;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int i = 0; i < m; ++i) {
-        const float4 tt = tb[wv][i];
-        a0 = a0 + tt.x;
-        a1 = a1 + tt.y;
-        a2 = a2 + tt.z;
-        a3 = a3 + tt.w;
+      if (lane < 4) {
+        if (m == 64) {
+          const float4* r4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+          for (int q = 0; q < 16; q += 4) {
+            const float4 u0 = r4[q], u1 = r4[q + 1], u2 = r4[q + 2], u3 = r4[q + 3];
+            acc = acc + u0.x; acc = acc + u0.y; acc = acc + u0.z; acc = acc + u0.w;
+            acc = acc + u1.x; acc = acc + u1.y; acc = acc + u1.z; acc = acc + u1.w;
+            acc = acc + u2.x; acc = acc + u2.y; acc = acc + u2.z; acc = acc + u2.w;
+            acc = acc + u3.x; acc = acc + u3.y; acc = acc + u3.z; acc = acc + u3.w;
+          }
+        } else {
+          for (int j = 0; j < m; ++j) acc = acc + row[j];
+        }
       }
     }
-    if (lane == 0) aj.y[v] = make_float4(a0, a1, a2, a3);
+    if (lane < 4) reinterpret_cast<float*>(aj.y + v)[lane] = acc;
   }
 }
 
@@ -587,7 +636,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
   // blocks after the first form the attraction of the same step (it does
   // not depend on the tree), on other CUs while block 0 builds the tree
   if (blockIdx.x > 0) {
-    __shared__ float4 tb[kSTB / 64][64];
+    __shared__ __align__(16) AttractStage tb[kSTB / 64];
     attract_waves<kSTB / 64>(aj, tb, blockIdx.x - 1, gridDim.x - 1);
     return;
   }
@@ -1126,12 +1175,20 @@ __global__ void k_centres(const int64_t* ptr, const int32_t* pins, int32_t l, co
 // Attraction of eq. (7): sum over the vertex's nets in ascending net order.
 // Nets are taken eight at a time: their loads are issued together (vertices of
 // coarse levels meet many nets), the sums stay in net order.
-__global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, const float* c, const float4* x,
-                          const float4* z, float4* y) {
+// Attraction with one thread per vertex; the first hb blocks give the listed
+// heavy vertices a wavefront each (attract_waves), the others skip them.
+__global__ __launch_bounds__(kLT) void k_attract(AttractJob aj, int32_t hb) {
+  if ((int32_t)blockIdx.x < hb) {
+    __shared__ __align__(16) AttractStage tb[kLT / 64];
+    attract_waves<kLT / 64>(aj, tb, blockIdx.x, hb);
+    return;
+  }
   constexpr int B = 8;
-  GRID_STRIDE(v, k) {
-    int64_t b = dptr[v], e = dptr[v + 1];
-    const float4 xv = x[v];
+  const int64_t stride = (int64_t)(gridDim.x - hb) * blockDim.x;
+  for (int64_t v = (int64_t)(blockIdx.x - hb) * blockDim.x + threadIdx.x; v < aj.k; v += stride) {
+    const int64_t b = aj.dptr[v], e = aj.dptr[v + 1];
+    if (aj.heavy && e - b > kHeavyDeg) continue;
+    const float4 xv = aj.x[v];
     const float x0 = xv.x, x1 = xv.y, x2 = xv.z, x3 = xv.w;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
     for (int64_t t0 = b; t0 < e; t0 += B) {
@@ -1139,12 +1196,12 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
       float cb[B];
       float4 zb[B];
 #pragma unroll
-      for (int u = 0; u < B; ++u) nb[u] = t0 + u < e ? dpins[t0 + u] : -1;
+      for (int u = 0; u < B; ++u) nb[u] = t0 + u < e ? aj.dpins[t0 + u] : -1;
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         if (nb[u] >= 0) {
-          cb[u] = c ? c[nb[u]] : 1.0f;
-          zb[u] = z[nb[u]];
+          cb[u] = aj.c ? aj.c[nb[u]] : 1.0f;
+          zb[u] = aj.z[nb[u]];
         }
       }
 #pragma unroll
@@ -1158,13 +1215,13 @@ __global__ void k_attract(const int64_t* dptr, const int32_t* dpins, int32_t k, 
         a3 = a3 + ce * d3;
       }
     }
-    y[v] = make_float4(a0, a1, a2, a3);
+    aj.y[v] = make_float4(a0, a1, a2, a3);
   }
 }
 // The same attraction with one wavefront per vertex (attract_waves), four
 // vertices per block.
 __global__ __launch_bounds__(256) void k_attract_wave(AttractJob aj) {
-  __shared__ float4 tb[4][64];
+  __shared__ __align__(16) AttractStage tb[4];
   attract_waves<4>(aj, tb, blockIdx.x, gridDim.x);
 }
 __global__ void k_z_soa(const float4* z, int32_t l, float* out) {
@@ -1538,8 +1595,12 @@ static void gradient_prepare(Ctx& C, const Level& L, const float4* x, double th2
   }
   if (L.k <= 16384)
     VMO_LAUNCH(k_attract_wave, nblocks(L.k, 4), 256, 0, s, aj);
-  else
-    VMO_LAUNCH(k_attract, gsz(L.k), kLT, 0, s, L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y);
+  else {
+    AttractJob ah = aj;
+    ah.heavy = L.heavy.p;
+    const int64_t hb = heavy_blocks(L);
+    VMO_LAUNCH(k_attract, (unsigned)(hb + gsz(L.k)), kLT, 0, s, ah, (int32_t)hb);
+  }
   build_tree(C, gw.T, x, L.w.p, L.k, cap, gw.box.p, th2, s);
 }
 
@@ -1624,36 +1685,82 @@ __device__ __forceinline__ bool prio_gt(const Prio& x, const Prio& y) {
 
 // Best unmatched candidate partner of every unmatched vertex: the pair of
 // highest priority (cost/(|e|-1) over a shared net of 2..mm pins, then the
-// keyed hash, then the smaller ids).
+// keyed hash, then the smaller ids).  The priorities of distinct pairs differ,
+// so the best partner is unique whatever order the candidates are met in.
 // prev: the match count of the previous round of the group (NULL for its
 // first round); after a round that matched nothing the rounds change nothing,
 // so both kernels return at once.
-__global__ void k_match_best(const int64_t* ptr, const int32_t* pins, const int64_t* dptr, const int32_t* dpins,
-                             const float* c, int32_t k, int32_t mm, const int32_t* mate, uint64_t seed, uint64_t mkey,
-                             const int32_t* prev, int32_t* best) {
+struct MatchJob {
+  const int64_t* ptr;
+  const int32_t* pins;
+  const int64_t* dptr;
+  const int32_t* dpins;
+  const float* c;
+  int32_t k, mm;
+  const int32_t* mate;
+  uint64_t seed, mkey;
+  const int32_t* heavy;  // [0]: count, then the vertices of more than kHeavyDeg nets
+};
+// candidates of u over its nets dptr[u]+t0, t0+step, ... into (bp, bv)
+__device__ __forceinline__ void match_scan(const MatchJob& mj, int32_t u, int64_t t0, int64_t step, Prio& bp,
+                                           int32_t& bv) {
+  for (int64_t t = mj.dptr[u] + t0; t < mj.dptr[u + 1]; t += step) {
+    int32_t e = mj.dpins[t];
+    int64_t b = mj.ptr[e], n = mj.ptr[e + 1] - b;
+    if (n < 2 || n > mj.mm) continue;
+    double om = (double)(mj.c ? mj.c[e] : 1.0f) / (double)(n - 1);
+    for (int64_t p = b; p < b + n; ++p) {
+      int32_t v = mj.pins[p];
+      if (v == u || mj.mate[v] >= 0) continue;
+      Prio q;
+      q.om = om;
+      q.a = u < v ? u : v;
+      q.b = u < v ? v : u;
+      q.hs = rng3(mj.seed, mj.mkey, (uint64_t)q.a, (uint64_t)q.b);
+      if (bv < 0 || prio_gt(q, bp)) { bp = q; bv = v; }
+    }
+  }
+}
+// One thread per vertex; the first hb blocks give the heavy vertices a
+// wavefront each, whose lanes take every 64th net and then keep the best of
+// the lanes' candidates.
+__global__ __launch_bounds__(kLT) void k_match_best(MatchJob mj, int32_t hb, const int32_t* prev, int32_t* best) {
   if (prev && *prev == 0) return;
-  GRID_STRIDE(u64, k) {
+  if ((int32_t)blockIdx.x < hb) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)hb * (kLT / 64), nh = mj.heavy[0];
+    for (int64_t i = (int64_t)blockIdx.x * (kLT / 64) + (threadIdx.x >> 6); i < nh; i += nw) {
+      const int32_t u = mj.heavy[1 + i];
+      if (mj.mate[u] >= 0) {
+        if (lane == 0) best[u] = -1;
+        continue;
+      }
+      Prio bp;
+      bp.om = -1.0; bp.hs = 0; bp.a = 0x7fffffff; bp.b = 0x7fffffff;
+      int32_t bv = -1;
+      match_scan(mj, u, lane, 64, bp, bv);
+      for (int off = 32; off > 0; off >>= 1) {
+        Prio q;
+        q.om = __shfl_xor(bp.om, off);
+        q.hs = __shfl_xor(bp.hs, off);
+        const int32_t v = __shfl_xor(bv, off);
+        q.a = u < v ? u : v;
+        q.b = u < v ? v : u;
+        if (v >= 0 && (bv < 0 || prio_gt(q, bp))) { bp = q; bv = v; }
+      }
+      if (lane == 0) best[u] = bv;
+    }
+    return;
+  }
+  const int64_t stride = (int64_t)(gridDim.x - hb) * blockDim.x;
+  for (int64_t u64 = (int64_t)(blockIdx.x - hb) * blockDim.x + threadIdx.x; u64 < mj.k; u64 += stride) {
     int32_t u = (int32_t)u64;
-    if (mate[u] >= 0) { best[u] = -1; continue; }
+    if (mj.dptr[u + 1] - mj.dptr[u] > kHeavyDeg) continue;
+    if (mj.mate[u] >= 0) { best[u] = -1; continue; }
     Prio bp;
     bp.om = -1.0; bp.hs = 0; bp.a = 0x7fffffff; bp.b = 0x7fffffff;
     int32_t bv = -1;
-    for (int64_t t = dptr[u]; t < dptr[u + 1]; ++t) {
-      int32_t e = dpins[t];
-      int64_t b = ptr[e], n = ptr[e + 1] - b;
-      if (n < 2 || n > mm) continue;
-      double om = (double)(c ? c[e] : 1.0f) / (double)(n - 1);
-      for (int64_t p = b; p < b + n; ++p) {
-        int32_t v = pins[p];
-        if (v == u || mate[v] >= 0) continue;
-        Prio q;
-        q.om = om;
-        q.a = u < v ? u : v;
-        q.b = u < v ? v : u;
-        q.hs = rng3(seed, mkey, (uint64_t)q.a, (uint64_t)q.b);
-        if (bv < 0 || prio_gt(q, bp)) { bp = q; bv = v; }
-      }
-    }
+    match_scan(mj, u, 0, 1, bp, bv);
     best[u] = bv;
   }
 }
@@ -1844,14 +1951,15 @@ static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t 
   constexpr int kRounds = 8;
   Buf<int32_t> mate(Cx.pool, k), best(Cx.pool, k), chg(Cx.pool, kRounds);
   fill_i32(mate.p, -1, k, s);
+  const MatchJob mj{F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, F.c.p, k, mm, mate.p, seed, mkey, F.heavy.p};
+  const int64_t hb = heavy_blocks(F);
   // every round matches at least the best remaining pair, so at most k/2 + 1
   for (int64_t round = 0;; round += kRounds) {
     VMO_REQUIRE(round <= (int64_t)k / 2 + 1, "matching did not settle");
     VMO_HIP(hipMemsetAsync(chg.p, 0, 4 * kRounds, s));
     for (int r = 0; r < kRounds; ++r) {
       const int32_t* prev = r > 0 ? chg.p + r - 1 : nullptr;
-      VMO_LAUNCH(k_match_best, gsz(k), kLT, 0, s, F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, F.c.p, k, mm, mate.p, seed,
-                 mkey, prev, best.p);
+      VMO_LAUNCH(k_match_best, (unsigned)(hb + gsz(k)), kLT, 0, s, mj, (int32_t)hb, prev, best.p);
       VMO_LAUNCH(k_match_pair, gsz(k), kLT, 0, s, best.p, k, prev, mate.p, chg.p + r);
     }
     if (read1(chg.p + kRounds - 1, s) == 0) break;

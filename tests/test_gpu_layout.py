@@ -77,6 +77,23 @@ def test_gradient(ctx, seed, k, l, theta):
         assert nint == int(cnt.sum())
 
 
+def test_gradient_heavy_vertices(ctx):
+    # k > 16384 with Zipf vertex degrees up to 2000: the attraction of the
+    # vertices of more than 32 nets is summed by a wavefront each, the rest by
+    # one thread each, both in net order
+    g = vmo_gen.zipf_rect(20000, 10000, 6, clip=2000)
+    h = oracle.colnet(g.m, g.n, g.rowptr, g.col)
+    r = vmo_gen.rng(6, 5)
+    h.w = r.uniform(0.5, 2.0, size=h.k).astype(np.float32)
+    h.c = r.uniform(0.5, 2.0, size=h.l).astype(np.float32)
+    assert np.diff(g.rowptr).max() > 500
+    x = vmo_gen.random_points(h.k, 6, clusters=6)
+    y, z = oracle.gradient(h, x, theta=0.5)
+    gy, gz, _ = ctx.gradient(dev_h(h), dev_x(x), theta=0.5)
+    assert np.array_equal(host(gz), z)
+    assert np.array_equal(host(gy), y)
+
+
 @pytest.mark.parametrize("k", [3000, 9000])
 def test_gradient_coincident_points(ctx, k):
     """Many coincident points: leaves at depth 16 hold more than leaf_cap
@@ -142,9 +159,17 @@ def test_profile_times_every_nth_walk(ctx):
     assert np.array_equal(host(gx), res[1][1])
 
 
-@pytest.mark.parametrize("case", ["random", "grid3d", "star", "weighted", "pairs", "short_nets"])
+@pytest.mark.parametrize("case", ["random", "grid3d", "star", "weighted", "pairs", "short_nets", "heavy"])
 def test_coarsen(ctx, case):
-    if case == "random":
+    if case == "heavy":
+        # column nets of Zipf rows: about 2% of the vertices lie in more than
+        # 32 nets (up to 600), past the degree where a vertex's candidates are
+        # scanned by a whole wavefront
+        g = vmo_gen.zipf_rect(3000, 6000, 3, clip=600)
+        h = oracle.colnet(g.m, g.n, g.rowptr, g.col)
+        deg = np.diff(g.rowptr)
+        assert (deg > 32).sum() > 20 and deg.max() > 200
+    elif case == "random":
         g = vmo_gen.random_hypergraph_csr(3000, 2500, 1, maxdeg=6)
         h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
     elif case == "grid3d":
