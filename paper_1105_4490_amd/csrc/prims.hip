@@ -88,11 +88,28 @@ Pool::~Pool() {
 
 // --------------------------------------------------------------- profile ----
 namespace {
-// The pinned scalar buffer of a host thread, released when the thread ends.
+// Pinned buffers of threads that have ended, handed to the next threads that
+// need one.  Held through pointers that are never deleted, so that a thread
+// ending during or after static destruction still finds them.
+std::mutex& pinned_mu() {
+  static std::mutex* m = new std::mutex;
+  return *m;
+}
+std::vector<void*>& pinned_free() {
+  static std::vector<void*>* v = new std::vector<void*>;
+  return *v;
+}
+// The pinned scalar buffer of a host thread.  When the thread ends it goes
+// back to the list above, with no HIP call: the thread-local state of the HIP
+// runtime and of a preloaded profiler tool may already be destroyed by then
+// (the order in which the libraries' thread-local objects are destroyed is
+// unspecified), and a HIP call from here would run into it.
 struct PinnedScratch {
   void* p = nullptr;
   ~PinnedScratch() {
-    if (p) (void)hipHostFree(p);
+    if (!p) return;
+    std::lock_guard<std::mutex> g(pinned_mu());
+    pinned_free().push_back(p);
   }
 };
 thread_local PinnedScratch t_pinned;
@@ -104,7 +121,16 @@ bool& thread_noalloc() { return t_noalloc; }
 
 void* pinned_scratch() {
   if (t_noalloc) return t_plain;  // plain host memory: copies into it are staged by the runtime
-  if (!t_pinned.p) VMO_HIP(hipHostMalloc(&t_pinned.p, kPinnedBytes, hipHostMallocDefault));
+  if (!t_pinned.p) {
+    {
+      std::lock_guard<std::mutex> g(pinned_mu());
+      if (!pinned_free().empty()) {
+        t_pinned.p = pinned_free().back();
+        pinned_free().pop_back();
+      }
+    }
+    if (!t_pinned.p) VMO_HIP(hipHostMalloc(&t_pinned.p, kPinnedBytes, hipHostMallocDefault));
+  }
   return t_pinned.p;
 }
 
