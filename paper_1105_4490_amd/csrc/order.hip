@@ -185,16 +185,38 @@ __global__ void k_quantize(const JobDev* jobs, int32_t nj, const float* xs, int6
 
 // --------------------------------------------------------- level kernels ----
 // Segment of every position in [p0, p1) for segments [s0, s0 + S).
+// Segment of every position in [p0, p1) (-1: none; segments sorted by
+// position), and per aligned group of four positions the one value its four
+// positions share (kPackMixed when they differ or reach outside [p0, p1)), so
+// that the Lloyd passes read one word per four positions.
+constexpr int32_t kPackMixed = -2;
 __global__ void k_segpos(const int64_t* sbeg, const int64_t* send, int64_t s0, int64_t S, int64_t p0,
-                         int64_t p1, int32_t* segpos) {
-  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1; i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t lo = s0, hi = s0 + S;
-    if (S == 0 || sbeg[lo] > i) { segpos[i] = -1; continue; }
-    while (hi - lo > 1) {
-      int64_t mid = (lo + hi) >> 1;
-      if (sbeg[mid] <= i) lo = mid; else hi = mid;
+                         int64_t p1, int32_t* segpos, int32_t* segpack) {
+  const int64_t g0 = p0 >> 2, g1 = (p1 + 3) >> 2;
+  for (int64_t g = g0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < g1;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int32_t first = 0;
+    bool uni = true;
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = 4 * g + u;
+      if (i < p0 || i >= p1) {
+        uni = false;
+        continue;
+      }
+      int32_t v = -1;
+      int64_t lo = s0, hi = s0 + S;
+      if (S > 0 && sbeg[lo] <= i) {
+        while (hi - lo > 1) {
+          int64_t mid = (lo + hi) >> 1;
+          if (sbeg[mid] <= i) lo = mid; else hi = mid;
+        }
+        v = i < send[lo] ? (int32_t)lo : -1;
+      }
+      segpos[i] = v;
+      if (u == 0) first = v;
+      else if (v != first) uni = false;
     }
-    segpos[i] = i < send[lo] ? (int32_t)lo : -1;
+    segpack[g] = uni ? first : kPackMixed;
   }
 }
 
@@ -306,7 +328,8 @@ __device__ __forceinline__ bool wave_seg_sum32(int key, int32_t (&v)[F]) {
 // prev: segments still iterating after the previous iteration (NULL: run);
 // when none is, this iteration would skip every segment, so it returns.
 template <int PPT>
-__global__ __launch_bounds__(1024) void k_assign(SegArrays sg, const int32_t* segpos, const uint32_t* q, int64_t Np,
+__global__ __launch_bounds__(1024) void k_assign(SegArrays sg, const int32_t* segpos, const int32_t* segpack,
+                                                 const uint32_t* q, int64_t Np,
                                                  int64_t p0, int64_t p1, int it, uint8_t* side,
                                                  unsigned long long* work, const int32_t* prev) {
   if (prev && *prev == 0) return;
@@ -322,7 +345,10 @@ __global__ __launch_bounds__(1024) void k_assign(SegArrays sg, const int32_t* se
   for (int h = 0; h < PPT / 4; ++h) {
     const int64_t bh = b + 4 * h;
     if (bh >= p1) break;
-    const int4 sp = *reinterpret_cast<const int4*>(segpos + bh);
+    // the four positions' segments: one word when they share it
+    const int32_t pk = segpack[bh >> 2];
+    int4 sp = make_int4(pk, pk, pk, pk);
+    if (pk == kPackMixed) sp = *reinterpret_cast<const int4*>(segpos + bh);
     const uint4 q0 = *reinterpret_cast<const uint4*>(q + bh);
     const uint4 q1 = *reinterpret_cast<const uint4*>(q + Np + bh);
     const uint4 q2 = *reinterpret_cast<const uint4*>(q + 2 * Np + bh);
@@ -901,6 +927,7 @@ void Engine::setup(const std::vector<JobHost>& jobs) {
   pos = Buf<int32_t>(c.pool, Np);
   side = Buf<uint8_t>(c.pool, Np);
   segpos = Buf<int32_t>(c.pool, Np);
+  segpack = Buf<int32_t>(c.pool, (Np >> 2) + 2);
   VMO_LAUNCH(k_gather_x, gsz(Np), kT, 0, s, dj.p, nj, dxp.p, N, Np, xs.p, id.p, pos.p);
   Buf<uint32_t> box(c.pool, 8 * (size_t)nj);
   std::vector<uint32_t> hbox(8 * (size_t)nj);
@@ -1057,7 +1084,7 @@ constexpr int kLloydCheck = 8;
 void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max, bool tuned) {
   SegArrays sg = view(cur);
   int64_t np = p1 - p0;
-  VMO_LAUNCH(k_segpos, gsz(np), kT, 0, s, cur.beg.p, cur.end.p, s0, Sn, p0, p1, segpos.p);
+  VMO_LAUNCH(k_segpos, gsz((np >> 2) + 2), kT, 0, s, cur.beg.p, cur.end.p, s0, Sn, p0, p1, segpos.p, segpack.p);
   VMO_LAUNCH(k_seed1, nblocks(Sn, kT), kT, 0, s, dj.p, sg, s0, Sn);
   Buf<U128> dd(c.pool, Np + 1);
   VMO_LAUNCH(k_d2, nblocks(np, kT), kT, 0, s, sg, segpos.p, q.p, Np, p0, p1, dd.p);
@@ -1082,10 +1109,10 @@ void Engine::two_means(int64_t s0, int64_t Sn, int64_t p0, int64_t p1, int t_max
     // once, except the launches that are timed (tuner, profile), which run
     const int32_t* prev = it > 0 ? active.p + it - 1 : nullptr;
     if (ppt == 4)
-      VMO_LAUNCH(k_assign<4>, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw,
+      VMO_LAUNCH(k_assign<4>, nblocks(packs, B), B, 0, s, sg, segpos.p, segpack.p, q.p, Np, p0, p1, it, side.p, tw,
                  timed || ph >= 0 ? nullptr : prev);
     else
-      VMO_LAUNCH(k_assign<8>, nblocks(packs, B), B, 0, s, sg, segpos.p, q.p, Np, p0, p1, it, side.p, tw,
+      VMO_LAUNCH(k_assign<8>, nblocks(packs, B), B, 0, s, sg, segpos.p, segpack.p, q.p, Np, p0, p1, it, side.p, tw,
                  timed || ph >= 0 ? nullptr : prev);
     prof_end(c, ph, s);
     if (timed) tune_end(c, s);
@@ -1323,6 +1350,7 @@ void Engine::arena_init(int64_t max_v, int64_t max_nodes, int64_t max_edges, int
   pos = Buf<int32_t>(c.pool, Np);
   side = Buf<uint8_t>(c.pool, Np);
   segpos = Buf<int32_t>(c.pool, Np);
+  segpack = Buf<int32_t>(c.pool, (Np >> 2) + 2);
   VMO_LAUNCH(k_fill_u32, gsz(4 * Np), kT, 0, s, q.p, 0u, 4 * Np);
   iota_i32(id.p, Np, s);
   iota_i32(pos.p, Np, s);

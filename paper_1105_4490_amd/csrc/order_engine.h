@@ -99,6 +99,7 @@ class Engine {
   int64_t N = 0, Np = 0, NT = 0, E = 0, L = 0, S = 0, npins_ = 0;
   Buf<uint32_t> q, q2;
   Buf<int32_t> id, id2, pos, segpos;
+  Buf<int32_t> segpack;  // per aligned group of four positions: their shared segment (k_segpos)
   Buf<uint8_t> side;
   SegBufs cur;
   Buf<int32_t> nd_state, nd_K, nd_p0;
