@@ -72,6 +72,8 @@ def main():
                     help="host threads of the oracle's all-cores leg (capped at the cores this process may use)")
     ap.add_argument("--no-batch", action="store_true", help="path mode: leave out the batched-ordering field")
     ap.add_argument("--no-serve", action="store_true", help="path mode: leave out the serving field")
+    ap.add_argument("--no-zipf", action="store_true",
+                    help="path mode: leave out the rectangular Zipf V+O field (200,000 x 100,000, column-net)")
     ap.add_argument("--mode", choices=("path", "batch", "serve", "copy"), default="path",
                     help="copy: a plain 256 MiB device copy, three times (calibrates the HBM byte counters)")
     ap.add_argument("--jobs", type=int, default=512, help="batch mode: number of matrices")
@@ -203,6 +205,12 @@ def main():
         except Exception as e:  # noqa: BLE001
             line["extras_error"] = f"{type(e).__name__}: {e}"
             print(f"bench: extra fields failed: {e}", file=sys.stderr, flush=True)
+        if not args.no_zipf:
+            try:
+                line["zipf"] = bench_zipf(ctx, lp, 3)
+            except Exception as e:  # noqa: BLE001
+                line["zipf_error"] = f"{type(e).__name__}: {e}"
+                print(f"bench: zipf field failed: {e}", file=sys.stderr, flush=True)
         if not args.no_batch:
             try:
                 line["batch"] = bench_batch(args, ctx, field=True)
@@ -260,6 +268,48 @@ def order_only_and_border(ctx, h, g, lp, o, steps):
             "schur": {"P3": SCHUR_P3, "value": g.nnz / dt_s, "unit": "nnz/s", "ms": 1e3 * dt_s,
                       "what": "Schur-complement recursion: every separator block of the ordering reordered by the "
                               "BBD ordering of its induced graph into P3 parts, all blocks in one batched pass"}}
+
+
+def bench_zipf(ctx, lp, steps):
+    """V+O of the rectangular Zipf matrix: 200,000 x 100,000, row degrees
+    min(Zipf(2), 2000), column-net, 256 parts, SBD (net mode), from
+    device-resident CSR; one untimed run, then `steps` timed runs, each split
+    into its layout and its ordering."""
+    import numpy as np
+    import torch
+    import paper_1105_4490_amd as P
+    import vmo_gen
+    g = vmo_gen.zipf_rect(200000, 100000, SEED)
+    rowptr = torch.as_tensor(g.rowptr).cuda()
+    col = torch.as_tensor(g.col).cuda()
+    parts = 256
+
+    def run():
+        h = ctx.model(P.COLUMN_NET, g.m, g.n, rowptr, col)
+        a = time.perf_counter()
+        x = ctx.layout(h, lp)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        o = ctx.order(h, x, parts, SEED, mode=P.NET, order=P.SBD)
+        c = ctx.cut(h, o["part"], parts)
+        torch.cuda.synchronize()
+        return b - a, time.perf_counter() - b, c
+
+    run()
+    lay, ordr = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a, b, c = run()
+        lay.append(a)
+        ordr.append(b)
+    dt = (time.perf_counter() - t0) / steps
+    deg = np.diff(g.rowptr)
+    return {"metric": "matrix nnz ordered/sec (V+O, recursive SBD)", "value": g.nnz / dt, "unit": "nnz/s",
+            "ms": 1e3 * dt, "layout_ms": 1e3 * statistics.median(lay), "order_cut_ms": 1e3 * statistics.median(ordr),
+            "steps": steps, "cut_net": c["cut_net"], "max_split": c["max_split"],
+            "config": {"workload": f"rectangular Zipf {g.m} x {g.n} ({g.nnz} nnz), row degrees min(Zipf(2), 2000) "
+                                   f"(largest {int(deg.max())}), column-net, {parts} parts, recursive SBD, "
+                                   "layout + order from device-resident CSR", "seed": SEED}}
 
 
 def bench_kl(ctx, h, x, o, steps, passes=4):
