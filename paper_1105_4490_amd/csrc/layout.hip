@@ -1690,6 +1690,20 @@ __device__ __forceinline__ bool prio_gt(const Prio& x, const Prio& y) {
 // prev: the match count of the previous round of the group (NULL for its
 // first round); after a round that matched nothing the rounds change nothing,
 // so both kernels return at once.
+// A vertex whose scan meets more than kMatchLight candidate pins, or that
+// lies in more than kHeavyDeg nets, is listed once per coarsening step; its
+// nets are scanned in chunks of kMatchChunk, one wavefront per chunk; a vertex
+// of several chunks keeps each chunk's best candidate, and the wavefront that
+// finishes the vertex's last chunk takes the best of them (counted by an
+// agent-scope acquire-release add, so that the chunks' records are visible to
+// it).  Every other vertex is scanned by one thread.
+constexpr int32_t kMatchChunk = 256;
+constexpr int32_t kMatchLight = 512;
+struct ChunkBest {
+  double om;
+  uint64_t hs;
+  int32_t v, pad;
+};
 struct MatchJob {
   const int64_t* ptr;
   const int32_t* pins;
@@ -1699,12 +1713,16 @@ struct MatchJob {
   int32_t k, mm;
   const int32_t* mate;
   uint64_t seed, mkey;
-  const int32_t* heavy;  // [0]: count, then the vertices of more than kHeavyDeg nets
+  const int32_t* heavy;   // [0]: count, then the listed vertices (in no particular order)
+  const uint8_t* listed;  // [k]: 1 for the listed vertices
+  const int32_t* cstart;  // [k + 1]: first chunk of each listed vertex (exclusive scan)
+  ChunkBest* cres;        // per chunk: its best candidate
+  int32_t* hdone;         // per listed vertex: chunks finished in this launch (left at zero)
 };
-// candidates of u over its nets dptr[u]+t0, t0+step, ... into (bp, bv)
-__device__ __forceinline__ void match_scan(const MatchJob& mj, int32_t u, int64_t t0, int64_t step, Prio& bp,
-                                           int32_t& bv) {
-  for (int64_t t = mj.dptr[u] + t0; t < mj.dptr[u + 1]; t += step) {
+// candidates of u over its nets tb, tb + step, ... below te into (bp, bv)
+__device__ __forceinline__ void match_scan(const MatchJob& mj, int32_t u, int64_t tb, int64_t te, int64_t step,
+                                           Prio& bp, int32_t& bv) {
+  for (int64_t t = tb; t < te; t += step) {
     int32_t e = mj.dpins[t];
     int64_t b = mj.ptr[e], n = mj.ptr[e + 1] - b;
     if (n < 2 || n > mj.mm) continue;
@@ -1721,47 +1739,115 @@ __device__ __forceinline__ void match_scan(const MatchJob& mj, int32_t u, int64_
     }
   }
 }
-// One thread per vertex; the first hb blocks give the heavy vertices a
-// wavefront each, whose lanes take every 64th net and then keep the best of
-// the lanes' candidates.
+// (bp, bv) <- the better of (bp, bv) and candidate (om, hs, v) of u
+__device__ __forceinline__ void match_keep(int32_t u, double om, uint64_t hs, int32_t v, Prio& bp, int32_t& bv) {
+  Prio q;
+  q.om = om;
+  q.hs = hs;
+  q.a = u < v ? u : v;
+  q.b = u < v ? v : u;
+  if (v >= 0 && (bv < 0 || prio_gt(q, bp))) { bp = q; bv = v; }
+}
+// One thread per vertex; the first hb blocks give the chunks of the heavy
+// vertices a wavefront each, whose lanes take every 64th net of the chunk and
+// then keep the best of the lanes' candidates.
 __global__ __launch_bounds__(kLT) void k_match_best(MatchJob mj, int32_t hb, const int32_t* prev, int32_t* best) {
   if (prev && *prev == 0) return;
   if ((int32_t)blockIdx.x < hb) {
     const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)hb * (kLT / 64), nh = mj.heavy[0];
-    for (int64_t i = (int64_t)blockIdx.x * (kLT / 64) + (threadIdx.x >> 6); i < nh; i += nw) {
-      const int32_t u = mj.heavy[1 + i];
+    const int64_t nw = (int64_t)hb * (kLT / 64);
+    const int32_t nh = mj.heavy[0], nc = mj.cstart[nh];
+    for (int64_t c = (int64_t)blockIdx.x * (kLT / 64) + (threadIdx.x >> 6); c < nc; c += nw) {
+      // the listed vertex of chunk c: the last i with cstart[i] <= c
+      int32_t lo = 0, hi = nh;
+      while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (mj.cstart[mid] <= c) lo = mid; else hi = mid;
+      }
+      const int32_t i = lo, u = mj.heavy[1 + i];
+      const int32_t c0 = mj.cstart[i], nch = mj.cstart[i + 1] - c0;
       if (mj.mate[u] >= 0) {
-        if (lane == 0) best[u] = -1;
+        if (lane == 0 && c == c0) best[u] = -1;
         continue;
       }
+      const int64_t tb = mj.dptr[u] + (int64_t)(c - c0) * kMatchChunk;
+      const int64_t te = min(mj.dptr[u + 1], tb + kMatchChunk);
       Prio bp;
       bp.om = -1.0; bp.hs = 0; bp.a = 0x7fffffff; bp.b = 0x7fffffff;
       int32_t bv = -1;
-      match_scan(mj, u, lane, 64, bp, bv);
+      match_scan(mj, u, tb + lane, te, 64, bp, bv);
       for (int off = 32; off > 0; off >>= 1) {
-        Prio q;
-        q.om = __shfl_xor(bp.om, off);
-        q.hs = __shfl_xor(bp.hs, off);
+        const double om = __shfl_xor(bp.om, off);
+        const uint64_t hs = __shfl_xor(bp.hs, off);
         const int32_t v = __shfl_xor(bv, off);
-        q.a = u < v ? u : v;
-        q.b = u < v ? v : u;
-        if (v >= 0 && (bv < 0 || prio_gt(q, bp))) { bp = q; bv = v; }
+        match_keep(u, om, hs, v, bp, bv);
       }
-      if (lane == 0) best[u] = bv;
+      if (lane != 0) continue;
+      if (nch == 1) {
+        best[u] = bv;
+        continue;
+      }
+      ChunkBest r;
+      r.om = bp.om; r.hs = bp.hs; r.v = bv; r.pad = 0;
+      mj.cres[c] = r;
+      const int32_t done =
+          __hip_atomic_fetch_add(&mj.hdone[i], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (done != nch - 1) continue;
+      // the last chunk of u: every chunk's record is visible here
+      Prio b2;
+      b2.om = -1.0; b2.hs = 0; b2.a = 0x7fffffff; b2.b = 0x7fffffff;
+      int32_t v2 = -1;
+      for (int32_t q = 0; q < nch; ++q) {
+        const ChunkBest cb = mj.cres[c0 + q];
+        match_keep(u, cb.om, cb.hs, cb.v, b2, v2);
+      }
+      best[u] = v2;
+      mj.hdone[i] = 0;  // every chunk of u has counted: zero again for the next launch
     }
     return;
   }
   const int64_t stride = (int64_t)(gridDim.x - hb) * blockDim.x;
   for (int64_t u64 = (int64_t)(blockIdx.x - hb) * blockDim.x + threadIdx.x; u64 < mj.k; u64 += stride) {
     int32_t u = (int32_t)u64;
-    if (mj.dptr[u + 1] - mj.dptr[u] > kHeavyDeg) continue;
+    if (mj.listed[u]) continue;
     if (mj.mate[u] >= 0) { best[u] = -1; continue; }
     Prio bp;
     bp.om = -1.0; bp.hs = 0; bp.a = 0x7fffffff; bp.b = 0x7fffffff;
     int32_t bv = -1;
-    match_scan(mj, u, 0, 1, bp, bv);
+    match_scan(mj, u, mj.dptr[u], mj.dptr[u + 1], 1, bp, bv);
     best[u] = bv;
+  }
+}
+// The vertices the matching scans by chunks: more than kHeavyDeg nets, or
+// more than kMatchLight pins over their nets of 2..mm pins.
+__global__ void k_match_list(const int64_t* ptr, const int64_t* dptr, const int32_t* dpins, int32_t k, int32_t mm,
+                             int32_t* list, uint8_t* listed) {
+  GRID_STRIDE(u, k) {
+    const int64_t b = dptr[u], e = dptr[u + 1];
+    bool heavy = e - b > kHeavyDeg;
+    if (!heavy) {
+      int64_t w = 0;
+      for (int64_t t = b; t < e; ++t) {
+        const int32_t n = dpins[t];
+        const int64_t m = ptr[n + 1] - ptr[n];
+        if (m >= 2 && m <= mm) w += m;
+      }
+      heavy = w > kMatchLight;
+    }
+    listed[u] = heavy ? 1 : 0;
+    if (heavy) list[1 + atomicAdd(list, 1)] = (int32_t)u;
+  }
+}
+// chunks of each listed vertex (the entries past the list's count get none)
+__global__ void k_match_chunks(const int32_t* heavy, const int64_t* dptr, int64_t cap, int32_t* cnt) {
+  const int32_t nh = heavy[0];
+  GRID_STRIDE(i, cap) {
+    int32_t n = 0;
+    if (i < nh) {
+      const int32_t u = heavy[1 + i];
+      n = (int32_t)((dptr[u + 1] - dptr[u] + kMatchChunk - 1) / kMatchChunk);
+    }
+    cnt[i] = n;
   }
 }
 __global__ void k_match_pair(const int32_t* best, int32_t k, const int32_t* prev, int32_t* mate, int32_t* changed) {
@@ -1951,8 +2037,20 @@ static void coarsen_level(Ctx& Cx, Level& F, Level& Cl, uint64_t seed, uint64_t 
   constexpr int kRounds = 8;
   Buf<int32_t> mate(Cx.pool, k), best(Cx.pool, k), chg(Cx.pool, kRounds);
   fill_i32(mate.p, -1, k, s);
-  const MatchJob mj{F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, F.c.p, k, mm, mate.p, seed, mkey, F.heavy.p};
-  const int64_t hb = heavy_blocks(F);
+  // the vertices scanned by chunks, and their chunks: at most one per
+  // kMatchChunk pins of the dual plus one per listed vertex
+  Buf<int32_t> mlist(Cx.pool, (size_t)k + 1), cstart(Cx.pool, (size_t)k + 1), hdone(Cx.pool, (size_t)k);
+  Buf<uint8_t> listed(Cx.pool, (size_t)k);
+  const int64_t ccap = (int64_t)k + np / kMatchChunk + 1;
+  Buf<ChunkBest> cres(Cx.pool, (size_t)ccap);
+  fill_i32(mlist.p, 0, 1, s);
+  VMO_LAUNCH(k_match_list, gsz(k), kLT, 0, s, F.ptr.p, F.dptr.p, F.dpins.p, k, mm, mlist.p, listed.p);
+  VMO_LAUNCH(k_match_chunks, gsz(k), kLT, 0, s, mlist.p, F.dptr.p, (int64_t)k, cstart.p);
+  scan_exclusive<int32_t>(Cx, cstart.p, cstart.p, k, cstart.p + k, s);
+  fill_i32(hdone.p, 0, k, s);
+  const MatchJob mj{F.ptr.p, F.pins.p, F.dptr.p, F.dpins.p, F.c.p, k, mm, mate.p, seed, mkey, mlist.p,
+                    listed.p, cstart.p, cres.p, hdone.p};
+  const int64_t hb = std::min<int64_t>(kHeavyBlocks, (ccap + kLT / 64 - 1) / (kLT / 64));
   // every round matches at least the best remaining pair, so at most k/2 + 1
   for (int64_t round = 0;; round += kRounds) {
     VMO_REQUIRE(round <= (int64_t)k / 2 + 1, "matching did not settle");

@@ -159,9 +159,21 @@ def test_profile_times_every_nth_walk(ctx):
     assert np.array_equal(host(gx), res[1][1])
 
 
-@pytest.mark.parametrize("case", ["random", "grid3d", "star", "weighted", "pairs", "short_nets", "heavy"])
+@pytest.mark.parametrize("case", ["random", "grid3d", "star", "weighted", "pairs", "short_nets", "heavy", "hubs"])
 def test_coarsen(ctx, case):
-    if case == "heavy":
+    if case == "hubs":
+        # three hubs in 5,000, 4,097 and 2,049 nets of 2-4 pins (chunks of
+        # 2,048 nets: 3, 3 and 2 of them), with costs that tie and differ
+        r = vmo_gen.rng(9, 2)
+        nets = []
+        for hub, deg in ((0, 5000), (1, 4097), (2, 2049)):
+            for i in range(deg):
+                m = int(r.integers(1, 4))
+                nets.append([hub] + sorted(int(v) for v in r.choice(np.arange(3, 6000), size=m, replace=False)))
+        nets += [sorted(int(v) for v in r.choice(np.arange(3, 6000), size=3, replace=False)) for _ in range(3000)]
+        h = oracle.hypergraph(6000, nets)
+        h.c = r.integers(1, 3, size=h.l).astype(np.float32)
+    elif case == "heavy":
         # column nets of Zipf rows: about 2% of the vertices lie in more than
         # 32 nets (up to 600), past the degree where a vertex's candidates are
         # scanned by a whole wavefront
