@@ -782,41 +782,78 @@ __device__ __forceinline__ int32_t heap_lca(int32_t a, int32_t b) {
 }
 
 // Net mode: a net belongs to the lowest common ancestor of its pins' leaves.
+// kNetG lanes per net: each takes every kNetG-th pin (consecutive lanes read
+// consecutive pins), and the group combines its lanes' ancestors (the lowest
+// common ancestor of a set does not depend on the order it is formed in).
+constexpr int kNetG = 16;
 __global__ void k_net_node(const JobDev* jobs, int32_t nj, const int64_t* nptr, const int32_t* npins, int64_t Lv,
                            const int32_t* leafh, const int32_t* rank_of, const OutPtrs* outs, const int64_t* keybase,
-                           uint32_t* key, int32_t* val, int32_t* node_of_net) {
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < Lv; u += (int64_t)gridDim.x * blockDim.x) {
-    int32_t j = find_v(jobs, nj, u, 2);
+                           uint32_t* key, int32_t* val) {
+  const int gl = threadIdx.x & (kNetG - 1);
+  const int64_t ng = (int64_t)gridDim.x * blockDim.x / kNetG;
+  for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kNetG; u < Lv; u += ng) {
+    const int32_t j = find_v(jobs, nj, u, 2);
     const JobDev& J = jobs[j];
-    int64_t g = J.noff + (u - J.ve0);
-    int64_t b = nptr[g], e = nptr[g + 1];
-    int32_t rk;
-    int32_t node = 0;
-    if (b == e) rk = outs[j].n_nodes[0];
-    else {
-      node = leafh[npins[b]];
-      for (int64_t p = b + 1; p < e; ++p) node = heap_lca(node, leafh[npins[p]]);
-      rk = rank_of[J.node_base + node];
+    const int64_t g = J.noff + (u - J.ve0);
+    const int64_t b = nptr[g], e = nptr[g + 1];
+    int32_t node = 0;  // none yet (heap ids start at 1)
+    for (int64_t p = b + gl; p < e; p += kNetG) {
+      const int32_t h = leafh[npins[p]];
+      node = node ? heap_lca(node, h) : h;
     }
-    node_of_net[u] = node;
+    for (int off = kNetG / 2; off > 0; off >>= 1) {
+      const int32_t o = __shfl_xor(node, off, kNetG);
+      if (o) node = node ? heap_lca(node, o) : o;
+    }
+    if (gl != 0) continue;
+    const int32_t rk = b == e ? outs[j].n_nodes[0] : rank_of[J.node_base + node];
     key[u] = (uint32_t)(keybase[j] + rk);
     val[u] = (int32_t)(u - J.ve0);
   }
 }
 
-__global__ void k_net_cut(const JobDev* jobs, int32_t nj, int64_t Lv, const int32_t* node_of_net, NodeArrays nd,
-                          const int32_t* rank_of, float* const* costs, const OutPtrs* outs, const uint32_t* key,
-                          int64_t* keycount) {
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < Lv; u += (int64_t)gridDim.x * blockDim.x) {
-    int32_t j = find_v(jobs, nj, u, 2);
-    atomicAdd((unsigned long long*)&keycount[key[u]], 1ull);
-    int32_t node = node_of_net[u];
-    if (node == 0) continue;
-    const JobDev& J = jobs[j];
-    if (nd.state[J.node_base + node] != kNodeInternal) continue;
+// Nets per key (counting sort of the nets by node): a wavefront adds each
+// run of equal keys among its lanes with one atomic (the nets of a node are
+// mostly consecutive).
+__global__ void k_net_count(const uint32_t* key, int64_t Lv, int64_t* keycount) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < Lv; base += stride) {
+    const int64_t u = base + lane;
+    const int nvalid = Lv - base < 64 ? (int)(Lv - base) : 64;
+    const uint32_t k = u < Lv ? key[u] : 0xffffffffu;
+    const uint32_t pk = __shfl_up(k, 1);
+    const bool head = lane < nvalid && (lane == 0 || pk != k);
+    const uint64_t heads = __ballot(head);
+    if (head) {
+      const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
+      const int next = after ? lane + __ffsll((unsigned long long)after) : nvalid;
+      atomicAdd((unsigned long long*)&keycount[k], (unsigned long long)(next - lane));
+    }
+  }
+}
+
+// Cut of every split (Table 4) in net mode: the costs of the nets of an
+// internal node, summed in FP64 one by one in ascending net id (the nets are
+// sorted by node, stably: their order within a node is the input order).
+__global__ void k_net_split(const JobDev* jobs, int32_t nj, const int64_t* keybase, int64_t kt, const int64_t* kc,
+                            const int32_t* val, NodeArrays nd, float* const* costs, const OutPtrs* outs) {
+  for (int64_t kk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; kk < kt; kk += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nj;  // the last job whose keys begin at or before kk
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (keybase[mid] <= kk) lo = mid; else hi = mid;
+    }
+    const int32_t j = lo;
+    const OutPtrs& O = outs[j];
+    const int64_t r = kk - keybase[j];
+    if (!O.node_nptr || r >= O.n_nodes[0]) continue;  // not a net-mode node: no nets
+    const int32_t h = O.node_heap[r];
+    if (nd.state[jobs[j].node_base + h] != kNodeInternal) continue;
     const float* c = costs[j];
-    double cv = c ? (double)c[u - J.ve0] : 1.0;
-    atomicAdd(&outs[j].split_cut[rank_of[J.node_base + node]], cv);
+    double sum = 0.0;
+    for (int64_t q = kc[kk]; q < kc[kk + 1]; ++q) sum += c ? (double)c[val[q]] : 1.0;
+    O.split_cut[r] = sum;
   }
 }
 
@@ -1283,14 +1320,15 @@ void Engine::emit(const std::vector<int32_t>& slots, const std::vector<JobHost>&
   VMO_LAUNCH(k_emit, m, kEmitT, 0, s, dsub.p, m, nd, douts.p, rank_of.p, esz.p, eoff.p);
   if (Lv > 0) {
     Buf<uint32_t> key(c.pool, Lv);
-    Buf<int32_t> val(c.pool, Lv), nnode(c.pool, Lv);
-    VMO_LAUNCH(k_net_node, gsz(Lv), kT, 0, s, dsub.p, m, nptr.p, npins_buf.p, Lv, leafh.p, rank_of.p, douts.p,
-               keybase.p, key.p, val.p, nnode.p);
+    Buf<int32_t> val(c.pool, Lv);
+    VMO_LAUNCH(k_net_node, gsz(Lv * kNetG), kT, 0, s, dsub.p, m, nptr.p, npins_buf.p, Lv, leafh.p, rank_of.p,
+               douts.p, keybase.p, key.p, val.p);
     Buf<int64_t> kc(c.pool, kt + 1);
     fill_i64(kc.p, 0, kt + 1, s);
-    VMO_LAUNCH(k_net_cut, gsz(Lv), kT, 0, s, dsub.p, m, Lv, nnode.p, nd, rank_of.p, dcost.p, douts.p, key.p, kc.p);
+    VMO_LAUNCH(k_net_count, gsz(Lv), kT, 0, s, key.p, Lv, kc.p);
     scan_exclusive<int64_t>(c, kc.p, kc.p, kt, kc.p + kt, s);
     radix_sort<uint32_t>(c, key.p, val.p, Lv, bits_for((uint64_t)kt), s);
+    VMO_LAUNCH(k_net_split, gsz(kt), kT, 0, s, dsub.p, m, keybase.p, kt, kc.p, val.p, nd, dcost.p, douts.p);
     VMO_LAUNCH(k_net_out, gsz(Lv), kT, 0, s, dsub.p, m, Lv, val.p, douts.p);
     VMO_LAUNCH(k_net_ptr, m, kT, 0, s, dsub.p, m, kc.p, keybase.p, douts.p);
   }

@@ -173,7 +173,7 @@ def test_order_graph_mode(ctx, N, P, ordr):
     assert c["separators"] and c["max_split"] == ref.split_cut[:ref.n_nodes].max()
 
 
-@pytest.mark.parametrize("case", ["grid", "zipf", "tiny"])
+@pytest.mark.parametrize("case", ["grid", "zipf", "tiny", "costs"])
 @pytest.mark.parametrize("ordr", [0, 1])
 def test_order_net_mode(ctx, case, ordr):
     if case == "grid":
@@ -181,11 +181,16 @@ def test_order_net_mode(ctx, case, ordr):
         h = oracle.rownet(g.m, g.n, g.rowptr, g.col)
         x = oracle.layout(h, oracle.layout_params(seed=3))
         P = 16
-    elif case == "zipf":
+    elif case in ("zipf", "costs"):
         g = vmo_gen.zipf_rect(20000, 10000, 3)
         h = oracle.colnet(g.m, g.n, g.rowptr, g.col)
         x = vmo_gen.random_points(h.k, 3, clusters=20)
         P = 256
+        if case == "costs":
+            # non-integer costs over seven orders of magnitude: the split cuts
+            # are FP64 sums whose value depends on their order
+            r = vmo_gen.rng(3, 9)
+            h.c = (r.uniform(0.1, 1.0, h.l) * 10.0 ** r.integers(-3, 4, h.l)).astype(np.float32)
     else:
         h = oracle.hypergraph(7, [[0, 1], [], [2, 3, 4], [5, 6], [0, 6], []])
         x = vmo_gen.random_points(7, 4)
