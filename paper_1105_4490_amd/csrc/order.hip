@@ -786,19 +786,20 @@ __device__ __forceinline__ int32_t heap_lca(int32_t a, int32_t b) {
 // consecutive pins), and the group combines its lanes' ancestors (the lowest
 // common ancestor of a set does not depend on the order it is formed in).
 constexpr int kNetG = 16;
-__global__ void k_net_node(const JobDev* jobs, int32_t nj, const int64_t* nptr, const int32_t* npins, int64_t Lv,
-                           const int32_t* leafh, const int32_t* rank_of, const OutPtrs* outs, const int64_t* keybase,
-                           uint32_t* key, int32_t* val) {
+__global__ void k_net_node(const JobDev* jobs, int32_t nj, int64_t Lv, const int32_t* leafh, const int32_t* rank_of,
+                           const OutPtrs* outs, const int64_t* keybase, uint32_t* key, int32_t* val) {
   const int gl = threadIdx.x & (kNetG - 1);
   const int64_t ng = (int64_t)gridDim.x * blockDim.x / kNetG;
   for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kNetG; u < Lv; u += ng) {
     const int32_t j = find_v(jobs, nj, u, 2);
     const JobDev& J = jobs[j];
-    const int64_t g = J.noff + (u - J.ve0);
-    const int64_t b = nptr[g], e = nptr[g + 1];
+    const int64_t ul = u - J.ve0;
+    const int64_t b = J.nets_ptr[ul], e = J.nets_ptr[ul + 1];
+    const int32_t* pins = J.nets_pins;
+    const int32_t va = J.pin_vadd;
     int32_t node = 0;  // none yet (heap ids start at 1)
     for (int64_t p = b + gl; p < e; p += kNetG) {
-      const int32_t h = leafh[npins[p]];
+      const int32_t h = leafh[pins[p] + va];
       node = node ? heap_lca(node, h) : h;
     }
     for (int off = kNetG / 2; off > 0; off >>= 1) {
@@ -847,7 +848,7 @@ __global__ void k_net_split(const JobDev* jobs, int32_t nj, const int64_t* keyba
     const int32_t j = lo;
     const OutPtrs& O = outs[j];
     const int64_t r = kk - keybase[j];
-    if (!O.node_nptr || r >= O.n_nodes[0]) continue;  // not a net-mode node: no nets
+    if (jobs[j].mode != VMO_NET || r >= O.n_nodes[0]) continue;  // the bucket of empty nets
     const int32_t h = O.node_heap[r];
     if (nd.state[jobs[j].node_base + h] != kNodeInternal) continue;
     const float* c = costs[j];
@@ -1060,33 +1061,28 @@ __global__ void k_mu_global(const int32_t* mu, int32_t k, int64_t voff, int32_t*
 
 void Engine::set_edges(const std::vector<JobHost>& jobs, const std::vector<int64_t>& jpins) {
   // graph-mode edges, global vertex ids; net-mode nets, global pins
+  // (net-mode nets stay in the caller's arrays: the emission reads them
+  // through the job table)
   edges = Buf<int32_t>(c.pool, 2 * (E > 0 ? E : 1));
-  nptr = Buf<int64_t>(c.pool, L + 1);
   int64_t npins = 0;
   for (int32_t j = 0; j < nj; ++j)
     if (jobs[j].mode == VMO_NET) npins += jpins[j];
   npins_ = npins;
-  npins_buf = Buf<int32_t>(c.pool, npins > 0 ? npins : 1);
   jnoff = Buf<int64_t>(c.pool, nj);
   std::vector<int64_t> hnoff(nj);
-  std::vector<OffCopy> c32, c64, cpin;
-  int64_t pinoff = 0;
+  std::vector<OffCopy> c32;
   for (int32_t j = 0; j < nj; ++j) {
     const JobHost& H = jobs[j];
     hnoff[j] = hj[j].noff;
     if (H.mode == VMO_GRAPH) {
       if (H.h.l > 0) c32.push_back(OffCopy{H.h.pins, 2 * hj[j].eoff, 2 * (int64_t)H.h.l, hj[j].voff});
     } else {
-      // l + 1 pointer entries; the last one equals the next job's first
-      c64.push_back(OffCopy{H.h.net_ptr, hj[j].noff, (int64_t)H.h.l + 1, pinoff});
-      const int64_t np = jpins[j];
-      if (np > 0) cpin.push_back(OffCopy{H.h.pins, pinoff, np, hj[j].voff});
-      pinoff += np;
+      hj[j].nets_ptr = H.h.net_ptr;
+      hj[j].nets_pins = H.h.pins;
+      hj[j].pin_vadd = (int32_t)hj[j].voff;
     }
   }
   offset_copy_all<int32_t>(c, c32, edges.p, s);
-  offset_copy_all<int64_t>(c, c64, nptr.p, s);
-  offset_copy_all<int32_t>(c, cpin, npins_buf.p, s);
   VMO_HIP(hipMemcpyAsync(jnoff.p, hnoff.data(), 8 * nj, hipMemcpyHostToDevice, s));
   // strengthened diagonals, in global vertex ids
   has_mu = false;
@@ -1321,8 +1317,8 @@ void Engine::emit(const std::vector<int32_t>& slots, const std::vector<JobHost>&
   if (Lv > 0) {
     Buf<uint32_t> key(c.pool, Lv);
     Buf<int32_t> val(c.pool, Lv);
-    VMO_LAUNCH(k_net_node, gsz(Lv * kNetG), kT, 0, s, dsub.p, m, nptr.p, npins_buf.p, Lv, leafh.p, rank_of.p,
-               douts.p, keybase.p, key.p, val.p);
+    VMO_LAUNCH(k_net_node, gsz(Lv * kNetG), kT, 0, s, dsub.p, m, Lv, leafh.p, rank_of.p, douts.p, keybase.p,
+               key.p, val.p);
     Buf<int64_t> kc(c.pool, kt + 1);
     fill_i64(kc.p, 0, kt + 1, s);
     VMO_LAUNCH(k_net_count, gsz(Lv), kT, 0, s, key.p, Lv, kc.p);
@@ -1486,6 +1482,13 @@ void Engine::arena_admit(int32_t slot, const JobHost& H, int64_t voff, int64_t n
     launch_offset_copy_ptr(H.h.net_ptr, nptr.p + noff, (int64_t)H.h.l + 1, pinoff);
     int64_t np = read1(H.h.net_ptr + H.h.l, s);
     if (np > 0) launch_offset_copy_i32(H.h.pins, npins_buf.p + pinoff, np, (int32_t)voff);
+  }
+  if (H.mode == VMO_NET) {
+    // the emission reads the arena copies (global vertex ids already)
+    hj[slot].nets_ptr = nptr.p + noff;
+    hj[slot].nets_pins = npins_buf.p;
+    hj[slot].pin_vadd = 0;
+    VMO_HIP(hipMemcpyAsync(dj.p + slot, &hj[slot], sizeof(JobDev), hipMemcpyHostToDevice, s));
   }
   VMO_HIP(hipStreamSynchronize(s));
   if (D.k >= 2 && D.P > 1) append_root(slot);

@@ -20,11 +20,15 @@ struct JobDev {
   int64_t eoff;        // first edge (graph mode)
   int64_t noff;        // first net (net mode)
   int32_t nnets;
-  int32_t pad;
+  int32_t pin_vadd;    // net mode: added to nets_pins[] to give global vertex ids
   // bases of this job in the index spaces of one emission call (vertices,
   // tree nodes, nets): a subset of jobs is emitted over the concatenation of
   // their ranges
   int64_t vk0, vn0, ve0;
+  // net mode: the job's nets (pins of net u at nets_pins[nets_ptr[u] ..
+  // nets_ptr[u + 1]]): the caller's arrays in a call, the arena in serving
+  const int64_t* nets_ptr;
+  const int32_t* nets_pins;
 };
 
 struct JobHost {
