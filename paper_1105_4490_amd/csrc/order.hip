@@ -784,16 +784,28 @@ __device__ __forceinline__ int32_t heap_lca(int32_t a, int32_t b) {
 // Net mode: a net belongs to the lowest common ancestor of its pins' leaves.
 // kNetG lanes per net: each takes every kNetG-th pin (consecutive lanes read
 // consecutive pins), and the group combines its lanes' ancestors (the lowest
-// common ancestor of a set does not depend on the order it is formed in).
-constexpr int kNetG = 16;
+// common ancestor of a set does not depend on the order it is formed in).  A
+// wavefront takes kNetRun consecutive runs of 64 / kNetG consecutive nets, so
+// its nets mostly belong to one job, whose range it keeps.
+constexpr int kNetG = 16, kNetRun = 16;
 __global__ void k_net_node(const JobDev* jobs, int32_t nj, int64_t Lv, const int32_t* leafh, const int32_t* rank_of,
                            const OutPtrs* outs, const int64_t* keybase, uint32_t* key, int32_t* val) {
+  constexpr int kPerWave = 64 / kNetG;
   const int gl = threadIdx.x & (kNetG - 1);
-  const int64_t ng = (int64_t)gridDim.x * blockDim.x / kNetG;
-  for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kNetG; u < Lv; u += ng) {
-    const int32_t j = find_v(jobs, nj, u, 2);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t u0 = wave * kPerWave * kNetRun + ((threadIdx.x & 63) / kNetG);
+  int32_t j = -1;
+  int64_t jlo = 0, jhi = 0;  // nets of job j: [jlo, jhi)
+  for (int r = 0; r < kNetRun; ++r) {
+    const int64_t u = u0 + (int64_t)r * kPerWave;
+    if (u >= Lv) break;
+    if (u < jlo || u >= jhi) {
+      j = find_v(jobs, nj, u, 2);
+      jlo = jobs[j].ve0;
+      jhi = j + 1 < nj ? jobs[j + 1].ve0 : Lv;
+    }
     const JobDev& J = jobs[j];
-    const int64_t ul = u - J.ve0;
+    const int64_t ul = u - jlo;
     const int64_t b = J.nets_ptr[ul], e = J.nets_ptr[ul + 1];
     const int32_t* pins = J.nets_pins;
     const int32_t va = J.pin_vadd;
@@ -809,7 +821,7 @@ __global__ void k_net_node(const JobDev* jobs, int32_t nj, int64_t Lv, const int
     if (gl != 0) continue;
     const int32_t rk = b == e ? outs[j].n_nodes[0] : rank_of[J.node_base + node];
     key[u] = (uint32_t)(keybase[j] + rk);
-    val[u] = (int32_t)(u - J.ve0);
+    val[u] = (int32_t)ul;
   }
 }
 
@@ -852,8 +864,21 @@ __global__ void k_net_split(const JobDev* jobs, int32_t nj, const int64_t* keyba
     const int32_t h = O.node_heap[r];
     if (nd.state[jobs[j].node_base + h] != kNodeInternal) continue;
     const float* c = costs[j];
+    const int64_t q0 = kc[kk], q1 = kc[kk + 1];
     double sum = 0.0;
-    for (int64_t q = kc[kk]; q < kc[kk + 1]; ++q) sum += c ? (double)c[val[q]] : 1.0;
+    if (!c) {
+      for (int64_t q = q0; q < q1; ++q) sum += 1.0;
+    } else {
+      // eight costs loaded together, added one by one in order
+      for (int64_t q = q0; q < q1; q += 8) {
+        float cv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cv[i] = q + i < q1 ? c[val[q + i]] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (q + i < q1) sum += (double)cv[i];
+      }
+    }
     O.split_cut[r] = sum;
   }
 }
@@ -1317,8 +1342,9 @@ void Engine::emit(const std::vector<int32_t>& slots, const std::vector<JobHost>&
   if (Lv > 0) {
     Buf<uint32_t> key(c.pool, Lv);
     Buf<int32_t> val(c.pool, Lv);
-    VMO_LAUNCH(k_net_node, gsz(Lv * kNetG), kT, 0, s, dsub.p, m, Lv, leafh.p, rank_of.p, douts.p, keybase.p,
-               key.p, val.p);
+    const int64_t nwaves = (Lv + (64 / kNetG) * kNetRun - 1) / ((64 / kNetG) * kNetRun);
+    VMO_LAUNCH(k_net_node, (unsigned)((nwaves + kT / 64 - 1) / (kT / 64)), kT, 0, s, dsub.p, m, Lv, leafh.p,
+               rank_of.p, douts.p, keybase.p, key.p, val.p);
     Buf<int64_t> kc(c.pool, kt + 1);
     fill_i64(kc.p, 0, kt + 1, s);
     VMO_LAUNCH(k_net_count, gsz(Lv), kT, 0, s, key.p, Lv, kc.p);
