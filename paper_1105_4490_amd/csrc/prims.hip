@@ -699,17 +699,35 @@ __global__ void k_check_ptr(const int64_t* ptr, int32_t l, int* bad) {
 }
 // pins of net e: in range and strictly ascending (checked per pin with its
 // predecessor inside the same net, net found by binary search)
-__global__ void k_check_pins(const int64_t* ptr, const int32_t* pins, int32_t l, int32_t k, int64_t np, int* bad) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
-    int32_t v = pins[p];
-    if (v < 0 || v >= k) { atomicOr(bad, 2); continue; }
-    int32_t lo = 0, hi = l;  // last e with ptr[e] <= p
-    while (hi - lo > 1) {
-      int32_t mid = (lo + hi) >> 1;
-      if (ptr[mid] <= p) lo = mid; else hi = mid;
-    }
-    if (p > ptr[lo] && pins[p - 1] >= v) atomicOr(bad, 4);
+// Pins of every net: in [0, k) and strictly ascending.  kChkG lanes per net
+// (consecutive lanes read consecutive pins); a wavefront takes kChkRun runs of
+// 64 / kChkG consecutive nets.
+constexpr int kChkG = 16, kChkRun = 16, kChkPerWave = 64 / kChkG;
+static unsigned chk_blocks(int64_t nets) {
+  const int64_t waves = (nets + kChkPerWave * kChkRun - 1) / (kChkPerWave * kChkRun);
+  return (unsigned)((waves + 3) / 4);  // blocks of 256 threads
+}
+__device__ __forceinline__ int check_net_pins(const int64_t* ptr, const int32_t* pins, int32_t k, int64_t e, int gl) {
+  int flags = 0;
+  const int64_t b = ptr[e], en = ptr[e + 1];
+  for (int64_t p = b + gl; p < en; p += kChkG) {
+    const int32_t v = pins[p];
+    if (v < 0 || v >= k) flags |= 2;
+    else if (p > b && pins[p - 1] >= v) flags |= 4;
   }
+  return flags;
+}
+__global__ void k_check_pins(const int64_t* ptr, const int32_t* pins, int32_t l, int32_t k, int* bad) {
+  const int gl = threadIdx.x & (kChkG - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t e0 = wave * kChkPerWave * kChkRun + ((threadIdx.x & 63) / kChkG);
+  int flags = 0;
+  for (int r = 0; r < kChkRun; ++r) {
+    const int64_t e = e0 + (int64_t)r * kChkPerWave;
+    if (e >= l) break;
+    flags |= check_net_pins(ptr, pins, k, e, gl);
+  }
+  if (flags) atomicOr(bad, flags);
 }
 __global__ void k_check_vals(const float* v, int64_t n, int positive, int* bad) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -738,7 +756,7 @@ void validate_hypergraph(Ctx& c, const vmo_hypergraph* h, bool positive_wc, hipS
   VMO_REQUIRE(np >= 0 && np < (int64_t(1) << 31) * 2, "too many pins");
   if (np > 0) {
     VMO_REQUIRE(h->pins != nullptr, "pins is NULL");
-    VMO_LAUNCH(k_check_pins, gs_blocks(np), 256, 0, s, h->net_ptr, h->pins, h->l, h->k, np, bad.p);
+    VMO_LAUNCH(k_check_pins, chk_blocks(h->l), 256, 0, s, h->net_ptr, h->pins, h->l, h->k, bad.p);
   }
   if (h->w) VMO_LAUNCH(k_check_vals, gs_blocks(h->k), 256, 0, s, h->w, (int64_t)h->k, positive_wc ? 1 : 0, bad.p);
   if (h->c && h->l > 0) VMO_LAUNCH(k_check_vals, gs_blocks(h->l), 256, 0, s, h->c, (int64_t)h->l, positive_wc ? 1 : 0, bad.p);
@@ -778,24 +796,29 @@ __global__ void k_check_ptr_all(const CheckJob* jb, const int64_t* cum, int32_t 
     if (ptr[e + 1] < ptr[e] || (e == 0 && ptr[0] != 0)) atomicOr(&bad[j], 1);
   }
 }
-// pass 2: pins (range, ascending in a net) over cum = prefix of np
+// pass 2: pins of every net (range, ascending) over cum = prefix of l; a
+// wavefront keeps the job range it found (its nets mostly share one job)
 __global__ void k_check_pins_all(const CheckJob* jb, const int64_t* cum, int32_t nj, int64_t total, int* bad) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t j = job_of(cum, nj, i);
-    const CheckJob& J = jb[j];
-    const int64_t p = i - cum[j];
-    const int32_t v = J.pins[p];
-    if (v < 0 || v >= J.k) { atomicOr(&bad[j], 2); continue; }
-    // a descent from the previous pin is an error unless p starts a net:
-    // only then is the net of p looked up
-    if (p == 0 || J.pins[p - 1] < v) continue;
-    int32_t lo = 0, hi = J.l;  // last e with ptr[e] <= p
-    while (hi - lo > 1) {
-      int32_t mid = (lo + hi) >> 1;
-      if (J.ptr[mid] <= p) lo = mid; else hi = mid;
+  const int gl = threadIdx.x & (kChkG - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t i0 = wave * kChkPerWave * kChkRun + ((threadIdx.x & 63) / kChkG);
+  int32_t j = -1;
+  int64_t jlo = 0, jhi = 0;
+  int flags = 0;
+  for (int r = 0; r < kChkRun; ++r) {
+    const int64_t i = i0 + (int64_t)r * kChkPerWave;
+    if (i >= total) break;
+    if (i < jlo || i >= jhi) {
+      if (flags) atomicOr(&bad[j], flags);
+      flags = 0;
+      j = job_of(cum, nj, i);
+      jlo = cum[j];
+      jhi = j + 1 < nj ? cum[j + 1] : total;
     }
-    if (p > J.ptr[lo]) atomicOr(&bad[j], 4);
+    const CheckJob& J = jb[j];
+    flags |= check_net_pins(J.ptr, J.pins, J.k, i - jlo, gl);
   }
+  if (flags) atomicOr(&bad[j], flags);
 }
 // pass 2: per vertex (weights, 4 coordinates) over cum = prefix of k
 __global__ void k_check_vertices_all(const CheckJob* jb, const int64_t* cum, int32_t nj, int64_t total, int* bad) {
@@ -870,18 +893,18 @@ void validate_jobs(Ctx& c, const std::vector<JobCheck>& jobs, std::vector<int64_
   }
   VMO_HIP(hipMemcpyAsync(dj.p, hj.data(), sizeof(CheckJob) * nj, hipMemcpyHostToDevice, s));
   // pass 2: pins, then vertices (weights, coordinates), then nets (costs, edges)
-  Buf<int64_t> cum2(c.pool, nj), cum3(c.pool, nj), cum4(c.pool, nj);
-  std::vector<int64_t> h2(nj), h3(nj), h4(nj);
+  Buf<int64_t> cum3(c.pool, nj), cum4(c.pool, nj);
+  std::vector<int64_t> h3(nj), h4(nj);
   int64_t t2 = 0, t3 = 0, t4 = 0;
   for (int32_t j = 0; j < nj; ++j) {
-    h2[j] = t2; t2 += npins[j];
+    t2 += npins[j];
     h3[j] = t3; t3 += hj[j].k;
     h4[j] = t4; t4 += (int64_t)hj[j].l + 1;
   }
-  VMO_HIP(hipMemcpyAsync(cum2.p, h2.data(), 8 * nj, hipMemcpyHostToDevice, s));
   VMO_HIP(hipMemcpyAsync(cum3.p, h3.data(), 8 * nj, hipMemcpyHostToDevice, s));
   VMO_HIP(hipMemcpyAsync(cum4.p, h4.data(), 8 * nj, hipMemcpyHostToDevice, s));
-  if (t2 > 0) VMO_LAUNCH(k_check_pins_all, gs_blocks(t2), 256, 0, s, dj.p, cum2.p, nj, t2, bad.p);
+  // (pins are checked net by net: over the prefix of l, as pass 1)
+  if (t2 > 0 && tot > 0) VMO_LAUNCH(k_check_pins_all, chk_blocks(tot), 256, 0, s, dj.p, cum.p, nj, tot, bad.p);
   VMO_LAUNCH(k_check_vertices_all, gs_blocks(t3), 256, 0, s, dj.p, cum3.p, nj, t3, bad.p);
   VMO_LAUNCH(k_check_nets_all, gs_blocks(t4), 256, 0, s, dj.p, cum4.p, nj, t4, bad.p);
   read_bytes(hb.data(), bad.p, sizeof(int) * nj, s);
