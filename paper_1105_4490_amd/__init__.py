@@ -8,6 +8,7 @@ there is no fallback.
 from __future__ import annotations
 
 import ctypes as C
+from collections.abc import Mapping
 import functools
 import os
 from dataclasses import dataclass
@@ -161,6 +162,30 @@ class DeviceHypergraph:
             pins = torch.zeros(1, dtype=torch.int32, device=device)
         return DeviceHypergraph(int(h.k), int(h.l), t(ptr, torch.int64), pins, t(getattr(h, "w", None), torch.float32),
                                 t(getattr(h, "c", None), torch.float32))
+
+
+class _BatchOut(Mapping):
+    """Outputs of one job of a batch: views into the batch's shared arrays,
+    formed when read (a batch of hundreds of jobs would otherwise spend
+    milliseconds forming views that are never used)."""
+    __slots__ = ("_flat", "_sz", "_off", "_i", "_net", "_l")
+
+    def __init__(self, flat, sz, off, i, net, l):
+        self._flat, self._sz, self._off, self._i, self._net, self._l = flat, sz, off, i, net, l
+
+    def __getitem__(self, f):
+        if f not in self._flat:
+            raise KeyError(f)
+        if not self._net and f in ("nperm", "node_nptr"):
+            return None
+        n = self._l if f == "nperm" else self._sz[f][self._i]
+        return self._flat[f].narrow(0, self._off[f][self._i], n)
+
+    def __iter__(self):
+        return iter(self._flat)
+
+    def __len__(self):
+        return len(self._flat)
 
 
 class Context:
@@ -423,16 +448,9 @@ class Context:
             arr["o_" + f] = ptrs
         fn = lib().vmo_order_batch_plain if plain else lib().vmo_order_batch
         self._check(fn(self.h, C.c_int32(nj), C.c_void_p(arr.ctypes.data), C.c_int32(t_max), _stream()))
-        views = {f: torch.split(flat[f][:int(sizes[f].sum())], sizes[f].tolist()) for f in sizes}
-        outs = []
-        for i in range(nj):
-            o = {f: views[f][i] for f in sizes}
-            if net[i]:
-                o["nperm"] = o["nperm"][:int(l[i])]
-            else:
-                o["nperm"] = o["node_nptr"] = None
-            outs.append(o)
-        return outs
+        sz = {f: sizes[f].tolist() for f in sizes}
+        of = {f: offs[f].tolist() for f in sizes}
+        return [_BatchOut(flat, sz, of, i, bool(net[i]), int(l[i])) for i in range(nj)]
 
     # ---------------------------------------------------------------- layout --
     def layout(self, h: DeviceHypergraph, params: LayoutParams | None = None) -> torch.Tensor:
