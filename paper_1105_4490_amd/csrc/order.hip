@@ -341,12 +341,17 @@ __global__ __launch_bounds__(1024) void k_assign(SegArrays sg, const int32_t* se
   int32_t cs = -1;
   bool citer = false;
   double pl[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int32_t scanned = 0;  // positions read (for the timing's byte count)
 #pragma unroll
   for (int h = 0; h < PPT / 4; ++h) {
     const int64_t bh = b + 4 * h;
     if (bh >= p1) break;
-    // the four positions' segments: one word when they share it
+    // the four positions' segments: one word when they share it; four
+    // positions of a segment that no longer iterates are neither read nor
+    // written
     const int32_t pk = segpack[bh >> 2];
+    if (pk != kPackMixed && (pk < 0 || sg.state[pk] != kStIter)) continue;
+    scanned += (int32_t)(min(bh + 4, p1) - max(bh, p0));
     int4 sp = make_int4(pk, pk, pk, pk);
     if (pk == kPackMixed) sp = *reinterpret_cast<const int4*>(segpos + bh);
     const uint4 q0 = *reinterpret_cast<const uint4*>(q + bh);
@@ -433,7 +438,11 @@ __global__ __launch_bounds__(1024) void k_assign(SegArrays sg, const int32_t* se
       if (kw >= 0) a += ssum[w][f];
     }
   }
-  if (work && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(work, 17ull * (unsigned long long)(p1 - p0));
+  if (work) {
+    // 17 algorithmic bytes per position read (16 B coordinates, 1 B side)
+    const int32_t tot = wave_sum_dpp(scanned);
+    if (lane_id() == 63 && tot) atomicAdd(work, 17ull * (unsigned long long)tot);
+  }
 }
 
 // End of a Lloyd iteration for segment s: new centres and plane, or the
