@@ -74,8 +74,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="path mode: leave out the serving field")
     ap.add_argument("--no-zipf", action="store_true",
                     help="path mode: leave out the rectangular Zipf V+O field (200,000 x 100,000, column-net)")
-    ap.add_argument("--mode", choices=("path", "batch", "serve", "copy"), default="path",
-                    help="copy: a plain 256 MiB device copy, three times (calibrates the HBM byte counters)")
+    ap.add_argument("--mode", choices=("path", "batch", "serve", "zipf", "copy"), default="path",
+                    help="copy: a plain 256 MiB device copy, three times (calibrates the HBM byte counters); "
+                         "zipf: only the rectangular Zipf V+O field")
     ap.add_argument("--jobs", type=int, default=512, help="batch mode: number of matrices")
     ap.add_argument("--layout-threads", type=int, default=4, help="batch mode: streams laying out the matrices")
     ap.add_argument("--no-plain", action="store_true", help="batch mode: skip the plain per-subproblem form")
@@ -111,6 +112,9 @@ def main():
         return bench_batch(args, ctx)
     if args.mode == "serve":
         return bench_serve(args, ctx)
+    if args.mode == "zipf":
+        print(json.dumps(bench_zipf(ctx, P.layout_params(seed=SEED), args.steps)))
+        return None
     g = vmo_gen.grid3d(args.side, seed=SEED)
     nnz = g.nnz
     rowptr = torch.as_tensor(g.rowptr).cuda()

@@ -155,14 +155,15 @@ __global__ void k_net_split(const int64_t* ptr, const int32_t* pins, int32_t l, 
   }
 }
 // split[h] = costs of the nets cut at h, one by one in ascending net id
-__global__ void k_split_sum(const uint32_t* key, const int32_t* val, int32_t l, int32_t P, const float* c,
-                            double* split) {
-  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < 4 * (int64_t)P;
-       h += (int64_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(kCT) void k_split_sum(const uint32_t* key, const int32_t* val, int32_t l, int32_t P,
+                                                   const float* c, double* split) {
+  // one wavefront per node h: its nets are [lower_bound(h), lower_bound(h + 1))
+  __shared__ __align__(16) float stage[kCT / 64][64];
+  const int wv = threadIdx.x >> 6;
+  for (int64_t h = (int64_t)blockIdx.x * (kCT / 64) + wv; h < 4 * (int64_t)P; h += (int64_t)gridDim.x * (kCT / 64)) {
     const int32_t b = lower_bound_u32(key, l, (uint32_t)h), e = lower_bound_u32(key, l, (uint32_t)h + 1u);
-    double a = 0.0;
-    for (int32_t i = b; i < e; ++i) a = a + (c ? (double)c[val[i]] : 1.0);
-    split[h] = a;
+    const double a = wave_ordered_cost_sum(c, val, b, e, stage[wv]);
+    if ((threadIdx.x & 63) == 0) split[h] = a;
   }
 }
 // graph mode: split[h] = |S_h|, the vertices with part id P + h
@@ -268,7 +269,7 @@ void cut(Ctx& c, const vmo_hypergraph* h, const int32_t* part, int32_t nparts, d
       Buf<int32_t> val(c.pool, l);
       VMO_LAUNCH(k_net_split, gsz(l), kCT, 0, s, h->net_ptr, h->pins, l, part, lam.p, nparts, key.p, val.p);
       radix_sort<uint32_t>(c, key.p, val.p, l, bits_for((uint64_t)nh), s);
-      VMO_LAUNCH(k_split_sum, gsz(nh), kCT, 0, s, key.p, val.p, l, nparts, h->c, split.p);
+      VMO_LAUNCH(k_split_sum, gsz(nh * 64), kCT, 0, s, key.p, val.p, l, nparts, h->c, split.p);
     } else {
       VMO_HIP(hipMemsetAsync(split.p, 0, sizeof(double) * nh, s));
     }

@@ -857,10 +857,14 @@ __global__ void k_net_count(const uint32_t* key, int64_t Lv, int64_t* keycount) 
 
 // Cut of every split (Table 4) in net mode: the costs of the nets of an
 // internal node, summed in FP64 one by one in ascending net id (the nets are
-// sorted by node, stably: their order within a node is the input order).
-__global__ void k_net_split(const JobDev* jobs, int32_t nj, const int64_t* keybase, int64_t kt, const int64_t* kc,
-                            const int32_t* val, NodeArrays nd, float* const* costs, const OutPtrs* outs) {
-  for (int64_t kk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; kk < kt; kk += (int64_t)gridDim.x * blockDim.x) {
+// sorted by node, stably: their order within a node is the input order); one
+// wavefront per node.
+__global__ __launch_bounds__(kT) void k_net_split(const JobDev* jobs, int32_t nj, const int64_t* keybase, int64_t kt,
+                                                  const int64_t* kc, const int32_t* val, NodeArrays nd,
+                                                  float* const* costs, const OutPtrs* outs) {
+  __shared__ __align__(16) float stage[kT / 64][64];
+  const int wv = threadIdx.x >> 6;
+  for (int64_t kk = (int64_t)blockIdx.x * (kT / 64) + wv; kk < kt; kk += (int64_t)gridDim.x * (kT / 64)) {
     int32_t lo = 0, hi = nj;  // the last job whose keys begin at or before kk
     while (hi - lo > 1) {
       const int32_t mid = (lo + hi) >> 1;
@@ -872,23 +876,8 @@ __global__ void k_net_split(const JobDev* jobs, int32_t nj, const int64_t* keyba
     if (jobs[j].mode != VMO_NET || r >= O.n_nodes[0]) continue;  // the bucket of empty nets
     const int32_t h = O.node_heap[r];
     if (nd.state[jobs[j].node_base + h] != kNodeInternal) continue;
-    const float* c = costs[j];
-    const int64_t q0 = kc[kk], q1 = kc[kk + 1];
-    double sum = 0.0;
-    if (!c) {
-      for (int64_t q = q0; q < q1; ++q) sum += 1.0;
-    } else {
-      // eight costs loaded together, added one by one in order
-      for (int64_t q = q0; q < q1; q += 8) {
-        float cv[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) cv[i] = q + i < q1 ? c[val[q + i]] : 0.0f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (q + i < q1) sum += (double)cv[i];
-      }
-    }
-    O.split_cut[r] = sum;
+    const double sum = wave_ordered_cost_sum(costs[j], val, kc[kk], kc[kk + 1], stage[wv]);
+    if ((threadIdx.x & 63) == 0) O.split_cut[r] = sum;
   }
 }
 
@@ -1359,7 +1348,7 @@ void Engine::emit(const std::vector<int32_t>& slots, const std::vector<JobHost>&
     VMO_LAUNCH(k_net_count, gsz(Lv), kT, 0, s, key.p, Lv, kc.p);
     scan_exclusive<int64_t>(c, kc.p, kc.p, kt, kc.p + kt, s);
     radix_sort<uint32_t>(c, key.p, val.p, Lv, bits_for((uint64_t)kt), s);
-    VMO_LAUNCH(k_net_split, gsz(kt), kT, 0, s, dsub.p, m, keybase.p, kt, kc.p, val.p, nd, dcost.p, douts.p);
+    VMO_LAUNCH(k_net_split, gsz(kt * 64), kT, 0, s, dsub.p, m, keybase.p, kt, kc.p, val.p, nd, dcost.p, douts.p);
     VMO_LAUNCH(k_net_out, gsz(Lv), kT, 0, s, dsub.p, m, Lv, val.p, douts.p);
     VMO_LAUNCH(k_net_ptr, m, kT, 0, s, dsub.p, m, kc.p, keybase.p, douts.p);
   }

@@ -387,4 +387,41 @@ inline int bits_for(uint64_t maxval) {
   return b;
 }
 
+// FP64 sum of c[val[q]] for q = b .. e-1 (1 each when c is NULL), one by
+// one in that order, by a whole wavefront: its lanes load 64 costs at a time
+// into `stage` (64 floats of LDS owned by the wavefront), then every lane
+// adds them in order (the loads of a chunk are in flight together instead of
+// one dependent load per term).  All lanes return the sum.
+__device__ inline double wave_ordered_cost_sum(const float* c, const int32_t* val, int64_t b, int64_t e,
+                                               float* stage) {
+  if (!c) return (double)(e > b ? e - b : 0);  // n ones, exact below 2^53
+  const int lane = threadIdx.x & 63;
+  double a = 0.0;
+  for (int64_t q0 = b; q0 < e; q0 += 64) {
+    const int m = e - q0 < 64 ? (int)(e - q0) : 64;
+    const float v = lane < m ? c[val[q0 + lane]] : 0.0f;
+    // the previous chunk's reads are done before the stage is overwritten
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    stage[lane] = v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (m == 64) {
+      const float4* s4 = reinterpret_cast<const float4*>(stage);
+#pragma unroll
+      for (int r = 0; r < 16; r += 4) {
+        const float4 u0 = s4[r], u1 = s4[r + 1], u2 = s4[r + 2], u3 = s4[r + 3];
+        a += (double)u0.x; a += (double)u0.y; a += (double)u0.z; a += (double)u0.w;
+        a += (double)u1.x; a += (double)u1.y; a += (double)u1.z; a += (double)u1.w;
+        a += (double)u2.x; a += (double)u2.y; a += (double)u2.z; a += (double)u2.w;
+        a += (double)u3.x; a += (double)u3.y; a += (double)u3.z; a += (double)u3.w;
+      }
+    } else {
+      for (int i = 0; i < m; ++i) a += (double)stage[i];
+    }
+  }
+  return a;
+}
+
 }  // namespace vmo
