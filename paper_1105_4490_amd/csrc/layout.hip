@@ -1243,10 +1243,13 @@ __device__ __forceinline__ void interact(float* y, const float* xn, float wn2, f
   r2 = __builtin_fmaf(dx1, dx1, r2);
   r2 = __builtin_fmaf(dx2, dx2, r2);
   r2 = __builtin_fmaf(dx3, dx3, r2);
-  if (!(r2 > 0.0f)) return;
   float num = W * wn2;  // (2 W) w_n = W (2 w_n) exactly
   float den = r2 * r2;
+  // no branch at zero distance: f = 0 there, and fma(0, dx, y) = y, since
+  // dx is finite and y, a sum that starts at +0, is never -0
   float f = num / den;
+  asm volatile("" : "+v"(f));  // formed on every lane: a select below, not a branch
+  f = r2 > 0.0f ? f : 0.0f;
   y[0] = __builtin_fmaf(f, dx0, y[0]);
   y[1] = __builtin_fmaf(f, dx1, y[1]);
   y[2] = __builtin_fmaf(f, dx2, y[2]);
