@@ -1411,7 +1411,16 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
             if (near) {
               // the point itself is not skipped by index: its distance is
               // zero, and interact() leaves y unchanged at zero distance
-              for (int32_t i = 0; i < m; ++i) {
+              // two points per step, both read before the first interaction
+              // (the interactions stay in point order)
+              int32_t i = 0;
+              for (; i + 1 < m; i += 2) {
+                const float4 pa = lp[wv][o2 + i], pb = lp[wv][o2 + i + 1];
+                const float wa = lw[wv][o2 + i], wb = lw[wv][o2 + i + 1];
+                interact(y, xn, wn2, pa.x, pa.y, pa.z, pa.w, wa);
+                interact(y, xn, wn2, pb.x, pb.y, pb.z, pb.w, wb);
+              }
+              if (i < m) {
                 const float4 pi = lp[wv][o2 + i];
                 interact(y, xn, wn2, pi.x, pi.y, pi.z, pi.w, lw[wv][o2 + i]);
               }
