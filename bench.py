@@ -38,14 +38,15 @@ N_SIDE = 64
 SEED = 1
 SCHUR_P3 = 8         # parts of each separator block in the Schur-complement recursion
 # Algorithmic flops of one interaction (one term of the repulsion in eq. (7)),
-# the count fixed for this measurement; the kernel itself executes 23 (4 sub,
-# r^2 as 1 mul + 3 fma, 1 mul for W (2 w_n), 1 mul for r^4, 1 div, 4 fma).
+# the count fixed for this measurement (the kernel executes about 26 VALU
+# instructions per interaction: 4 sub, r^2 as 1 mul + 3 fma, 2 mul, the IEEE
+# division's 11, 4 fma, and the zero-distance select).
 FLOPS_PER_INTERACTION = 20
 # HBM bytes per walk launch (average over the walk launches of one counting and
 # one timed step of this workload), from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
 # plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
-WALK_TRAFFIC_BYTES = 88.27e6 + 18.77e6
+WALK_TRAFFIC_BYTES = 82.89e6 + 18.77e6
 PEAK_FP32_VALU_TFLOPS = 157.3        # 256 CUs x 128 FP32 lanes (packed) x 2 (fma) x 2.4 GHz
 PEAK_FP32_UNPACKED_TFLOPS = 78.6     # the same without packed FP32 (this build disables it)
 # live timing brackets every PROFILE_EVERY-th launch of a kernel with HIP
