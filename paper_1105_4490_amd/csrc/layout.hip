@@ -1358,11 +1358,16 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
     while (t < t1) {
       if (t < wb || t >= wb + kWin) {
         wb = t;
-        if (t + po < n) {
-          win[wv][pc][po] = nodes4[5 * (int64_t)(t + po) + pc];
-          win[wv][pc + 1][po] = nodes4[5 * (int64_t)(t + po) + pc + 1];
+        // the three loads issued together (lanes past the tree's end, or
+        // past the window for chunk 4, read node t again and write nothing)
+        const bool oka = t + po < n, okb = lane < kWin && t + lane < n;
+        const int64_t ia = oka ? t + po : t, ib = okb ? t + lane : t;
+        const int4 c0 = nodes4[5 * ia + pc], c1 = nodes4[5 * ia + pc + 1], c4 = nodes4[5 * ib + 4];
+        if (oka) {
+          win[wv][pc][po] = c0;
+          win[wv][pc + 1][po] = c1;
         }
-        if (lane < kWin && t + lane < n) win[wv][4][lane] = nodes4[5 * (int64_t)(t + lane) + 4];
+        if (okb) win[wv][4][lane] = c4;
         wave_sync();
       }
       const int o = t - wb;
