@@ -355,7 +355,63 @@ struct NodeView {
   int32_t* nch;
   int32_t* ctr;  // depth lists of the one-block build
   int32_t* cid;  // [n][16] children in order (a cell has at most 16 sub-cells)
+  int32_t* plan;  // [kPlan] launch order of the walk's part rows (walk_plan)
 };
+
+// The walk's launch plan.  A part row of the walk (the root's child i1 and,
+// spread, its child i2) is heavy when many points lie in its node: those
+// points walk its whole subtree.  Its blocks are launched in the order of
+// that count, largest first, and a row's first block takes the node's first
+// points, so that the longest walks start first instead of last (a level's
+// walk ends with its longest wavefront).  Which block walks which row and
+// points changes no point's walk or sums.  Layout: [256] spread rows in launch
+// order, [256] each spread row's first point block, [16] and [16] the same for
+// the unspread rows.
+constexpr int kPlan = 256 + 256 + 16 + 16;
+// Called by every thread of a block of at least 256 (the first 256 take part);
+// sw: 288 ints of LDS.
+__device__ void walk_plan(const NodeView& nd, int32_t* sw) {
+  const int t = threadIdx.x;
+  int32_t w16 = -1, x16 = 0;
+  if (t < kParts * kParts) {
+    const bool rleaf = (nd.t[0].b.w >> 8) & 1;
+    const int n1 = rleaf ? 1 : min(nd.nch[0], kParts);
+    const int i1 = t / kParts, i2 = t % kParts;
+    if (i1 < n1) {
+      const int32_t c1 = rleaf ? 0 : nd.cid[i1];
+      const int4 b1 = nd.t[c1].b;
+      if (i2 == 0) {
+        sw[256 + i1] = b1.z;
+        sw[272 + i1] = b1.y / 64;
+      }
+      if ((b1.w >> 8) & 1) {
+        if (i2 == 0) { w16 = b1.z; x16 = b1.y / 64; }
+      } else if (i2 < min(nd.nch[c1], kParts)) {
+        const int4 b2 = nd.t[nd.cid[16 * (int64_t)c1 + i2]].b;
+        w16 = b2.z;
+        x16 = b2.y / 64;
+      }
+    } else if (i2 == 0) {
+      sw[256 + i1] = -1;
+      sw[272 + i1] = 0;
+    }
+    sw[t] = w16;
+  }
+  __syncthreads();
+  if (t < kParts * kParts) {
+    int r = 0;
+    for (int u = 0; u < kParts * kParts; ++u) r += sw[u] > w16 || (sw[u] == w16 && u < t);
+    nd.plan[r] = t;
+    nd.plan[256 + t] = x16;
+  }
+  if (t < kParts) {
+    const int32_t w1 = sw[256 + t];
+    int r = 0;
+    for (int u = 0; u < kParts; ++u) r += sw[256 + u] > w1 || (sw[256 + u] == w1 && u < t);
+    nd.plan[512 + r] = t;
+    nd.plan[528 + t] = sw[272 + t];
+  }
+}
 
 // Nodes in pre-order: index = base[i] + (L - cpl[i] - 1) for the node of
 // depth L beginning at point i; next = first node beginning at its end.
@@ -513,6 +569,11 @@ __global__ __launch_bounds__(kMomT) void k_moments_sub(int32_t k, const float* x
 
 // Internal nodes of depths 2, 1, 0 (one block of kParts^2 threads).
 __global__ __launch_bounds__(kParts * kParts) void k_moments_top(NodeView nd) {
+  {
+    // the nodes, counts and children lists are final here
+    __shared__ int32_t sw[288];
+    walk_plan(nd, sw);
+  }
   if ((nd.t[0].b.w >> 8) & 1) return;
   const int i1 = threadIdx.x / kParts, i2 = threadIdx.x % kParts;
   const int n1 = min(nd.nch[0], kParts);
@@ -1074,6 +1135,8 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     }
     __syncthreads();
   }
+  __shared__ int32_t sw_plan[288];
+  walk_plan(nd, sw_plan);
 }
 
 struct Tree {
@@ -1085,11 +1148,11 @@ struct Tree {
   Buf<TNode> nodes;
   Buf<float4> P;  // points in tree order
   Buf<double> Wd, Sd;
-  Buf<int32_t> nch, ctr, cid;
+  Buf<int32_t> nch, ctr, cid, plan;
   NodeView view() {
     NodeView v;
     v.t = nodes.p; v.Wd = Wd.p; v.Sd = Sd.p;
-    v.nch = nch.p; v.ctr = ctr.p; v.cid = cid.p;
+    v.nch = nch.p; v.ctr = ctr.p; v.cid = cid.p; v.plan = plan.p;
     return v;
   }
 };
@@ -1125,6 +1188,7 @@ static void build_tree(Ctx& C, Tree& T, const float4* x, const float* w, int32_t
   grow(T.Sd, 4 * nmax);
   grow(T.nch, nmax);
   grow(T.cid, 16 * nmax);
+  grow(T.plan, kPlan);
   if (small_ok && k > 0 && k <= kSmallK) {
     grow(T.ctr, nmax);
     AttractJob none{};
@@ -1307,12 +1371,16 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
                                               const float* __restrict__ ws, const int32_t* __restrict__ p2,
                                               const TNode* __restrict__ nodes, const int32_t* __restrict__ cid,
                                               const int32_t* __restrict__ nch, int spread, float* __restrict__ part,
-                                              unsigned long long* nint) {
+                                              unsigned long long* nint, const int32_t* __restrict__ plan) {
   constexpr int NW = kWT / 64;
   __shared__ int4 win[NW][5][kWin];  // the five 16-byte chunks of kWin nodes
   __shared__ float4 lp[NW][kWin];
   __shared__ float lw[NW][kWin];
-  const int i1 = blockIdx.y / spread, i2s = blockIdx.y % spread;
+  // the row and the points of this block, from the launch plan (walk_plan)
+  const int32_t yrow = spread > 1 ? plan[blockIdx.y] : plan[512 + blockIdx.y];
+  int32_t bx = (int32_t)blockIdx.x + (spread > 1 ? plan[256 + yrow] : plan[528 + yrow]);
+  if (bx >= (int32_t)gridDim.x) bx -= (int32_t)gridDim.x;
+  const int i1 = yrow / spread, i2s = yrow % spread;
   const int32_t n = *n_dev;
   const bool rleaf = (nodes[0].b.w >> 8) & 1;
   const int n1 = rleaf ? 1 : min(nch[0], kParts);
@@ -1323,7 +1391,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
   const int n2 = c1leaf ? 0 : min(nch[c1], kParts);
   if (i2s > 0 && i2s >= n2) return;  // the whole block
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = (int64_t)bx * kWT + threadIdx.x;
   const bool valid = j < k;
   // interactions of the wavefront (uniform: counted from lane masks)
   unsigned long long cnt = 0;
@@ -1655,10 +1723,10 @@ static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, doub
   const dim3 wgrid(nblocks(L.k, kWT), kParts * spread);
   if (target)
     VMO_LAUNCH((k_walk<true>), wgrid, kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p, gw.T.nodes.p,
-               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, C.wslots);
+               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, C.wslots, gw.T.plan.p);
   else
     VMO_LAUNCH((k_walk<false>), wgrid, kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p, gw.T.nodes.p,
-               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, nullptr);
+               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, nullptr, gw.T.plan.p);
   prof_end(C, ph, s);
   if (target) VMO_LAUNCH(k_sum_slots, 1, kCntSlots, 0, s, C.wslots, target);
   VMO_LAUNCH(k_combine, nblocks(L.k, 64), kCombT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p,
