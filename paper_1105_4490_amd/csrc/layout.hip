@@ -359,20 +359,24 @@ struct NodeView {
 };
 
 // The walk's launch plan.  A part row of the walk (the root's child i1 and,
-// spread, its child i2) is heavy when many points lie in its node: those
-// points walk its whole subtree.  Its blocks are launched in the order of
-// that count, largest first, and a row's first block takes the node's first
-// points, so that the longest walks start first instead of last (a level's
-// walk ends with its longest wavefront).  Which block walks which row and
-// points changes no point's walk or sums.  Layout: [256] spread rows in launch
-// order, [256] each spread row's first point block, [16] and [16] the same for
-// the unspread rows.
-constexpr int kPlan = 256 + 256 + 16 + 16;
-// Called by every thread of a block of at least 256 (the first 256 take part);
-// sw: 288 ints of LDS.
+// spread, its child i2) has a node (that grandchild, or the child itself);
+// the points inside it walk its whole subtree and are the longest walks.  The
+// walk's grid first gives those points wavefronts of kHeavyPts (short unions,
+// so the longest wavefronts shrink), rows with the most such points first,
+// then the rows' other points in wavefronts of 64, rows in the same order and
+// each row's blocks starting at its node's points.  Which wavefront walks which
+// row and points changes no point's walk or sums.
+constexpr int kHeavyPts = 40;
+// plan layout (ints): spread rows (256) then unspread rows (16) of each table
+constexpr int kPlP = 0, kPlX = 272, kPlH = 544, kPlF = 818, kPlC = 1090, kPlan = 1362;
+// rows in launch order [256 | 16]: kPlP; each row's first 64-point block
+// [256 | 16]: kPlX; heavy wavefronts before each launch rank [257 | 17]:
+// kPlH; each row's node's first point and point count [256 | 16]: kPlF, kPlC.
+// Called by every thread of a block of at least 256 (the first 256 take
+// part); sw: 640 ints of LDS.
 __device__ void walk_plan(const NodeView& nd, int32_t* sw) {
   const int t = threadIdx.x;
-  int32_t w16 = -1, x16 = 0;
+  int32_t w16 = -1, x16 = 0, f16 = 0;
   if (t < kParts * kParts) {
     const bool rleaf = (nd.t[0].b.w >> 8) & 1;
     const int n1 = rleaf ? 1 : min(nd.nch[0], kParts);
@@ -383,33 +387,52 @@ __device__ void walk_plan(const NodeView& nd, int32_t* sw) {
       if (i2 == 0) {
         sw[256 + i1] = b1.z;
         sw[272 + i1] = b1.y / 64;
+        sw[288 + i1] = b1.y;
       }
       if ((b1.w >> 8) & 1) {
-        if (i2 == 0) { w16 = b1.z; x16 = b1.y / 64; }
+        if (i2 == 0) { w16 = b1.z; x16 = b1.y / 64; f16 = b1.y; }
       } else if (i2 < min(nd.nch[c1], kParts)) {
         const int4 b2 = nd.t[nd.cid[16 * (int64_t)c1 + i2]].b;
         w16 = b2.z;
         x16 = b2.y / 64;
+        f16 = b2.y;
       }
     } else if (i2 == 0) {
       sw[256 + i1] = -1;
       sw[272 + i1] = 0;
+      sw[288 + i1] = 0;
     }
     sw[t] = w16;
   }
   __syncthreads();
+  int32_t* hc = sw + 320;  // heavy wavefronts by launch rank: [256] spread, [16] unspread
   if (t < kParts * kParts) {
     int r = 0;
     for (int u = 0; u < kParts * kParts; ++u) r += sw[u] > w16 || (sw[u] == w16 && u < t);
-    nd.plan[r] = t;
-    nd.plan[256 + t] = x16;
+    nd.plan[kPlP + r] = t;
+    nd.plan[kPlX + t] = x16;
+    nd.plan[kPlF + t] = f16;
+    nd.plan[kPlC + t] = w16 > 0 ? w16 : 0;
+    hc[r] = w16 > 0 ? (w16 + kHeavyPts - 1) / kHeavyPts : 0;
   }
   if (t < kParts) {
     const int32_t w1 = sw[256 + t];
     int r = 0;
     for (int u = 0; u < kParts; ++u) r += sw[256 + u] > w1 || (sw[256 + u] == w1 && u < t);
-    nd.plan[512 + r] = t;
-    nd.plan[528 + t] = sw[272 + t];
+    nd.plan[kPlP + 256 + r] = t;
+    nd.plan[kPlX + 256 + t] = sw[272 + t];
+    nd.plan[kPlF + 256 + t] = sw[288 + t];
+    nd.plan[kPlC + 256 + t] = w1 > 0 ? w1 : 0;
+    hc[256 + r] = w1 > 0 ? (w1 + kHeavyPts - 1) / kHeavyPts : 0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int32_t a = 0;
+    for (int r = 0; r < kParts * kParts; ++r) { nd.plan[kPlH + r] = a; a += hc[r]; }
+    nd.plan[kPlH + 256] = a;
+    a = 0;
+    for (int r = 0; r < kParts; ++r) { nd.plan[kPlH + 257 + r] = a; a += hc[256 + r]; }
+    nd.plan[kPlH + 257 + 16] = a;
   }
 }
 
@@ -571,7 +594,7 @@ __global__ __launch_bounds__(kMomT) void k_moments_sub(int32_t k, const float* x
 __global__ __launch_bounds__(kParts * kParts) void k_moments_top(NodeView nd) {
   {
     // the nodes, counts and children lists are final here
-    __shared__ int32_t sw[288];
+    __shared__ int32_t sw[640];
     walk_plan(nd, sw);
   }
   if ((nd.t[0].b.w >> 8) & 1) return;
@@ -1135,7 +1158,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     }
     __syncthreads();
   }
-  __shared__ int32_t sw_plan[288];
+  __shared__ int32_t sw_plan[640];
   walk_plan(nd, sw_plan);
 }
 
@@ -1371,15 +1394,43 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
                                               const float* __restrict__ ws, const int32_t* __restrict__ p2,
                                               const TNode* __restrict__ nodes, const int32_t* __restrict__ cid,
                                               const int32_t* __restrict__ nch, int spread, float* __restrict__ part,
-                                              unsigned long long* nint, const int32_t* __restrict__ plan) {
+                                              unsigned long long* nint, const int32_t* __restrict__ plan,
+                                              int32_t hblocks) {
   constexpr int NW = kWT / 64;
   __shared__ int4 win[NW][5][kWin];  // the five 16-byte chunks of kWin nodes
   __shared__ float4 lp[NW][kWin];
   __shared__ float lw[NW][kWin];
-  // the row and the points of this block, from the launch plan (walk_plan)
-  const int32_t yrow = spread > 1 ? plan[blockIdx.y] : plan[512 + blockIdx.y];
-  int32_t bx = (int32_t)blockIdx.x + (spread > 1 ? plan[256 + yrow] : plan[528 + yrow]);
-  if (bx >= (int32_t)gridDim.x) bx -= (int32_t)gridDim.x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // The row and the points of this block, from the launch plan (walk_plan):
+  // blocks below hblocks take kHeavyPts points of a row's node, the others
+  // 64 points of a row outside its node.
+  const int R = kParts * spread, so = spread > 1 ? 0 : 256;
+  const int64_t gb = blockIdx.x;
+  int32_t yrow;
+  int64_t j;
+  bool valid;
+  if (gb < hblocks) {
+    const int32_t* hp = plan + kPlH + (spread > 1 ? 0 : 257);
+    if (gb >= hp[R]) return;  // the whole block: past the heavy wavefronts
+    int lo = 0, hi = R;       // the launch rank r with hp[r] <= gb < hp[r + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (hp[mid] <= gb) lo = mid; else hi = mid;
+    }
+    yrow = plan[kPlP + so + lo];
+    const int64_t nf = plan[kPlF + so + yrow], nc = plan[kPlC + so + yrow];
+    j = nf + (gb - hp[lo]) * kHeavyPts + lane;
+    valid = lane < kHeavyPts && j < nf + nc;
+  } else {
+    const int64_t gx = ((int64_t)k + 63) / 64, bn = gb - hblocks;
+    const int r = (int)(bn / gx);
+    yrow = plan[kPlP + so + r];
+    int64_t x = bn % gx + plan[kPlX + so + yrow];
+    if (x >= gx) x -= gx;
+    const int64_t nf = plan[kPlF + so + yrow], nc = plan[kPlC + so + yrow];
+    j = x * 64 + lane;
+    valid = j < k && !(j >= nf && j < nf + nc);
+  }
   const int i1 = yrow / spread, i2s = yrow % spread;
   const int32_t n = *n_dev;
   const bool rleaf = (nodes[0].b.w >> 8) & 1;
@@ -1390,9 +1441,6 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
   const bool c1leaf = (b1.w >> 8) & 1;
   const int n2 = c1leaf ? 0 : min(nch[c1], kParts);
   if (i2s > 0 && i2s >= n2) return;  // the whole block
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)bx * kWT + threadIdx.x;
-  const bool valid = j < k;
   // interactions of the wavefront (uniform: counted from lane masks)
   unsigned long long cnt = 0;
   float xn[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1549,7 +1597,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
   if (kCount) {
     // kCntSlots counters, 128 bytes apart, so that the wavefronts' atomics
     // (finishing at about the same time) do not queue on one address
-    const unsigned slot = ((unsigned)blockIdx.x * (kWT / 64) + wv + (unsigned)blockIdx.y * 61u) % kCntSlots;
+    const unsigned slot = ((unsigned)blockIdx.x * (kWT / 64) + wv) % kCntSlots;
     if (lane == 0 && cnt) atomicAdd(&nint[16 * slot], cnt);
   }
 }
@@ -1720,13 +1768,17 @@ static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, doub
     VMO_HIP(hipMemsetAsync(C.wslots, 0, sizeof(unsigned long long) * 16 * kCntSlots, s));
     if (ph >= 0) prof_restart(C, ph, s);
   }
-  const dim3 wgrid(nblocks(L.k, kWT), kParts * spread);
+  // heavy wavefronts: at most one per kHeavyPts points plus one per row
+  // (the rows' nodes are disjoint), then 64-point blocks for every row
+  const int64_t rows = (int64_t)kParts * spread;
+  const int64_t hblocks = ((int64_t)L.k + kHeavyPts - 1) / kHeavyPts + rows;
+  const unsigned wgrid = (unsigned)(hblocks + nblocks(L.k, kWT) * rows);
   if (target)
     VMO_LAUNCH((k_walk<true>), wgrid, kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p, gw.T.nodes.p,
-               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, C.wslots, gw.T.plan.p);
+               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, C.wslots, gw.T.plan.p, (int32_t)hblocks);
   else
     VMO_LAUNCH((k_walk<false>), wgrid, kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p, gw.T.nodes.p,
-               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, nullptr, gw.T.plan.p);
+               gw.T.cid.p, gw.T.nch.p, spread, gw.part.p, nullptr, gw.T.plan.p, (int32_t)hblocks);
   prof_end(C, ph, s);
   if (target) VMO_LAUNCH(k_sum_slots, 1, kCntSlots, 0, s, C.wslots, target);
   VMO_LAUNCH(k_combine, nblocks(L.k, 64), kCombT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p,
