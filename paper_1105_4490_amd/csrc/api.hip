@@ -416,7 +416,7 @@ size_t vmo_layout_bytes(int32_t k, int32_t l, int64_t npins) {
   // each); the layout's own 16 B per net and 24 B per pin; and a quarter more
   // for the pool's size classes.
   const double kd = (double)k, ld = (double)l, pd = (double)npins;
-  const double parts = std::max(256.0 * kd, 4096.0 * std::min(kd, 200000.0));
+  const double parts = std::max(256.0 * kd, 4096.0 * std::min(kd, 300000.0));
   const double per_v = 17.0 * 192.0 + 32.0 + 64.0 + 2.5 * (70.0 + 16.0);
   const double lvl = 2.5 * (12.0 * ld + 8.0 * pd);
   return (size_t)(1.25 * (kd * per_v + parts + lvl + 16.0 * ld + 24.0 * pd)) + ((size_t)1 << 20);

@@ -1747,7 +1747,7 @@ static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, doub
   // parts to write and add up.  Above it the unspread walk already has more
   // than six wavefronts per resident slot of the chip (256 CUs x 32), and
   // spreading only adds traffic.
-  constexpr int32_t kSpreadMax = 200000;
+  constexpr int32_t kSpreadMax = 300000;
   if (L.k <= 0) return;
   const int spread = L.k <= kSpreadMax ? kParts : 1;
   const size_t np = (size_t)kParts * spread * 4 * L.k;
