@@ -373,7 +373,7 @@ constexpr int kPlP = 0, kPlX = 272, kPlH = 544, kPlF = 818, kPlC = 1090, kPlan =
 // [256 | 16]: kPlX; heavy wavefronts before each launch rank [257 | 17]:
 // kPlH; each row's node's first point and point count [256 | 16]: kPlF, kPlC.
 // Called by every thread of a block of at least 256 (the first 256 take
-// part); sw: 640 ints of LDS.
+// part); sw: 704 ints of LDS.
 __device__ void walk_plan(const NodeView& nd, int32_t* sw) {
   const int t = threadIdx.x;
   int32_t w16 = -1, x16 = 0, f16 = 0;
@@ -404,11 +404,32 @@ __device__ void walk_plan(const NodeView& nd, int32_t* sw) {
     }
     sw[t] = w16;
   }
+  // launch order: rows bucketed by the bit length of their node's point
+  // count, longest first (any order is correct; the order within a bucket is
+  // whatever the atomics give); sw[320..] holds 33 + 33 bucket counts, then
+  // the heavy wavefronts by launch rank
+  int32_t* bc = sw + 320;   // [33] spread, [33] unspread: counts, then cursors
+  int32_t* hc = sw + 400;   // [256] spread, [16] unspread
+  if (t < 66) bc[t] = 0;
   __syncthreads();
-  int32_t* hc = sw + 320;  // heavy wavefronts by launch rank: [256] spread, [16] unspread
+  const int bk16 = w16 > 0 ? 32 - __clz(w16) : 0;  // 0: no points (last)
+  int bk1 = 0;
+  if (t < kParts * kParts) atomicAdd(&bc[32 - bk16], 1);
+  if (t < kParts) {
+    const int32_t w1 = sw[256 + t];
+    bk1 = w1 > 0 ? 32 - __clz(w1) : 0;
+    atomicAdd(&bc[33 + 32 - bk1], 1);
+  }
+  __syncthreads();
+  if (t == 0) {
+    int32_t a = 0;
+    for (int i = 0; i < 33; ++i) { const int32_t c = bc[i]; bc[i] = a; a += c; }
+    a = 0;
+    for (int i = 33; i < 66; ++i) { const int32_t c = bc[i]; bc[i] = a; a += c; }
+  }
+  __syncthreads();
   if (t < kParts * kParts) {
-    int r = 0;
-    for (int u = 0; u < kParts * kParts; ++u) r += sw[u] > w16 || (sw[u] == w16 && u < t);
+    const int r = atomicAdd(&bc[32 - bk16], 1);
     nd.plan[kPlP + r] = t;
     nd.plan[kPlX + t] = x16;
     nd.plan[kPlF + t] = f16;
@@ -417,8 +438,7 @@ __device__ void walk_plan(const NodeView& nd, int32_t* sw) {
   }
   if (t < kParts) {
     const int32_t w1 = sw[256 + t];
-    int r = 0;
-    for (int u = 0; u < kParts; ++u) r += sw[256 + u] > w1 || (sw[256 + u] == w1 && u < t);
+    const int r = atomicAdd(&bc[33 + 32 - bk1], 1);
     nd.plan[kPlP + 256 + r] = t;
     nd.plan[kPlX + 256 + t] = sw[272 + t];
     nd.plan[kPlF + 256 + t] = sw[288 + t];
@@ -426,13 +446,30 @@ __device__ void walk_plan(const NodeView& nd, int32_t* sw) {
     hc[256 + r] = w1 > 0 ? (w1 + kHeavyPts - 1) / kHeavyPts : 0;
   }
   __syncthreads();
-  if (t == 0) {
-    int32_t a = 0;
-    for (int r = 0; r < kParts * kParts; ++r) { nd.plan[kPlH + r] = a; a += hc[r]; }
-    nd.plan[kPlH + 256] = a;
-    a = 0;
-    for (int r = 0; r < kParts; ++r) { nd.plan[kPlH + 257 + r] = a; a += hc[256 + r]; }
-    nd.plan[kPlH + 257 + 16] = a;
+  // exclusive prefix of the heavy wavefronts by launch rank: one wavefront,
+  // four ranks per lane (spread), and lanes 0..15 (unspread)
+  if (t < 64) {
+    const int32_t h0 = hc[4 * t], h1 = hc[4 * t + 1], h2 = hc[4 * t + 2], h3 = hc[4 * t + 3];
+    const int32_t tot = h0 + h1 + h2 + h3;
+    int32_t inc = tot;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t u = __shfl_up(inc, off, 64);
+      if (t >= off) inc += u;
+    }
+    const int32_t ex = inc - tot;
+    nd.plan[kPlH + 4 * t] = ex;
+    nd.plan[kPlH + 4 * t + 1] = ex + h0;
+    nd.plan[kPlH + 4 * t + 2] = ex + h0 + h1;
+    nd.plan[kPlH + 4 * t + 3] = ex + h0 + h1 + h2;
+    if (t == 63) nd.plan[kPlH + 256] = inc;
+    const int32_t g = t < kParts ? hc[256 + t] : 0;
+    int32_t inc1 = g;
+    for (int off = 1; off < kParts; off <<= 1) {
+      const int32_t u = __shfl_up(inc1, off, 64);
+      if (t >= off) inc1 += u;
+    }
+    if (t < kParts) nd.plan[kPlH + 257 + t] = inc1 - g;
+    if (t == kParts - 1) nd.plan[kPlH + 257 + kParts] = inc1;
   }
 }
 
@@ -594,7 +631,7 @@ __global__ __launch_bounds__(kMomT) void k_moments_sub(int32_t k, const float* x
 __global__ __launch_bounds__(kParts * kParts) void k_moments_top(NodeView nd) {
   {
     // the nodes, counts and children lists are final here
-    __shared__ int32_t sw[640];
+    __shared__ int32_t sw[704];
     walk_plan(nd, sw);
   }
   if ((nd.t[0].b.w >> 8) & 1) return;
@@ -1158,7 +1195,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     }
     __syncthreads();
   }
-  __shared__ int32_t sw_plan[640];
+  __shared__ int32_t sw_plan[704];
   walk_plan(nd, sw_plan);
 }
 
