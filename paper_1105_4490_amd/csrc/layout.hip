@@ -156,16 +156,34 @@ __device__ __forceinline__ void grid_coords(const float4* x, int64_t v, const ui
   grid_coords_of(x[v], box, kq);
 }
 
+// Bit b of x (b < 16) to bit 4b, and back (shift-and-mask stages).
+__device__ __forceinline__ uint64_t spread4(uint32_t x) {
+  uint64_t v = x & 0xffffu;
+  v = (v | (v << 24)) & 0x000000ff000000ffull;
+  v = (v | (v << 12)) & 0x000f000f000f000full;
+  v = (v | (v << 6)) & 0x0303030303030303ull;
+  v = (v | (v << 3)) & 0x1111111111111111ull;
+  return v;
+}
+__device__ __forceinline__ uint32_t compact4(uint64_t v) {
+  v &= 0x1111111111111111ull;
+  v = (v | (v >> 3)) & 0x0303030303030303ull;
+  v = (v | (v >> 6)) & 0x000f000f000f000full;
+  v = (v | (v >> 12)) & 0x000000ff000000ffull;
+  v = (v | (v >> 24)) & 0xffffull;
+  return (uint32_t)v;
+}
 // Morton key: digit at depth L (1..16) = bits (16-L) of the four coordinates,
-// dimension 0 most significant; depth-1 digit in the top nibble.
+// dimension 0 most significant; depth-1 digit in the top nibble (bit b of
+// coordinate d at bit 4b + 3 - d).
+__device__ __forceinline__ uint64_t morton4(const uint32_t* kq) {
+  return (spread4(kq[0]) << 3) | (spread4(kq[1]) << 2) | (spread4(kq[2]) << 1) | spread4(kq[3]);
+}
 __global__ void k_tree_keys(const float4* x, int32_t k, const uint32_t* box, uint64_t* key, int32_t* val) {
   GRID_STRIDE(v, k) {
     uint32_t kq[4];
     grid_coords(x, v, box, kq);
-    uint64_t m = 0;
-    for (int b = 15; b >= 0; --b)
-      for (int d = 0; d < 4; ++d) m = (m << 1) | ((kq[d] >> b) & 1u);
-    key[v] = m;
+    key[v] = morton4(kq);
     val[v] = (int32_t)v;
   }
 }
@@ -742,11 +760,7 @@ constexpr int kSTB = 1024;
 constexpr int kSmallK = 4096;
 
 // grid coordinate of dimension d back from a Morton key (inverse of k_tree_keys)
-__device__ __forceinline__ int32_t key_coord(uint64_t m, int d) {
-  int32_t a = 0;
-  for (int b = 15; b >= 0; --b) a |= (int32_t)((m >> (4 * b + 3 - d)) & 1u) << b;
-  return a;
-}
+__device__ __forceinline__ int32_t key_coord(uint64_t m, int d) { return (int32_t)compact4(m >> (3 - d)); }
 
 __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ x, const float* __restrict__ w,
                                                      int32_t k, int32_t cap, uint32_t* __restrict__ box,
@@ -818,10 +832,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     if (v >= k) break;
     uint32_t kq[4];
     grid_coords_of(xr[r], sbox, kq);
-    uint64_t m = 0;
-    for (int b = 15; b >= 0; --b)
-      for (int d = 0; d < 4; ++d) m = (m << 1) | ((kq[d] >> b) & 1u);
-    key[v] = m;
+    key[v] = morton4(kq);
     val[v] = v;
   }
   __syncthreads();
