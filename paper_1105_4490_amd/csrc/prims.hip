@@ -467,8 +467,8 @@ template void scan_exclusive<U128>(Ctx&, const U128*, U128*, int64_t, U128*, hip
 // ready), an aggregate of that tile alone, or an inclusive prefix.  Earlier
 // tiles belong to blocks that already run, so every wait ends; the wait is
 // still bounded, and a bound that runs out sets the context's device error
-// flag.  A tile is `ri` rounds of 256 keys, ri chosen so that large inputs
-// give about 512 tiles.
+// flag.  A tile is `ri` rounds of 256 keys; the tile count is tuned online
+// per size (radix_sort).
 constexpr int kRsT = 256, kRsMaxI = 16;
 constexpr uint64_t kStA = 1ull << 62, kStP = 2ull << 62, kStMask = (1ull << 62) - 1;
 constexpr int kSpinLimit = 1 << 24;
@@ -491,7 +491,10 @@ __global__ __launch_bounds__(kRsT) void k_rs_hist(const K* __restrict__ keys, in
 
 // RI: rounds per tile (a power of two up to kRsMaxI); the LDS counts and the
 // key registers are sized for it, so that short tiles leave room for more
-// blocks per CU.
+// blocks per CU.  Loads that do not depend on each other are issued together:
+// the scan of the pass's digit totals runs while the tile number is fetched,
+// the values are loaded with the keys, and the look-back reads four earlier
+// tiles' words at a time.
 template <class K, int RI>
 __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, const int32_t* __restrict__ vin,
                                                      K* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
@@ -505,14 +508,34 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
   __shared__ int tile_sh;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (t == 0) tile_sh = (int)atomicAdd(tile_ctr, 1u);
+  // exclusive scan of the digit totals of this pass (the same for every
+  // tile): within each wavefront by shuffles, then the earlier wavefronts'
+  // totals
+  const int g = (int)ghist[t];
+  int inc = g;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += u;
+  }
+  if (lane == 63) wsum[w] = inc;
   uint32_t* cnt32 = reinterpret_cast<uint32_t*>(&cnt[0][0][0]);
   for (int e = t; e < ri * (kRsT / 64) * 256 / 2; e += kRsT) cnt32[e] = 0u;
   __syncthreads();
+  int pre = inc - g;
+  for (int ww = 0; ww < w; ++ww) pre += wsum[ww];
   const int64_t tile = tile_sh;
   const int64_t base = tile * kRsT * ri;
   const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
   K key[RI];
+  int32_t val[RI];
   int dig[RI], rk[RI];
+#pragma unroll
+  for (int r = 0; r < RI; ++r) {
+    const int64_t idx = base + (int64_t)r * kRsT + t;
+    const bool valid = idx < n;
+    key[r] = valid ? kin[idx] : K(0);
+    val[r] = valid && vin ? vin[idx] : 0;
+  }
   // ranks of every round at once: lanes of a wavefront with equal digits are
   // found by eight ballots; each (round, wavefront, digit) count is written by
   // the first such lane
@@ -520,7 +543,6 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
   for (int r = 0; r < RI; ++r) {
     const int64_t idx = base + (int64_t)r * kRsT + t;
     const bool valid = idx < n;
-    key[r] = valid ? kin[idx] : K(0);
     dig[r] = valid ? (int)((key[r] >> shift) & 255u) : -1;
     const int d = valid ? dig[r] : 0;
     uint64_t m = __ballot(valid);
@@ -543,7 +565,8 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
       c += v;
     }
   // publish this tile's count of digit t, then look back for the keys of
-  // digit t in earlier tiles
+  // digit t in earlier tiles: up to four words per round trip, taken in
+  // order from the nearest; a word not yet written ends the round there
   uint64_t* st = status + tile * 256 + t;
   uint64_t excl = 0;
   if (tile == 0) {
@@ -553,34 +576,35 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
     int64_t pt = tile - 1;
     int spins = 0;
     while (true) {
-      const uint64_t v = __hip_atomic_load(status + pt * 256 + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const uint64_t f = v & ~kStMask;
-      if (f == 0) {
+      uint64_t v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v[q] = pt - q >= 0 ? __hip_atomic_load(status + (pt - q) * 256 + t, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)
+                           : kStP;  // not reached: tile 0's word is an inclusive prefix
+      int q = 0;
+      bool done = false;
+      for (; q < 4; ++q) {
+        const uint64_t f = v[q] & ~kStMask;
+        if (f == 0) break;
+        excl += v[q] & kStMask;
+        if (f == kStP) {
+          done = true;
+          break;
+        }
+      }
+      if (done) break;
+      pt -= q;
+      if (q < 4) {
         if (++spins > kSpinLimit) {
           atomicExch(err, 1);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      excl += v & kStMask;
-      if (f == kStP || pt == 0) break;
-      --pt;
     }
     __hip_atomic_store(st, kStP | (excl + (uint64_t)c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  // exclusive scan of the digit totals of this pass: within each wavefront by
-  // shuffles, then the totals of the earlier wavefronts
-  const int g = (int)ghist[t];
-  int inc = g;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int u = __shfl_up(inc, off, 64);
-    if (lane >= off) inc += u;
-  }
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  int pre = inc - g;
-  for (int ww = 0; ww < w; ++ww) pre += wsum[ww];
   run[t] = (int)(pre + excl);
   __syncthreads();
 #pragma unroll
@@ -589,7 +613,7 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const K* __restrict__ kin, 
     const int d = dig[r];
     const int dest = run[d] + cnt[r][w][d] + rk[r];
     kout[dest] = key[r];
-    if (vin) vout[dest] = vin[base + (int64_t)r * kRsT + t];
+    if (vin) vout[dest] = val[r];
   }
 }
 
@@ -619,10 +643,10 @@ void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t
   const int passes = (bits + 7) / 8;
   // tiles of ri rounds: the target tile count is tuned online per size bucket
   // (fewer tiles: shorter look-back chains; more: more blocks in flight)
-  static const int kTarget[4] = {64, 128, 256, 512};
+  static const int kTarget[6] = {4, 16, 64, 128, 256, 512};
   const int bucket = bits_for((uint64_t)n);
   bool tuned = false;
-  const int cfg = n > (int64_t)64 * kRsT ? tune_pick(c, kTuneSort, bucket, 4, &tuned) : 3;
+  const int cfg = n > (int64_t)4 * kRsT ? tune_pick(c, kTuneSort, bucket, 6, &tuned) : 5;
   int ri = 1;
   while (ri < kRsMaxI && n > (int64_t)kTarget[cfg] * kRsT * ri) ri *= 2;
   if (tuned) tune_begin_host(c, kTuneSort, bucket, cfg, (double)n * passes, s);
