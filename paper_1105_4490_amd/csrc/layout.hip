@@ -777,10 +777,9 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
   }
   __shared__ uint64_t key[kSmallK];
   __shared__ __align__(16) unsigned char rb[32768];
-  // per (round, wavefront, digit) counts of the sort, then their offsets
+  // 32 KB: the second buffer of the merge sort, later the next links and
+  // the FP64 charges of small trees
   __shared__ uint16_t cnt[4][16][256];
-  __shared__ int32_t run[256];
-  __shared__ int32_t rtot[4][256];
   // during the sort
   int32_t* val = reinterpret_cast<int32_t*>(rb);                // [4096]
   // after the sort
@@ -882,96 +881,125 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     __syncthreads();
   }
 
-  // stable LSD radix sort, 8-bit digits.  Item r of thread t is position
-  // r * 1024 + t.  Each pass ranks all four rounds at once: lanes of a wave
-  // with equal digits are found by ballots, the (round, wave, digit) counts
-  // are turned into offsets by one scan per digit in (round, wave) order, and
-  // the digit bases by a scan over the digits: a stable order.
-  const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
-  uint32_t* cnt32 = reinterpret_cast<uint32_t*>(&cnt[0][0][0]);
-  const int rounds = (k + kSTB - 1) / kSTB;  // rounds holding items (uniform)
-  for (int pass = 0; pass < (k <= kSTB ? 0 : 8); ++pass) {
-    const int sh = 8 * pass;
-    uint64_t mk[4];
-    int32_t mv[4];
-    int md[4], rk[4];
+  if (k > kSTB) {
+    // Runs of 256 positions sorted by one wavefront each in registers (a
+    // bitonic network; lane l holds positions 4l..4l+3 of its run), then
+    // merged pairwise in LDS until one run remains; each merge step gives a
+    // thread four consecutive outputs, found by a merge-path search.  The
+    // (key, index) pairs are all distinct, so the result is the stable order
+    // by key.  N = 2048 or 4096 positions; those from k on hold
+    // (2^64 - 1, INT_MAX), which sorts after every point.
+    int N = 2 * kSTB;
+    while (N < k) N <<= 1;
+    const int merges = N == 2 * kSTB ? 3 : 4;  // log2(N / 256)
+    uint64_t* kX = key;
+    int32_t* vX = val;
+    uint64_t* kY = reinterpret_cast<uint64_t*>(&cnt[0][0][0]);  // [4096]
+    int32_t* vY = reinterpret_cast<int32_t*>(rb + 16384);       // [4096]
+    auto less = [](uint64_t ka, int32_t va, uint64_t kb, int32_t vb) {
+      return ka < kb || (ka == kb && va < vb);
+    };
+    if (wv < N / 256) {
+      uint64_t mk[4];
+      int32_t mv[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = r * kSTB + t;
-      const bool ok = i < k;
-      mk[r] = ok ? key[i] : 0ull;
-      mv[r] = ok ? val[i] : 0;
-      md[r] = ok ? (int)((mk[r] >> sh) & 255u) : -1;
-    }
-    for (int e = t; e < rounds * 16 * 256 / 2; e += kSTB) cnt32[e] = 0u;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (r >= rounds) break;
-      const bool valid = md[r] >= 0;
-      const int d = valid ? md[r] : 0;
-      uint64_t m = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1;
-        const uint64_t bb = __ballot(valid && bit);
-        m &= bit ? bb : ~bb;
+      for (int q = 0; q < 4; ++q) {
+        const int p = 256 * wv + 4 * lane + q;
+        mk[q] = p < k ? key[p] : ~0ull;
+        mv[q] = p < k ? val[p] : 0x7fffffff;
       }
-      rk[r] = __popcll(m & below);
-      if (valid && rk[r] == 0) cnt[r][wv][d] = (uint16_t)__popcll(m);
-    }
-    __syncthreads();
-    {
-      // digit d = t % 256, round r = t / 256: exclusive offsets over the
-      // waves of round r, then the totals of the earlier rounds are added
-      const int d = t & 255, r = t >> 8;
-      int acc = 0;
-      int cv[16];  // the counts of (r, every wave, d), read before any write
-      if (r < rounds) {
+      for (int kk = 2; kk <= 256; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+          if (j >= 4) {
+            // partner position p ^ j is lane l ^ (j / 4), same slot
 #pragma unroll
-        for (int ww = 0; ww < 16; ++ww) cv[ww] = cnt[r][ww][d];
-#pragma unroll
-        for (int ww = 0; ww < 16; ++ww) acc += cv[ww];
-      }
-      rtot[r][d] = acc;
-      __syncthreads();
-      int pre = 0;
-      for (int r2 = 0; r2 < r; ++r2) pre += rtot[r2][d];
-      if (r < rounds) {
-        int a = pre;
-#pragma unroll
-        for (int ww = 0; ww < 16; ++ww) {
-          cnt[r][ww][d] = (uint16_t)a;
-          a += cv[ww];
+            for (int q = 0; q < 4; ++q) {
+              const int p = 4 * lane + q;
+              const uint32_t lo = __shfl_xor((uint32_t)mk[q], j >> 2, 64);
+              const uint32_t hi = __shfl_xor((uint32_t)(mk[q] >> 32), j >> 2, 64);
+              const uint64_t ok = ((uint64_t)hi << 32) | lo;
+              const int32_t ov = __shfl_xor(mv[q], j >> 2, 64);
+              // the lower position of a pair keeps the smaller pair in
+              // ascending runs ((p & kk) == 0), the larger in descending ones
+              const bool keep_min = ((p & j) == 0) == ((p & kk) == 0);
+              if (less(ok, ov, mk[q], mv[q]) == keep_min) {
+                mk[q] = ok;
+                mv[q] = ov;
+              }
+            }
+          } else {
+            // partners in the same lane: slots (q, q | j)
+            auto cas = [&](int q, int q2) {
+              const bool asc = ((4 * lane + q) & kk) == 0;
+              const bool sw = asc ? less(mk[q2], mv[q2], mk[q], mv[q]) : less(mk[q], mv[q], mk[q2], mv[q2]);
+              if (sw) {
+                const uint64_t tk = mk[q];
+                const int32_t tv = mv[q];
+                mk[q] = mk[q2];
+                mv[q] = mv[q2];
+                mk[q2] = tk;
+                mv[q2] = tv;
+              }
+            };
+            if (j == 2) {
+              cas(0, 2);
+              cas(1, 3);
+            } else {
+              cas(0, 1);
+              cas(2, 3);
+            }
+          }
         }
       }
-      if (r == 3) run[d] = pre + acc;
-    }
-    __syncthreads();
-    if (t < 64) {
-      // exclusive scan of the 256 digit counts by one wavefront, 4 per lane
-      const int h0 = run[4 * t], h1 = run[4 * t + 1], h2 = run[4 * t + 2], h3 = run[4 * t + 3];
-      const int tot = h0 + h1 + h2 + h3;
-      int inc = tot;
-      for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(inc, off, 64);
-        if (t >= off) inc += u;
-      }
-      const int ex = inc - tot;
-      run[4 * t] = ex;
-      run[4 * t + 1] = ex + h0;
-      run[4 * t + 2] = ex + h0 + h1;
-      run[4 * t + 3] = ex + h0 + h1 + h2;
-    }
-    __syncthreads();
+      // an odd number of merges ends in the other buffer: start there
+      uint64_t* kd = (merges & 1) ? kY : kX;
+      int32_t* vd = (merges & 1) ? vY : vX;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (md[r] < 0) continue;
-      const int dst = run[md[r]] + cnt[r][wv][md[r]] + rk[r];
-      key[dst] = mk[r];
-      val[dst] = mv[r];
+      for (int q = 0; q < 4; ++q) {
+        const int p = 256 * wv + 4 * lane + q;
+        kd[p] = mk[q];
+        vd[p] = mv[q];
+      }
     }
     __syncthreads();
+    uint64_t* ks = (merges & 1) ? kY : kX;
+    int32_t* vs = (merges & 1) ? vY : vX;
+    uint64_t* kt = (merges & 1) ? kX : kY;
+    int32_t* vt = (merges & 1) ? vX : vY;
+    for (int R = 256; R < N; R <<= 1) {
+      const int o = 4 * t;  // N <= 4 * kSTB
+      if (o < N) {
+        const int a0 = o & ~(2 * R - 1), d = o - a0;
+        const uint64_t* kA = ks + a0;
+        const int32_t* vA = vs + a0;
+        const uint64_t* kB = kA + R;
+        const int32_t* vB = vA + R;
+        // i = the number of the run A's pairs among the first d outputs
+        int lo = d - R > 0 ? d - R : 0, hi = d < R ? d : R;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (less(kA[mid], vA[mid], kB[d - 1 - mid], vB[d - 1 - mid])) lo = mid + 1;
+          else hi = mid;
+        }
+        int i = lo, j = d - lo;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool fromA = j >= R || (i < R && less(kA[i], vA[i], kB[j], vB[j]));
+          if (fromA) {
+            kt[o + u] = kA[i];
+            vt[o + u] = vA[i];
+            ++i;
+          } else {
+            kt[o + u] = kB[j];
+            vt[o + u] = vB[j];
+            ++j;
+          }
+        }
+      }
+      __syncthreads();
+      uint64_t* k2 = ks; ks = kt; kt = k2;
+      int32_t* v2 = vs; vs = vt; vt = v2;
+    }
   }
 
   // points in tree order (the four rounds unrolled)
