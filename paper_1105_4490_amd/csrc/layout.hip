@@ -596,13 +596,21 @@ __device__ __forceinline__ void child_sums(NodeView nd, int32_t p, int32_t nc, d
 // the way when i1..i3 below it are zero, and forms its charges bottom-up:
 // leaves first, then the internal nodes depth by depth, deepest first, with a
 // barrier between depths.  k_moments_top then forms the charges of the
-// internal nodes of depths 2, 1 and 0.  The sums and their order are those of
+// internal nodes of depths 2, 1 and 0 (and one more workgroup of the first
+// launch forms the walk's launch plan).  The sums and their order are those of
 // the one-block build: a leaf sums its points in tree order, an internal node
 // its children's charges in child order, in FP64.
 constexpr int kMomT = 256;
-constexpr int kMomD = 3;  // depth of the subtree roots
+constexpr int kMomD = 3;          // depth of the subtree roots
+constexpr int kMomList = 4096;    // internal nodes listed in LDS
 __global__ __launch_bounds__(kMomT) void k_moments_sub(int32_t k, const float* xs, const float* ws, NodeView nd) {
-  __shared__ int maxd;
+  if (blockIdx.x == kParts * kParts * kParts) {
+    // the extra block: the walk's launch plan (nodes, counts and children
+    // lists are final here; the plan needs no charges)
+    __shared__ int32_t sw[704];
+    walk_plan(nd, sw);
+    return;
+  }
   const int idx[kMomD] = {(int)blockIdx.x / (kParts * kParts), (int)(blockIdx.x / kParts) % kParts,
                           (int)blockIdx.x % kParts};
   int32_t r = 0;
@@ -616,9 +624,13 @@ __global__ __launch_bounds__(kMomT) void k_moments_sub(int32_t k, const float* x
     r = nd.cid[16 * (int64_t)r + idx[lv]];
   }
   const int32_t lo = r, hi = nd.t[r].b.x;
-  if (threadIdx.x == 0) maxd = -1;
+  // the range's internal nodes are counted by depth while the leaves are
+  // summed, then listed by depth in LDS (when they fit), so that each depth
+  // of the bottom-up pass visits its own nodes only
+  __shared__ int32_t dcnt[18], doff[18];
+  __shared__ int32_t dl[kMomList];
+  if (threadIdx.x < 18) dcnt[threadIdx.x] = 0;
   __syncthreads();
-  int md = -1;
   for (int32_t t = lo + threadIdx.x; t < hi; t += kMomT) {
     const int4 b = nd.t[t].b;
     if ((b.w >> 8) & 1) {
@@ -626,32 +638,54 @@ __global__ __launch_bounds__(kMomT) void k_moments_sub(int32_t k, const float* x
       leaf_sums(b.y, b.z, k, xs, ws, Wd, Sd);
       node_finish(nd, t, Wd, Sd);
     } else {
-      md = max(md, b.w & 255);
+      atomicAdd(&dcnt[b.w & 255], 1);
     }
   }
-  if (md >= 0) atomicMax(&maxd, md);
   __syncthreads();
-  const int top = maxd;  // deepest internal node of the range (uniform)
+  if (threadIdx.x == 0) {
+    int32_t a = 0;
+    for (int L = 0; L <= 16; ++L) {
+      doff[L] = a;
+      a += dcnt[L];
+      dcnt[L] = doff[L];  // the cursors of the lists
+    }
+    doff[17] = a;
+  }
+  __syncthreads();
   const int L0 = nd.t[lo].b.w & 255;
-  for (int L = top; L >= L0; --L) {
+  if (doff[17] <= kMomList) {
     for (int32_t t = lo + threadIdx.x; t < hi; t += kMomT) {
-      const int4 b = nd.t[t].b;
-      if ((b.w & 0x1ff) != L) continue;  // internal (leaf bit clear) at depth L
-      double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
-      child_sums(nd, t, nd.nch[t], Wd, Sd);
-      node_finish(nd, t, Wd, Sd);
+      const int w = nd.t[t].b.w;
+      if (!((w >> 8) & 1)) dl[atomicAdd(&dcnt[w & 255], 1)] = t;
     }
     __syncthreads();
+    for (int L = 16; L >= L0; --L) {
+      if (doff[L] == doff[L + 1]) continue;  // uniform: doff is in LDS
+      for (int32_t e = doff[L] + threadIdx.x; e < doff[L + 1]; e += kMomT) {
+        const int32_t t = dl[e];
+        double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+        child_sums(nd, t, nd.nch[t], Wd, Sd);
+        node_finish(nd, t, Wd, Sd);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int L = 16; L >= L0; --L) {
+      if (doff[L] == doff[L + 1]) continue;
+      for (int32_t t = lo + threadIdx.x; t < hi; t += kMomT) {
+        const int4 b = nd.t[t].b;
+        if ((b.w & 0x1ff) != L) continue;  // internal (leaf bit clear) at depth L
+        double Wd = 0.0, Sd[4] = {0.0, 0.0, 0.0, 0.0};
+        child_sums(nd, t, nd.nch[t], Wd, Sd);
+        node_finish(nd, t, Wd, Sd);
+      }
+      __syncthreads();
+    }
   }
 }
 
 // Internal nodes of depths 2, 1, 0 (one block of kParts^2 threads).
 __global__ __launch_bounds__(kParts * kParts) void k_moments_top(NodeView nd) {
-  {
-    // the nodes, counts and children lists are final here
-    __shared__ int32_t sw[704];
-    walk_plan(nd, sw);
-  }
   if ((nd.t[0].b.w >> 8) & 1) return;
   const int i1 = threadIdx.x / kParts, i2 = threadIdx.x % kParts;
   const int n1 = min(nd.nch[0], kParts);
@@ -1312,7 +1346,7 @@ static void build_tree(Ctx& C, Tree& T, const float4* x, const float* w, int32_t
   // (below 2 k), grid-stride loops up to the count
   const int32_t* n_dev = T.nn.p + k;
   VMO_LAUNCH(k_tree_links, gsz(2 * (int64_t)k), kLT, 0, s, n_dev, nd);
-  VMO_LAUNCH(k_moments_sub, kParts * kParts * kParts, kMomT, 0, s, k, T.xs.p, T.ws.p, nd);
+  VMO_LAUNCH(k_moments_sub, kParts * kParts * kParts + 1, kMomT, 0, s, k, T.xs.p, T.ws.p, nd);
   VMO_LAUNCH(k_moments_top, 1, kParts * kParts, 0, s, nd);
 }
 

@@ -413,9 +413,12 @@ __global__ __launch_bounds__(kScanT) void k_scan_reduce(const T* __restrict__ in
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// part: NULL (one tile), the tiles' exclusive offsets (sum_parts == 0), or
+// the tiles' totals (sum_parts != 0), whose sum over the earlier tiles each
+// block forms itself (integer sums: any order gives the same offset)
 template <class T>
 __global__ __launch_bounds__(kScanT) void k_scan_down(const T* in, T* out, int64_t n, const T* part,
-                                                      T* total, int last_block) {
+                                                      int sum_parts, T* total, int last_block) {
   __shared__ T sh[kScanT];
   int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
   T v[kScanI];
@@ -425,9 +428,17 @@ __global__ __launch_bounds__(kScanT) void k_scan_down(const T* in, T* out, int64
     v[i] = base + i < n ? in[base + i] : tzero<T>();
     s = tadd(s, v[i]);
   }
+  T off = tzero<T>();
+  if (part && sum_parts) {
+    T o = tzero<T>();
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanT) o = tadd(o, part[i]);
+    (void)block_excl(o, sh, &off);
+  } else if (part) {
+    off = part[blockIdx.x];
+  }
   T tot;
   T ex = block_excl(s, sh, &tot);
-  T run = part ? tadd(part[blockIdx.x], ex) : ex;
+  T run = tadd(off, ex);
 #pragma unroll
   for (int i = 0; i < kScanI; ++i) {
     if (base + i < n) out[base + i] = run;
@@ -444,13 +455,19 @@ void scan_exclusive(Ctx& c, const T* in, T* out, int64_t n, T* total, hipStream_
   }
   int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 1) {
-    VMO_LAUNCH((k_scan_down<T>), 1, kScanT, 0, s, in, out, n, (const T*)nullptr, total, 0);
+    VMO_LAUNCH((k_scan_down<T>), 1, kScanT, 0, s, in, out, n, (const T*)nullptr, 0, total, 0);
     return;
   }
   Buf<T> part(c.pool, nb);
   VMO_LAUNCH((k_scan_reduce<T>), (unsigned)nb, kScanT, 0, s, in, n, part.p);
+  if (nb <= kScanTile) {
+    // few tiles: each block adds up the earlier tiles' totals itself
+    VMO_LAUNCH((k_scan_down<T>), (unsigned)nb, kScanT, 0, s, in, out, n, (const T*)part.p, 1, total,
+               (int)(nb - 1));
+    return;
+  }
   scan_exclusive<T>(c, part.p, part.p, nb, total, s);
-  VMO_LAUNCH((k_scan_down<T>), (unsigned)nb, kScanT, 0, s, in, out, n, (const T*)part.p, (T*)nullptr, 0);
+  VMO_LAUNCH((k_scan_down<T>), (unsigned)nb, kScanT, 0, s, in, out, n, (const T*)part.p, 0, (T*)nullptr, 0);
 }
 
 template void scan_exclusive<int32_t>(Ctx&, const int32_t*, int32_t*, int64_t, int32_t*, hipStream_t);
