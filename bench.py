@@ -586,6 +586,17 @@ def bench_serve(args, ctx, field=False):
         "busy_ms": st["busy_ms"], "ticks": st["ticks"], "max_tick_jobs": st["max_tick_jobs"],
         "mean_tick_jobs": st["tick_jobs"] / max(st["ticks"], 1), "layout_bytes_peak": st["layout_bytes_peak"],
     }
+    # the same jobs one at a time through the plain call, back to back: the
+    # rate serving is measured against
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for jb, _, _ in jobs:
+        ctx.order(jb["h"], None, jb["P"], SEED, mode=jb["mode"], order=jb["order"], lp=lp)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t
+    line["sequential"] = {"nnz_per_s": total / seq_s, "s": seq_s,
+                          "what": "the same jobs one at a time through the plain call (layout + order)"}
+    line["served_over_sequential"] = capacity * seq_s / total
     if not args.no_stable and capacity < line["offered_nnz_per_s"]:
         # the same jobs again as a Poisson stream at half the measured capacity
         rate = 0.5 * capacity / (total / len(jobs))
@@ -599,7 +610,8 @@ def bench_serve(args, ctx, field=False):
         line["scaled"] = f"{len(jobs)} requests of the 3,000-request stream"
         return {k: line[k] for k in ("metric", "value", "unit", "config", "latency_ms", "offered_nnz_per_s",
                                      "busy_ms", "ticks", "max_tick_jobs", "mean_tick_jobs", "layout_bytes_peak",
-                                     "scaled") + (("stable",) if "stable" in line else ())}
+                                     "sequential", "served_over_sequential", "scaled")
+                + (("stable",) if "stable" in line else ())}
     print(json.dumps(line))
 
 
