@@ -2771,7 +2771,8 @@ void tree(Ctx& C, const float* x, const float* w, int32_t k, int32_t cap, int32_
   VMO_LAUNCH(k_to_rec, gsz(k), kLT, 0, s, x, k, xr.p);
   box_of(xr.p, k, box.p, s);
   Tree T;
-  build_tree(C, T, xr.p, w, k, cap, box.p, 0.25, s, false);
+  // the same builds as the layout's: one workgroup up to kSmallK points
+  build_tree(C, T, xr.p, w, k, cap, box.p, 0.25, s);
   const int32_t n = read1(T.nn.p + k, s);
   VMO_REQUIRE(n <= max_nodes, "max_nodes is too small");
   VMO_LAUNCH(k_tree_out, gsz(n), kLT, 0, s, n, T.view(), ints, cell2, flt);

@@ -34,7 +34,12 @@ def tree_points(k, seed):
     return x
 
 
-@pytest.mark.parametrize("k,seed,cap", [(1, 1, 8), (7, 2, 8), (500, 3, 8), (5000, 4, 1), (30011, 5, 4), (100000, 6, 8)])
+# k <= 1,024: the one-workgroup build's bitonic sort; 1,025..4,096: its
+# wavefront runs merged in LDS (three merges up to 2,048 points, four above);
+# larger: the multi-kernel build
+@pytest.mark.parametrize("k,seed,cap", [(1, 1, 8), (7, 2, 8), (500, 3, 8), (1024, 7, 8), (1025, 8, 4), (2048, 9, 8),
+                                        (2049, 10, 1), (3001, 11, 8), (4096, 12, 8), (4097, 13, 8), (5000, 4, 1),
+                                        (30011, 5, 4), (100000, 6, 8)])
 def test_tree(ctx, k, seed, cap):
     x = tree_points(k, seed) if k > 40 else vmo_gen.random_points(k, seed)
     w = vmo_gen.rng(seed, 3).uniform(0.5, 2, size=k).astype(np.float32)
