@@ -379,12 +379,18 @@ struct NodeView {
 // The walk's launch plan.  A part row of the walk (the root's child i1 and,
 // spread, its child i2) has a node (that grandchild, or the child itself);
 // the points inside it walk its whole subtree and are the longest walks.  The
-// walk's grid first gives those points wavefronts of kHeavyPts (short unions,
+// walk's grid first gives those points wavefronts of heavy_pts(k) (short unions,
 // so the longest wavefronts shrink), rows with the most such points first,
 // then the rows' other points in wavefronts of 64, rows in the same order and
 // each row's blocks starting at its node's points.  Which wavefront walks which
 // row and points changes no point's walk or sums.
-constexpr int kHeavyPts = 40;
+// Points per heavy wavefront at a level of k points: few where the level's
+// walk is bound by its longest wavefronts (the chip is not full), up to a whole
+// wavefront where it fills the chip and shared unions save work (measured on
+// the 64^3 hierarchy's levels).
+__host__ __device__ constexpr int heavy_pts(int64_t k) {
+  return k < 5000 ? 4 : k < 20000 ? 8 : k < 60000 ? 16 : k < 100000 ? 24 : k < 200000 ? 40 : 64;
+}
 // plan layout (ints): spread rows (256) then unspread rows (16) of each table
 constexpr int kPlP = 0, kPlX = 272, kPlH = 544, kPlF = 818, kPlC = 1090, kPlan = 1362;
 // rows in launch order [256 | 16]: kPlP; each row's first 64-point block
@@ -392,7 +398,7 @@ constexpr int kPlP = 0, kPlX = 272, kPlH = 544, kPlF = 818, kPlC = 1090, kPlan =
 // kPlH; each row's node's first point and point count [256 | 16]: kPlF, kPlC.
 // Called by every thread of a block of at least 256 (the first 256 take
 // part); sw: 704 ints of LDS.
-__device__ void walk_plan(const NodeView& nd, int32_t* sw) {
+__device__ void walk_plan(const NodeView& nd, int32_t* sw, int hpts) {
   const int t = threadIdx.x;
   int32_t w16 = -1, x16 = 0, f16 = 0;
   if (t < kParts * kParts) {
@@ -452,7 +458,7 @@ __device__ void walk_plan(const NodeView& nd, int32_t* sw) {
     nd.plan[kPlX + t] = x16;
     nd.plan[kPlF + t] = f16;
     nd.plan[kPlC + t] = w16 > 0 ? w16 : 0;
-    hc[r] = w16 > 0 ? (w16 + kHeavyPts - 1) / kHeavyPts : 0;
+    hc[r] = w16 > 0 ? (w16 + hpts - 1) / hpts : 0;
   }
   if (t < kParts) {
     const int32_t w1 = sw[256 + t];
@@ -461,7 +467,7 @@ __device__ void walk_plan(const NodeView& nd, int32_t* sw) {
     nd.plan[kPlX + 256 + t] = sw[272 + t];
     nd.plan[kPlF + 256 + t] = sw[288 + t];
     nd.plan[kPlC + 256 + t] = w1 > 0 ? w1 : 0;
-    hc[256 + r] = w1 > 0 ? (w1 + kHeavyPts - 1) / kHeavyPts : 0;
+    hc[256 + r] = w1 > 0 ? (w1 + hpts - 1) / hpts : 0;
   }
   __syncthreads();
   // exclusive prefix of the heavy wavefronts by launch rank: one wavefront,
@@ -608,7 +614,7 @@ __global__ __launch_bounds__(kMomT) void k_moments_sub(int32_t k, const float* x
     // the extra block: the walk's launch plan (nodes, counts and children
     // lists are final here; the plan needs no charges)
     __shared__ int32_t sw[704];
-    walk_plan(nd, sw);
+    walk_plan(nd, sw, heavy_pts(k));
     return;
   }
   const int idx[kMomD] = {(int)blockIdx.x / (kParts * kParts), (int)(blockIdx.x / kParts) % kParts,
@@ -1269,7 +1275,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     __syncthreads();
   }
   __shared__ int32_t sw_plan[704];
-  walk_plan(nd, sw_plan);
+  walk_plan(nd, sw_plan, heavy_pts(k));
 }
 
 struct Tree {
@@ -1512,7 +1518,7 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
   __shared__ float lw[NW][kWin];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // The row and the points of this block, from the launch plan (walk_plan):
-  // blocks below hblocks take kHeavyPts points of a row's node, the others
+  // blocks below hblocks take heavy_pts(k) points of a row's node, the others
   // 64 points of a row outside its node.
   const int R = kParts * spread, so = spread > 1 ? 0 : 256;
   const int64_t gb = blockIdx.x;
@@ -1529,8 +1535,9 @@ __global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restri
     }
     yrow = plan[kPlP + so + lo];
     const int64_t nf = plan[kPlF + so + yrow], nc = plan[kPlC + so + yrow];
-    j = nf + (gb - hp[lo]) * kHeavyPts + lane;
-    valid = lane < kHeavyPts && j < nf + nc;
+    const int hpts = heavy_pts(k);
+    j = nf + (gb - hp[lo]) * hpts + lane;
+    valid = lane < hpts && j < nf + nc;
   } else {
     const int64_t gx = ((int64_t)k + 63) / 64, bn = gb - hblocks;
     const int r = (int)(bn / gx);
@@ -1878,10 +1885,10 @@ static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, doub
     VMO_HIP(hipMemsetAsync(C.wslots, 0, sizeof(unsigned long long) * 16 * kCntSlots, s));
     if (ph >= 0) prof_restart(C, ph, s);
   }
-  // heavy wavefronts: at most one per kHeavyPts points plus one per row
+  // heavy wavefronts: at most one per heavy_pts(k) points plus one per row
   // (the rows' nodes are disjoint), then 64-point blocks for every row
   const int64_t rows = (int64_t)kParts * spread;
-  const int64_t hblocks = ((int64_t)L.k + kHeavyPts - 1) / kHeavyPts + rows;
+  const int64_t hblocks = ((int64_t)L.k + heavy_pts(L.k) - 1) / heavy_pts(L.k) + rows;
   const unsigned wgrid = (unsigned)(hblocks + nblocks(L.k, kWT) * rows);
   if (target)
     VMO_LAUNCH((k_walk<true>), wgrid, kWT, 0, s, L.k, gw.T.nn.p + L.k, gw.T.P.p, gw.T.ws.p, gw.T.p2.p, gw.T.nodes.p,
