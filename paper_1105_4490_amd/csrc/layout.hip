@@ -106,14 +106,6 @@ __global__ void k_box_init(uint32_t* box) {
 
 struct HostBox {
   float lo[4], hi[4];
-  double ext() const {
-    double e = 0.0;
-    for (int d = 0; d < 4; ++d) {
-      double a = (double)hi[d] - (double)lo[d];
-      if (a > e) e = a;
-    }
-    return e;
-  }
 };
 
 static void box_of(const float4* x, int32_t k, uint32_t* dbox, hipStream_t s) {
@@ -1746,7 +1738,8 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
                                                     const int32_t* __restrict__ p2, const TNode* __restrict__ nodes,
                                                     const int32_t* __restrict__ cid, const int32_t* __restrict__ nch,
                                                     int spread, const float* __restrict__ part, float4* y,
-                                                    float4* xmove, double alpha) {
+                                                    float4* xmove, double alpha, const double* __restrict__ alpha_d,
+                                                    int32_t it, double decay) {
   __shared__ float4 sh[kParts][64];
   const int i1 = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 64 + lane;
@@ -1813,7 +1806,14 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
   n2s = n2s + yv[2] * yv[2];
   n2s = n2s + yv[3] * yv[3];
   if (!(n2s > 0.0f)) return;
-  float f = (float)(alpha / sqrt((double)n2s));
+  double a = alpha;
+  if (alpha_d) {
+    // the step length of step it of the level: alpha_0, then times decay
+    // after every step, as the host carries it
+    a = *alpha_d;
+    for (int32_t i = 0; i < it; ++i) a = a * decay;
+  }
+  float f = (float)(a / sqrt((double)n2s));
   const float xv[4] = {xo.x, xo.y, xo.z, xo.w};
   float xn[4];
   for (int d = 0; d < 4; ++d) {
@@ -1828,6 +1828,7 @@ struct GradWork {
   Buf<uint32_t> box;
   Buf<float> part;  // partial repulsions, tree order: [16][4][k], or [16][16][4][k] when spread
   Tree T;
+  Buf<double> alpha;  // alpha_0 of the level (device step length)
 };
 
 // Attraction into y, net centres, box of x (gw.box) and the tree of x.
@@ -1857,8 +1858,11 @@ static void gradient_prepare(Ctx& C, const Level& L, const float4* x, double th2
 // Repulsion by the tree walk, added to the attraction in y.  xmove == NULL:
 // y receives the gradient of eq. (6); else the descent step of length alpha
 // is applied to xmove (the layout being descended) and y is left as is.
+// alpha_d (device, may be NULL): alpha_0 of the level, the step length of
+// step it being alpha_0 times decay it times; else alpha is the step length.
 static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, double alpha, GradWork& gw,
-                          unsigned long long* nint, hipStream_t s) {
+                          unsigned long long* nint, hipStream_t s, const double* alpha_d = nullptr,
+                          int32_t it = 0, double decay = 1.0) {
   // Levels of up to kSpreadMax points spread each part of the walk over the
   // children of its cell: 16 times the wavefronts, and up to 16 times the
   // parts to write and add up.  Above it the unspread walk already has more
@@ -1899,15 +1903,38 @@ static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, doub
   prof_end(C, ph, s);
   if (target) VMO_LAUNCH(k_sum_slots, 1, kCntSlots, 0, s, C.wslots, target);
   VMO_LAUNCH(k_combine, nblocks(L.k, 64), kCombT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p,
-             gw.T.nch.p, spread, gw.part.p, y, xmove, alpha);
+             gw.T.nch.p, spread, gw.part.p, y, xmove, alpha, alpha_d, it, decay);
+}
+
+// alpha_0 = step0 * V^(1/4) from the box (V = 0: its largest side), as the
+// host forms it (one thread).
+__global__ void k_alpha0(const uint32_t* box, double step0, double* alpha) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double V = 1.0, ext = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    const double e = (double)fkey_inv(box[4 + d]) - (double)fkey_inv(box[d]);
+    V = V * e;
+    if (e > ext) ext = e;
+  }
+  const double side = V > 0.0 ? sqrt(sqrt(V)) : ext;
+  *alpha = step0 * side;
 }
 
 // One descent step (Algorithm 3).  alpha: step length (host); at it == 0 it
-// is set from the box, alpha = step0 * V^(1/4) (V = 0: largest side).
+// is set from the box, alpha = step0 * V^(1/4) (V = 0: largest side), then
+// multiplied by decay after every step.  alpha == NULL: the same on the
+// device (no read-back): alpha_0 formed at it == 0, the combine applying the
+// decays.
 static void descent_step(Ctx& C, const Level& L, float4* x, const vmo_layout_params* p, int32_t it, double* alpha,
                          float4* y, GradWork& gw, hipStream_t s) {
   double th2 = (double)p->theta * (double)p->theta;
   gradient_prepare(C, L, x, th2, p->leaf_cap, y, gw, s);
+  if (!alpha) {
+    if (!gw.alpha.p) gw.alpha = Buf<double>(C.pool, 1);
+    if (it == 0) VMO_LAUNCH(k_alpha0, 1, 64, 0, s, gw.box.p, (double)p->step0_frac, gw.alpha.p);
+    gradient_walk(C, L, y, x, 0.0, gw, nullptr, s, gw.alpha.p, it, (double)p->decay);
+    return;
+  }
   if (it == 0) {
     HostBox hb = read_box(gw.box.p, s);
     double V = 1.0, ext = 0.0;
@@ -2408,8 +2435,17 @@ __global__ void k_init_x(int32_t k, uint64_t seed, uint64_t key, float a, float4
     x[v] = make_float4(c[0], c[1], c[2], c[3]);
   }
 }
+// eps = jitter * ext / kc^(1/4) from the coarse layout's box (ext its largest
+// side), formed by every thread as the host would.
 __global__ void k_prolong(int32_t kf, const int32_t* pi, const float4* xc, uint64_t seed, uint64_t key, float sigma,
-                          float eps, float4* xf) {
+                          const uint32_t* box, double jitter, int32_t kc, float4* xf) {
+  double ext = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    const double a = (double)fkey_inv(box[4 + d]) - (double)fkey_inv(box[d]);
+    if (a > ext) ext = a;
+  }
+  const double epsd = jitter * ext;
+  const float eps = (float)(epsd / sqrt(sqrt((double)kc)));
   GRID_STRIDE(v, kf) {
     const float4 cv = xc[pi[v]];
     const float cc[4] = {cv.x, cv.y, cv.z, cv.w};
@@ -2465,21 +2501,18 @@ static void layout_component(Ctx& C, std::vector<Level>& L, const vmo_layout_par
   GradWork gw;
   for (int32_t j = J; j >= 0; --j) {
     int32_t iters = j == J ? p->coarsest_iters : p->level_iters;
-    double alpha = 0.0;
     Buf<float4> y(C.pool, (size_t)L[j].k);
-    for (int32_t it = 0; it < iters; ++it) descent_step(C, L[j], x.p, p, it, &alpha, y.p, gw, s);
+    // the step lengths stay on the device: no read-back inside the descent
+    for (int32_t it = 0; it < iters; ++it) descent_step(C, L[j], x.p, p, it, nullptr, y.p, gw, s);
     if (j > 0) {
       if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
       box_of(x.p, L[j].k, gw.box.p, s);
-      HostBox hb = read_box(gw.box.p, s);
-      double ext = hb.ext();
       int32_t kf = L[j - 1].k, kc = L[j].k;
       float sigma = (float)sqrt(sqrt((double)kf / (double)kc));
-      double epsd = (double)p->jitter * ext;
-      float eps = (float)(epsd / sqrt(sqrt((double)kc)));
       uint64_t key = kTagProlong | ((uint64_t)(j - 1) << 8) | (comp << 32);
       Buf<float4> xf(C.pool, (size_t)kf);
-      VMO_LAUNCH(k_prolong, gsz(kf), kLT, 0, s, kf, L[j - 1].pi.p, x.p, p->seed, key, sigma, eps, xf.p);
+      VMO_LAUNCH(k_prolong, gsz(kf), kLT, 0, s, kf, L[j - 1].pi.p, x.p, p->seed, key, sigma, gw.box.p,
+                 (double)p->jitter, kc, xf.p);
       x = std::move(xf);
     }
   }
