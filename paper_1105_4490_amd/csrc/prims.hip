@@ -660,10 +660,10 @@ void radix_sort(Ctx& c, K* keys, int32_t* vals, int64_t n, int bits, hipStream_t
   const int passes = (bits + 7) / 8;
   // tiles of ri rounds: the target tile count is tuned online per size bucket
   // (fewer tiles: shorter look-back chains; more: more blocks in flight)
-  static const int kTarget[6] = {4, 16, 64, 128, 256, 512};
+  static const int kTarget[8] = {4, 8, 16, 32, 64, 128, 256, 512};
   const int bucket = bits_for((uint64_t)n);
   bool tuned = false;
-  const int cfg = n > (int64_t)4 * kRsT ? tune_pick(c, kTuneSort, bucket, 6, &tuned) : 5;
+  const int cfg = n > (int64_t)4 * kRsT ? tune_pick(c, kTuneSort, bucket, 8, &tuned) : 7;
   int ri = 1;
   while (ri < kRsMaxI && n > (int64_t)kTarget[cfg] * kRsT * ri) ri *= 2;
   if (tuned) tune_begin_host(c, kTuneSort, bucket, cfg, (double)n * passes, s);
