@@ -108,8 +108,9 @@ struct HostBox {
   float lo[4], hi[4];
 };
 
-static void box_of(const float4* x, int32_t k, uint32_t* dbox, hipStream_t s) {
-  VMO_LAUNCH(k_box_init, 1, 64, 0, s, dbox);
+// reset: dbox already holds the empty box (the previous step's combine left it so)
+static void box_of(const float4* x, int32_t k, uint32_t* dbox, hipStream_t s, bool reset = false) {
+  if (!reset) VMO_LAUNCH(k_box_init, 1, 64, 0, s, dbox);
   // at most 128 blocks: the 8 atomics of every block meet on one cache line
   int64_t nb = nblocks(k, kLT);
   VMO_LAUNCH(k_box, (unsigned)(nb < 128 ? nb : 128), kLT, 0, s, x, k, dbox);
@@ -1739,7 +1740,10 @@ __global__ __launch_bounds__(kCombT) void k_combine(int32_t k, const int32_t* __
                                                     const int32_t* __restrict__ cid, const int32_t* __restrict__ nch,
                                                     int spread, const float* __restrict__ part, float4* y,
                                                     float4* xmove, double alpha, const double* __restrict__ alpha_d,
-                                                    int32_t it, double decay) {
+                                                    int32_t it, double decay, uint32_t* box_next) {
+  // the empty box for the next step's box of the moved points (every reader
+  // of this step's box ran before this launch)
+  if (box_next && blockIdx.x == 0 && threadIdx.x < 8) box_next[threadIdx.x] = threadIdx.x < 4 ? 0xffffffffu : 0u;
   __shared__ float4 sh[kParts][64];
   const int i1 = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 64 + lane;
@@ -1829,13 +1833,16 @@ struct GradWork {
   Buf<float> part;  // partial repulsions, tree order: [16][4][k], or [16][16][4][k] when spread
   Tree T;
   Buf<double> alpha;  // alpha_0 of the level (device step length)
+  bool box_reset = false;  // box holds the empty box (set by the last combine)
 };
 
 // Attraction into y, net centres, box of x (gw.box) and the tree of x.
 static void gradient_prepare(Ctx& C, const Level& L, const float4* x, double th2, int32_t cap, float4* y, GradWork& gw,
                              hipStream_t s) {
   if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
-  if (L.k > kSmallK) box_of(x, L.k, gw.box.p, s);  // else the one-block tree build forms it
+  // else the one-block tree build forms it
+  if (L.k > kSmallK) box_of(x, L.k, gw.box.p, s, gw.box_reset);
+  gw.box_reset = false;
   gw.z = Buf<float4>(C.pool, (size_t)(L.l > 0 ? L.l : 1));
   if (L.l > 0) VMO_LAUNCH(k_centres, gsz(L.l), kLT, 0, s, L.ptr.p, L.pins.p, L.l, x, gw.z.p);
   const AttractJob aj{L.dptr.p, L.dpins.p, L.k, L.c.p, x, gw.z.p, y};
@@ -1903,7 +1910,8 @@ static void gradient_walk(Ctx& C, const Level& L, float4* y, float4* xmove, doub
   prof_end(C, ph, s);
   if (target) VMO_LAUNCH(k_sum_slots, 1, kCntSlots, 0, s, C.wslots, target);
   VMO_LAUNCH(k_combine, nblocks(L.k, 64), kCombT, 0, s, L.k, gw.T.order.p, gw.T.p2.p, gw.T.nodes.p, gw.T.cid.p,
-             gw.T.nch.p, spread, gw.part.p, y, xmove, alpha, alpha_d, it, decay);
+             gw.T.nch.p, spread, gw.part.p, y, xmove, alpha, alpha_d, it, decay, xmove ? gw.box.p : nullptr);
+  gw.box_reset = xmove != nullptr && gw.box.p != nullptr;
 }
 
 // alpha_0 = step0 * V^(1/4) from the box (V = 0: its largest side), as the
@@ -2507,6 +2515,7 @@ static void layout_component(Ctx& C, std::vector<Level>& L, const vmo_layout_par
     if (j > 0) {
       if (!gw.box.p) gw.box = Buf<uint32_t>(C.pool, 8);
       box_of(x.p, L[j].k, gw.box.p, s);
+      gw.box_reset = false;  // it holds this box now
       int32_t kf = L[j - 1].k, kc = L[j].k;
       float sigma = (float)sqrt(sqrt((double)kf / (double)kc));
       uint64_t key = kTagProlong | ((uint64_t)(j - 1) << 8) | (comp << 32);
