@@ -199,21 +199,7 @@ __global__ void k_tree_points(const float4* x, const float* w, int32_t k, const 
   }
 }
 
-constexpr int kCplB = 256;
-// cpl[i] = number of leading equal digits of keys i-1 and i (16 if equal);
-// cpl[0] = cpl[k] = -1.
-__global__ __launch_bounds__(kCplB) void k_cpl(const uint64_t* key, int32_t k, int8_t* cpl) {
-  int64_t i = (int64_t)blockIdx.x * kCplB + threadIdx.x;
-  if (i <= k) {
-    int c;
-    if (i == 0 || i == k) c = -1;
-    else {
-      uint64_t d = key[i - 1] ^ key[i];
-      c = d == 0 ? 16 : (__clzll(d) >> 2);
-    }
-    cpl[i] = (int8_t)c;
-  }
-}
+constexpr int kCplB = 256;  // the prefix lengths are allocated in multiples of it
 
 // End of the node of depth L beginning at position i: the first j > i whose
 // key differs from key[i] in its first L digits (keys are sorted, so these
@@ -273,29 +259,58 @@ __device__ __forceinline__ int leaf_depth16(CplAt cpl_at, int32_t i, int32_t lo,
   return L > 16 ? 16 : L;
 }
 
-__global__ void k_tree_ell(const int8_t* cpl, int32_t k, int32_t cap, int8_t* ell, int32_t* nn) {
-  GRID_STRIDE(i64, (int64_t)k + 1) {
-    int32_t i = (int32_t)i64;
-    if (i == k) { nn[k] = 0; continue; }
-    int lo = i - cap + 1 < 0 ? 0 : i - cap + 1;
-    int hi = i + cap > k ? k : i + cap;
-    int L = 0;
-    if (cap <= 16) {
-      L = leaf_depth16([&](int32_t p) { return cpl[p]; }, i, lo, hi, cap);
-    } else {
-      for (; L <= 16; ++L) {
-        int b = -1, e = -1;
-        for (int j = i; j >= lo; --j)
-          if (cpl[j] < L) { b = j; break; }
-        for (int j = i + 1; j <= hi; ++j)
-          if (cpl[j] < L) { e = j; break; }
-        if (b >= 0 && e >= 0 && e - b <= cap) break;
+// Common-prefix length cpl[i] of sorted keys i-1 and i in 4-bit digits (16
+// when equal, -1 at 0 and k), and the leaf depth and the number of nodes
+// beginning at each position, in one launch: a block forms the prefix lengths
+// of its kLT positions and of cap positions on each side in LDS, writes its
+// own and finds the leaf depths from LDS (cap <= kCplHalo, the largest leaf
+// capacity).
+constexpr int kCplHalo = 64;
+__global__ __launch_bounds__(kLT) void k_cpl_ell(const uint64_t* key, int32_t k, int32_t cap, int8_t* cpl,
+                                                int8_t* ell, int32_t* nn) {
+  __shared__ int8_t sc[kLT + 2 * kCplHalo];
+  for (int64_t b0 = (int64_t)blockIdx.x * kLT; b0 <= k; b0 += (int64_t)gridDim.x * kLT) {
+    const int64_t w0 = b0 - cap;  // sc[q] = cpl[w0 + q]
+    for (int q = threadIdx.x; q < kLT + 2 * cap; q += kLT) {
+      const int64_t p = w0 + q;
+      int c = -1;  // positions 0 and k (and any outside [0, k], never read)
+      if (p > 0 && p < k) {
+        const uint64_t d = key[p - 1] ^ key[p];
+        c = d == 0 ? 16 : (__clzll(d) >> 2);
       }
-      if (L > 16) L = 16;
+      sc[q] = (int8_t)c;
     }
-    ell[i] = (int8_t)L;
-    int ci = cpl[i];
-    nn[i] = L >= ci + 1 ? L - ci : 0;
+    __syncthreads();
+    const int64_t i64 = b0 + threadIdx.x;
+    if (i64 <= k) {
+      const int32_t i = (int32_t)i64;
+      auto cpl_at = [&](int64_t p) { return (int)sc[p - w0]; };
+      cpl[i] = (int8_t)cpl_at(i);
+      if (i == k) {
+        nn[k] = 0;
+      } else {
+        const int lo = i - cap + 1 < 0 ? 0 : i - cap + 1;
+        const int hi = i + cap > k ? k : i + cap;
+        int L = 0;
+        if (cap <= 16) {
+          L = leaf_depth16([&](int32_t p) { return cpl_at(p); }, i, lo, hi, cap);
+        } else {
+          for (; L <= 16; ++L) {
+            int b = -1, e = -1;
+            for (int j = i; j >= lo; --j)
+              if (cpl_at(j) < L) { b = j; break; }
+            for (int j = i + 1; j <= hi; ++j)
+              if (cpl_at(j) < L) { e = j; break; }
+            if (b >= 0 && e >= 0 && e - b <= cap) break;
+          }
+          if (L > 16) L = 16;
+        }
+        ell[i] = (int8_t)L;
+        const int ci = cpl_at(i);
+        nn[i] = L >= ci + 1 ? L - ci : 0;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1065,7 +1080,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
     cpl[i] = (int8_t)c;
   }
   __syncthreads();
-  // leaf depth and the number of nodes beginning at each position (as k_tree_ell)
+  // leaf depth and the number of nodes beginning at each position (as k_cpl_ell)
   for (int i = t; i <= k; i += kSTB) {
     if (i == k) { base[k] = 0; continue; }
     const int lo = i - cap + 1 < 0 ? 0 : i - cap + 1;
@@ -1333,11 +1348,9 @@ static void build_tree(Ctx& C, Tree& T, const float4* x, const float* w, int32_t
   VMO_LAUNCH(k_tree_keys, gsz(k), kLT, 0, s, x, k, dbox, T.key.p, T.order.p);
   radix_sort<uint64_t>(C, T.key.p, T.order.p, k, 64, s);
   VMO_LAUNCH(k_tree_points, gsz(k), kLT, 0, s, x, w, k, dbox, T.order.p, T.xs.p, T.ws.p, T.p2.p, T.P.p);
-  int32_t nb = k / kCplB + 1;
   grow(T.cpl, (kk / kCplB + 1) * kCplB);
-  VMO_LAUNCH(k_cpl, nb, kCplB, 0, s, T.key.p, k, T.cpl.p);
   grow(T.ell, kk + 1);
-  VMO_LAUNCH(k_tree_ell, gsz((int64_t)k + 1), kLT, 0, s, T.cpl.p, k, cap, T.ell.p, T.nn.p);
+  VMO_LAUNCH(k_cpl_ell, gsz((int64_t)k + 1), kLT, 0, s, T.key.p, k, cap, T.cpl.p, T.ell.p, T.nn.p);
   scan_exclusive<int32_t>(C, T.nn.p, T.nn.p, (int64_t)k + 1, nullptr, s);
   NodeView nd = T.view();
   VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.key.p, T.ell.p, T.nn.p, T.p2.p, k, far_table(th2), nd);
