@@ -264,11 +264,14 @@ __device__ __forceinline__ int leaf_depth16(CplAt cpl_at, int32_t i, int32_t lo,
 // beginning at each position, in one launch: a block forms the prefix lengths
 // of its kLT positions and of cap positions on each side in LDS, writes its
 // own and finds the leaf depths from LDS (cap <= kCplHalo, the largest leaf
-// capacity).
+// capacity).  nnp[b] = the node counts' sum over positions [b kLT, (b+1) kLT),
+// for the scan of the counts.
 constexpr int kCplHalo = 64;
+static_assert(kLT == kScanPart, "a block's positions are one group of the scan");
 __global__ __launch_bounds__(kLT) void k_cpl_ell(const uint64_t* key, int32_t k, int32_t cap, int8_t* cpl,
-                                                int8_t* ell, int32_t* nn) {
+                                                int8_t* ell, int32_t* nn, int32_t* nnp) {
   __shared__ int8_t sc[kLT + 2 * kCplHalo];
+  __shared__ int32_t wsum[kLT / 64];
   for (int64_t b0 = (int64_t)blockIdx.x * kLT; b0 <= k; b0 += (int64_t)gridDim.x * kLT) {
     const int64_t w0 = b0 - cap;  // sc[q] = cpl[w0 + q]
     for (int q = threadIdx.x; q < kLT + 2 * cap; q += kLT) {
@@ -282,6 +285,7 @@ __global__ __launch_bounds__(kLT) void k_cpl_ell(const uint64_t* key, int32_t k,
     }
     __syncthreads();
     const int64_t i64 = b0 + threadIdx.x;
+    int32_t cnt = 0;
     if (i64 <= k) {
       const int32_t i = (int32_t)i64;
       auto cpl_at = [&](int64_t p) { return (int)sc[p - w0]; };
@@ -307,8 +311,17 @@ __global__ __launch_bounds__(kLT) void k_cpl_ell(const uint64_t* key, int32_t k,
         }
         ell[i] = (int8_t)L;
         const int ci = cpl_at(i);
-        nn[i] = L >= ci + 1 ? L - ci : 0;
+        cnt = L >= ci + 1 ? L - ci : 0;
+        nn[i] = cnt;
       }
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t a = 0;
+      for (int w = 0; w < kLT / 64; ++w) a += wsum[w];
+      nnp[b0 / kLT] = a;
     }
     __syncthreads();
   }
@@ -1289,7 +1302,7 @@ __global__ __launch_bounds__(kSTB) void k_tree_small(const float4* __restrict__ 
 struct Tree {
   int32_t k = 0, n = 0;
   Buf<uint64_t> key;
-  Buf<int32_t> order, p2, nn;
+  Buf<int32_t> order, p2, nn, nnp;
   Buf<float> xs, ws;
   Buf<int8_t> cpl, ell;
   Buf<TNode> nodes;
@@ -1350,8 +1363,10 @@ static void build_tree(Ctx& C, Tree& T, const float4* x, const float* w, int32_t
   VMO_LAUNCH(k_tree_points, gsz(k), kLT, 0, s, x, w, k, dbox, T.order.p, T.xs.p, T.ws.p, T.p2.p, T.P.p);
   grow(T.cpl, (kk / kCplB + 1) * kCplB);
   grow(T.ell, kk + 1);
-  VMO_LAUNCH(k_cpl_ell, gsz((int64_t)k + 1), kLT, 0, s, T.key.p, k, cap, T.cpl.p, T.ell.p, T.nn.p);
-  scan_exclusive<int32_t>(C, T.nn.p, T.nn.p, (int64_t)k + 1, nullptr, s);
+  grow(T.nnp, kk / kLT + 1);
+  VMO_LAUNCH(k_cpl_ell, gsz((int64_t)k + 1), kLT, 0, s, T.key.p, k, cap, T.cpl.p, T.ell.p, T.nn.p, T.nnp.p);
+  if ((int64_t)k + 1 <= kScanPartMax) scan_exclusive_parts(C, T.nn.p, T.nn.p, (int64_t)k + 1, T.nnp.p, s);
+  else scan_exclusive<int32_t>(C, T.nn.p, T.nn.p, (int64_t)k + 1, nullptr, s);
   NodeView nd = T.view();
   VMO_LAUNCH(k_tree_nodes, gsz(k), kLT, 0, s, T.cpl.p, T.key.p, T.ell.p, T.nn.p, T.p2.p, k, far_table(th2), nd);
   // the node count stays on the device: grids sized for the usual count

@@ -414,8 +414,9 @@ __global__ __launch_bounds__(kScanT) void k_scan_reduce(const T* __restrict__ in
 }
 
 // part: NULL (one tile), the tiles' exclusive offsets (sum_parts == 0), or
-// the tiles' totals (sum_parts != 0), whose sum over the earlier tiles each
-// block forms itself (integer sums: any order gives the same offset)
+// the totals of groups of sum_parts items (sum_parts > 0; a tile holds
+// kScanTile / sum_parts groups), whose sum over the earlier tiles each block
+// forms itself (integer sums: any order gives the same offset)
 template <class T>
 __global__ __launch_bounds__(kScanT) void k_scan_down(const T* in, T* out, int64_t n, const T* part,
                                                       int sum_parts, T* total, int last_block) {
@@ -431,7 +432,8 @@ __global__ __launch_bounds__(kScanT) void k_scan_down(const T* in, T* out, int64
   T off = tzero<T>();
   if (part && sum_parts) {
     T o = tzero<T>();
-    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanT) o = tadd(o, part[i]);
+    const int np = (int)blockIdx.x * (kScanTile / sum_parts);
+    for (int i = threadIdx.x; i < np; i += kScanT) o = tadd(o, part[i]);
     (void)block_excl(o, sh, &off);
   } else if (part) {
     off = part[blockIdx.x];
@@ -462,12 +464,20 @@ void scan_exclusive(Ctx& c, const T* in, T* out, int64_t n, T* total, hipStream_
   VMO_LAUNCH((k_scan_reduce<T>), (unsigned)nb, kScanT, 0, s, in, n, part.p);
   if (nb <= kScanTile) {
     // few tiles: each block adds up the earlier tiles' totals itself
-    VMO_LAUNCH((k_scan_down<T>), (unsigned)nb, kScanT, 0, s, in, out, n, (const T*)part.p, 1, total,
+    VMO_LAUNCH((k_scan_down<T>), (unsigned)nb, kScanT, 0, s, in, out, n, (const T*)part.p, kScanTile, total,
                (int)(nb - 1));
     return;
   }
   scan_exclusive<T>(c, part.p, part.p, nb, total, s);
   VMO_LAUNCH((k_scan_down<T>), (unsigned)nb, kScanT, 0, s, in, out, n, (const T*)part.p, 0, (T*)nullptr, 0);
+}
+
+void scan_exclusive_parts(Ctx& c, const int32_t* in, int32_t* out, int64_t n, const int32_t* parts, hipStream_t s) {
+  (void)c;
+  static_assert(kScanTile % kScanPart == 0, "a tile holds whole groups");
+  VMO_REQUIRE(n >= 1 && n <= kScanPartMax, "scan size out of range");
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  VMO_LAUNCH((k_scan_down<int32_t>), (unsigned)nb, kScanT, 0, s, in, out, n, parts, kScanPart, (int32_t*)nullptr, 0);
 }
 
 template void scan_exclusive<int32_t>(Ctx&, const int32_t*, int32_t*, int64_t, int32_t*, hipStream_t);

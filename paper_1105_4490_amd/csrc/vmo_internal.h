@@ -340,6 +340,12 @@ __host__ __device__ inline bool u128_zero(U128 a) { return a.lo == 0 && a.hi == 
 // receives the sum.  T: int32_t, int64_t, uint64_t, U128.
 template <class T>
 void scan_exclusive(Ctx& c, const T* in, T* out, int64_t n, T* total, hipStream_t s);
+// Exclusive scan of n ints whose sums over consecutive groups of kScanPart
+// items are given (parts[ceil(n / kScanPart)], formed by the producer of in):
+// one launch.  n <= kScanPartMax.
+constexpr int kScanPart = 256;
+constexpr int64_t kScanPartMax = (int64_t)2048 * 2048;
+void scan_exclusive_parts(Ctx& c, const int32_t* in, int32_t* out, int64_t n, const int32_t* parts, hipStream_t s);
 
 // Stable LSD radix sort of keys (uint32_t or uint64_t) on bits [0, bits), with
 // optional int32 values carried along.  Sorted output overwrites keys/vals.
