@@ -46,7 +46,7 @@ FLOPS_PER_INTERACTION = 20
 # one timed step of this workload), from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors a
 # plain copy of known size gives); profiles/k_walk_grid3d64_traffic.md
-WALK_TRAFFIC_BYTES = 107.60e6 + 29.28e6
+WALK_TRAFFIC_BYTES = 111.16e6 + 29.28e6
 PEAK_FP32_VALU_TFLOPS = 157.3        # 256 CUs x 128 FP32 lanes (packed) x 2 (fma) x 2.4 GHz
 PEAK_FP32_UNPACKED_TFLOPS = 78.6     # the same without packed FP32 (this build disables it)
 # live timing brackets every PROFILE_EVERY-th launch of a kernel with HIP

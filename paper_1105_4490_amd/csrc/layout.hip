@@ -1527,12 +1527,13 @@ constexpr int kWT = 64;     // threads per block of the walk: one wavefront (mea
 constexpr int kCntSlots = 256;  // interaction counters of the walk (16 words apart)
 
 template <bool kCount>  // kCount: count the interactions into nint
-__global__ __launch_bounds__(kWT) void k_walk(int32_t k, const int32_t* __restrict__ n_dev, const float4* __restrict__ P,
-                                              const float* __restrict__ ws, const int32_t* __restrict__ p2,
-                                              const TNode* __restrict__ nodes, const int32_t* __restrict__ cid,
-                                              const int32_t* __restrict__ nch, int spread, float* __restrict__ part,
-                                              unsigned long long* nint, const int32_t* __restrict__ plan,
-                                              int32_t hblocks) {
+// 64 registers (eight wavefronts per SIMD instead of seven at the compiler's 72:
+// the finest levels' walks fill the chip and gain from the extra wavefront)
+__global__ __launch_bounds__(kWT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_walk(
+    int32_t k, const int32_t* __restrict__ n_dev, const float4* __restrict__ P, const float* __restrict__ ws,
+    const int32_t* __restrict__ p2, const TNode* __restrict__ nodes, const int32_t* __restrict__ cid,
+    const int32_t* __restrict__ nch, int spread, float* __restrict__ part, unsigned long long* nint,
+    const int32_t* __restrict__ plan, int32_t hblocks) {
   constexpr int NW = kWT / 64;
   __shared__ int4 win[NW][5][kWin];  // the five 16-byte chunks of kWin nodes
   __shared__ float4 lp[NW][kWin];
