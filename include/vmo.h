@@ -214,8 +214,9 @@ size_t vmo_layout_bytes(int32_t k, int32_t l, int64_t npins);
 /* [async] Full layout.  x [4][k] FP32 SoA output.  Reads back: the input
    checks, the component count and each component's size, each coarse level's
    sizes (its buffers are sized from them), one matching flag per eight
-   matching rounds, the bounding box at the first step of each level (the
-   step length), and the component boxes (packing offsets). */
+   matching rounds, and the component boxes (packing offsets).  The descent
+   reads nothing back: each level's step length is formed on the device from
+   its bounding box. */
 vmo_status vmo_layout(vmo_ctx ctx, const vmo_hypergraph* h, const vmo_layout_params* p /* (host) */,
                       float* x, vmo_stream stream);
 
@@ -238,7 +239,9 @@ vmo_status vmo_coarsen(vmo_ctx ctx, const vmo_hypergraph* h, uint64_t seed, uint
    (charge and its weighted centre); order [k] = point ids in tree order.
    *n_nodes (host). */
 /* (vmo_tree reads back the node count, a host output; it does not wait for
-   the copy of the node arrays: [async] for ints, cell2, flt and order.) */
+   the copy of the node arrays: [async] for ints, cell2, flt and order.  The
+   tree is built as the layout builds it: in one workgroup up to 4,096
+   points, else by the multi-kernel build; both give the same tree.) */
 vmo_status vmo_tree(vmo_ctx ctx, const float* x, const float* w, int32_t k, int32_t leaf_cap,
                     int32_t* ints, int32_t* cell2, float* flt, int32_t* order, int32_t max_nodes,
                     int32_t* n_nodes, vmo_stream stream);
